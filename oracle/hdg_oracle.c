@@ -1,0 +1,795 @@
+/*
+ * FP64 CPU oracle for the hybrid NS-LES / Euler DGSEM residual.
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, by the smoke check and by
+ * the benchmark's CPU-baseline leg; never by the product path.  Plain loops,
+ * double precision, the discretisation written in the weak form the paper
+ * states (App. B, the integrated-by-parts element equations with a numerical
+ * flux on the element boundary and collocated quadrature).  OpenMP only
+ * splits independent elements across threads; every element's arithmetic is
+ * the same sequential loop whatever the thread count.
+ *
+ * Method (paper: Sec. 2.3 and App. A-B), as read for this build:
+ *  - unknowns (p, u, v, w) of the incompressible equations in artificial
+ *    compressibility form, dp/dt + c0^2 div u = 0 (unit density);
+ *  - every element gets the convective flux (Sec. 2.3); elements flagged
+ *    viscous/turbulent also get the viscous + LES flux 2 (nu + nu_t) S
+ *    (App. A stress tensor, incompressible, no trace term);
+ *  - element coupling through a Roe flux on every face and the BR1
+ *    (Bassi-Rebay 1) average of viscous fluxes on faces with a viscous side,
+ *    single valued per face (Sec. 2.3 face cases, Sec. 4 remark on a
+ *    single-valued viscous flux);
+ *  - LES eddy viscosity: Smagorinsky or Vreman (App. A, Vreman equation);
+ *  - Gauss-Lobatto-Legendre collocation, curvilinear hexahedra with metric
+ *    terms in curl (conservative) form (App. B transformed equation);
+ *  - three-stage low-storage RK (Sec. 2.3 time marching), Williamson's
+ *    2N-storage coefficients.
+ */
+#include "hdg_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXN 9
+
+static char g_err[512];
+const char *orc_last_error(void) { return g_err; }
+
+struct orc_mesh {
+    int ne, P, N, N2, N3;
+    double xi[MAXN], w[MAXN], D[MAXN * MAXN];
+    double *x;      /* [e][3][N3] node coordinates */
+    double *J;      /* [e][N3] Jacobian */
+    double *Ja;     /* [e][3 (i)][3 (d)][N3] contravariant metric Ja^i_d */
+    double *delta;  /* [e] LES filter width */
+    int *nbr;
+    signed char *nbr_face, *orient;
+    unsigned char *flag;
+};
+
+static int g_threads = 0;
+void orc_set_threads(int n) { g_threads = n; }
+int orc_get_threads(void) {
+#ifdef _OPENMP
+    return g_threads > 0 ? g_threads : omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quadrature: Gauss-Lobatto-Legendre nodes/weights, Lagrange derivative.    */
+/* ------------------------------------------------------------------------ */
+
+/* Legendre polynomial L_n and its derivative at x by the three-term recurrence. */
+static void legendre(int n, double x, double *L, double *dL)
+{
+    double l0 = 1.0, l1 = x, d0 = 0.0, d1 = 1.0;
+    if (n == 0) { *L = 1.0; *dL = 0.0; return; }
+    for (int k = 1; k < n; ++k) {
+        double l2 = ((2.0 * k + 1.0) * x * l1 - k * l0) / (k + 1.0);
+        double d2 = d0 + (2.0 * k + 1.0) * l1;
+        l0 = l1; l1 = l2; d0 = d1; d1 = d2;
+    }
+    *L = l1; *dL = d1;
+}
+
+/* l_j'(x_i) for the Lagrange basis on nodes x[0..N-1], from its definition
+ * l_j(x) = prod_{m != j} (x - x_m) / (x_j - x_m). */
+static void lagrange_derivative_matrix(int N, const double *x, double *D)
+{
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < N; ++k) {
+                if (k == j) continue;
+                double t = 1.0 / (x[j] - x[k]);
+                for (int m = 0; m < N; ++m) {
+                    if (m == j || m == k) continue;
+                    t *= (x[i] - x[m]) / (x[j] - x[m]);
+                }
+                s += t;
+            }
+            D[i * N + j] = s;
+        }
+}
+
+static double lagrange_value(int M1, const double *nodes, int k, double x)
+{
+    double v = 1.0;
+    for (int m = 0; m < M1; ++m)
+        if (m != k) v *= (x - nodes[m]) / (nodes[k] - nodes[m]);
+    return v;
+}
+
+void orc_lgl(int P, double *xi, double *w, double *D)
+{
+    int N = P + 1;
+    xi[0] = -1.0;
+    xi[P] = 1.0;
+    /* interior nodes: roots of L_P', Newton from Chebyshev-Lobatto guesses */
+    for (int k = 1; k < P; ++k) {
+        double x = -cos(M_PI * k / P);
+        for (int it = 0; it < 100; ++it) {
+            double L, dL;
+            legendre(P, x, &L, &dL);
+            double d2L = (2.0 * x * dL - P * (P + 1.0) * L) / (1.0 - x * x);
+            double dx = dL / d2L;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        xi[k] = x;
+    }
+    for (int k = 0; k < N; ++k) {
+        double L, dL;
+        legendre(P, xi[k], &L, &dL);
+        w[k] = 2.0 / (P * (P + 1.0) * L * L);
+    }
+    lagrange_derivative_matrix(N, xi, D);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh topology helpers                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* volume node of face-local point (a, b) on local face f */
+static int face_node(int N, int f, int a, int b)
+{
+    int d = f / 2, s = (f & 1) ? N - 1 : 0;
+    if (d == 0) return s + N * a + N * N * b;
+    if (d == 1) return a + N * s + N * N * b;
+    return a + N * b + N * N * s;
+}
+
+static void orient_map(int o, int M, int a, int b, int *a2, int *b2)
+{
+    int s = (o & 1) ? b : a, t = (o & 1) ? a : b;
+    *a2 = (o & 2) ? M - s : s;
+    *b2 = (o & 4) ? M - t : t;
+}
+
+static int is_owner(const orc_mesh *m, int e, int f)
+{
+    int e2 = m->nbr[e * 6 + f];
+    if (e2 < 0) return 1;
+    int f2 = m->nbr_face[e * 6 + f];
+    return (e < e2) || (e == e2 && f < f2);
+}
+
+/* This element's own outward s*n at face f, node n: +-Ja^{f/2}. */
+static void own_outward(const orc_mesh *m, int e, int f, int node, double v[3])
+{
+    int i = f / 2;
+    double sg = (f & 1) ? 1.0 : -1.0;
+    for (int d = 0; d < 3; ++d)
+        v[d] = sg * m->Ja[(((size_t)e * 3 + i) * 3 + d) * m->N3 + node];
+}
+
+typedef struct {
+    int interior;      /* 1 if a neighbour element, else boundary */
+    int bc;            /* -1 wall, -2 far field (boundary only) */
+    int e2, f2, node2; /* partner element, face and its volume node */
+} partner_t;
+
+static partner_t partner(const orc_mesh *m, int e, int f, int a, int b)
+{
+    partner_t p;
+    int e2 = m->nbr[e * 6 + f];
+    if (e2 < 0) {
+        p.interior = 0; p.bc = e2; p.e2 = e; p.f2 = f; p.node2 = face_node(m->N, f, a, b);
+        return p;
+    }
+    int a2, b2;
+    orient_map(m->orient[e * 6 + f], m->N - 1, a, b, &a2, &b2);
+    p.interior = 1; p.bc = 0; p.e2 = e2; p.f2 = m->nbr_face[e * 6 + f];
+    p.node2 = face_node(m->N, p.f2, a2, b2);
+    return p;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh construction: geometry at the nodes, curl-form metrics               */
+/* ------------------------------------------------------------------------ */
+
+static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
+{
+    int N = m->N, N3 = m->N3, G1 = Pg + 1;
+    double gn[MAXN];
+    for (int k = 0; k < G1; ++k) gn[k] = -1.0 + 2.0 * k / Pg;
+    double lg[MAXN][MAXN]; /* lg[a][k] = l_k^geom(xi_a) */
+    for (int a = 0; a < N; ++a)
+        for (int k = 0; k < G1; ++k) lg[a][k] = lagrange_value(G1, gn, k, m->xi[a]);
+
+    /* The metric terms are invariant under a translation of the element, so
+     * the geometry is interpolated and differentiated in coordinates relative
+     * to the element's first control point: round-off then stays relative to
+     * the element size rather than to its distance from the origin. */
+    double *x = m->x + (size_t)e * 3 * N3;
+    double *xl = malloc(sizeof(double) * 3 * N3);
+    for (int c = 0; c < 3; ++c) {
+        const double *Xc = X + (size_t)c * G1 * G1 * G1;
+        for (int n = 0; n < N3; ++n) {
+            int a = n % N, b = (n / N) % N, cc = n / (N * N);
+            double s = 0.0;
+            for (int k3 = 0; k3 < G1; ++k3)
+                for (int k2 = 0; k2 < G1; ++k2)
+                    for (int k1 = 0; k1 < G1; ++k1)
+                        s += (Xc[k1 + G1 * k2 + G1 * G1 * k3] - Xc[0])
+                             * lg[a][k1] * lg[b][k2] * lg[cc][k3];
+            xl[c * N3 + n] = s;
+            x[c * N3 + n] = Xc[0] + s;
+        }
+    }
+
+    /* derivative of a nodal field along reference direction k at node n */
+#define DREF(field, k, n, out)                                                  \
+    do {                                                                        \
+        int a_ = (n) % N, b_ = ((n) / N) % N, c_ = (n) / (N * N);               \
+        double s_ = 0.0;                                                        \
+        for (int q_ = 0; q_ < N; ++q_) {                                        \
+            int idx_ = (k) == 0 ? q_ + N * b_ + N * N * c_                      \
+                     : (k) == 1 ? a_ + N * q_ + N * N * c_                      \
+                                : a_ + N * b_ + N * N * q_;                     \
+            int row_ = (k) == 0 ? a_ : (k) == 1 ? b_ : c_;                      \
+            s_ += m->D[row_ * N + q_] * (field)[idx_];                          \
+        }                                                                       \
+        (out) = s_;                                                             \
+    } while (0)
+
+    double *dX = malloc(sizeof(double) * 9 * N3);   /* dX[c][k][n] = dX_c/dxi_k */
+    for (int c = 0; c < 3; ++c)
+        for (int k = 0; k < 3; ++k)
+            for (int n = 0; n < N3; ++n) DREF(xl + c * N3, k, n, dX[(c * 3 + k) * N3 + n]);
+
+    double *J = m->J + (size_t)e * N3;
+    for (int n = 0; n < N3; ++n) {
+        double a11 = dX[(0 * 3 + 0) * N3 + n], a12 = dX[(0 * 3 + 1) * N3 + n], a13 = dX[(0 * 3 + 2) * N3 + n];
+        double a21 = dX[(1 * 3 + 0) * N3 + n], a22 = dX[(1 * 3 + 1) * N3 + n], a23 = dX[(1 * 3 + 2) * N3 + n];
+        double a31 = dX[(2 * 3 + 0) * N3 + n], a32 = dX[(2 * 3 + 1) * N3 + n], a33 = dX[(2 * 3 + 2) * N3 + n];
+        J[n] = a11 * (a22 * a33 - a23 * a32) - a12 * (a21 * a33 - a23 * a31) + a13 * (a21 * a32 - a22 * a31);
+    }
+
+    /* Ja^i_n = -[curl_xi (X_l grad_xi X_m)]_i with (n, m, l) cyclic */
+    double *V = malloc(sizeof(double) * 3 * N3);
+    for (int nn = 0; nn < 3; ++nn) {
+        int mm = (nn + 1) % 3, ll = (nn + 2) % 3;
+        for (int k = 0; k < 3; ++k)
+            for (int n = 0; n < N3; ++n)
+                V[k * N3 + n] = xl[ll * N3 + n] * dX[(mm * 3 + k) * N3 + n];
+        for (int n = 0; n < N3; ++n) {
+            double d1V2, d2V1, d2V0, d0V2, d0V1, d1V0;
+            DREF(V + 2 * N3, 1, n, d1V2);
+            DREF(V + 1 * N3, 2, n, d2V1);
+            DREF(V + 0 * N3, 2, n, d2V0);
+            DREF(V + 2 * N3, 0, n, d0V2);
+            DREF(V + 1 * N3, 0, n, d0V1);
+            DREF(V + 0 * N3, 1, n, d1V0);
+            double curl[3] = {d1V2 - d2V1, d2V0 - d0V2, d0V1 - d1V0};
+            for (int i = 0; i < 3; ++i)
+                m->Ja[(((size_t)e * 3 + i) * 3 + nn) * N3 + n] = -curl[i];
+        }
+    }
+#undef DREF
+    free(V);
+    free(xl);
+    free(dX);
+
+    double vol = 0.0;
+    for (int n = 0; n < N3; ++n) {
+        int a = n % N, b = (n / N) % N, c = n / (N * N);
+        vol += m->w[a] * m->w[b] * m->w[c] * J[n];
+    }
+    m->delta[e] = cbrt(vol) / N;
+}
+
+orc_mesh *orc_mesh_new(int ne, int P, int Pg, const double *xyz_geom, const int *nbr,
+                       const signed char *nbr_face, const signed char *orient,
+                       const unsigned char *flag)
+{
+    g_err[0] = 0;
+    if (ne <= 0 || P < 1 || P > MAXN - 1 || Pg < 1 || Pg > MAXN - 1) {
+        snprintf(g_err, sizeof g_err, "bad sizes: n_elem=%d P=%d Pg=%d", ne, P, Pg);
+        return NULL;
+    }
+    /* connectivity must be symmetric with mutually inverse orientation maps */
+    for (int e = 0; e < ne; ++e)
+        for (int f = 0; f < 6; ++f) {
+            int e2 = nbr[e * 6 + f];
+            if (e2 < 0) {
+                if (e2 != -1 && e2 != -2) {
+                    snprintf(g_err, sizeof g_err, "element %d face %d: bad boundary code %d", e, f, e2);
+                    return NULL;
+                }
+                continue;
+            }
+            int f2 = nbr_face[e * 6 + f];
+            if (e2 >= ne || f2 < 0 || f2 > 5 || nbr[e2 * 6 + f2] != e || nbr_face[e2 * 6 + f2] != f) {
+                snprintf(g_err, sizeof g_err, "element %d face %d: asymmetric connectivity", e, f);
+                return NULL;
+            }
+            int o = orient[e * 6 + f], o2 = orient[e2 * 6 + f2];
+            if (o < 0 || o > 7 || o2 < 0 || o2 > 7) {
+                snprintf(g_err, sizeof g_err, "element %d face %d: bad orientation", e, f);
+                return NULL;
+            }
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) {
+                    int a2, b2, a3, b3;
+                    orient_map(o, 1, a, b, &a2, &b2);
+                    orient_map(o2, 1, a2, b2, &a3, &b3);
+                    if (a3 != a || b3 != b) {
+                        snprintf(g_err, sizeof g_err, "element %d face %d: orientation codes not inverse", e, f);
+                        return NULL;
+                    }
+                }
+        }
+
+    orc_mesh *m = calloc(1, sizeof *m);
+    m->ne = ne; m->P = P; m->N = P + 1; m->N2 = m->N * m->N; m->N3 = m->N2 * m->N;
+    orc_lgl(P, m->xi, m->w, m->D);
+    size_t N3 = m->N3;
+    m->x = malloc(sizeof(double) * (size_t)ne * 3 * N3);
+    m->J = malloc(sizeof(double) * (size_t)ne * N3);
+    m->Ja = malloc(sizeof(double) * (size_t)ne * 9 * N3);
+    m->delta = malloc(sizeof(double) * ne);
+    m->nbr = malloc(sizeof(int) * ne * 6);
+    m->nbr_face = malloc(ne * 6);
+    m->orient = malloc(ne * 6);
+    m->flag = malloc(ne);
+    memcpy(m->nbr, nbr, sizeof(int) * ne * 6);
+    memcpy(m->nbr_face, nbr_face, ne * 6);
+    memcpy(m->orient, orient, ne * 6);
+    memcpy(m->flag, flag, ne);
+    size_t G3 = (size_t)(Pg + 1) * (Pg + 1) * (Pg + 1);
+#pragma omp parallel for schedule(static) num_threads(orc_get_threads())
+    for (int e = 0; e < ne; ++e) element_metrics(m, e, Pg, xyz_geom + (size_t)e * 3 * G3);
+    for (size_t i = 0; i < (size_t)ne * N3; ++i)
+        if (!(m->J[i] > 0.0)) {
+            snprintf(g_err, sizeof g_err, "non-positive Jacobian in element %zu", i / N3);
+            orc_mesh_free(m);
+            return NULL;
+        }
+    return m;
+}
+
+void orc_mesh_free(orc_mesh *m)
+{
+    if (!m) return;
+    free(m->x); free(m->J); free(m->Ja); free(m->delta);
+    free(m->nbr); free(m->nbr_face); free(m->orient); free(m->flag);
+    free(m);
+}
+
+void orc_set_flags(orc_mesh *m, const unsigned char *flag) { memcpy(m->flag, flag, m->ne); }
+
+void orc_node_coords(const orc_mesh *m, double *xyz)
+{
+    memcpy(xyz, m->x, sizeof(double) * (size_t)m->ne * 3 * m->N3);
+}
+
+void orc_metrics(const orc_mesh *m, double *J, double *Ja)
+{
+    if (J) memcpy(J, m->J, sizeof(double) * (size_t)m->ne * m->N3);
+    if (Ja) memcpy(Ja, m->Ja, sizeof(double) * (size_t)m->ne * 9 * m->N3);
+}
+
+double orc_filter_width(const orc_mesh *m, int e) { return m->delta[e]; }
+
+/* ------------------------------------------------------------------------ */
+/* Pointwise physics                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* normal convective flux F.n of (p, u): (c0^2 u.n, u (u.n) + p n) */
+static void normal_flux(double c0sq, const double *q, const double *n, double *F)
+{
+    double un = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
+    F[0] = c0sq * un;
+    for (int r = 0; r < 3; ++r) F[1 + r] = q[1 + r] * un + q[0] * n[r];
+}
+
+/* Invert a 4x4 matrix by Gauss-Jordan elimination with partial pivoting. */
+static void invert4(const double A_in[4][4], double inv[4][4])
+{
+    double A[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) A[i][j] = j < 4 ? A_in[i][j] : (j - 4 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (piv != c)
+            for (int j = 0; j < 8; ++j) { double t = A[c][j]; A[c][j] = A[piv][j]; A[piv][j] = t; }
+        double d = A[c][c];
+        for (int j = 0; j < 8; ++j) A[c][j] /= d;
+        for (int r = 0; r < 4; ++r) {
+            if (r == c) continue;
+            double fct = A[r][c];
+            for (int j = 0; j < 8; ++j) A[r][j] -= fct * A[c][j];
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) inv[i][j] = A[i][j + 4];
+}
+
+/* Roe flux for the artificial-compressibility system along the unit normal n:
+ * F = (F(qL) + F(qR))/2 - |A(qbar)| (qR - qL) / 2, with |A| = R |Lambda| R^-1
+ * built from the eigen-decomposition of the flux Jacobian at the mean state.
+ * Since the flux is quadratic, A(qbar) (qR - qL) = F(qR) - F(qL) exactly. */
+void orc_roe_flux(double c0sq, const double *qL, const double *qR, const double *n, double *F)
+{
+    double FL[4], FR[4];
+    normal_flux(c0sq, qL, n, FL);
+    normal_flux(c0sq, qR, n, FR);
+    double ub[3] = {0.5 * (qL[1] + qR[1]), 0.5 * (qL[2] + qR[2]), 0.5 * (qL[3] + qR[3])};
+    double un = ub[0] * n[0] + ub[1] * n[1] + ub[2] * n[2];
+    double a = sqrt(un * un + c0sq);
+    /* acoustic eigenpairs: lambda = un +- a, vector (pi, v) with pi = -un +- a,
+     * v = +-(pi n + ubar)/a; tangential pair: lambda = un, vector (0, t), t.n = 0 */
+    double pip = -un + a, pim = -un - a;
+    double R[4][4], lam[4];
+    R[0][0] = pip;
+    R[0][1] = pim;
+    for (int d = 0; d < 3; ++d) {
+        R[1 + d][0] = (pip * n[d] + ub[d]) / a;
+        R[1 + d][1] = -(pim * n[d] + ub[d]) / a;
+    }
+    lam[0] = un + a;
+    lam[1] = un - a;
+    double h[3] = {1.0, 0.0, 0.0};
+    if (fabs(n[0]) > 0.9) { h[0] = 0.0; h[1] = 1.0; }
+    double hn = h[0] * n[0] + h[1] * n[1] + h[2] * n[2];
+    double t1[3] = {h[0] - hn * n[0], h[1] - hn * n[1], h[2] - hn * n[2]};
+    double t1n = sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+    for (int d = 0; d < 3; ++d) t1[d] /= t1n;
+    double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+    R[0][2] = 0.0; R[0][3] = 0.0;
+    for (int d = 0; d < 3; ++d) { R[1 + d][2] = t1[d]; R[1 + d][3] = t2[d]; }
+    lam[2] = un; lam[3] = un;
+    double Ri[4][4];
+    invert4(R, Ri);
+    double dq[4], alpha[4];
+    for (int k = 0; k < 4; ++k) dq[k] = qR[k] - qL[k];
+    for (int k = 0; k < 4; ++k) {
+        alpha[k] = 0.0;
+        for (int j = 0; j < 4; ++j) alpha[k] += Ri[k][j] * dq[j];
+    }
+    for (int r = 0; r < 4; ++r) {
+        double diss = 0.0;
+        for (int k = 0; k < 4; ++k) diss += R[r][k] * fabs(lam[k]) * alpha[k];
+        F[r] = 0.5 * (FL[r] + FR[r]) - 0.5 * diss;
+    }
+}
+
+/* LES eddy viscosity from the velocity gradient G[r*3+d] = du_r/dx_d. */
+double orc_les_nut(int model, double C, double delta, const double *G)
+{
+    if (model == 1) {          /* Smagorinsky: (Cs Delta)^2 sqrt(2 S:S) */
+        double SS = 0.0;
+        for (int r = 0; r < 3; ++r)
+            for (int d = 0; d < 3; ++d) {
+                double s = 0.5 * (G[r * 3 + d] + G[d * 3 + r]);
+                SS += s * s;
+            }
+        return (C * delta) * (C * delta) * sqrt(2.0 * SS);
+    }
+    if (model == 2) {          /* Vreman: Cv sqrt(B_beta / alpha:alpha), unit density */
+        double al[3][3], be[3][3], aa = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) { al[i][j] = G[j * 3 + i]; aa += al[i][j] * al[i][j]; }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0;
+                for (int mm = 0; mm < 3; ++mm) s += al[mm][i] * al[mm][j];
+                be[i][j] = delta * delta * s;
+            }
+        double B = be[0][0] * be[1][1] - be[0][1] * be[0][1] + be[0][0] * be[2][2] - be[0][2] * be[0][2]
+                 + be[1][1] * be[2][2] - be[1][2] * be[1][2];
+        if (aa == 0.0) return 0.0;
+        if (B < 0.0) B = 0.0;
+        return C * sqrt(B / aa);
+    }
+    return 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Traces                                                                    */
+/* ------------------------------------------------------------------------ */
+
+static void trace_outside(const orc_mesh *m, const orc_params *p, const double *q, int e,
+                          int node, partner_t pt, double out[4])
+{
+    size_t N3 = m->N3;
+    if (pt.interior) {
+        for (int k = 0; k < 4; ++k) out[k] = q[((size_t)pt.e2 * 4 + k) * N3 + pt.node2];
+    } else if (pt.bc == -1) {   /* no-slip wall: mirrored velocity, same pressure */
+        out[0] = q[((size_t)e * 4 + 0) * N3 + node];
+        for (int k = 1; k < 4; ++k) out[k] = -q[((size_t)e * 4 + k) * N3 + node];
+    } else {                    /* far field: prescribed state */
+        for (int k = 0; k < 4; ++k) out[k] = p->q_inf[k];
+    }
+}
+
+/* The outward s*n of the face's owner at this face point (single valued per face). */
+static void owner_normal(const orc_mesh *m, int e, int f, int node, partner_t pt, double v[3])
+{
+    if (is_owner(m, e, f)) own_outward(m, e, f, node, v);
+    else own_outward(m, pt.e2, pt.f2, pt.node2, v);
+}
+
+/* ------------------------------------------------------------------------ */
+/* BR1 gradient (weak form) on viscous elements                              */
+/* ------------------------------------------------------------------------ */
+
+static void element_gradient(const orc_mesh *m, const orc_params *p, const double *q, int e, double *G)
+{
+    int N = m->N, N3 = m->N3;
+    const double *qe = q + (size_t)e * 4 * N3;
+    const double *Ja = m->Ja + (size_t)e * 9 * N3;
+    const double *J = m->J + (size_t)e * N3;
+    for (int j = 0; j < N3; ++j) {
+        int ijk[3] = {j % N, (j / N) % N, j / (N * N)};
+        double acc[3][3] = {{0}};
+        /* - sum over quadrature nodes of W (Ja^i_d u_r) d(phi_j)/dxi^i */
+        for (int i = 0; i < 3; ++i) {
+            double wother = 1.0;
+            for (int k = 0; k < 3; ++k) if (k != i) wother *= m->w[ijk[k]];
+            for (int mq = 0; mq < N; ++mq) {
+                int mijk[3] = {ijk[0], ijk[1], ijk[2]};
+                mijk[i] = mq;
+                int mn = mijk[0] + N * mijk[1] + N * N * mijk[2];
+                double coef = m->w[mq] * wother * m->D[mq * N + ijk[i]];
+                for (int r = 0; r < 3; ++r)
+                    for (int d = 0; d < 3; ++d)
+                        acc[r][d] -= coef * qe[(1 + r) * N3 + mn] * Ja[(i * 3 + d) * N3 + mn];
+            }
+        }
+        /* + surface integral of u* (s n)_out phi_j, u* = mean of the two traces */
+        for (int f = 0; f < 6; ++f) {
+            int d = f / 2, s = (f & 1) ? N - 1 : 0;
+            if (ijk[d] != s) continue;
+            int a = d == 0 ? ijk[1] : ijk[0];
+            int b = d == 2 ? ijk[1] : ijk[2];
+            partner_t pt = partner(m, e, f, a, b);
+            double qo[4], nv[3];
+            trace_outside(m, p, q, e, j, pt, qo);
+            owner_normal(m, e, f, j, pt, nv);
+            double sg = is_owner(m, e, f) ? 1.0 : -1.0;
+            double wf = m->w[a] * m->w[b];
+            for (int r = 0; r < 3; ++r) {
+                double ustar = 0.5 * (qe[(1 + r) * N3 + j] + qo[1 + r]);
+                for (int dd = 0; dd < 3; ++dd) acc[r][dd] += wf * ustar * sg * nv[dd];
+            }
+        }
+        double mass = m->w[ijk[0]] * m->w[ijk[1]] * m->w[ijk[2]] * J[j];
+        for (int r = 0; r < 3; ++r)
+            for (int d = 0; d < 3; ++d) G[((size_t)(r * 3 + d)) * N3 + j] = acc[r][d] / mass;
+    }
+}
+
+void orc_gradient(const orc_mesh *m, const orc_params *p, const double *q, double *G)
+{
+    size_t N3 = m->N3;
+#pragma omp parallel for schedule(dynamic, 8) num_threads(orc_get_threads())
+    for (int e = 0; e < m->ne; ++e)
+        if (m->flag[e]) element_gradient(m, p, q, e, G + (size_t)e * 9 * N3);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Residual                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* viscous flux 2 (nu + nu_t) S at every node of a viscous element: fv[r][d][N3] */
+static void element_viscous_flux(const orc_mesh *m, const orc_params *p, const double *G, int e, double *fv)
+{
+    int N3 = m->N3;
+    for (int n = 0; n < N3; ++n) {
+        double g[9];
+        for (int k = 0; k < 9; ++k) g[k] = G[(size_t)k * N3 + n];
+        double nut = orc_les_nut(p->les_model, p->C_les, m->delta[e], g);
+        for (int r = 0; r < 3; ++r)
+            for (int d = 0; d < 3; ++d)
+                fv[(size_t)(r * 3 + d) * N3 + n] = 2.0 * (p->nu + nut) * 0.5 * (g[r * 3 + d] + g[d * 3 + r]);
+    }
+}
+
+/* fv . v at a node (momentum rows), zero for an Euler element */
+static void fv_dot(const orc_mesh *m, const double *fv, int e, int node, const double v[3], double out[3])
+{
+    if (!m->flag[e]) { out[0] = out[1] = out[2] = 0.0; return; }
+    size_t N3 = m->N3;
+    const double *fe = fv + (size_t)e * 9 * N3;
+    for (int r = 0; r < 3; ++r) {
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) s += fe[(size_t)(r * 3 + d) * N3 + node] * v[d];
+        out[r] = s;
+    }
+}
+
+/* Numerical flux through face f of element e at face point (a, b), outward for e,
+ * already multiplied by the surface scaling s. */
+static void face_flux(const orc_mesh *m, const orc_params *p, const double *q, const double *fv,
+                      int e, int f, int a, int b, double Fout[4])
+{
+    size_t N3 = m->N3;
+    int node = face_node(m->N, f, a, b);
+    partner_t pt = partner(m, e, f, a, b);
+    int own = is_owner(m, e, f);
+    double qm[4], qp[4], nv[3];
+    for (int k = 0; k < 4; ++k) qm[k] = q[((size_t)e * 4 + k) * N3 + node];
+    trace_outside(m, p, q, e, node, pt, qp);
+    owner_normal(m, e, f, node, pt, nv);
+    double s = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    double nh[3] = {nv[0] / s, nv[1] / s, nv[2] / s};
+    const double *qL = own ? qm : qp;
+    const double *qR = own ? qp : qm;
+    double F[4];
+    orc_roe_flux(p->c0sq, qL, qR, nh, F);
+    for (int k = 0; k < 4; ++k) F[k] *= s;
+
+    /* BR1 viscous flux: mean of the two sides' viscous fluxes along s n */
+    double fvo[3] = {0, 0, 0};
+    if (!pt.interior) {
+        fv_dot(m, fv, e, node, nv, fvo);              /* boundary: interior viscous flux */
+    } else {
+        int eo = own ? e : pt.e2, no = own ? node : pt.node2;     /* owner side */
+        int en = own ? pt.e2 : e, nn = own ? pt.node2 : node;     /* other side */
+        double fL[3], fR[3];
+        fv_dot(m, fv, eo, no, nv, fL);
+        fv_dot(m, fv, en, nn, nv, fR);
+        int both = m->flag[eo] && m->flag[en];
+        if (p->mixed_face == 0 || both)
+            for (int r = 0; r < 3; ++r) fvo[r] = 0.5 * (fL[r] + fR[r]);
+    }
+    for (int r = 0; r < 3; ++r) F[1 + r] -= fvo[r];
+    double sg = own ? 1.0 : -1.0;
+    for (int k = 0; k < 4; ++k) Fout[k] = sg * F[k];
+}
+
+static void element_residual(const orc_mesh *m, const orc_params *p, const double *q, const double *fv,
+                             int e, double *Re)
+{
+    int N = m->N, N3 = m->N3;
+    const double *qe = q + (size_t)e * 4 * N3;
+    const double *Ja = m->Ja + (size_t)e * 9 * N3;
+    const double *J = m->J + (size_t)e * N3;
+    const double *fve = fv + (size_t)e * 9 * N3;
+    double *Ft = malloc(sizeof(double) * 12 * N3);     /* Ft[i][row][n] */
+    for (int n = 0; n < N3; ++n) {
+        double pr = qe[n], u[3] = {qe[N3 + n], qe[2 * N3 + n], qe[3 * N3 + n]};
+        double f[4][3];
+        for (int d = 0; d < 3; ++d) {
+            f[0][d] = p->c0sq * u[d];
+            for (int r = 0; r < 3; ++r) f[1 + r][d] = u[r] * u[d] + (r == d ? pr : 0.0);
+        }
+        if (m->flag[e])
+            for (int r = 0; r < 3; ++r)
+                for (int d = 0; d < 3; ++d) f[1 + r][d] -= fve[(size_t)(r * 3 + d) * N3 + n];
+        for (int i = 0; i < 3; ++i)
+            for (int row = 0; row < 4; ++row) {
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d) s += Ja[(i * 3 + d) * N3 + n] * f[row][d];
+                Ft[(i * 4 + row) * N3 + n] = s;
+            }
+    }
+    for (int j = 0; j < N3; ++j) {
+        int ijk[3] = {j % N, (j / N) % N, j / (N * N)};
+        double vol[4] = {0, 0, 0, 0}, surf[4] = {0, 0, 0, 0};
+        /* + sum over quadrature nodes of W Ft^i d(phi_j)/dxi^i */
+        for (int i = 0; i < 3; ++i) {
+            double wother = 1.0;
+            for (int k = 0; k < 3; ++k) if (k != i) wother *= m->w[ijk[k]];
+            for (int mq = 0; mq < N; ++mq) {
+                int mijk[3] = {ijk[0], ijk[1], ijk[2]};
+                mijk[i] = mq;
+                int mn = mijk[0] + N * mijk[1] + N * N * mijk[2];
+                double coef = m->w[mq] * wother * m->D[mq * N + ijk[i]];
+                for (int row = 0; row < 4; ++row) vol[row] += coef * Ft[(i * 4 + row) * N3 + mn];
+            }
+        }
+        /* surface integral of the numerical flux times phi_j */
+        for (int f = 0; f < 6; ++f) {
+            int d = f / 2, s = (f & 1) ? N - 1 : 0;
+            if (ijk[d] != s) continue;
+            int a = d == 0 ? ijk[1] : ijk[0];
+            int b = d == 2 ? ijk[1] : ijk[2];
+            double Fo[4];
+            face_flux(m, p, q, fv, e, f, a, b, Fo);
+            double wf = m->w[a] * m->w[b];
+            for (int row = 0; row < 4; ++row) surf[row] += wf * Fo[row];
+        }
+        double mass = m->w[ijk[0]] * m->w[ijk[1]] * m->w[ijk[2]] * J[j];
+        for (int row = 0; row < 4; ++row) Re[(size_t)row * N3 + j] = (vol[row] - surf[row]) / mass;
+    }
+    free(Ft);
+}
+
+void orc_residual(const orc_mesh *m, const orc_params *p, const double *q, double *R)
+{
+    size_t N3 = m->N3;
+    double *fv = malloc(sizeof(double) * (size_t)m->ne * 9 * N3);
+#pragma omp parallel num_threads(orc_get_threads())
+    {
+        double *G = malloc(sizeof(double) * 9 * N3);
+#pragma omp for schedule(dynamic, 8)
+        for (int e = 0; e < m->ne; ++e) {
+            if (!m->flag[e]) continue;
+            element_gradient(m, p, q, e, G);
+            element_viscous_flux(m, p, G, e, fv + (size_t)e * 9 * N3);
+        }
+        free(G);
+#pragma omp for schedule(dynamic, 8)
+        for (int e = 0; e < m->ne; ++e) element_residual(m, p, q, fv, e, R + (size_t)e * 4 * N3);
+    }
+    free(fv);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Low-storage three-stage RK (Williamson 2N coefficients)                   */
+/* ------------------------------------------------------------------------ */
+
+typedef void (*rhs_fn)(void *ctx, const double *y, double *r);
+
+static void rk3_drive(size_t n, double *y, double dt, int nsteps, rhs_fn f, void *ctx)
+{
+    static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+    static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    double *dq = calloc(n, sizeof(double));
+    double *r = malloc(n * sizeof(double));
+    for (int step = 0; step < nsteps; ++step)
+        for (int s = 0; s < 3; ++s) {
+            f(ctx, y, r);
+            for (size_t i = 0; i < n; ++i) {
+                dq[i] = A[s] * dq[i] + dt * r[i];
+                y[i] += B[s] * dq[i];
+            }
+        }
+    free(r);
+    free(dq);
+}
+
+typedef struct { const orc_mesh *m; const orc_params *p; } mesh_ctx;
+static void mesh_rhs(void *ctx, const double *y, double *r)
+{
+    mesh_ctx *c = ctx;
+    orc_residual(c->m, c->p, y, r);
+}
+
+void orc_rk3_steps(const orc_mesh *m, const orc_params *p, double *q, double dt, int nsteps)
+{
+    mesh_ctx c = {m, p};
+    rk3_drive((size_t)m->ne * 4 * m->N3, q, dt, nsteps, mesh_rhs, &c);
+}
+
+typedef struct { double re, im; } lin_ctx;
+static void linear_rhs(void *ctx, const double *y, double *r)
+{
+    lin_ctx *c = ctx;
+    r[0] = c->re * y[0] - c->im * y[1];
+    r[1] = c->re * y[1] + c->im * y[0];
+}
+
+void orc_rk3_linear(double lam_re, double lam_im, double dt, int nsteps, double *y_re, double *y_im)
+{
+    lin_ctx c = {lam_re, lam_im};
+    double y[2] = {*y_re, *y_im};
+    rk3_drive(2, y, dt, nsteps, linear_rhs, &c);
+    *y_re = y[0];
+    *y_im = y[1];
+}
+
+static void riccati_rhs(void *ctx, const double *y, double *r)
+{
+    (void)ctx;
+    r[0] = -y[0] * y[0];
+}
+
+double orc_rk3_riccati(double y0, double dt, int nsteps)
+{
+    double y = y0;
+    rk3_drive(1, &y, dt, nsteps, riccati_rhs, NULL);
+    return y;
+}

@@ -1,0 +1,508 @@
+"""Pins for the FP64 CPU oracle, checked against what the mathematics fixes.
+
+None of these compares the oracle with itself or retypes its formulas: each
+uses a closed form, a textbook value, a library routine (numpy), an invariant
+of the discretisation, or a convergence rate.  The paper prints no residual
+values or worked example for the method (App. B only states the scheme), so
+absolute residuals on the benchmark workloads stay "parity unpinned".
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2403_05463_amd import workloads as W
+
+# --------------------------------------------------------------------------
+# Quadrature (App. B: collocated Gauss-type quadrature; Gauss-Lobatto nodes)
+# --------------------------------------------------------------------------
+
+
+def test_lgl_textbook_values(orc):
+    xi, w, _ = orc.lgl(2)
+    np.testing.assert_allclose(xi, [-1, 0, 1], atol=1e-15)
+    np.testing.assert_allclose(w, [1 / 3, 4 / 3, 1 / 3], rtol=1e-15)
+    xi, w, _ = orc.lgl(3)
+    s = 1 / math.sqrt(5)
+    np.testing.assert_allclose(xi, [-1, -s, s, 1], rtol=1e-15)
+    np.testing.assert_allclose(w, [1 / 6, 5 / 6, 5 / 6, 1 / 6], rtol=1e-15)
+    xi, w, _ = orc.lgl(4)
+    s = math.sqrt(3 / 7)
+    np.testing.assert_allclose(xi, [-1, -s, 0, s, 1], rtol=1e-15, atol=1e-16)
+    np.testing.assert_allclose(w, [1 / 10, 49 / 90, 32 / 45, 49 / 90, 1 / 10], rtol=1e-14)
+
+
+@pytest.mark.parametrize("P", range(1, 9))
+def test_lgl_nodes_are_roots_of_legendre_derivative(orc, P):
+    xi, w, _ = orc.lgl(P)
+    LP = np.polynomial.legendre.Legendre.basis(P)
+    roots = np.sort(LP.deriv().roots().real) if P > 1 else np.array([])
+    np.testing.assert_allclose(xi[1:-1], roots, atol=1e-14)
+    assert xi[0] == -1.0 and xi[-1] == 1.0
+
+
+@pytest.mark.parametrize("P", range(1, 9))
+def test_lgl_quadrature_exact_to_degree_2P_minus_1(orc, P):
+    xi, w, _ = orc.lgl(P)
+    for k in range(2 * P):
+        exact = (1 - (-1) ** (k + 1)) / (k + 1)
+        assert abs(np.dot(w, xi ** k) - exact) < 1e-14
+    k = 2 * P     # not exact one degree higher: the rule is Lobatto, not Gauss
+    assert abs(np.dot(w, xi ** k) - 2 / (k + 1)) > 1e-6
+
+
+@pytest.mark.parametrize("P", range(1, 9))
+def test_derivative_matrix_exact_on_polynomials(orc, P):
+    xi, w, D = orc.lgl(P)
+    for k in range(P + 1):
+        d = D @ xi ** k
+        exact = k * xi ** (k - 1) if k > 0 else np.zeros_like(xi)
+        np.testing.assert_allclose(d, exact, atol=2e-13 * max(1, P * P))
+    err = np.abs(D @ xi ** (P + 1) - (P + 1) * xi ** P).max()
+    assert err > 1e-6
+
+
+@pytest.mark.parametrize("P", range(1, 9))
+def test_summation_by_parts(orc, P):
+    xi, w, D = orc.lgl(P)
+    Q = np.diag(w) @ D
+    B = np.zeros((P + 1, P + 1))
+    B[0, 0], B[-1, -1] = -1, 1
+    np.testing.assert_allclose(Q + Q.T, B, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Geometry (App. B: transfinite polynomial map, Jacobian, contravariant terms)
+# --------------------------------------------------------------------------
+
+
+def _single_affine_element(A, b, Pg=1):
+    g = np.linspace(-1, 1, Pg + 1)
+    K, Jg, I = np.meshgrid(g, g, g, indexing="ij")
+    ref = np.stack([I.ravel(), Jg.ravel(), K.ravel()])       # x fastest
+    xyz = (A @ ref + b[:, None])[None]
+    corners = np.arange(8)[None]
+    nbr, nf, o = W.connectivity(corners, lambda e, f: W.FARFIELD)
+    return W.HexMesh(Pg=Pg, xyz_geom=xyz, corners=corners, nbr=nbr, nbr_face=nf, orient=o,
+                     centroid=b[None].copy())
+
+
+def test_metrics_affine_closed_form(orc):
+    rng = np.random.default_rng(3)
+    A = np.eye(3) * 0.7 + 0.2 * rng.standard_normal((3, 3))
+    assert np.linalg.det(A) > 0
+    b = rng.standard_normal(3)
+    m = _single_affine_element(A, b, Pg=2)
+    om = orc.OracleMesh(m, 4, np.zeros(1, np.uint8))
+    J, Ja = om.metrics()
+    detA = np.linalg.det(A)
+    np.testing.assert_allclose(J, detA, rtol=1e-13)
+    # Ja^i_d = J d(xi^i)/d(x_d) = det(A) inv(A)[i, d]
+    cof = detA * np.linalg.inv(A)
+    for i in range(3):
+        for d in range(3):
+            np.testing.assert_allclose(Ja[0, i, d], cof[i, d], atol=1e-13)
+    # node coordinates follow the affine map of the textbook LGL nodes
+    xi, _, _ = orc.lgl(4)
+    K, Jg, I = np.meshgrid(xi, xi, xi, indexing="ij")
+    ref = np.stack([I.ravel(), Jg.ravel(), K.ravel()])
+    np.testing.assert_allclose(om.node_coords()[0], A @ ref + b[:, None], atol=1e-14)
+    # filter width: element volume^(1/3) / (P+1)
+    assert abs(om.filter_width(0) - (8 * detA) ** (1 / 3) / 5) < 1e-14
+
+
+def _metric_divergence(Ja, D, N):
+    Jae = Ja.reshape(Ja.shape[0], 3, 3, N, N, N)           # e, i, d, k, j, i(x)
+    return (np.einsum("am,edkjm->edkja", D, Jae[:, 0]) + np.einsum("bm,edkmi->edkbi", D, Jae[:, 1])
+            + np.einsum("cm,edmji->edcji", D, Jae[:, 2]))
+
+
+@pytest.mark.parametrize("P,Pg", [(2, 2), (3, 2), (4, 3), (5, 3)])
+def test_discrete_metric_identities_curved(orc, P, Pg):
+    m = W.periodic_box(3, Pg=Pg, curve_amp=0.35)
+    om = orc.OracleMesh(m, P, np.zeros(m.n_elem, np.uint8))
+    J, Ja = om.metrics()
+    _, _, D = orc.lgl(P)
+    div = _metric_divergence(Ja, D, P + 1)
+    assert np.abs(div).max() < 1e-13 * np.abs(Ja).max() * (P + 1) ** 2
+
+
+@pytest.mark.parametrize("P", [3, 4, 6])
+def test_curved_periodic_volume_is_exact(orc, P):
+    # a watertight deformation of the 3-torus keeps its volume; J of a
+    # quadratic map has degree <= 5 per direction, integrated exactly for P >= 3
+    L = 2 * math.pi
+    m = W.periodic_box(3, L=L, Pg=2, curve_amp=0.4)
+    om = orc.OracleMesh(m, P, np.zeros(m.n_elem, np.uint8))
+    J, _ = om.metrics()
+    xi, w, _ = orc.lgl(P)
+    W3 = np.einsum("k,j,i->kji", w, w, w).ravel()
+    vol = (J * W3).sum()
+    assert abs(vol - L ** 3) < 1e-12 * L ** 3
+    assert J.min() > 0
+
+
+def test_ogrid_jacobian_positive_and_mask_fraction(orc):
+    m = W.naca_ogrid(48, 24, 4, Pg=2)
+    om = orc.OracleMesh(m, 3, np.zeros(m.n_elem, np.uint8))
+    J, _ = om.metrics()
+    assert J.min() > 0
+    wl = W.naca_working()
+    frac = wl.flag.mean()
+    assert 0.25 < frac < 0.35
+    assert wl.mesh.n_elem * (wl.P + 1) ** 3 == 4_608_000
+
+
+# --------------------------------------------------------------------------
+# Roe flux (Sec. 2.3: Roe Riemann solver for the convective flux)
+# --------------------------------------------------------------------------
+
+C0SQ = 25.0
+
+
+def _Fn(q, n):
+    p, u = q[0], np.asarray(q[1:])
+    un = u @ n
+    return np.concatenate([[C0SQ * un], u * un + p * np.asarray(n)])
+
+
+def _rand_state_pair(rng):
+    qL = rng.standard_normal(4)
+    qR = qL + 0.3 * rng.standard_normal(4)
+    n = rng.standard_normal(3)
+    return qL, qR, n / np.linalg.norm(n)
+
+
+def test_roe_consistency(orc):
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        q, _, n = _rand_state_pair(rng)
+        np.testing.assert_allclose(orc.roe_flux(C0SQ, q, q, n), _Fn(q, n), rtol=1e-13, atol=1e-13)
+
+
+def test_roe_antisymmetry(orc):
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        qL, qR, n = _rand_state_pair(rng)
+        a = orc.roe_flux(C0SQ, qL, qR, n)
+        b = orc.roe_flux(C0SQ, qR, qL, -n)
+        np.testing.assert_allclose(a, -b, rtol=1e-12, atol=1e-12)
+
+
+def test_roe_dissipation_matches_numpy_eigendecomposition(orc):
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        qL, qR, n = _rand_state_pair(rng)
+        qb = 0.5 * (qL + qR)
+        # Jacobian of the quadratic flux by central differences (exact for a quadratic)
+        A = np.zeros((4, 4))
+        for k in range(4):
+            e = np.zeros(4)
+            e[k] = 1.0
+            A[:, k] = (_Fn(qb + e, n) - _Fn(qb - e, n)) / 2
+        # exact Roe property of the mean-state Jacobian
+        np.testing.assert_allclose(A @ (qR - qL), _Fn(qR, n) - _Fn(qL, n), atol=1e-12)
+        lam, V = np.linalg.eig(A)
+        absA = (V @ np.diag(np.abs(lam)) @ np.linalg.inv(V)).real
+        expect = 0.5 * (_Fn(qL, n) + _Fn(qR, n)) - 0.5 * absA @ (qR - qL)
+        np.testing.assert_allclose(orc.roe_flux(C0SQ, qL, qR, n), expect, rtol=1e-11, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# LES closures (App. A: Vreman model; Smagorinsky as the configured model)
+# --------------------------------------------------------------------------
+
+
+def test_les_pure_shear(orc):
+    g, delta, Cs, Cv = 1.7, 0.3, 0.1, 0.07
+    G = np.zeros((3, 3))
+    G[0, 1] = g          # u = g y
+    assert abs(orc.les_nut(1, Cs, delta, G) - (Cs * delta) ** 2 * g) < 1e-15
+    # Vreman vanishes for a pure shear (a designed property of the model)
+    assert abs(orc.les_nut(2, Cv, delta, G)) < 1e-15
+
+
+def test_les_axisymmetric_strain(orc):
+    a, delta, Cs, Cv = 0.8, 0.25, 0.1, 0.07
+    G = np.diag([a, a, -2 * a])
+    assert abs(orc.les_nut(1, Cs, delta, G) - (Cs * delta) ** 2 * math.sqrt(12) * a) < 1e-14
+    assert abs(orc.les_nut(2, Cv, delta, G) - Cv * delta ** 2 * a * math.sqrt(1.5)) < 1e-14
+
+
+def test_les_random_tensors_against_invariant_forms(orc):
+    rng = np.random.default_rng(4)
+    for _ in range(100):
+        G = rng.standard_normal((3, 3))
+        delta = rng.uniform(0.01, 1)
+        S = 0.5 * (G + G.T)
+        # Smagorinsky via the eigenvalues of S
+        ev = np.linalg.eigvalsh(S)
+        np.testing.assert_allclose(orc.les_nut(1, 0.1, delta, G),
+                                   (0.1 * delta) ** 2 * math.sqrt(2 * (ev ** 2).sum()), rtol=1e-12)
+        # Vreman: B_beta is the second invariant of beta = Delta^2 alpha^T alpha
+        alpha = G.T
+        beta = delta ** 2 * alpha.T @ alpha
+        B = 0.5 * (np.trace(beta) ** 2 - np.trace(beta @ beta))
+        np.testing.assert_allclose(orc.les_nut(2, 0.07, delta, G),
+                                   0.07 * math.sqrt(max(B, 0) / (alpha ** 2).sum()), rtol=1e-12)
+    assert orc.les_nut(2, 0.07, 0.5, np.zeros((3, 3))) == 0.0
+
+
+# --------------------------------------------------------------------------
+# Time marching (Sec. 2.3: low-storage third-order explicit RK)
+# --------------------------------------------------------------------------
+
+
+def test_rk3_amplification_is_cubic_taylor(orc):
+    for z in [-0.3, -1.0, 0.5j, -0.2 + 0.9j, -2.0 + 0.5j]:
+        g = orc.rk3_linear(complex(z), 1.0, 1)
+        assert abs(g - (1 + z + z ** 2 / 2 + z ** 3 / 6)) < 1e-14
+
+
+def test_rk3_third_order_on_riccati(orc):
+    T = 1.0
+    errs = []
+    for n in (10, 20, 40, 80):
+        y = orc.rk3_riccati(1.0, T / n, n)
+        errs.append(abs(y - 1 / (1 + T)))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert min(rates) > 2.8 and max(rates) < 3.3
+
+
+# --------------------------------------------------------------------------
+# Whole residual: invariants of the DGSEM / BR1 discretisation (App. B)
+# --------------------------------------------------------------------------
+
+def _params(orc, **kw):
+    base = dict(c0sq=C0SQ, nu=1e-2, les_model=1, C_les=0.1, mixed_face=0, q_inf=(0, 0, 0, 0))
+    base.update(kw)
+    return orc.make_params(**base)
+
+
+def _const_state(ne, N3, q):
+    s = np.zeros((ne, 4, N3))
+    s[:] = np.asarray(q)[None, :, None]
+    return s
+
+
+@pytest.mark.parametrize("les", [0, 1, 2])
+@pytest.mark.parametrize("Pg,P", [(1, 3), (2, 3), (3, 4)])
+def test_freestream_preservation_curved_box(orc, les, Pg, P):
+    m = W.periodic_box(3, Pg=Pg, curve_amp=0.0 if Pg == 1 else 0.35)
+    flag = W.bernoulli_mask(m.n_elem, 0.5, 7)
+    om = orc.OracleMesh(m, P, flag)
+    qc = [0.3, 1.0, -0.5, 0.2]
+    R = om.residual(_params(orc, les_model=les, C_les=0.1 if les == 1 else 0.07), _const_state(m.n_elem, (P + 1) ** 3, qc))
+    scale = C0SQ * 1.2 / (2 * math.pi / 3)
+    assert np.abs(R).max() < 1e-10 * scale
+
+
+def test_freestream_preservation_reoriented_and_ogrid(orc):
+    m, _ = W.reorient(W.periodic_box(3, Pg=2, curve_amp=0.3), seed=11)
+    om = orc.OracleMesh(m, 3, W.bernoulli_mask(m.n_elem, 0.5, 2))
+    R = om.residual(_params(orc), _const_state(m.n_elem, 64, [0.1, 0.5, 0.7, -0.3]))
+    assert np.abs(R).max() < 1e-10 * C0SQ / (2 * math.pi / 3)
+    # O-grid: far field carries the same state, so only wall elements see a change
+    g = W.naca_ogrid(48, 16, 4, Pg=2)
+    qc = [0.0, math.cos(0.3), math.sin(0.3), 0.0]
+    om = orc.OracleMesh(g, 4, W.naca_mask(g))
+    R = om.residual(_params(orc, q_inf=qc, nu=1e-4), _const_state(g.n_elem, 125, qc))
+    nowall = (g.nbr != W.WALL).all(axis=1)
+    h = W.min_edge_length(g)
+    assert np.abs(R[nowall]).max() < 1e-10 * C0SQ / h
+    assert np.abs(R[~nowall]).max() > 1.0       # the no-slip wall does act
+
+
+def _mass(orc, om, P):
+    J, _ = om.metrics()
+    _, w, _ = orc.lgl(P)
+    return J * np.einsum("k,j,i->kji", w, w, w).ravel()[None]
+
+
+@pytest.mark.parametrize("mixed_face", [0, 1])
+@pytest.mark.parametrize("les", [1, 2])
+def test_discrete_conservation_periodic(orc, mixed_face, les):
+    P = 3
+    m, _ = W.reorient(W.periodic_box(3, Pg=2, curve_amp=0.3), seed=5)
+    flag = W.bernoulli_mask(m.n_elem, 0.5, 3)
+    om = orc.OracleMesh(m, P, flag)
+    rng = np.random.default_rng(9)
+    q = rng.uniform(-1, 1, size=(m.n_elem, 4, (P + 1) ** 3))
+    R = om.residual(_params(orc, les_model=les, C_les=0.1 if les == 1 else 0.07,
+                            mixed_face=mixed_face), q)
+    WJ = _mass(orc, om, P)
+    for f in range(4):
+        tot = (WJ * R[:, f]).sum()
+        mag = np.abs(WJ * R[:, f]).sum()
+        assert abs(tot) < 1e-13 * mag, (f, tot, mag)
+
+
+def test_euler_equals_navier_stokes_with_zero_viscosity_bitwise(orc):
+    P = 3
+    m = W.periodic_box(3, Pg=2, curve_amp=0.3)
+    om = orc.OracleMesh(m, P, np.zeros(m.n_elem, np.uint8))
+    rng = np.random.default_rng(1)
+    q = rng.uniform(-1, 1, size=(m.n_elem, 4, 64))
+    R_euler = om.residual(_params(orc), q)
+    om.set_flags(np.ones(m.n_elem, np.uint8))
+    R_ns0 = om.residual(_params(orc, nu=0.0, C_les=0.0), q)
+    assert np.array_equal(R_euler, R_ns0)
+    R_ns = om.residual(_params(orc, nu=1e-2), q)
+    assert np.abs(R_ns - R_euler).max() > 1e-6          # the viscous terms are not dropped
+
+
+@pytest.mark.parametrize("mixed_face", [0, 1])
+def test_mixed_face_readings(orc, mixed_face):
+    """Reading A: an Euler element next to a viscous one receives half the viscous
+    face flux; reading B: a mixed face carries no viscous flux.  Either way an
+    Euler element's residual never depends on nu through its own volume terms."""
+    P = 3
+    m = W.periodic_box(4, Pg=1)
+    flag = np.zeros(m.n_elem, np.uint8)
+    flag[21] = 1
+    om = orc.OracleMesh(m, P, flag)
+    rng = np.random.default_rng(2)
+    q = rng.uniform(-1, 1, size=(m.n_elem, 4, 64))
+    R1 = om.residual(_params(orc, nu=1e-2, les_model=0, mixed_face=mixed_face), q)
+    R0 = om.residual(_params(orc, nu=0.0, les_model=0, mixed_face=mixed_face), q)
+    d = np.abs(R1 - R0).max(axis=(1, 2))
+    nbrs = set(int(x) for x in m.nbr[21])
+    assert d[21] > 1e-6
+    for e in range(m.n_elem):
+        if e == 21:
+            continue
+        if e in nbrs and mixed_face == 0:
+            assert d[e] > 1e-8
+        else:
+            assert d[e] == 0.0
+
+
+def _interior_box(P, skew=0.3):
+    m = W.box((3, 3, 3), lo=(-1.2, -0.9, -1.0), hi=(1.3, 1.0, 0.8), Pg=1, skew=skew)
+    return m, 13     # element (1,1,1) has only interior faces
+
+
+@pytest.mark.parametrize("P", [2, 3, 5])
+def test_polynomial_exactness_euler_linear_state(orc, P):
+    m, ec = _interior_box(P)
+    om = orc.OracleMesh(m, P, np.zeros(m.n_elem, np.uint8))
+    X = om.node_coords()
+    rng = np.random.default_rng(P)
+    p0, gp = rng.standard_normal(), rng.standard_normal(3)
+    u0, G = rng.standard_normal(3), rng.standard_normal((3, 3))
+    x = X.transpose(0, 2, 1)                                    # (e, n, 3)
+    q = np.empty((m.n_elem, 4, (P + 1) ** 3))
+    q[:, 0] = p0 + x @ gp
+    q[:, 1:] = (u0[None, None] + x @ G.T).transpose(0, 2, 1)
+    R = om.residual(_params(orc, q_inf=(0.2, 0.1, 0.0, 0.3)), q)
+    xe = x[ec]
+    u = u0[None] + xe @ G.T
+    tr = np.trace(G)
+    expect_p = -C0SQ * tr * np.ones(xe.shape[0])
+    expect_u = -(u @ G.T) - u * tr - gp[None]
+    np.testing.assert_allclose(R[ec, 0], expect_p, atol=1e-11 * C0SQ)
+    np.testing.assert_allclose(R[ec, 1:].T, expect_u, atol=1e-11 * C0SQ)
+
+
+@pytest.mark.parametrize("P", [4, 5])
+@pytest.mark.parametrize("les", [0, 1])
+def test_polynomial_exactness_viscous_quadratic_state(orc, P, les):
+    """All-viscous, quadratic velocity: R = -div f_c + nu (lap u + grad div u);
+    with LES on, a quadratic field gives a non-constant nu_t, so only LES off is
+    exact; LES on is checked to differ (the eddy viscosity is not dropped)."""
+    m, ec = _interior_box(P)
+    om = orc.OracleMesh(m, P, np.ones(m.n_elem, np.uint8))
+    X = om.node_coords()
+    rng = np.random.default_rng(10 + P)
+    p0, gp = rng.standard_normal(), rng.standard_normal(3)
+    u0, G = rng.standard_normal(3), rng.standard_normal((3, 3))
+    H = rng.standard_normal((3, 3, 3))
+    H = 0.5 * (H + H.transpose(0, 2, 1))                       # H[r] symmetric
+    x = X.transpose(0, 2, 1)
+    u = u0[None, None] + x @ G.T + 0.5 * np.einsum("eni,rij,enj->enr", x, H, x)
+    q = np.empty((m.n_elem, 4, (P + 1) ** 3))
+    q[:, 0] = p0 + x @ gp
+    q[:, 1:] = u.transpose(0, 2, 1)
+    nu = 0.05
+    R = om.residual(_params(orc, nu=nu, les_model=les, C_les=0.1), q)
+    xe, ue = x[ec], u[ec]
+    grad = G[None] + np.einsum("rij,nj->nri", H, xe)            # grad[n, r, d] = du_r/dx_d
+    div = np.einsum("nrr->n", grad)
+    expect_p = -C0SQ * div
+    conv = np.einsum("nrd,nd->nr", grad, ue) + ue * div[:, None]
+    lap = np.einsum("rii->r", H)
+    graddiv = np.einsum("ddr->r", H)
+    expect_u = -conv - gp[None] + nu * (lap + graddiv)[None]
+    if les == 0:
+        np.testing.assert_allclose(R[ec, 0], expect_p, atol=1e-10 * C0SQ)
+        np.testing.assert_allclose(R[ec, 1:].T, expect_u, atol=1e-10 * C0SQ)
+        Gr = om.gradient(_params(orc, nu=nu), q)
+        np.testing.assert_allclose(Gr[ec].reshape(9, -1).T, grad.reshape(-1, 9), atol=1e-11)
+    else:
+        assert np.abs(R[ec, 1:].T - expect_u).max() > 1e-8
+
+
+@pytest.mark.parametrize("P", [2, 3])
+def test_residual_converges_on_smooth_field(orc, P):
+    """Taylor-Green field on a curved periodic box: the residual approaches the
+    exact -div f_c + nu div(2S) at rate about P (truncation error of DGSEM)."""
+    errs = []
+    nu = 0.01
+    for n in (4, 8):
+        m = W.periodic_box(n, Pg=2, curve_amp=0.15)
+        om = orc.OracleMesh(m, P, np.ones(m.n_elem, np.uint8))
+        X = om.node_coords()
+        q = W.taylor_green_state(X, 0.0, 0)
+        R = om.residual(_params(orc, nu=nu, les_model=0), q)
+        x, y, z = X[:, 0], X[:, 1], X[:, 2]
+        u = np.sin(x) * np.cos(y) * np.cos(z)
+        v = -np.cos(x) * np.sin(y) * np.cos(z)
+        # TGV: div u = 0; -(u.grad)u - grad p + nu lap u
+        px = -2 * np.sin(2 * x) * (np.cos(2 * z) + 2) / 16
+        py = -2 * np.sin(2 * y) * (np.cos(2 * z) + 2) / 16
+        pz = -2 * (np.cos(2 * x) + np.cos(2 * y)) * np.sin(2 * z) / 16
+        ux, uy, uz = np.cos(x) * np.cos(y) * np.cos(z), -np.sin(x) * np.sin(y) * np.cos(z), -np.sin(x) * np.cos(y) * np.sin(z)
+        vx, vy, vz = np.sin(x) * np.sin(y) * np.cos(z), -np.cos(x) * np.cos(y) * np.cos(z), np.cos(x) * np.sin(y) * np.sin(z)
+        ex = [np.zeros_like(x),
+              -(u * ux + v * uy) - px - 3 * nu * u,
+              -(u * vx + v * vy) - py - 3 * nu * v,
+              -pz]
+        err = max(np.abs(R[:, k] - ex[k]).max() for k in range(4))
+        errs.append(err)
+    rate = math.log2(errs[0] / errs[1])
+    assert rate > P - 0.6, (errs, rate)
+
+
+def test_orientation_invariance(orc):
+    P = 3
+    base = W.periodic_box(3, Pg=2, curve_amp=0.3)
+    flag = W.bernoulli_mask(base.n_elem, 0.5, 4)
+    om0 = orc.OracleMesh(base, P, flag)
+    X0 = om0.node_coords()
+    q0 = W.taylor_green_state(X0, 0.05, 3)
+    prm = _params(orc, les_model=2, C_les=0.07)
+    R0 = om0.residual(prm, q0)
+    m1, frames = W.reorient(base, seed=21)
+    assert len(set(int(o) for o in m1.orient.ravel())) > 4
+    om1 = orc.OracleMesh(m1, P, flag)
+    q1 = np.empty_like(q0)
+    maps = [W.index_map(perm, flips, P) for perm, flips in frames]
+    for e, mp in enumerate(maps):
+        q1[e][:, mp] = q0[e]
+    X1 = om1.node_coords()
+    for e, mp in enumerate(maps):
+        np.testing.assert_allclose(X1[e][:, mp], X0[e], atol=1e-12)
+    R1 = om1.residual(prm, q1)
+    R1b = np.empty_like(R1)
+    for e, mp in enumerate(maps):
+        R1b[e] = R1[e][:, mp]
+    scale = np.abs(R0).max()
+    assert np.abs(R1b - R0).max() < 1e-12 * scale
+
+
+def test_dof_per_element(orc):
+    # the paper counts N = (P+1)^3 degrees of freedom per element (Sec. 2.1)
+    for P in (1, 2, 3, 4):
+        m = W.periodic_box(3, Pg=1)
+        om = orc.OracleMesh(m, P, np.zeros(m.n_elem, np.uint8))
+        assert om.node_coords().shape == (27, 3, (P + 1) ** 3)
