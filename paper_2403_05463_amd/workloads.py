@@ -205,8 +205,10 @@ def periodic_box(n: int, L: float = 2 * math.pi, Pg: int = 1, curve_amp: float =
 
 
 def box(n_xyz: tuple[int, int, int], lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
-        Pg: int = 1, boundary: int = FARFIELD, skew: float = 0.0) -> HexMesh:
-    """Non-periodic box of affine hexahedra, every outer face of the given boundary type.
+        Pg: int = 1, boundary: int = FARFIELD, skew: float = 0.0,
+        periodic: tuple[bool, bool, bool] = (False, False, False)) -> HexMesh:
+    """Box of affine hexahedra; outer faces of non-periodic directions get the
+    given boundary type.
 
     ``skew`` shears x by ``skew * y`` so the elements are parallelepipeds.
     """
@@ -225,10 +227,14 @@ def box(n_xyz: tuple[int, int, int], lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
     e = np.arange(nx * ny * nz)
     ei, ej, ek = e % nx, (e // nx) % ny, e // (nx * ny)
     xyz = _element_control_points(gx, gy, gz, ei, ej, ek, Pg)
+    for d, per in enumerate(periodic):
+        if per and n_xyz[d] < 3:
+            raise ValueError("periodic directions need at least three elements")
+    vx, vy, vz = [n_xyz[d] if periodic[d] else n_xyz[d] + 1 for d in range(3)]
     corners = np.empty((e.size, 8), dtype=np.int64)
     for c in range(8):
         ci, cj, ck = c & 1, (c >> 1) & 1, (c >> 2) & 1
-        corners[:, c] = (ei + ci) + (nx + 1) * ((ej + cj) + (ny + 1) * (ek + ck))
+        corners[:, c] = ((ei + ci) % vx) + vx * (((ej + cj) % vy) + vy * ((ek + ck) % vz))
     nbr, nbr_face, orient = connectivity(corners, lambda e_, f_: boundary)
     return HexMesh(Pg=Pg, xyz_geom=xyz, corners=corners, nbr=nbr, nbr_face=nbr_face,
                    orient=orient, centroid=xyz.mean(axis=2), name=f"box{nx}x{ny}x{nz}")

@@ -506,3 +506,38 @@ def test_dof_per_element(orc):
         m = W.periodic_box(3, Pg=1)
         om = orc.OracleMesh(m, P, np.zeros(m.n_elem, np.uint8))
         assert om.node_coords().shape == (27, 3, (P + 1) ** 3)
+
+
+def test_br1_gradient_integrates_to_zero_on_periodic_mesh(orc):
+    """With a single-valued interface trace u* the lifted gradient of any
+    (discontinuous) periodic field integrates to zero over the domain."""
+    P = 3
+    m, _ = W.reorient(W.periodic_box(3, Pg=2, curve_amp=0.3), seed=8)
+    om = orc.OracleMesh(m, P, np.ones(m.n_elem, np.uint8))
+    rng = np.random.default_rng(12)
+    q = rng.uniform(-1, 1, size=(m.n_elem, 4, (P + 1) ** 3))
+    G = om.gradient(_params(orc), q)
+    WJ = _mass(orc, om, P)
+    for k in range(9):
+        r, d = divmod(k, 3)
+        tot = (WJ * G[:, r, d]).sum()
+        assert abs(tot) < 1e-13 * np.abs(WJ * G[:, r, d]).sum()
+
+
+@pytest.mark.parametrize("bc", [W.WALL, W.FARFIELD])
+@pytest.mark.parametrize("P", [2, 3])
+def test_channel_profile_exact_with_boundaries(orc, bc, P):
+    """w = x (L - x) between two boundary planes (no-slip walls, or a zero far
+    field): an exact steady state of the convective terms, so every element,
+    boundary ones included, gives R = (0, 0, 0, -2 nu) (2 nu from nu lap w)."""
+    L = 1.5
+    m = W.box((3, 3, 3), lo=(0, 0, 0), hi=(L, 1.0, 1.2), Pg=1, boundary=bc, periodic=(False, True, True))
+    om = orc.OracleMesh(m, P, np.ones(m.n_elem, np.uint8))
+    x = om.node_coords()[:, 0]
+    q = np.zeros((m.n_elem, 4, (P + 1) ** 3))
+    q[:, 3] = x * (L - x)
+    nu = 0.03
+    R = om.residual(_params(orc, nu=nu, les_model=0), q)
+    expect = np.zeros_like(R)
+    expect[:, 3] = -2 * nu
+    np.testing.assert_allclose(R, expect, atol=1e-11)
