@@ -1,0 +1,161 @@
+"""Throughput of the hybrid NS-LES / Euler DGSEM residual on one MI355X.
+
+A step is one time step of the three-stage low-storage RK: three hybrid
+residual evaluations with the RK update fused into the residual kernels.
+Workload: extruded NACA0012 O-grid, 96 x 48 x 8 quadratic hexahedra, P = 4
+(4,608,000 nodes, 18.4M DOF with 4 fields), Re = 1e4, alpha = 20 deg, about
+29% of the elements flagged viscous (wall band + wake wedge), FP64.
+
+Prints one JSON line: DOF-residual evaluations per second (nodes x 4 fields
+x residuals / s), the roofline of the dominant kernel measured with HIP
+events inside the timed region, and the FP64 CPU oracle timed on this
+host's cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DOF-residual evals/s (mixed NS-LES/Euler DG), plain vs batched FP32; p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kind: int, n_elem: int, N: int, fused_rk: bool) -> float:
+    """Bytes a launch must move at least once (perfect caching), FP64.
+
+    Element kernels: state 32 B/node, metric terms (1/J + 9 Ja) 80 B/node;
+    fused RK stage: + dq read/write 64 + next state 32; residual only: + R 32.
+    Faces: each element owns three faces on average; face geometry 32 B per
+    face node (unit normal + scale); viscous face traces 24 B per face node
+    and side.
+    """
+    N3, N2 = N ** 3, N ** 2
+    if kind == 0:      # viscous traces: u, v, w + metric in, 6 faces of traces out
+        return n_elem * (24 * N3 + 80 * N3 + 3 * N2 * 32 + 6 * N2 * 24)
+    per_node = 32 + 80 + (96 + 32 if fused_rk else 32)
+    b = n_elem * (per_node * N3 + 3 * N2 * 32)
+    if kind == 2:      # viscous residual also reads both sides of its faces' traces
+        b += n_elem * 3 * N2 * 2 * 24
+    return float(b)
+
+
+def cpu_baseline(w, q0, budget_s: float = 12.0) -> dict:
+    import oracle
+    om = oracle.OracleMesh(w.mesh, w.P, w.flag)
+    prm = oracle.make_params(**w.params)
+    nodes = w.mesh.n_elem * (w.P + 1) ** 3
+    t0 = time.perf_counter()
+    evals = 0
+    while True:
+        om.residual(prm, q0)
+        evals += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or evals >= 60:
+            break
+    return {"value": nodes * 4 * evals / el, "unit": "DOF-residual evals/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": f"{evals} full residual evaluations of the same workload ({nodes} nodes), {el:.1f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args(argv)
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU element partition is a design only in this build", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2403_05463_amd import hdg, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    w = W.naca_working()
+    q0 = W.initial_state(w, None)
+    dt = W.cfl_dt(w.mesh, w.P, q0, w.params["c0sq"])
+    N = w.P + 1
+    nodes = w.mesh.n_elem * N ** 3
+    ctx = hdg.hdg_init(0)
+    mesh = hdg.hdg_mesh_create(ctx, w.mesh, w.P, w.flag, hdg.make_params(**w.params))
+    info = hdg.hdg_mesh_info(mesh)
+    q = torch.from_numpy(q0).cuda()
+    dq = torch.empty_like(q)
+    stream = torch.cuda.current_stream()
+    print(f"[bench] {w.name}: {nodes} nodes, {info['n_viscous']} viscous of {w.mesh.n_elem} elements, "
+          f"dt={dt:.3e}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+
+    hdg.hdg_rk3_steps(mesh, q, dq, dt, args.warmup, stream=stream)
+    torch.cuda.synchronize()
+    hdg.hdg_timing_enable(mesh, True)
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    hdg.hdg_rk3_steps(mesh, q, dq, dt, args.steps, stream=stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms = t_start.elapsed_time(t_end)
+    kern = {}
+    for k, name in hdg.KERNEL_NAMES.items():
+        tot, n = hdg.hdg_timing_read(mesh, k)
+        kern[name] = (tot, n)
+    hdg.hdg_timing_enable(mesh, False)
+    red = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
+
+    n_visc = info["n_viscous"]
+    n_eul = w.mesh.n_elem - n_visc
+    counts = {"viscous_traces": n_visc, "residual_euler": n_eul, "residual_viscous": n_visc}
+    kinds = {"viscous_traces": 0, "residual_euler": 1, "residual_viscous": 2}
+    dom = max(kern, key=lambda k: kern[k][0])
+    tot, n = kern[dom]
+    avg_s = tot / max(n, 1) / 1e3
+    bytes_launch = algorithmic_bytes(kinds[dom], counts[dom], N, fused_rk=True)
+    achieved = bytes_launch / avg_s / 1e9
+    evals = 3 * args.steps
+    out = {
+        "metric": METRIC,
+        "value": nodes * 4 * evals / (ms / 1e3),
+        "unit": "DOF-residual evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "form": "plain FP64", "elements": w.mesh.n_elem, "P": w.P,
+                   "nodes": nodes, "dof": nodes * 4, "viscous_elements": n_visc,
+                   "residuals_per_step": 3, "dt": dt, "rk": "3-stage low-storage (2N)"},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch},
+        "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern.items()},
+        "node_evals_per_s": nodes * evals / (ms / 1e3),
+        "state_finite": bool(red["finite"]),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, q0, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

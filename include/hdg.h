@@ -1,0 +1,186 @@
+/*
+ * hdg.h -- C ABI of the hybrid Navier-Stokes-LES / Euler DGSEM residual library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the spatial residual of a discontinuous Galerkin spectral
+ * element method (DGSEM) on curvilinear hexahedra, in which every element
+ * carries an equation flag: flagged (viscous/turbulent) elements solve the
+ * Navier-Stokes equations with an LES eddy viscosity, the others the Euler
+ * equations, and neighbours of either kind couple through numerical face
+ * fluxes.  Paper: Otmani, Mateo-Gabin, Rubio, Ferrer, "Accelerating high order
+ * discontinuous Galerkin solvers through a clustering-based
+ * viscous/turbulent-inviscid domain decomposition" (arXiv 2403.05463):
+ *   - the per-element choice of equations and the three kinds of face
+ *     coupling: Sec. 2.3;
+ *   - the element region ID that the flag stands for: Sec. 2.1 (element
+ *     means of node memberships);
+ *   - the equations (convective flux, viscous + turbulent stress, Vreman
+ *     model): App. A;
+ *   - the DGSEM discretisation (mapped element, contravariant fluxes, weak
+ *     form with a numerical flux, BR1 viscous treatment, collocated
+ *     quadrature): App. B;
+ *   - the low-storage third-order explicit Runge-Kutta time marching: Sec. 2.3.
+ * Equation system used here: incompressible flow in artificial-compressibility
+ * form with unknowns (p, u, v, w) and unit density,
+ *     dp/dt + c0^2 div u = 0,   du/dt + div(u u + p I) = div(2 (nu + nu_t) S),
+ * with the viscous right-hand side present only on flagged elements.
+ *
+ * Conventions
+ *   N = P + 1 Gauss-Lobatto-Legendre nodes per direction, N^3 per element.
+ *   State / residual layout: element-major, then field (p, u, v, w), then node
+ *   a + N b + N^2 c (a along xi).  Element e starts at offset 4 N^3 e.
+ *   Geometry: (Pg+1)^3 control points per element at equispaced reference
+ *   positions -1 + 2k/Pg, stored [e][3][(Pg+1)^3], x index fastest.
+ *   Local faces: 0 xi-, 1 xi+, 2 eta-, 3 eta+, 4 zeta-, 5 zeta+.  Face
+ *   coordinates (a, b): (eta, zeta) on faces 0/1, (xi, zeta) on 2/3, (xi, eta)
+ *   on 4/5.  orient[e][f] maps my face coordinates to the neighbour's:
+ *   (s, t) = bit0 ? (b, a) : (a, b); a' = bit1 ? N-1-s : s; b' = bit2 ? N-1-t : t.
+ *   nbr[e][f] >= 0 is the neighbouring element; HDG_WALL (no-slip wall, ghost
+ *   state (p, -u)) or HDG_FARFIELD (ghost state q_inf) marks a boundary face.
+ *
+ * Ownership
+ *   The caller owns every state, residual and RK buffer (device pointers,
+ *   e.g. from torch tensors).  The library owns geometry, metric terms,
+ *   connectivity, element lists and its scratch (face viscous-flux traces, the
+ *   RK ping-pong state, reduction partials) from hdg_mesh_create to
+ *   hdg_mesh_destroy.  No call after hdg_mesh_create allocates device memory.
+ *
+ * Errors
+ *   Every call returns an hdg_status and never throws across the ABI;
+ *   hdg_last_error() gives a thread-local message for the last failure.
+ *   hdg_mesh_create validates the mesh (symmetric connectivity, mutually
+ *   inverse orientation codes, positive Jacobian).  Kernel launch failures
+ *   map to HDG_EHIP.  Calls taking a stream are asynchronous on it, except
+ *   hdg_reduce and hdg_timing_read, which synchronise it.
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hdg_ctx hdg_ctx;
+typedef struct hdg_mesh hdg_mesh;
+
+typedef enum {
+    HDG_OK = 0,
+    HDG_EINVAL = -1,        /* bad argument (null pointer, size, code) */
+    HDG_ENOMEM = -2,        /* device or host allocation failed */
+    HDG_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    HDG_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+    HDG_EMESH = -5,         /* inconsistent mesh description */
+    HDG_ENONFINITE = -6     /* hdg_reduce found a NaN or Inf */
+} hdg_status;
+
+typedef enum { HDG_F64 = 0, HDG_F32 = 1 } hdg_prec;
+
+enum { HDG_WALL = -1, HDG_FARFIELD = -2 };
+enum { HDG_LES_NONE = 0, HDG_LES_SMAGORINSKY = 1, HDG_LES_VREMAN = 2 };
+
+/* Kernel classes reported by hdg_timing_read. */
+enum {
+    HDG_KERNEL_VISCOUS_TRACES = 0,   /* BR1 gradient + LES + viscous face traces, flagged elements */
+    HDG_KERNEL_RESIDUAL_EULER = 1,   /* residual (or fused RK stage) of Euler elements */
+    HDG_KERNEL_RESIDUAL_VISCOUS = 2, /* residual (or fused RK stage) of flagged elements */
+    HDG_KERNEL_COUNT = 3
+};
+
+/* Mesh description (Sec. 2.1: per-element region ID; App. B: curvilinear
+ * hexahedra mapped from the reference cube by a polynomial map).  All
+ * pointers are host pointers read during hdg_mesh_create only. */
+typedef struct {
+    int32_t n_elem;
+    const int32_t *P;          /* [n_elem] polynomial order, 1..7; must be uniform (else HDG_EUNSUPPORTED) */
+    int32_t geom_order;        /* Pg >= 1: geometry control points per direction minus one */
+    const double *xyz_geom;    /* [n_elem][3][(Pg+1)^3] */
+    const uint8_t *flag;       /* [n_elem] 1: Navier-Stokes + LES, 0: Euler (Sec. 2.3) */
+    const int32_t *nbr;        /* [n_elem][6] */
+    const int8_t *nbr_face;    /* [n_elem][6] the neighbour's local face, -1 on boundaries */
+    const int8_t *orient;      /* [n_elem][6] orientation code 0..7 */
+} hdg_mesh_desc;
+
+/* Physical and scheme parameters. */
+typedef struct {
+    double c0sq;         /* artificial sound speed squared, > 0 */
+    double nu;           /* kinematic viscosity on flagged elements, >= 0 */
+    int32_t les_model;   /* HDG_LES_* (App. A: Vreman; Smagorinsky also offered) */
+    double C_les;        /* Cs (Smagorinsky) or Cv (Vreman), >= 0 */
+    int32_t mixed_face;  /* viscous flux on a face with one Euler side: 0 = BR1 mean with
+                            a zero Euler-side flux, 1 = no viscous flux */
+    double q_inf[4];     /* far-field state (p, u, v, w) */
+} hdg_params;
+
+/* Bind a context to HIP device `device`. */
+hdg_status hdg_init(hdg_ctx **ctx, int32_t device);
+void hdg_finalize(hdg_ctx *ctx);
+
+/* Validate the mesh, build the Gauss-Lobatto-Legendre rule, node geometry,
+ * metric terms (curl form), face normals, element lists, and upload them.
+ * Synchronous.  HDG_EMESH on inconsistent connectivity or J <= 0. */
+hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *desc, const hdg_params *params,
+                           hdg_mesh **out);
+void hdg_mesh_destroy(hdg_mesh *mesh);
+
+/* Replace the equation flags (a new clustering, Sec. 2.3 static/dynamic
+ * clustering).  Host array [n_elem].  Synchronous. */
+hdg_status hdg_mesh_set_flags(hdg_mesh *mesh, const uint8_t *flag_host);
+hdg_status hdg_mesh_set_params(hdg_mesh *mesh, const hdg_params *params);
+
+/* Sizes: nodes = n_elem N^3, state_len = 4 nodes (doubles), bytes of device
+ * memory the mesh holds, number of flagged elements.  Any pointer may be NULL. */
+hdg_status hdg_mesh_info(const hdg_mesh *mesh, int64_t *n_nodes, int64_t *state_len,
+                         int64_t *device_bytes, int32_t *n_viscous);
+
+/* Physical coordinates of the collocation nodes, host array [n_elem][3][N^3]. */
+hdg_status hdg_mesh_node_coords(const hdg_mesh *mesh, double *xyz_host);
+
+/* Host-only (no device needed): the geometry hdg_mesh_create would build for
+ * this description (App. B mapping): node coordinates xyz [n_elem][3][N^3],
+ * Jacobian J [n_elem][N^3], contravariant metric terms Ja [n_elem][3 (i)][3 (d)][N^3]
+ * in curl form, and the GLL rule xi[N], w[N], D[N*N] (D[i*N+j] = l_j'(xi_i)).
+ * Any output may be NULL.  Validates the description like hdg_mesh_create. */
+hdg_status hdg_mesh_geometry(const hdg_mesh_desc *desc, double *xyz, double *J, double *Ja,
+                             double *xi, double *w, double *D);
+
+/* R = dq/dt of the semi-discrete hybrid DGSEM (App. B with the Sec. 2.3
+ * coupling), for device state q_dev, into device r_dev (same layout, must not
+ * alias q_dev).  prec: HDG_F64 (double in, double out). */
+hdg_status hdg_residual(hdg_mesh *mesh, const void *q_dev, void *r_dev, hdg_prec prec, void *stream);
+
+/* nsteps steps of the three-stage low-storage RK (Sec. 2.3; Williamson 2N
+ * coefficients A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15)) on the device
+ * state q_dev in place.  dq_dev is the caller's second register (same length);
+ * its content on entry is ignored, on return it holds the last stage's
+ * register.  dt > 0 fixed. */
+hdg_status hdg_rk3_steps(hdg_mesh *mesh, double *q_dev, double *dq_dev, double dt, int32_t nsteps,
+                         hdg_prec prec, void *stream);
+
+/* Per-field reductions of a device array in state layout: mass-weighted sum
+ * sum w_a w_b w_c J r (discrete conservation), mass-weighted L2 norm and max
+ * |r|.  Host outputs, any may be NULL.  Synchronises the stream.
+ * HDG_ENONFINITE if any entry is NaN or Inf (outputs still written). */
+hdg_status hdg_reduce(hdg_mesh *mesh, const double *r_dev, double out_sum[4], double out_l2[4],
+                      double out_max[4], void *stream);
+
+/* Kernel timing: while enabled, every launch the mesh makes is bracketed by
+ * HIP events on its stream (up to 65536 launches are kept).  hdg_timing_read
+ * synchronises on the last event, then returns the summed duration and count
+ * of the launches of one kernel class (HDG_KERNEL_*) since enabling. */
+hdg_status hdg_timing_enable(hdg_mesh *mesh, int32_t enable);
+hdg_status hdg_timing_read(hdg_mesh *mesh, int32_t kernel_class, double *total_ms, int64_t *launches);
+
+/* Plain device-to-device copy kernel (nbytes a multiple of 16, 16-byte aligned
+ * pointers): the HBM bandwidth probe that calibrates traffic counters. */
+hdg_status hdg_stream_copy(hdg_ctx *ctx, void *dst_dev, const void *src_dev, int64_t nbytes,
+                           void *stream);
+
+/* Message describing the last error on this thread ("" if none). */
+const char *hdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDG_H */

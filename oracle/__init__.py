@@ -17,6 +17,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+def needs_build() -> bool:
+    return not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+
+
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (always recompiles)."""
     tmp = _LIB + ".tmp"
@@ -45,7 +49,7 @@ def make_params(c0sq=25.0, nu=1e-3, les_model=1, C_les=0.1, mixed_face=0, q_inf=
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if needs_build():
             build()
         L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)

@@ -1,0 +1,570 @@
+// gfx950 kernels of the hybrid Navier-Stokes-LES / Euler DGSEM residual.
+//
+// One workgroup per element, one lane per collocation node (N^3 nodes rounded
+// up to whole 64-lane waves).  Work is split by equation flag (Sec. 2.3): the
+// viscous-trace kernel and the viscous residual run only on flagged elements,
+// the Euler residual carries no gradient, LES or viscous-flux code at all.
+//
+// Per element the residual kernel
+//   1. loads the state and the metric terms of its own nodes (coalesced),
+//   2. [flagged] lifts the velocity gradient (BR1: volume derivative of
+//      Ja^i u plus a face correction towards the mean of the two traces),
+//      evaluates the eddy viscosity and the viscous flux 2 (nu + nu_t) S,
+//   3. forms the contravariant fluxes F^i = Ja^i . (f_conv - f_visc) in LDS,
+//   4. takes their reference divergence with the N-point derivative matrix,
+//   5. adds, on face nodes, the jump between the single-valued numerical
+//      flux (Roe + BR1 mean of the stored viscous face traces) and the
+//      element's own flux, divided by the end-point weight,
+//   6. scales by -1/J and writes R, or applies a low-storage RK stage.
+// These are the strong-form (summation-by-parts) equivalent of the weak form
+// in App. B: on Gauss-Lobatto nodes the two agree to round-off.
+#include "hdg_internal.h"
+
+namespace hdg {
+namespace {
+
+template <int N>
+struct Shape {
+    static constexpr int N2 = N * N;
+    static constexpr int N3 = N * N * N;
+    static constexpr int NT = ((N3 + 63) / 64) * 64;
+};
+
+// Workgroups are dealt to the XCDs round-robin; give every XCD a contiguous
+// run of the (spatially ordered) element list so neighbour traces hit its L2.
+__device__ __forceinline__ int xcd_slot(int per_xcd)
+{
+    const int b = blockIdx.x;
+    return (b % kXcd) * per_xcd + b / kXcd;
+}
+
+template <int N>
+__device__ __forceinline__ int face_node(int f, int a, int b)
+{
+    const int s = (f & 1) ? N - 1 : 0;
+    const int d = f >> 1;
+    return d == 0 ? s + N * (a + N * b) : d == 1 ? a + N * (s + N * b) : a + N * (b + N * s);
+}
+
+template <int N>
+__device__ __forceinline__ void orient_map(int o, int a, int b, int &a2, int &b2)
+{
+    const int s = (o & 1) ? b : a, t = (o & 1) ? a : b;
+    a2 = (o & 2) ? N - 1 - s : s;
+    b2 = (o & 4) ? N - 1 - t : t;
+}
+
+// Roe flux of the artificial-compressibility system along the unit normal n
+// (Sec. 2.3: Roe Riemann solver).  The mean-state Jacobian has eigenvalues
+// u_n (twice, tangential) and u_n +- a, a = sqrt(u_n^2 + c0^2); the jump is
+// projected on its eigenvectors in closed form.
+__device__ __forceinline__ void roe_flux(double c0sq, const double (&qL)[4], const double (&qR)[4],
+                                         const double (&n)[3], double (&F)[4])
+{
+    const double unL = qL[1] * n[0] + qL[2] * n[1] + qL[3] * n[2];
+    const double unR = qR[1] * n[0] + qR[2] * n[1] + qR[3] * n[2];
+    const double ub[3] = {0.5 * (qL[1] + qR[1]), 0.5 * (qL[2] + qR[2]), 0.5 * (qL[3] + qR[3])};
+    const double un = ub[0] * n[0] + ub[1] * n[1] + ub[2] * n[2];
+    const double a = sqrt(un * un + c0sq);
+    const double ia = 1.0 / a;
+    const double dp = qR[0] - qL[0];
+    const double du[3] = {qR[1] - qL[1], qR[2] - qL[2], qR[3] - qL[3]};
+    const double s = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+    const double pip = a - un, pim = -a - un;
+    const double alp = 0.5 * ia * (dp - pim * s);     // acoustic wave un + a
+    const double alm = 0.5 * ia * (pip * s - dp);     // acoustic wave un - a
+    const double lp = (un + a) * alp, lm = (a - un) * alm, l0 = fabs(un);
+    F[0] = 0.5 * (c0sq * (unL + unR) - (lp * pip + lm * pim));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double vp = (pip * n[d] + ub[d]) * ia;
+        const double vm = -(pim * n[d] + ub[d]) * ia;
+        const double tang = du[d] - alp * vp - alm * vm;
+        const double flux = qL[1 + d] * unL + qR[1 + d] * unR + (qL[0] + qR[0]) * n[d];
+        F[1 + d] = 0.5 * (flux - (lp * vp + lm * vm + l0 * tang));
+    }
+}
+
+// LES eddy viscosity from the velocity gradient G[r][d] = du_r/dx_d
+// (App. A: Vreman, unit density; Smagorinsky as the alternative closure).
+__device__ __forceinline__ double les_nut(int model, double C, double delta, const double (&G)[3][3])
+{
+    if (model == HDG_LES_SMAGORINSKY) {
+        double ss = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double sd = 0.5 * (G[r][d] + G[d][r]);
+                ss += sd * sd;
+            }
+        const double cd = C * delta;
+        return cd * cd * sqrt(2.0 * ss);
+    }
+    if (model == HDG_LES_VREMAN) {
+        // alpha_ij = du_j/dx_i = G[j][i]; beta_ij = Delta^2 sum_m G[i][m] G[j][m]
+        double b[3][3], aa = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) aa += G[r][d] * G[r][d];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                b[i][j] = delta * delta * (G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2]);
+        double B = b[0][0] * b[1][1] - b[0][1] * b[0][1] + b[0][0] * b[2][2] - b[0][2] * b[0][2]
+                 + b[1][1] * b[2][2] - b[1][2] * b[1][2];
+        B = B > 0.0 ? B : 0.0;
+        return aa > 0.0 ? C * sqrt(B / aa) : 0.0;
+    }
+    return 0.0;
+}
+
+// Outside state at a face node: neighbour's trace or boundary ghost.
+// Returns the coordinates of the node in the face owner's ordering.
+template <int N, int NF>
+__device__ __forceinline__ void outside_state(const ElemArgs &A, const FaceRef &fr, int fa, int fb,
+                                              const double (&q)[4], double (&qo)[NF], int &oa, int &ob)
+{
+    constexpr int N3 = Shape<N>::N3;
+    const bool own = fr.code & kOwnerBit;
+    oa = fa;
+    ob = fb;
+    if (fr.nbr >= 0) {
+        int a2, b2;
+        orient_map<N>(fr.code & 7, fa, fb, a2, b2);
+        if (!own) { oa = a2; ob = b2; }
+        const double *qn = A.q + (size_t)fr.nbr * 4 * N3 + face_node<N>((fr.code >> 3) & 7, a2, b2);
+#pragma unroll
+        for (int c = 0; c < NF; ++c) qo[c] = qn[(4 - NF + c) * N3];
+    } else if (fr.nbr == HDG_WALL) {
+#pragma unroll
+        for (int c = 0; c < NF; ++c) qo[c] = (4 - NF + c == 0) ? q[0] : -q[4 - NF + c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NF; ++c) qo[c] = A.qinf[4 - NF + c];
+    }
+}
+
+// BR1 gradient G[r][d] = du_r/dx_d of the velocity on a flagged element.
+// Uses lds[12 * N3] as scratch; all lanes of the block must call it.
+template <int N>
+__device__ __forceinline__ void br1_gradient(const ElemArgs &A, int e, int tid, bool act, int i, int j, int k,
+                                             const double (&Dx)[N], const double (&Dy)[N], const double (&Dz)[N],
+                                             const double (&Ja)[3][3], double invJ, const double (&q)[4],
+                                             double *lds, double (&G)[3][3])
+{
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
+    if (act) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) lds[r * N3 + tid] = q[1 + r];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) lds[(3 + 3 * ii + d) * N3 + tid] = Ja[ii][d];
+    }
+    __syncthreads();
+    double JG[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) JG[r][d] = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const int n0 = m + N * j + N2 * k, n1 = i + N * m + N2 * k, n2 = i + N * j + N2 * m;
+        double u0[3], u1[3], u2[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            u0[r] = lds[r * N3 + n0];
+            u1[r] = lds[r * N3 + n1];
+            u2[r] = lds[r * N3 + n2];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double g0 = Dx[m] * lds[(3 + d) * N3 + n0];
+            const double g1 = Dy[m] * lds[(6 + d) * N3 + n1];
+            const double g2 = Dz[m] * lds[(9 + d) * N3 + n2];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) JG[r][d] += g0 * u0[r] + g1 * u1[r] + g2 * u2[r];
+        }
+    }
+    // face correction: (u* (s n)_out - u (+-Ja^dir)) / w_end, u* the mean of the traces
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+        const int idx = dir == 0 ? i : dir == 1 ? j : k;
+        if (act && (idx == 0 || idx == N - 1)) {
+            const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
+            const int fa = dir == 0 ? j : i;
+            const int fb = dir == 2 ? j : k;
+            const FaceRef fr = A.conn[(size_t)e * 6 + f];
+            double uo[3];
+            int oa, ob;
+            outside_state<N, 3>(A, fr, fa, fb, q, uo, oa, ob);
+            const double *g = A.fgeo + ((size_t)fr.face * N2 + oa + N * ob) * 4;
+            const double so = (fr.code & kOwnerBit) ? g[3] : -g[3];
+            const double sn[3] = {g[0] * so, g[1] * so, g[2] * so};
+            const double sf = (f & 1) ? 1.0 : -1.0;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const double ustar = 0.5 * (q[1 + r] + uo[r]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) JG[r][d] += (ustar * sn[d] - q[1 + r] * sf * Ja[dir][d]) * A.inv_wend;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) G[r][d] = JG[r][d] * invJ;
+    __syncthreads();   // lds is reused by the caller
+}
+
+template <int N>
+struct ElemCtx {
+    int e, tid, t, i, j, k;
+    bool act;
+    double q[4];
+    double invJ;
+    double Ja[3][3];
+    double Dx[N], Dy[N], Dz[N];
+};
+
+// Common prologue: element id, own state and metric terms, derivative rows.
+// Returns false for workgroups past the end of the list (uniform per block).
+template <int N>
+__device__ __forceinline__ bool load_element(const ElemArgs &A, double *sD, ElemCtx<N> &c)
+{
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
+    const int slot = xcd_slot(A.per_xcd);
+    if (slot >= A.count) return false;
+    c.e = A.list[slot];
+    c.tid = threadIdx.x;
+    c.act = c.tid < N3;
+    c.t = c.act ? c.tid : N3 - 1;
+    c.i = c.t % N;
+    c.j = (c.t / N) % N;
+    c.k = c.t / N2;
+    for (int x = c.tid; x < N2; x += blockDim.x) sD[x] = A.Dmat[x];
+    const double *qe = A.q + (size_t)c.e * 4 * N3;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) c.q[f] = qe[f * N3 + c.t];
+    const double *me = A.metric + (size_t)c.e * 10 * N3;
+    c.invJ = me[c.t];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) c.Ja[ii][d] = me[(1 + 3 * ii + d) * N3 + c.t];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        c.Dx[m] = sD[c.i * N + m];
+        c.Dy[m] = sD[c.j * N + m];
+        c.Dz[m] = sD[c.k * N + m];
+    }
+    return true;
+}
+
+template <int N>
+__device__ __forceinline__ void viscous_flux(const ElemArgs &A, ElemCtx<N> &c, double *lds, double (&fv)[3][3])
+{
+    double G[3][3];
+    br1_gradient<N>(A, c.e, c.tid, c.act, c.i, c.j, c.k, c.Dx, c.Dy, c.Dz, c.Ja, c.invJ, c.q, lds, G);
+    const double mu = A.nu + les_nut(A.les_model, A.C_les, A.delta[c.e], G);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fv[r][d] = mu * (G[r][d] + G[d][r]);
+}
+
+// Viscous face traces of flagged elements: fv . (s n) at every face node, with
+// the face owner's normal, stored per face side for the BR1 mean.
+template <int N>
+__global__ __launch_bounds__(Shape<N>::NT) void k_viscous_traces(ElemArgs A)
+{
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
+    __shared__ double lds[12 * N3];
+    __shared__ double sD[N2];
+    ElemCtx<N> c;
+    if (!load_element<N>(A, sD, c)) return;
+    double fv[3][3];
+    viscous_flux<N>(A, c, lds, fv);
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+        const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
+        if (c.act && (idx == 0 || idx == N - 1)) {
+            const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
+            const int fa = dir == 0 ? c.j : c.i;
+            const int fb = dir == 2 ? c.j : c.k;
+            const FaceRef fr = A.conn[(size_t)c.e * 6 + f];
+            const bool own = fr.code & kOwnerBit;
+            int oa = fa, ob = fb;
+            if (!own) orient_map<N>(fr.code & 7, fa, fb, oa, ob);
+            const int fnode = oa + N * ob;
+            const double *g = A.fgeo + ((size_t)fr.face * N2 + fnode) * 4;
+            const double sn[3] = {g[0] * g[3], g[1] * g[3], g[2] * g[3]};
+            double *out = A.fvt + (((size_t)fr.face * 2 + (own ? 0 : 1)) * N2 + fnode) * 3;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) out[r] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
+        }
+    }
+}
+
+template <int N, bool VISC, int EPI>
+__global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
+{
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
+    __shared__ double lds[12 * N3];
+    __shared__ double sD[N2];
+    ElemCtx<N> c;
+    if (!load_element<N>(A, sD, c)) return;
+
+    double fv[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fv[r][d] = 0.0;
+    if constexpr (VISC) viscous_flux<N>(A, c, lds, fv);
+
+    // contravariant fluxes F^i_row = sum_d Ja^i_d (f_conv - f_visc)_{row,d}
+    {
+        double f[4][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f[0][d] = A.c0sq * c.q[1 + d];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) f[1 + r][d] = c.q[1 + r] * c.q[1 + d] + (r == d ? c.q[0] : 0.0) - fv[r][d];
+        }
+        if (c.act) {
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+                for (int row = 0; row < 4; ++row)
+                    lds[(ii * 4 + row) * N3 + c.tid] =
+                        c.Ja[ii][0] * f[row][0] + c.Ja[ii][1] * f[row][1] + c.Ja[ii][2] * f[row][2];
+        }
+    }
+    __syncthreads();
+
+    // reference divergence
+    double V[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const int n0 = m + N * c.j + N2 * c.k, n1 = c.i + N * m + N2 * c.k, n2 = c.i + N * c.j + N2 * m;
+#pragma unroll
+        for (int row = 0; row < 4; ++row)
+            V[row] += c.Dx[m] * lds[row * N3 + n0] + c.Dy[m] * lds[(4 + row) * N3 + n1]
+                    + c.Dz[m] * lds[(8 + row) * N3 + n2];
+    }
+
+    // face nodes: single-valued numerical flux minus own flux, over w_end
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+        const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
+        if (c.act && (idx == 0 || idx == N - 1)) {
+            const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
+            const int fa = dir == 0 ? c.j : c.i;
+            const int fb = dir == 2 ? c.j : c.k;
+            const FaceRef fr = A.conn[(size_t)c.e * 6 + f];
+            const bool own = fr.code & kOwnerBit;
+            double qo[4];
+            int oa, ob;
+            outside_state<N, 4>(A, fr, fa, fb, c.q, qo, oa, ob);
+            const int fnode = oa + N * ob;
+            const double *g = A.fgeo + ((size_t)fr.face * N2 + fnode) * 4;
+            const double nh[3] = {g[0], g[1], g[2]};
+            const double s = g[3];
+            double qL[4], qR[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                qL[x] = own ? c.q[x] : qo[x];
+                qR[x] = own ? qo[x] : c.q[x];
+            }
+            double F[4];
+            roe_flux(A.c0sq, qL, qR, nh, F);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) F[x] *= s;
+            const bool nb_visc = fr.nbr >= 0 && A.flag[fr.nbr];
+            const bool visL = own ? VISC : nb_visc;
+            const bool visR = own ? nb_visc : VISC;
+            if (visL || visR) {
+                const double *tv = A.fvt + ((size_t)fr.face * 2 * N2 + fnode) * 3;
+                double fvn[3];
+                if (fr.nbr < 0) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) fvn[r] = tv[r];
+                } else {
+                    const bool keep = A.mixed_face == 0 || (visL && visR);
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        const double vl = visL ? tv[r] : 0.0;
+                        const double vr = visR ? tv[N2 * 3 + r] : 0.0;
+                        fvn[r] = keep ? 0.5 * (vl + vr) : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 3; ++r) F[1 + r] -= fvn[r];
+            }
+            const double so = own ? 1.0 : -1.0;
+            const double sf = (f & 1) ? 1.0 : -1.0;
+#pragma unroll
+            for (int row = 0; row < 4; ++row)
+                V[row] += (so * F[row] - sf * lds[(dir * 4 + row) * N3 + c.tid]) * A.inv_wend;
+        }
+    }
+
+    if (!c.act) return;
+    const size_t base = (size_t)c.e * 4 * N3 + c.tid;
+#pragma unroll
+    for (int row = 0; row < 4; ++row) {
+        const double R = -V[row] * c.invJ;
+        const size_t idx = base + (size_t)row * N3;
+        if constexpr (EPI == (int)Epi::Residual) {
+            A.out[idx] = R;
+        } else {
+            const double d = A.first_stage ? A.dt * R : A.rkA * A.dq[idx] + A.dt * R;
+            A.dq[idx] = d;
+            A.out[idx] = c.q[row] + A.rkB * d;
+        }
+    }
+}
+
+// Per-block partial reductions over whole elements: sum(m r), sum(m r^2),
+// max |r| per field, and a non-finite flag.  Fixed order, no atomics.
+template <int N>
+__global__ __launch_bounds__(256) void k_reduce_partial(const double *r, const double *mass, int64_t ne,
+                                                        double *partials)
+{
+    constexpr int N3 = Shape<N>::N3;
+    __shared__ double red[13][256];
+    double acc[13];
+#pragma unroll
+    for (int x = 0; x < 13; ++x) acc[x] = 0.0;
+    const int64_t total = ne * N3;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = p / N3, n = p % N3;
+        const double m = mass[p];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const double v = r[(e * 4 + f) * N3 + n];
+            acc[f] += m * v;
+            acc[4 + f] += m * v * v;
+            const double av = fabs(v);
+            acc[8 + f] = av > acc[8 + f] ? av : acc[8 + f];
+            if (!isfinite(v)) acc[12] = 1.0;
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 13; ++x) red[x][threadIdx.x] = acc[x];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int x = 0; x < 8; ++x) red[x][threadIdx.x] += red[x][threadIdx.x + w];
+#pragma unroll
+            for (int x = 8; x < 13; ++x) red[x][threadIdx.x] = fmax(red[x][threadIdx.x], red[x][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 13) partials[(size_t)blockIdx.x * 13 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void k_reduce_final(const double *partials, int nblocks, double *out)
+{
+    if (threadIdx.x >= 13) return;
+    const int x = threadIdx.x;
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        const double p = partials[(size_t)b * 13 + x];
+        v = x < 8 ? v + p : fmax(v, p);
+    }
+    out[x] = v;
+}
+
+__global__ __launch_bounds__(256) void k_copy(uint4 *dst, const uint4 *src, int64_t n16)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+template <int N>
+hipError_t launch_traces_n(const ElemArgs &a, hipStream_t s)
+{
+    if (a.count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_viscous_traces<N>, dim3(kXcd * a.per_xcd), dim3(Shape<N>::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_residual_n(bool viscous, Epi epi, const ElemArgs &a, hipStream_t s)
+{
+    if (a.count == 0) return hipSuccess;
+    const dim3 grid(kXcd * a.per_xcd), block(Shape<N>::NT);
+    if (viscous) {
+        if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<N, true, 0>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_residual<N, true, 1>), grid, block, 0, s, a);
+    } else {
+        if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<N, false, 0>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_residual<N, false, 1>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_reduce_n(const double *r, const double *mass, int64_t ne, double *partials, int nblocks,
+                           double *final13, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_partial<N>, dim3(nblocks), dim3(256), 0, s, r, mass, ne, partials);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, partials, nblocks, final13);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define HDG_DISPATCH_N(N, CALL)                                                       \
+    switch (N) {                                                                       \
+    case 2: return CALL(2);                                                            \
+    case 3: return CALL(3);                                                            \
+    case 4: return CALL(4);                                                            \
+    case 5: return CALL(5);                                                            \
+    case 6: return CALL(6);                                                            \
+    case 7: return CALL(7);                                                            \
+    case 8: return CALL(8);                                                            \
+    default: return hipErrorInvalidValue;                                              \
+    }
+
+hipError_t launch_viscous_traces(int N, const ElemArgs &a, hipStream_t s)
+{
+#define C_(n) launch_traces_n<n>(a, s)
+    HDG_DISPATCH_N(N, C_)
+#undef C_
+}
+
+hipError_t launch_residual(int N, bool viscous, Epi epi, const ElemArgs &a, hipStream_t s)
+{
+#define C_(n) launch_residual_n<n>(viscous, epi, a, s)
+    HDG_DISPATCH_N(N, C_)
+#undef C_
+}
+
+hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_elem, double *partials,
+                         int nblocks, double *final13, hipStream_t s)
+{
+#define C_(n) launch_reduce_n<n>(r, mass, n_elem, partials, nblocks, final13, s)
+    HDG_DISPATCH_N(N, C_)
+#undef C_
+}
+
+hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s)
+{
+    const int64_t n16 = nbytes / 16;
+    int64_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (uint4 *)dst, (const uint4 *)src, n16);
+    return hipGetLastError();
+}
+
+}  // namespace hdg

@@ -1,0 +1,276 @@
+"""Python binding of the C ABI in ``include/hdg.h`` (argument marshalling only).
+
+Every function keeps the C name and forwards plain pointers and sizes to
+``libhdg.so``; device buffers are torch tensors on the GPU (used only for
+memory and streams).  There is no fallback: if the library or a GPU is
+missing the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdg.so")
+
+HDG_OK, HDG_EINVAL, HDG_ENOMEM, HDG_EHIP, HDG_EUNSUPPORTED, HDG_EMESH, HDG_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+HDG_F64, HDG_F32 = 0, 1
+HDG_WALL, HDG_FARFIELD = -1, -2
+HDG_LES_NONE, HDG_LES_SMAGORINSKY, HDG_LES_VREMAN = 0, 1, 2
+HDG_KERNEL_VISCOUS_TRACES, HDG_KERNEL_RESIDUAL_EULER, HDG_KERNEL_RESIDUAL_VISCOUS = 0, 1, 2
+KERNEL_NAMES = {0: "viscous_traces", 1: "residual_euler", 2: "residual_viscous"}
+
+EXPORTED = [
+    "hdg_init", "hdg_finalize", "hdg_mesh_create", "hdg_mesh_destroy", "hdg_mesh_set_flags",
+    "hdg_mesh_set_params", "hdg_mesh_info", "hdg_mesh_node_coords", "hdg_mesh_geometry", "hdg_residual",
+    "hdg_rk3_steps",
+    "hdg_reduce", "hdg_timing_enable", "hdg_timing_read", "hdg_stream_copy", "hdg_last_error",
+]
+
+
+class HdgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hdg status {status}: {msg}")
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_elem", C.c_int32), ("P", C.POINTER(C.c_int32)), ("geom_order", C.c_int32),
+                ("xyz_geom", C.POINTER(C.c_double)), ("flag", C.POINTER(C.c_uint8)),
+                ("nbr", C.POINTER(C.c_int32)), ("nbr_face", C.POINTER(C.c_int8)),
+                ("orient", C.POINTER(C.c_int8))]
+
+
+class Params(C.Structure):
+    _fields_ = [("c0sq", C.c_double), ("nu", C.c_double), ("les_model", C.c_int32),
+                ("C_les", C.c_double), ("mixed_face", C.c_int32), ("q_inf", C.c_double * 4)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load ``libhdg.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2403_05463_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+        L.hdg_init.argtypes = [C.POINTER(vp), i32]
+        L.hdg_finalize.argtypes = [vp]
+        L.hdg_finalize.restype = None
+        L.hdg_mesh_create.argtypes = [vp, C.POINTER(MeshDesc), C.POINTER(Params), C.POINTER(vp)]
+        L.hdg_mesh_destroy.argtypes = [vp]
+        L.hdg_mesh_destroy.restype = None
+        L.hdg_mesh_set_flags.argtypes = [vp, C.POINTER(C.c_uint8)]
+        L.hdg_mesh_set_params.argtypes = [vp, C.POINTER(Params)]
+        L.hdg_mesh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
+        L.hdg_mesh_node_coords.argtypes = [vp, dp]
+        L.hdg_mesh_geometry.argtypes = [C.POINTER(MeshDesc), dp, dp, dp, dp, dp, dp]
+        L.hdg_residual.argtypes = [vp, vp, vp, i32, vp]
+        L.hdg_rk3_steps.argtypes = [vp, vp, vp, C.c_double, i32, i32, vp]
+        L.hdg_reduce.argtypes = [vp, vp, dp, dp, dp, vp]
+        L.hdg_timing_enable.argtypes = [vp, i32]
+        L.hdg_timing_read.argtypes = [vp, i32, dp, C.POINTER(i64)]
+        L.hdg_stream_copy.argtypes = [vp, vp, vp, i64, vp]
+        L.hdg_last_error.restype = C.c_char_p
+        for name in EXPORTED:
+            f = getattr(L, name)
+            if name not in ("hdg_finalize", "hdg_mesh_destroy", "hdg_last_error"):
+                f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str = ""):
+    if status != HDG_OK:
+        raise HdgError(status, (what + ": " if what else "") + lib().hdg_last_error().decode())
+
+
+def hdg_last_error() -> str:
+    return lib().hdg_last_error().decode()
+
+
+def make_params(c0sq=25.0, nu=1e-3, les_model=HDG_LES_SMAGORINSKY, C_les=0.1, mixed_face=0,
+                q_inf=(0.0, 0.0, 0.0, 0.0)) -> Params:
+    p = Params()
+    p.c0sq, p.nu, p.les_model, p.C_les, p.mixed_face = c0sq, nu, les_model, C_les, mixed_face
+    for k in range(4):
+        p.q_inf[k] = float(q_inf[k])
+    return p
+
+
+def _ptr(t) -> int:
+    """Device pointer of a torch tensor (or an int address)."""
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Context:
+    def __init__(self, handle: int, device: int):
+        self.handle, self.device = handle, device
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.hdg_finalize(self.handle)
+            self.handle = None
+
+
+class Mesh:
+    """Owner of an ``hdg_mesh`` handle plus its sizes."""
+
+    def __init__(self, ctx: Context, handle: int, n_elem: int, P: int):
+        self.ctx, self.handle, self.n_elem, self.P = ctx, handle, n_elem, P
+        self.N3 = (P + 1) ** 3
+
+    @property
+    def state_shape(self):
+        return (self.n_elem, 4, self.N3)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.hdg_mesh_destroy(self.handle)
+            self.handle = None
+
+
+def hdg_init(device: int = 0) -> Context:
+    h = C.c_void_p()
+    _check(lib().hdg_init(C.byref(h), int(device)), "hdg_init")
+    return Context(h.value, device)
+
+
+def hdg_mesh_create(ctx: Context, mesh, P: int, flag, params: Params) -> Mesh:
+    """Create a device mesh from a ``workloads.HexMesh``-like object."""
+    ne = int(mesh.xyz_geom.shape[0])
+    keep = dict(
+        P=np.full(ne, P, dtype=np.int32),
+        xyz=np.ascontiguousarray(mesh.xyz_geom, dtype=np.float64),
+        flag=np.ascontiguousarray(flag, dtype=np.uint8),
+        nbr=np.ascontiguousarray(mesh.nbr, dtype=np.int32),
+        nf=np.ascontiguousarray(mesh.nbr_face, dtype=np.int8),
+        o=np.ascontiguousarray(mesh.orient, dtype=np.int8),
+    )
+    if keep["flag"].shape != (ne,):
+        raise ValueError("flag must have one entry per element")
+    d = MeshDesc()
+    d.n_elem = ne
+    d.P = keep["P"].ctypes.data_as(C.POINTER(C.c_int32))
+    d.geom_order = int(mesh.Pg)
+    d.xyz_geom = keep["xyz"].ctypes.data_as(C.POINTER(C.c_double))
+    d.flag = keep["flag"].ctypes.data_as(C.POINTER(C.c_uint8))
+    d.nbr = keep["nbr"].ctypes.data_as(C.POINTER(C.c_int32))
+    d.nbr_face = keep["nf"].ctypes.data_as(C.POINTER(C.c_int8))
+    d.orient = keep["o"].ctypes.data_as(C.POINTER(C.c_int8))
+    h = C.c_void_p()
+    _check(lib().hdg_mesh_create(ctx.handle, C.byref(d), C.byref(params), C.byref(h)), "hdg_mesh_create")
+    return Mesh(ctx, h.value, ne, P)
+
+
+def hdg_mesh_set_flags(mesh: Mesh, flag):
+    f = np.ascontiguousarray(flag, dtype=np.uint8)
+    if f.shape != (mesh.n_elem,):
+        raise ValueError("flag must have one entry per element")
+    _check(lib().hdg_mesh_set_flags(mesh.handle, f.ctypes.data_as(C.POINTER(C.c_uint8))), "hdg_mesh_set_flags")
+
+
+def hdg_mesh_set_params(mesh: Mesh, params: Params):
+    _check(lib().hdg_mesh_set_params(mesh.handle, C.byref(params)), "hdg_mesh_set_params")
+
+
+def hdg_mesh_info(mesh: Mesh) -> dict:
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    v = C.c_int32()
+    _check(lib().hdg_mesh_info(mesh.handle, C.byref(a), C.byref(b), C.byref(c), C.byref(v)), "hdg_mesh_info")
+    return dict(n_nodes=a.value, state_len=b.value, device_bytes=c.value, n_viscous=v.value)
+
+
+def hdg_mesh_node_coords(mesh: Mesh) -> np.ndarray:
+    x = np.zeros((mesh.n_elem, 3, mesh.N3))
+    _check(lib().hdg_mesh_node_coords(mesh.handle, x.ctypes.data_as(C.POINTER(C.c_double))), "node_coords")
+    return x
+
+
+def hdg_mesh_geometry(mesh, P: int) -> dict:
+    """Host-only geometry of a mesh description: node coordinates, J, Ja and the GLL rule."""
+    ne = int(mesh.xyz_geom.shape[0])
+    N = P + 1
+    N3 = N ** 3
+    Pa = np.full(ne, P, dtype=np.int32)
+    xyz = np.ascontiguousarray(mesh.xyz_geom, dtype=np.float64)
+    flag = np.zeros(ne, dtype=np.uint8)
+    nbr = np.ascontiguousarray(mesh.nbr, dtype=np.int32)
+    nf = np.ascontiguousarray(mesh.nbr_face, dtype=np.int8)
+    o = np.ascontiguousarray(mesh.orient, dtype=np.int8)
+    d = MeshDesc()
+    d.n_elem = ne
+    d.P = Pa.ctypes.data_as(C.POINTER(C.c_int32))
+    d.geom_order = int(mesh.Pg)
+    d.xyz_geom = xyz.ctypes.data_as(C.POINTER(C.c_double))
+    d.flag = flag.ctypes.data_as(C.POINTER(C.c_uint8))
+    d.nbr = nbr.ctypes.data_as(C.POINTER(C.c_int32))
+    d.nbr_face = nf.ctypes.data_as(C.POINTER(C.c_int8))
+    d.orient = o.ctypes.data_as(C.POINTER(C.c_int8))
+    out = dict(x=np.zeros((ne, 3, N3)), J=np.zeros((ne, N3)), Ja=np.zeros((ne, 3, 3, N3)),
+               xi=np.zeros(N), w=np.zeros(N), D=np.zeros((N, N)))
+    dp = C.POINTER(C.c_double)
+    _check(lib().hdg_mesh_geometry(C.byref(d), *(out[k].ctypes.data_as(dp) for k in ("x", "J", "Ja", "xi", "w", "D"))),
+           "hdg_mesh_geometry")
+    return out
+
+
+def _check_state(mesh: Mesh, t, name: str):
+    if isinstance(t, int):
+        return
+    import torch
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != 4 * mesh.n_elem * mesh.N3:
+        raise ValueError(f"{name}: need a contiguous float64 CUDA tensor of {4 * mesh.n_elem * mesh.N3} entries")
+
+
+def hdg_residual(mesh: Mesh, q, r, prec: int = HDG_F64, stream=None):
+    _check_state(mesh, q, "q")
+    _check_state(mesh, r, "r")
+    _check(lib().hdg_residual(mesh.handle, _ptr(q), _ptr(r), prec, _stream(stream)), "hdg_residual")
+
+
+def hdg_rk3_steps(mesh: Mesh, q, dq, dt: float, nsteps: int, prec: int = HDG_F64, stream=None):
+    _check_state(mesh, q, "q")
+    _check_state(mesh, dq, "dq")
+    _check(lib().hdg_rk3_steps(mesh.handle, _ptr(q), _ptr(dq), float(dt), int(nsteps), prec, _stream(stream)),
+           "hdg_rk3_steps")
+
+
+def hdg_reduce(mesh: Mesh, r, stream=None, allow_nonfinite: bool = False) -> dict:
+    _check_state(mesh, r, "r")
+    s, l2, mx = (C.c_double * 4)(), (C.c_double * 4)(), (C.c_double * 4)()
+    st = lib().hdg_reduce(mesh.handle, _ptr(r), s, l2, mx, _stream(stream))
+    out = dict(sum=np.array(s[:]), l2=np.array(l2[:]), max=np.array(mx[:]), finite=st != HDG_ENONFINITE)
+    if not (allow_nonfinite and st == HDG_ENONFINITE):
+        _check(st, "hdg_reduce")
+    return out
+
+
+def hdg_timing_enable(mesh: Mesh, enable: bool = True):
+    _check(lib().hdg_timing_enable(mesh.handle, 1 if enable else 0), "hdg_timing_enable")
+
+
+def hdg_timing_read(mesh: Mesh, kernel_class: int) -> tuple[float, int]:
+    ms, n = C.c_double(), C.c_int64()
+    _check(lib().hdg_timing_read(mesh.handle, kernel_class, C.byref(ms), C.byref(n)), "hdg_timing_read")
+    return ms.value, n.value
+
+
+def hdg_stream_copy(ctx: Context, dst, src, nbytes: int, stream=None):
+    _check(lib().hdg_stream_copy(ctx.handle, _ptr(dst), _ptr(src), int(nbytes), _stream(stream)), "hdg_stream_copy")

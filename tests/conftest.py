@@ -16,5 +16,6 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def orc():
     import oracle
-    oracle.build()
+    if oracle.needs_build():
+        oracle.build()
     return oracle
