@@ -64,16 +64,23 @@ int orc_get_threads(void) {
 
 /* ------------------------------------------------------------------------ */
 /* Quadrature: Gauss-Lobatto-Legendre nodes/weights, Lagrange derivative.    */
+/*                                                                          */
+/* The quadrature rule and the element geometry are set-up quantities, not  */
+/* part of the residual arithmetic: they are evaluated in x87 extended      */
+/* precision and rounded once to double, so that they are the correctly     */
+/* rounded values of the quantities they define.                            */
 /* ------------------------------------------------------------------------ */
 
+typedef long double xreal;
+
 /* Legendre polynomial L_n and its derivative at x by the three-term recurrence. */
-static void legendre(int n, double x, double *L, double *dL)
+static void legendre(int n, xreal x, xreal *L, xreal *dL)
 {
-    double l0 = 1.0, l1 = x, d0 = 0.0, d1 = 1.0;
-    if (n == 0) { *L = 1.0; *dL = 0.0; return; }
+    xreal l0 = 1.0L, l1 = x, d0 = 0.0L, d1 = 1.0L;
+    if (n == 0) { *L = 1.0L; *dL = 0.0L; return; }
     for (int k = 1; k < n; ++k) {
-        double l2 = ((2.0 * k + 1.0) * x * l1 - k * l0) / (k + 1.0);
-        double d2 = d0 + (2.0 * k + 1.0) * l1;
+        xreal l2 = ((2.0L * k + 1.0L) * x * l1 - k * l0) / (k + 1.0L);
+        xreal d2 = d0 + (2.0L * k + 1.0L) * l1;
         l0 = l1; l1 = l2; d0 = d1; d1 = d2;
     }
     *L = l1; *dL = d1;
@@ -81,14 +88,14 @@ static void legendre(int n, double x, double *L, double *dL)
 
 /* l_j'(x_i) for the Lagrange basis on nodes x[0..N-1], from its definition
  * l_j(x) = prod_{m != j} (x - x_m) / (x_j - x_m). */
-static void lagrange_derivative_matrix(int N, const double *x, double *D)
+static void lagrange_derivative_matrix(int N, const xreal *x, xreal *D)
 {
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) {
-            double s = 0.0;
+            xreal s = 0.0L;
             for (int k = 0; k < N; ++k) {
                 if (k == j) continue;
-                double t = 1.0 / (x[j] - x[k]);
+                xreal t = 1.0L / (x[j] - x[k]);
                 for (int m = 0; m < N; ++m) {
                     if (m == j || m == k) continue;
                     t *= (x[i] - x[m]) / (x[j] - x[m]);
@@ -99,38 +106,47 @@ static void lagrange_derivative_matrix(int N, const double *x, double *D)
         }
 }
 
-static double lagrange_value(int M1, const double *nodes, int k, double x)
+static xreal lagrange_value(int M1, const xreal *nodes, int k, xreal x)
 {
-    double v = 1.0;
+    xreal v = 1.0L;
     for (int m = 0; m < M1; ++m)
         if (m != k) v *= (x - nodes[m]) / (nodes[k] - nodes[m]);
     return v;
 }
 
-void orc_lgl(int P, double *xi, double *w, double *D)
+static void lgl_rule_x(int P, xreal *xi, xreal *w, xreal *D)
 {
     int N = P + 1;
-    xi[0] = -1.0;
-    xi[P] = 1.0;
+    xi[0] = -1.0L;
+    xi[P] = 1.0L;
     /* interior nodes: roots of L_P', Newton from Chebyshev-Lobatto guesses */
     for (int k = 1; k < P; ++k) {
-        double x = -cos(M_PI * k / P);
+        xreal x = -cosl(3.14159265358979323846264338327950288L * k / P);
         for (int it = 0; it < 100; ++it) {
-            double L, dL;
+            xreal L, dL;
             legendre(P, x, &L, &dL);
-            double d2L = (2.0 * x * dL - P * (P + 1.0) * L) / (1.0 - x * x);
-            double dx = dL / d2L;
+            xreal d2L = (2.0L * x * dL - P * (P + 1.0L) * L) / (1.0L - x * x);
+            xreal dx = dL / d2L;
             x -= dx;
-            if (fabs(dx) < 1e-16) break;
+            if (fabsl(dx) < 1e-19L) break;
         }
         xi[k] = x;
     }
     for (int k = 0; k < N; ++k) {
-        double L, dL;
+        xreal L, dL;
         legendre(P, xi[k], &L, &dL);
-        w[k] = 2.0 / (P * (P + 1.0) * L * L);
+        w[k] = 2.0L / (P * (P + 1.0L) * L * L);
     }
     lagrange_derivative_matrix(N, xi, D);
+}
+
+void orc_lgl(int P, double *xi, double *w, double *D)
+{
+    int N = P + 1;
+    xreal x[MAXN], wx[MAXN], Dx[MAXN * MAXN];
+    lgl_rule_x(P, x, wx, Dx);
+    for (int k = 0; k < N; ++k) { xi[k] = (double)x[k]; w[k] = (double)wx[k]; }
+    for (int k = 0; k < N * N; ++k) D[k] = (double)Dx[k];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -198,30 +214,32 @@ static partner_t partner(const orc_mesh *m, int e, int f, int a, int b)
 static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
 {
     int N = m->N, N3 = m->N3, G1 = Pg + 1;
-    double gn[MAXN];
-    for (int k = 0; k < G1; ++k) gn[k] = -1.0 + 2.0 * k / Pg;
-    double lg[MAXN][MAXN]; /* lg[a][k] = l_k^geom(xi_a) */
+    xreal xq[MAXN], wq[MAXN], Dq[MAXN * MAXN];
+    lgl_rule_x(m->P, xq, wq, Dq);
+    xreal gn[MAXN];
+    for (int k = 0; k < G1; ++k) gn[k] = -1.0L + 2.0L * k / Pg;
+    xreal lg[MAXN][MAXN]; /* lg[a][k] = l_k^geom(xi_a) */
     for (int a = 0; a < N; ++a)
-        for (int k = 0; k < G1; ++k) lg[a][k] = lagrange_value(G1, gn, k, m->xi[a]);
+        for (int k = 0; k < G1; ++k) lg[a][k] = lagrange_value(G1, gn, k, xq[a]);
 
     /* The metric terms are invariant under a translation of the element, so
      * the geometry is interpolated and differentiated in coordinates relative
      * to the element's first control point: round-off then stays relative to
      * the element size rather than to its distance from the origin. */
     double *x = m->x + (size_t)e * 3 * N3;
-    double *xl = malloc(sizeof(double) * 3 * N3);
+    xreal *xl = malloc(sizeof(xreal) * 3 * N3);
     for (int c = 0; c < 3; ++c) {
         const double *Xc = X + (size_t)c * G1 * G1 * G1;
         for (int n = 0; n < N3; ++n) {
             int a = n % N, b = (n / N) % N, cc = n / (N * N);
-            double s = 0.0;
+            xreal s = 0.0L;
             for (int k3 = 0; k3 < G1; ++k3)
                 for (int k2 = 0; k2 < G1; ++k2)
                     for (int k1 = 0; k1 < G1; ++k1)
-                        s += (Xc[k1 + G1 * k2 + G1 * G1 * k3] - Xc[0])
+                        s += ((xreal)Xc[k1 + G1 * k2 + G1 * G1 * k3] - (xreal)Xc[0])
                              * lg[a][k1] * lg[b][k2] * lg[cc][k3];
             xl[c * N3 + n] = s;
-            x[c * N3 + n] = Xc[0] + s;
+            x[c * N3 + n] = (double)((xreal)Xc[0] + s);
         }
     }
 
@@ -229,61 +247,59 @@ static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
 #define DREF(field, k, n, out)                                                  \
     do {                                                                        \
         int a_ = (n) % N, b_ = ((n) / N) % N, c_ = (n) / (N * N);               \
-        double s_ = 0.0;                                                        \
+        xreal s_ = 0.0L;                                                        \
         for (int q_ = 0; q_ < N; ++q_) {                                        \
             int idx_ = (k) == 0 ? q_ + N * b_ + N * N * c_                      \
                      : (k) == 1 ? a_ + N * q_ + N * N * c_                      \
                                 : a_ + N * b_ + N * N * q_;                     \
             int row_ = (k) == 0 ? a_ : (k) == 1 ? b_ : c_;                      \
-            s_ += m->D[row_ * N + q_] * (field)[idx_];                          \
+            s_ += Dq[row_ * N + q_] * (field)[idx_];                            \
         }                                                                       \
         (out) = s_;                                                             \
     } while (0)
 
-    double *dX = malloc(sizeof(double) * 9 * N3);   /* dX[c][k][n] = dX_c/dxi_k */
+    xreal *dX = malloc(sizeof(xreal) * 9 * N3);   /* dX[c][k][n] = dX_c/dxi_k */
     for (int c = 0; c < 3; ++c)
         for (int k = 0; k < 3; ++k)
             for (int n = 0; n < N3; ++n) DREF(xl + c * N3, k, n, dX[(c * 3 + k) * N3 + n]);
 
     double *J = m->J + (size_t)e * N3;
+    xreal vol = 0.0L;
     for (int n = 0; n < N3; ++n) {
-        double a11 = dX[(0 * 3 + 0) * N3 + n], a12 = dX[(0 * 3 + 1) * N3 + n], a13 = dX[(0 * 3 + 2) * N3 + n];
-        double a21 = dX[(1 * 3 + 0) * N3 + n], a22 = dX[(1 * 3 + 1) * N3 + n], a23 = dX[(1 * 3 + 2) * N3 + n];
-        double a31 = dX[(2 * 3 + 0) * N3 + n], a32 = dX[(2 * 3 + 1) * N3 + n], a33 = dX[(2 * 3 + 2) * N3 + n];
-        J[n] = a11 * (a22 * a33 - a23 * a32) - a12 * (a21 * a33 - a23 * a31) + a13 * (a21 * a32 - a22 * a31);
+        xreal a11 = dX[(0 * 3 + 0) * N3 + n], a12 = dX[(0 * 3 + 1) * N3 + n], a13 = dX[(0 * 3 + 2) * N3 + n];
+        xreal a21 = dX[(1 * 3 + 0) * N3 + n], a22 = dX[(1 * 3 + 1) * N3 + n], a23 = dX[(1 * 3 + 2) * N3 + n];
+        xreal a31 = dX[(2 * 3 + 0) * N3 + n], a32 = dX[(2 * 3 + 1) * N3 + n], a33 = dX[(2 * 3 + 2) * N3 + n];
+        xreal Jx = a11 * (a22 * a33 - a23 * a32) - a12 * (a21 * a33 - a23 * a31) + a13 * (a21 * a32 - a22 * a31);
+        J[n] = (double)Jx;
+        int a = n % N, b = (n / N) % N, c = n / (N * N);
+        vol += wq[a] * wq[b] * wq[c] * Jx;
     }
 
     /* Ja^i_n = -[curl_xi (X_l grad_xi X_m)]_i with (n, m, l) cyclic */
-    double *V = malloc(sizeof(double) * 3 * N3);
+    xreal *V = malloc(sizeof(xreal) * 3 * N3);
     for (int nn = 0; nn < 3; ++nn) {
         int mm = (nn + 1) % 3, ll = (nn + 2) % 3;
         for (int k = 0; k < 3; ++k)
             for (int n = 0; n < N3; ++n)
                 V[k * N3 + n] = xl[ll * N3 + n] * dX[(mm * 3 + k) * N3 + n];
         for (int n = 0; n < N3; ++n) {
-            double d1V2, d2V1, d2V0, d0V2, d0V1, d1V0;
+            xreal d1V2, d2V1, d2V0, d0V2, d0V1, d1V0;
             DREF(V + 2 * N3, 1, n, d1V2);
             DREF(V + 1 * N3, 2, n, d2V1);
             DREF(V + 0 * N3, 2, n, d2V0);
             DREF(V + 2 * N3, 0, n, d0V2);
             DREF(V + 1 * N3, 0, n, d0V1);
             DREF(V + 0 * N3, 1, n, d1V0);
-            double curl[3] = {d1V2 - d2V1, d2V0 - d0V2, d0V1 - d1V0};
+            xreal curl[3] = {d1V2 - d2V1, d2V0 - d0V2, d0V1 - d1V0};
             for (int i = 0; i < 3; ++i)
-                m->Ja[(((size_t)e * 3 + i) * 3 + nn) * N3 + n] = -curl[i];
+                m->Ja[(((size_t)e * 3 + i) * 3 + nn) * N3 + n] = (double)(-curl[i]);
         }
     }
 #undef DREF
     free(V);
     free(xl);
     free(dX);
-
-    double vol = 0.0;
-    for (int n = 0; n < N3; ++n) {
-        int a = n % N, b = (n / N) % N, c = n / (N * N);
-        vol += m->w[a] * m->w[b] * m->w[c] * J[n];
-    }
-    m->delta[e] = cbrt(vol) / N;
+    m->delta[e] = (double)(cbrtl(vol) / N);
 }
 
 orc_mesh *orc_mesh_new(int ne, int P, int Pg, const double *xyz_geom, const int *nbr,

@@ -2,6 +2,10 @@
 // terms, processing order.  Runs once per mesh (App. B: the mapping of every
 // curvilinear hexahedron onto the reference cube, its Jacobian and the
 // contravariant metric terms that turn physical fluxes into reference ones).
+//
+// These set-up quantities are evaluated in x87 extended precision and rounded
+// once to double, so the stored rule and metric terms are the correctly
+// rounded values of what they define; the residual itself is all FP64.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -14,61 +18,59 @@ namespace hdg {
 
 namespace {
 
+using xreal = long double;
+
 // Legendre L_n(x) and L_n'(x).
-void legendre_pair(int n, double x, double &L, double &dL)
+void legendre_pair(int n, xreal x, xreal &L, xreal &dL)
 {
-    double lm1 = 1.0, l = x, dlm1 = 0.0, dl = 1.0;
-    if (n == 0) { L = 1.0; dL = 0.0; return; }
+    xreal lm1 = 1.0L, l = x, dlm1 = 0.0L, dl = 1.0L;
+    if (n == 0) { L = 1.0L; dL = 0.0L; return; }
     for (int k = 2; k <= n; ++k) {
-        double lk = ((2 * k - 1) * x * l - (k - 1) * lm1) / k;
-        double dlk = dlm1 + (2 * k - 1) * l;
+        xreal lk = ((2 * k - 1) * x * l - (k - 1) * lm1) / k;
+        xreal dlk = dlm1 + (2 * k - 1) * l;
         lm1 = l; l = lk; dlm1 = dl; dl = dlk;
     }
     L = l; dL = dl;
 }
 
-}  // namespace
-
-// GLL nodes are the zeros of q(x) = L_{P+1}(x) - L_{P-1}(x) (which contains
-// the end points): Newton on q with q' = L'_{P+1} - L'_{P-1}.  The derivative
-// matrix uses barycentric weights; its diagonal is the negative row sum, so
-// it maps constants to exactly zero.
-void gll_rule(int P, std::vector<double> &xi, std::vector<double> &w, std::vector<double> &D)
+// Extended-precision GLL rule: nodes, weights, derivative matrix.
+void gll_rule_x(int P, std::vector<xreal> &xi, std::vector<xreal> &w, std::vector<xreal> &D)
 {
     const int N = P + 1;
-    xi.assign(N, 0.0);
-    w.assign(N, 0.0);
-    D.assign(N * N, 0.0);
-    xi[0] = -1.0;
-    xi[P] = 1.0;
+    const xreal pi = 3.14159265358979323846264338327950288L;
+    xi.assign(N, 0.0L);
+    w.assign(N, 0.0L);
+    D.assign(N * N, 0.0L);
+    xi[0] = -1.0L;
+    xi[P] = 1.0L;
     for (int j = 1; 2 * j <= P; ++j) {
-        double x = -std::cos(M_PI * (j + 0.25) / P - 3.0 / (8.0 * P * M_PI * (j + 0.25)));
+        xreal x = -std::cos(pi * (j + 0.25L) / P - 3.0L / (8.0L * P * pi * (j + 0.25L)));
         for (int it = 0; it < 200; ++it) {
-            double La, dLa, Lb, dLb;
+            xreal La, dLa, Lb, dLb;
             legendre_pair(P + 1, x, La, dLa);
             legendre_pair(P - 1, x, Lb, dLb);
-            double step = (La - Lb) / (dLa - dLb);
+            xreal step = (La - Lb) / (dLa - dLb);
             x -= step;
-            if (std::fabs(step) <= 1e-16 * std::max(1.0, std::fabs(x))) break;
+            if (std::fabs(step) <= 1e-19L) break;
         }
         xi[j] = x;
         xi[P - j] = -x;
     }
-    if (P % 2 == 0) xi[P / 2] = 0.0;
+    if (P % 2 == 0) xi[P / 2] = 0.0L;
     for (int j = 0; j < N; ++j) {
-        double L, dL;
+        xreal L, dL;
         legendre_pair(P, xi[j], L, dL);
-        w[j] = 2.0 / (P * (P + 1.0) * L * L);
+        w[j] = 2.0L / (P * (P + 1.0L) * L * L);
     }
-    std::vector<double> lam(N, 1.0);
+    std::vector<xreal> lam(N, 1.0L);
     for (int j = 0; j < N; ++j)
         for (int k = 0; k < N; ++k)
             if (k != j) lam[j] /= (xi[j] - xi[k]);
     for (int i = 0; i < N; ++i) {
-        double diag = 0.0;
+        xreal diag = 0.0L;
         for (int j = 0; j < N; ++j) {
             if (j == i) continue;
-            double v = (lam[j] / lam[i]) / (xi[i] - xi[j]);
+            xreal v = (lam[j] / lam[i]) / (xi[i] - xi[j]);
             D[i * N + j] = v;
             diag -= v;
         }
@@ -76,23 +78,38 @@ void gll_rule(int P, std::vector<double> &xi, std::vector<double> &w, std::vecto
     }
 }
 
+}  // namespace
+
+// GLL nodes are the zeros of q(x) = L_{P+1}(x) - L_{P-1}(x) (which contains
+// the end points): Newton on q with q' = L'_{P+1} - L'_{P-1}.  The derivative
+// matrix uses barycentric weights; its diagonal is the negative row sum, so
+// it maps constants to zero.
+void gll_rule(int P, std::vector<double> &xi, std::vector<double> &w, std::vector<double> &D)
+{
+    std::vector<xreal> x, wx, Dx;
+    gll_rule_x(P, x, wx, Dx);
+    xi.assign(x.begin(), x.end());
+    w.assign(wx.begin(), wx.end());
+    D.assign(Dx.begin(), Dx.end());
+}
+
 namespace {
 
 // Lagrange interpolation matrix from nodes src (m points) to points dst.
-std::vector<double> interp_matrix(const std::vector<double> &src, const std::vector<double> &dst)
+std::vector<xreal> interp_matrix(const std::vector<xreal> &src, const std::vector<xreal> &dst)
 {
     const int m = (int)src.size(), n = (int)dst.size();
-    std::vector<double> bw(m, 1.0);
+    std::vector<xreal> bw(m, 1.0L);
     for (int j = 0; j < m; ++j)
         for (int k = 0; k < m; ++k)
             if (k != j) bw[j] /= (src[j] - src[k]);
-    std::vector<double> I(n * m, 0.0);
+    std::vector<xreal> I(n * m, 0.0L);
     for (int i = 0; i < n; ++i) {
         int hit = -1;
         for (int j = 0; j < m; ++j)
             if (dst[i] == src[j]) hit = j;
-        if (hit >= 0) { I[i * m + hit] = 1.0; continue; }
-        double den = 0.0;
+        if (hit >= 0) { I[i * m + hit] = 1.0L; continue; }
+        xreal den = 0.0L;
         for (int j = 0; j < m; ++j) den += bw[j] / (dst[i] - src[j]);
         for (int j = 0; j < m; ++j) I[i * m + j] = (bw[j] / (dst[i] - src[j])) / den;
     }
@@ -101,8 +118,8 @@ std::vector<double> interp_matrix(const std::vector<double> &src, const std::vec
 
 // out[n] = sum_k M[idx(n,dir)][k] in[... k along dir ...] on an (nx, ny, nz) lattice,
 // producing an (ox, oy, oz) lattice where only dir changes size.
-void apply_dir(const std::vector<double> &M, int rows, int cols, int dir, const double *in,
-               int nx, int ny, int nz, double *out)
+void apply_dir(const std::vector<xreal> &M, int rows, int cols, int dir, const xreal *in,
+               int nx, int ny, int nz, xreal *out)
 {
     int dims_in[3] = {nx, ny, nz};
     int dims_out[3] = {nx, ny, nz};
@@ -112,7 +129,7 @@ void apply_dir(const std::vector<double> &M, int rows, int cols, int dir, const 
         for (int b = 0; b < dims_out[1]; ++b)
             for (int a = 0; a < dims_out[0]; ++a) {
                 int o[3] = {a, b, c};
-                double s = 0.0;
+                xreal s = 0.0L;
                 for (int k = 0; k < dims_in[dir]; ++k) {
                     int ii[3] = {a, b, c};
                     ii[dir] = k;
@@ -130,10 +147,14 @@ bool build_geometry(const hdg_mesh_desc &d, int P, HostGeometry &g, std::string 
     const int64_t ne = d.n_elem;
     g.N = N;
     g.N3 = N3;
-    gll_rule(P, g.xi, g.w, g.D);
-    std::vector<double> gnodes(G1);
-    for (int k = 0; k < G1; ++k) gnodes[k] = -1.0 + 2.0 * k / Pg;
-    const std::vector<double> I = interp_matrix(gnodes, g.xi);
+    std::vector<xreal> xq, wq, Dq;
+    gll_rule_x(P, xq, wq, Dq);
+    g.xi.assign(xq.begin(), xq.end());
+    g.w.assign(wq.begin(), wq.end());
+    g.D.assign(Dq.begin(), Dq.end());
+    std::vector<xreal> gnodes(G1);
+    for (int k = 0; k < G1; ++k) gnodes[k] = -1.0L + 2.0L * k / Pg;
+    const std::vector<xreal> I = interp_matrix(gnodes, xq);
     g.x.assign(ne * 3 * N3, 0.0);
     g.J.assign(ne * N3, 0.0);
     g.Ja.assign(ne * 9 * N3, 0.0);
@@ -141,53 +162,48 @@ bool build_geometry(const hdg_mesh_desc &d, int P, HostGeometry &g, std::string 
     std::atomic<int64_t> bad{-1};
 
     auto body = [&](int64_t e) {
-        std::vector<double> t1(N * G1 * G1), t2(N * N * G1), loc(3 * N3), dX(9 * N3), V(3 * N3);
+        std::vector<xreal> t1(N * G1 * G1), t2(N * N * G1), loc(3 * N3), dX(9 * N3), V(3 * N3), dV(9 * N3);
+        std::vector<xreal> rel(G3);
         const double *Xe = d.xyz_geom + e * 3 * G3;
         // geometry at the nodes, relative to the element's first control point
         // (the metric terms do not depend on a translation; this keeps their
         // round-off relative to the element size)
         for (int c = 0; c < 3; ++c) {
-            std::vector<double> rel(G3);
-            for (int k = 0; k < G3; ++k) rel[k] = Xe[c * G3 + k] - Xe[c * G3];
+            for (int k = 0; k < G3; ++k) rel[k] = (xreal)Xe[c * G3 + k] - (xreal)Xe[c * G3];
             apply_dir(I, N, G1, 0, rel.data(), G1, G1, G1, t1.data());
             apply_dir(I, N, G1, 1, t1.data(), N, G1, G1, t2.data());
             apply_dir(I, N, G1, 2, t2.data(), N, N, G1, &loc[c * N3]);
-            for (int n = 0; n < N3; ++n) g.x[(e * 3 + c) * N3 + n] = Xe[c * G3] + loc[c * N3 + n];
+            for (int n = 0; n < N3; ++n) g.x[(e * 3 + c) * N3 + n] = (double)((xreal)Xe[c * G3] + loc[c * N3 + n]);
         }
         for (int c = 0; c < 3; ++c)
-            for (int k = 0; k < 3; ++k) apply_dir(g.D, N, N, k, &loc[c * N3], N, N, N, &dX[(c * 3 + k) * N3]);
+            for (int k = 0; k < 3; ++k) apply_dir(Dq, N, N, k, &loc[c * N3], N, N, N, &dX[(c * 3 + k) * N3]);
+        xreal vol = 0.0L;
         for (int n = 0; n < N3; ++n) {
             auto m = [&](int c, int k) { return dX[(c * 3 + k) * N3 + n]; };
-            g.J[e * N3 + n] = m(0, 0) * (m(1, 1) * m(2, 2) - m(1, 2) * m(2, 1))
-                            - m(0, 1) * (m(1, 0) * m(2, 2) - m(1, 2) * m(2, 0))
-                            + m(0, 2) * (m(1, 0) * m(2, 1) - m(1, 1) * m(2, 0));
+            const xreal J = m(0, 0) * (m(1, 1) * m(2, 2) - m(1, 2) * m(2, 1))
+                          - m(0, 1) * (m(1, 0) * m(2, 2) - m(1, 2) * m(2, 0))
+                          + m(0, 2) * (m(1, 0) * m(2, 1) - m(1, 1) * m(2, 0));
+            g.J[e * N3 + n] = (double)J;
+            const int a = n % N, b = (n / N) % N, c = n / (N * N);
+            vol += wq[a] * wq[b] * wq[c] * J;
+            if (!(J > 0.0L)) bad.store(e);
         }
+        g.delta[e] = (double)(std::cbrt(vol) / N);
         // curl form: Ja^i_n = -(curl_xi (x_l grad_xi x_m))_i, (n, m, l) cyclic
         for (int n = 0; n < 3; ++n) {
             const int mm = (n + 1) % 3, ll = (n + 2) % 3;
             for (int k = 0; k < 3; ++k)
                 for (int p = 0; p < N3; ++p) V[k * N3 + p] = loc[ll * N3 + p] * dX[(mm * 3 + k) * N3 + p];
-            std::vector<double> dV(9 * N3);    // dV[k][j] = d V_k / d xi_j
             for (int k = 0; k < 3; ++k)
                 for (int j = 0; j < 3; ++j)
-                    if (j != k) apply_dir(g.D, N, N, j, &V[k * N3], N, N, N, &dV[(k * 3 + j) * N3]);
+                    if (j != k) apply_dir(Dq, N, N, j, &V[k * N3], N, N, N, &dV[(k * 3 + j) * N3]);
             for (int p = 0; p < N3; ++p) {
                 auto dv = [&](int k, int j) { return dV[(k * 3 + j) * N3 + p]; };
-                double c0 = dv(2, 1) - dv(1, 2);
-                double c1 = dv(0, 2) - dv(2, 0);
-                double c2 = dv(1, 0) - dv(0, 1);
-                g.Ja[((e * 3 + 0) * 3 + n) * N3 + p] = -c0;
-                g.Ja[((e * 3 + 1) * 3 + n) * N3 + p] = -c1;
-                g.Ja[((e * 3 + 2) * 3 + n) * N3 + p] = -c2;
+                g.Ja[((e * 3 + 0) * 3 + n) * N3 + p] = (double)(-(dv(2, 1) - dv(1, 2)));
+                g.Ja[((e * 3 + 1) * 3 + n) * N3 + p] = (double)(-(dv(0, 2) - dv(2, 0)));
+                g.Ja[((e * 3 + 2) * 3 + n) * N3 + p] = (double)(-(dv(1, 0) - dv(0, 1)));
             }
         }
-        double vol = 0.0;
-        for (int p = 0; p < N3; ++p) {
-            const int a = p % N, b = (p / N) % N, c = p / (N * N);
-            vol += g.w[a] * g.w[b] * g.w[c] * g.J[e * N3 + p];
-            if (!(g.J[e * N3 + p] > 0.0)) bad.store(e);
-        }
-        g.delta[e] = std::cbrt(vol) / N;
     };
     const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
