@@ -29,22 +29,23 @@ METRIC = "DOF-residual evals/s (mixed NS-LES/Euler DG), plain vs batched FP32; p
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(kind: int, n_elem: int, N: int, fused_rk: bool) -> float:
+def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: bool) -> float:
     """Bytes a launch must move at least once (perfect caching), FP64.
 
-    Element kernels: state 32 B/node, metric terms (1/J + 9 Ja) 80 B/node;
-    fused RK stage: + dq read/write 64 + next state 32; residual only: + R 32.
-    Faces: each element owns three faces on average; face geometry 32 B per
-    face node (unit normal + scale); viscous face traces 24 B per face node
-    and side.
+    Residual kernel, every element: state 32 B/node, metric terms (1/J + 9 Ja)
+    80 B/node; fused RK stage: + dq read/write 64 + next state 32 (residual
+    only: + R 32); face geometry 32 B per face node, three faces owned per
+    element.  Flagged elements add the viscous divergence part (24 B/node)
+    and both sides' viscous face traces (24 B per face node and side).
+    Viscous kernel, flagged elements: velocity 24 + metric 80 B/node, face
+    geometry, out the viscous part 24 B/node and six faces of traces.
     """
     N3, N2 = N ** 3, N ** 2
-    if kind == 0:      # viscous traces: u, v, w + metric in, 6 faces of traces out
-        return n_elem * (24 * N3 + 80 * N3 + 3 * N2 * 32 + 6 * N2 * 24)
+    if kind == 0:
+        return float(n_visc * ((24 + 80 + 24) * N3 + 3 * N2 * 32 + 6 * N2 * 24))
     per_node = 32 + 80 + (96 + 32 if fused_rk else 32)
     b = n_elem * (per_node * N3 + 3 * N2 * 32)
-    if kind == 2:      # viscous residual also reads both sides of its faces' traces
-        b += n_elem * 3 * N2 * 2 * 24
+    b += n_visc * (24 * N3 + 6 * N2 * 24)
     return float(b)
 
 
@@ -73,6 +74,7 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-mb", type=int, default=1024, help="size of the stream-copy probe")
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -88,7 +90,7 @@ def main(argv=None) -> int:
         return 1
     w = W.naca_working()
     q0 = W.initial_state(w, None)
-    dt = W.cfl_dt(w.mesh, w.P, q0, w.params["c0sq"])
+    dt = w.dt
     N = w.P + 1
     nodes = w.mesh.n_elem * N ** 3
     ctx = hdg.hdg_init(0)
@@ -117,14 +119,27 @@ def main(argv=None) -> int:
     hdg.hdg_timing_enable(mesh, False)
     red = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
 
+    # plain copy kernel of known size: attainable HBM bandwidth, and the
+    # reference dispatch that calibrates the FETCH_SIZE / WRITE_SIZE counters
+    copy_bytes = args.copy_mb << 20
+    src = torch.empty(copy_bytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    hdg.hdg_stream_copy(ctx, dst, src, copy_bytes, stream=stream)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        hdg.hdg_stream_copy(ctx, dst, src, copy_bytes, stream=stream)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * copy_bytes * 5 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+
     n_visc = info["n_viscous"]
-    n_eul = w.mesh.n_elem - n_visc
-    counts = {"viscous_traces": n_visc, "residual_euler": n_eul, "residual_viscous": n_visc}
-    kinds = {"viscous_traces": 0, "residual_euler": 1, "residual_viscous": 2}
+    kinds = {name: k for k, name in hdg.KERNEL_NAMES.items()}
     dom = max(kern, key=lambda k: kern[k][0])
     tot, n = kern[dom]
     avg_s = tot / max(n, 1) / 1e3
-    bytes_launch = algorithmic_bytes(kinds[dom], counts[dom], N, fused_rk=True)
+    bytes_launch = algorithmic_bytes(kinds[dom], w.mesh.n_elem, n_visc, N, fused_rk=True)
     achieved = bytes_launch / avg_s / 1e9
     evals = 3 * args.steps
     out = {
@@ -149,6 +164,8 @@ def main(argv=None) -> int:
         "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern.items()},
         "node_evals_per_s": nodes * evals / (ms / 1e3),
         "state_finite": bool(red["finite"]),
+        "stream_copy_GBps": copy_gbs,
+        "frac_of_stream_copy": achieved / copy_gbs,
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)

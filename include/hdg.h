@@ -82,10 +82,9 @@ enum { HDG_LES_NONE = 0, HDG_LES_SMAGORINSKY = 1, HDG_LES_VREMAN = 2 };
 
 /* Kernel classes reported by hdg_timing_read. */
 enum {
-    HDG_KERNEL_VISCOUS_TRACES = 0,   /* BR1 gradient + LES + viscous face traces, flagged elements */
-    HDG_KERNEL_RESIDUAL_EULER = 1,   /* residual (or fused RK stage) of Euler elements */
-    HDG_KERNEL_RESIDUAL_VISCOUS = 2, /* residual (or fused RK stage) of flagged elements */
-    HDG_KERNEL_COUNT = 3
+    HDG_KERNEL_VISCOUS = 0,   /* flagged elements: BR1 gradient, LES, viscous divergence and face traces */
+    HDG_KERNEL_RESIDUAL = 1,  /* every element: convective divergence, face fluxes, -1/J (or fused RK stage) */
+    HDG_KERNEL_COUNT = 2
 };
 
 /* Mesh description (Sec. 2.1: per-element region ID; App. B: curvilinear

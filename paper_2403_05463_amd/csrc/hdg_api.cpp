@@ -61,13 +61,13 @@ struct hdg_mesh {
     std::vector<uint8_t> flag;
     std::vector<double> x;                 // node coordinates, host
     std::vector<int32_t> order;            // processing order
-    int32_t n_visc = 0, n_euler = 0;
+    int32_t n_visc = 0;
     // device buffers
-    double *metric = nullptr, *fgeo = nullptr, *fvt = nullptr, *qpp = nullptr, *mass = nullptr;
+    double *metric = nullptr, *fgeo = nullptr, *fvt = nullptr, *wvis = nullptr, *qpp = nullptr, *mass = nullptr;
     double *delta = nullptr, *Dmat = nullptr, *partials = nullptr, *final13 = nullptr;
     FaceRef *conn = nullptr;
     uint8_t *flag_d = nullptr;
-    int32_t *list_visc = nullptr, *list_euler = nullptr;
+    int32_t *list_visc = nullptr, *list_all = nullptr;
     int nblocks_reduce = 0;
     int64_t bytes = 0;
     // timing
@@ -91,8 +91,8 @@ hdg_status dev_alloc(hdg_mesh *m, T **p, size_t count)
 
 void free_device(hdg_mesh *m)
 {
-    void *ptrs[] = {m->metric, m->fgeo, m->fvt, m->qpp, m->mass, m->delta, m->Dmat, m->partials,
-                    m->final13, m->conn, m->flag_d, m->list_visc, m->list_euler};
+    void *ptrs[] = {m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->Dmat, m->partials,
+                    m->final13, m->conn, m->flag_d, m->list_visc, m->list_all};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : m->ev) (void)hipEventDestroy(e);
@@ -111,15 +111,14 @@ hdg_status check_params(const hdg_params *p)
     return HDG_OK;
 }
 
-// Element lists by flag, in the processing order.
+// Flagged-element list in the processing order, and the flags.
 hdg_status upload_lists(hdg_mesh *m)
 {
-    std::vector<int32_t> v, eu;
-    for (int32_t e : m->order) (m->flag[e] ? v : eu).push_back(e);
+    std::vector<int32_t> v;
+    for (int32_t e : m->order)
+        if (m->flag[e]) v.push_back(e);
     m->n_visc = (int32_t)v.size();
-    m->n_euler = (int32_t)eu.size();
     if (!v.empty()) HDG_HIP(hipMemcpy(m->list_visc, v.data(), v.size() * 4, hipMemcpyHostToDevice));
-    if (!eu.empty()) HDG_HIP(hipMemcpy(m->list_euler, eu.data(), eu.size() * 4, hipMemcpyHostToDevice));
     HDG_HIP(hipMemcpy(m->flag_d, m->flag.data(), m->ne, hipMemcpyHostToDevice));
     return HDG_OK;
 }
@@ -132,6 +131,7 @@ ElemArgs base_args(const hdg_mesh *m)
     a.conn = m->conn;
     a.flag = m->flag_d;
     a.fvt = m->fvt;
+    a.wvis = m->wvis;
     a.delta = m->delta;
     a.Dmat = m->Dmat;
     a.c0sq = m->prm.c0sq;
@@ -179,16 +179,13 @@ hdg_status run_stage(hdg_mesh *m, const double *q, double *out, double *dq, Epi 
     a.rkB = B;
     a.dt = dt;
     a.first_stage = first ? 1 : 0;
-    hdg_status st;
     ElemArgs av = a;
     set_list(av, m->list_visc, m->n_visc);
-    st = timed(m, HDG_KERNEL_VISCOUS_TRACES, s, [&] { return hdg::launch_viscous_traces(m->N, av, s); });
+    hdg_status st = timed(m, HDG_KERNEL_VISCOUS, s, [&] { return hdg::launch_viscous(m->N, av, s); });
     if (st != HDG_OK) return st;
-    ElemArgs ae = a;
-    set_list(ae, m->list_euler, m->n_euler);
-    st = timed(m, HDG_KERNEL_RESIDUAL_EULER, s, [&] { return hdg::launch_residual(m->N, false, epi, ae, s); });
-    if (st != HDG_OK) return st;
-    return timed(m, HDG_KERNEL_RESIDUAL_VISCOUS, s, [&] { return hdg::launch_residual(m->N, true, epi, av, s); });
+    ElemArgs ar = a;
+    set_list(ar, m->list_all, (int32_t)m->ne);
+    return timed(m, HDG_KERNEL_RESIDUAL, s, [&] { return hdg::launch_residual(m->N, epi, ar, s); });
 }
 
 // Sizes, pointers, uniform order, symmetric connectivity with mutually inverse
@@ -341,6 +338,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(dev_alloc(m, &m->mass, mass.size()));
     chk(dev_alloc(m, &m->fgeo, fgeo.size()));
     chk(dev_alloc(m, &m->fvt, (size_t)nf * 2 * N2 * 3));
+    chk(dev_alloc(m, &m->wvis, (size_t)ne * 3 * N3));
     chk(dev_alloc(m, &m->qpp, (size_t)ne * 4 * N3));
     chk(dev_alloc(m, &m->delta, (size_t)ne));
     chk(dev_alloc(m, &m->Dmat, (size_t)N2));
@@ -349,7 +347,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(dev_alloc(m, &m->conn, conn.size()));
     chk(dev_alloc(m, &m->flag_d, (size_t)ne));
     chk(dev_alloc(m, &m->list_visc, (size_t)ne));
-    chk(dev_alloc(m, &m->list_euler, (size_t)ne));
+    chk(dev_alloc(m, &m->list_all, (size_t)ne));
     if (s2 != HDG_OK) {
         free_device(m);
         delete m;
@@ -365,6 +363,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(up(m->delta, g.delta.data(), g.delta.size() * 8));
     chk(up(m->Dmat, g.D.data(), g.D.size() * 8));
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
+    chk(up(m->list_all, m->order.data(), m->order.size() * sizeof(int32_t)));
     if (s2 == HDG_OK) s2 = upload_lists(m);
     if (s2 != HDG_OK) {
         free_device(m);

@@ -34,6 +34,7 @@ struct ElemArgs {
     const FaceRef *conn;    // [e][6]
     const uint8_t *flag;    // [e]
     double *fvt;            // [face][2 sides][N^2][3]: viscous flux . (s n), side 0 = owner
+    double *wvis;           // [e][3][N^3]: viscous part of the reference divergence (flagged elements)
     const int32_t *list;    // elements handled by this launch
     const double *delta;    // [e] LES filter width
     const double *Dmat;     // [N][N] derivative matrix, D[i][j] = l_j'(xi_i)
@@ -50,8 +51,8 @@ struct ElemArgs {
 enum class Epi : int { Residual = 0, RkStage = 1 };
 
 // Kernel launchers (hdg_kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_viscous_traces(int N, const ElemArgs &a, hipStream_t s);
-hipError_t launch_residual(int N, bool viscous, Epi epi, const ElemArgs &a, hipStream_t s);
+hipError_t launch_viscous(int N, const ElemArgs &a, hipStream_t s);
+hipError_t launch_residual(int N, Epi epi, const ElemArgs &a, hipStream_t s);
 hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_elem,
                          double *partials, int nblocks, double *final13, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s);

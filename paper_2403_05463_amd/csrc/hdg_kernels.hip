@@ -1,23 +1,25 @@
 // gfx950 kernels of the hybrid Navier-Stokes-LES / Euler DGSEM residual.
 //
 // One workgroup per element, one lane per collocation node (N^3 nodes rounded
-// up to whole 64-lane waves).  Work is split by equation flag (Sec. 2.3): the
-// viscous-trace kernel and the viscous residual run only on flagged elements,
-// the Euler residual carries no gradient, LES or viscous-flux code at all.
+// up to whole 64-lane waves).  Work is split by equation flag (Sec. 2.3):
 //
-// Per element the residual kernel
-//   1. loads the state and the metric terms of its own nodes (coalesced),
-//   2. [flagged] lifts the velocity gradient (BR1: volume derivative of
-//      Ja^i u plus a face correction towards the mean of the two traces),
-//      evaluates the eddy viscosity and the viscous flux 2 (nu + nu_t) S,
-//   3. forms the contravariant fluxes F^i = Ja^i . (f_conv - f_visc) in LDS,
-//   4. takes their reference divergence with the N-point derivative matrix,
-//   5. adds, on face nodes, the jump between the single-valued numerical
-//      flux (Roe + BR1 mean of the stored viscous face traces) and the
-//      element's own flux, divided by the end-point weight,
-//   6. scales by -1/J and writes R, or applies a low-storage RK stage.
-// These are the strong-form (summation-by-parts) equivalent of the weak form
-// in App. B: on Gauss-Lobatto nodes the two agree to round-off.
+//  k_viscous   (flagged elements only) lifts the velocity gradient (BR1:
+//              volume derivative of Ja^i u plus a face correction towards the
+//              mean of the two traces), evaluates the eddy viscosity and the
+//              viscous stress 2 (nu + nu_t) S, and writes
+//                - the viscous part of the element's reference divergence,
+//                  -D F_v + (own-face flux)/w_end, 3 momentum rows per node,
+//                - the viscous face traces tau . (s n) of its six faces, per
+//                  face side, for the single-valued BR1 face flux;
+//  k_residual  (every element) forms the contravariant convective fluxes in
+//              LDS, takes their reference divergence, adds on face nodes the
+//              jump between the single-valued numerical flux (Roe + BR1 mean
+//              of the stored viscous traces) and its own flux over the end
+//              weight, adds the viscous part on flagged elements, scales by
+//              -1/J and writes R or applies a low-storage RK stage.
+// This is the strong (summation-by-parts) equivalent of the weak form in
+// App. B: on Gauss-Lobatto nodes the two agree to round-off.  Euler elements
+// run no gradient, LES or viscous-flux arithmetic at all.
 #include "hdg_internal.h"
 
 namespace hdg {
@@ -277,10 +279,9 @@ __device__ __forceinline__ void viscous_flux(const ElemArgs &A, ElemCtx<N> &c, d
         for (int d = 0; d < 3; ++d) fv[r][d] = mu * (G[r][d] + G[d][r]);
 }
 
-// Viscous face traces of flagged elements: fv . (s n) at every face node, with
-// the face owner's normal, stored per face side for the BR1 mean.
+// Viscous operator of a flagged element: viscous divergence part and face traces.
 template <int N>
-__global__ __launch_bounds__(Shape<N>::NT) void k_viscous_traces(ElemArgs A)
+__global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
     __shared__ double lds[12 * N3];
@@ -288,12 +289,32 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous_traces(ElemArgs A)
     ElemCtx<N> c;
     if (!load_element<N>(A, sD, c)) return;
     double fv[3][3];
-    viscous_flux<N>(A, c, lds, fv);
+    viscous_flux<N>(A, c, lds, fv);     // ends with a barrier: lds is free
+    if (c.act) {
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                lds[(ii * 3 + r) * N3 + c.tid] = c.Ja[ii][0] * fv[r][0] + c.Ja[ii][1] * fv[r][1] + c.Ja[ii][2] * fv[r][2];
+    }
+    __syncthreads();
+    double W[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const int n0 = m + N * c.j + N2 * c.k, n1 = c.i + N * m + N2 * c.k, n2 = c.i + N * c.j + N2 * m;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            W[r] -= c.Dx[m] * lds[r * N3 + n0] + c.Dy[m] * lds[(3 + r) * N3 + n1] + c.Dz[m] * lds[(6 + r) * N3 + n2];
+    }
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
         const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
         if (c.act && (idx == 0 || idx == N - 1)) {
             const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
+            const double sf = (f & 1) ? 1.0 : -1.0;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) W[r] += sf * lds[(dir * 3 + r) * N3 + c.tid] * A.inv_wend;
+            // face trace tau . (s n), n the face owner's outward normal
             const int fa = dir == 0 ? c.j : c.i;
             const int fb = dir == 2 ? c.j : c.k;
             const FaceRef fr = A.conn[(size_t)c.e * 6 + f];
@@ -308,9 +329,14 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous_traces(ElemArgs A)
             for (int r = 0; r < 3; ++r) out[r] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
         }
     }
+    if (c.act) {
+        double *wv = A.wvis + (size_t)c.e * 3 * N3 + c.tid;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) wv[r * N3] = W[r];
+    }
 }
 
-template <int N, bool VISC, int EPI>
+template <int N, int EPI>
 __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
@@ -318,22 +344,16 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
     __shared__ double sD[N2];
     ElemCtx<N> c;
     if (!load_element<N>(A, sD, c)) return;
+    const bool visc = A.flag[c.e] != 0;
 
-    double fv[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) fv[r][d] = 0.0;
-    if constexpr (VISC) viscous_flux<N>(A, c, lds, fv);
-
-    // contravariant fluxes F^i_row = sum_d Ja^i_d (f_conv - f_visc)_{row,d}
+    // contravariant convective fluxes F^i_row = sum_d Ja^i_d f_{row,d}
     {
         double f[4][3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             f[0][d] = A.c0sq * c.q[1 + d];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) f[1 + r][d] = c.q[1 + r] * c.q[1 + d] + (r == d ? c.q[0] : 0.0) - fv[r][d];
+            for (int r = 0; r < 3; ++r) f[1 + r][d] = c.q[1 + r] * c.q[1 + d] + (r == d ? c.q[0] : 0.0);
         }
         if (c.act) {
 #pragma unroll
@@ -385,9 +405,10 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
 #pragma unroll
             for (int x = 0; x < 4; ++x) F[x] *= s;
             const bool nb_visc = fr.nbr >= 0 && A.flag[fr.nbr];
-            const bool visL = own ? VISC : nb_visc;
-            const bool visR = own ? nb_visc : VISC;
+            const bool visL = own ? visc : nb_visc;
+            const bool visR = own ? nb_visc : visc;
             if (visL || visR) {
+                // BR1: mean of the two sides' viscous traces (an Euler side contributes zero)
                 const double *tv = A.fvt + ((size_t)fr.face * 2 * N2 + fnode) * 3;
                 double fvn[3];
                 if (fr.nbr < 0) {
@@ -414,6 +435,11 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
     }
 
     if (!c.act) return;
+    if (visc) {
+        const double *wv = A.wvis + (size_t)c.e * 3 * N3 + c.tid;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) V[1 + r] += wv[r * N3];
+    }
     const size_t base = (size_t)c.e * 4 * N3 + c.tid;
 #pragma unroll
     for (int row = 0; row < 4; ++row) {
@@ -488,25 +514,20 @@ __global__ __launch_bounds__(256) void k_copy(uint4 *dst, const uint4 *src, int6
 }
 
 template <int N>
-hipError_t launch_traces_n(const ElemArgs &a, hipStream_t s)
+hipError_t launch_viscous_n(const ElemArgs &a, hipStream_t s)
 {
     if (a.count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_viscous_traces<N>, dim3(kXcd * a.per_xcd), dim3(Shape<N>::NT), 0, s, a);
+    hipLaunchKernelGGL(k_viscous<N>, dim3(kXcd * a.per_xcd), dim3(Shape<N>::NT), 0, s, a);
     return hipGetLastError();
 }
 
 template <int N>
-hipError_t launch_residual_n(bool viscous, Epi epi, const ElemArgs &a, hipStream_t s)
+hipError_t launch_residual_n(Epi epi, const ElemArgs &a, hipStream_t s)
 {
     if (a.count == 0) return hipSuccess;
     const dim3 grid(kXcd * a.per_xcd), block(Shape<N>::NT);
-    if (viscous) {
-        if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<N, true, 0>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_residual<N, true, 1>), grid, block, 0, s, a);
-    } else {
-        if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<N, false, 0>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_residual<N, false, 1>), grid, block, 0, s, a);
-    }
+    if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<N, 0>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_residual<N, 1>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
@@ -535,16 +556,16 @@ hipError_t launch_reduce_n(const double *r, const double *mass, int64_t ne, doub
     default: return hipErrorInvalidValue;                                              \
     }
 
-hipError_t launch_viscous_traces(int N, const ElemArgs &a, hipStream_t s)
+hipError_t launch_viscous(int N, const ElemArgs &a, hipStream_t s)
 {
-#define C_(n) launch_traces_n<n>(a, s)
+#define C_(n) launch_viscous_n<n>(a, s)
     HDG_DISPATCH_N(N, C_)
 #undef C_
 }
 
-hipError_t launch_residual(int N, bool viscous, Epi epi, const ElemArgs &a, hipStream_t s)
+hipError_t launch_residual(int N, Epi epi, const ElemArgs &a, hipStream_t s)
 {
-#define C_(n) launch_residual_n<n>(viscous, epi, a, s)
+#define C_(n) launch_residual_n<n>(epi, a, s)
     HDG_DISPATCH_N(N, C_)
 #undef C_
 }

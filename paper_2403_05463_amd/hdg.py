@@ -19,8 +19,8 @@ HDG_OK, HDG_EINVAL, HDG_ENOMEM, HDG_EHIP, HDG_EUNSUPPORTED, HDG_EMESH, HDG_ENONF
 HDG_F64, HDG_F32 = 0, 1
 HDG_WALL, HDG_FARFIELD = -1, -2
 HDG_LES_NONE, HDG_LES_SMAGORINSKY, HDG_LES_VREMAN = 0, 1, 2
-HDG_KERNEL_VISCOUS_TRACES, HDG_KERNEL_RESIDUAL_EULER, HDG_KERNEL_RESIDUAL_VISCOUS = 0, 1, 2
-KERNEL_NAMES = {0: "viscous_traces", 1: "residual_euler", 2: "residual_viscous"}
+HDG_KERNEL_VISCOUS, HDG_KERNEL_RESIDUAL = 0, 1
+KERNEL_NAMES = {0: "viscous", 1: "residual"}
 
 EXPORTED = [
     "hdg_init", "hdg_finalize", "hdg_mesh_create", "hdg_mesh_destroy", "hdg_mesh_set_flags",

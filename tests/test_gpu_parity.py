@@ -120,10 +120,22 @@ def test_residual_parity_naca_working_size(orc, torch_cuda, ctx):
 def test_rk3_parity_naca_working_size(orc, torch_cuda, ctx):
     w = W.naca_working()
     q = W.initial_state(w, None)
-    dt = W.cfl_dt(w.mesh, w.P, q, w.params["c0sq"])
-    _say(f"{w.name} 2 RK3 steps dt={dt:.3e}")
-    out, ref, mass, _ = _run_pair(orc, torch_cuda, ctx, w.mesh, w.P, w.flag, w.params, q, rk=(dt, 2))
+    _say(f"{w.name} 2 RK3 steps dt={w.dt:.3e}")
+    out, ref, mass, _ = _run_pair(orc, torch_cuda, ctx, w.mesh, w.P, w.flag, w.params, q, rk=(w.dt, 2))
     assert_parity(out, ref, mass, what=w.name + " rk3")
+
+
+def test_naca_working_size_stays_bounded(torch_cuda, ctx):
+    """100 RK steps of the benchmark workload at its stated dt: finite and bounded."""
+    torch = torch_cuda
+    w = W.naca_working()
+    _say(f"{w.name} {w.nsteps} RK3 steps dt={w.dt:.1e}: finiteness")
+    m = hdg.hdg_mesh_create(ctx, w.mesh, w.P, w.flag, hdg.make_params(**w.params))
+    q = torch.from_numpy(W.initial_state(w, None)).cuda()
+    dq = torch.empty_like(q)
+    hdg.hdg_rk3_steps(m, q, dq, w.dt, w.nsteps)
+    red = hdg.hdg_reduce(m, q)
+    assert red["finite"] and red["max"][1:].max() < 3.0
 
 
 def test_deterministic_bitwise(orc, torch_cuda, ctx):
@@ -139,8 +151,8 @@ def test_deterministic_bitwise(orc, torch_cuda, ctx):
     assert torch.equal(r1, r2)
     qa, qb = q.clone(), q.clone()
     dq = torch.empty_like(q)
-    hdg.hdg_rk3_steps(m, qa, dq, 1e-5, 3)
-    hdg.hdg_rk3_steps(m, qb, dq, 1e-5, 3)
+    hdg.hdg_rk3_steps(m, qa, dq, 1e-7, 3)
+    hdg.hdg_rk3_steps(m, qb, dq, 1e-7, 3)
     torch.cuda.synchronize()
     assert torch.equal(qa, qb)
 
@@ -241,8 +253,8 @@ def test_timing_and_copy_probe(torch_cuda, ctx):
     q = torch.from_numpy(W.initial_state(w, None)).cuda()
     dq = torch.empty_like(q)
     hdg.hdg_timing_enable(m, True)
-    hdg.hdg_rk3_steps(m, q, dq, 1e-5, 2)
-    for k in range(3):
+    hdg.hdg_rk3_steps(m, q, dq, 1e-7, 2)
+    for k in hdg.KERNEL_NAMES:
         ms, n = hdg.hdg_timing_read(m, k)
         assert n == 6 and ms > 0
     hdg.hdg_timing_enable(m, False)
