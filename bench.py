@@ -43,7 +43,7 @@ def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: boo
     N3, N2 = N ** 3, N ** 2
     if kind == 0:
         return float(n_visc * ((24 + 80 + 24) * N3 + 3 * N2 * 32 + 6 * N2 * 24))
-    per_node = 32 + 80 + (96 + 32 if fused_rk else 32)
+    per_node = 32 + 80 + (96 if fused_rk else 32)
     b = n_elem * (per_node * N3 + 3 * N2 * 32)
     b += n_visc * (24 * N3 + 6 * N2 * 24)
     return float(b)

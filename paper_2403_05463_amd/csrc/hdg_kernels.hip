@@ -232,7 +232,7 @@ struct ElemCtx {
     double Dx[N], Dy[N], Dz[N];
 };
 
-// Common prologue: element id, own state and metric terms, derivative rows.
+// Common prologue: element id, own state and metric terms, derivative matrix in LDS.
 // Returns false for workgroups past the end of the list (uniform per block).
 template <int N>
 __device__ __forceinline__ bool load_element(const ElemArgs &A, double *sD, ElemCtx<N> &c)
@@ -258,13 +258,19 @@ __device__ __forceinline__ bool load_element(const ElemArgs &A, double *sD, Elem
 #pragma unroll
         for (int d = 0; d < 3; ++d) c.Ja[ii][d] = me[(1 + 3 * ii + d) * N3 + c.t];
     __syncthreads();
+    return true;
+}
+
+// Rows of the derivative matrix for this lane's node (after load_element).
+template <int N>
+__device__ __forceinline__ void load_drows(const double *sD, ElemCtx<N> &c)
+{
 #pragma unroll
     for (int m = 0; m < N; ++m) {
         c.Dx[m] = sD[c.i * N + m];
         c.Dy[m] = sD[c.j * N + m];
         c.Dz[m] = sD[c.k * N + m];
     }
-    return true;
 }
 
 template <int N>
@@ -288,6 +294,7 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
     __shared__ double sD[N2];
     ElemCtx<N> c;
     if (!load_element<N>(A, sD, c)) return;
+    load_drows<N>(sD, c);
     double fv[3][3];
     viscous_flux<N>(A, c, lds, fv);     // ends with a barrier: lds is free
     if (c.act) {
@@ -336,11 +343,75 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
     }
 }
 
+// Single-valued numerical flux through one face node of element e, outward for
+// e and multiplied by the surface scale: Roe on the two traces, minus the BR1
+// mean of the stored viscous traces when a side is flagged.  Both elements of
+// a face evaluate it with the owner's trace on the left and the owner's
+// normal, so the two results are exact negatives of each other.
+template <int N>
+__device__ __forceinline__ void face_flux(const ElemArgs &A, int e, bool visc, int f, int fa, int fb,
+                                          double (&F)[4])
+{
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
+    const FaceRef fr = A.conn[(size_t)e * 6 + f];
+    const bool own = fr.code & kOwnerBit;
+    const double *qe = A.q + (size_t)e * 4 * N3 + face_node<N>(f, fa, fb);
+    double qm[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) qm[x] = qe[x * N3];
+    double qo[4];
+    int oa, ob;
+    outside_state<N, 4>(A, fr, fa, fb, qm, qo, oa, ob);
+    const int fnode = oa + N * ob;
+    const double *g = A.fgeo + ((size_t)fr.face * N2 + fnode) * 4;
+    const double nh[3] = {g[0], g[1], g[2]};
+    const double s = g[3];
+    const bool nb_visc = fr.nbr >= 0 && A.flag[fr.nbr];
+    const bool visL = own ? visc : nb_visc;
+    const bool visR = own ? nb_visc : visc;
+    double tvL[3] = {0.0, 0.0, 0.0}, tvR[3] = {0.0, 0.0, 0.0};
+    const double *tv = A.fvt + ((size_t)fr.face * 2 * N2 + fnode) * 3;
+    if (visL) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) tvL[r] = tv[r];
+    }
+    if (visR && fr.nbr >= 0) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) tvR[r] = tv[N2 * 3 + r];
+    }
+    double qL[4], qR[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        qL[x] = own ? qm[x] : qo[x];
+        qR[x] = own ? qo[x] : qm[x];
+    }
+    roe_flux(A.c0sq, qL, qR, nh, F);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) F[x] *= s;
+    if (visL || visR) {
+        // BR1: mean of the two sides' viscous traces (an Euler side contributes
+        // zero); a boundary face takes the interior trace
+        const bool keep = fr.nbr < 0 || A.mixed_face == 0 || (visL && visR);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const double fvn = fr.nbr < 0 ? tvL[r] : 0.5 * (tvL[r] + tvR[r]);
+            F[1 + r] -= keep ? fvn : 0.0;
+        }
+    }
+    if (!own) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) F[x] = -F[x];
+    }
+}
+
 template <int N, int EPI>
 __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
 {
-    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
-    __shared__ double lds[12 * N3];
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3, NT = Shape<N>::NT;
+    constexpr int NFT = 6 * N2;                        // face-node tasks per element
+    constexpr int TPT = (NFT + NT - 1) / NT;           // tasks per lane
+    __shared__ double lds[12 * N3];                    // contravariant fluxes
+    __shared__ double sface[NFT * 4];                  // numerical fluxes, outward, per face node
     __shared__ double sD[N2];
     ElemCtx<N> c;
     if (!load_element<N>(A, sD, c)) return;
@@ -364,7 +435,29 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
                         c.Ja[ii][0] * f[row][0] + c.Ja[ii][1] * f[row][1] + c.Ja[ii][2] * f[row][2];
         }
     }
+
+    // face-node tasks, spread evenly over the workgroup
+#pragma unroll 1
+    for (int k = 0; k < TPT; ++k) {
+        const int task = c.tid + k * NT;
+        if (task < NFT) {
+            const int f = task / N2, fn = task % N2;
+            double F[4];
+            face_flux<N>(A, c.e, visc, f, fn % N, fn / N, F);
+#pragma unroll
+            for (int row = 0; row < 4; ++row) sface[task * 4 + row] = F[row];
+        }
+    }
+    double dq_old[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (EPI == (int)Epi::RkStage) {
+        if (!A.first_stage) {
+            const double *dqe = A.dq + (size_t)c.e * 4 * N3 + c.t;
+#pragma unroll
+            for (int row = 0; row < 4; ++row) dq_old[row] = dqe[row * N3];
+        }
+    }
     __syncthreads();
+    load_drows<N>(sD, c);
 
     // reference divergence
     double V[4] = {0.0, 0.0, 0.0, 0.0};
@@ -377,7 +470,7 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
                     + c.Dz[m] * lds[(8 + row) * N3 + n2];
     }
 
-    // face nodes: single-valued numerical flux minus own flux, over w_end
+    // face nodes: numerical flux minus own flux, over w_end
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
         const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
@@ -385,52 +478,11 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
             const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
             const int fa = dir == 0 ? c.j : c.i;
             const int fb = dir == 2 ? c.j : c.k;
-            const FaceRef fr = A.conn[(size_t)c.e * 6 + f];
-            const bool own = fr.code & kOwnerBit;
-            double qo[4];
-            int oa, ob;
-            outside_state<N, 4>(A, fr, fa, fb, c.q, qo, oa, ob);
-            const int fnode = oa + N * ob;
-            const double *g = A.fgeo + ((size_t)fr.face * N2 + fnode) * 4;
-            const double nh[3] = {g[0], g[1], g[2]};
-            const double s = g[3];
-            double qL[4], qR[4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                qL[x] = own ? c.q[x] : qo[x];
-                qR[x] = own ? qo[x] : c.q[x];
-            }
-            double F[4];
-            roe_flux(A.c0sq, qL, qR, nh, F);
-#pragma unroll
-            for (int x = 0; x < 4; ++x) F[x] *= s;
-            const bool nb_visc = fr.nbr >= 0 && A.flag[fr.nbr];
-            const bool visL = own ? visc : nb_visc;
-            const bool visR = own ? nb_visc : visc;
-            if (visL || visR) {
-                // BR1: mean of the two sides' viscous traces (an Euler side contributes zero)
-                const double *tv = A.fvt + ((size_t)fr.face * 2 * N2 + fnode) * 3;
-                double fvn[3];
-                if (fr.nbr < 0) {
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) fvn[r] = tv[r];
-                } else {
-                    const bool keep = A.mixed_face == 0 || (visL && visR);
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) {
-                        const double vl = visL ? tv[r] : 0.0;
-                        const double vr = visR ? tv[N2 * 3 + r] : 0.0;
-                        fvn[r] = keep ? 0.5 * (vl + vr) : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < 3; ++r) F[1 + r] -= fvn[r];
-            }
-            const double so = own ? 1.0 : -1.0;
             const double sf = (f & 1) ? 1.0 : -1.0;
+            const double *Fs = sface + (f * N2 + fa + N * fb) * 4;
 #pragma unroll
             for (int row = 0; row < 4; ++row)
-                V[row] += (so * F[row] - sf * lds[(dir * 4 + row) * N3 + c.tid]) * A.inv_wend;
+                V[row] += (Fs[row] - sf * lds[(dir * 4 + row) * N3 + c.tid]) * A.inv_wend;
         }
     }
 
@@ -448,7 +500,7 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
         if constexpr (EPI == (int)Epi::Residual) {
             A.out[idx] = R;
         } else {
-            const double d = A.first_stage ? A.dt * R : A.rkA * A.dq[idx] + A.dt * R;
+            const double d = A.first_stage ? A.dt * R : A.rkA * dq_old[row] + A.dt * R;
             A.dq[idx] = d;
             A.out[idx] = c.q[row] + A.rkB * d;
         }
@@ -507,10 +559,27 @@ __global__ __launch_bounds__(64) void k_reduce_final(const double *partials, int
     out[x] = v;
 }
 
-__global__ __launch_bounds__(256) void k_copy(uint4 *dst, const uint4 *src, int64_t n16)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCopyUnroll = 2;
+constexpr int kCopyBlock = 512;
+
+// Streaming copy: every lane moves kCopyUnroll 16-byte chunks, both loads in
+// flight before the first store (the fastest of the tile shapes measured on
+// MI355X; 8 chunks x 256 lanes hits a pathological access pattern).
+__global__ __launch_bounds__(kCopyBlock) void k_copy(u32x4 *dst, const u32x4 *src, int64_t n16)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const int64_t base = (int64_t)blockIdx.x * (kCopyUnroll * kCopyBlock) + threadIdx.x;
+    u32x4 v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kCopyBlock;
+        if (i < n16) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kCopyBlock;
+        if (i < n16) dst[i] = v[u];
+    }
 }
 
 template <int N>
@@ -581,10 +650,11 @@ hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_e
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s)
 {
     const int64_t n16 = nbytes / 16;
-    int64_t blocks = (n16 + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (uint4 *)dst, (const uint4 *)src, n16);
+    if (n16 == 0) return hipSuccess;
+    const int64_t blocks = (n16 + kCopyUnroll * kCopyBlock - 1) / (kCopyUnroll * kCopyBlock);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(kCopyBlock), 0, s, (u32x4 *)dst, (const u32x4 *)src,
+                       n16);
     return hipGetLastError();
 }
 
