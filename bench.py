@@ -27,6 +27,8 @@ if ROOT not in sys.path:
 
 METRIC = "DOF-residual evals/s (mixed NS-LES/Euler DG), plain vs batched FP32; p99 latency"
 HBM_PEAK_GBS = 8000.0
+# FETCH_SIZE / WRITE_SIZE summary of the benchmark's kernels (rocprofv3 --pmc)
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_naca0012_ogrid_96x48x8_P4_fp64.txt")
 
 
 def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: bool) -> float:
@@ -60,7 +62,7 @@ def cpu_baseline(w, q0, budget_s: float = 12.0) -> dict:
         om.residual(prm, q0)
         evals += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or evals >= 60:
+        if el >= budget_s or evals >= 1000:
             break
     return {"value": nodes * 4 * evals / el, "unit": "DOF-residual evals/s", "cores": oracle.get_threads(),
             "kind": "oracle",
@@ -84,6 +86,7 @@ def main(argv=None) -> int:
 
     import torch
     from paper_2403_05463_amd import hdg, workloads as W
+    from paper_2403_05463_amd.profiling import traffic_for
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -139,7 +142,9 @@ def main(argv=None) -> int:
     dom = max(kern, key=lambda k: kern[k][0])
     tot, n = kern[dom]
     avg_s = tot / max(n, 1) / 1e3
-    bytes_launch = algorithmic_bytes(kinds[dom], w.mesh.n_elem, n_visc, N, fused_rk=True)
+    # every stage runs each kernel class once over its element set
+    stages = 3 * args.steps
+    bytes_launch = algorithmic_bytes(kinds[dom], w.mesh.n_elem, n_visc, N, fused_rk=True) * stages / max(n, 1)
     achieved = bytes_launch / avg_s / 1e9
     evals = 3 * args.steps
     out = {
@@ -159,7 +164,8 @@ def main(argv=None) -> int:
                    "nodes": nodes, "dof": nodes * 4, "viscous_elements": n_visc,
                    "residuals_per_step": 3, "dt": dt, "rk": "3-stage low-storage (2N)"},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_for(TRAFFIC_SUMMARY, "k_" + dom),
                      "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch},
         "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern.items()},
         "node_evals_per_s": nodes * evals / (ms / 1e3),

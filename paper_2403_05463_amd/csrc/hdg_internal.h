@@ -33,7 +33,7 @@ struct ElemArgs {
     const double *fgeo;     // [face][N^2][4]: unit normal (outward for the owner), surface scale s
     const FaceRef *conn;    // [e][6]
     const uint8_t *flag;    // [e]
-    double *fvt;            // [face][2 sides][N^2][3]: viscous flux . (s n), side 0 = owner
+    double *fvt;            // [face][2 sides][3][N^2]: viscous flux . (s n), side 0 = owner
     double *wvis;           // [e][3][N^3]: viscous part of the reference divergence (flagged elements)
     const int32_t *list;    // elements handled by this launch
     const double *delta;    // [e] LES filter width

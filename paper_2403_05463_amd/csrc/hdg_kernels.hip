@@ -149,79 +149,6 @@ __device__ __forceinline__ void outside_state(const ElemArgs &A, const FaceRef &
     }
 }
 
-// BR1 gradient G[r][d] = du_r/dx_d of the velocity on a flagged element.
-// Uses lds[12 * N3] as scratch; all lanes of the block must call it.
-template <int N>
-__device__ __forceinline__ void br1_gradient(const ElemArgs &A, int e, int tid, bool act, int i, int j, int k,
-                                             const double (&Dx)[N], const double (&Dy)[N], const double (&Dz)[N],
-                                             const double (&Ja)[3][3], double invJ, const double (&q)[4],
-                                             double *lds, double (&G)[3][3])
-{
-    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
-    if (act) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) lds[r * N3 + tid] = q[1 + r];
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) lds[(3 + 3 * ii + d) * N3 + tid] = Ja[ii][d];
-    }
-    __syncthreads();
-    double JG[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) JG[r][d] = 0.0;
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-        const int n0 = m + N * j + N2 * k, n1 = i + N * m + N2 * k, n2 = i + N * j + N2 * m;
-        double u0[3], u1[3], u2[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            u0[r] = lds[r * N3 + n0];
-            u1[r] = lds[r * N3 + n1];
-            u2[r] = lds[r * N3 + n2];
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double g0 = Dx[m] * lds[(3 + d) * N3 + n0];
-            const double g1 = Dy[m] * lds[(6 + d) * N3 + n1];
-            const double g2 = Dz[m] * lds[(9 + d) * N3 + n2];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) JG[r][d] += g0 * u0[r] + g1 * u1[r] + g2 * u2[r];
-        }
-    }
-    // face correction: (u* (s n)_out - u (+-Ja^dir)) / w_end, u* the mean of the traces
-#pragma unroll
-    for (int dir = 0; dir < 3; ++dir) {
-        const int idx = dir == 0 ? i : dir == 1 ? j : k;
-        if (act && (idx == 0 || idx == N - 1)) {
-            const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
-            const int fa = dir == 0 ? j : i;
-            const int fb = dir == 2 ? j : k;
-            const FaceRef fr = A.conn[(size_t)e * 6 + f];
-            double uo[3];
-            int oa, ob;
-            outside_state<N, 3>(A, fr, fa, fb, q, uo, oa, ob);
-            const double *g = A.fgeo + ((size_t)fr.face * N2 + oa + N * ob) * 4;
-            const double so = (fr.code & kOwnerBit) ? g[3] : -g[3];
-            const double sn[3] = {g[0] * so, g[1] * so, g[2] * so};
-            const double sf = (f & 1) ? 1.0 : -1.0;
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const double ustar = 0.5 * (q[1 + r] + uo[r]);
-#pragma unroll
-                for (int d = 0; d < 3; ++d) JG[r][d] += (ustar * sn[d] - q[1 + r] * sf * Ja[dir][d]) * A.inv_wend;
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) G[r][d] = JG[r][d] * invJ;
-    __syncthreads();   // lds is reused by the caller
-}
-
 template <int N>
 struct ElemCtx {
     int e, tid, t, i, j, k;
@@ -274,29 +201,134 @@ __device__ __forceinline__ void load_drows(const double *sD, ElemCtx<N> &c)
 }
 
 template <int N>
-__device__ __forceinline__ void viscous_flux(const ElemArgs &A, ElemCtx<N> &c, double *lds, double (&fv)[3][3])
+__device__ __forceinline__ FaceRef select_face(const FaceRef (&frs)[6], int f)
 {
-    double G[3][3];
-    br1_gradient<N>(A, c.e, c.tid, c.act, c.i, c.j, c.k, c.Dx, c.Dy, c.Dz, c.Ja, c.invJ, c.q, lds, G);
-    const double mu = A.nu + les_nut(A.les_model, A.C_les, A.delta[c.e], G);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) fv[r][d] = mu * (G[r][d] + G[d][r]);
+    FaceRef fr = frs[0];
+    if (f == 1) fr = frs[1];
+    if (f == 2) fr = frs[2];
+    if (f == 3) fr = frs[3];
+    if (f == 4) fr = frs[4];
+    if (f == 5) fr = frs[5];
+    return fr;
 }
 
-// Viscous operator of a flagged element: viscous divergence part and face traces.
+// Viscous operator of a flagged element.
+//  1. face-node tasks gather the neighbours' velocity traces and this
+//     element's outward s n (the face owner's normal, signed) into LDS;
+//  2. BR1 lifted gradient: J G = sum_i D_i (Ja^i u) + on face nodes
+//     (u* (s n) - u (+-Ja^dir)) / w_end, u* the mean of the two traces
+//     (no-slip wall: ghost -u; far field: ghost u_inf);
+//  3. eddy viscosity and stress tau = 2 (nu + nu_t) S;
+//  4. viscous part of the reference divergence, -D F_v + (+-F_v^dir)/w_end on
+//     face nodes, and the face traces tau . (s n) with the owner's normal.
 template <int N>
 __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
 {
-    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
-    __shared__ double lds[12 * N3];
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3, NT = Shape<N>::NT;
+    constexpr int NFT = 6 * N2;
+    constexpr int TPT = (NFT + NT - 1) / NT;
+    __shared__ double lds[12 * N3];        // u, v, w and Ja; later the viscous contravariant fluxes
+    __shared__ double sfu[3 * NFT];        // neighbour velocity trace per face node (interior faces), [r][task]
+    __shared__ double sfn[3 * NFT];        // outward s n per face node, [d][task]
     __shared__ double sD[N2];
     ElemCtx<N> c;
     if (!load_element<N>(A, sD, c)) return;
-    load_drows<N>(sD, c);
+    FaceRef frs[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) frs[f] = A.conn[(size_t)c.e * 6 + f];
+    if (c.act) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) lds[r * N3 + c.tid] = c.q[1 + r];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) lds[(3 + 3 * ii + d) * N3 + c.tid] = c.Ja[ii][d];
+    }
+#pragma unroll 1
+    for (int kk = 0; kk < TPT; ++kk) {
+        const int task = c.tid + kk * NT;
+        if (task < NFT) {
+            const int f = task / N2, fn = task % N2, fa = fn % N, fb = fn / N;
+            const FaceRef fr = select_face<N>(frs, f);
+            const bool own = fr.code & kOwnerBit;
+            int oa = fa, ob = fb;
+            if (fr.nbr >= 0) {
+                int a2, b2;
+                orient_map<N>(fr.code & 7, fa, fb, a2, b2);
+                if (!own) { oa = a2; ob = b2; }
+                const double *qn = A.q + (size_t)fr.nbr * 4 * N3 + face_node<N>((fr.code >> 3) & 7, a2, b2);
+#pragma unroll
+                for (int r = 0; r < 3; ++r) sfu[r * NFT + task] = qn[(1 + r) * N3];
+            }
+            const double *g = A.fgeo + ((size_t)fr.face * N2 + oa + N * ob) * 4;
+            const double so = own ? g[3] : -g[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sfn[d * NFT + task] = g[d] * so;
+        }
+    }
+    __syncthreads();
+
+    double G[3][3];
+    {
+        double JG[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) JG[r][d] = 0.0;
+#pragma unroll 1
+        for (int m = 0; m < N; ++m) {
+            const int n0 = m + N * c.j + N2 * c.k, n1 = c.i + N * m + N2 * c.k, n2 = c.i + N * c.j + N2 * m;
+            double u0[3], u1[3], u2[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                u0[r] = lds[r * N3 + n0];
+                u1[r] = lds[r * N3 + n1];
+                u2[r] = lds[r * N3 + n2];
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double g0 = sD[c.i * N + m] * lds[(3 + d) * N3 + n0];
+                const double g1 = sD[c.j * N + m] * lds[(6 + d) * N3 + n1];
+                const double g2 = sD[c.k * N + m] * lds[(9 + d) * N3 + n2];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) JG[r][d] += g0 * u0[r] + g1 * u1[r] + g2 * u2[r];
+            }
+        }
+#pragma unroll
+        for (int dir = 0; dir < 3; ++dir) {
+            const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
+            if (c.act && (idx == 0 || idx == N - 1)) {
+                const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
+                const int task = f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
+                const FaceRef fr = select_face<N>(frs, f);
+                double uo[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+                    uo[r] = fr.nbr >= 0 ? sfu[r * NFT + task] : fr.nbr == HDG_WALL ? -c.q[1 + r] : A.qinf[1 + r];
+                const double sf = (f & 1) ? 1.0 : -1.0;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const double ustar = 0.5 * (c.q[1 + r] + uo[r]);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        JG[r][d] += (ustar * sfn[d * NFT + task] - c.q[1 + r] * sf * c.Ja[dir][d]) * A.inv_wend;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) G[r][d] = JG[r][d] * c.invJ;
+    }
     double fv[3][3];
-    viscous_flux<N>(A, c, lds, fv);     // ends with a barrier: lds is free
+    {
+        const double mu = A.nu + les_nut(A.les_model, A.C_les, A.delta[c.e], G);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) fv[r][d] = mu * (G[r][d] + G[d][r]);
+    }
+    __syncthreads();     // every lane is done reading u and Ja from lds
     if (c.act) {
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii)
@@ -306,12 +338,12 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
     }
     __syncthreads();
     double W[3] = {0.0, 0.0, 0.0};
-#pragma unroll
+#pragma unroll 1
     for (int m = 0; m < N; ++m) {
         const int n0 = m + N * c.j + N2 * c.k, n1 = c.i + N * m + N2 * c.k, n2 = c.i + N * c.j + N2 * m;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-            W[r] -= c.Dx[m] * lds[r * N3 + n0] + c.Dy[m] * lds[(3 + r) * N3 + n1] + c.Dz[m] * lds[(6 + r) * N3 + n2];
+            W[r] -= sD[c.i * N + m] * lds[r * N3 + n0] + sD[c.j * N + m] * lds[(3 + r) * N3 + n1] + sD[c.k * N + m] * lds[(6 + r) * N3 + n2];
     }
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
@@ -321,19 +353,19 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
             const double sf = (f & 1) ? 1.0 : -1.0;
 #pragma unroll
             for (int r = 0; r < 3; ++r) W[r] += sf * lds[(dir * 3 + r) * N3 + c.tid] * A.inv_wend;
-            // face trace tau . (s n), n the face owner's outward normal
+            // face trace tau . (s n) with the face owner's outward normal
             const int fa = dir == 0 ? c.j : c.i;
             const int fb = dir == 2 ? c.j : c.k;
-            const FaceRef fr = A.conn[(size_t)c.e * 6 + f];
+            const int task = f * N2 + fa + N * fb;
+            const FaceRef fr = select_face<N>(frs, f);
             const bool own = fr.code & kOwnerBit;
             int oa = fa, ob = fb;
             if (!own) orient_map<N>(fr.code & 7, fa, fb, oa, ob);
-            const int fnode = oa + N * ob;
-            const double *g = A.fgeo + ((size_t)fr.face * N2 + fnode) * 4;
-            const double sn[3] = {g[0] * g[3], g[1] * g[3], g[2] * g[3]};
-            double *out = A.fvt + (((size_t)fr.face * 2 + (own ? 0 : 1)) * N2 + fnode) * 3;
+            const double so = own ? 1.0 : -1.0;
+            const double sn[3] = {sfn[task] * so, sfn[NFT + task] * so, sfn[2 * NFT + task] * so};
+            double *out = A.fvt + ((size_t)fr.face * 2 + (own ? 0 : 1)) * 3 * N2 + oa + N * ob;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) out[r] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
+            for (int r = 0; r < 3; ++r) out[r * N2] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
         }
     }
     if (c.act) {
@@ -350,10 +382,15 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
 // normal, so the two results are exact negatives of each other.
 template <int N>
 __device__ __forceinline__ void face_flux(const ElemArgs &A, int e, bool visc, int f, int fa, int fb,
-                                          double (&F)[4])
+                                          double (&F)[4], const FaceRef (&frs)[6])
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
-    const FaceRef fr = A.conn[(size_t)e * 6 + f];
+    FaceRef fr = frs[0];
+    if (f == 1) fr = frs[1];
+    if (f == 2) fr = frs[2];
+    if (f == 3) fr = frs[3];
+    if (f == 4) fr = frs[4];
+    if (f == 5) fr = frs[5];
     const bool own = fr.code & kOwnerBit;
     const double *qe = A.q + (size_t)e * 4 * N3 + face_node<N>(f, fa, fb);
     double qm[4];
@@ -370,14 +407,14 @@ __device__ __forceinline__ void face_flux(const ElemArgs &A, int e, bool visc, i
     const bool visL = own ? visc : nb_visc;
     const bool visR = own ? nb_visc : visc;
     double tvL[3] = {0.0, 0.0, 0.0}, tvR[3] = {0.0, 0.0, 0.0};
-    const double *tv = A.fvt + ((size_t)fr.face * 2 * N2 + fnode) * 3;
+    const double *tv = A.fvt + (size_t)fr.face * 6 * N2 + fnode;
     if (visL) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) tvL[r] = tv[r];
+        for (int r = 0; r < 3; ++r) tvL[r] = tv[r * N2];
     }
     if (visR && fr.nbr >= 0) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) tvR[r] = tv[N2 * 3 + r];
+        for (int r = 0; r < 3; ++r) tvR[r] = tv[(3 + r) * N2];
     }
     double qL[4], qR[4];
 #pragma unroll
@@ -411,7 +448,7 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
     constexpr int NFT = 6 * N2;                        // face-node tasks per element
     constexpr int TPT = (NFT + NT - 1) / NT;           // tasks per lane
     __shared__ double lds[12 * N3];                    // contravariant fluxes
-    __shared__ double sface[NFT * 4];                  // numerical fluxes, outward, per face node
+    __shared__ double sface[4 * NFT];                  // numerical fluxes, outward, [row][face node]
     __shared__ double sD[N2];
     ElemCtx<N> c;
     if (!load_element<N>(A, sD, c)) return;
@@ -436,6 +473,9 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
         }
     }
 
+    FaceRef frs[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) frs[f] = A.conn[(size_t)c.e * 6 + f];
     // face-node tasks, spread evenly over the workgroup
 #pragma unroll 1
     for (int k = 0; k < TPT; ++k) {
@@ -443,9 +483,9 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
         if (task < NFT) {
             const int f = task / N2, fn = task % N2;
             double F[4];
-            face_flux<N>(A, c.e, visc, f, fn % N, fn / N, F);
+            face_flux<N>(A, c.e, visc, f, fn % N, fn / N, F, frs);
 #pragma unroll
-            for (int row = 0; row < 4; ++row) sface[task * 4 + row] = F[row];
+            for (int row = 0; row < 4; ++row) sface[row * NFT + task] = F[row];
         }
     }
     double dq_old[4] = {0.0, 0.0, 0.0, 0.0};
@@ -479,10 +519,10 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
             const int fa = dir == 0 ? c.j : c.i;
             const int fb = dir == 2 ? c.j : c.k;
             const double sf = (f & 1) ? 1.0 : -1.0;
-            const double *Fs = sface + (f * N2 + fa + N * fb) * 4;
+            const double *Fs = sface + f * N2 + fa + N * fb;
 #pragma unroll
             for (int row = 0; row < 4; ++row)
-                V[row] += (Fs[row] - sf * lds[(dir * 4 + row) * N3 + c.tid]) * A.inv_wend;
+                V[row] += (Fs[row * NFT] - sf * lds[(dir * 4 + row) * N3 + c.tid]) * A.inv_wend;
         }
     }
 
@@ -547,16 +587,34 @@ __global__ __launch_bounds__(256) void k_reduce_partial(const double *r, const d
     if (threadIdx.x < 13) partials[(size_t)blockIdx.x * 13 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(64) void k_reduce_final(const double *partials, int nblocks, double *out)
+// Final reduction of the per-block partials: 256 lanes, fixed order (lane x
+// takes blocks x, x + 256, ...; then a tree), so results are deterministic.
+__global__ __launch_bounds__(256) void k_reduce_final(const double *partials, int nblocks, double *out)
 {
-    if (threadIdx.x >= 13) return;
-    const int x = threadIdx.x;
-    double v = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-        const double p = partials[(size_t)b * 13 + x];
-        v = x < 8 ? v + p : fmax(v, p);
+    __shared__ double red[13][256];
+    double acc[13];
+#pragma unroll
+    for (int x = 0; x < 13; ++x) acc[x] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+        for (int x = 0; x < 13; ++x) {
+            const double p = partials[(size_t)b * 13 + x];
+            acc[x] = x < 8 ? acc[x] + p : fmax(acc[x], p);
+        }
     }
-    out[x] = v;
+#pragma unroll
+    for (int x = 0; x < 13; ++x) red[x][threadIdx.x] = acc[x];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int x = 0; x < 8; ++x) red[x][threadIdx.x] += red[x][threadIdx.x + w];
+#pragma unroll
+            for (int x = 8; x < 13; ++x) red[x][threadIdx.x] = fmax(red[x][threadIdx.x], red[x][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 13) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -607,7 +665,7 @@ hipError_t launch_reduce_n(const double *r, const double *mass, int64_t ne, doub
     hipLaunchKernelGGL(k_reduce_partial<N>, dim3(nblocks), dim3(256), 0, s, r, mass, ne, partials);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, partials, nblocks, final13);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partials, nblocks, final13);
     return hipGetLastError();
 }
 
