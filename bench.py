@@ -28,27 +28,35 @@ if ROOT not in sys.path:
 METRIC = "DOF-residual evals/s (mixed NS-LES/Euler DG), plain vs batched FP32; p99 latency"
 HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE summary of the benchmark's kernels (rocprofv3 --pmc)
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_naca0012_ogrid_96x48x8_P4_fp64.txt")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_naca0012_ogrid_96x48x8_P4.txt")
 
 
-def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: bool) -> float:
-    """Bytes a launch must move at least once (perfect caching), FP64.
+def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: bool, f32: bool = False) -> float:
+    """Bytes a launch must move at least once (perfect caching).
 
-    Residual kernel, every element: state 32 B/node, metric terms (1/J + 9 Ja)
-    80 B/node; fused RK stage: + dq read/write 64 + next state 32 (residual
-    only: + R 32); face geometry 32 B per face node, three faces owned per
-    element.  Flagged elements add the viscous divergence part (24 B/node)
-    and both sides' viscous face traces (24 B per face node and side).
-    Viscous kernel, flagged elements: velocity 24 + metric 80 B/node, face
-    geometry, out the viscous part 24 B/node and six faces of traces.
+    Residual kernel, every element: state 32 B/node (FP64 in both precision
+    forms), metric terms (1/J + 9 Ja) 80 B/node in FP64, 40 in FP32; fused
+    RK stage: + dq read/write 64 + next state 32 (residual only: + R 32 in
+    FP64, 16 in FP32); face geometry (n, s) 32 B (16) per face node, three
+    faces owned per element.  Flagged elements add the viscous divergence
+    part (24 B/node, 12 in FP32) and both sides' viscous face traces (24 B,
+    12 in FP32, per face node and side).
+    Viscous kernel, flagged elements: velocity 24 + metric terms per node,
+    out the viscous part per node and six faces of traces.
     """
     N3, N2 = N ** 3, N ** 2
+    met, tv, fg = (40, 12, 16) if f32 else (80, 24, 32)
     if kind == 0:
-        return float(n_visc * ((24 + 80 + 24) * N3 + 3 * N2 * 32 + 6 * N2 * 24))
-    per_node = 32 + 80 + (96 if fused_rk else 32)
-    b = n_elem * (per_node * N3 + 3 * N2 * 32)
-    b += n_visc * (24 * N3 + 6 * N2 * 24)
+        return float(n_visc * ((24 + met + tv) * N3 + 6 * N2 * tv))
+    per_node = 32 + met + (96 if fused_rk else (16 if f32 else 32))
+    b = n_elem * (per_node * N3 + 3 * N2 * fg)
+    b += n_visc * (tv * N3 + 6 * N2 * tv)
     return float(b)
+
+
+def kernel_symbol(kind: int, N: int, f32: bool, fused_rk: bool = True) -> str:
+    t = "float" if f32 else "double"
+    return f"k_viscous<{N}, {t}>" if kind == 0 else f"k_residual<{N}, {1 if fused_rk else 0}, {t}>"
 
 
 def cpu_baseline(w, q0, budget_s: float = 12.0) -> dict:
@@ -105,21 +113,22 @@ def main(argv=None) -> int:
     print(f"[bench] {w.name}: {nodes} nodes, {info['n_viscous']} viscous of {w.mesh.n_elem} elements, "
           f"dt={dt:.3e}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
 
-    hdg.hdg_rk3_steps(mesh, q, dq, dt, args.warmup, stream=stream)
-    torch.cuda.synchronize()
-    hdg.hdg_timing_enable(mesh, True)
-    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    hdg.hdg_rk3_steps(mesh, q, dq, dt, args.steps, stream=stream)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    ms = t_start.elapsed_time(t_end)
-    kern = {}
-    for k, name in hdg.KERNEL_NAMES.items():
-        tot, n = hdg.hdg_timing_read(mesh, k)
-        kern[name] = (tot, n)
-    hdg.hdg_timing_enable(mesh, False)
+    def timed_run(prec):
+        """K timed RK steps after W warm-up steps; wall time and per-kernel event totals."""
+        hdg.hdg_rk3_steps(mesh, q, dq, dt, args.warmup, prec=prec, stream=stream)
+        torch.cuda.synchronize()
+        hdg.hdg_timing_enable(mesh, True)
+        t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        hdg.hdg_rk3_steps(mesh, q, dq, dt, args.steps, prec=prec, stream=stream)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        kern = {name: hdg.hdg_timing_read(mesh, k) for k, name in hdg.KERNEL_NAMES.items()}
+        hdg.hdg_timing_enable(mesh, False)
+        return t_start.elapsed_time(t_end), kern
+
+    ms, kern = timed_run(hdg.HDG_F64)
     red = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
 
     # plain copy kernel of known size: attainable HBM bandwidth, and the
@@ -139,14 +148,24 @@ def main(argv=None) -> int:
 
     n_visc = info["n_viscous"]
     kinds = {name: k for k, name in hdg.KERNEL_NAMES.items()}
-    dom = max(kern, key=lambda k: kern[k][0])
-    tot, n = kern[dom]
-    avg_s = tot / max(n, 1) / 1e3
-    # every stage runs each kernel class once over its element set
-    stages = 3 * args.steps
-    bytes_launch = algorithmic_bytes(kinds[dom], w.mesh.n_elem, n_visc, N, fused_rk=True) * stages / max(n, 1)
-    achieved = bytes_launch / avg_s / 1e9
     evals = 3 * args.steps
+
+    def roofline(kern, f32):
+        """Dominant kernel class: algorithmic bytes per launch over its mean event-timed duration."""
+        dom = max(kern, key=lambda k: kern[k][0])
+        tot, n = kern[dom]
+        avg_s = tot / max(n, 1) / 1e3
+        # every stage runs each kernel class once over its element set
+        bytes_launch = algorithmic_bytes(kinds[dom], w.mesh.n_elem, n_visc, N, fused_rk=True, f32=f32) \
+            * evals / max(n, 1)
+        achieved = bytes_launch / avg_s / 1e9
+        sym = kernel_symbol(kinds[dom], N, f32)
+        return {"kernel": sym, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(TRAFFIC_SUMMARY, sym),
+                "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch}
+
+    roof = roofline(kern, False)
+    achieved = roof["achieved"]
     out = {
         "metric": METRIC,
         "value": nodes * 4 * evals / (ms / 1e3),
@@ -163,16 +182,22 @@ def main(argv=None) -> int:
         "config": {"workload": w.name, "form": "plain FP64", "elements": w.mesh.n_elem, "P": w.P,
                    "nodes": nodes, "dof": nodes * 4, "viscous_elements": n_visc,
                    "residuals_per_step": 3, "dt": dt, "rk": "3-stage low-storage (2N)"},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_for(TRAFFIC_SUMMARY, "k_" + dom),
-                     "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch},
+        "roofline": roof,
         "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern.items()},
         "node_evals_per_s": nodes * evals / (ms / 1e3),
         "state_finite": bool(red["finite"]),
         "stream_copy_GBps": copy_gbs,
         "frac_of_stream_copy": achieved / copy_gbs,
     }
+    # precision form on the same workload and state: FP32 contractions and
+    # fluxes, FP64 state and RK accumulation
+    q.copy_(torch.from_numpy(q0))
+    ms32, kern32 = timed_run(hdg.HDG_F32)
+    red32 = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
+    out["fp32_plain"] = {"value": nodes * 4 * evals / (ms32 / 1e3), "ms_per_step": ms32 / args.steps,
+                         "speedup_vs_fp64": ms / ms32, "state_finite": bool(red32["finite"]),
+                         "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern32.items()},
+                         "roofline": roofline(kern32, True), "dtype": "f32 residual, f64 state"}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, q0, args.cpu_seconds)

@@ -145,15 +145,21 @@ hdg_status hdg_mesh_geometry(const hdg_mesh_desc *desc, double *xyz, double *J, 
                              double *xi, double *w, double *D);
 
 /* R = dq/dt of the semi-discrete hybrid DGSEM (App. B with the Sec. 2.3
- * coupling), for device state q_dev, into device r_dev (same layout, must not
- * alias q_dev).  prec: HDG_F64 (double in, double out). */
+ * coupling), for device state q_dev (double, [e][4][N^3]) into device r_dev
+ * (same layout, must not alias q_dev).
+ *   HDG_F64: all arithmetic in double, r_dev is double.
+ *   HDG_F32: contractions, fluxes and their accumulation in float, from one
+ *            float rounding of the metric terms, face geometry and derivative
+ *            matrix; r_dev is float. */
 hdg_status hdg_residual(hdg_mesh *mesh, const void *q_dev, void *r_dev, hdg_prec prec, void *stream);
 
 /* nsteps steps of the three-stage low-storage RK (Sec. 2.3; Williamson 2N
  * coefficients A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15)) on the device
  * state q_dev in place.  dq_dev is the caller's second register (same length);
  * its content on entry is ignored, on return it holds the last stage's
- * register.  dt > 0 fixed. */
+ * register.  dt > 0 fixed.  prec selects the residual arithmetic (as in
+ * hdg_residual); the stage accumulation dq = A dq + dt R, q += B dq and both
+ * registers are double in either case. */
 hdg_status hdg_rk3_steps(hdg_mesh *mesh, double *q_dev, double *dq_dev, double dt, int32_t nsteps,
                          hdg_prec prec, void *stream);
 

@@ -65,6 +65,8 @@ struct hdg_mesh {
     // device buffers
     double *metric = nullptr, *fgeo = nullptr, *fvt = nullptr, *wvis = nullptr, *qpp = nullptr, *mass = nullptr;
     double *delta = nullptr, *Dmat = nullptr, *partials = nullptr, *final13 = nullptr;
+    // FP32 copies (one rounding of the FP64 set-up) read by the HDG_F32 kernels
+    float *metric32 = nullptr, *fgeo32 = nullptr, *Dmat32 = nullptr;
     FaceRef *conn = nullptr;
     uint8_t *flag_d = nullptr;
     int32_t *list_visc = nullptr, *list_all = nullptr;
@@ -92,7 +94,8 @@ hdg_status dev_alloc(hdg_mesh *m, T **p, size_t count)
 void free_device(hdg_mesh *m)
 {
     void *ptrs[] = {m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->Dmat, m->partials,
-                    m->final13, m->conn, m->flag_d, m->list_visc, m->list_all};
+                    m->final13, m->conn, m->flag_d, m->list_visc, m->list_all, m->metric32, m->fgeo32,
+                    m->Dmat32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : m->ev) (void)hipEventDestroy(e);
@@ -123,17 +126,17 @@ hdg_status upload_lists(hdg_mesh *m)
     return HDG_OK;
 }
 
-ElemArgs base_args(const hdg_mesh *m)
+ElemArgs base_args(const hdg_mesh *m, bool f32)
 {
     ElemArgs a{};
-    a.metric = m->metric;
-    a.fgeo = m->fgeo;
+    a.metric = f32 ? (const void *)m->metric32 : (const void *)m->metric;
+    a.fgeo = f32 ? (const void *)m->fgeo32 : (const void *)m->fgeo;
     a.conn = m->conn;
     a.flag = m->flag_d;
     a.fvt = m->fvt;
     a.wvis = m->wvis;
     a.delta = m->delta;
-    a.Dmat = m->Dmat;
+    a.Dmat = f32 ? (const void *)m->Dmat32 : (const void *)m->Dmat;
     a.c0sq = m->prm.c0sq;
     a.nu = m->prm.nu;
     a.C_les = m->prm.C_les;
@@ -168,10 +171,10 @@ hdg_status timed(hdg_mesh *m, int kind, hipStream_t s, F launch)
 }
 
 // One residual evaluation (EPI Residual) or one fused RK stage (EPI RkStage).
-hdg_status run_stage(hdg_mesh *m, const double *q, double *out, double *dq, Epi epi, double A, double B,
-                     double dt, bool first, hipStream_t s)
+hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi epi, bool f32, double A,
+                     double B, double dt, bool first, hipStream_t s)
 {
-    ElemArgs a = base_args(m);
+    ElemArgs a = base_args(m, f32);
     a.q = q;
     a.out = out;
     a.dq = dq;
@@ -181,11 +184,11 @@ hdg_status run_stage(hdg_mesh *m, const double *q, double *out, double *dq, Epi 
     a.first_stage = first ? 1 : 0;
     ElemArgs av = a;
     set_list(av, m->list_visc, m->n_visc);
-    hdg_status st = timed(m, HDG_KERNEL_VISCOUS, s, [&] { return hdg::launch_viscous(m->N, av, s); });
+    hdg_status st = timed(m, HDG_KERNEL_VISCOUS, s, [&] { return hdg::launch_viscous(m->N, f32, av, s); });
     if (st != HDG_OK) return st;
     ElemArgs ar = a;
     set_list(ar, m->list_all, (int32_t)m->ne);
-    return timed(m, HDG_KERNEL_RESIDUAL, s, [&] { return hdg::launch_residual(m->N, epi, ar, s); });
+    return timed(m, HDG_KERNEL_RESIDUAL, s, [&] { return hdg::launch_residual(m->N, epi, f32, ar, s); });
 }
 
 // Sizes, pointers, uniform order, symmetric connectivity with mutually inverse
@@ -342,6 +345,9 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(dev_alloc(m, &m->qpp, (size_t)ne * 4 * N3));
     chk(dev_alloc(m, &m->delta, (size_t)ne));
     chk(dev_alloc(m, &m->Dmat, (size_t)N2));
+    chk(dev_alloc(m, &m->metric32, metric.size()));
+    chk(dev_alloc(m, &m->fgeo32, fgeo.size()));
+    chk(dev_alloc(m, &m->Dmat32, (size_t)N2));
     chk(dev_alloc(m, &m->partials, (size_t)m->nblocks_reduce * 13));
     chk(dev_alloc(m, &m->final13, 13));
     chk(dev_alloc(m, &m->conn, conn.size()));
@@ -362,6 +368,13 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(up(m->fgeo, fgeo.data(), fgeo.size() * 8));
     chk(up(m->delta, g.delta.data(), g.delta.size() * 8));
     chk(up(m->Dmat, g.D.data(), g.D.size() * 8));
+    {
+        std::vector<float> m32(metric.begin(), metric.end()), f32(fgeo.begin(), fgeo.end()),
+            d32(g.D.begin(), g.D.end());
+        chk(up(m->metric32, m32.data(), m32.size() * 4));
+        chk(up(m->fgeo32, f32.data(), f32.size() * 4));
+        chk(up(m->Dmat32, d32.data(), d32.size() * 4));
+    }
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
     chk(up(m->list_all, m->order.data(), m->order.size() * sizeof(int32_t)));
     if (s2 == HDG_OK) s2 = upload_lists(m);
@@ -442,9 +455,9 @@ hdg_status hdg_residual(hdg_mesh *m, const void *q, void *r, hdg_prec prec, void
 {
     if (!m || !q || !r) return fail(HDG_EINVAL, "NULL argument");
     if (q == r) return fail(HDG_EINVAL, "residual must not alias the state");
-    if (prec != HDG_F64) return fail(HDG_EUNSUPPORTED, "only HDG_F64 is implemented");
+    if (prec != HDG_F64 && prec != HDG_F32) return fail(HDG_EINVAL, "prec must be HDG_F64 or HDG_F32");
     HDG_HIP(hipSetDevice(m->ctx->device));
-    return run_stage(m, (const double *)q, (double *)r, nullptr, Epi::Residual, 0.0, 0.0, 0.0, false,
+    return run_stage(m, (const double *)q, r, nullptr, Epi::Residual, prec == HDG_F32, 0.0, 0.0, 0.0, false,
                      (hipStream_t)stream);
 }
 
@@ -456,13 +469,13 @@ hdg_status hdg_rk3_steps(hdg_mesh *m, double *q, double *dq, double dt, int32_t 
     if (!m || !q || !dq) return fail(HDG_EINVAL, "NULL argument");
     if (q == dq) return fail(HDG_EINVAL, "dq must not alias q");
     if (!(dt > 0.0) || !std::isfinite(dt) || nsteps < 0) return fail(HDG_EINVAL, "need dt > 0 and nsteps >= 0");
-    if (prec != HDG_F64) return fail(HDG_EUNSUPPORTED, "only HDG_F64 is implemented");
+    if (prec != HDG_F64 && prec != HDG_F32) return fail(HDG_EINVAL, "prec must be HDG_F64 or HDG_F32");
     HDG_HIP(hipSetDevice(m->ctx->device));
     hipStream_t s = (hipStream_t)stream;
     double *cur = q, *nxt = m->qpp;
     for (int32_t step = 0; step < nsteps; ++step)
         for (int st = 0; st < 3; ++st) {
-            hdg_status r = run_stage(m, cur, nxt, dq, Epi::RkStage, A[st], B[st], dt, st == 0, s);
+            hdg_status r = run_stage(m, cur, nxt, dq, Epi::RkStage, prec == HDG_F32, A[st], B[st], dt, st == 0, s);
             if (r != HDG_OK) return r;
             std::swap(cur, nxt);
         }

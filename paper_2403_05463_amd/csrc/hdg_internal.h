@@ -25,19 +25,22 @@ struct FaceRef {
 constexpr int kOwnerBit = 1 << 6;
 
 // Arguments of every element kernel (plain pointers, all device memory).
+// The state, the RK register and the RK stage are always FP64; metric terms,
+// face geometry, derivative matrix, viscous scratch and a residual output
+// are in the kernel's compute type (double, or float for HDG_F32).
 struct ElemArgs {
     const double *q;        // state in, [e][4][N^3]
-    double *out;            // residual, or the next RK state
+    void *out;              // residual [e][4][N^3] (compute type), or the next RK state (double)
     double *dq;             // RK register (fused stage only)
-    const double *metric;   // [e][10][N^3]: 1/J, then Ja^i_d for i = 0..2, d = 0..2
-    const double *fgeo;     // [face][N^2][4]: unit normal (outward for the owner), surface scale s
+    const void *metric;     // [e][10][N^3]: 1/J, then Ja^i_d for i = 0..2, d = 0..2
+    const void *fgeo;       // [face][N^2][4]: unit normal (outward for the owner), surface scale s
     const FaceRef *conn;    // [e][6]
     const uint8_t *flag;    // [e]
-    double *fvt;            // [face][2 sides][3][N^2]: viscous flux . (s n), side 0 = owner
-    double *wvis;           // [e][3][N^3]: viscous part of the reference divergence (flagged elements)
+    void *fvt;              // [face][2 sides][3][N^2]: viscous flux . (s n), side 0 = owner
+    void *wvis;             // [e][3][N^3]: viscous part of the reference divergence (flagged elements)
     const int32_t *list;    // elements handled by this launch
     const double *delta;    // [e] LES filter width
-    const double *Dmat;     // [N][N] derivative matrix, D[i][j] = l_j'(xi_i)
+    const void *Dmat;       // [N][N] derivative matrix, D[i][j] = l_j'(xi_i)
     int32_t count;          // entries in list
     int32_t per_xcd;        // list entries per XCD (grid = kXcd * per_xcd)
     double c0sq, nu, C_les;
@@ -51,8 +54,8 @@ struct ElemArgs {
 enum class Epi : int { Residual = 0, RkStage = 1 };
 
 // Kernel launchers (hdg_kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_viscous(int N, const ElemArgs &a, hipStream_t s);
-hipError_t launch_residual(int N, Epi epi, const ElemArgs &a, hipStream_t s);
+hipError_t launch_viscous(int N, bool f32, const ElemArgs &a, hipStream_t s);
+hipError_t launch_residual(int N, Epi epi, bool f32, const ElemArgs &a, hipStream_t s);
 hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_elem,
                          double *partials, int nblocks, double *final13, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s);

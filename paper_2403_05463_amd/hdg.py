@@ -231,17 +231,19 @@ def hdg_mesh_geometry(mesh, P: int) -> dict:
     return out
 
 
-def _check_state(mesh: Mesh, t, name: str):
+def _check_state(mesh: Mesh, t, name: str, f32: bool = False):
     if isinstance(t, int):
         return
     import torch
-    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != 4 * mesh.n_elem * mesh.N3:
-        raise ValueError(f"{name}: need a contiguous float64 CUDA tensor of {4 * mesh.n_elem * mesh.N3} entries")
+    dt = torch.float32 if f32 else torch.float64
+    if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or t.numel() != 4 * mesh.n_elem * mesh.N3:
+        raise ValueError(f"{name}: need a contiguous {dt} CUDA tensor of {4 * mesh.n_elem * mesh.N3} entries")
 
 
 def hdg_residual(mesh: Mesh, q, r, prec: int = HDG_F64, stream=None):
+    """R = dq/dt; q is always float64, r is float64 (HDG_F64) or float32 (HDG_F32)."""
     _check_state(mesh, q, "q")
-    _check_state(mesh, r, "r")
+    _check_state(mesh, r, "r", f32=(prec == HDG_F32))
     _check(lib().hdg_residual(mesh.handle, _ptr(q), _ptr(r), prec, _stream(stream)), "hdg_residual")
 
 

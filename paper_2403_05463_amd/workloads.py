@@ -525,12 +525,16 @@ def naca_working(ni=96, nj=48, nk=8, P=4) -> Workload:
 
 
 def tgv_box_precision(n=32, P=5) -> Workload:
-    """Periodic 32^3 box, P = 5, Taylor-Green at Re = 1600, Bernoulli(0.5) mask."""
+    """Periodic [0, 2pi]^3 box of 32^3 elements, P = 5 (7,077,888 nodes),
+    decaying Taylor-Green vortex at Re = 1600 (nu = 1/1600), Smagorinsky
+    Cs = 0.1, seeded Bernoulli(0.5) mask.  dt = 2e-4: half the convective
+    limit 0.5 h / ((P+1)^2 lambda) with h = 2 pi / 32 and lambda = |u| +
+    sqrt(|u|^2 + c0^2) ~ 6.1."""
     mesh = periodic_box(n, Pg=1)
     flag = bernoulli_mask(mesh.n_elem, 0.5, seed=1)
     params = dict(c0sq=25.0, nu=1.0 / 1600.0, les_model=1, C_les=0.1, mixed_face=0,
                   q_inf=[0.0, 0.0, 0.0, 0.0])
-    return Workload(f"tgv_box{n}_P{P}", mesh, P, flag, params, None, 1000, "tgv",
+    return Workload(f"tgv_box{n}_P{P}", mesh, P, flag, params, 2e-4, 1000, "tgv",
                     dict(amp=0.0, seed=0))
 
 

@@ -1,0 +1,127 @@
+"""GPU precision form: FP32 residual contractions and fluxes (FP64 state, RK
+accumulation and reductions) against the FP64 CPU oracle, per field.
+
+Target: per-field relative L2 error of the FP32 residual against the FP64
+oracle <= 1e-5 (norms defined in tests/parity.py); the max-norm error is
+reported and bounded by 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2403_05463_amd import hdg, workloads as W
+from parity import TOL_F32, fp32_errors, oracle_mass, pressure_term_scale
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_cuda):
+    return hdg.hdg_init(0)
+
+
+def _f32_residual(torch, m, q):
+    qd = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    r = torch.empty(qd.shape, dtype=torch.float32, device="cuda")
+    hdg.hdg_residual(m, qd, r, prec=hdg.HDG_F32)
+    torch.cuda.synchronize()
+    return r.cpu().numpy().astype(np.float64)
+
+
+def _cases():
+    w = W.tgv_box_small()
+    yield "tgv box 4^3 P=3", w.mesh, w.P, w.flag, w.params, "tgv"
+    m, _ = W.reorient(W.periodic_box(3, Pg=2, curve_amp=0.3), seed=4)
+    yield "curved reoriented box P=4", m, 4, W.bernoulli_mask(m.n_elem, 0.5, 4), \
+        dict(c0sq=25.0, nu=5e-3, les_model=2, C_les=0.07, mixed_face=0, q_inf=(0, 0, 0, 0)), "tgv"
+    g = W.naca_ogrid(48, 16, 4, Pg=2)
+    yield "O-grid 48x16x4 P=4", g, 4, W.naca_mask(g), \
+        dict(c0sq=25.0, nu=1e-4, les_model=1, C_les=0.1, mixed_face=0, q_inf=W.free_stream(20.0)), "inflow"
+
+
+@pytest.mark.parametrize("case", list(range(3)))
+def test_fp32_residual_per_field_error(orc, torch_cuda, ctx, case):
+    name, mesh, P, flag, prm, kind = list(_cases())[case]
+    _say(f"FP32 residual: {name}")
+    om = orc.OracleMesh(mesh, P, flag)
+    if kind == "tgv":
+        q = W.taylor_green_state(om.node_coords(), 0.05, seed=case)
+    else:
+        q = W.uniform_inflow_state(mesh.n_elem, (P + 1) ** 3, 20.0, 1.0, 0.01, seed=case)
+    m = hdg.hdg_mesh_create(ctx, mesh, P, flag, hdg.make_params(**prm))
+    R32 = _f32_residual(torch_cuda, m, q)
+    po = orc.make_params(**prm)
+    ref = om.residual(po, q)
+    e = fp32_errors(R32, ref, oracle_mass(orc, om, P), pressure_term_scale(orc, om, po, q, flag, prm["c0sq"]))
+    _say(f"{name}: per-field L2 {e['l2_f32']}, max {e['max_f32']} (floored norms: L2 {e['l2']}, max {e['max']})")
+    assert e["l2_f32"].max() <= TOL_F32
+    assert e["max_f32"].max() <= 10 * TOL_F32
+    assert e["l2_f32"].max() > 1e-10       # the float path really ran in float
+
+
+def test_fp32_rk_steps_track_fp64_oracle(orc, torch_cuda, ctx):
+    torch = torch_cuda
+    w = W.tgv_box_small()
+    _say("FP32-residual RK, 10 steps on the TGV box")
+    om = orc.OracleMesh(w.mesh, w.P, w.flag)
+    q0 = W.initial_state(w, om.node_coords())
+    m = hdg.hdg_mesh_create(ctx, w.mesh, w.P, w.flag, hdg.make_params(**w.params))
+    q = torch.from_numpy(q0).cuda()
+    dq = torch.empty_like(q)
+    hdg.hdg_rk3_steps(m, q, dq, w.dt, w.nsteps, prec=hdg.HDG_F32)
+    ref = om.rk3(orc.make_params(**w.params), q0, w.dt, w.nsteps)
+    err = np.abs(q.cpu().numpy() - ref).max() / np.abs(ref).max()
+    _say(f"state error after {w.nsteps} steps: {err:.3e}")
+    assert err < 1e-6
+
+
+def test_precision_form_tgv32_P5(orc, torch_cuda, ctx):
+    """32^3 elements, P = 5 (7.08M nodes): FP32 residual error per field against
+    the oracle, one RK step against the oracle, and 100 / 1000 steps against the
+    GPU FP64 path (itself oracle-matched), reported per field."""
+    torch = torch_cuda
+    w = W.tgv_box_precision()
+    _say(f"{w.name}: FP32 vs FP64 oracle and GPU FP64 path")
+    om = orc.OracleMesh(w.mesh, w.P, w.flag)
+    q0 = W.initial_state(w, om.node_coords())
+    prm_o = orc.make_params(**w.params)
+    mass = oracle_mass(orc, om, w.P)
+    m = hdg.hdg_mesh_create(ctx, w.mesh, w.P, w.flag, hdg.make_params(**w.params))
+    R32 = _f32_residual(torch, m, q0)
+    e = fp32_errors(R32, om.residual(prm_o, q0), mass,
+                    pressure_term_scale(orc, om, prm_o, q0, w.flag, w.params["c0sq"]))
+    _say(f"residual: per-field L2 {e['l2_f32']}, max {e['max_f32']} (floored norms: L2 {e['l2']}, max {e['max']})")
+    assert e["l2_f32"].max() <= TOL_F32
+    assert e["max_f32"].max() <= 10 * TOL_F32
+    q = torch.from_numpy(q0).cuda()
+    dq = torch.empty_like(q)
+    hdg.hdg_rk3_steps(m, q, dq, w.dt, 1, prec=hdg.HDG_F32)
+    ref1 = om.rk3(prm_o, q0, w.dt, 1)
+    d1 = q.cpu().numpy() - ref1
+    e1 = np.abs(d1).max(axis=(0, 2)) / np.abs(ref1).max()
+    _say(f"1 step vs oracle: per-field max error / max|q| {e1}")
+    assert e1.max() < 1e-7
+    for steps in (100, 1000):
+        q32 = torch.from_numpy(q0).cuda()
+        q64 = torch.from_numpy(q0).cuda()
+        hdg.hdg_rk3_steps(m, q32, dq, w.dt, steps, prec=hdg.HDG_F32)
+        hdg.hdg_rk3_steps(m, q64, dq, w.dt, steps, prec=hdg.HDG_F64)
+        a, b = q32.cpu().numpy(), q64.cpu().numpy()
+        assert np.all(np.isfinite(b))
+        ek = np.abs(a - b).max(axis=(0, 2)) / np.abs(b).max()
+        _say(f"{steps} steps vs GPU FP64 path: per-field max error / max|q| {ek}")
+        assert ek.max() < 1e-5
