@@ -163,6 +163,13 @@ hdg_status hdg_residual(hdg_mesh *mesh, const void *q_dev, void *r_dev, hdg_prec
 hdg_status hdg_rk3_steps(hdg_mesh *mesh, double *q_dev, double *dq_dev, double dt, int32_t nsteps,
                          hdg_prec prec, void *stream);
 
+/* With graphs enabled (the default) and kernel timing off, hdg_rk3_steps
+ * captures two RK steps (six stages) once per (q, dq, dt, prec) into a HIP
+ * graph on a private stream and replays it on the caller's stream; an odd
+ * last step runs eagerly.  Results are bitwise identical to eager launches.
+ * Re-flagging, new parameters or launch shapes drop the captured graph. */
+hdg_status hdg_mesh_set_graphs(hdg_mesh *mesh, int32_t enable);
+
 /* Per-field reductions of a device array in state layout: mass-weighted sum
  * sum w_a w_b w_c J r (discrete conservation), mass-weighted L2 norm and max
  * |r|.  Host outputs, any may be NULL.  Synchronises the stream.
@@ -176,6 +183,33 @@ hdg_status hdg_reduce(hdg_mesh *mesh, const double *r_dev, double out_sum[4], do
  * of the launches of one kernel class (HDG_KERNEL_*) since enabling. */
 hdg_status hdg_timing_enable(hdg_mesh *mesh, int32_t enable);
 hdg_status hdg_timing_read(hdg_mesh *mesh, int32_t kernel_class, double *total_ms, int64_t *launches);
+
+/* Launch configuration of one kernel class for one precision and one order N
+ * = P + 1.  Work is cut into tiles of same-order, same-class elements, one
+ * tile per workgroup of `block` lanes (128, 256 or 512; an element takes N^3
+ * lanes from P = 3 on rounded to whole 64-lane waves, fewer elements share a
+ * wave below); `persistent` launches only as many workgroups as stay
+ * resident, each walking its XCD's share of the tiles, else one workgroup per
+ * tile.  The configuration changes launch shape only: results are bitwise
+ * identical for every choice. */
+typedef struct {
+    int32_t block;
+    int32_t persistent;
+    double us_per_launch;   /* measured by hdg_mesh_autotune, else 0 */
+} hdg_launch_cfg;
+
+/* Autotuner: for each precision, kernel class and order present, times every
+ * supported (block, persistent) pair on this mesh with reps launches of a
+ * fused RK stage reading q_dev (device state, not modified) and keeps the
+ * fastest.  Allocates a scratch register for the duration of the call and
+ * writes the mesh's internal ping-pong state; synchronises the stream.
+ * Default without tuning: block 512, persistent. */
+hdg_status hdg_mesh_autotune(hdg_mesh *mesh, const double *q_dev, int32_t reps, void *stream);
+hdg_status hdg_mesh_get_launch(const hdg_mesh *mesh, int32_t kernel_class, hdg_prec prec, int32_t N,
+                               hdg_launch_cfg *out);
+/* HDG_EUNSUPPORTED if no kernel exists for (N, block); us_per_launch ignored. */
+hdg_status hdg_mesh_set_launch(hdg_mesh *mesh, int32_t kernel_class, hdg_prec prec, int32_t N,
+                               const hdg_launch_cfg *cfg);
 
 /* Plain device-to-device copy kernel (nbytes a multiple of 16, 16-byte aligned
  * pointers): the HBM bandwidth probe that calibrates traffic counters. */

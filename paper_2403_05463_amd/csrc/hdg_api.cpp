@@ -9,9 +9,11 @@
 
 #include "hdg_internal.h"
 
-using hdg::ElemArgs;
 using hdg::Epi;
 using hdg::FaceRef;
+using hdg::Member;
+using hdg::StageArgs;
+using hdg::Tile;
 
 namespace {
 
@@ -48,8 +50,65 @@ constexpr int kMaxEvents = 65536;
 }  // namespace
 
 struct hdg_ctx {
-    int device;
+    int device = 0;
+    int n_cu = 0;
+    double *D64 = nullptr;     // derivative matrices for N = 2..8, packed at d_offset(N)
+    float *D32 = nullptr;
 };
+
+namespace {
+
+// Tile list of one kernel kind, one order N and one workgroup size, on the device.
+struct TilePlan {
+    int N = 0, B = 0;
+    int32_t ntiles = 0, chunk = 0;
+    Tile *tiles = nullptr;
+    int32_t *elems = nullptr;
+};
+
+// Launch configuration of one (kernel kind, precision, order): workgroup size
+// and grid (persistent: resident workgroups only, or one workgroup per tile).
+struct LaunchCfg {
+    int B = 512;
+    bool persistent = true;
+    double us = 0.0;           // measured mean launch time when tuned, else 0
+};
+
+// Split the elements (visited in `order`) into tiles of equal (N, class), each
+// of at most tile_ept(N, B, kind) elements; tiles are ordered by the position
+// of their first element, so the tile list keeps the spatial order.
+void cut_tiles(const std::vector<int32_t> &order, const std::vector<int> &Ne, const std::vector<int> &cls,
+               int member, int B, int kind, std::vector<Tile> &tiles, std::vector<int32_t> &elems)
+{
+    struct Chunk { size_t pos; int N; std::vector<int32_t> e; };
+    std::vector<Chunk> done;
+    std::vector<Chunk> open(2 * (hdg::kMaxN + 1));
+    std::vector<bool> has(open.size(), false);
+    for (size_t r = 0; r < order.size(); ++r) {
+        const int32_t e = order[r];
+        if (cls[e] < 0) continue;
+        const int key = cls[e] * (hdg::kMaxN + 1) + Ne[e];
+        const int ept = hdg::tile_ept(Ne[e], B, kind);
+        if (!has[key]) {
+            open[key] = Chunk{r, Ne[e], {}};
+            has[key] = true;
+        }
+        open[key].e.push_back(e);
+        if ((int)open[key].e.size() == ept) {
+            done.push_back(std::move(open[key]));
+            has[key] = false;
+        }
+    }
+    for (size_t k = 0; k < open.size(); ++k)
+        if (has[k]) done.push_back(std::move(open[k]));
+    std::sort(done.begin(), done.end(), [](const Chunk &a, const Chunk &b) { return a.pos < b.pos; });
+    for (auto &c : done) {
+        tiles.push_back(Tile{member, c.N, (int32_t)c.e.size(), (int32_t)elems.size()});
+        elems.insert(elems.end(), c.e.begin(), c.e.end());
+    }
+}
+
+}  // namespace
 
 struct hdg_mesh {
     hdg_ctx *ctx = nullptr;
@@ -64,12 +123,17 @@ struct hdg_mesh {
     int32_t n_visc = 0;
     // device buffers
     double *metric = nullptr, *fgeo = nullptr, *fvt = nullptr, *wvis = nullptr, *qpp = nullptr, *mass = nullptr;
-    double *delta = nullptr, *Dmat = nullptr, *partials = nullptr, *final13 = nullptr;
+    double *delta = nullptr, *partials = nullptr, *final13 = nullptr;
     // FP32 copies (one rounding of the FP64 set-up) read by the HDG_F32 kernels
-    float *metric32 = nullptr, *fgeo32 = nullptr, *Dmat32 = nullptr;
+    float *metric32 = nullptr, *fgeo32 = nullptr;
     FaceRef *conn = nullptr;
     uint8_t *flag_d = nullptr;
-    int32_t *list_visc = nullptr, *list_all = nullptr;
+    int64_t *eoff = nullptr, *foff = nullptr;
+    Member *member = nullptr;              // the mesh's member record (device)
+    Member host_member{};
+    // tile plans per kernel kind, for every (order, workgroup size) pair
+    std::vector<TilePlan> plans[2];
+    LaunchCfg cfg[2][2][hdg::kMaxN + 1];   // [kind][precision][N]
     int nblocks_reduce = 0;
     int64_t bytes = 0;
     // timing
@@ -77,6 +141,15 @@ struct hdg_mesh {
     std::vector<hipEvent_t> ev;            // pairs (start, stop)
     std::vector<int> ev_kind;
     size_t ev_used = 0;
+    // RK steps captured as a HIP graph (two steps, so the ping-pong state
+    // ends where it started), replayed on the caller's stream
+    bool graphs = true;
+    hipStream_t cap = nullptr;             // private stream used only for capture
+    hipGraphExec_t gexec = nullptr;
+    const double *g_q = nullptr;
+    const double *g_dq = nullptr;
+    double g_dt = 0.0;
+    int g_prec = -1;
 };
 
 namespace {
@@ -93,13 +166,23 @@ hdg_status dev_alloc(hdg_mesh *m, T **p, size_t count)
 
 void free_device(hdg_mesh *m)
 {
-    void *ptrs[] = {m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->Dmat, m->partials,
-                    m->final13, m->conn, m->flag_d, m->list_visc, m->list_all, m->metric32, m->fgeo32,
-                    m->Dmat32};
+    void *ptrs[] = {m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->partials,
+                    m->final13, m->conn, m->flag_d, m->metric32, m->fgeo32, m->eoff, m->foff, m->member};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto &v : m->plans) {
+        for (auto &pl : v) {
+            if (pl.tiles) (void)hipFree(pl.tiles);
+            if (pl.elems) (void)hipFree(pl.elems);
+        }
+        v.clear();
+    }
     for (hipEvent_t e : m->ev) (void)hipEventDestroy(e);
     m->ev.clear();
+    if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+    if (m->cap) (void)hipStreamDestroy(m->cap);
+    m->gexec = nullptr;
+    m->cap = nullptr;
 }
 
 hdg_status check_params(const hdg_params *p)
@@ -114,44 +197,95 @@ hdg_status check_params(const hdg_params *p)
     return HDG_OK;
 }
 
-// Flagged-element list in the processing order, and the flags.
-hdg_status upload_lists(hdg_mesh *m)
+constexpr int kBlocks[3] = {128, 256, 512};
+
+const TilePlan *find_plan(const hdg_mesh *m, int kind, int N, int B)
 {
-    std::vector<int32_t> v;
-    for (int32_t e : m->order)
-        if (m->flag[e]) v.push_back(e);
-    m->n_visc = (int32_t)v.size();
-    if (!v.empty()) HDG_HIP(hipMemcpy(m->list_visc, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+    for (const auto &pl : m->plans[kind])
+        if (pl.N == N && pl.B == B) return &pl;
+    return nullptr;
+}
+
+// Drop the captured RK graph (its launches bake in plans, shapes and buffers).
+void drop_graph(hdg_mesh *m)
+{
+    if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+    m->gexec = nullptr;
+    m->g_prec = -1;
+}
+
+// Flags and the tile plans of every (order, workgroup size) the mesh uses.
+hdg_status upload_plans(hdg_mesh *m)
+{
+    drop_graph(m);
+    m->n_visc = 0;
+    for (int64_t e = 0; e < m->ne; ++e) m->n_visc += m->flag[e];
     HDG_HIP(hipMemcpy(m->flag_d, m->flag.data(), m->ne, hipMemcpyHostToDevice));
+    std::vector<int> Ne(m->ne, m->N), cls(m->ne);
+    for (auto &v : m->plans) {
+        for (auto &pl : v) {
+            if (pl.tiles) (void)hipFree(pl.tiles);
+            if (pl.elems) (void)hipFree(pl.elems);
+        }
+        v.clear();
+    }
+    for (int kind = 0; kind < 2; ++kind) {
+        for (int64_t e = 0; e < m->ne; ++e) cls[e] = kind == hdg::kTileViscous ? (m->flag[e] ? 0 : -1) : m->flag[e];
+        for (int N = 2; N <= hdg::kMaxN; ++N) {
+            std::vector<int> cn(m->ne);
+            bool any = false;
+            for (int64_t e = 0; e < m->ne; ++e) {
+                cn[e] = Ne[e] == N ? cls[e] : -1;
+                any = any || cn[e] >= 0;
+            }
+            if (!any) continue;
+            for (int B : kBlocks) {
+                if (!hdg::shape_supported(N, B)) continue;
+                std::vector<Tile> tiles;
+                std::vector<int32_t> elems;
+                cut_tiles(m->order, Ne, cn, 0, B, kind, tiles, elems);
+                TilePlan pl;
+                pl.N = N;
+                pl.B = B;
+                pl.ntiles = (int32_t)tiles.size();
+                pl.chunk = (pl.ntiles + hdg::kXcd - 1) / hdg::kXcd;
+                HDG_HIP(hipMalloc((void **)&pl.tiles, tiles.size() * sizeof(Tile)));
+                HDG_HIP(hipMalloc((void **)&pl.elems, elems.size() * sizeof(int32_t)));
+                HDG_HIP(hipMemcpy(pl.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+                HDG_HIP(hipMemcpy(pl.elems, elems.data(), elems.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+                m->plans[kind].push_back(pl);
+            }
+        }
+    }
     return HDG_OK;
 }
 
-ElemArgs base_args(const hdg_mesh *m, bool f32)
+void fill_member_params(Member &mb, const hdg_params &p)
 {
-    ElemArgs a{};
-    a.metric = f32 ? (const void *)m->metric32 : (const void *)m->metric;
-    a.fgeo = f32 ? (const void *)m->fgeo32 : (const void *)m->fgeo;
-    a.conn = m->conn;
-    a.flag = m->flag_d;
-    a.fvt = m->fvt;
-    a.wvis = m->wvis;
-    a.delta = m->delta;
-    a.Dmat = f32 ? (const void *)m->Dmat32 : (const void *)m->Dmat;
-    a.c0sq = m->prm.c0sq;
-    a.nu = m->prm.nu;
-    a.C_les = m->prm.C_les;
-    a.les_model = m->prm.les_model;
-    a.mixed_face = m->prm.mixed_face;
-    for (int k = 0; k < 4; ++k) a.qinf[k] = m->prm.q_inf[k];
-    a.inv_wend = m->inv_wend;
-    return a;
+    mb.c0sq = p.c0sq;
+    mb.nu = p.nu;
+    mb.C_les = p.C_les;
+    mb.les_model = p.les_model;
+    mb.mixed_face = p.mixed_face;
+    for (int k = 0; k < 4; ++k) mb.qinf[k] = p.q_inf[k];
 }
 
-void set_list(ElemArgs &a, const int32_t *list, int32_t count)
+hdg_status upload_member(hdg_mesh *m)
 {
-    a.list = list;
-    a.count = count;
-    a.per_xcd = (count + hdg::kXcd - 1) / hdg::kXcd;
+    fill_member_params(m->host_member, m->prm);
+    HDG_HIP(hipMemcpy(m->member, &m->host_member, sizeof(Member), hipMemcpyHostToDevice));
+    return HDG_OK;
+}
+
+int grid_for(const hdg_mesh *m, const TilePlan &pl, int kind, Epi epi, bool f32, bool persistent)
+{
+    int64_t g = pl.ntiles;
+    if (persistent) {
+        const int per_cu = hdg::resident_blocks_per_cu(kind, pl.N, pl.B, epi, f32);
+        g = std::min<int64_t>(g, (int64_t)per_cu * m->ctx->n_cu);
+    }
+    g = (g + hdg::kXcd - 1) / hdg::kXcd * hdg::kXcd;
+    return (int)std::max<int64_t>(g, hdg::kXcd);
 }
 
 // Launch with optional event bracketing for the kernel timer.
@@ -160,6 +294,7 @@ hdg_status timed(hdg_mesh *m, int kind, hipStream_t s, F launch)
 {
     const bool rec = m->timing && m->ev_used + 2 <= m->ev.size();
     if (rec) HDG_HIP(hipEventRecord(m->ev[m->ev_used], s));
+    (void)hipGetLastError();   // the launch check below must see this launch's status only
     hipError_t e = launch();
     if (e != hipSuccess) return fail(HDG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     if (rec) {
@@ -170,25 +305,58 @@ hdg_status timed(hdg_mesh *m, int kind, hipStream_t s, F launch)
     return HDG_OK;
 }
 
-// One residual evaluation (EPI Residual) or one fused RK stage (EPI RkStage).
+StageArgs stage_args(const hdg_mesh *m, const TilePlan &pl)
+{
+    StageArgs a{};
+    a.mem = m->member;
+    a.tiles = pl.tiles;
+    a.elems = pl.elems;
+    a.ntiles = pl.ntiles;
+    a.chunk = pl.chunk;
+    a.D64 = m->ctx->D64;
+    a.D32 = m->ctx->D32;
+    return a;
+}
+
+// One launch of kernel `kind` over the order-N tiles with configuration cf.
+hdg_status launch_one(hdg_mesh *m, int kind, int N, const LaunchCfg &cf, const double *q, void *out, double *dq,
+                      Epi epi, bool f32, double A, double B, double dt, bool first, hipStream_t s, bool time_it)
+{
+    const TilePlan *pl = find_plan(m, kind, N, cf.B);
+    if (!pl) return HDG_OK;
+    StageArgs a = stage_args(m, *pl);
+    a.q_in = q;
+    a.q_out = epi == Epi::RkStage ? (double *)out : nullptr;
+    a.r = epi == Epi::Residual ? out : nullptr;
+    a.dq = dq;
+    a.dt = dt;
+    a.rkA = A;
+    a.rkB = B;
+    a.first_stage = first ? 1 : 0;
+    const int grid = grid_for(m, *pl, kind, epi, f32, cf.persistent);
+    auto go = [&] {
+        return kind == hdg::kTileViscous ? hdg::launch_viscous(N, pl->B, f32, a, grid, s)
+                                         : hdg::launch_residual(N, pl->B, epi, f32, a, grid, s);
+    };
+    if (time_it) return timed(m, kind == hdg::kTileViscous ? HDG_KERNEL_VISCOUS : HDG_KERNEL_RESIDUAL, s, go);
+    (void)hipGetLastError();
+    hipError_t e = go();
+    if (e != hipSuccess) return fail(HDG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return HDG_OK;
+}
+
+// One residual evaluation (EPI Residual) or one fused RK stage (EPI RkStage):
+// the viscous kernels of every order present, then the residual kernels.
 hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi epi, bool f32, double A,
                      double B, double dt, bool first, hipStream_t s)
 {
-    ElemArgs a = base_args(m, f32);
-    a.q = q;
-    a.out = out;
-    a.dq = dq;
-    a.rkA = A;
-    a.rkB = B;
-    a.dt = dt;
-    a.first_stage = first ? 1 : 0;
-    ElemArgs av = a;
-    set_list(av, m->list_visc, m->n_visc);
-    hdg_status st = timed(m, HDG_KERNEL_VISCOUS, s, [&] { return hdg::launch_viscous(m->N, f32, av, s); });
-    if (st != HDG_OK) return st;
-    ElemArgs ar = a;
-    set_list(ar, m->list_all, (int32_t)m->ne);
-    return timed(m, HDG_KERNEL_RESIDUAL, s, [&] { return hdg::launch_residual(m->N, epi, f32, ar, s); });
+    const int pi = f32 ? 1 : 0;
+    for (int kind = 0; kind < 2; ++kind)
+        for (int N = 2; N <= hdg::kMaxN; ++N) {
+            hdg_status st = launch_one(m, kind, N, m->cfg[kind][pi][N], q, out, dq, epi, f32, A, B, dt, first, s, true);
+            if (st != HDG_OK) return st;
+        }
+    return HDG_OK;
 }
 
 // Sizes, pointers, uniform order, symmetric connectivity with mutually inverse
@@ -244,11 +412,42 @@ hdg_status hdg_init(hdg_ctx **ctx, int32_t device)
     HDG_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(HDG_EINVAL, "no such device " + std::to_string(device));
     HDG_HIP(hipSetDevice(device));
-    *ctx = new hdg_ctx{device};
+    hipDeviceProp_t prop;
+    HDG_HIP(hipGetDeviceProperties(&prop, device));
+    auto *c = new hdg_ctx();
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    // derivative matrices of every supported order, FP64 and one FP32 rounding
+    std::vector<double> d64(hdg::kDTableSize);
+    for (int N = 2; N <= hdg::kMaxN; ++N) {
+        std::vector<double> xi, w, D;
+        hdg::gll_rule(N - 1, xi, w, D);
+        std::copy(D.begin(), D.end(), d64.begin() + hdg::d_offset(N));
+    }
+    std::vector<float> d32(d64.begin(), d64.end());
+    hipError_t e1 = hipMalloc((void **)&c->D64, d64.size() * 8);
+    hipError_t e2 = hipMalloc((void **)&c->D32, d32.size() * 4);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (c->D64) (void)hipFree(c->D64);
+        if (c->D32) (void)hipFree(c->D32);
+        delete c;
+        return fail(HDG_ENOMEM, "hipMalloc of the derivative tables failed");
+    }
+    HDG_HIP(hipMemcpy(c->D64, d64.data(), d64.size() * 8, hipMemcpyHostToDevice));
+    HDG_HIP(hipMemcpy(c->D32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice));
+    *ctx = c;
     return HDG_OK;
 }
 
-void hdg_finalize(hdg_ctx *ctx) { delete ctx; }
+void hdg_finalize(hdg_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->D64) (void)hipFree(ctx->D64);
+    if (ctx->D32) (void)hipFree(ctx->D32);
+    delete ctx;
+}
 
 hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_params *params, hdg_mesh **out)
 {
@@ -344,16 +543,15 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(dev_alloc(m, &m->wvis, (size_t)ne * 3 * N3));
     chk(dev_alloc(m, &m->qpp, (size_t)ne * 4 * N3));
     chk(dev_alloc(m, &m->delta, (size_t)ne));
-    chk(dev_alloc(m, &m->Dmat, (size_t)N2));
     chk(dev_alloc(m, &m->metric32, metric.size()));
     chk(dev_alloc(m, &m->fgeo32, fgeo.size()));
-    chk(dev_alloc(m, &m->Dmat32, (size_t)N2));
     chk(dev_alloc(m, &m->partials, (size_t)m->nblocks_reduce * 13));
     chk(dev_alloc(m, &m->final13, 13));
     chk(dev_alloc(m, &m->conn, conn.size()));
     chk(dev_alloc(m, &m->flag_d, (size_t)ne));
-    chk(dev_alloc(m, &m->list_visc, (size_t)ne));
-    chk(dev_alloc(m, &m->list_all, (size_t)ne));
+    chk(dev_alloc(m, &m->eoff, (size_t)ne));
+    chk(dev_alloc(m, &m->foff, (size_t)nf));
+    chk(dev_alloc(m, &m->member, 1));
     if (s2 != HDG_OK) {
         free_device(m);
         delete m;
@@ -367,17 +565,38 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(up(m->mass, mass.data(), mass.size() * 8));
     chk(up(m->fgeo, fgeo.data(), fgeo.size() * 8));
     chk(up(m->delta, g.delta.data(), g.delta.size() * 8));
-    chk(up(m->Dmat, g.D.data(), g.D.size() * 8));
     {
-        std::vector<float> m32(metric.begin(), metric.end()), f32(fgeo.begin(), fgeo.end()),
-            d32(g.D.begin(), g.D.end());
+        std::vector<float> m32(metric.begin(), metric.end()), f32(fgeo.begin(), fgeo.end());
         chk(up(m->metric32, m32.data(), m32.size() * 4));
         chk(up(m->fgeo32, f32.data(), f32.size() * 4));
-        chk(up(m->Dmat32, d32.data(), d32.size() * 4));
     }
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
-    chk(up(m->list_all, m->order.data(), m->order.size() * sizeof(int32_t)));
-    if (s2 == HDG_OK) s2 = upload_lists(m);
+    {
+        std::vector<int64_t> eo(ne), fo(nf);
+        for (int64_t e = 0; e < ne; ++e) eo[e] = e * N3;
+        for (int64_t f = 0; f < nf; ++f) fo[f] = f * N2;
+        chk(up(m->eoff, eo.data(), eo.size() * 8));
+        chk(up(m->foff, fo.data(), fo.size() * 8));
+    }
+    {
+        Member &mb = m->host_member;
+        mb = Member{};
+        mb.qA = nullptr;
+        mb.qB = m->qpp;
+        mb.metric[0] = m->metric;
+        mb.metric[1] = m->metric32;
+        mb.fgeo[0] = m->fgeo;
+        mb.fgeo[1] = m->fgeo32;
+        mb.fvt = m->fvt;
+        mb.wvis = m->wvis;
+        mb.conn = m->conn;
+        mb.flag = m->flag_d;
+        mb.delta = m->delta;
+        mb.eoff = m->eoff;
+        mb.foff = m->foff;
+    }
+    if (s2 == HDG_OK) s2 = upload_member(m);
+    if (s2 == HDG_OK) s2 = upload_plans(m);
     if (s2 != HDG_OK) {
         free_device(m);
         delete m;
@@ -402,7 +621,7 @@ hdg_status hdg_mesh_set_flags(hdg_mesh *m, const uint8_t *flag_host)
     HDG_HIP(hipSetDevice(m->ctx->device));
     HDG_HIP(hipDeviceSynchronize());
     for (int64_t e = 0; e < m->ne; ++e) m->flag[e] = flag_host[e] ? 1 : 0;
-    return upload_lists(m);
+    return upload_plans(m);
 }
 
 hdg_status hdg_mesh_set_params(hdg_mesh *m, const hdg_params *params)
@@ -410,8 +629,11 @@ hdg_status hdg_mesh_set_params(hdg_mesh *m, const hdg_params *params)
     if (!m) return fail(HDG_EINVAL, "NULL mesh");
     hdg_status st = check_params(params);
     if (st != HDG_OK) return st;
+    HDG_HIP(hipSetDevice(m->ctx->device));
+    HDG_HIP(hipDeviceSynchronize());        // launches in flight read the member record
     m->prm = *params;
-    return HDG_OK;
+    drop_graph(m);
+    return upload_member(m);
 }
 
 hdg_status hdg_mesh_info(const hdg_mesh *m, int64_t *n_nodes, int64_t *state_len, int64_t *device_bytes,
@@ -472,14 +694,69 @@ hdg_status hdg_rk3_steps(hdg_mesh *m, double *q, double *dq, double dt, int32_t 
     if (prec != HDG_F64 && prec != HDG_F32) return fail(HDG_EINVAL, "prec must be HDG_F64 or HDG_F32");
     HDG_HIP(hipSetDevice(m->ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    double *cur = q, *nxt = m->qpp;
-    for (int32_t step = 0; step < nsteps; ++step)
+    const bool f32 = prec == HDG_F32;
+    auto one_step = [&](double *&cur, double *&nxt, hipStream_t st_) -> hdg_status {
         for (int st = 0; st < 3; ++st) {
-            hdg_status r = run_stage(m, cur, nxt, dq, Epi::RkStage, prec == HDG_F32, A[st], B[st], dt, st == 0, s);
+            hdg_status r = run_stage(m, cur, nxt, dq, Epi::RkStage, f32, A[st], B[st], dt, st == 0, st_);
             if (r != HDG_OK) return r;
             std::swap(cur, nxt);
         }
+        return HDG_OK;
+    };
+    int32_t eager = nsteps;
+    if (m->graphs && !m->timing && nsteps >= 2) {
+        // two RK steps (six stages) per replay: q -> qpp -> q ... ends in q
+        if (!m->gexec || m->g_q != q || m->g_dq != dq || m->g_dt != dt || m->g_prec != (int)prec) {
+            drop_graph(m);
+            if (!m->cap) HDG_HIP(hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking));
+            // occupancy queries happen before capture, not inside it
+            for (int kind = 0; kind < 2; ++kind)
+                for (int N = 2; N <= hdg::kMaxN; ++N) {
+                    const LaunchCfg &cf = m->cfg[kind][f32][N];
+                    if (const TilePlan *pl = find_plan(m, kind, N, cf.B))
+                        (void)grid_for(m, *pl, kind, Epi::RkStage, f32, cf.persistent);
+                }
+            (void)hipGetLastError();
+            HDG_HIP(hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal));
+            double *cur = q, *nxt = m->qpp;
+            hdg_status r = one_step(cur, nxt, m->cap);
+            if (r == HDG_OK) r = one_step(cur, nxt, m->cap);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(m->cap, &g);
+            if (r != HDG_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return r;
+            }
+            if (e != hipSuccess) return fail(HDG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&m->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                m->gexec = nullptr;
+                return fail(HDG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            m->g_q = q;
+            m->g_dq = dq;
+            m->g_dt = dt;
+            m->g_prec = (int)prec;
+        }
+        for (int32_t k = 0; k < nsteps / 2; ++k) HDG_HIP(hipGraphLaunch(m->gexec, s));
+        eager = nsteps % 2;
+    }
+    double *cur = q, *nxt = m->qpp;
+    for (int32_t step = 0; step < eager; ++step) {
+        hdg_status r = one_step(cur, nxt, s);
+        if (r != HDG_OK) return r;
+    }
     if (cur != q) HDG_HIP(hipMemcpyAsync(q, cur, (size_t)m->ne * 4 * m->N3 * 8, hipMemcpyDeviceToDevice, s));
+    return HDG_OK;
+}
+
+hdg_status hdg_mesh_set_graphs(hdg_mesh *m, int32_t enable)
+{
+    if (!m) return fail(HDG_EINVAL, "NULL mesh");
+    HDG_HIP(hipSetDevice(m->ctx->device));
+    drop_graph(m);
+    m->graphs = enable != 0;
     return HDG_OK;
 }
 
@@ -533,6 +810,89 @@ hdg_status hdg_timing_read(hdg_mesh *m, int32_t kind, double *total_ms, int64_t 
     }
     if (total_ms) *total_ms = tot;
     if (launches) *launches = cnt;
+    return HDG_OK;
+}
+
+hdg_status hdg_mesh_autotune(hdg_mesh *m, const double *q, int32_t reps, void *stream)
+{
+    if (!m || !q || reps < 1) return fail(HDG_EINVAL, "autotune: need a mesh, a state and reps >= 1");
+    HDG_HIP(hipSetDevice(m->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nq = (size_t)m->ne * 4 * m->N3;
+    double *dq = nullptr;
+    HDG_HIP(hipMalloc((void **)&dq, nq * sizeof(double)));
+    hipEvent_t e0, e1;
+    hdg_status st = HDG_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(HDG_EHIP, "hipEventCreate");
+    if (st == HDG_OK && hipMemsetAsync(dq, 0, nq * sizeof(double), s) != hipSuccess) st = fail(HDG_EHIP, "hipMemsetAsync");
+    const bool was_timing = m->timing;
+    m->timing = false;
+    drop_graph(m);
+    // an RK stage as the RK driver runs it; the next state goes to the
+    // internal ping-pong buffer, which a later step overwrites
+    for (int pi = 0; pi < 2 && st == HDG_OK; ++pi)
+        for (int kind = 0; kind < 2 && st == HDG_OK; ++kind)
+            for (int N = 2; N <= hdg::kMaxN && st == HDG_OK; ++N) {
+                LaunchCfg best;
+                best.us = -1.0;
+                for (int B : kBlocks) {
+                    if (!find_plan(m, kind, N, B)) continue;
+                    for (int pers = 1; pers >= 0 && st == HDG_OK; --pers) {
+                        LaunchCfg cf;
+                        cf.B = B;
+                        cf.persistent = pers != 0;
+                        auto once = [&] {
+                            return launch_one(m, kind, N, cf, q, m->qpp, dq, Epi::RkStage, pi == 1, -0.5, 0.5, 1e-9,
+                                              false, s, false);
+                        };
+                        st = once();
+                        if (st != HDG_OK) break;
+                        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(HDG_EHIP, "hipEventRecord"); break; }
+                        for (int r = 0; r < reps && st == HDG_OK; ++r) st = once();
+                        if (st != HDG_OK) break;
+                        float ms = 0.0f;
+                        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                            st = fail(HDG_EHIP, "autotune event timing");
+                            break;
+                        }
+                        cf.us = 1e3 * ms / reps;
+                        if (best.us < 0.0 || cf.us < best.us) best = cf;
+                    }
+                }
+                if (st == HDG_OK && best.us >= 0.0) m->cfg[kind][pi][N] = best;
+            }
+    m->timing = was_timing;
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(dq);
+    return st;
+}
+
+hdg_status hdg_mesh_get_launch(const hdg_mesh *m, int32_t kernel_class, hdg_prec prec, int32_t N, hdg_launch_cfg *out)
+{
+    if (!m || !out || kernel_class < 0 || kernel_class >= HDG_KERNEL_COUNT || (prec != HDG_F64 && prec != HDG_F32) ||
+        N < 2 || N > hdg::kMaxN)
+        return fail(HDG_EINVAL, "get_launch: bad argument");
+    const LaunchCfg &c = m->cfg[kernel_class][prec == HDG_F32][N];
+    out->block = c.B;
+    out->persistent = c.persistent ? 1 : 0;
+    out->us_per_launch = c.us;
+    return HDG_OK;
+}
+
+hdg_status hdg_mesh_set_launch(hdg_mesh *m, int32_t kernel_class, hdg_prec prec, int32_t N, const hdg_launch_cfg *cfg)
+{
+    if (!m || !cfg || kernel_class < 0 || kernel_class >= HDG_KERNEL_COUNT || (prec != HDG_F64 && prec != HDG_F32) ||
+        N < 2 || N > hdg::kMaxN)
+        return fail(HDG_EINVAL, "set_launch: bad argument");
+    if (!hdg::shape_supported(N, cfg->block)) return fail(HDG_EUNSUPPORTED, "set_launch: no kernel for this order and block");
+    drop_graph(m);
+    LaunchCfg &c = m->cfg[kernel_class][prec == HDG_F32][N];
+    c.B = cfg->block;
+    c.persistent = cfg->persistent != 0;
+    c.us = 0.0;
     return HDG_OK;
 }
 

@@ -24,38 +24,101 @@ struct FaceRef {
 
 constexpr int kOwnerBit = 1 << 6;
 
-// Arguments of every element kernel (plain pointers, all device memory).
-// The state, the RK register and the RK stage are always FP64; metric terms,
-// face geometry, derivative matrix, viscous scratch and a residual output
-// are in the kernel's compute type (double, or float for HDG_F32).
-struct ElemArgs {
-    const double *q;        // state in, [e][4][N^3]
-    void *out;              // residual [e][4][N^3] (compute type), or the next RK state (double)
-    double *dq;             // RK register (fused stage only)
-    const void *metric;     // [e][10][N^3]: 1/J, then Ja^i_d for i = 0..2, d = 0..2
-    const void *fgeo;       // [face][N^2][4]: unit normal (outward for the owner), surface scale s
+// Work is cut into tiles: up to tile_ept() elements of one polynomial order
+// and one equation class, all from one member mesh, processed together by one
+// workgroup of B lanes (element s of the tile owns lanes [s N^3, (s+1) N^3)).
+struct Tile {
+    int32_t member;         // index into the member table
+    int32_t N;              // nodes per direction
+    int32_t count;          // elements in this tile (1 .. tile_ept)
+    int32_t first;          // first entry in the element array
+};
+
+enum TileKind : int { kTileViscous = 0, kTileResidual = 1 };
+
+// LDS budget of one workgroup of B lanes (eight 128-lane, four 256-lane or
+// two 512-lane workgroups share a 160 KB CU).
+constexpr int tile_lds_budget(int B) { return B <= 128 ? 20 * 1024 : B <= 256 ? 40 * 1024 : 78 * 1024; }
+
+// Lanes per element: N^3 packed for N <= 3 (several elements share a wave),
+// whole 64-lane waves from N = 4 on, so that the element is uniform per wave.
+constexpr int tile_lanes(int N)
+{
+    const int n3 = N * N * N;
+    return n3 < 64 ? n3 : (n3 + 63) / 64 * 64;
+}
+
+// Elements per tile for order N, workgroup size B and kernel kind, sized for
+// FP64 LDS (the same tiles serve both precisions); 0 if an element needs more
+// than B lanes.
+constexpr int tile_ept(int N, int B, int kind)
+{
+    const int n3 = N * N * N, n2 = N * N;
+    const int per = (12 * n3 + (kind == kTileViscous ? 18 : 24) * n2) * 8;
+    const int by_lanes = B / tile_lanes(N);
+    const int by_lds = (tile_lds_budget(B) - n2 * 8) / per;
+    return by_lanes < by_lds ? by_lanes : by_lds;
+}
+
+// Per-mesh data of the element kernels (device resident, one record per
+// member mesh of a launch).  Element e's state starts at 4 eoff[e], its
+// metric terms at 10 eoff[e], its viscous part at 3 eoff[e]; face f's
+// geometry at 4 foff[f] and viscous traces at 6 foff[f].  Metric terms, face
+// geometry and viscous scratch exist in FP64 and FP32; the kernel reads the
+// copy of its compute type.
+struct Member {
+    double *qA, *qB;        // RK ping-pong states (qA is the caller's)
+    double *dq;             // RK register
+    const void *metric[2];  // [e][10][N^3]: 1/J, then Ja^i_d; [0] FP64, [1] FP32
+    const void *fgeo[2];    // [face][N^2][4]: owner's unit outward normal, surface scale
+    void *fvt;              // [face][2 sides][3][N^2]: viscous flux . (s n), side 0 = owner
+    void *wvis;             // [e][3][N^3]: viscous part of the reference divergence
     const FaceRef *conn;    // [e][6]
     const uint8_t *flag;    // [e]
-    void *fvt;              // [face][2 sides][3][N^2]: viscous flux . (s n), side 0 = owner
-    void *wvis;             // [e][3][N^3]: viscous part of the reference divergence (flagged elements)
-    const int32_t *list;    // elements handled by this launch
     const double *delta;    // [e] LES filter width
-    const void *Dmat;       // [N][N] derivative matrix, D[i][j] = l_j'(xi_i)
-    int32_t count;          // entries in list
-    int32_t per_xcd;        // list entries per XCD (grid = kXcd * per_xcd)
-    double c0sq, nu, C_les;
-    int32_t les_model, mixed_face;
+    const int64_t *eoff;    // [e] first node of the element
+    const int64_t *foff;    // [face] first face node of the face
+    double c0sq, nu, C_les, dt;
     double qinf[4];
-    double inv_wend;        // 1 / w_0 (end-point quadrature weight)
-    double rkA, rkB, dt;    // fused RK stage: dq = A dq + dt R; q_next = q + B dq
-    int32_t first_stage;    // A = 0: dq is not read
+    int32_t les_model, mixed_face;
 };
+
+// Arguments of one persistent launch over a tile list.  With q_in set, the
+// launch has a single member and reads/writes the given buffers (and dt);
+// otherwise each member's ping-pong pair is selected by `parity`.
+struct StageArgs {
+    const Member *mem;
+    const Tile *tiles;
+    const int32_t *elems;   // member-local element ids, grouped by tile
+    int32_t ntiles;
+    int32_t chunk;          // tiles per XCD chunk; the grid is a multiple of kXcd
+    const double *D64;      // derivative matrices for N = 2..8, packed at d_offset(N)
+    const float *D32;
+    const double *q_in;     // single-member mode
+    double *q_out;
+    double *dq;
+    void *r;                // residual output (compute type)
+    double dt;
+    double rkA, rkB;        // fused RK stage: dq = A dq + dt R; q_next = q + B dq
+    int32_t first_stage;    // A = 0: dq is not read
+    int32_t parity;         // member mode: stage input is qB if set, else qA
+};
+
+// Offset of the N x N derivative matrix in the packed table (N = 2..8).
+constexpr int d_offset(int N) { return (N - 1) * N * (2 * N - 1) / 6 - 1; }
+constexpr int kDTableSize = d_offset(kMaxN + 1);
 
 enum class Epi : int { Residual = 0, RkStage = 1 };
 
-// Kernel launchers (hdg_kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_viscous(int N, bool f32, const ElemArgs &a, hipStream_t s);
-hipError_t launch_residual(int N, Epi epi, bool f32, const ElemArgs &a, hipStream_t s);
+// Kernel launchers (hdg_kernels.hip): one persistent kernel per (kind, order
+// N, workgroup size B), over a tile list of order-N tiles; grid of `grid`
+// workgroups (a multiple of kXcd).  Return hipSuccess or the launch error.
+hipError_t launch_viscous(int N, int B, bool f32, const StageArgs &a, int grid, hipStream_t s);
+hipError_t launch_residual(int N, int B, Epi epi, bool f32, const StageArgs &a, int grid, hipStream_t s);
+// Resident workgroups per CU of a kernel configuration (occupancy query).
+int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32);
+// Whether kernels are instantiated for order N with workgroup size B.
+bool shape_supported(int N, int B);
 hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_elem,
                          double *partials, int nblocks, double *final13, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s);

@@ -1,7 +1,11 @@
 // gfx950 kernels of the hybrid Navier-Stokes-LES / Euler DGSEM residual.
 //
-// One workgroup per element, one lane per collocation node (N^3 nodes rounded
-// up to whole 64-lane waves).  Work is split by equation flag (Sec. 2.3):
+// Work comes as a list of tiles.  A tile holds up to tile_ept() elements of
+// one order N and one equation class from one member mesh; one workgroup of B
+// lanes takes it, one lane per collocation node (element s of the tile owns
+// lanes [s N^3, (s+1) N^3)).  Each launch is persistent: a fixed grid walks
+// the whole tile list, every order and every member mesh of the batch, in one
+// dispatch.  Work is split by equation flag (Sec. 2.3):
 //
 //  k_viscous   (flagged elements only) lifts the velocity gradient (BR1:
 //              volume derivative of Ja^i u plus a face correction towards the
@@ -22,10 +26,13 @@
 // surface terms are formed from the trace jumps, so rounding errors scale
 // with variations of the solution, not with its size; this is what keeps the
 // FP32 instantiation accurate.
+//
 // This is the strong (summation-by-parts) equivalent of the weak form in
 // App. B: on Gauss-Lobatto nodes the two agree to round-off.  Euler elements
 // run no gradient, LES or viscous-flux arithmetic at all.
 #include "hdg_internal.h"
+
+#include <type_traits>
 
 namespace hdg {
 namespace {
@@ -34,16 +41,7 @@ template <int N>
 struct Shape {
     static constexpr int N2 = N * N;
     static constexpr int N3 = N * N * N;
-    static constexpr int NT = ((N3 + 63) / 64) * 64;
 };
-
-// Workgroups are dealt to the XCDs round-robin; give every XCD a contiguous
-// run of the (spatially ordered) element list so neighbour traces hit its L2.
-__device__ __forceinline__ int xcd_slot(int per_xcd)
-{
-    const int b = blockIdx.x;
-    return (b % kXcd) * per_xcd + b / kXcd;
-}
 
 template <int N>
 __device__ __forceinline__ int face_node(int f, int a, int b)
@@ -98,29 +96,55 @@ __device__ __forceinline__ T les_nut(int model, T C, T delta, const T (&G)[3][3]
     return T(0);
 }
 
-// Per-launch constants converted to the compute type.
+// Pointers read from the member table are generic pointers to the compiler;
+// casting them through the global address space lets it emit global (not
+// flat) memory instructions with scalar bases.
 template <class T>
-struct Consts {
-    T c0sq, nu, C_les, inv_wend, qinf[4];
-    __device__ explicit Consts(const ElemArgs &A)
-        : c0sq((T)A.c0sq), nu((T)A.nu), C_les((T)A.C_les), inv_wend((T)A.inv_wend),
-          qinf{(T)A.qinf[0], (T)A.qinf[1], (T)A.qinf[2], (T)A.qinf[3]} {}
-};
+using gmem = __attribute__((address_space(1))) T;
 
+template <class P>
+__device__ __forceinline__ gmem<P> *gp(P *p)
+{
+    return (gmem<P> *)p;
+}
+
+__device__ __forceinline__ FaceRef load_face(const FaceRef *conn, size_t i)
+{
+    const gmem<const int32_t> *p = gp((const int32_t *)conn) + 4 * i;
+    FaceRef r;
+    r.face = p[0];
+    r.nbr = p[1];
+    r.code = p[2];
+    r.pad = 0;
+    return r;
+}
+
+template <class T> __device__ __forceinline__ const T *dtable(const StageArgs &A);
+template <> __device__ __forceinline__ const double *dtable<double>(const StageArgs &A) { return A.D64; }
+template <> __device__ __forceinline__ const float *dtable<float>(const StageArgs &A) { return A.D32; }
+template <class T> constexpr int prec_index() { return sizeof(T) == 4 ? 1 : 0; }
+
+// One lane's view of its element and node within a tile.
 template <int N, class T>
-struct ElemCtx {
-    int e, tid, t, i, j, k;
-    bool act;
-    double qd[4];   // own state, FP64 (the RK stage accumulates in FP64)
-    T q[4];         // own state in the compute type
-    T qr[4];        // the element's reference state (its centre node) ...
-    T qt[4];        // ... and this node's deviation from it, formed in FP64
+struct TileCtx {
+    int tid, s, t, i, j, k;
+    int g;            // s N^3 + t: node index in the tile's LDS arrays
+    bool act;         // the lane holds a node of a real element
+    int e;            // member-local element id
+    int64_t eo;       // first node of the element
+    double qd[4];     // own state, FP64 (the RK stage accumulates in FP64)
+    T q[4];           // own state in the compute type
+    T qr[4];          // the element's reference state (its centre node) ...
+    T qt[4];          // ... and this node's deviation from it, formed in FP64
     T invJ;
     T Ja[3][3];
+    T c0sq, nu, C_les, inv_wend;
+    const gmem<double> *qin;
 };
 
-// Common prologue: element id, own state and metric terms, derivative matrix in LDS.
-// Returns false for workgroups past the end of the list (uniform per block).
+// Common prologue: element and node of this lane, own state and metric terms,
+// derivative matrix in LDS.  Lanes past an element's nodes or the tile's
+// elements take the last node of an element of the tile (reads only).
 //
 // Volume derivatives act on deviations from a per-element reference state
 // q_r: the flux of a constant state has zero discrete divergence (the curl-form
@@ -128,22 +152,28 @@ struct ElemCtx {
 // changes nothing in exact arithmetic, while the rounding error of the
 // contraction scales with the deviation instead of the state.  The deviation
 // is formed in FP64 before conversion to the compute type.
-template <int N, class T>
-__device__ __forceinline__ bool load_element(const ElemArgs &A, T *sD, ElemCtx<N, T> &c)
+template <int N, int EPT, class T>
+__device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, const Tile &tl, T *sD,
+                                          TileCtx<N, T> &c)
 {
-    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
-    const int slot = xcd_slot(A.per_xcd);
-    if (slot >= A.count) return false;
-    c.e = A.list[slot];
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3, NL = tile_lanes(N);
     c.tid = threadIdx.x;
-    c.act = c.tid < N3;
-    c.t = c.act ? c.tid : N3 - 1;
+    const int raw = c.tid / NL, within = c.tid - raw * NL;
+    c.act = raw < tl.count && within < N3;
+    c.s = raw < tl.count ? raw : tl.count - 1;
+    // from N = 4 on an element spans whole waves: its slot is wave-uniform
+    if constexpr (NL % 64 == 0) c.s = __builtin_amdgcn_readfirstlane(c.s);
+    c.t = c.act ? within : N3 - 1;
+    c.g = c.s * N3 + c.t;
     c.i = c.t % N;
     c.j = (c.t / N) % N;
     c.k = c.t / N2;
-    const T *Dm = (const T *)A.Dmat;
+    c.e = A.elems[tl.first + c.s];
+    c.eo = gp(M.eoff)[c.e];
+    const T *Dm = dtable<T>(A) + d_offset(N);
     for (int x = c.tid; x < N2; x += blockDim.x) sD[x] = Dm[x];
-    const double *qe = A.q + (size_t)c.e * 4 * N3;
+    c.qin = gp((const double *)(A.q_in ? A.q_in : (A.parity ? M.qB : M.qA)));
+    const gmem<double> *qe = c.qin + 4 * c.eo;
     constexpr int cref = (N / 2) * (1 + N + N2);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -153,37 +183,40 @@ __device__ __forceinline__ bool load_element(const ElemArgs &A, T *sD, ElemCtx<N
         c.qr[f] = (T)ref;
         c.qt[f] = (T)(c.qd[f] - ref);
     }
-    const T *me = (const T *)A.metric + (size_t)c.e * 10 * N3;
+    const gmem<const T> *me = gp((const T *)M.metric[prec_index<T>()]) + 10 * c.eo;
     c.invJ = me[c.t];
 #pragma unroll
     for (int ii = 0; ii < 3; ++ii)
 #pragma unroll
         for (int d = 0; d < 3; ++d) c.Ja[ii][d] = me[(1 + 3 * ii + d) * N3 + c.t];
-    __syncthreads();
-    return true;
+    c.c0sq = (T)M.c0sq;
+    c.nu = (T)M.nu;
+    c.C_les = (T)M.C_les;
+    c.inv_wend = T(N * (N - 1) / 2);   // 1 / w_0 = P (P + 1) / 2
 }
 
-// The six face records of an element, loaded once per workgroup (uniform, so
-// scalar loads) and kept in named fields: a private array indexed by a lane's
-// face number would be placed in scratch memory.
-struct Faces6 {
-    FaceRef f0, f1, f2, f3, f4, f5;
-    __device__ explicit Faces6(const FaceRef *c)
-        : f0(c[0]), f1(c[1]), f2(c[2]), f3(c[3]), f4(c[4]), f5(c[5]) {}
-    // field-wise selects on plain integers (a select of whole structs would
-    // again go through memory)
-    __device__ __forceinline__ FaceRef operator[](int f) const
-    {
-        FaceRef r;
-        r.face = f == 0 ? f0.face : f == 1 ? f1.face : f == 2 ? f2.face : f == 3 ? f3.face : f == 4 ? f4.face : f5.face;
-        r.nbr = f == 0 ? f0.nbr : f == 1 ? f1.nbr : f == 2 ? f2.nbr : f == 3 ? f3.nbr : f == 4 ? f4.nbr : f5.nbr;
-        r.code = f == 0 ? f0.code : f == 1 ? f1.code : f == 2 ? f2.code : f == 3 ? f3.code : f == 4 ? f4.code : f5.code;
-        r.pad = 0;
-        return r;
-    }
+// Face-node task of a tile: element slot, element id, face, face coordinates.
+template <int N>
+struct FaceTask {
+    int s, e, f, fa, fb;
 };
 
-// Viscous operator of a flagged element.
+template <int N>
+__device__ __forceinline__ FaceTask<N> face_task(const StageArgs &A, const Tile &tl, int task)
+{
+    constexpr int N2 = Shape<N>::N2, NFT = 6 * N2;
+    FaceTask<N> ft;
+    ft.s = task / NFT;
+    const int r = task - ft.s * NFT;
+    ft.f = r / N2;
+    const int fn = r - ft.f * N2;
+    ft.fa = fn % N;
+    ft.fb = fn / N;
+    ft.e = ft.s < tl.count ? A.elems[tl.first + ft.s] : 0;
+    return ft;
+}
+
+// Viscous operator of the flagged elements of one tile.
 //  1. face-node tasks form u* - u, half the jump to the other side's velocity
 //     trace, in FP64 and stage it in LDS;
 //  2. BR1 lifted gradient: J G = sum_i D_i (Ja^i (u - u_r)) + on face nodes
@@ -195,52 +228,51 @@ struct Faces6 {
 //     face nodes, and the face traces tau . (s n) oriented by the face
 //     owner's outward normal, staged in LDS and stored by face-node lanes so
 //     that consecutive lanes write consecutive words.
-template <int N, class T>
-__global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
+template <int N, int EPT, class T>
+__device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl, char *smem)
 {
-    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3, NT = Shape<N>::NT;
-    constexpr int NFT = 6 * N2;
-    constexpr int TPT = (NFT + NT - 1) / NT;
-    __shared__ T lds[12 * N3];        // u, v, w and Ja; later the viscous contravariant fluxes
-    __shared__ T sfu[3 * NFT];        // [r][face node]: neighbour velocity trace, later tau . (s n)
-    __shared__ T sD[N2];
-    ElemCtx<N, T> c;
-    if (!load_element<N, T>(A, sD, c)) return;
-    const Consts<T> K(A);
-    const Faces6 frs(A.conn + (size_t)c.e * 6);
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
+    constexpr int NFT = 6 * N2, NN = EPT * N3, NTASK = EPT * NFT;
+    T *lds = (T *)smem;               // [12][NN]: u - u_r, v - v_r, w - w_r and Ja; later F_v
+    T *sfu = lds + 12 * NN;           // [3][NTASK]: half jumps, later tau . (s n)
+    T *sD = sfu + 3 * NTASK;          // [N2]
+    const Member &M = A.mem[tl.member];
+    TileCtx<N, T> c;
+    load_tile<N, EPT, T>(A, M, tl, sD, c);
     if (c.act) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) lds[r * N3 + c.tid] = c.qt[1 + r];
+        for (int r = 0; r < 3; ++r) lds[r * NN + c.g] = c.qt[1 + r];
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) lds[(3 + 3 * ii + d) * N3 + c.tid] = c.Ja[ii][d];
+            for (int d = 0; d < 3; ++d) lds[(3 + 3 * ii + d) * NN + c.g] = c.Ja[ii][d];
     }
 #pragma unroll 1
-    for (int kk = 0; kk < TPT; ++kk) {
-        const int task = c.tid + kk * NT;
-        if (task < NFT) {
+    for (int task = c.tid; task < NTASK; task += blockDim.x) {
+        const FaceTask<N> ft = face_task<N>(A, tl, task);
+        if (ft.s < tl.count) {
             // u* - u = (u_other - u) / 2, formed in FP64
-            const int f = task / N2, fn = task % N2;
-            const FaceRef fr = frs[f];
-            const double *qm = A.q + (size_t)c.e * 4 * N3 + face_node<N>(f, fn % N, fn / N);
+            const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
+            const gmem<const double> *qm = c.qin + 4 * gp(M.eoff)[ft.e] + face_node<N>(ft.f, ft.fa, ft.fb);
             double uo[3];
             if (fr.nbr >= 0) {
                 int a2, b2;
-                orient_map<N>(fr.code & 7, fn % N, fn / N, a2, b2);
-                const double *qn = A.q + (size_t)fr.nbr * 4 * N3 + face_node<N>((fr.code >> 3) & 7, a2, b2);
+                orient_map<N>(fr.code & 7, ft.fa, ft.fb, a2, b2);
+                const gmem<const double> *qn = c.qin + 4 * gp(M.eoff)[fr.nbr] + face_node<N>((fr.code >> 3) & 7, a2, b2);
 #pragma unroll
                 for (int r = 0; r < 3; ++r) uo[r] = qn[(1 + r) * N3];
             } else {
 #pragma unroll
-                for (int r = 0; r < 3; ++r) uo[r] = fr.nbr == HDG_WALL ? -qm[(1 + r) * N3] : A.qinf[1 + r];
+                for (int r = 0; r < 3; ++r) uo[r] = fr.nbr == HDG_WALL ? -qm[(1 + r) * N3] : M.qinf[1 + r];
             }
 #pragma unroll
-            for (int r = 0; r < 3; ++r) sfu[r * NFT + task] = (T)(0.5 * (uo[r] - qm[(1 + r) * N3]));
+            for (int r = 0; r < 3; ++r) sfu[r * NTASK + task] = (T)(0.5 * (uo[r] - qm[(1 + r) * N3]));
         }
     }
     __syncthreads();
 
+    const int base = c.s * N3;
+    const int tbase = c.s * NFT;
     T G[3][3];
     {
         T JG[3][3];
@@ -250,19 +282,20 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
             for (int d = 0; d < 3; ++d) JG[r][d] = T(0);
 #pragma unroll 1
         for (int m = 0; m < N; ++m) {
-            const int n0 = m + N * c.j + N2 * c.k, n1 = c.i + N * m + N2 * c.k, n2 = c.i + N * c.j + N2 * m;
+            const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
+                      n2 = base + c.i + N * c.j + N2 * m;
             T u0[3], u1[3], u2[3];
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                u0[r] = lds[r * N3 + n0];
-                u1[r] = lds[r * N3 + n1];
-                u2[r] = lds[r * N3 + n2];
+                u0[r] = lds[r * NN + n0];
+                u1[r] = lds[r * NN + n1];
+                u2[r] = lds[r * NN + n2];
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const T g0 = sD[c.i * N + m] * lds[(3 + d) * N3 + n0];
-                const T g1 = sD[c.j * N + m] * lds[(6 + d) * N3 + n1];
-                const T g2 = sD[c.k * N + m] * lds[(9 + d) * N3 + n2];
+                const T g0 = sD[c.i * N + m] * lds[(3 + d) * NN + n0];
+                const T g1 = sD[c.j * N + m] * lds[(6 + d) * NN + n1];
+                const T g2 = sD[c.k * N + m] * lds[(9 + d) * NN + n2];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) JG[r][d] += g0 * u0[r] + g1 * u1[r] + g2 * u2[r];
             }
@@ -272,11 +305,11 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
             const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
             if (c.act && (idx == 0 || idx == N - 1)) {
                 const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
-                const int task = f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
+                const int task = tbase + f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
                 const T sf = (f & 1) ? T(1) : T(-1);
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
-                    const T jump = sfu[r * NFT + task] * sf * K.inv_wend;
+                    const T jump = sfu[r * NTASK + task] * sf * c.inv_wend;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) JG[r][d] += jump * c.Ja[dir][d];
                 }
@@ -289,28 +322,30 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
     }
     T fv[3][3];
     {
-        const T mu = K.nu + les_nut<T>(A.les_model, K.C_les, (T)A.delta[c.e], G);
+        const T mu = c.nu + les_nut<T>(M.les_model, c.C_les, (T)gp(M.delta)[c.e], G);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int d = 0; d < 3; ++d) fv[r][d] = mu * (G[r][d] + G[d][r]);
     }
-    __syncthreads();     // every lane is done reading u, Ja and the neighbour traces from lds
+    __syncthreads();     // every lane is done reading u, Ja and the half jumps from LDS
     if (c.act) {
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii)
 #pragma unroll
             for (int r = 0; r < 3; ++r)
-                lds[(ii * 3 + r) * N3 + c.tid] = c.Ja[ii][0] * fv[r][0] + c.Ja[ii][1] * fv[r][1] + c.Ja[ii][2] * fv[r][2];
+                lds[(ii * 3 + r) * NN + c.g] = c.Ja[ii][0] * fv[r][0] + c.Ja[ii][1] * fv[r][1] + c.Ja[ii][2] * fv[r][2];
     }
     __syncthreads();
     T W[3] = {T(0), T(0), T(0)};
 #pragma unroll 1
     for (int m = 0; m < N; ++m) {
-        const int n0 = m + N * c.j + N2 * c.k, n1 = c.i + N * m + N2 * c.k, n2 = c.i + N * c.j + N2 * m;
+        const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
+                  n2 = base + c.i + N * c.j + N2 * m;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-            W[r] -= sD[c.i * N + m] * lds[r * N3 + n0] + sD[c.j * N + m] * lds[(3 + r) * N3 + n1] + sD[c.k * N + m] * lds[(6 + r) * N3 + n2];
+            W[r] -= sD[c.i * N + m] * lds[r * NN + n0] + sD[c.j * N + m] * lds[(3 + r) * NN + n1] +
+                    sD[c.k * N + m] * lds[(6 + r) * NN + n2];
     }
 #pragma unroll
     for (int dir = 0; dir < 3; ++dir) {
@@ -319,35 +354,34 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
             const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
             const T sf = (f & 1) ? T(1) : T(-1);
 #pragma unroll
-            for (int r = 0; r < 3; ++r) W[r] += sf * lds[(dir * 3 + r) * N3 + c.tid] * K.inv_wend;
+            for (int r = 0; r < 3; ++r) W[r] += sf * lds[(dir * 3 + r) * NN + c.g] * c.inv_wend;
             // tau . (s n) with the owner's outward normal: +-(this element's outward)
-            const int task = f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
-            const FaceRef fr = frs[f];
+            const int task = tbase + f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
+            const FaceRef fr = load_face(M.conn, (size_t)c.e * 6 + f);
             const T so = (fr.code & kOwnerBit) ? sf : -sf;
             const T sn[3] = {so * c.Ja[dir][0], so * c.Ja[dir][1], so * c.Ja[dir][2]};
 #pragma unroll
-            for (int r = 0; r < 3; ++r) sfu[r * NFT + task] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
+            for (int r = 0; r < 3; ++r) sfu[r * NTASK + task] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
         }
     }
     if (c.act) {
-        T *wv = (T *)A.wvis + (size_t)c.e * 3 * N3 + c.tid;
+        gmem<T> *wv = gp((T *)M.wvis) + 3 * c.eo + c.t;
 #pragma unroll
         for (int r = 0; r < 3; ++r) wv[r * N3] = W[r];
     }
     __syncthreads();
-    T *fvt = (T *)A.fvt;
+    gmem<T> *fvt = gp((T *)M.fvt);
 #pragma unroll 1
-    for (int kk = 0; kk < TPT; ++kk) {
-        const int task = c.tid + kk * NT;
-        if (task < NFT) {
-            const int f = task / N2, fn = task % N2;
-            const FaceRef fr = frs[f];
+    for (int task = c.tid; task < NTASK; task += blockDim.x) {
+        const FaceTask<N> ft = face_task<N>(A, tl, task);
+        if (ft.s < tl.count) {
+            const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
             const bool own = fr.code & kOwnerBit;
-            int oa = fn % N, ob = fn / N;
-            if (!own) orient_map<N>(fr.code & 7, fn % N, fn / N, oa, ob);
-            T *out = fvt + ((size_t)fr.face * 2 + (own ? 0 : 1)) * 3 * N2 + oa + N * ob;
+            int oa = ft.fa, ob = ft.fb;
+            if (!own) orient_map<N>(fr.code & 7, ft.fa, ft.fb, oa, ob);
+            gmem<T> *out = fvt + 6 * gp(M.foff)[fr.face] + (own ? 0 : 3 * N2) + oa + N * ob;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) out[r * N2] = sfu[r * NFT + task];
+            for (int r = 0; r < 3; ++r) out[r * N2] = sfu[r * NTASK + task];
         }
     }
 }
@@ -364,13 +398,13 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_viscous(ElemArgs A)
 // viscous traces when a side is flagged.  The non-owner sees -F*, and the two
 // sides' implied fluxes are exact negatives in exact arithmetic.
 template <int N, class T>
-__device__ __forceinline__ void face_jump(const ElemArgs &A, const Consts<T> &K, int e, bool visc, int f, int fa,
-                                          int fb, T (&F)[4], const Faces6 &frs)
+__device__ __forceinline__ void face_jump(const Member &M, const gmem<const double> *qin, T c0sq, int e, bool visc,
+                                          int f, int fa, int fb, T (&F)[4])
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
-    const FaceRef fr = frs[f];
+    const FaceRef fr = load_face(M.conn, (size_t)e * 6 + f);
     const bool own = fr.code & kOwnerBit;
-    const double *qe = A.q + (size_t)e * 4 * N3 + face_node<N>(f, fa, fb);
+    const gmem<const double> *qe = qin + 4 * gp(M.eoff)[e] + face_node<N>(f, fa, fb);
     double qm[4], qo[4];
 #pragma unroll
     for (int x = 0; x < 4; ++x) qm[x] = qe[x * N3];
@@ -379,7 +413,7 @@ __device__ __forceinline__ void face_jump(const ElemArgs &A, const Consts<T> &K,
         int a2, b2;
         orient_map<N>(fr.code & 7, fa, fb, a2, b2);
         if (!own) { oa = a2; ob = b2; }
-        const double *qn = A.q + (size_t)fr.nbr * 4 * N3 + face_node<N>((fr.code >> 3) & 7, a2, b2);
+        const gmem<const double> *qn = qin + 4 * gp(M.eoff)[fr.nbr] + face_node<N>((fr.code >> 3) & 7, a2, b2);
 #pragma unroll
         for (int x = 0; x < 4; ++x) qo[x] = qn[x * N3];
     } else if (fr.nbr == HDG_WALL) {
@@ -388,10 +422,10 @@ __device__ __forceinline__ void face_jump(const ElemArgs &A, const Consts<T> &K,
         for (int x = 1; x < 4; ++x) qo[x] = -qm[x];
     } else {
 #pragma unroll
-        for (int x = 0; x < 4; ++x) qo[x] = A.qinf[x];
+        for (int x = 0; x < 4; ++x) qo[x] = M.qinf[x];
     }
     const int fnode = oa + N * ob;
-    const T *g = (const T *)A.fgeo + ((size_t)fr.face * N2 + fnode) * 4;
+    const gmem<const T> *g = gp((const T *)M.fgeo[prec_index<T>()]) + 4 * (gp(M.foff)[fr.face] + fnode);
     const T n[3] = {g[0], g[1], g[2]};
     const T sc = g[3];
     T uL[3], du[3];
@@ -407,14 +441,14 @@ __device__ __forceinline__ void face_jump(const ElemArgs &A, const Consts<T> &K,
     const T uRn = uLn + dun;
     // mean-state eigen-decomposition of |A| dq (eigenvalues u_n, u_n, u_n +- a)
     const T un = uLn + h * dun;
-    const T a = sqrt(un * un + K.c0sq);
+    const T a = sqrt(un * un + c0sq);
     const T ia = T(1) / a;
     const T pip = a - un, pim = -a - un;
     const T alp = h * ia * (dp - pim * dun);   // acoustic wave u_n + a
     const T alm = h * ia * (pip * dun - dp);   // acoustic wave u_n - a
     const T lp = (un + a) * alp, lm = (a - un) * alm, l0 = fabs(un);
     const T sg = own ? T(-1) : T(1);           // -|A| dq for the owner, + for the other side
-    F[0] = h * sc * (K.c0sq * dun + sg * (lp * pip + lm * pim));
+    F[0] = h * sc * (c0sq * dun + sg * (lp * pip + lm * pim));
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const T ub = uL[d] + h * du[d];
@@ -424,14 +458,14 @@ __device__ __forceinline__ void face_jump(const ElemArgs &A, const Consts<T> &K,
         const T dF = uL[d] * dun + du[d] * uRn + dp * n[d];
         F[1 + d] = h * sc * (dF + sg * (lp * vp + lm * vm + l0 * tang));
     }
-    const bool nb_visc = fr.nbr >= 0 && A.flag[fr.nbr];
+    const bool nb_visc = fr.nbr >= 0 && gp(M.flag)[fr.nbr];
     const bool visL = own ? visc : nb_visc;
     const bool visR = own ? nb_visc : visc;
     if (visL || visR) {
         // BR1: mean of the two sides' viscous traces (an Euler side contributes
         // zero); a boundary face takes the interior trace.  F* carries -F_v*.
-        const bool keep = fr.nbr < 0 || A.mixed_face == 0 || (visL && visR);
-        const T *tv = (const T *)A.fvt + (size_t)fr.face * 6 * N2 + fnode;
+        const bool keep = fr.nbr < 0 || M.mixed_face == 0 || (visL && visR);
+        const gmem<const T> *tv = gp((const T *)M.fvt) + 6 * gp(M.foff)[fr.face] + fnode;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const T tL = visL ? tv[r * N2] : T(0);
@@ -442,19 +476,18 @@ __device__ __forceinline__ void face_jump(const ElemArgs &A, const Consts<T> &K,
     }
 }
 
-template <int N, int EPI, class T>
-__global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
+template <int N, int EPT, int EPI, class T>
+__device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl, char *smem)
 {
-    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3, NT = Shape<N>::NT;
-    constexpr int NFT = 6 * N2;                        // face-node tasks per element
-    constexpr int TPT = (NFT + NT - 1) / NT;           // tasks per lane
-    __shared__ T lds[12 * N3];                         // contravariant fluxes
-    __shared__ T sface[4 * NFT];                       // surface terms F* - F_own, [row][face node]
-    __shared__ T sD[N2];
-    ElemCtx<N, T> c;
-    if (!load_element<N, T>(A, sD, c)) return;
-    const Consts<T> K(A);
-    const bool visc = A.flag[c.e] != 0;
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
+    constexpr int NFT = 6 * N2, NN = EPT * N3, NTASK = EPT * NFT;
+    T *lds = (T *)smem;               // [12][NN] contravariant fluxes
+    T *sface = lds + 12 * NN;         // [4][NTASK] surface terms F* - F_own
+    T *sD = sface + 4 * NTASK;        // [N2]
+    const Member &M = A.mem[tl.member];
+    TileCtx<N, T> c;
+    load_tile<N, EPT, T>(A, M, tl, sD, c);
+    const bool visc = gp(M.flag)[c.e] != 0;
 
     // contravariant convective fluxes F^i_row = sum_d Ja^i_d f_{row,d} of the
     // deviation f(q) - f(q_r): c0^2 (u - u_r) and
@@ -463,7 +496,7 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
         T f[4][3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            f[0][d] = K.c0sq * c.qt[1 + d];
+            f[0][d] = c.c0sq * c.qt[1 + d];
 #pragma unroll
             for (int r = 0; r < 3; ++r)
                 f[1 + r][d] = c.q[1 + r] * c.qt[1 + d] + c.qt[1 + r] * c.qr[1 + d] + (r == d ? c.qt[0] : T(0));
@@ -473,49 +506,46 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
             for (int ii = 0; ii < 3; ++ii)
 #pragma unroll
                 for (int row = 0; row < 4; ++row)
-                    lds[(ii * 4 + row) * N3 + c.tid] =
+                    lds[(ii * 4 + row) * NN + c.g] =
                         c.Ja[ii][0] * f[row][0] + c.Ja[ii][1] * f[row][1] + c.Ja[ii][2] * f[row][2];
         }
     }
 
-    const Faces6 frs(A.conn + (size_t)c.e * 6);
-    // face-node tasks, spread evenly over the workgroup
+    // face-node tasks, spread evenly over the workgroup; a tile's elements
+    // share one equation class
 #pragma unroll 1
-    for (int k = 0; k < TPT; ++k) {
-        const int task = c.tid + k * NT;
-        if (task < NFT) {
-            const int f = task / N2, fn = task % N2;
+    for (int task = c.tid; task < NTASK; task += blockDim.x) {
+        const FaceTask<N> ft = face_task<N>(A, tl, task);
+        if (ft.s < tl.count) {
             T F[4];
-            face_jump<N, T>(A, K, c.e, visc, f, fn % N, fn / N, F, frs);
+            face_jump<N, T>(M, c.qin, c.c0sq, ft.e, visc, ft.f, ft.fa, ft.fb, F);
 #pragma unroll
-            for (int row = 0; row < 4; ++row) sface[row * NFT + task] = F[row];
+            for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
         }
     }
+    gmem<double> *dqp = gp(A.q_in ? A.dq : M.dq);
     double dq_old[4] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (EPI == (int)Epi::RkStage) {
         if (!A.first_stage) {
-            const double *dqe = A.dq + (size_t)c.e * 4 * N3 + c.t;
+            const gmem<double> *dqe = dqp + 4 * c.eo + c.t;
 #pragma unroll
             for (int row = 0; row < 4; ++row) dq_old[row] = dqe[row * N3];
         }
     }
     __syncthreads();
-    T Dx[N], Dy[N], Dz[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-        Dx[m] = sD[c.i * N + m];
-        Dy[m] = sD[c.j * N + m];
-        Dz[m] = sD[c.k * N + m];
-    }
 
-    // reference divergence
+    // reference divergence (a rolled loop: unrolled, the scheduler hoists all
+    // 12 N LDS reads and doubles the register count)
+    const int base = c.s * N3;
     T V[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
+#pragma unroll 1
     for (int m = 0; m < N; ++m) {
-        const int n0 = m + N * c.j + N2 * c.k, n1 = c.i + N * m + N2 * c.k, n2 = c.i + N * c.j + N2 * m;
+        const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
+                  n2 = base + c.i + N * c.j + N2 * m;
+        const T dx = sD[c.i * N + m], dy = sD[c.j * N + m], dz = sD[c.k * N + m];
 #pragma unroll
         for (int row = 0; row < 4; ++row)
-            V[row] += Dx[m] * lds[row * N3 + n0] + Dy[m] * lds[(4 + row) * N3 + n1] + Dz[m] * lds[(8 + row) * N3 + n2];
+            V[row] += dx * lds[row * NN + n0] + dy * lds[(4 + row) * NN + n1] + dz * lds[(8 + row) * NN + n2];
     }
 
     // face nodes: numerical flux minus own flux, over w_end
@@ -526,32 +556,73 @@ __global__ __launch_bounds__(Shape<N>::NT) void k_residual(ElemArgs A)
             const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
             const int fa = dir == 0 ? c.j : c.i;
             const int fb = dir == 2 ? c.j : c.k;
-            const T *Fs = sface + f * N2 + fa + N * fb;
+            const T *Fs = sface + c.s * NFT + f * N2 + fa + N * fb;
 #pragma unroll
-            for (int row = 0; row < 4; ++row) V[row] += Fs[row * NFT] * K.inv_wend;
+            for (int row = 0; row < 4; ++row) V[row] += Fs[row * NTASK] * c.inv_wend;
         }
     }
 
-    if (!c.act) return;
-    if (visc) {
-        const T *wv = (const T *)A.wvis + (size_t)c.e * 3 * N3 + c.tid;
+    if (c.act) {
+        if (visc) {
+            const gmem<const T> *wv = gp((const T *)M.wvis) + 3 * c.eo + c.t;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) V[1 + r] += wv[r * N3];
-    }
-    const size_t base = (size_t)c.e * 4 * N3 + c.tid;
-#pragma unroll
-    for (int row = 0; row < 4; ++row) {
-        const T R = -V[row] * c.invJ;
-        const size_t idx = base + (size_t)row * N3;
-        if constexpr (EPI == (int)Epi::Residual) {
-            ((T *)A.out)[idx] = R;
-        } else {
-            // FP64 stage accumulation into the state
-            const double Rd = (double)R;
-            const double d = A.first_stage ? A.dt * Rd : A.rkA * dq_old[row] + A.dt * Rd;
-            A.dq[idx] = d;
-            ((double *)A.out)[idx] = c.qd[row] + A.rkB * d;
+            for (int r = 0; r < 3; ++r) V[1 + r] += wv[r * N3];
         }
+        const size_t base_o = 4 * c.eo + c.t;
+#pragma unroll
+        for (int row = 0; row < 4; ++row) {
+            const T R = -V[row] * c.invJ;
+            const size_t idx = base_o + (size_t)row * N3;
+            if constexpr (EPI == (int)Epi::Residual) {
+                gp((T *)A.r)[idx] = R;
+            } else {
+                // FP64 stage accumulation into the state
+                const double Rd = (double)R;
+                const double dt = A.q_in ? A.dt : M.dt;
+                const double d = A.first_stage ? dt * Rd : A.rkA * dq_old[row] + dt * Rd;
+                dqp[idx] = d;
+                gmem<double> *qout = gp(A.q_in ? A.q_out : (A.parity ? M.qA : M.qB));
+                qout[idx] = c.qd[row] + A.rkB * d;
+            }
+        }
+    }
+}
+
+// Persistent tile loop: the grid is a multiple of kXcd; workgroup b runs on
+// XCD b mod kXcd (round-robin dispatch) and walks that XCD's contiguous chunk
+// of the (spatially ordered) tile list, so neighbour traces hit its L2.
+#define HDG_TILE_LOOP(A, tl)                                                                   \
+    const int xcd_ = blockIdx.x % kXcd, loc_ = blockIdx.x / kXcd, nloc_ = gridDim.x / kXcd;   \
+    for (int i_ = loc_; i_ < (A).chunk; i_ += nloc_)                                           \
+        if (const int ti_ = xcd_ * (A).chunk + i_; ti_ < (A).ntiles)                            \
+            if (const Tile tl = (A).tiles[ti_]; true)
+
+// One persistent kernel per (kind, order, workgroup size): a single kernel
+// over every order would carry the register demand of all of them at once
+// (measured: about 1.7x the largest single order), halving occupancy.
+template <class T, int N, int B>
+__global__ __launch_bounds__(B) void k_viscous(StageArgs A)
+{
+    constexpr int EPT = tile_ept(N, B, kTileViscous);
+    static_assert(EPT > 0, "tile does not fit the workgroup");
+    constexpr int N2 = N * N, NN = EPT * N * N2, NTASK = EPT * 6 * N2;
+    __shared__ __attribute__((aligned(16))) char smem[(12 * NN + 3 * NTASK + N2) * sizeof(T)];
+    HDG_TILE_LOOP(A, tl) {
+        viscous_tile<N, EPT, T>(A, tl, smem);
+        __syncthreads();
+    }
+}
+
+template <class T, int EPI, int N, int B>
+__global__ __launch_bounds__(B) void k_residual(StageArgs A)
+{
+    constexpr int EPT = tile_ept(N, B, kTileResidual);
+    static_assert(EPT > 0, "tile does not fit the workgroup");
+    constexpr int N2 = N * N, NN = EPT * N * N2, NTASK = EPT * 6 * N2;
+    __shared__ __attribute__((aligned(16))) char smem[(12 * NN + 4 * NTASK + N2) * sizeof(T)];
+    HDG_TILE_LOOP(A, tl) {
+        residual_tile<N, EPT, EPI, T>(A, tl, smem);
+        __syncthreads();
     }
 }
 
@@ -649,31 +720,6 @@ __global__ __launch_bounds__(kCopyBlock) void k_copy(u32x4 *dst, const u32x4 *sr
 }
 
 template <int N>
-hipError_t launch_viscous_n(bool f32, const ElemArgs &a, hipStream_t s)
-{
-    if (a.count == 0) return hipSuccess;
-    const dim3 grid(kXcd * a.per_xcd), block(Shape<N>::NT);
-    if (f32) hipLaunchKernelGGL((k_viscous<N, float>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_viscous<N, double>), grid, block, 0, s, a);
-    return hipGetLastError();
-}
-
-template <int N>
-hipError_t launch_residual_n(Epi epi, bool f32, const ElemArgs &a, hipStream_t s)
-{
-    if (a.count == 0) return hipSuccess;
-    const dim3 grid(kXcd * a.per_xcd), block(Shape<N>::NT);
-    if (f32) {
-        if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<N, 0, float>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_residual<N, 1, float>), grid, block, 0, s, a);
-    } else {
-        if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<N, 0, double>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_residual<N, 1, double>), grid, block, 0, s, a);
-    }
-    return hipGetLastError();
-}
-
-template <int N>
 hipError_t launch_reduce_n(const double *r, const double *mass, int64_t ne, double *partials, int nblocks,
                            double *final13, hipStream_t s)
 {
@@ -698,18 +744,73 @@ hipError_t launch_reduce_n(const double *r, const double *mass, int64_t ne, doub
     default: return hipErrorInvalidValue;                                              \
     }
 
-hipError_t launch_viscous(int N, bool f32, const ElemArgs &a, hipStream_t s)
+// Calls f(integral_constant<N>, integral_constant<B>) for a supported pair.
+template <class F>
+hipError_t by_shape(int N, int B, F f)
 {
-#define C_(n) launch_viscous_n<n>(f32, a, s)
-    HDG_DISPATCH_N(N, C_)
-#undef C_
+#define SH_(n, b)                                                                          \
+    if (N == n && B == b) return f(std::integral_constant<int, n>{}, std::integral_constant<int, b>{});
+    SH_(2, 128) SH_(3, 128) SH_(4, 128) SH_(5, 128)
+    SH_(2, 256) SH_(3, 256) SH_(4, 256) SH_(5, 256) SH_(6, 256)
+    SH_(2, 512) SH_(3, 512) SH_(4, 512) SH_(5, 512) SH_(6, 512) SH_(7, 512) SH_(8, 512)
+#undef SH_
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_residual(int N, Epi epi, bool f32, const ElemArgs &a, hipStream_t s)
+hipError_t launch_viscous(int N, int B, bool f32, const StageArgs &a, int grid, hipStream_t s)
 {
-#define C_(n) launch_residual_n<n>(epi, f32, a, s)
-    HDG_DISPATCH_N(N, C_)
-#undef C_
+    if (a.ntiles == 0) return hipSuccess;
+    if (grid <= 0 || grid % kXcd) return hipErrorInvalidValue;
+    return by_shape(N, B, [&](auto nc, auto bc) {
+        constexpr int NN = decltype(nc)::value, BB = decltype(bc)::value;
+        if (f32) hipLaunchKernelGGL((k_viscous<float, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
+        else hipLaunchKernelGGL((k_viscous<double, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_residual(int N, int B, Epi epi, bool f32, const StageArgs &a, int grid, hipStream_t s)
+{
+    if (a.ntiles == 0) return hipSuccess;
+    if (grid <= 0 || grid % kXcd) return hipErrorInvalidValue;
+    return by_shape(N, B, [&](auto nc, auto bc) {
+        constexpr int NN = decltype(nc)::value, BB = decltype(bc)::value;
+        if (f32) {
+            if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<float, 0, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
+            else hipLaunchKernelGGL((k_residual<float, 1, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
+        } else {
+            if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<double, 0, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
+            else hipLaunchKernelGGL((k_residual<double, 1, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
+        }
+        return hipGetLastError();
+    });
+}
+
+int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32)
+{
+    // occupancy does not change at run time: query each configuration once
+    static int cache[2][kMaxN + 1][3][2][2] = {};
+    int &slot = cache[kind & 1][N][B <= 128 ? 0 : B <= 256 ? 1 : 2][(int)epi & 1][f32];
+    if (slot > 0) return slot;
+    int n = 0;
+    hipError_t e = by_shape(N, B, [&](auto nc, auto bc) {
+        constexpr int NN = decltype(nc)::value, BB = decltype(bc)::value;
+        const void *fn = nullptr;
+        if (kind == kTileViscous)
+            fn = f32 ? (const void *)k_viscous<float, NN, BB> : (const void *)k_viscous<double, NN, BB>;
+        else if (f32)
+            fn = epi == Epi::Residual ? (const void *)k_residual<float, 0, NN, BB> : (const void *)k_residual<float, 1, NN, BB>;
+        else
+            fn = epi == Epi::Residual ? (const void *)k_residual<double, 0, NN, BB> : (const void *)k_residual<double, 1, NN, BB>;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, BB, 0);
+    });
+    slot = e == hipSuccess && n > 0 ? n : 1;
+    return slot;
+}
+
+bool shape_supported(int N, int B)
+{
+    return by_shape(N, B, [](auto, auto) { return hipSuccess; }) == hipSuccess;
 }
 
 hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_elem, double *partials,

@@ -27,6 +27,7 @@ EXPORTED = [
     "hdg_mesh_set_params", "hdg_mesh_info", "hdg_mesh_node_coords", "hdg_mesh_geometry", "hdg_residual",
     "hdg_rk3_steps",
     "hdg_reduce", "hdg_timing_enable", "hdg_timing_read", "hdg_stream_copy", "hdg_last_error",
+    "hdg_mesh_autotune", "hdg_mesh_get_launch", "hdg_mesh_set_launch", "hdg_mesh_set_graphs",
 ]
 
 
@@ -46,6 +47,10 @@ class MeshDesc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("c0sq", C.c_double), ("nu", C.c_double), ("les_model", C.c_int32),
                 ("C_les", C.c_double), ("mixed_face", C.c_int32), ("q_inf", C.c_double * 4)]
+
+
+class LaunchCfg(C.Structure):
+    _fields_ = [("block", C.c_int32), ("persistent", C.c_int32), ("us_per_launch", C.c_double)]
 
 
 _lib = None
@@ -76,6 +81,11 @@ def lib() -> C.CDLL:
         L.hdg_timing_enable.argtypes = [vp, i32]
         L.hdg_timing_read.argtypes = [vp, i32, dp, C.POINTER(i64)]
         L.hdg_stream_copy.argtypes = [vp, vp, vp, i64, vp]
+        L.hdg_mesh_autotune.argtypes = [vp, vp, i32, vp]
+        L.hdg_mesh_get_launch.argtypes = [vp, i32, i32, i32, C.POINTER(LaunchCfg)]
+        L.hdg_mesh_set_launch.argtypes = [vp, i32, i32, i32, C.POINTER(LaunchCfg)]
+        L.hdg_mesh_set_graphs.argtypes = [vp, i32]
+        L.hdg_last_error.argtypes = []
         L.hdg_last_error.restype = C.c_char_p
         for name in EXPORTED:
             f = getattr(L, name)
@@ -272,6 +282,26 @@ def hdg_timing_read(mesh: Mesh, kernel_class: int) -> tuple[float, int]:
     ms, n = C.c_double(), C.c_int64()
     _check(lib().hdg_timing_read(mesh.handle, kernel_class, C.byref(ms), C.byref(n)), "hdg_timing_read")
     return ms.value, n.value
+
+
+def hdg_mesh_autotune(mesh: Mesh, q, reps: int = 5, stream=None):
+    _check_state(mesh, q, "q")
+    _check(lib().hdg_mesh_autotune(mesh.handle, _ptr(q), int(reps), _stream(stream)), "hdg_mesh_autotune")
+
+
+def hdg_mesh_get_launch(mesh: Mesh, kernel_class: int, prec: int, N: int) -> dict:
+    c = LaunchCfg()
+    _check(lib().hdg_mesh_get_launch(mesh.handle, kernel_class, prec, N, C.byref(c)), "hdg_mesh_get_launch")
+    return dict(block=c.block, persistent=bool(c.persistent), us_per_launch=c.us_per_launch)
+
+
+def hdg_mesh_set_launch(mesh: Mesh, kernel_class: int, prec: int, N: int, block: int, persistent: bool):
+    c = LaunchCfg(int(block), 1 if persistent else 0, 0.0)
+    _check(lib().hdg_mesh_set_launch(mesh.handle, kernel_class, prec, N, C.byref(c)), "hdg_mesh_set_launch")
+
+
+def hdg_mesh_set_graphs(mesh: Mesh, enable: bool):
+    _check(lib().hdg_mesh_set_graphs(mesh.handle, 1 if enable else 0), "hdg_mesh_set_graphs")
 
 
 def hdg_stream_copy(ctx: Context, dst, src, nbytes: int, stream=None):

@@ -18,6 +18,14 @@ def _declared_functions():
     return sorted(set(names))
 
 
+def test_binding_declares_argument_types():
+    """Every binding has explicit argument types, so 64-bit handles and
+    pointers are never passed as C ints."""
+    L = hdg.lib()
+    for name in hdg.EXPORTED:
+        assert getattr(L, name).argtypes is not None, name
+
+
 def test_library_exports_every_declared_symbol():
     declared = _declared_functions()
     assert len(declared) >= 15
