@@ -211,6 +211,43 @@ hdg_status hdg_mesh_get_launch(const hdg_mesh *mesh, int32_t kernel_class, hdg_p
 hdg_status hdg_mesh_set_launch(hdg_mesh *mesh, int32_t kernel_class, hdg_prec prec, int32_t N,
                                const hdg_launch_cfg *cfg);
 
+/* ---- Batches of independent meshes (continuous batching) ----
+ *
+ * A batch advances many independent solves together: each member is a mesh
+ * created as above with its own device state q, RK register dq (both
+ * caller-owned, double, state layout), time step dt and parameters (copied
+ * from the mesh at add).  Every RK stage of the whole batch is one persistent
+ * launch per (kernel kind, order present) over the union of the members'
+ * element tiles, so small meshes share launches.  Each element is computed
+ * exactly as for its mesh alone: a member's result is bitwise independent of
+ * the rest of the batch.  Members can be added and removed between calls
+ * (at RK step boundaries).  A mesh in a batch uses its internal ping-pong and
+ * viscous scratch for the batch: do not step it on its own, re-flag it or
+ * change its parameters while it is a member, and remove it before
+ * destroying it.  All batch launches of one batch go to one stream. */
+typedef struct hdg_batch hdg_batch;
+
+hdg_status hdg_batch_create(hdg_ctx *ctx, int32_t max_members, hdg_batch **out);
+void hdg_batch_destroy(hdg_batch *batch);
+/* Adds `mesh` with its state q_dev, register dq_dev (distinct device arrays of
+ * the mesh's state length) and dt > 0; returns the slot.  HDG_ENOMEM when
+ * every slot is taken, HDG_EINVAL if the mesh is already a member. */
+hdg_status hdg_batch_add(hdg_batch *batch, hdg_mesh *mesh, double *q_dev, double *dq_dev, double dt,
+                         int32_t *slot);
+hdg_status hdg_batch_remove(hdg_batch *batch, int32_t slot);
+hdg_status hdg_batch_info(const hdg_batch *batch, int32_t *n_members, int64_t *n_elements, int64_t *n_nodes);
+/* nsteps RK steps of every member with its own dt (as hdg_rk3_steps; prec
+ * selects the residual arithmetic).  After a membership change the first call
+ * waits for the stream and rebuilds the tile lists; with graphs enabled (the
+ * default) two steps at a time replay a captured HIP graph. */
+hdg_status hdg_batch_rk3_steps(hdg_batch *batch, int32_t nsteps, hdg_prec prec, void *stream);
+hdg_status hdg_batch_set_graphs(hdg_batch *batch, int32_t enable);
+/* Autotuner over the batch's tiles (as hdg_mesh_autotune); writes every
+ * member's RK register and ping-pong buffer, not its state. */
+hdg_status hdg_batch_autotune(hdg_batch *batch, int32_t reps, void *stream);
+hdg_status hdg_batch_get_launch(const hdg_batch *batch, int32_t kernel_class, hdg_prec prec, int32_t N,
+                                hdg_launch_cfg *out);
+
 /* Plain device-to-device copy kernel (nbytes a multiple of 16, 16-byte aligned
  * pointers): the HBM bandwidth probe that calibrates traffic counters. */
 hdg_status hdg_stream_copy(hdg_ctx *ctx, void *dst_dev, const void *src_dev, int64_t nbytes,

@@ -7,30 +7,46 @@
 #include <string>
 #include <vector>
 
-#include "hdg_internal.h"
+#include "hdg_host.h"
 
 using hdg::Epi;
 using hdg::FaceRef;
+using hdg::kBlocks;
+using hdg::kMaxEvents;
+using hdg::LaunchCfg;
 using hdg::Member;
 using hdg::StageArgs;
 using hdg::Tile;
+using hdg::TilePlan;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-hdg_status fail(hdg_status s, const std::string &msg)
+namespace hdg {
+
+hdg_status set_error(hdg_status s, const std::string &msg)
 {
     g_err = msg;
     return s;
 }
 
-#define HDG_HIP(call)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(HDG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
-    } while (0)
+int launch_grid(const TilePlan &pl, int kind, Epi epi, bool f32, bool persistent, int n_cu)
+{
+    int64_t g = pl.ntiles;
+    if (persistent) {
+        const int per_cu = resident_blocks_per_cu(kind, pl.N, pl.B, epi, f32);
+        g = std::min<int64_t>(g, (int64_t)per_cu * n_cu);
+    }
+    g = (g + kXcd - 1) / kXcd * kXcd;
+    return (int)std::max<int64_t>(g, kXcd);
+}
+
+}  // namespace hdg
+
+namespace {
+
+hdg_status fail(hdg_status s, const std::string &msg) { return hdg::set_error(s, msg); }
 
 int face_node(int N, int f, int a, int b)
 {
@@ -45,112 +61,9 @@ void orient_map(int o, int M, int a, int b, int &a2, int &b2)
     b2 = (o & 4) ? M - t : t;
 }
 
-constexpr int kMaxEvents = 65536;
-
 }  // namespace
 
-struct hdg_ctx {
-    int device = 0;
-    int n_cu = 0;
-    double *D64 = nullptr;     // derivative matrices for N = 2..8, packed at d_offset(N)
-    float *D32 = nullptr;
-};
 
-namespace {
-
-// Tile list of one kernel kind, one order N and one workgroup size, on the device.
-struct TilePlan {
-    int N = 0, B = 0;
-    int32_t ntiles = 0, chunk = 0;
-    Tile *tiles = nullptr;
-    int32_t *elems = nullptr;
-};
-
-// Launch configuration of one (kernel kind, precision, order): workgroup size
-// and grid (persistent: resident workgroups only, or one workgroup per tile).
-struct LaunchCfg {
-    int B = 512;
-    bool persistent = true;
-    double us = 0.0;           // measured mean launch time when tuned, else 0
-};
-
-// Split the elements (visited in `order`) into tiles of equal (N, class), each
-// of at most tile_ept(N, B, kind) elements; tiles are ordered by the position
-// of their first element, so the tile list keeps the spatial order.
-void cut_tiles(const std::vector<int32_t> &order, const std::vector<int> &Ne, const std::vector<int> &cls,
-               int member, int B, int kind, std::vector<Tile> &tiles, std::vector<int32_t> &elems)
-{
-    struct Chunk { size_t pos; int N; std::vector<int32_t> e; };
-    std::vector<Chunk> done;
-    std::vector<Chunk> open(2 * (hdg::kMaxN + 1));
-    std::vector<bool> has(open.size(), false);
-    for (size_t r = 0; r < order.size(); ++r) {
-        const int32_t e = order[r];
-        if (cls[e] < 0) continue;
-        const int key = cls[e] * (hdg::kMaxN + 1) + Ne[e];
-        const int ept = hdg::tile_ept(Ne[e], B, kind);
-        if (!has[key]) {
-            open[key] = Chunk{r, Ne[e], {}};
-            has[key] = true;
-        }
-        open[key].e.push_back(e);
-        if ((int)open[key].e.size() == ept) {
-            done.push_back(std::move(open[key]));
-            has[key] = false;
-        }
-    }
-    for (size_t k = 0; k < open.size(); ++k)
-        if (has[k]) done.push_back(std::move(open[k]));
-    std::sort(done.begin(), done.end(), [](const Chunk &a, const Chunk &b) { return a.pos < b.pos; });
-    for (auto &c : done) {
-        tiles.push_back(Tile{member, c.N, (int32_t)c.e.size(), (int32_t)elems.size()});
-        elems.insert(elems.end(), c.e.begin(), c.e.end());
-    }
-}
-
-}  // namespace
-
-struct hdg_mesh {
-    hdg_ctx *ctx = nullptr;
-    int64_t ne = 0;
-    int P = 0, N = 0, N2 = 0, N3 = 0;
-    int64_t nfaces = 0;
-    hdg_params prm{};
-    double inv_wend = 0.0;
-    std::vector<uint8_t> flag;
-    std::vector<double> x;                 // node coordinates, host
-    std::vector<int32_t> order;            // processing order
-    int32_t n_visc = 0;
-    // device buffers
-    double *metric = nullptr, *fgeo = nullptr, *fvt = nullptr, *wvis = nullptr, *qpp = nullptr, *mass = nullptr;
-    double *delta = nullptr, *partials = nullptr, *final13 = nullptr;
-    // FP32 copies (one rounding of the FP64 set-up) read by the HDG_F32 kernels
-    float *metric32 = nullptr, *fgeo32 = nullptr;
-    FaceRef *conn = nullptr;
-    uint8_t *flag_d = nullptr;
-    int64_t *eoff = nullptr, *foff = nullptr;
-    Member *member = nullptr;              // the mesh's member record (device)
-    Member host_member{};
-    // tile plans per kernel kind, for every (order, workgroup size) pair
-    std::vector<TilePlan> plans[2];
-    LaunchCfg cfg[2][2][hdg::kMaxN + 1];   // [kind][precision][N]
-    int nblocks_reduce = 0;
-    int64_t bytes = 0;
-    // timing
-    bool timing = false;
-    std::vector<hipEvent_t> ev;            // pairs (start, stop)
-    std::vector<int> ev_kind;
-    size_t ev_used = 0;
-    // RK steps captured as a HIP graph (two steps, so the ping-pong state
-    // ends where it started), replayed on the caller's stream
-    bool graphs = true;
-    hipStream_t cap = nullptr;             // private stream used only for capture
-    hipGraphExec_t gexec = nullptr;
-    const double *g_q = nullptr;
-    const double *g_dq = nullptr;
-    double g_dt = 0.0;
-    int g_prec = -1;
-};
 
 namespace {
 
@@ -197,7 +110,6 @@ hdg_status check_params(const hdg_params *p)
     return HDG_OK;
 }
 
-constexpr int kBlocks[3] = {128, 256, 512};
 
 const TilePlan *find_plan(const hdg_mesh *m, int kind, int N, int B)
 {
@@ -243,7 +155,7 @@ hdg_status upload_plans(hdg_mesh *m)
                 if (!hdg::shape_supported(N, B)) continue;
                 std::vector<Tile> tiles;
                 std::vector<int32_t> elems;
-                cut_tiles(m->order, Ne, cn, 0, B, kind, tiles, elems);
+                hdg::cut_tiles(m->order, Ne, cn, 0, B, kind, tiles, elems);
                 TilePlan pl;
                 pl.N = N;
                 pl.B = B;
@@ -279,13 +191,7 @@ hdg_status upload_member(hdg_mesh *m)
 
 int grid_for(const hdg_mesh *m, const TilePlan &pl, int kind, Epi epi, bool f32, bool persistent)
 {
-    int64_t g = pl.ntiles;
-    if (persistent) {
-        const int per_cu = hdg::resident_blocks_per_cu(kind, pl.N, pl.B, epi, f32);
-        g = std::min<int64_t>(g, (int64_t)per_cu * m->ctx->n_cu);
-    }
-    g = (g + hdg::kXcd - 1) / hdg::kXcd * hdg::kXcd;
-    return (int)std::max<int64_t>(g, hdg::kXcd);
+    return hdg::launch_grid(pl, kind, epi, f32, persistent, m->ctx->n_cu);
 }
 
 // Launch with optional event bracketing for the kernel timer.

@@ -28,6 +28,8 @@ EXPORTED = [
     "hdg_rk3_steps",
     "hdg_reduce", "hdg_timing_enable", "hdg_timing_read", "hdg_stream_copy", "hdg_last_error",
     "hdg_mesh_autotune", "hdg_mesh_get_launch", "hdg_mesh_set_launch", "hdg_mesh_set_graphs",
+    "hdg_batch_create", "hdg_batch_destroy", "hdg_batch_add", "hdg_batch_remove", "hdg_batch_info",
+    "hdg_batch_rk3_steps", "hdg_batch_set_graphs", "hdg_batch_autotune", "hdg_batch_get_launch",
 ]
 
 
@@ -85,11 +87,21 @@ def lib() -> C.CDLL:
         L.hdg_mesh_get_launch.argtypes = [vp, i32, i32, i32, C.POINTER(LaunchCfg)]
         L.hdg_mesh_set_launch.argtypes = [vp, i32, i32, i32, C.POINTER(LaunchCfg)]
         L.hdg_mesh_set_graphs.argtypes = [vp, i32]
+        L.hdg_batch_create.argtypes = [vp, i32, C.POINTER(vp)]
+        L.hdg_batch_destroy.argtypes = [vp]
+        L.hdg_batch_destroy.restype = None
+        L.hdg_batch_add.argtypes = [vp, vp, vp, vp, C.c_double, C.POINTER(i32)]
+        L.hdg_batch_remove.argtypes = [vp, i32]
+        L.hdg_batch_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64)]
+        L.hdg_batch_rk3_steps.argtypes = [vp, i32, i32, vp]
+        L.hdg_batch_set_graphs.argtypes = [vp, i32]
+        L.hdg_batch_autotune.argtypes = [vp, i32, vp]
+        L.hdg_batch_get_launch.argtypes = [vp, i32, i32, i32, C.POINTER(LaunchCfg)]
         L.hdg_last_error.argtypes = []
         L.hdg_last_error.restype = C.c_char_p
         for name in EXPORTED:
             f = getattr(L, name)
-            if name not in ("hdg_finalize", "hdg_mesh_destroy", "hdg_last_error"):
+            if name not in ("hdg_finalize", "hdg_mesh_destroy", "hdg_batch_destroy", "hdg_last_error"):
                 f.restype = C.c_int
         _lib = L
     return _lib
@@ -302,6 +314,66 @@ def hdg_mesh_set_launch(mesh: Mesh, kernel_class: int, prec: int, N: int, block:
 
 def hdg_mesh_set_graphs(mesh: Mesh, enable: bool):
     _check(lib().hdg_mesh_set_graphs(mesh.handle, 1 if enable else 0), "hdg_mesh_set_graphs")
+
+
+class Batch:
+    """Owner of an ``hdg_batch`` handle; keeps its members (mesh and the torch
+    tensors of their state and RK register) alive while they are in it."""
+
+    def __init__(self, ctx: Context, max_members: int):
+        h = C.c_void_p()
+        _check(lib().hdg_batch_create(ctx.handle, int(max_members), C.byref(h)), "hdg_batch_create")
+        self.handle = h
+        self.ctx = ctx
+        self.members = {}
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.hdg_batch_destroy(self.handle)
+            self.handle = None
+
+
+def hdg_batch_create(ctx: Context, max_members: int) -> Batch:
+    return Batch(ctx, max_members)
+
+
+def hdg_batch_add(batch: Batch, mesh: Mesh, q, dq, dt: float) -> int:
+    _check_state(mesh, q, "q")
+    _check_state(mesh, dq, "dq")
+    slot = C.c_int32()
+    _check(lib().hdg_batch_add(batch.handle, mesh.handle, _ptr(q), _ptr(dq), float(dt), C.byref(slot)),
+           "hdg_batch_add")
+    batch.members[slot.value] = (mesh, q, dq)
+    return slot.value
+
+
+def hdg_batch_remove(batch: Batch, slot: int):
+    _check(lib().hdg_batch_remove(batch.handle, int(slot)), "hdg_batch_remove")
+    batch.members.pop(slot, None)
+
+
+def hdg_batch_info(batch: Batch) -> dict:
+    nm, ne, nn = C.c_int32(), C.c_int64(), C.c_int64()
+    _check(lib().hdg_batch_info(batch.handle, C.byref(nm), C.byref(ne), C.byref(nn)), "hdg_batch_info")
+    return dict(n_members=nm.value, n_elements=ne.value, n_nodes=nn.value)
+
+
+def hdg_batch_rk3_steps(batch: Batch, nsteps: int, prec: int = HDG_F64, stream=None):
+    _check(lib().hdg_batch_rk3_steps(batch.handle, int(nsteps), prec, _stream(stream)), "hdg_batch_rk3_steps")
+
+
+def hdg_batch_set_graphs(batch: Batch, enable: bool):
+    _check(lib().hdg_batch_set_graphs(batch.handle, 1 if enable else 0), "hdg_batch_set_graphs")
+
+
+def hdg_batch_autotune(batch: Batch, reps: int = 3, stream=None):
+    _check(lib().hdg_batch_autotune(batch.handle, int(reps), _stream(stream)), "hdg_batch_autotune")
+
+
+def hdg_batch_get_launch(batch: Batch, kernel_class: int, prec: int, N: int) -> dict:
+    c = LaunchCfg()
+    _check(lib().hdg_batch_get_launch(batch.handle, kernel_class, prec, N, C.byref(c)), "hdg_batch_get_launch")
+    return dict(block=c.block, persistent=bool(c.persistent), us_per_launch=c.us_per_launch)
 
 
 def hdg_stream_copy(ctx: Context, dst, src, nbytes: int, stream=None):

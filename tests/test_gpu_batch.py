@@ -1,0 +1,156 @@
+"""Batches of independent meshes: every member's result is bitwise the result
+of the same mesh advanced on its own, whatever else is in the batch and when
+members join or leave."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2403_05463_amd import hdg, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_cuda):
+    return hdg.hdg_init(0)
+
+
+def _requests(k, seed):
+    """k small periodic-box solves with seeded size, order, mask fraction and viscosity."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(k):
+        n = int(rng.integers(3, 6))
+        P = int(rng.integers(1, 8))
+        frac = float(rng.uniform(0.2, 0.8))
+        nu = float(10 ** rng.uniform(-4, -2))
+        out.append(dict(n=n, P=P, frac=frac, nu=nu, seed=1000 * seed + i))
+    return out
+
+
+def _make(ctx, r):
+    mesh = W.periodic_box(r["n"], Pg=1)
+    flag = W.bernoulli_mask(mesh.n_elem, r["frac"], r["seed"])
+    m = hdg.hdg_mesh_create(ctx, mesh, r["P"], flag,
+                            hdg.make_params(c0sq=25.0, nu=r["nu"], les_model=1, C_les=0.1))
+    q0 = W.taylor_green_state(hdg.hdg_mesh_node_coords(m), 0.01, seed=r["seed"])
+    dt = 0.5 * W.cfl_dt(mesh, r["P"], q0, 25.0)
+    return m, q0, dt
+
+
+def _alone(torch, m, q0, dt, steps, prec):
+    q = torch.from_numpy(q0).cuda()
+    dq = torch.empty_like(q)
+    hdg.hdg_rk3_steps(m, q, dq, dt, steps, prec=prec)
+    torch.cuda.synchronize()
+    return q.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [hdg.HDG_F64, hdg.HDG_F32])
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batch_members_equal_alone(torch_cuda, ctx, prec, graphs):
+    torch = torch_cuda
+    reqs = _requests(6, seed=7 + prec)
+    made = [_make(ctx, r) for r in reqs]
+    _say(f"batch of {len(reqs)} boxes (n, P) = {[(r['n'], r['P']) for r in reqs]}, prec {prec}, graphs {graphs}")
+    alone = [_alone(torch, m, q0, dt, 5, prec) for (m, q0, dt) in made]
+    b = hdg.hdg_batch_create(ctx, 8)
+    hdg.hdg_batch_set_graphs(b, graphs)
+    qs = []
+    for (m, q0, dt) in made:
+        q = torch.from_numpy(q0).cuda()
+        dq = torch.empty_like(q)
+        hdg.hdg_batch_add(b, m, q, dq, dt)
+        qs.append(q)
+    info = hdg.hdg_batch_info(b)
+    assert info["n_members"] == len(reqs)
+    hdg.hdg_batch_rk3_steps(b, 5, prec=prec)
+    torch.cuda.synchronize()
+    for i, q in enumerate(qs):
+        assert np.array_equal(q.cpu().numpy(), alone[i]), f"member {i} differs from its solve alone"
+
+
+def test_batch_join_and_leave(torch_cuda, ctx):
+    """Members join and leave between calls (continuous batching); each one's
+    state equals its own solve advanced by the steps it was in the batch."""
+    torch = torch_cuda
+    prec = hdg.HDG_F32
+    reqs = _requests(5, seed=21)
+    made = [_make(ctx, r) for r in reqs]
+    _say(f"join/leave on boxes (n, P) = {[(r['n'], r['P']) for r in reqs]}")
+    b = hdg.hdg_batch_create(ctx, 3)
+    state = {}
+    slot_of = {}
+
+    def join(i):
+        m, q0, dt = made[i]
+        q = torch.from_numpy(q0).cuda()
+        dq = torch.empty_like(q)
+        slot_of[i] = hdg.hdg_batch_add(b, m, q, dq, dt)
+        state[i] = [q, 0]
+
+    def run(k):
+        hdg.hdg_batch_rk3_steps(b, k, prec=prec)
+        for i in slot_of:
+            state[i][1] += k
+
+    def leave(i):
+        torch.cuda.synchronize()
+        hdg.hdg_batch_remove(b, slot_of.pop(i))
+
+    join(0); join(1); join(2)
+    with pytest.raises(hdg.HdgError) as ex:          # three slots: the fourth waits
+        m, q0, dt = made[3]
+        qq = torch.from_numpy(q0).cuda()
+        hdg.hdg_batch_add(b, m, qq, torch.empty_like(qq), dt)
+    assert ex.value.status == hdg.HDG_ENOMEM
+    run(3)
+    leave(1)
+    join(3)
+    run(2)
+    leave(0)
+    join(4)
+    run(3)
+    torch.cuda.synchronize()
+    for i, (q, steps) in state.items():
+        m, q0, dt = made[i]
+        ref = _alone(torch, m, q0, dt, steps, prec)
+        assert np.array_equal(q.cpu().numpy(), ref), f"request {i} after {steps} steps"
+    with pytest.raises(hdg.HdgError) as ex:
+        hdg.hdg_batch_remove(b, 7)
+    assert ex.value.status == hdg.HDG_EINVAL
+
+
+def test_batch_autotune_keeps_results(torch_cuda, ctx):
+    torch = torch_cuda
+    reqs = _requests(4, seed=33)
+    made = [_make(ctx, r) for r in reqs]
+    b = hdg.hdg_batch_create(ctx, 4)
+    qs = []
+    for (m, q0, dt) in made:
+        q = torch.from_numpy(q0).cuda()
+        qs.append(q)
+        hdg.hdg_batch_add(b, m, q, torch.empty_like(q), dt)
+    hdg.hdg_batch_autotune(b, reps=2)
+    for (m, q0, dt), q in zip(made, qs):
+        assert np.array_equal(q.cpu().numpy(), q0)      # the states are not modified
+    hdg.hdg_batch_rk3_steps(b, 2, prec=hdg.HDG_F64)
+    torch.cuda.synchronize()
+    for i, (m, q0, dt) in enumerate(made):
+        assert np.array_equal(qs[i].cpu().numpy(), _alone(torch, m, q0, dt, 2, hdg.HDG_F64))
+    c = hdg.hdg_batch_get_launch(b, hdg.HDG_KERNEL_RESIDUAL, hdg.HDG_F64, reqs[0]["P"] + 1)
+    assert c["us_per_launch"] > 0
