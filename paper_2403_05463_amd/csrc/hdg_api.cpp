@@ -25,6 +25,12 @@ thread_local std::string g_err;
 
 namespace hdg {
 
+std::mutex &device_mutex()
+{
+    static std::mutex mu;
+    return mu;
+}
+
 hdg_status set_error(hdg_status s, const std::string &msg)
 {
     g_err = msg;
@@ -440,6 +446,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     m->order = hdg::locality_order(*d);
     m->nblocks_reduce = (int)std::min<int64_t>(1024, (ne * N3 + 255) / 256);
 
+    std::lock_guard<std::mutex> device_lock(hdg::device_mutex());
     hdg_status s2 = HDG_OK;
     auto chk = [&](hdg_status s) { if (s2 == HDG_OK) s2 = s; };
     chk(dev_alloc(m, &m->metric, metric.size()));
@@ -515,6 +522,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
 void hdg_mesh_destroy(hdg_mesh *m)
 {
     if (!m) return;
+    std::lock_guard<std::mutex> device_lock(hdg::device_mutex());
     (void)hipSetDevice(m->ctx->device);
     (void)hipDeviceSynchronize();
     free_device(m);
@@ -623,6 +631,7 @@ hdg_status hdg_rk3_steps(hdg_mesh *m, double *q, double *dq, double dt, int32_t 
                         (void)grid_for(m, *pl, kind, Epi::RkStage, f32, cf.persistent);
                 }
             (void)hipGetLastError();
+            std::lock_guard<std::mutex> device_lock(hdg::device_mutex());
             HDG_HIP(hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal));
             double *cur = q, *nxt = m->qpp;
             hdg_status r = one_step(cur, nxt, m->cap);

@@ -291,6 +291,7 @@ hdg_status hdg_batch_rk3_steps(hdg_batch *b, int32_t nsteps, hdg_prec prec, void
                         (void)hdg::launch_grid(*pl, kind, Epi::RkStage, f32, cf.persistent, b->ctx->n_cu);
                 }
             (void)hipGetLastError();
+            std::lock_guard<std::mutex> device_lock(hdg::device_mutex());
             HDG_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
             hdg_status r = batch_steps(b, 2, f32, b->cap);
             hipGraph_t g = nullptr;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -70,6 +71,11 @@ inline void cut_tiles(const std::vector<int32_t> &order, const std::vector<int> 
 
 constexpr int kBlocks[3] = {128, 256, 512};
 constexpr int kMaxEvents = 65536;
+
+// Held while a HIP graph is captured and while a mesh allocates, uploads or
+// frees device memory: those calls, made from another thread during a
+// capture, invalidate it.
+std::mutex &device_mutex();
 
 // Set the thread's last-error message and return s.
 hdg_status set_error(hdg_status s, const std::string &msg);
