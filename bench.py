@@ -77,6 +77,62 @@ def cpu_baseline(w, q0, budget_s: float = 12.0) -> dict:
             "sample": f"{evals} full residual evaluations of the same workload ({nodes} nodes), {el:.1f} s"}
 
 
+def serving_leg(ctx, args, torch, hdg) -> dict:
+    """Request stream: Poisson arrivals of independent periodic-box solves (n^3
+    elements, n uniform in 4..24, P uniform in 2..6, 20-80 % viscous, nu in
+    [1e-4, 1e-2], 50 RK steps each, FP32 residual with FP64 state), admitted by
+    device footprint into one continuously refilled batch.  Then, on a fixed
+    set of those solves, batched stepping against stepping each mesh on its
+    own (plain) for the same RK steps."""
+    from paper_2403_05463_amd import serving as S
+    reqs = S.make_requests(args.serve_requests, rate=args.serve_rate, seed=0)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    print(f"[bench] serving {len(reqs)} requests at {args.serve_rate}/s", file=sys.stderr, flush=True)
+    be = S.HdgBackend(ctx, max_members=64, prec=hdg.HDG_F32, torch=torch)
+    st = S.serve(reqs, be, mem_budget=budget, max_members=64, max_steps_per_call=10, setup_workers=8)
+    res = st.summary()
+    res.update({"all_finite": all(bool(r.result) for r in st.requests),
+                "config": {"requests": len(reqs), "rate_per_s": args.serve_rate, "n": "U{4..24}", "P": "U{2..6}",
+                           "viscous_fraction": "U[0.2, 0.8]", "nu": "U[1e-4, 1e-2]", "rk_steps": 50,
+                           "memory_budget_bytes": budget, "slots": 64, "steps_per_batch_call": 10,
+                           "prec": "f32 residual, f64 state"}})
+    del be, st
+    # batched vs plain on a fixed set of solves (already resident)
+    fixed = S.make_requests(32, rate=1.0, seed=1)
+    be = S.HdgBackend(ctx, max_members=32, prec=hdg.HDG_F32, torch=torch)
+    solves = [be.make_alone(r) for r in fixed]
+    nodes = sum(m.n_elem * m.N3 for (m, _, _, _) in solves)
+    steps = 10
+    stream = torch.cuda.current_stream()
+    for (m, q, dq, dt) in solves:
+        hdg.hdg_rk3_steps(m, q, dq, dt, 2, prec=hdg.HDG_F32, stream=stream)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for (m, q, dq, dt) in solves:
+        hdg.hdg_rk3_steps(m, q, dq, dt, steps, prec=hdg.HDG_F32, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = t0.elapsed_time(t1)
+    b = hdg.hdg_batch_create(ctx, len(solves))
+    for (m, q, dq, dt) in solves:
+        hdg.hdg_batch_add(b, m, q, dq, dt)
+    hdg.hdg_batch_autotune(b, reps=2, stream=stream)
+    hdg.hdg_batch_rk3_steps(b, 2, prec=hdg.HDG_F32, stream=stream)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    hdg.hdg_batch_rk3_steps(b, steps, prec=hdg.HDG_F32, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = t0.elapsed_time(t1)
+    dof = nodes * 4 * 3 * steps
+    res["batched_vs_plain"] = {"solves": len(solves), "nodes": nodes, "rk_steps": steps,
+                               "plain_f32_value": dof / (plain_ms / 1e3), "batched_f32_value": dof / (batch_ms / 1e3),
+                               "speedup": plain_ms / batch_ms, "unit": "DOF-residual evals/s"}
+    return res
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +141,10 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-mb", type=int, default=1024, help="size of the stream-copy probe")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-stream leg")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -207,6 +267,9 @@ def main(argv=None) -> int:
                          "speedup_vs_fp64": ms / ms32, "state_finite": bool(red32["finite"]),
                          "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern32.items()},
                          "roofline": roofline(kern32, True), "dtype": "f32 residual, f64 state"}
+    del q, dq
+    if not args.no_serving:
+        out["serving"] = serving_leg(ctx, args, torch, hdg)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, q0, args.cpu_seconds)
