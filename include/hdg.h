@@ -203,7 +203,8 @@ typedef struct {
  * fused RK stage reading q_dev (device state, not modified) and keeps the
  * fastest.  Allocates a scratch register for the duration of the call and
  * writes the mesh's internal ping-pong state; synchronises the stream.
- * Default without tuning: block 512, persistent. */
+ * Default without tuning: the smallest block that fits an element, one
+ * workgroup per tile. */
 hdg_status hdg_mesh_autotune(hdg_mesh *mesh, const double *q_dev, int32_t reps, void *stream);
 hdg_status hdg_mesh_get_launch(const hdg_mesh *mesh, int32_t kernel_class, hdg_prec prec, int32_t N,
                                hdg_launch_cfg *out);

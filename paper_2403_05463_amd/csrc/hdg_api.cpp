@@ -247,8 +247,8 @@ hdg_status launch_one(hdg_mesh *m, int kind, int N, const LaunchCfg &cf, const d
     a.first_stage = first ? 1 : 0;
     const int grid = grid_for(m, *pl, kind, epi, f32, cf.persistent);
     auto go = [&] {
-        return kind == hdg::kTileViscous ? hdg::launch_viscous(N, pl->B, f32, a, grid, s)
-                                         : hdg::launch_residual(N, pl->B, epi, f32, a, grid, s);
+        return kind == hdg::kTileViscous ? hdg::launch_viscous(N, pl->B, f32, cf.persistent, a, grid, s)
+                                         : hdg::launch_residual(N, pl->B, epi, f32, cf.persistent, a, grid, s);
     };
     if (time_it) return timed(m, kind == hdg::kTileViscous ? HDG_KERNEL_VISCOUS : HDG_KERNEL_RESIDUAL, s, go);
     (void)hipGetLastError();
@@ -386,6 +386,9 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     m->N3 = m->N2 * m->N;
     m->prm = *params;
     m->inv_wend = 1.0 / g.w[0];
+    for (auto &kc : m->cfg)
+        for (auto &pc : kc)
+            for (int n = 2; n <= hdg::kMaxN; ++n) pc[n] = hdg::default_cfg(n);
     m->flag.assign(d->flag, d->flag + ne);
     for (auto &f : m->flag) f = f ? 1 : 0;
     const int N = m->N, N2 = m->N2, N3 = m->N3;
@@ -462,8 +465,6 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(dev_alloc(m, &m->final13, 13));
     chk(dev_alloc(m, &m->conn, conn.size()));
     chk(dev_alloc(m, &m->flag_d, (size_t)ne));
-    chk(dev_alloc(m, &m->eoff, (size_t)ne));
-    chk(dev_alloc(m, &m->foff, (size_t)nf));
     chk(dev_alloc(m, &m->member, 1));
     if (s2 != HDG_OK) {
         free_device(m);
@@ -485,13 +486,6 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     }
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
     {
-        std::vector<int64_t> eo(ne), fo(nf);
-        for (int64_t e = 0; e < ne; ++e) eo[e] = e * N3;
-        for (int64_t f = 0; f < nf; ++f) fo[f] = f * N2;
-        chk(up(m->eoff, eo.data(), eo.size() * 8));
-        chk(up(m->foff, fo.data(), fo.size() * 8));
-    }
-    {
         Member &mb = m->host_member;
         mb = Member{};
         mb.qA = nullptr;
@@ -505,8 +499,8 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         mb.conn = m->conn;
         mb.flag = m->flag_d;
         mb.delta = m->delta;
-        mb.eoff = m->eoff;
-        mb.foff = m->foff;
+        mb.eoff = nullptr;        // one order: offsets are e N^3 and face N^2
+        mb.foff = nullptr;
     }
     if (s2 == HDG_OK) s2 = upload_member(m);
     if (s2 == HDG_OK) s2 = upload_plans(m);

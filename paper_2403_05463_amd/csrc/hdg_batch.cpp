@@ -127,8 +127,8 @@ hdg_status batch_stage(hdg_batch *b, bool f32, double A, double B, bool first, i
             a.parity = parity;
             const int grid = hdg::launch_grid(*pl, kind, Epi::RkStage, f32, cf.persistent, b->ctx->n_cu);
             (void)hipGetLastError();
-            hipError_t e = kind == hdg::kTileViscous ? hdg::launch_viscous(N, pl->B, f32, a, grid, s)
-                                                     : hdg::launch_residual(N, pl->B, Epi::RkStage, f32, a, grid, s);
+            hipError_t e = kind == hdg::kTileViscous ? hdg::launch_viscous(N, pl->B, f32, cf.persistent, a, grid, s)
+                                                     : hdg::launch_residual(N, pl->B, Epi::RkStage, f32, cf.persistent, a, grid, s);
             if (e != hipSuccess) return fail(HDG_EHIP, std::string("batch kernel launch: ") + hipGetErrorString(e));
         }
     return HDG_OK;
@@ -171,7 +171,7 @@ hdg_status hdg_batch_create(hdg_ctx *ctx, int32_t max_members, hdg_batch **out)
     b->slots.resize(max_members);
     for (auto &kc : b->cfg)
         for (auto &pc : kc)
-            for (int N = 0; N <= hdg::kMaxN; ++N) pc[N] = LaunchCfg{};
+            for (int N = 2; N <= hdg::kMaxN; ++N) pc[N] = hdg::default_cfg(N);
     hipError_t e = hipMalloc((void **)&b->members, sizeof(Member) * max_members);
     if (e != hipSuccess) {
         delete b;
@@ -376,8 +376,9 @@ hdg_status hdg_batch_autotune(hdg_batch *b, int32_t reps, void *stream)
                         auto once = [&]() -> hdg_status {
                             (void)hipGetLastError();
                             hipError_t e = kind == hdg::kTileViscous
-                                               ? hdg::launch_viscous(N, B, pi == 1, a, grid, s)
-                                               : hdg::launch_residual(N, B, Epi::RkStage, pi == 1, a, grid, s);
+                                               ? hdg::launch_viscous(N, B, pi == 1, pers != 0, a, grid, s)
+                                               : hdg::launch_residual(N, B, Epi::RkStage, pi == 1, pers != 0, a, grid,
+                                                                      s);
                             return e == hipSuccess ? HDG_OK : fail(HDG_EHIP, std::string("autotune launch: ") +
                                                                                  hipGetErrorString(e));
                         };

@@ -70,6 +70,20 @@ inline void cut_tiles(const std::vector<int32_t> &order, const std::vector<int> 
 
 
 constexpr int kBlocks[3] = {128, 256, 512};
+
+// Untuned launch configuration of order N: the smallest workgroup that fits
+// an element, one workgroup per tile.
+inline LaunchCfg default_cfg(int N)
+{
+    LaunchCfg c;
+    for (int B : kBlocks)
+        if (tile_ept(N, B, kTileViscous) > 0 && tile_ept(N, B, kTileResidual) > 0) {
+            c.B = B;
+            break;
+        }
+    c.persistent = false;
+    return c;
+}
 constexpr int kMaxEvents = 65536;
 
 // Held while a HIP graph is captured and while a mesh allocates, uploads or

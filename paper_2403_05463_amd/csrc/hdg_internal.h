@@ -76,8 +76,8 @@ struct Member {
     const FaceRef *conn;    // [e][6]
     const uint8_t *flag;    // [e]
     const double *delta;    // [e] LES filter width
-    const int64_t *eoff;    // [e] first node of the element
-    const int64_t *foff;    // [face] first face node of the face
+    const int64_t *eoff;    // [e] first node of the element; NULL: e N^3 (one order)
+    const int64_t *foff;    // [face] first face node of the face; NULL: face N^2
     double c0sq, nu, C_les, dt;
     double qinf[4];
     int32_t les_model, mixed_face;
@@ -110,11 +110,13 @@ constexpr int kDTableSize = d_offset(kMaxN + 1);
 
 enum class Epi : int { Residual = 0, RkStage = 1 };
 
-// Kernel launchers (hdg_kernels.hip): one persistent kernel per (kind, order
-// N, workgroup size B), over a tile list of order-N tiles; grid of `grid`
-// workgroups (a multiple of kXcd).  Return hipSuccess or the launch error.
-hipError_t launch_viscous(int N, int B, bool f32, const StageArgs &a, int grid, hipStream_t s);
-hipError_t launch_residual(int N, int B, Epi epi, bool f32, const StageArgs &a, int grid, hipStream_t s);
+// Kernel launchers (hdg_kernels.hip): one kernel per (kind, order N,
+// workgroup size B, persistence) over a tile list of order-N tiles; grid of
+// `grid` workgroups, a multiple of kXcd (non-persistent: kXcd * chunk or
+// more).  Return hipSuccess or the launch error.
+hipError_t launch_viscous(int N, int B, bool f32, bool persistent, const StageArgs &a, int grid, hipStream_t s);
+hipError_t launch_residual(int N, int B, Epi epi, bool f32, bool persistent, const StageArgs &a, int grid,
+                           hipStream_t s);
 // Resident workgroups per CU of a kernel configuration (occupancy query).
 int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32);
 // Whether kernels are instantiated for order N with workgroup size B.

@@ -108,6 +108,21 @@ __device__ __forceinline__ gmem<P> *gp(P *p)
     return (gmem<P> *)p;
 }
 
+// First node of element e and first face node of face f: tables for meshes
+// of mixed order, plain products when every element has order N (the
+// tables are then absent and no dependent load sits on the address path).
+template <int N>
+__device__ __forceinline__ int64_t elem_off(const Member &M, int e)
+{
+    return M.eoff ? gp(M.eoff)[e] : (int64_t)e * (N * N * N);
+}
+
+template <int N>
+__device__ __forceinline__ int64_t face_off(const Member &M, int f)
+{
+    return M.foff ? gp(M.foff)[f] : (int64_t)f * (N * N);
+}
+
 __device__ __forceinline__ FaceRef load_face(const FaceRef *conn, size_t i)
 {
     const gmem<const int32_t> *p = gp((const int32_t *)conn) + 4 * i;
@@ -169,7 +184,7 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     c.j = (c.t / N) % N;
     c.k = c.t / N2;
     c.e = A.elems[tl.first + c.s];
-    c.eo = gp(M.eoff)[c.e];
+    c.eo = elem_off<N>(M, c.e);
     const T *Dm = dtable<T>(A) + d_offset(N);
     for (int x = c.tid; x < N2; x += blockDim.x) sD[x] = Dm[x];
     c.qin = gp((const double *)(A.q_in ? A.q_in : (A.parity ? M.qB : M.qA)));
@@ -201,12 +216,12 @@ struct FaceTask {
     int s, e, f, fa, fb;
 };
 
-template <int N>
+template <int N, int EPT>
 __device__ __forceinline__ FaceTask<N> face_task(const StageArgs &A, const Tile &tl, int task)
 {
     constexpr int N2 = Shape<N>::N2, NFT = 6 * N2;
     FaceTask<N> ft;
-    ft.s = task / NFT;
+    ft.s = EPT == 1 ? 0 : task / NFT;       // one element: its id stays uniform
     const int r = task - ft.s * NFT;
     ft.f = r / N2;
     const int fn = r - ft.f * N2;
@@ -249,16 +264,16 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
     }
 #pragma unroll 1
     for (int task = c.tid; task < NTASK; task += blockDim.x) {
-        const FaceTask<N> ft = face_task<N>(A, tl, task);
+        const FaceTask<N> ft = face_task<N, EPT>(A, tl, task);
         if (ft.s < tl.count) {
             // u* - u = (u_other - u) / 2, formed in FP64
             const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
-            const gmem<const double> *qm = c.qin + 4 * gp(M.eoff)[ft.e] + face_node<N>(ft.f, ft.fa, ft.fb);
+            const gmem<const double> *qm = c.qin + 4 * elem_off<N>(M, ft.e) + face_node<N>(ft.f, ft.fa, ft.fb);
             double uo[3];
             if (fr.nbr >= 0) {
                 int a2, b2;
                 orient_map<N>(fr.code & 7, ft.fa, ft.fb, a2, b2);
-                const gmem<const double> *qn = c.qin + 4 * gp(M.eoff)[fr.nbr] + face_node<N>((fr.code >> 3) & 7, a2, b2);
+                const gmem<const double> *qn = c.qin + 4 * elem_off<N>(M, fr.nbr) + face_node<N>((fr.code >> 3) & 7, a2, b2);
 #pragma unroll
                 for (int r = 0; r < 3; ++r) uo[r] = qn[(1 + r) * N3];
             } else {
@@ -373,13 +388,13 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
     gmem<T> *fvt = gp((T *)M.fvt);
 #pragma unroll 1
     for (int task = c.tid; task < NTASK; task += blockDim.x) {
-        const FaceTask<N> ft = face_task<N>(A, tl, task);
+        const FaceTask<N> ft = face_task<N, EPT>(A, tl, task);
         if (ft.s < tl.count) {
             const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
             const bool own = fr.code & kOwnerBit;
             int oa = ft.fa, ob = ft.fb;
             if (!own) orient_map<N>(fr.code & 7, ft.fa, ft.fb, oa, ob);
-            gmem<T> *out = fvt + 6 * gp(M.foff)[fr.face] + (own ? 0 : 3 * N2) + oa + N * ob;
+            gmem<T> *out = fvt + 6 * face_off<N>(M, fr.face) + (own ? 0 : 3 * N2) + oa + N * ob;
 #pragma unroll
             for (int r = 0; r < 3; ++r) out[r * N2] = sfu[r * NTASK + task];
         }
@@ -404,7 +419,7 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
     const FaceRef fr = load_face(M.conn, (size_t)e * 6 + f);
     const bool own = fr.code & kOwnerBit;
-    const gmem<const double> *qe = qin + 4 * gp(M.eoff)[e] + face_node<N>(f, fa, fb);
+    const gmem<const double> *qe = qin + 4 * elem_off<N>(M, e) + face_node<N>(f, fa, fb);
     double qm[4], qo[4];
 #pragma unroll
     for (int x = 0; x < 4; ++x) qm[x] = qe[x * N3];
@@ -413,7 +428,7 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
         int a2, b2;
         orient_map<N>(fr.code & 7, fa, fb, a2, b2);
         if (!own) { oa = a2; ob = b2; }
-        const gmem<const double> *qn = qin + 4 * gp(M.eoff)[fr.nbr] + face_node<N>((fr.code >> 3) & 7, a2, b2);
+        const gmem<const double> *qn = qin + 4 * elem_off<N>(M, fr.nbr) + face_node<N>((fr.code >> 3) & 7, a2, b2);
 #pragma unroll
         for (int x = 0; x < 4; ++x) qo[x] = qn[x * N3];
     } else if (fr.nbr == HDG_WALL) {
@@ -425,7 +440,7 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
         for (int x = 0; x < 4; ++x) qo[x] = M.qinf[x];
     }
     const int fnode = oa + N * ob;
-    const gmem<const T> *g = gp((const T *)M.fgeo[prec_index<T>()]) + 4 * (gp(M.foff)[fr.face] + fnode);
+    const gmem<const T> *g = gp((const T *)M.fgeo[prec_index<T>()]) + 4 * (face_off<N>(M, fr.face) + fnode);
     const T n[3] = {g[0], g[1], g[2]};
     const T sc = g[3];
     T uL[3], du[3];
@@ -465,7 +480,7 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
         // BR1: mean of the two sides' viscous traces (an Euler side contributes
         // zero); a boundary face takes the interior trace.  F* carries -F_v*.
         const bool keep = fr.nbr < 0 || M.mixed_face == 0 || (visL && visR);
-        const gmem<const T> *tv = gp((const T *)M.fvt) + 6 * gp(M.foff)[fr.face] + fnode;
+        const gmem<const T> *tv = gp((const T *)M.fvt) + 6 * face_off<N>(M, fr.face) + fnode;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const T tL = visL ? tv[r * N2] : T(0);
@@ -476,7 +491,7 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
     }
 }
 
-template <int N, int EPT, int EPI, class T>
+template <int N, int EPT, int EPI, class T, bool UNROLL>
 __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl, char *smem)
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
@@ -515,7 +530,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     // share one equation class
 #pragma unroll 1
     for (int task = c.tid; task < NTASK; task += blockDim.x) {
-        const FaceTask<N> ft = face_task<N>(A, tl, task);
+        const FaceTask<N> ft = face_task<N, EPT>(A, tl, task);
         if (ft.s < tl.count) {
             T F[4];
             face_jump<N, T>(M, c.qin, c.c0sq, ft.e, visc, ft.f, ft.fa, ft.fb, F);
@@ -534,18 +549,39 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     }
     __syncthreads();
 
-    // reference divergence (a rolled loop: unrolled, the scheduler hoists all
-    // 12 N LDS reads and doubles the register count)
+    // reference divergence.  Inside the persistent tile loop the contraction
+    // stays rolled: unrolled there, the scheduler hoists all 12 N LDS reads
+    // and doubles the register count.  A workgroup that takes one tile
+    // unrolls it with the D rows in registers.
     const int base = c.s * N3;
     T V[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll 1
-    for (int m = 0; m < N; ++m) {
-        const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
-                  n2 = base + c.i + N * c.j + N2 * m;
-        const T dx = sD[c.i * N + m], dy = sD[c.j * N + m], dz = sD[c.k * N + m];
+    if constexpr (UNROLL) {
+        T Dx[N], Dy[N], Dz[N];
 #pragma unroll
-        for (int row = 0; row < 4; ++row)
-            V[row] += dx * lds[row * NN + n0] + dy * lds[(4 + row) * NN + n1] + dz * lds[(8 + row) * NN + n2];
+        for (int m = 0; m < N; ++m) {
+            Dx[m] = sD[c.i * N + m];
+            Dy[m] = sD[c.j * N + m];
+            Dz[m] = sD[c.k * N + m];
+        }
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
+                      n2 = base + c.i + N * c.j + N2 * m;
+#pragma unroll
+            for (int row = 0; row < 4; ++row)
+                V[row] += Dx[m] * lds[row * NN + n0] + Dy[m] * lds[(4 + row) * NN + n1] +
+                          Dz[m] * lds[(8 + row) * NN + n2];
+        }
+    } else {
+#pragma unroll 1
+        for (int m = 0; m < N; ++m) {
+            const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
+                      n2 = base + c.i + N * c.j + N2 * m;
+            const T dx = sD[c.i * N + m], dy = sD[c.j * N + m], dz = sD[c.k * N + m];
+#pragma unroll
+            for (int row = 0; row < 4; ++row)
+                V[row] += dx * lds[row * NN + n0] + dy * lds[(4 + row) * NN + n1] + dz * lds[(8 + row) * NN + n2];
+        }
     }
 
     // face nodes: numerical flux minus own flux, over w_end
@@ -588,41 +624,58 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     }
 }
 
-// Persistent tile loop: the grid is a multiple of kXcd; workgroup b runs on
-// XCD b mod kXcd (round-robin dispatch) and walks that XCD's contiguous chunk
-// of the (spatially ordered) tile list, so neighbour traces hit its L2.
+// Tile assignment: the grid is a multiple of kXcd; workgroup b runs on XCD
+// b mod kXcd (round-robin dispatch) and takes tiles from that XCD's
+// contiguous chunk of the (spatially ordered) tile list, so neighbour traces
+// hit its L2.  Persistent launches walk the chunk; otherwise the grid is
+// kXcd * chunk and every workgroup takes exactly one tile.
 #define HDG_TILE_LOOP(A, tl)                                                                   \
     const int xcd_ = blockIdx.x % kXcd, loc_ = blockIdx.x / kXcd, nloc_ = gridDim.x / kXcd;   \
     for (int i_ = loc_; i_ < (A).chunk; i_ += nloc_)                                           \
         if (const int ti_ = xcd_ * (A).chunk + i_; ti_ < (A).ntiles)                            \
             if (const Tile tl = (A).tiles[ti_]; true)
 
-// One persistent kernel per (kind, order, workgroup size): a single kernel
+#define HDG_ONE_TILE(A, tl)                                                                    \
+    const int xcd_ = blockIdx.x % kXcd, loc_ = blockIdx.x / kXcd;                              \
+    if (const int ti_ = xcd_ * (A).chunk + loc_; loc_ < (A).chunk && ti_ < (A).ntiles)          \
+        if (const Tile tl = (A).tiles[ti_]; true)
+
+// One kernel per (kind, order, workgroup size, persistence): a single kernel
 // over every order would carry the register demand of all of them at once
-// (measured: about 1.7x the largest single order), halving occupancy.
-template <class T, int N, int B>
+// (measured: about 1.7x the largest single order), halving occupancy; and a
+// loop around the tile body alone costs the unrolled contraction twice its
+// registers, so only persistent launches loop.
+template <class T, int N, int B, bool PERS>
 __global__ __launch_bounds__(B) void k_viscous(StageArgs A)
 {
     constexpr int EPT = tile_ept(N, B, kTileViscous);
     static_assert(EPT > 0, "tile does not fit the workgroup");
     constexpr int N2 = N * N, NN = EPT * N * N2, NTASK = EPT * 6 * N2;
     __shared__ __attribute__((aligned(16))) char smem[(12 * NN + 3 * NTASK + N2) * sizeof(T)];
-    HDG_TILE_LOOP(A, tl) {
-        viscous_tile<N, EPT, T>(A, tl, smem);
-        __syncthreads();
+    if constexpr (PERS) {
+        HDG_TILE_LOOP(A, tl) {
+            viscous_tile<N, EPT, T>(A, tl, smem);
+            __syncthreads();
+        }
+    } else {
+        HDG_ONE_TILE(A, tl) viscous_tile<N, EPT, T>(A, tl, smem);
     }
 }
 
-template <class T, int EPI, int N, int B>
+template <class T, int EPI, int N, int B, bool PERS>
 __global__ __launch_bounds__(B) void k_residual(StageArgs A)
 {
     constexpr int EPT = tile_ept(N, B, kTileResidual);
     static_assert(EPT > 0, "tile does not fit the workgroup");
     constexpr int N2 = N * N, NN = EPT * N * N2, NTASK = EPT * 6 * N2;
     __shared__ __attribute__((aligned(16))) char smem[(12 * NN + 4 * NTASK + N2) * sizeof(T)];
-    HDG_TILE_LOOP(A, tl) {
-        residual_tile<N, EPT, EPI, T>(A, tl, smem);
-        __syncthreads();
+    if constexpr (PERS) {
+        HDG_TILE_LOOP(A, tl) {
+            residual_tile<N, EPT, EPI, T, false>(A, tl, smem);
+            __syncthreads();
+        }
+    } else {
+        HDG_ONE_TILE(A, tl) residual_tile<N, EPT, EPI, T, true>(A, tl, smem);
     }
 }
 
@@ -757,38 +810,58 @@ hipError_t by_shape(int N, int B, F f)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_viscous(int N, int B, bool f32, const StageArgs &a, int grid, hipStream_t s)
+// Grid check: a non-persistent launch must cover every tile with one workgroup.
+bool grid_ok(const StageArgs &a, int grid, bool pers)
+{
+    if (grid <= 0 || grid % kXcd) return false;
+    return pers || grid / kXcd >= a.chunk;
+}
+
+hipError_t launch_viscous(int N, int B, bool f32, bool pers, const StageArgs &a, int grid, hipStream_t s)
 {
     if (a.ntiles == 0) return hipSuccess;
-    if (grid <= 0 || grid % kXcd) return hipErrorInvalidValue;
+    if (!grid_ok(a, grid, pers)) return hipErrorInvalidValue;
     return by_shape(N, B, [&](auto nc, auto bc) {
         constexpr int NN = decltype(nc)::value, BB = decltype(bc)::value;
-        if (f32) hipLaunchKernelGGL((k_viscous<float, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
-        else hipLaunchKernelGGL((k_viscous<double, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
+        if (f32) {
+            if (pers) hipLaunchKernelGGL((k_viscous<float, NN, BB, true>), dim3(grid), dim3(BB), 0, s, a);
+            else hipLaunchKernelGGL((k_viscous<float, NN, BB, false>), dim3(grid), dim3(BB), 0, s, a);
+        } else {
+            if (pers) hipLaunchKernelGGL((k_viscous<double, NN, BB, true>), dim3(grid), dim3(BB), 0, s, a);
+            else hipLaunchKernelGGL((k_viscous<double, NN, BB, false>), dim3(grid), dim3(BB), 0, s, a);
+        }
         return hipGetLastError();
     });
 }
 
-hipError_t launch_residual(int N, int B, Epi epi, bool f32, const StageArgs &a, int grid, hipStream_t s)
+template <class T, int NN, int BB>
+void launch_residual_t(Epi epi, bool pers, const StageArgs &a, int grid, hipStream_t s)
+{
+    if (epi == Epi::Residual) {
+        if (pers) hipLaunchKernelGGL((k_residual<T, 0, NN, BB, true>), dim3(grid), dim3(BB), 0, s, a);
+        else hipLaunchKernelGGL((k_residual<T, 0, NN, BB, false>), dim3(grid), dim3(BB), 0, s, a);
+    } else {
+        if (pers) hipLaunchKernelGGL((k_residual<T, 1, NN, BB, true>), dim3(grid), dim3(BB), 0, s, a);
+        else hipLaunchKernelGGL((k_residual<T, 1, NN, BB, false>), dim3(grid), dim3(BB), 0, s, a);
+    }
+}
+
+hipError_t launch_residual(int N, int B, Epi epi, bool f32, bool pers, const StageArgs &a, int grid, hipStream_t s)
 {
     if (a.ntiles == 0) return hipSuccess;
-    if (grid <= 0 || grid % kXcd) return hipErrorInvalidValue;
+    if (!grid_ok(a, grid, pers)) return hipErrorInvalidValue;
     return by_shape(N, B, [&](auto nc, auto bc) {
         constexpr int NN = decltype(nc)::value, BB = decltype(bc)::value;
-        if (f32) {
-            if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<float, 0, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
-            else hipLaunchKernelGGL((k_residual<float, 1, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
-        } else {
-            if (epi == Epi::Residual) hipLaunchKernelGGL((k_residual<double, 0, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
-            else hipLaunchKernelGGL((k_residual<double, 1, NN, BB>), dim3(grid), dim3(BB), 0, s, a);
-        }
+        if (f32) launch_residual_t<float, NN, BB>(epi, pers, a, grid, s);
+        else launch_residual_t<double, NN, BB>(epi, pers, a, grid, s);
         return hipGetLastError();
     });
 }
 
 int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32)
 {
-    // occupancy does not change at run time: query each configuration once
+    // occupancy of the persistent kernels; it does not change at run time:
+    // query each configuration once
     static int cache[2][kMaxN + 1][3][2][2] = {};
     int &slot = cache[kind & 1][N][B <= 128 ? 0 : B <= 256 ? 1 : 2][(int)epi & 1][f32];
     if (slot > 0) return slot;
@@ -797,11 +870,13 @@ int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32)
         constexpr int NN = decltype(nc)::value, BB = decltype(bc)::value;
         const void *fn = nullptr;
         if (kind == kTileViscous)
-            fn = f32 ? (const void *)k_viscous<float, NN, BB> : (const void *)k_viscous<double, NN, BB>;
+            fn = f32 ? (const void *)k_viscous<float, NN, BB, true> : (const void *)k_viscous<double, NN, BB, true>;
         else if (f32)
-            fn = epi == Epi::Residual ? (const void *)k_residual<float, 0, NN, BB> : (const void *)k_residual<float, 1, NN, BB>;
+            fn = epi == Epi::Residual ? (const void *)k_residual<float, 0, NN, BB, true>
+                                      : (const void *)k_residual<float, 1, NN, BB, true>;
         else
-            fn = epi == Epi::Residual ? (const void *)k_residual<double, 0, NN, BB> : (const void *)k_residual<double, 1, NN, BB>;
+            fn = epi == Epi::Residual ? (const void *)k_residual<double, 0, NN, BB, true>
+                                      : (const void *)k_residual<double, 1, NN, BB, true>;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, BB, 0);
     });
     slot = e == hipSuccess && n > 0 ? n : 1;
