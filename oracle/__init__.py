@@ -57,6 +57,11 @@ def lib():
         L.orc_mesh_new.restype = C.c_void_p
         L.orc_mesh_new.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.POINTER(C.c_int),
                                    C.POINTER(C.c_byte), C.POINTER(C.c_byte), C.POINTER(C.c_ubyte)]
+        L.orc_mesh_new_mixed.restype = C.c_void_p
+        L.orc_mesh_new_mixed.argtypes = [C.c_int, C.POINTER(C.c_int), C.c_int, dp, C.POINTER(C.c_int),
+                                         C.POINTER(C.c_byte), C.POINTER(C.c_byte), C.POINTER(C.c_ubyte)]
+        L.orc_mesh_nodes.restype = C.c_size_t
+        L.orc_mesh_nodes.argtypes = [C.c_void_p]
         L.orc_mesh_free.argtypes = [C.c_void_p]
         L.orc_last_error.restype = C.c_char_p
         L.orc_set_flags.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte)]
@@ -123,26 +128,40 @@ def get_threads() -> int:
 
 
 class OracleMesh:
-    """An oracle-side mesh: geometry, metrics and connectivity in FP64 host memory."""
+    """An oracle-side mesh: geometry, metrics and connectivity in FP64 host memory.
 
-    def __init__(self, mesh, P: int, flag):
-        self.P, self.N = P, P + 1
-        self.N3 = self.N ** 3
+    ``P`` is one order for every element, or one per element.  With one order,
+    arrays have shape (n_elem, fields, N^3); with several, they are flat,
+    element after element ([fields][N_e^3] each), and ``offsets`` gives each
+    element's first node."""
+
+    def __init__(self, mesh, P, flag):
+        Ps = np.broadcast_to(np.asarray(P, dtype=np.int32), (mesh.n_elem,)).copy()
+        self.Ps = Ps
+        self.uniform = bool(np.all(Ps == Ps[0]))
+        self.P = int(Ps[0]) if self.uniform else None
+        self.N = self.P + 1 if self.uniform else None
+        self.N3 = self.N ** 3 if self.uniform else None
         self.n_elem = mesh.n_elem
+        n3 = (Ps.astype(np.int64) + 1) ** 3
+        self.offsets = np.concatenate([[0], np.cumsum(n3)[:-1]])
+        self.nodes = int(n3.sum())
         self._keep = (
             np.ascontiguousarray(mesh.xyz_geom, dtype=np.float64),
             np.ascontiguousarray(mesh.nbr, dtype=np.int32),
             np.ascontiguousarray(mesh.nbr_face, dtype=np.int8),
             np.ascontiguousarray(mesh.orient, dtype=np.int8),
             np.ascontiguousarray(flag, dtype=np.uint8),
+            Ps,
         )
-        x, nb, nf, o, fl = self._keep
-        h = lib().orc_mesh_new(mesh.n_elem, P, mesh.Pg, _dp(x), nb.ctypes.data_as(C.POINTER(C.c_int)),
-                               nf.ctypes.data_as(C.POINTER(C.c_byte)), o.ctypes.data_as(C.POINTER(C.c_byte)),
-                               fl.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        x, nb, nf, o, fl, pp = self._keep
+        h = lib().orc_mesh_new_mixed(mesh.n_elem, pp.ctypes.data_as(C.POINTER(C.c_int)), mesh.Pg, _dp(x),
+                                     nb.ctypes.data_as(C.POINTER(C.c_int)), nf.ctypes.data_as(C.POINTER(C.c_byte)),
+                                     o.ctypes.data_as(C.POINTER(C.c_byte)), fl.ctypes.data_as(C.POINTER(C.c_ubyte)))
         if not h:
             raise ValueError("oracle mesh rejected: " + lib().orc_last_error().decode())
         self._h = h
+        assert lib().orc_mesh_nodes(h) == self.nodes
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -154,14 +173,25 @@ class OracleMesh:
         fl = np.ascontiguousarray(flag, dtype=np.uint8)
         lib().orc_set_flags(self._h, fl.ctypes.data_as(C.POINTER(C.c_ubyte)))
 
+    def _shape(self, fields):
+        return (self.n_elem, fields, self.N3) if self.uniform else (fields * self.nodes,)
+
+    def element(self, arr, e, fields):
+        """Element e's block [fields][N_e^3] of a flat (or uniform) array."""
+        if self.uniform:
+            return arr[e]
+        n3 = (int(self.Ps[e]) + 1) ** 3
+        o = fields * int(self.offsets[e])
+        return arr[o:o + fields * n3].reshape(fields, n3)
+
     def node_coords(self):
-        x = np.zeros((self.n_elem, 3, self.N3))
+        x = np.zeros(self._shape(3))
         lib().orc_node_coords(self._h, _dp(x))
         return x
 
     def metrics(self):
-        J = np.zeros((self.n_elem, self.N3))
-        Ja = np.zeros((self.n_elem, 3, 3, self.N3))
+        J = np.zeros(self._shape(1)) if not self.uniform else np.zeros((self.n_elem, self.N3))
+        Ja = np.zeros((self.n_elem, 3, 3, self.N3)) if self.uniform else np.zeros(9 * self.nodes)
         lib().orc_metrics(self._h, _dp(J), _dp(Ja))
         return J, Ja
 
@@ -170,13 +200,13 @@ class OracleMesh:
 
     def _chk(self, q):
         q = np.ascontiguousarray(q, dtype=np.float64)
-        if q.shape != (self.n_elem, 4, self.N3):
-            raise ValueError(f"state shape {q.shape} != {(self.n_elem, 4, self.N3)}")
+        if q.shape != self._shape(4):
+            raise ValueError(f"state shape {q.shape} != {self._shape(4)}")
         return q
 
     def gradient(self, params: Params, q):
         q = self._chk(q)
-        G = np.zeros((self.n_elem, 3, 3, self.N3))
+        G = np.zeros((self.n_elem, 3, 3, self.N3)) if self.uniform else np.zeros(9 * self.nodes)
         lib().orc_gradient(self._h, C.byref(params), _dp(q), _dp(G))
         return G
 

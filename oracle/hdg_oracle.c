@@ -41,16 +41,23 @@ static char g_err[512];
 const char *orc_last_error(void) { return g_err; }
 
 struct orc_mesh {
-    int ne, P, N, N2, N3;
-    double xi[MAXN], w[MAXN], D[MAXN * MAXN];
-    double *x;      /* [e][3][N3] node coordinates */
-    double *J;      /* [e][N3] Jacobian */
-    double *Ja;     /* [e][3 (i)][3 (d)][N3] contravariant metric Ja^i_d */
+    int ne;
+    int *P;         /* [e] polynomial order */
+    size_t *off;    /* [e] first node of element e; element e holds (P_e+1)^3 nodes */
+    size_t nodes;   /* total nodes */
+    /* GLL rule of every order in use, indexed by N = P + 1 */
+    double xi[MAXN + 1][MAXN], w[MAXN + 1][MAXN], D[MAXN + 1][MAXN * MAXN];
+    double *x;      /* [e][3][N_e^3] node coordinates */
+    double *J;      /* [e][N_e^3] Jacobian */
+    double *Ja;     /* [e][3 (i)][3 (d)][N_e^3] contravariant metric Ja^i_d */
     double *delta;  /* [e] LES filter width */
     int *nbr;
     signed char *nbr_face, *orient;
     unsigned char *flag;
 };
+
+static int NE(const orc_mesh *m, int e) { return m->P[e] + 1; }
+static int N3E(const orc_mesh *m, int e) { int n = m->P[e] + 1; return n * n * n; }
 
 static int g_threads = 0;
 void orc_set_threads(int n) { g_threads = n; }
@@ -182,8 +189,9 @@ static void own_outward(const orc_mesh *m, int e, int f, int node, double v[3])
 {
     int i = f / 2;
     double sg = (f & 1) ? 1.0 : -1.0;
+    size_t n3 = N3E(m, e);
     for (int d = 0; d < 3; ++d)
-        v[d] = sg * m->Ja[(((size_t)e * 3 + i) * 3 + d) * m->N3 + node];
+        v[d] = sg * m->Ja[9 * m->off[e] + (size_t)(i * 3 + d) * n3 + node];
 }
 
 typedef struct {
@@ -192,19 +200,47 @@ typedef struct {
     int e2, f2, node2; /* partner element, face and its volume node */
 } partner_t;
 
+/* Partner of a face point on a conforming face (both sides of one order). */
 static partner_t partner(const orc_mesh *m, int e, int f, int a, int b)
 {
     partner_t p;
+    int N = NE(m, e);
     int e2 = m->nbr[e * 6 + f];
     if (e2 < 0) {
-        p.interior = 0; p.bc = e2; p.e2 = e; p.f2 = f; p.node2 = face_node(m->N, f, a, b);
+        p.interior = 0; p.bc = e2; p.e2 = e; p.f2 = f; p.node2 = face_node(N, f, a, b);
         return p;
     }
     int a2, b2;
-    orient_map(m->orient[e * 6 + f], m->N - 1, a, b, &a2, &b2);
+    orient_map(m->orient[e * 6 + f], N - 1, a, b, &a2, &b2);
     p.interior = 1; p.bc = 0; p.e2 = e2; p.f2 = m->nbr_face[e * 6 + f];
-    p.node2 = face_node(m->N, p.f2, a2, b2);
+    p.node2 = face_node(N, p.f2, a2, b2);
     return p;
+}
+
+/* A face between elements of different order (p-nonconforming) is coupled
+ * through a mortar (the paper's solver supports such faces, Sec. 2.1):
+ *  - the mortar carries the higher order M and the higher-order side's face
+ *    nodes, frame and outward normal;
+ *  - the lower-order side's trace is extended to the mortar nodes by its own
+ *    Lagrange interpolant;
+ *  - the numerical flux is evaluated once per mortar node;
+ *  - the higher-order side takes it at its nodes; the lower-order side's
+ *    surface integral of (flux x test function) is evaluated exactly on the
+ *    mortar (the M-node Gauss-Lobatto rule integrates a degree M + P_low <=
+ *    2M - 1 integrand exactly).
+ * Returns 1 if face f of e is such a face. */
+static int is_mortar(const orc_mesh *m, int e, int f)
+{
+    int e2 = m->nbr[e * 6 + f];
+    return e2 >= 0 && m->P[e2] != m->P[e];
+}
+
+/* value of the order-P Lagrange basis function k at the M-node GLL point i */
+static double interp_coef(const orc_mesh *m, int Nlo, int Nhi, int i, int k)
+{
+    xreal xl[MAXN];
+    for (int a = 0; a < Nlo; ++a) xl[a] = m->xi[Nlo][a];
+    return (double)lagrange_value(Nlo, xl, k, (xreal)m->xi[Nhi][i]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -213,9 +249,9 @@ static partner_t partner(const orc_mesh *m, int e, int f, int a, int b)
 
 static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
 {
-    int N = m->N, N3 = m->N3, G1 = Pg + 1;
+    int N = NE(m, e), N3 = N3E(m, e), G1 = Pg + 1;
     xreal xq[MAXN], wq[MAXN], Dq[MAXN * MAXN];
-    lgl_rule_x(m->P, xq, wq, Dq);
+    lgl_rule_x(m->P[e], xq, wq, Dq);
     xreal gn[MAXN];
     for (int k = 0; k < G1; ++k) gn[k] = -1.0L + 2.0L * k / Pg;
     xreal lg[MAXN][MAXN]; /* lg[a][k] = l_k^geom(xi_a) */
@@ -226,7 +262,7 @@ static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
      * the geometry is interpolated and differentiated in coordinates relative
      * to the element's first control point: round-off then stays relative to
      * the element size rather than to its distance from the origin. */
-    double *x = m->x + (size_t)e * 3 * N3;
+    double *x = m->x + 3 * m->off[e];
     xreal *xl = malloc(sizeof(xreal) * 3 * N3);
     for (int c = 0; c < 3; ++c) {
         const double *Xc = X + (size_t)c * G1 * G1 * G1;
@@ -263,7 +299,7 @@ static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
         for (int k = 0; k < 3; ++k)
             for (int n = 0; n < N3; ++n) DREF(xl + c * N3, k, n, dX[(c * 3 + k) * N3 + n]);
 
-    double *J = m->J + (size_t)e * N3;
+    double *J = m->J + m->off[e];
     xreal vol = 0.0L;
     for (int n = 0; n < N3; ++n) {
         xreal a11 = dX[(0 * 3 + 0) * N3 + n], a12 = dX[(0 * 3 + 1) * N3 + n], a13 = dX[(0 * 3 + 2) * N3 + n];
@@ -292,7 +328,7 @@ static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
             DREF(V + 0 * N3, 1, n, d1V0);
             xreal curl[3] = {d1V2 - d2V1, d2V0 - d0V2, d0V1 - d1V0};
             for (int i = 0; i < 3; ++i)
-                m->Ja[(((size_t)e * 3 + i) * 3 + nn) * N3 + n] = (double)(-curl[i]);
+                m->Ja[9 * m->off[e] + (size_t)(i * 3 + nn) * N3 + n] = (double)(-curl[i]);
         }
     }
 #undef DREF
@@ -302,15 +338,20 @@ static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
     m->delta[e] = (double)(cbrtl(vol) / N);
 }
 
-orc_mesh *orc_mesh_new(int ne, int P, int Pg, const double *xyz_geom, const int *nbr,
-                       const signed char *nbr_face, const signed char *orient,
-                       const unsigned char *flag)
+orc_mesh *orc_mesh_new_mixed(int ne, const int *P, int Pg, const double *xyz_geom, const int *nbr,
+                             const signed char *nbr_face, const signed char *orient,
+                             const unsigned char *flag)
 {
     g_err[0] = 0;
-    if (ne <= 0 || P < 1 || P > MAXN - 1 || Pg < 1 || Pg > MAXN - 1) {
-        snprintf(g_err, sizeof g_err, "bad sizes: n_elem=%d P=%d Pg=%d", ne, P, Pg);
+    if (ne <= 0 || Pg < 1 || Pg > MAXN - 1) {
+        snprintf(g_err, sizeof g_err, "bad sizes: n_elem=%d Pg=%d", ne, Pg);
         return NULL;
     }
+    for (int e = 0; e < ne; ++e)
+        if (P[e] < 1 || P[e] > MAXN - 1) {
+            snprintf(g_err, sizeof g_err, "element %d: order %d outside 1..%d", e, P[e], MAXN - 1);
+            return NULL;
+        }
     /* connectivity must be symmetric with mutually inverse orientation maps */
     for (int e = 0; e < ne; ++e)
         for (int f = 0; f < 6; ++f) {
@@ -344,13 +385,34 @@ orc_mesh *orc_mesh_new(int ne, int P, int Pg, const double *xyz_geom, const int 
                 }
         }
 
+    /* mortar faces need geometry the lower order represents exactly: the
+     * curl-form metric terms of a degree-Pg map have degree 2 Pg per face
+     * direction */
+    for (int e = 0; e < ne; ++e)
+        for (int f = 0; f < 6; ++f) {
+            int e2 = nbr[e * 6 + f];
+            if (e2 >= 0 && P[e2] != P[e]) {
+                int plo = P[e] < P[e2] ? P[e] : P[e2];
+                if (2 * Pg > plo) {
+                    snprintf(g_err, sizeof g_err,
+                             "element %d face %d: orders %d/%d need geometry order <= %d", e, f, P[e], P[e2], plo / 2);
+                    return NULL;
+                }
+            }
+        }
+
     orc_mesh *m = calloc(1, sizeof *m);
-    m->ne = ne; m->P = P; m->N = P + 1; m->N2 = m->N * m->N; m->N3 = m->N2 * m->N;
-    orc_lgl(P, m->xi, m->w, m->D);
-    size_t N3 = m->N3;
-    m->x = malloc(sizeof(double) * (size_t)ne * 3 * N3);
-    m->J = malloc(sizeof(double) * (size_t)ne * N3);
-    m->Ja = malloc(sizeof(double) * (size_t)ne * 9 * N3);
+    m->ne = ne;
+    m->P = malloc(sizeof(int) * ne);
+    m->off = malloc(sizeof(size_t) * ne);
+    memcpy(m->P, P, sizeof(int) * ne);
+    size_t tot = 0;
+    for (int e = 0; e < ne; ++e) { m->off[e] = tot; tot += (size_t)N3E(m, e); }
+    m->nodes = tot;
+    for (int n = 2; n <= MAXN; ++n) orc_lgl(n - 1, m->xi[n], m->w[n], m->D[n]);
+    m->x = malloc(sizeof(double) * tot * 3);
+    m->J = malloc(sizeof(double) * tot);
+    m->Ja = malloc(sizeof(double) * tot * 9);
     m->delta = malloc(sizeof(double) * ne);
     m->nbr = malloc(sizeof(int) * ne * 6);
     m->nbr_face = malloc(ne * 6);
@@ -363,19 +425,37 @@ orc_mesh *orc_mesh_new(int ne, int P, int Pg, const double *xyz_geom, const int 
     size_t G3 = (size_t)(Pg + 1) * (Pg + 1) * (Pg + 1);
 #pragma omp parallel for schedule(static) num_threads(orc_get_threads())
     for (int e = 0; e < ne; ++e) element_metrics(m, e, Pg, xyz_geom + (size_t)e * 3 * G3);
-    for (size_t i = 0; i < (size_t)ne * N3; ++i)
-        if (!(m->J[i] > 0.0)) {
-            snprintf(g_err, sizeof g_err, "non-positive Jacobian in element %zu", i / N3);
-            orc_mesh_free(m);
-            return NULL;
-        }
+    for (int e = 0; e < ne; ++e)
+        for (size_t i = 0; i < (size_t)N3E(m, e); ++i)
+            if (!(m->J[m->off[e] + i] > 0.0)) {
+                snprintf(g_err, sizeof g_err, "non-positive Jacobian in element %d", e);
+                orc_mesh_free(m);
+                return NULL;
+            }
     return m;
 }
+
+orc_mesh *orc_mesh_new(int ne, int P, int Pg, const double *xyz_geom, const int *nbr,
+                       const signed char *nbr_face, const signed char *orient,
+                       const unsigned char *flag)
+{
+    if (ne <= 0) {
+        snprintf(g_err, sizeof g_err, "bad sizes: n_elem=%d", ne);
+        return NULL;
+    }
+    int *Pe = malloc(sizeof(int) * ne);
+    for (int e = 0; e < ne; ++e) Pe[e] = P;
+    orc_mesh *m = orc_mesh_new_mixed(ne, Pe, Pg, xyz_geom, nbr, nbr_face, orient, flag);
+    free(Pe);
+    return m;
+}
+
+size_t orc_mesh_nodes(const orc_mesh *m) { return m->nodes; }
 
 void orc_mesh_free(orc_mesh *m)
 {
     if (!m) return;
-    free(m->x); free(m->J); free(m->Ja); free(m->delta);
+    free(m->x); free(m->J); free(m->Ja); free(m->delta); free(m->P); free(m->off);
     free(m->nbr); free(m->nbr_face); free(m->orient); free(m->flag);
     free(m);
 }
@@ -384,13 +464,13 @@ void orc_set_flags(orc_mesh *m, const unsigned char *flag) { memcpy(m->flag, fla
 
 void orc_node_coords(const orc_mesh *m, double *xyz)
 {
-    memcpy(xyz, m->x, sizeof(double) * (size_t)m->ne * 3 * m->N3);
+    memcpy(xyz, m->x, sizeof(double) * m->nodes * 3);
 }
 
 void orc_metrics(const orc_mesh *m, double *J, double *Ja)
 {
-    if (J) memcpy(J, m->J, sizeof(double) * (size_t)m->ne * m->N3);
-    if (Ja) memcpy(Ja, m->Ja, sizeof(double) * (size_t)m->ne * 9 * m->N3);
+    if (J) memcpy(J, m->J, sizeof(double) * m->nodes);
+    if (Ja) memcpy(Ja, m->Ja, sizeof(double) * m->nodes * 9);
 }
 
 double orc_filter_width(const orc_mesh *m, int e) { return m->delta[e]; }
@@ -518,12 +598,13 @@ double orc_les_nut(int model, double C, double delta, const double *G)
 static void trace_outside(const orc_mesh *m, const orc_params *p, const double *q, int e,
                           int node, partner_t pt, double out[4])
 {
-    size_t N3 = m->N3;
     if (pt.interior) {
-        for (int k = 0; k < 4; ++k) out[k] = q[((size_t)pt.e2 * 4 + k) * N3 + pt.node2];
+        size_t n3 = N3E(m, pt.e2);
+        for (int k = 0; k < 4; ++k) out[k] = q[4 * m->off[pt.e2] + (size_t)k * n3 + pt.node2];
     } else if (pt.bc == -1) {   /* no-slip wall: mirrored velocity, same pressure */
-        out[0] = q[((size_t)e * 4 + 0) * N3 + node];
-        for (int k = 1; k < 4; ++k) out[k] = -q[((size_t)e * 4 + k) * N3 + node];
+        size_t n3 = N3E(m, e);
+        out[0] = q[4 * m->off[e] + node];
+        for (int k = 1; k < 4; ++k) out[k] = -q[4 * m->off[e] + (size_t)k * n3 + node];
     } else {                    /* far field: prescribed state */
         for (int k = 0; k < 4; ++k) out[k] = p->q_inf[k];
     }
@@ -536,28 +617,122 @@ static void owner_normal(const orc_mesh *m, int e, int f, int node, partner_t pt
     else own_outward(m, pt.e2, pt.f2, pt.node2, v);
 }
 
+/* A mortar face seen from its higher-order side (eh, fh): the lower-order
+ * side (el, fl), the mortar size M = N_eh, and for mortar node (i, j) of the
+ * higher side the index (i', j') of the same point in the lower side's face
+ * frame on an M-node grid. */
+typedef struct {
+    int eh, fh, el, fl, M, Nl;
+} mortar_t;
+
+static mortar_t mortar_of(const orc_mesh *m, int e, int f)
+{
+    mortar_t mt;
+    int e2 = m->nbr[e * 6 + f], f2 = m->nbr_face[e * 6 + f];
+    if (m->P[e] > m->P[e2]) { mt.eh = e; mt.fh = f; mt.el = e2; mt.fl = f2; }
+    else { mt.eh = e2; mt.fh = f2; mt.el = e; mt.fl = f; }
+    mt.M = NE(m, mt.eh);
+    mt.Nl = NE(m, mt.el);
+    return mt;
+}
+
+static void mortar_lowframe(const orc_mesh *m, const mortar_t *mt, int i, int j, int *il, int *jl)
+{
+    orient_map(m->orient[mt->eh * 6 + mt->fh], mt->M - 1, i, j, il, jl);
+}
+
+/* lower side's nodal field g[a + Nl b] (face-local) extended to mortar node (i, j) */
+static double mortar_extend(const orc_mesh *m, const mortar_t *mt, const double *g, int i, int j)
+{
+    int il, jl;
+    mortar_lowframe(m, mt, i, j, &il, &jl);
+    double s = 0.0;
+    for (int b = 0; b < mt->Nl; ++b)
+        for (int a = 0; a < mt->Nl; ++a)
+            s += interp_coef(m, mt->Nl, mt->M, il, a) * interp_coef(m, mt->Nl, mt->M, jl, b) * g[a + mt->Nl * b];
+    return s;
+}
+
+/* exact surface integral of a mortar field G(i, j) against the lower side's
+ * basis function of face node (a, b): sum_ij w_i w_j l_a l_b G */
+static double mortar_project(const orc_mesh *m, const mortar_t *mt, const double *G, int a, int b)
+{
+    double s = 0.0;
+    for (int j = 0; j < mt->M; ++j)
+        for (int i = 0; i < mt->M; ++i) {
+            int il, jl;
+            mortar_lowframe(m, mt, i, j, &il, &jl);
+            s += m->w[mt->M][i] * m->w[mt->M][j] * interp_coef(m, mt->Nl, mt->M, il, a)
+                 * interp_coef(m, mt->Nl, mt->M, jl, b) * G[i + mt->M * j];
+        }
+    return s;
+}
+
 /* ------------------------------------------------------------------------ */
 /* BR1 gradient (weak form) on viscous elements                              */
 /* ------------------------------------------------------------------------ */
 
+/* Mortar u* (s n) of the higher side at every mortar node: us[3 (r)][3 (d)][M^2] */
+static void mortar_ustar_sn(const orc_mesh *m, const double *q, const mortar_t *mt, double *us)
+{
+    int M = mt->M, Nl = mt->Nl;
+    size_t n3h = N3E(m, mt->eh), n3l = N3E(m, mt->el);
+    double *gl = malloc(sizeof(double) * Nl * Nl);
+    for (int r = 0; r < 3; ++r) {
+        for (int b = 0; b < Nl; ++b)
+            for (int a = 0; a < Nl; ++a)
+                gl[a + Nl * b] = q[4 * m->off[mt->el] + (size_t)(1 + r) * n3l + face_node(Nl, mt->fl, a, b)];
+        for (int j = 0; j < M; ++j)
+            for (int i = 0; i < M; ++i) {
+                int node = face_node(M, mt->fh, i, j);
+                double uh = q[4 * m->off[mt->eh] + (size_t)(1 + r) * n3h + node];
+                double ul = mortar_extend(m, mt, gl, i, j);
+                double nv[3];
+                own_outward(m, mt->eh, mt->fh, node, nv);
+                for (int d = 0; d < 3; ++d) us[(r * 3 + d) * M * M + i + M * j] = 0.5 * (uh + ul) * nv[d];
+            }
+    }
+    free(gl);
+}
+
 static void element_gradient(const orc_mesh *m, const orc_params *p, const double *q, int e, double *G)
 {
-    int N = m->N, N3 = m->N3;
-    const double *qe = q + (size_t)e * 4 * N3;
-    const double *Ja = m->Ja + (size_t)e * 9 * N3;
-    const double *J = m->J + (size_t)e * N3;
+    int N = NE(m, e), N3 = N3E(m, e);
+    const double *w = m->w[N], *D = m->D[N];
+    const double *qe = q + 4 * m->off[e];
+    const double *Ja = m->Ja + 9 * m->off[e];
+    const double *J = m->J + m->off[e];
+    /* mortar faces: u* (s n) integrated against each face node's basis function */
+    double *msurf[6] = {0};
+    for (int f = 0; f < 6; ++f) {
+        if (!is_mortar(m, e, f)) continue;
+        mortar_t mt = mortar_of(m, e, f);
+        int MM = mt.M * mt.M;
+        double *us = malloc(sizeof(double) * 9 * MM);
+        mortar_ustar_sn(m, q, &mt, us);
+        msurf[f] = malloc(sizeof(double) * 9 * N * N);
+        for (int b = 0; b < N; ++b)
+            for (int a = 0; a < N; ++a)
+                for (int k = 0; k < 9; ++k) {
+                    double v;
+                    if (mt.eh == e) v = w[a] * w[b] * us[k * MM + a + mt.M * b];
+                    else v = -mortar_project(m, &mt, us + k * MM, a, b);   /* lower side: inward normal */
+                    msurf[f][k * N * N + a + N * b] = v;
+                }
+        free(us);
+    }
     for (int j = 0; j < N3; ++j) {
         int ijk[3] = {j % N, (j / N) % N, j / (N * N)};
         double acc[3][3] = {{0}};
         /* - sum over quadrature nodes of W (Ja^i_d u_r) d(phi_j)/dxi^i */
         for (int i = 0; i < 3; ++i) {
             double wother = 1.0;
-            for (int k = 0; k < 3; ++k) if (k != i) wother *= m->w[ijk[k]];
+            for (int k = 0; k < 3; ++k) if (k != i) wother *= w[ijk[k]];
             for (int mq = 0; mq < N; ++mq) {
                 int mijk[3] = {ijk[0], ijk[1], ijk[2]};
                 mijk[i] = mq;
                 int mn = mijk[0] + N * mijk[1] + N * N * mijk[2];
-                double coef = m->w[mq] * wother * m->D[mq * N + ijk[i]];
+                double coef = w[mq] * wother * D[mq * N + ijk[i]];
                 for (int r = 0; r < 3; ++r)
                     for (int d = 0; d < 3; ++d)
                         acc[r][d] -= coef * qe[(1 + r) * N3 + mn] * Ja[(i * 3 + d) * N3 + mn];
@@ -569,29 +744,34 @@ static void element_gradient(const orc_mesh *m, const orc_params *p, const doubl
             if (ijk[d] != s) continue;
             int a = d == 0 ? ijk[1] : ijk[0];
             int b = d == 2 ? ijk[1] : ijk[2];
+            if (msurf[f]) {
+                for (int r = 0; r < 3; ++r)
+                    for (int dd = 0; dd < 3; ++dd) acc[r][dd] += msurf[f][(r * 3 + dd) * N * N + a + N * b];
+                continue;
+            }
             partner_t pt = partner(m, e, f, a, b);
             double qo[4], nv[3];
             trace_outside(m, p, q, e, j, pt, qo);
             owner_normal(m, e, f, j, pt, nv);
             double sg = is_owner(m, e, f) ? 1.0 : -1.0;
-            double wf = m->w[a] * m->w[b];
+            double wf = w[a] * w[b];
             for (int r = 0; r < 3; ++r) {
                 double ustar = 0.5 * (qe[(1 + r) * N3 + j] + qo[1 + r]);
                 for (int dd = 0; dd < 3; ++dd) acc[r][dd] += wf * ustar * sg * nv[dd];
             }
         }
-        double mass = m->w[ijk[0]] * m->w[ijk[1]] * m->w[ijk[2]] * J[j];
+        double mass = w[ijk[0]] * w[ijk[1]] * w[ijk[2]] * J[j];
         for (int r = 0; r < 3; ++r)
             for (int d = 0; d < 3; ++d) G[((size_t)(r * 3 + d)) * N3 + j] = acc[r][d] / mass;
     }
+    for (int f = 0; f < 6; ++f) free(msurf[f]);
 }
 
 void orc_gradient(const orc_mesh *m, const orc_params *p, const double *q, double *G)
 {
-    size_t N3 = m->N3;
 #pragma omp parallel for schedule(dynamic, 8) num_threads(orc_get_threads())
     for (int e = 0; e < m->ne; ++e)
-        if (m->flag[e]) element_gradient(m, p, q, e, G + (size_t)e * 9 * N3);
+        if (m->flag[e]) element_gradient(m, p, q, e, G + 9 * m->off[e]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -601,7 +781,7 @@ void orc_gradient(const orc_mesh *m, const orc_params *p, const double *q, doubl
 /* viscous flux 2 (nu + nu_t) S at every node of a viscous element: fv[r][d][N3] */
 static void element_viscous_flux(const orc_mesh *m, const orc_params *p, const double *G, int e, double *fv)
 {
-    int N3 = m->N3;
+    int N3 = N3E(m, e);
     for (int n = 0; n < N3; ++n) {
         double g[9];
         for (int k = 0; k < 9; ++k) g[k] = G[(size_t)k * N3 + n];
@@ -616,8 +796,8 @@ static void element_viscous_flux(const orc_mesh *m, const orc_params *p, const d
 static void fv_dot(const orc_mesh *m, const double *fv, int e, int node, const double v[3], double out[3])
 {
     if (!m->flag[e]) { out[0] = out[1] = out[2] = 0.0; return; }
-    size_t N3 = m->N3;
-    const double *fe = fv + (size_t)e * 9 * N3;
+    size_t N3 = N3E(m, e);
+    const double *fe = fv + 9 * m->off[e];
     for (int r = 0; r < 3; ++r) {
         double s = 0.0;
         for (int d = 0; d < 3; ++d) s += fe[(size_t)(r * 3 + d) * N3 + node] * v[d];
@@ -626,16 +806,16 @@ static void fv_dot(const orc_mesh *m, const double *fv, int e, int node, const d
 }
 
 /* Numerical flux through face f of element e at face point (a, b), outward for e,
- * already multiplied by the surface scaling s. */
+ * already multiplied by the surface scaling s (conforming and boundary faces). */
 static void face_flux(const orc_mesh *m, const orc_params *p, const double *q, const double *fv,
                       int e, int f, int a, int b, double Fout[4])
 {
-    size_t N3 = m->N3;
-    int node = face_node(m->N, f, a, b);
+    size_t N3 = N3E(m, e);
+    int node = face_node(NE(m, e), f, a, b);
     partner_t pt = partner(m, e, f, a, b);
     int own = is_owner(m, e, f);
     double qm[4], qp[4], nv[3];
-    for (int k = 0; k < 4; ++k) qm[k] = q[((size_t)e * 4 + k) * N3 + node];
+    for (int k = 0; k < 4; ++k) qm[k] = q[4 * m->off[e] + (size_t)k * N3 + node];
     trace_outside(m, p, q, e, node, pt, qp);
     owner_normal(m, e, f, node, pt, nv);
     double s = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
@@ -665,14 +845,61 @@ static void face_flux(const orc_mesh *m, const orc_params *p, const double *q, c
     for (int k = 0; k < 4; ++k) Fout[k] = sg * F[k];
 }
 
+/* Numerical flux at every mortar node, outward for the higher side and
+ * multiplied by s: Roe on (higher trace, extended lower trace) with the
+ * higher side's normal, minus the BR1 mean of the higher side's viscous
+ * trace and the extended lower side's viscous trace (each side's viscous
+ * flux dotted with the mortar's s n direction at its own nodes).
+ * F[row][M^2]. */
+static void mortar_flux(const orc_mesh *m, const orc_params *p, const double *q, const double *fv,
+                        const mortar_t *mt, double *F)
+{
+    int M = mt->M, Nl = mt->Nl, MM = M * M;
+    size_t n3h = N3E(m, mt->eh), n3l = N3E(m, mt->el);
+    int vh = m->flag[mt->eh], vl = m->flag[mt->el];
+    int keep = p->mixed_face == 0 || (vh && vl);
+    double *gl = malloc(sizeof(double) * 7 * Nl * Nl);   /* lower side: 4 state fields + 3 viscous trace rows */
+    for (int b = 0; b < Nl; ++b)
+        for (int a = 0; a < Nl; ++a) {
+            int node = face_node(Nl, mt->fl, a, b);
+            for (int k = 0; k < 4; ++k) gl[k * Nl * Nl + a + Nl * b] = q[4 * m->off[mt->el] + (size_t)k * n3l + node];
+            double nv[3], t[3];
+            own_outward(m, mt->el, mt->fl, node, nv);
+            for (int d = 0; d < 3; ++d) nv[d] = -nv[d];      /* the mortar's direction */
+            fv_dot(m, fv, mt->el, node, nv, t);
+            for (int r = 0; r < 3; ++r) gl[(4 + r) * Nl * Nl + a + Nl * b] = t[r];
+        }
+    for (int j = 0; j < M; ++j)
+        for (int i = 0; i < M; ++i) {
+            int node = face_node(M, mt->fh, i, j);
+            double qh[4], ql[4], nv[3], th[3], tl[3];
+            for (int k = 0; k < 4; ++k) {
+                qh[k] = q[4 * m->off[mt->eh] + (size_t)k * n3h + node];
+                ql[k] = mortar_extend(m, mt, gl + k * Nl * Nl, i, j);
+            }
+            own_outward(m, mt->eh, mt->fh, node, nv);
+            double s = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            double nh[3] = {nv[0] / s, nv[1] / s, nv[2] / s};
+            double Fr[4];
+            orc_roe_flux(p->c0sq, qh, ql, nh, Fr);
+            fv_dot(m, fv, mt->eh, node, nv, th);
+            for (int r = 0; r < 3; ++r) tl[r] = vl ? mortar_extend(m, mt, gl + (4 + r) * Nl * Nl, i, j) : 0.0;
+            for (int k = 0; k < 4; ++k) F[k * MM + i + M * j] = s * Fr[k];
+            if (vh || vl)
+                for (int r = 0; r < 3; ++r) F[(1 + r) * MM + i + M * j] -= keep ? 0.5 * (th[r] + tl[r]) : 0.0;
+        }
+    free(gl);
+}
+
 static void element_residual(const orc_mesh *m, const orc_params *p, const double *q, const double *fv,
                              int e, double *Re)
 {
-    int N = m->N, N3 = m->N3;
-    const double *qe = q + (size_t)e * 4 * N3;
-    const double *Ja = m->Ja + (size_t)e * 9 * N3;
-    const double *J = m->J + (size_t)e * N3;
-    const double *fve = fv + (size_t)e * 9 * N3;
+    int N = NE(m, e), N3 = N3E(m, e);
+    const double *w = m->w[N], *D = m->D[N];
+    const double *qe = q + 4 * m->off[e];
+    const double *Ja = m->Ja + 9 * m->off[e];
+    const double *J = m->J + m->off[e];
+    const double *fve = fv + 9 * m->off[e];
     double *Ft = malloc(sizeof(double) * 12 * N3);     /* Ft[i][row][n] */
     for (int n = 0; n < N3; ++n) {
         double pr = qe[n], u[3] = {qe[N3 + n], qe[2 * N3 + n], qe[3 * N3 + n]};
@@ -691,18 +918,37 @@ static void element_residual(const orc_mesh *m, const orc_params *p, const doubl
                 Ft[(i * 4 + row) * N3 + n] = s;
             }
     }
+    /* mortar faces: the flux integrated against each face node's basis function */
+    double *msurf[6] = {0};
+    for (int f = 0; f < 6; ++f) {
+        if (!is_mortar(m, e, f)) continue;
+        mortar_t mt = mortar_of(m, e, f);
+        int MM = mt.M * mt.M;
+        double *Fm = malloc(sizeof(double) * 4 * MM);
+        mortar_flux(m, p, q, fv, &mt, Fm);
+        msurf[f] = malloc(sizeof(double) * 4 * N * N);
+        for (int b = 0; b < N; ++b)
+            for (int a = 0; a < N; ++a)
+                for (int row = 0; row < 4; ++row) {
+                    double v;
+                    if (mt.eh == e) v = w[a] * w[b] * Fm[row * MM + a + mt.M * b];
+                    else v = -mortar_project(m, &mt, Fm + row * MM, a, b);   /* outward for the lower side */
+                    msurf[f][row * N * N + a + N * b] = v;
+                }
+        free(Fm);
+    }
     for (int j = 0; j < N3; ++j) {
         int ijk[3] = {j % N, (j / N) % N, j / (N * N)};
         double vol[4] = {0, 0, 0, 0}, surf[4] = {0, 0, 0, 0};
         /* + sum over quadrature nodes of W Ft^i d(phi_j)/dxi^i */
         for (int i = 0; i < 3; ++i) {
             double wother = 1.0;
-            for (int k = 0; k < 3; ++k) if (k != i) wother *= m->w[ijk[k]];
+            for (int k = 0; k < 3; ++k) if (k != i) wother *= w[ijk[k]];
             for (int mq = 0; mq < N; ++mq) {
                 int mijk[3] = {ijk[0], ijk[1], ijk[2]};
                 mijk[i] = mq;
                 int mn = mijk[0] + N * mijk[1] + N * N * mijk[2];
-                double coef = m->w[mq] * wother * m->D[mq * N + ijk[i]];
+                double coef = w[mq] * wother * D[mq * N + ijk[i]];
                 for (int row = 0; row < 4; ++row) vol[row] += coef * Ft[(i * 4 + row) * N3 + mn];
             }
         }
@@ -712,33 +958,37 @@ static void element_residual(const orc_mesh *m, const orc_params *p, const doubl
             if (ijk[d] != s) continue;
             int a = d == 0 ? ijk[1] : ijk[0];
             int b = d == 2 ? ijk[1] : ijk[2];
+            if (msurf[f]) {
+                for (int row = 0; row < 4; ++row) surf[row] += msurf[f][row * N * N + a + N * b];
+                continue;
+            }
             double Fo[4];
             face_flux(m, p, q, fv, e, f, a, b, Fo);
-            double wf = m->w[a] * m->w[b];
+            double wf = w[a] * w[b];
             for (int row = 0; row < 4; ++row) surf[row] += wf * Fo[row];
         }
-        double mass = m->w[ijk[0]] * m->w[ijk[1]] * m->w[ijk[2]] * J[j];
+        double mass = w[ijk[0]] * w[ijk[1]] * w[ijk[2]] * J[j];
         for (int row = 0; row < 4; ++row) Re[(size_t)row * N3 + j] = (vol[row] - surf[row]) / mass;
     }
+    for (int f = 0; f < 6; ++f) free(msurf[f]);
     free(Ft);
 }
 
 void orc_residual(const orc_mesh *m, const orc_params *p, const double *q, double *R)
 {
-    size_t N3 = m->N3;
-    double *fv = malloc(sizeof(double) * (size_t)m->ne * 9 * N3);
+    double *fv = malloc(sizeof(double) * m->nodes * 9);
 #pragma omp parallel num_threads(orc_get_threads())
     {
-        double *G = malloc(sizeof(double) * 9 * N3);
+        double *G = malloc(sizeof(double) * 9 * MAXN * MAXN * MAXN);
 #pragma omp for schedule(dynamic, 8)
         for (int e = 0; e < m->ne; ++e) {
             if (!m->flag[e]) continue;
             element_gradient(m, p, q, e, G);
-            element_viscous_flux(m, p, G, e, fv + (size_t)e * 9 * N3);
+            element_viscous_flux(m, p, G, e, fv + 9 * m->off[e]);
         }
         free(G);
 #pragma omp for schedule(dynamic, 8)
-        for (int e = 0; e < m->ne; ++e) element_residual(m, p, q, fv, e, R + (size_t)e * 4 * N3);
+        for (int e = 0; e < m->ne; ++e) element_residual(m, p, q, fv, e, R + 4 * m->off[e]);
     }
     free(fv);
 }
@@ -777,7 +1027,7 @@ static void mesh_rhs(void *ctx, const double *y, double *r)
 void orc_rk3_steps(const orc_mesh *m, const orc_params *p, double *q, double dt, int nsteps)
 {
     mesh_ctx c = {m, p};
-    rk3_drive((size_t)m->ne * 4 * m->N3, q, dt, nsteps, mesh_rhs, &c);
+    rk3_drive(4 * m->nodes, q, dt, nsteps, mesh_rhs, &c);
 }
 
 typedef struct { double re, im; } lin_ctx;

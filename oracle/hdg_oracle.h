@@ -8,7 +8,8 @@
  *
  * Data conventions (the interface format, shared with the library only as a
  * documented layout):
- *   - state / residual: [e][4][N^3], fields (p, u, v, w), node a + N b + N^2 c;
+ *   - state / residual: element after element, [4][N_e^3] each, N_e = P_e + 1,
+ *     fields (p, u, v, w), node a + N b + N^2 c;
  *   - geometry: [e][3][(Pg+1)^3] control points at equispaced reference
  *     positions -1 + 2k/Pg;
  *   - connectivity: nbr[e][6] (element, -1 wall, -2 far field), nbr_face[e][6],
@@ -17,6 +18,8 @@
  */
 #ifndef HDG_ORACLE_H
 #define HDG_ORACLE_H
+
+#include <stddef.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -41,19 +44,25 @@ void orc_lgl(int P, double *xi, double *w, double *D);
 orc_mesh *orc_mesh_new(int n_elem, int P, int Pg, const double *xyz_geom,
                        const int *nbr, const signed char *nbr_face,
                        const signed char *orient, const unsigned char *flag);
+/* Per-element orders P[e]; faces between different orders are coupled through
+ * a mortar (see hdg_oracle.c) and need 2 Pg <= the lower order. */
+orc_mesh *orc_mesh_new_mixed(int n_elem, const int *P, int Pg, const double *xyz_geom,
+                             const int *nbr, const signed char *nbr_face,
+                             const signed char *orient, const unsigned char *flag);
+size_t orc_mesh_nodes(const orc_mesh *m);
 void orc_mesh_free(orc_mesh *m);
 const char *orc_last_error(void);
 void orc_set_flags(orc_mesh *m, const unsigned char *flag);
 
-void orc_node_coords(const orc_mesh *m, double *xyz);          /* [e][3][N^3] */
-void orc_metrics(const orc_mesh *m, double *J, double *Ja);    /* [e][N^3], [e][3][3][N^3] */
+void orc_node_coords(const orc_mesh *m, double *xyz);          /* [e][3][N_e^3] */
+void orc_metrics(const orc_mesh *m, double *J, double *Ja);    /* [e][N_e^3], [e][3][3][N_e^3] */
 double orc_filter_width(const orc_mesh *m, int e);
 
 /* Building blocks exposed for the pins. */
 void orc_roe_flux(double c0sq, const double *qL, const double *qR, const double *n, double *F);
 double orc_les_nut(int model, double C, double delta, const double *G); /* G[r*3+d] = du_r/dx_d */
 
-/* BR1 gradient on every viscous element (others left untouched): G[e][3][3][N^3]. */
+/* BR1 gradient on every viscous element (others left untouched): G[e][3][3][N_e^3]. */
 void orc_gradient(const orc_mesh *m, const orc_params *p, const double *q, double *G);
 /* Residual R = dq/dt. */
 void orc_residual(const orc_mesh *m, const orc_params *p, const double *q, double *R);

@@ -418,6 +418,26 @@ def bernoulli_mask(n_elem: int, p: float, seed: int) -> np.ndarray:
     return (rng.random(n_elem) < p).astype(np.uint8)
 
 
+def mixed_orders(flag: np.ndarray, seed: int, orders=(2, 3, 4, 5, 6),
+                 w_viscous=(0.0, 0.1, 0.2, 0.3, 0.4), w_euler=(0.4, 0.3, 0.2, 0.1, 0.0)) -> np.ndarray:
+    """Seeded per-element polynomial order: viscous elements draw from
+    `w_viscous`, Euler elements from `w_euler` (higher orders where the
+    viscous/turbulent region is, as the paper's P-adaptation cases do)."""
+    rng = np.random.default_rng(seed)
+    orders = np.asarray(orders)
+    pv = np.asarray(w_viscous, dtype=float) / np.sum(w_viscous)
+    pe = np.asarray(w_euler, dtype=float) / np.sum(w_euler)
+    P = np.where(np.asarray(flag) != 0, rng.choice(orders, size=len(flag), p=pv),
+                 rng.choice(orders, size=len(flag), p=pe))
+    return P.astype(np.int32)
+
+
+def flat_offsets(P: np.ndarray) -> np.ndarray:
+    """First node of each element in element-after-element layouts."""
+    n3 = (np.asarray(P, dtype=np.int64) + 1) ** 3
+    return np.concatenate([[0], np.cumsum(n3)[:-1]])
+
+
 # ---------------------------------------------------------------------------
 # Initial states, layout [e][4][N^3] with fields (p, u, v, w)
 # ---------------------------------------------------------------------------
