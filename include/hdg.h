@@ -84,7 +84,8 @@ enum { HDG_LES_NONE = 0, HDG_LES_SMAGORINSKY = 1, HDG_LES_VREMAN = 2 };
 enum {
     HDG_KERNEL_VISCOUS = 0,   /* flagged elements: BR1 gradient, LES, viscous divergence and face traces */
     HDG_KERNEL_RESIDUAL = 1,  /* every element: convective divergence, face fluxes, -1/J (or fused RK stage) */
-    HDG_KERNEL_COUNT = 2
+    HDG_KERNEL_MORTAR = 2,    /* faces between elements of different order (BR1 lift, numerical flux) */
+    HDG_KERNEL_COUNT = 3
 };
 
 /* Mesh description (Sec. 2.1: per-element region ID; App. B: curvilinear
@@ -92,7 +93,15 @@ enum {
  * pointers are host pointers read during hdg_mesh_create only. */
 typedef struct {
     int32_t n_elem;
-    const int32_t *P;          /* [n_elem] polynomial order, 1..7; must be uniform (else HDG_EUNSUPPORTED) */
+    const int32_t *P;          /* [n_elem] polynomial order, 1..7, per element (Sec. 2.1 runs
+                                  regions of different order side by side).  A face between
+                                  orders is coupled through a mortar of the higher order: the
+                                  lower side's traces are extended by their own interpolants,
+                                  the Roe + BR1 flux is evaluated on the mortar with the higher
+                                  side's normal, and the lower side's surface integral is exact
+                                  on the mortar.  Such faces need 2 geom_order <= the lower
+                                  order (HDG_EUNSUPPORTED otherwise): the face geometry must
+                                  be exact at that order. */
     int32_t geom_order;        /* Pg >= 1: geometry control points per direction minus one */
     const double *xyz_geom;    /* [n_elem][3][(Pg+1)^3] */
     const uint8_t *flag;       /* [n_elem] 1: Navier-Stokes + LES, 0: Euler (Sec. 2.3) */
@@ -116,9 +125,10 @@ typedef struct {
 hdg_status hdg_init(hdg_ctx **ctx, int32_t device);
 void hdg_finalize(hdg_ctx *ctx);
 
-/* Validate the mesh, build the Gauss-Lobatto-Legendre rule, node geometry,
- * metric terms (curl form), face normals, element lists, and upload them.
- * Synchronous.  HDG_EMESH on inconsistent connectivity or J <= 0. */
+/* Validate the mesh, build the Gauss-Lobatto-Legendre rules, node geometry,
+ * metric terms (curl form), face normals, mortars, element lists, and upload
+ * them.  Synchronous.  HDG_EMESH on inconsistent connectivity or J <= 0.
+ * State layout: element after element, [4][(P_e+1)^3] each. */
 hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *desc, const hdg_params *params,
                            hdg_mesh **out);
 void hdg_mesh_destroy(hdg_mesh *mesh);
@@ -206,6 +216,7 @@ typedef struct {
  * Default without tuning: the smallest block that fits an element, one
  * workgroup per tile. */
 hdg_status hdg_mesh_autotune(hdg_mesh *mesh, const double *q_dev, int32_t reps, void *stream);
+/* kernel_class: HDG_KERNEL_VISCOUS or HDG_KERNEL_RESIDUAL (else HDG_EINVAL). */
 hdg_status hdg_mesh_get_launch(const hdg_mesh *mesh, int32_t kernel_class, hdg_prec prec, int32_t N,
                                hdg_launch_cfg *out);
 /* HDG_EUNSUPPORTED if no kernel exists for (N, block); us_per_launch ignored. */

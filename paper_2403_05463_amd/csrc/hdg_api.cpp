@@ -86,7 +86,8 @@ hdg_status dev_alloc(hdg_mesh *m, T **p, size_t count)
 void free_device(hdg_mesh *m)
 {
     void *ptrs[] = {m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->partials,
-                    m->final13, m->conn, m->flag_d, m->metric32, m->fgeo32, m->eoff, m->foff, m->member};
+                    m->final13, m->conn, m->flag_d, m->metric32, m->fgeo32, m->eoff, m->foff, m->member,
+                    m->Ne_d, m->mort, m->mslab, m->mgeo, m->mgeo32, m->mlist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &v : m->plans) {
@@ -139,7 +140,8 @@ hdg_status upload_plans(hdg_mesh *m)
     m->n_visc = 0;
     for (int64_t e = 0; e < m->ne; ++e) m->n_visc += m->flag[e];
     HDG_HIP(hipMemcpy(m->flag_d, m->flag.data(), m->ne, hipMemcpyHostToDevice));
-    std::vector<int> Ne(m->ne, m->N), cls(m->ne);
+    const std::vector<int> &Ne = m->Ne;
+    std::vector<int> cls(m->ne);
     for (auto &v : m->plans) {
         for (auto &pl : v) {
             if (pl.tiles) (void)hipFree(pl.tiles);
@@ -174,6 +176,22 @@ hdg_status upload_plans(hdg_mesh *m)
                 m->plans[kind].push_back(pl);
             }
         }
+    }
+    // mortar lists by higher order: lift (a flagged side), flux (all)
+    if (!m->mort_h.empty()) {
+        std::vector<int32_t> lists;
+        for (int kind = 0; kind < 2; ++kind)
+            for (int Nh = 0; Nh <= hdg::kMaxN + 1; ++Nh) {
+                m->mlist_off[kind][Nh] = (int64_t)lists.size();
+                if (Nh > hdg::kMaxN) continue;
+                for (size_t k = 0; k < m->mort_h.size(); ++k) {
+                    const hdg::MortarRef &r = m->mort_h[k];
+                    if (r.Nh != Nh) continue;
+                    if (kind == 0 && !m->flag[r.eh] && !m->flag[r.el]) continue;
+                    lists.push_back((int32_t)k);
+                }
+            }
+        HDG_HIP(hipMemcpy(m->mlist, lists.data(), lists.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
     return HDG_OK;
 }
@@ -227,6 +245,10 @@ StageArgs stage_args(const hdg_mesh *m, const TilePlan &pl)
     a.chunk = pl.chunk;
     a.D64 = m->ctx->D64;
     a.D32 = m->ctx->D32;
+    a.I64 = m->ctx->I64;
+    a.I32 = m->ctx->I32;
+    a.W64 = m->ctx->W64;
+    a.W32 = m->ctx->W32;
     return a;
 }
 
@@ -263,11 +285,31 @@ hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi ep
                      double B, double dt, bool first, hipStream_t s)
 {
     const int pi = f32 ? 1 : 0;
-    for (int kind = 0; kind < 2; ++kind)
+    for (int kind = 0; kind < 2; ++kind) {
+        // mortars: BR1 lift terms (kind 0) before the viscous kernels, numerical
+        // fluxes (kind 1) after them and before the residual kernels
+        if (!m->mort_h.empty())
+            for (int Nh = 2; Nh <= hdg::kMaxN; ++Nh) {
+                StageArgs a{};
+                a.mem = m->member;
+                a.I64 = m->ctx->I64;
+                a.I32 = m->ctx->I32;
+                a.W64 = m->ctx->W64;
+                a.W32 = m->ctx->W32;
+                a.q_in = q;
+                a.mlist = m->mlist + m->mlist_off[kind][Nh];
+                a.mcount = (int32_t)(m->mlist_off[kind][Nh + 1] - m->mlist_off[kind][Nh]);
+                if (a.mcount == 0) continue;
+                hdg_status st = timed(m, HDG_KERNEL_MORTAR, s, [&] {
+                    return kind == 0 ? hdg::launch_mortar_lift(Nh, f32, a, s) : hdg::launch_mortar_flux(Nh, f32, a, s);
+                });
+                if (st != HDG_OK) return st;
+            }
         for (int N = 2; N <= hdg::kMaxN; ++N) {
             hdg_status st = launch_one(m, kind, N, m->cfg[kind][pi][N], q, out, dq, epi, f32, A, B, dt, first, s, true);
             if (st != HDG_OK) return st;
         }
+    }
     return HDG_OK;
 }
 
@@ -279,10 +321,9 @@ hdg_status validate_desc(const hdg_mesh_desc *d, int &P)
         return fail(HDG_EINVAL, "mesh description: empty mesh or NULL array");
     if (d->geom_order < 1 || d->geom_order > 12) return fail(HDG_EINVAL, "geom_order must be 1..12");
     P = d->P[0];
-    if (P < 1 || P > hdg::kMaxN - 1) return fail(HDG_EUNSUPPORTED, "polynomial order must be 1..7");
     const int64_t ne = d->n_elem;
     for (int64_t e = 0; e < ne; ++e)
-        if (d->P[e] != P) return fail(HDG_EUNSUPPORTED, "non-uniform polynomial order");
+        if (d->P[e] < 1 || d->P[e] > hdg::kMaxN - 1) return fail(HDG_EUNSUPPORTED, "polynomial order must be 1..7");
     for (int64_t e = 0; e < ne; ++e)
         for (int f = 0; f < 6; ++f) {
             const int32_t e2 = d->nbr[e * 6 + f];
@@ -295,6 +336,9 @@ hdg_status validate_desc(const hdg_mesh_desc *d, int &P)
             if (e2 >= ne || f2 < 0 || f2 > 5 || d->nbr[(int64_t)e2 * 6 + f2] != e || d->nbr_face[(int64_t)e2 * 6 + f2] != f)
                 return fail(HDG_EMESH, "element " + std::to_string(e) + " face " + std::to_string(f) +
                                            ": asymmetric connectivity");
+            if (d->P[e2] != d->P[e] && 2 * d->geom_order > std::min(d->P[e], d->P[e2]))
+                return fail(HDG_EUNSUPPORTED, "element " + std::to_string(e) + " face " + std::to_string(f) +
+                                                  ": a face between orders needs 2 geom_order <= the lower order");
             const int o = d->orient[e * 6 + f], o2 = d->orient[(int64_t)e2 * 6 + f2];
             if (o < 0 || o > 7 || o2 < 0 || o2 > 7)
                 return fail(HDG_EMESH, "element " + std::to_string(e) + ": orientation code out of range");
@@ -337,16 +381,40 @@ hdg_status hdg_init(hdg_ctx **ctx, int32_t device)
         std::copy(D.begin(), D.end(), d64.begin() + hdg::d_offset(N));
     }
     std::vector<float> d32(d64.begin(), d64.end());
+    // interpolation between the GLL nodes of two orders, and GLL weights
+    std::vector<double> i64(hdg::kITableSize, 0.0), w64(hdg::kWTableSize, 0.0);
+    for (int Nh = 3; Nh <= hdg::kMaxN; ++Nh)
+        for (int Nl = 2; Nl < Nh; ++Nl) {
+            std::vector<double> I;
+            hdg::gll_interp(Nl - 1, Nh - 1, I);
+            std::copy(I.begin(), I.end(), i64.begin() + hdg::i_offset(Nl, Nh));
+        }
+    for (int N = 2; N <= hdg::kMaxN; ++N) {
+        std::vector<double> xi, w, D;
+        hdg::gll_rule(N - 1, xi, w, D);
+        std::copy(w.begin(), w.end(), w64.begin() + hdg::w_offset(N));
+    }
+    std::vector<float> i32(i64.begin(), i64.end()), w32(w64.begin(), w64.end());
     hipError_t e1 = hipMalloc((void **)&c->D64, d64.size() * 8);
     hipError_t e2 = hipMalloc((void **)&c->D32, d32.size() * 4);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
-        if (c->D64) (void)hipFree(c->D64);
-        if (c->D32) (void)hipFree(c->D32);
+    hipError_t e3 = hipMalloc((void **)&c->I64, i64.size() * 8);
+    hipError_t e4 = hipMalloc((void **)&c->I32, i32.size() * 4);
+    hipError_t e5 = hipMalloc((void **)&c->W64, w64.size() * 8);
+    hipError_t e6 = hipMalloc((void **)&c->W32, w32.size() * 4);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
+        e6 != hipSuccess) {
+        void *ps[] = {c->D64, c->D32, c->I64, c->I32, c->W64, c->W32};
+        for (void *p : ps)
+            if (p) (void)hipFree(p);
         delete c;
-        return fail(HDG_ENOMEM, "hipMalloc of the derivative tables failed");
+        return fail(HDG_ENOMEM, "hipMalloc of the operator tables failed");
     }
     HDG_HIP(hipMemcpy(c->D64, d64.data(), d64.size() * 8, hipMemcpyHostToDevice));
     HDG_HIP(hipMemcpy(c->D32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice));
+    HDG_HIP(hipMemcpy(c->I64, i64.data(), i64.size() * 8, hipMemcpyHostToDevice));
+    HDG_HIP(hipMemcpy(c->I32, i32.data(), i32.size() * 4, hipMemcpyHostToDevice));
+    HDG_HIP(hipMemcpy(c->W64, w64.data(), w64.size() * 8, hipMemcpyHostToDevice));
+    HDG_HIP(hipMemcpy(c->W32, w32.data(), w32.size() * 4, hipMemcpyHostToDevice));
     *ctx = c;
     return HDG_OK;
 }
@@ -356,8 +424,9 @@ void hdg_finalize(hdg_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->D64) (void)hipFree(ctx->D64);
-    if (ctx->D32) (void)hipFree(ctx->D32);
+    void *ps[] = {ctx->D64, ctx->D32, ctx->I64, ctx->I32, ctx->W64, ctx->W32};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
     delete ctx;
 }
 
@@ -375,25 +444,40 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
 
     hdg::HostGeometry g;
     std::string msg;
-    if (!hdg::build_geometry(*d, P, g, msg)) return fail(HDG_EMESH, msg);
+    if (!hdg::build_geometry(*d, g, msg)) return fail(HDG_EMESH, msg);
 
     auto *m = new hdg_mesh();
     m->ctx = ctx;
     m->ne = ne;
-    m->P = P;
-    m->N = P + 1;
+    m->Ne = g.Ne;
+    m->nodes = g.nodes;
+    m->mixed = false;
+    for (int64_t e = 0; e < ne; ++e) m->mixed = m->mixed || g.Ne[e] != g.Ne[0];
+    m->P = m->mixed ? 0 : P;
+    m->N = m->mixed ? 0 : P + 1;
     m->N2 = m->N * m->N;
     m->N3 = m->N2 * m->N;
     m->prm = *params;
-    m->inv_wend = 1.0 / g.w[0];
+    m->inv_wend = m->mixed ? 0.0 : 1.0 / g.w[0];
     for (auto &kc : m->cfg)
         for (auto &pc : kc)
             for (int n = 2; n <= hdg::kMaxN; ++n) pc[n] = hdg::default_cfg(n);
     m->flag.assign(d->flag, d->flag + ne);
     for (auto &f : m->flag) f = f ? 1 : 0;
-    const int N = m->N, N2 = m->N2, N3 = m->N3;
+    const std::vector<int> &Ne = g.Ne;
+    const std::vector<int64_t> &off = g.off;
+    auto Ja_at = [&](int64_t e, int i, int c, int n) {
+        const int N = Ne[e];
+        return g.Ja[9 * off[e] + (int64_t)(i * 3 + c) * N * N * N + n];
+    };
 
-    // canonical faces: the owner is the lower element id (lower local face on a tie)
+    // Faces.  A conforming face (both sides of one order) is canonical with
+    // the lower element id as owner (lower local face on a tie); a face
+    // between orders is a mortar named by its higher-order side.
+    auto mortar_face = [&](int64_t e, int f) {
+        const int32_t e2 = d->nbr[e * 6 + f];
+        return e2 >= 0 && Ne[e2] != Ne[e];
+    };
     std::vector<int32_t> fid(ne * 6, -1);
     auto is_owner = [&](int64_t e, int f) {
         const int32_t e2 = d->nbr[e * 6 + f];
@@ -401,53 +485,95 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         const int f2 = d->nbr_face[e * 6 + f];
         return e < e2 || (e == e2 && f < f2);
     };
-    int64_t nf = 0;
-    for (int64_t e = 0; e < ne; ++e)
-        for (int f = 0; f < 6; ++f)
-            if (is_owner(e, f)) fid[e * 6 + f] = (int32_t)nf++;
-    for (int64_t e = 0; e < ne; ++e)
-        for (int f = 0; f < 6; ++f)
-            if (!is_owner(e, f)) fid[e * 6 + f] = fid[(int64_t)d->nbr[e * 6 + f] * 6 + d->nbr_face[e * 6 + f]];
-    m->nfaces = nf;
-    std::vector<double> fgeo(nf * N2 * 4);
-    std::vector<FaceRef> conn(ne * 6);
+    int64_t nf = 0, nfn = 0, nm = 0, slab = 0, geo = 0;
+    std::vector<int64_t> foff;
     for (int64_t e = 0; e < ne; ++e)
         for (int f = 0; f < 6; ++f) {
-            const bool own = is_owner(e, f);
+            if (mortar_face(e, f)) {
+                const int64_t e2 = d->nbr[e * 6 + f];
+                if (Ne[e] < Ne[e2]) continue;      // named from the higher side
+                hdg::MortarRef r{};
+                r.eh = (int32_t)e;
+                r.fh = f;
+                r.el = (int32_t)e2;
+                r.fl = d->nbr_face[e * 6 + f];
+                r.Nh = Ne[e];
+                r.Nl = Ne[e2];
+                r.code_h = d->orient[e * 6 + f] & 7;
+                r.slab = slab;
+                r.geo = geo;
+                slab += hdg::mslab_size(r.Nh, r.Nl);
+                geo += (int64_t)r.Nh * r.Nh;
+                fid[e * 6 + f] = (int32_t)nm;
+                fid[e2 * 6 + r.fl] = (int32_t)nm;
+                m->mort_h.push_back(r);
+                ++nm;
+            } else if (is_owner(e, f)) {
+                fid[e * 6 + f] = (int32_t)nf++;
+                foff.push_back(nfn);
+                nfn += (int64_t)Ne[e] * Ne[e];
+            }
+        }
+    for (int64_t e = 0; e < ne; ++e)
+        for (int f = 0; f < 6; ++f)
+            if (!mortar_face(e, f) && !is_owner(e, f))
+                fid[e * 6 + f] = fid[(int64_t)d->nbr[e * 6 + f] * 6 + d->nbr_face[e * 6 + f]];
+    m->nfaces = nf;
+    std::vector<double> fgeo(std::max<int64_t>(nfn, 1) * 4), mgeo(std::max<int64_t>(geo, 1) * 4);
+    std::vector<FaceRef> conn(ne * 6);
+    auto put_normal = [&](double *o, int64_t e, int f, int n) {
+        const int i = f / 2;
+        const double sg = (f & 1) ? 1.0 : -1.0;
+        double v[3];
+        for (int c = 0; c < 3; ++c) v[c] = sg * Ja_at(e, i, c, n);
+        const double sc = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        o[0] = v[0] / sc;
+        o[1] = v[1] / sc;
+        o[2] = v[2] / sc;
+        o[3] = sc;
+    };
+    for (int64_t e = 0; e < ne; ++e)
+        for (int f = 0; f < 6; ++f) {
             FaceRef &r = conn[e * 6 + f];
             r.face = fid[e * 6 + f];
             r.nbr = d->nbr[e * 6 + f];
+            r.pad = 0;
+            const int N = Ne[e];
+            if (mortar_face(e, f)) {
+                const bool hi = Ne[e] > Ne[r.nbr];
+                r.code = hdg::kMortarBit | (hi ? hdg::kOwnerBit : 0);
+                if (hi) {
+                    const hdg::MortarRef &mr = m->mort_h[r.face];
+                    for (int b = 0; b < N; ++b)
+                        for (int a = 0; a < N; ++a)
+                            put_normal(&mgeo[(mr.geo + a + N * b) * 4], e, f, face_node(N, f, a, b));
+                }
+                continue;
+            }
+            const bool own = is_owner(e, f);
             r.code = (r.nbr >= 0 ? (d->orient[e * 6 + f] & 7) | ((d->nbr_face[e * 6 + f] & 7) << 3) : 0) |
                      (own ? hdg::kOwnerBit : 0);
-            r.pad = 0;
             if (!own) continue;
-            const int i = f / 2;
-            const double sg = (f & 1) ? 1.0 : -1.0;
             for (int b = 0; b < N; ++b)
-                for (int a = 0; a < N; ++a) {
-                    const int n = face_node(N, f, a, b);
-                    double v[3];
-                    for (int c = 0; c < 3; ++c) v[c] = sg * g.Ja[((e * 3 + i) * 3 + c) * N3 + n];
-                    const double s = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                    double *o = &fgeo[((size_t)r.face * N2 + a + N * b) * 4];
-                    o[0] = v[0] / s;
-                    o[1] = v[1] / s;
-                    o[2] = v[2] / s;
-                    o[3] = s;
-                }
+                for (int a = 0; a < N; ++a)
+                    put_normal(&fgeo[(foff[r.face] + a + N * b) * 4], e, f, face_node(N, f, a, b));
         }
-    std::vector<double> metric(ne * 10 * N3), mass(ne * N3);
-    for (int64_t e = 0; e < ne; ++e)
+    std::vector<double> metric(g.nodes * 10), mass(g.nodes);
+    for (int64_t e = 0; e < ne; ++e) {
+        const int N = Ne[e], N3 = N * N * N;
+        const std::vector<double> &w = g.ws[N];
         for (int n = 0; n < N3; ++n) {
-            const double J = g.J[e * N3 + n];
-            metric[(e * 10) * N3 + n] = 1.0 / J;
-            for (int k = 0; k < 9; ++k) metric[(e * 10 + 1 + k) * N3 + n] = g.Ja[(e * 9 + k) * N3 + n];
-            const int a = n % N, b = (n / N) % N, c = n / N2;
-            mass[e * N3 + n] = g.w[a] * g.w[b] * g.w[c] * J;
+            const double J = g.J[off[e] + n];
+            metric[10 * off[e] + n] = 1.0 / J;
+            for (int k = 0; k < 9; ++k) metric[10 * off[e] + (int64_t)(1 + k) * N3 + n] = g.Ja[9 * off[e] + (int64_t)k * N3 + n];
+            const int a = n % N, b = (n / N) % N, c = n / (N * N);
+            mass[off[e] + n] = w[a] * w[b] * w[c] * J;
         }
+    }
     m->x = std::move(g.x);
     m->order = hdg::locality_order(*d);
-    m->nblocks_reduce = (int)std::min<int64_t>(1024, (ne * N3 + 255) / 256);
+    m->nblocks_reduce = (int)std::min<int64_t>(1024, (g.nodes + 255) / 256);
+    m->nblocks_reduce = (int)std::min<int64_t>(m->nblocks_reduce, ne);
 
     std::lock_guard<std::mutex> device_lock(hdg::device_mutex());
     hdg_status s2 = HDG_OK;
@@ -455,9 +581,9 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(dev_alloc(m, &m->metric, metric.size()));
     chk(dev_alloc(m, &m->mass, mass.size()));
     chk(dev_alloc(m, &m->fgeo, fgeo.size()));
-    chk(dev_alloc(m, &m->fvt, (size_t)nf * 2 * N2 * 3));
-    chk(dev_alloc(m, &m->wvis, (size_t)ne * 3 * N3));
-    chk(dev_alloc(m, &m->qpp, (size_t)ne * 4 * N3));
+    chk(dev_alloc(m, &m->fvt, (size_t)std::max<int64_t>(nfn, 1) * 6));
+    chk(dev_alloc(m, &m->wvis, (size_t)g.nodes * 3));
+    chk(dev_alloc(m, &m->qpp, (size_t)g.nodes * 4));
     chk(dev_alloc(m, &m->delta, (size_t)ne));
     chk(dev_alloc(m, &m->metric32, metric.size()));
     chk(dev_alloc(m, &m->fgeo32, fgeo.size()));
@@ -466,6 +592,18 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(dev_alloc(m, &m->conn, conn.size()));
     chk(dev_alloc(m, &m->flag_d, (size_t)ne));
     chk(dev_alloc(m, &m->member, 1));
+    if (m->mixed) {
+        chk(dev_alloc(m, &m->eoff, (size_t)ne));
+        chk(dev_alloc(m, &m->foff, foff.size()));
+        chk(dev_alloc(m, &m->Ne_d, (size_t)ne));
+    }
+    if (nm > 0) {
+        chk(dev_alloc(m, &m->mort, (size_t)nm));
+        chk(dev_alloc(m, &m->mslab, (size_t)slab));       // FP64 slabs; FP32 ones use the first half
+        chk(dev_alloc(m, &m->mgeo, mgeo.size()));
+        chk(dev_alloc(m, &m->mgeo32, mgeo.size()));
+        chk(dev_alloc(m, &m->mlist, (size_t)2 * nm));
+    }
     if (s2 != HDG_OK) {
         free_device(m);
         delete m;
@@ -485,6 +623,18 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         chk(up(m->fgeo32, f32.data(), f32.size() * 4));
     }
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
+    if (m->mixed) {
+        std::vector<int8_t> n8(Ne.begin(), Ne.end());
+        chk(up(m->eoff, off.data(), off.size() * 8));
+        chk(up(m->foff, foff.data(), foff.size() * 8));
+        chk(up(m->Ne_d, n8.data(), n8.size()));
+    }
+    if (nm > 0) {
+        std::vector<float> g32(mgeo.begin(), mgeo.end());
+        chk(up(m->mort, m->mort_h.data(), m->mort_h.size() * sizeof(hdg::MortarRef)));
+        chk(up(m->mgeo, mgeo.data(), mgeo.size() * 8));
+        chk(up(m->mgeo32, g32.data(), g32.size() * 4));
+    }
     {
         Member &mb = m->host_member;
         mb = Member{};
@@ -499,8 +649,13 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         mb.conn = m->conn;
         mb.flag = m->flag_d;
         mb.delta = m->delta;
-        mb.eoff = nullptr;        // one order: offsets are e N^3 and face N^2
-        mb.foff = nullptr;
+        // one order: offsets are e N^3 and face N^2, no tables
+        mb.eoff = m->mixed ? m->eoff : nullptr;
+        mb.foff = m->mixed ? m->foff : nullptr;
+        mb.mort = m->mort;
+        mb.mslab = m->mslab;
+        mb.mgeo[0] = m->mgeo;
+        mb.mgeo[1] = m->mgeo32;
     }
     if (s2 == HDG_OK) s2 = upload_member(m);
     if (s2 == HDG_OK) s2 = upload_plans(m);
@@ -548,8 +703,8 @@ hdg_status hdg_mesh_info(const hdg_mesh *m, int64_t *n_nodes, int64_t *state_len
                          int32_t *n_viscous)
 {
     if (!m) return fail(HDG_EINVAL, "NULL mesh");
-    if (n_nodes) *n_nodes = m->ne * m->N3;
-    if (state_len) *state_len = 4 * m->ne * m->N3;
+    if (n_nodes) *n_nodes = m->nodes;
+    if (state_len) *state_len = 4 * m->nodes;
     if (device_bytes) *device_bytes = m->bytes;
     if (n_viscous) *n_viscous = m->n_visc;
     return HDG_OK;
@@ -571,7 +726,10 @@ hdg_status hdg_mesh_geometry(const hdg_mesh_desc *d, double *xyz, double *J, dou
     if (st != HDG_OK) return st;
     hdg::HostGeometry g;
     std::string msg;
-    if (!hdg::build_geometry(*d, P, g, msg)) return fail(HDG_EMESH, msg);
+    if (!hdg::build_geometry(*d, g, msg)) return fail(HDG_EMESH, msg);
+    for (int64_t e = 0; e < d->n_elem; ++e)
+        if (g.Ne[e] != g.Ne[0] && (xi || w || D))
+            return fail(HDG_EUNSUPPORTED, "geometry: xi, w and D are per order; pass NULL for a mesh of mixed order");
     if (xyz) std::memcpy(xyz, g.x.data(), g.x.size() * sizeof(double));
     if (J) std::memcpy(J, g.J.data(), g.J.size() * sizeof(double));
     if (Ja) std::memcpy(Ja, g.Ja.data(), g.Ja.size() * sizeof(double));
@@ -656,7 +814,7 @@ hdg_status hdg_rk3_steps(hdg_mesh *m, double *q, double *dq, double dt, int32_t 
         hdg_status r = one_step(cur, nxt, s);
         if (r != HDG_OK) return r;
     }
-    if (cur != q) HDG_HIP(hipMemcpyAsync(q, cur, (size_t)m->ne * 4 * m->N3 * 8, hipMemcpyDeviceToDevice, s));
+    if (cur != q) HDG_HIP(hipMemcpyAsync(q, cur, (size_t)m->nodes * 4 * 8, hipMemcpyDeviceToDevice, s));
     return HDG_OK;
 }
 
@@ -675,7 +833,9 @@ hdg_status hdg_reduce(hdg_mesh *m, const double *r, double out_sum[4], double ou
     if (!m || !r) return fail(HDG_EINVAL, "NULL argument");
     HDG_HIP(hipSetDevice(m->ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hdg::launch_reduce(m->N, r, m->mass, m->ne, m->partials, m->nblocks_reduce, m->final13, s);
+    hipError_t e = m->mixed ? hdg::launch_reduce_mixed(r, m->mass, m->eoff, m->Ne_d, m->ne, m->partials,
+                                                       m->nblocks_reduce, m->final13, s)
+                            : hdg::launch_reduce(m->N, r, m->mass, m->ne, m->partials, m->nblocks_reduce, m->final13, s);
     if (e != hipSuccess) return fail(HDG_EHIP, std::string("reduce launch: ") + hipGetErrorString(e));
     double h[13];
     HDG_HIP(hipMemcpyAsync(h, m->final13, sizeof h, hipMemcpyDeviceToHost, s));
@@ -781,7 +941,7 @@ hdg_status hdg_mesh_autotune(hdg_mesh *m, const double *q, int32_t reps, void *s
 
 hdg_status hdg_mesh_get_launch(const hdg_mesh *m, int32_t kernel_class, hdg_prec prec, int32_t N, hdg_launch_cfg *out)
 {
-    if (!m || !out || kernel_class < 0 || kernel_class >= HDG_KERNEL_COUNT || (prec != HDG_F64 && prec != HDG_F32) ||
+    if (!m || !out || kernel_class < 0 || kernel_class > HDG_KERNEL_RESIDUAL || (prec != HDG_F64 && prec != HDG_F32) ||
         N < 2 || N > hdg::kMaxN)
         return fail(HDG_EINVAL, "get_launch: bad argument");
     const LaunchCfg &c = m->cfg[kernel_class][prec == HDG_F32][N];
@@ -793,7 +953,7 @@ hdg_status hdg_mesh_get_launch(const hdg_mesh *m, int32_t kernel_class, hdg_prec
 
 hdg_status hdg_mesh_set_launch(hdg_mesh *m, int32_t kernel_class, hdg_prec prec, int32_t N, const hdg_launch_cfg *cfg)
 {
-    if (!m || !cfg || kernel_class < 0 || kernel_class >= HDG_KERNEL_COUNT || (prec != HDG_F64 && prec != HDG_F32) ||
+    if (!m || !cfg || kernel_class < 0 || kernel_class > HDG_KERNEL_RESIDUAL || (prec != HDG_F64 && prec != HDG_F32) ||
         N < 2 || N > hdg::kMaxN)
         return fail(HDG_EINVAL, "set_launch: bad argument");
     if (!hdg::shape_supported(N, cfg->block)) return fail(HDG_EUNSUPPORTED, "set_launch: no kernel for this order and block");

@@ -82,7 +82,8 @@ hdg_status rebuild_plans(hdg_batch *b)
                 for (size_t s = 0; s < b->slots.size(); ++s) {
                     const hdg_mesh *m = b->slots[s].mesh;
                     if (!m || m->N != N) continue;
-                    std::vector<int> Ne(m->ne, m->N), cls(m->ne);
+                    const std::vector<int> &Ne = m->Ne;
+                    std::vector<int> cls(m->ne);
                     for (int64_t e = 0; e < m->ne; ++e)
                         cls[e] = kind == hdg::kTileViscous ? (m->flag[e] ? 0 : -1) : m->flag[e];
                     hdg::cut_tiles(m->order, Ne, cls, (int)s, B, kind, tiles, elems);
@@ -205,6 +206,7 @@ hdg_status hdg_batch_add(hdg_batch *b, hdg_mesh *m, double *q, double *dq, doubl
     if (st != HDG_OK) return st;
     if (!m || !q || !dq || q == dq) return fail(HDG_EINVAL, "batch_add: need a mesh and distinct q, dq");
     if (m->ctx->device != b->ctx->device) return fail(HDG_EINVAL, "batch_add: mesh is on another device");
+    if (m->mixed) return fail(HDG_EUNSUPPORTED, "batch_add: members must have one polynomial order each");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HDG_EINVAL, "batch_add: need dt > 0");
     // a free slot no launch refers to any more; a slot freed since the last
     // plan rebuild may still be read by launches in flight
@@ -410,7 +412,7 @@ hdg_status hdg_batch_autotune(hdg_batch *b, int32_t reps, void *stream)
 hdg_status hdg_batch_get_launch(const hdg_batch *b, int32_t kernel_class, hdg_prec prec, int32_t N,
                                 hdg_launch_cfg *out)
 {
-    if (!b || !out || kernel_class < 0 || kernel_class >= HDG_KERNEL_COUNT || (prec != HDG_F64 && prec != HDG_F32) ||
+    if (!b || !out || kernel_class < 0 || kernel_class > HDG_KERNEL_RESIDUAL || (prec != HDG_F64 && prec != HDG_F32) ||
         N < 2 || N > hdg::kMaxN)
         return fail(HDG_EINVAL, "batch_get_launch: bad argument");
     const LaunchCfg &c = b->cfg[kernel_class][prec == HDG_F32][N];

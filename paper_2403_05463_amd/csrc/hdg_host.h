@@ -14,6 +14,10 @@ struct hdg_ctx {
     int n_cu = 0;
     double *D64 = nullptr;     // derivative matrices for N = 2..8, packed at d_offset(N)
     float *D32 = nullptr;
+    double *I64 = nullptr;     // interpolation matrices between orders, at i_offset(Nl, Nh)
+    float *I32 = nullptr;
+    double *W64 = nullptr;     // GLL weights, at w_offset(N)
+    float *W32 = nullptr;
 };
 
 namespace hdg {
@@ -125,7 +129,18 @@ struct hdg_mesh {
     float *metric32 = nullptr, *fgeo32 = nullptr;
     hdg::FaceRef *conn = nullptr;
     uint8_t *flag_d = nullptr;
-    int64_t *eoff = nullptr, *foff = nullptr;
+    int64_t *eoff = nullptr, *foff = nullptr;     // element / face offsets (meshes of mixed order)
+    int8_t *Ne_d = nullptr;                        // per-element N (meshes of mixed order)
+    bool mixed = false;                            // elements of more than one order
+    std::vector<int> Ne;                           // per-element N
+    int64_t nodes = 0;                             // total nodes
+    // mortars (faces between orders)
+    std::vector<hdg::MortarRef> mort_h;
+    hdg::MortarRef *mort = nullptr;
+    double *mslab = nullptr, *mgeo = nullptr;
+    float *mgeo32 = nullptr;
+    int32_t *mlist = nullptr;                      // mortar ids: lift lists, then flux lists, by Nh
+    int64_t mlist_off[2][hdg::kMaxN + 2] = {};     // [kind][Nh] start in mlist (kind 0 lift, 1 flux)
     hdg::Member *member = nullptr;              // the mesh's member record (device)
     hdg::Member host_member{};
     // tile plans per kernel kind, for every (order, workgroup size) pair

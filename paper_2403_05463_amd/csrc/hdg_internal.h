@@ -22,7 +22,33 @@ struct FaceRef {
     int32_t pad;
 };
 
-constexpr int kOwnerBit = 1 << 6;
+constexpr int kOwnerBit = 1 << 6;   // conforming face: this side owns it; mortar: this is the higher side
+constexpr int kMortarBit = 1 << 7;  // face between elements of different order: `face` is the mortar id
+
+// A face between elements of different order, coupled through a mortar of
+// the higher order in the higher side's face frame.  Its slab (values of the
+// compute type) holds, for the higher (h) and lower (l) side at the side's
+// own face nodes: viscous traces [3][N^2] (h, l), surface terms [4][N^2]
+// (h, l) and BR1 lift terms [9][N^2] (h, l).
+struct MortarRef {
+    int32_t eh, fh, el, fl;  // higher / lower order element and local face
+    int32_t Nh, Nl;          // nodes per direction on each side
+    int32_t code_h;          // orientation code of the higher side (its face coords -> the lower side's)
+    int32_t pad;
+    int64_t slab;            // first value of the slab
+    int64_t geo;             // first mortar node in the mortar geometry [node][4]: n (higher side outward), s
+};
+
+__host__ __device__ constexpr int64_t mslab_tr(int Nh, int Nl, bool hi) { return hi ? 0 : 3 * Nh * Nh; }
+__host__ __device__ constexpr int64_t mslab_surf(int Nh, int Nl, bool hi)
+{
+    return 3 * (Nh * Nh + Nl * Nl) + (hi ? 0 : 4 * Nh * Nh);
+}
+__host__ __device__ constexpr int64_t mslab_lift(int Nh, int Nl, bool hi)
+{
+    return 7 * (Nh * Nh + Nl * Nl) + (hi ? 0 : 9 * Nh * Nh);
+}
+__host__ __device__ constexpr int64_t mslab_size(int Nh, int Nl) { return 16 * (Nh * Nh + Nl * Nl); }
 
 // Work is cut into tiles: up to tile_ept() elements of one polynomial order
 // and one equation class, all from one member mesh, processed together by one
@@ -78,6 +104,9 @@ struct Member {
     const double *delta;    // [e] LES filter width
     const int64_t *eoff;    // [e] first node of the element; NULL: e N^3 (one order)
     const int64_t *foff;    // [face] first face node of the face; NULL: face N^2
+    const MortarRef *mort;  // [mortar] faces between orders (NULL if none)
+    void *mslab;            // mortar slabs (compute type)
+    const void *mgeo[2];    // mortar geometry [node][4], FP64 and FP32
     double c0sq, nu, C_les, dt;
     double qinf[4];
     int32_t les_model, mixed_face;
@@ -94,6 +123,12 @@ struct StageArgs {
     int32_t chunk;          // tiles per XCD chunk; the grid is a multiple of kXcd
     const double *D64;      // derivative matrices for N = 2..8, packed at d_offset(N)
     const float *D32;
+    const double *I64;      // interpolation matrices Nl -> Nh nodes, packed at i_offset(Nl, Nh)
+    const float *I32;
+    const double *W64;      // GLL weights of N nodes at w_offset(N)
+    const float *W32;
+    const int32_t *mlist;   // mortar kernels: mortar ids of this launch
+    int32_t mcount;
     const double *q_in;     // single-member mode
     double *q_out;
     double *dq;
@@ -105,8 +140,13 @@ struct StageArgs {
 };
 
 // Offset of the N x N derivative matrix in the packed table (N = 2..8).
-constexpr int d_offset(int N) { return (N - 1) * N * (2 * N - 1) / 6 - 1; }
+__host__ __device__ constexpr int d_offset(int N) { return (N - 1) * N * (2 * N - 1) / 6 - 1; }
 constexpr int kDTableSize = d_offset(kMaxN + 1);
+// Offset of the Nh x Nl interpolation matrix (2 <= Nl < Nh <= 8) and of the N weights.
+__host__ __device__ constexpr int i_offset(int Nl, int Nh) { return (Nh * kMaxN + Nl) * kMaxN * kMaxN; }
+constexpr int kITableSize = (kMaxN + 1) * kMaxN * kMaxN * kMaxN;
+__host__ __device__ constexpr int w_offset(int N) { return N * kMaxN; }
+constexpr int kWTableSize = (kMaxN + 1) * kMaxN;
 
 enum class Epi : int { Residual = 0, RkStage = 1 };
 
@@ -117,6 +157,14 @@ enum class Epi : int { Residual = 0, RkStage = 1 };
 hipError_t launch_viscous(int N, int B, bool f32, bool persistent, const StageArgs &a, int grid, hipStream_t s);
 hipError_t launch_residual(int N, int B, Epi epi, bool f32, bool persistent, const StageArgs &a, int grid,
                            hipStream_t s);
+// Mortar kernels: one 64-lane workgroup per mortar of higher order Nh, over
+// a.mlist[0 .. a.mcount).  The lift kernel (before the viscous kernels) forms
+// the BR1 lift terms, the flux kernel (after them) the surface terms.
+hipError_t launch_mortar_lift(int Nh, bool f32, const StageArgs &a, hipStream_t s);
+hipError_t launch_mortar_flux(int Nh, bool f32, const StageArgs &a, hipStream_t s);
+// Reductions of a mesh of mixed order: element after element, eoff / Ne per element.
+hipError_t launch_reduce_mixed(const double *r, const double *mass, const int64_t *eoff, const int8_t *Ne,
+                               int64_t n_elem, double *partials, int nblocks, double *final13, hipStream_t s);
 // Resident workgroups per CU of a kernel configuration (occupancy query).
 int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32);
 // Whether kernels are instantiated for order N with workgroup size B.
@@ -125,20 +173,28 @@ hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_e
                          double *partials, int nblocks, double *final13, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s);
 
-// Host-side mesh geometry (hdg_setup.cpp).
+// Host-side mesh geometry (hdg_setup.cpp), element after element: element e
+// has Ne[e] nodes per direction and starts at node off[e].
 struct HostGeometry {
-    int N = 0, N3 = 0;
-    std::vector<double> xi, w, D;          // GLL rule and derivative matrix
-    std::vector<double> x;                 // [e][3][N3]
-    std::vector<double> J;                 // [e][N3]
-    std::vector<double> Ja;                // [e][3][3][N3]
+    int N = 0, N3 = 0;                     // order of element 0 (all, on a one-order mesh)
+    std::vector<int> Ne;
+    std::vector<int64_t> off;
+    int64_t nodes = 0;
+    std::vector<double> xi, w, D;          // GLL rule and derivative matrix of element 0's order
+    std::vector<double> xis[kMaxN + 1], ws[kMaxN + 1], Ds[kMaxN + 1];   // every order in use
+    std::vector<double> x;                 // [e][3][Ne^3]
+    std::vector<double> J;                 // [e][Ne^3]
+    std::vector<double> Ja;                // [e][3][3][Ne^3]
     std::vector<double> delta;             // [e]
 };
 
 void gll_rule(int P, std::vector<double> &xi, std::vector<double> &w, std::vector<double> &D);
-// Interpolate geometry to the GLL nodes and build curl-form metric terms.
-// Returns false (with msg) on a non-positive Jacobian.
-bool build_geometry(const hdg_mesh_desc &d, int P, HostGeometry &g, std::string &msg);
+// Lagrange interpolation from the GLL nodes of order Plo to those of order
+// Phi, I[i][k] = l_k(xi_i), evaluated in extended precision.
+void gll_interp(int Plo, int Phi, std::vector<double> &I);
+// Interpolate geometry to the GLL nodes of each element's order and build
+// curl-form metric terms.  Returns false (with msg) on a non-positive Jacobian.
+bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg);
 // Spatially local processing order of the elements (recursive bisection of centroids).
 std::vector<int32_t> locality_order(const hdg_mesh_desc &d);
 

@@ -138,6 +138,24 @@ template <class T> __device__ __forceinline__ const T *dtable(const StageArgs &A
 template <> __device__ __forceinline__ const double *dtable<double>(const StageArgs &A) { return A.D64; }
 template <> __device__ __forceinline__ const float *dtable<float>(const StageArgs &A) { return A.D32; }
 template <class T> constexpr int prec_index() { return sizeof(T) == 4 ? 1 : 0; }
+template <class T> __device__ __forceinline__ const T *itable(const StageArgs &A);
+template <> __device__ __forceinline__ const double *itable<double>(const StageArgs &A) { return A.I64; }
+template <> __device__ __forceinline__ const float *itable<float>(const StageArgs &A) { return A.I32; }
+template <class T> __device__ __forceinline__ const T *wtable(const StageArgs &A);
+template <> __device__ __forceinline__ const double *wtable<double>(const StageArgs &A) { return A.W64; }
+template <> __device__ __forceinline__ const float *wtable<float>(const StageArgs &A) { return A.W32; }
+
+__device__ __forceinline__ MortarRef load_mortar(const MortarRef *mr, int m)
+{
+    const gmem<const int32_t> *p = gp((const int32_t *)(mr + m));
+    MortarRef r;
+    r.eh = p[0]; r.fh = p[1]; r.el = p[2]; r.fl = p[3];
+    r.Nh = p[4]; r.Nl = p[5]; r.code_h = p[6]; r.pad = 0;
+    const gmem<const int64_t> *p64 = gp((const int64_t *)(mr + m)) + 4;
+    r.slab = p64[0];
+    r.geo = p64[1];
+    return r;
+}
 
 // One lane's view of its element and node within a tile.
 template <int N, class T>
@@ -265,9 +283,9 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
 #pragma unroll 1
     for (int task = c.tid; task < NTASK; task += blockDim.x) {
         const FaceTask<N> ft = face_task<N, EPT>(A, tl, task);
-        if (ft.s < tl.count) {
+        const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
+        if (ft.s < tl.count && !(fr.code & kMortarBit)) {
             // u* - u = (u_other - u) / 2, formed in FP64
-            const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
             const gmem<const double> *qm = c.qin + 4 * elem_off<N>(M, ft.e) + face_node<N>(ft.f, ft.fa, ft.fb);
             double uo[3];
             if (fr.nbr >= 0) {
@@ -320,13 +338,27 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
             const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
             if (c.act && (idx == 0 || idx == N - 1)) {
                 const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
-                const int task = tbase + f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
+                const int fidx = (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
+                const int task = tbase + f * N2 + fidx;
                 const T sf = (f & 1) ? T(1) : T(-1);
+                const FaceRef fr = load_face(M.conn, (size_t)c.e * 6 + f);
+                if (fr.code & kMortarBit) {
+                    // mortar: (u* - u_r) (s n) integrated on the mortar, minus (u - u_r) (s n)_own
+                    const MortarRef mr = load_mortar(M.mort, fr.face);
+                    const gmem<const T> *lf = gp((const T *)M.mslab) + mr.slab +
+                                              mslab_lift(mr.Nh, mr.Nl, fr.code & kOwnerBit) + fidx;
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const T jump = sfu[r * NTASK + task] * sf * c.inv_wend;
+                    for (int r = 0; r < 3; ++r)
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) JG[r][d] += jump * c.Ja[dir][d];
+                        for (int d = 0; d < 3; ++d)
+                            JG[r][d] += (lf[(r * 3 + d) * N2] - c.qt[1 + r] * sf * c.Ja[dir][d]) * c.inv_wend;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        const T jump = sfu[r * NTASK + task] * sf * c.inv_wend;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) JG[r][d] += jump * c.Ja[dir][d];
+                    }
                 }
             }
         }
@@ -370,13 +402,23 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
             const T sf = (f & 1) ? T(1) : T(-1);
 #pragma unroll
             for (int r = 0; r < 3; ++r) W[r] += sf * lds[(dir * 3 + r) * NN + c.g] * c.inv_wend;
-            // tau . (s n) with the owner's outward normal: +-(this element's outward)
-            const int task = tbase + f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
+            // tau . (s n) with the owner's outward normal (mortar: the higher
+            // side's outward normal): +-(this element's outward)
+            const int fidx = (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
+            const int task = tbase + f * N2 + fidx;
             const FaceRef fr = load_face(M.conn, (size_t)c.e * 6 + f);
             const T so = (fr.code & kOwnerBit) ? sf : -sf;
             const T sn[3] = {so * c.Ja[dir][0], so * c.Ja[dir][1], so * c.Ja[dir][2]};
+            if (fr.code & kMortarBit) {
+                const MortarRef mr = load_mortar(M.mort, fr.face);
+                gmem<T> *tr = gp((T *)M.mslab) + mr.slab + mslab_tr(mr.Nh, mr.Nl, fr.code & kOwnerBit) + fidx;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) sfu[r * NTASK + task] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
+                for (int r = 0; r < 3; ++r) tr[r * N2] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+                    sfu[r * NTASK + task] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
+            }
         }
     }
     if (c.act) {
@@ -389,8 +431,8 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
 #pragma unroll 1
     for (int task = c.tid; task < NTASK; task += blockDim.x) {
         const FaceTask<N> ft = face_task<N, EPT>(A, tl, task);
-        if (ft.s < tl.count) {
-            const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
+        const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
+        if (ft.s < tl.count && !(fr.code & kMortarBit)) {
             const bool own = fr.code & kOwnerBit;
             int oa = ft.fa, ob = ft.fb;
             if (!own) orient_map<N>(fr.code & 7, ft.fa, ft.fb, oa, ob);
@@ -531,7 +573,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
 #pragma unroll 1
     for (int task = c.tid; task < NTASK; task += blockDim.x) {
         const FaceTask<N> ft = face_task<N, EPT>(A, tl, task);
-        if (ft.s < tl.count) {
+        if (ft.s < tl.count && !(load_face(M.conn, (size_t)ft.e * 6 + ft.f).code & kMortarBit)) {
             T F[4];
             face_jump<N, T>(M, c.qin, c.c0sq, ft.e, visc, ft.f, ft.fa, ft.fb, F);
 #pragma unroll
@@ -592,9 +634,22 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
             const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
             const int fa = dir == 0 ? c.j : c.i;
             const int fb = dir == 2 ? c.j : c.k;
-            const T *Fs = sface + c.s * NFT + f * N2 + fa + N * fb;
+            const FaceRef fr = load_face(M.conn, (size_t)c.e * 6 + f);
+            if (fr.code & kMortarBit) {
+                // mortar: the surface term relative to the reference flux,
+                // minus this element's outward deviation flux
+                const MortarRef mr = load_mortar(M.mort, fr.face);
+                const T sf = (f & 1) ? T(1) : T(-1);
+                const gmem<const T> *sm = gp((const T *)M.mslab) + mr.slab +
+                                          mslab_surf(mr.Nh, mr.Nl, fr.code & kOwnerBit) + fa + N * fb;
 #pragma unroll
-            for (int row = 0; row < 4; ++row) V[row] += Fs[row * NTASK] * c.inv_wend;
+                for (int row = 0; row < 4; ++row)
+                    V[row] += (sm[row * N2] - sf * lds[(dir * 4 + row) * NN + c.g]) * c.inv_wend;
+            } else {
+                const T *Fs = sface + c.s * NFT + f * N2 + fa + N * fb;
+#pragma unroll
+                for (int row = 0; row < 4; ++row) V[row] += Fs[row * NTASK] * c.inv_wend;
+            }
         }
     }
 
@@ -677,6 +732,269 @@ __global__ __launch_bounds__(B) void k_residual(StageArgs A)
     } else {
         HDG_ONE_TILE(A, tl) residual_tile<N, EPT, EPI, T, true>(A, tl, smem);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Mortars: faces between elements of different order.  The mortar carries
+// the higher order NH in the higher side's face frame; the lower side's
+// traces are extended to it by their own interpolants, the numerical flux is
+// evaluated once per mortar node with the higher side's normal, and the
+// lower side's share is its exact surface integral on the mortar against
+// each of its face basis functions (GLL weights of the mortar, interpolation
+// coefficients as test functions), divided by its own face weights.  Values
+// are formed relative to each side's reference state q_r (its centre node),
+// as in the element kernels, so that only deviations enter the compute type.
+// ---------------------------------------------------------------------------
+
+// Lower side's face-local node (a, b) value extended to mortar node (il, jl)
+// (indices in the lower side's frame on the NH grid), FP64.
+template <int NH>
+__device__ __forceinline__ double extend64(const StageArgs &A, const gmem<const double> *base, int Nl, int fl,
+                                           int il, int jl)
+{
+    const double *I = A.I64 + i_offset(Nl, NH);
+    double s = 0.0;
+    for (int b = 0; b < Nl; ++b) {
+        double sb = 0.0;
+        for (int a = 0; a < Nl; ++a) {
+            const int fs = (fl & 1) ? Nl - 1 : 0, d = fl >> 1;
+            const int node = d == 0 ? fs + Nl * (a + Nl * b) : d == 1 ? a + Nl * (fs + Nl * b) : a + Nl * (b + Nl * fs);
+            sb += I[il * Nl + a] * base[node];
+        }
+        s += I[jl * Nl + b] * sb;
+    }
+    return s;
+}
+
+template <int NH, class T>
+__device__ __forceinline__ T extendT(const StageArgs &A, const gmem<const T> *tr, int Nl, int il, int jl)
+{
+    const T *I = itable<T>(A) + i_offset(Nl, NH);
+    T s = T(0);
+    for (int b = 0; b < Nl; ++b) {
+        T sb = T(0);
+        for (int a = 0; a < Nl; ++a) sb += I[il * Nl + a] * tr[a + Nl * b];
+        s += I[jl * Nl + b] * sb;
+    }
+    return s;
+}
+
+// Exact integral on the mortar of G (LDS, [k][NH^2]) against the lower side's
+// face basis function of node (a, b), over that node's face weight.
+template <int NH, class T>
+__device__ __forceinline__ T project(const StageArgs &A, const T *G, int Nl, int code_h, int a, int b)
+{
+    const T *I = itable<T>(A) + i_offset(Nl, NH);
+    const T *wh = wtable<T>(A) + w_offset(NH);
+    const T *wl = wtable<T>(A) + w_offset(Nl);
+    T s = T(0);
+    for (int j = 0; j < NH; ++j)
+        for (int i = 0; i < NH; ++i) {
+            int il, jl;
+            orient_map<NH>(code_h & 7, i, j, il, jl);
+            s += wh[i] * wh[j] * I[il * Nl + a] * I[jl * Nl + b] * G[i + NH * j];
+        }
+    return s / (wl[a] * wl[b]);
+}
+
+template <int NH, class T>
+__global__ __launch_bounds__(64) void k_mortar_lift(StageArgs A)
+{
+    constexpr int M2 = NH * NH, N3H = NH * NH * NH;
+    __shared__ T G[9 * M2];
+    const int mi = blockIdx.x;
+    if (mi >= A.mcount) return;                  // uniform: the grid is mcount workgroups
+    const Member &M = A.mem[0];
+    const MortarRef mr = load_mortar(M.mort, A.mlist[mi]);
+    const int Nl = mr.Nl, N3L = Nl * Nl * Nl;
+    const gmem<const double> *q = gp((const double *)(A.q_in ? A.q_in : M.qA));
+    const gmem<const double> *qh = q + 4 * elem_off<NH>(M, mr.eh);
+    const gmem<const double> *ql = q + 4 * gp(M.eoff)[mr.el];
+    const int lane = threadIdx.x;
+    const int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (Nl / 2) * (1 + Nl + Nl * Nl);
+    gmem<T> *slab = gp((T *)M.mslab) + mr.slab;
+    if (lane < M2) {
+        const int i = lane % NH, j = lane / NH;
+        int il, jl;
+        orient_map<NH>(mr.code_h & 7, i, j, il, jl);
+        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (mr.geo + lane);
+        const T sn[3] = {g[0] * g[3], g[1] * g[3], g[2] * g[3]};
+        const int nodeh = face_node<NH>(mr.fh, i, j);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const double uh = qh[(1 + r) * N3H + nodeh];
+            const double ul = extend64<NH>(A, ql + (1 + r) * N3L, Nl, mr.fl, il, jl);
+            const double us = 0.5 * (uh + ul);
+            const T dh = (T)(us - qh[(1 + r) * N3H + crefh]);
+            const T dl = (T)(us - ql[(1 + r) * N3L + crefl]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                slab[mslab_lift(NH, Nl, true) + (r * 3 + d) * M2 + lane] = dh * sn[d];
+                G[(r * 3 + d) * M2 + lane] = -dl * sn[d];
+            }
+        }
+    }
+    __syncthreads();
+    if (lane < Nl * Nl) {
+        const int a = lane % Nl, b = lane / Nl;
+        for (int k = 0; k < 9; ++k)
+            slab[mslab_lift(NH, Nl, false) + k * Nl * Nl + lane] = project<NH, T>(A, G + k * M2, Nl, mr.code_h, a, b);
+    }
+}
+
+template <int NH, class T>
+__global__ __launch_bounds__(64) void k_mortar_flux(StageArgs A)
+{
+    constexpr int M2 = NH * NH, N3H = NH * NH * NH;
+    __shared__ T G[4 * M2];
+    const int mi = blockIdx.x;
+    if (mi >= A.mcount) return;
+    const Member &M = A.mem[0];
+    const MortarRef mr = load_mortar(M.mort, A.mlist[mi]);
+    const int Nl = mr.Nl, N3L = Nl * Nl * Nl;
+    const gmem<const double> *q = gp((const double *)(A.q_in ? A.q_in : M.qA));
+    const gmem<const double> *qh = q + 4 * elem_off<NH>(M, mr.eh);
+    const gmem<const double> *ql = q + 4 * gp(M.eoff)[mr.el];
+    const int lane = threadIdx.x;
+    const int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (Nl / 2) * (1 + Nl + Nl * Nl);
+    gmem<T> *slab = gp((T *)M.mslab) + mr.slab;
+    const T c0sq = (T)M.c0sq, h = T(0.5);
+    if (lane < M2) {
+        const int i = lane % NH, j = lane / NH;
+        int il, jl;
+        orient_map<NH>(mr.code_h & 7, i, j, il, jl);
+        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (mr.geo + lane);
+        const T n[3] = {g[0], g[1], g[2]};
+        const T sc = g[3];
+        const int nodeh = face_node<NH>(mr.fh, i, j);
+        double qa[4], qb[4], rh[4], rl[4];       // higher trace, extended lower trace, reference states
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            qa[x] = qh[x * N3H + nodeh];
+            qb[x] = extend64<NH>(A, ql + x * N3L, Nl, mr.fl, il, jl);
+            rh[x] = qh[x * N3H + crefh];
+            rl[x] = ql[x * N3L + crefl];
+        }
+        // Roe dissipation |A(q_mean)| dq with L = higher side, R = lower side
+        T uL[3], du[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            uL[d] = (T)qa[1 + d];
+            du[d] = (T)(qb[1 + d] - qa[1 + d]);
+        }
+        const T dp = (T)(qb[0] - qa[0]);
+        const T uLn = uL[0] * n[0] + uL[1] * n[1] + uL[2] * n[2];
+        const T dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+        const T un = uLn + h * dun;
+        const T a = sqrt(un * un + c0sq);
+        const T ia = T(1) / a;
+        const T pip = a - un, pim = -a - un;
+        const T alp = h * ia * (dp - pim * dun);
+        const T alm = h * ia * (pip * dun - dp);
+        const T lp = (un + a) * alp, lm = (a - un) * alm, l0 = fabs(un);
+        T Ad[4];
+        Ad[0] = lp * pip + lm * pim;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T ub = uL[d] + h * du[d];
+            const T vp = (pip * n[d] + ub) * ia;
+            const T vm = -(pim * n[d] + ub) * ia;
+            Ad[1 + d] = lp * vp + lm * vm + l0 * (du[d] - alp * vp - alm * vm);
+        }
+        // BR1: mean of the two sides' viscous traces along the higher side's s n
+        const bool vh = gp(M.flag)[mr.eh] != 0, vl = gp(M.flag)[mr.el] != 0;
+        T fvn[3] = {T(0), T(0), T(0)};
+        if ((vh || vl) && (M.mixed_face == 0 || (vh && vl))) {
+            const gmem<const T> *th = gp((const T *)M.mslab) + mr.slab + mslab_tr(NH, Nl, true);
+            const gmem<const T> *tl = gp((const T *)M.mslab) + mr.slab + mslab_tr(NH, Nl, false);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const T a_ = vh ? th[r * M2 + lane] : T(0);
+                const T b_ = vl ? extendT<NH, T>(A, tl + r * Nl * Nl, Nl, il, jl) : T(0);
+                fvn[r] = h * (a_ + b_);
+            }
+        }
+        // flux relative to each side's reference flux F_n(q_r):
+        //   F* - F_n(q_r) = ((F_n(qa) - F_n(q_r)) + (F_n(qb) - F_n(q_r)))/2 - |A| dq / 2,
+        //   F_n(q) - F_n(q_r) = [c0^2 du_n ; u du_n + du u_r,n + dp n], du = u - u_r
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const double *qr = side == 0 ? rh : rl;
+            const T urn = (T)qr[1] * n[0] + (T)qr[2] * n[1] + (T)qr[3] * n[2];
+            T F[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int lr = 0; lr < 2; ++lr) {
+                const double *qs = lr == 0 ? qa : qb;
+                const T dpp = (T)(qs[0] - qr[0]);
+                const T dv[3] = {(T)(qs[1] - qr[1]), (T)(qs[2] - qr[2]), (T)(qs[3] - qr[3])};
+                const T dvn = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
+                F[0] += c0sq * dvn;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) F[1 + d] += (T)qs[1 + d] * dvn + dv[d] * urn + dpp * n[d];
+            }
+            T out[4];
+            out[0] = sc * h * (F[0] - Ad[0]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) out[1 + d] = sc * h * (F[1 + d] - Ad[1 + d]) - fvn[d];
+            if (side == 0) {
+#pragma unroll
+                for (int row = 0; row < 4; ++row) slab[mslab_surf(NH, Nl, true) + row * M2 + lane] = out[row];
+            } else {
+#pragma unroll
+                for (int row = 0; row < 4; ++row) G[row * M2 + lane] = -out[row];   // outward for the lower side
+            }
+        }
+    }
+    __syncthreads();
+    if (lane < Nl * Nl) {
+        const int a = lane % Nl, b = lane / Nl;
+        for (int row = 0; row < 4; ++row)
+            slab[mslab_surf(NH, Nl, false) + row * Nl * Nl + lane] = project<NH, T>(A, G + row * M2, Nl, mr.code_h, a, b);
+    }
+}
+
+// Partial reductions over the elements of a mesh of mixed order: workgroup
+// b takes a contiguous range of elements, its lanes stride over each
+// element's nodes.  Fixed order, no atomics.
+__global__ __launch_bounds__(256) void k_reduce_partial_mixed(const double *r, const double *mass, const int64_t *eoff,
+                                                              const int8_t *Ne, int64_t ne, double *partials)
+{
+    __shared__ double red[13][256];
+    double acc[13];
+#pragma unroll
+    for (int x = 0; x < 13; ++x) acc[x] = 0.0;
+    const int64_t per = (ne + gridDim.x - 1) / gridDim.x;
+    const int64_t e0 = (int64_t)blockIdx.x * per, e1 = e0 + per < ne ? e0 + per : ne;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int N = Ne[e];
+        const int N3 = N * N * N;
+        const int64_t o = eoff[e];
+        for (int n = threadIdx.x; n < N3; n += blockDim.x) {
+            const double m = mass[o + n];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const double v = r[4 * o + (int64_t)f * N3 + n];
+                acc[f] += m * v;
+                acc[4 + f] += m * v * v;
+                const double av = fabs(v);
+                acc[8 + f] = av > acc[8 + f] ? av : acc[8 + f];
+                if (!isfinite(v)) acc[12] = 1.0;
+            }
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 13; ++x) red[x][threadIdx.x] = acc[x];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int x = 0; x < 8; ++x) red[x][threadIdx.x] += red[x][threadIdx.x + w];
+#pragma unroll
+            for (int x = 8; x < 13; ++x) red[x][threadIdx.x] = fmax(red[x][threadIdx.x], red[x][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 13) partials[(size_t)blockIdx.x * 13 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Per-block partial reductions over whole elements: sum(m r), sum(m r^2),
@@ -881,6 +1199,48 @@ int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32)
     });
     slot = e == hipSuccess && n > 0 ? n : 1;
     return slot;
+}
+
+hipError_t launch_mortar_lift(int Nh, bool f32, const StageArgs &a, hipStream_t s)
+{
+    if (a.mcount == 0) return hipSuccess;
+#define C_(n)                                                                                              \
+    do {                                                                                                   \
+        if (f32) hipLaunchKernelGGL((k_mortar_lift<n, float>), dim3(a.mcount), dim3(64), 0, s, a);        \
+        else hipLaunchKernelGGL((k_mortar_lift<n, double>), dim3(a.mcount), dim3(64), 0, s, a);           \
+        return hipGetLastError();                                                                          \
+    } while (0)
+    switch (Nh) {
+    case 3: C_(3); case 4: C_(4); case 5: C_(5); case 6: C_(6); case 7: C_(7); case 8: C_(8);
+    default: return hipErrorInvalidValue;
+    }
+#undef C_
+}
+
+hipError_t launch_mortar_flux(int Nh, bool f32, const StageArgs &a, hipStream_t s)
+{
+    if (a.mcount == 0) return hipSuccess;
+#define C_(n)                                                                                              \
+    do {                                                                                                   \
+        if (f32) hipLaunchKernelGGL((k_mortar_flux<n, float>), dim3(a.mcount), dim3(64), 0, s, a);        \
+        else hipLaunchKernelGGL((k_mortar_flux<n, double>), dim3(a.mcount), dim3(64), 0, s, a);           \
+        return hipGetLastError();                                                                          \
+    } while (0)
+    switch (Nh) {
+    case 3: C_(3); case 4: C_(4); case 5: C_(5); case 6: C_(6); case 7: C_(7); case 8: C_(8);
+    default: return hipErrorInvalidValue;
+    }
+#undef C_
+}
+
+hipError_t launch_reduce_mixed(const double *r, const double *mass, const int64_t *eoff, const int8_t *Ne,
+                               int64_t n_elem, double *partials, int nblocks, double *final13, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_partial_mixed, dim3(nblocks), dim3(256), 0, s, r, mass, eoff, Ne, n_elem, partials);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partials, nblocks, final13);
+    return hipGetLastError();
 }
 
 bool shape_supported(int N, int B)

@@ -141,27 +141,58 @@ void apply_dir(const std::vector<xreal> &M, int rows, int cols, int dir, const x
 
 }  // namespace
 
-bool build_geometry(const hdg_mesh_desc &d, int P, HostGeometry &g, std::string &msg)
+void gll_interp(int Plo, int Phi, std::vector<double> &I)
 {
-    const int N = P + 1, N3 = N * N * N, Pg = d.geom_order, G1 = Pg + 1, G3 = G1 * G1 * G1;
+    std::vector<xreal> xl, wl, Dl, xh, wh, Dh;
+    gll_rule_x(Plo, xl, wl, Dl);
+    gll_rule_x(Phi, xh, wh, Dh);
+    const std::vector<xreal> Ix = interp_matrix(xl, xh);
+    I.assign(Ix.begin(), Ix.end());
+}
+
+bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg)
+{
+    const int Pg = d.geom_order, G1 = Pg + 1, G3 = G1 * G1 * G1;
     const int64_t ne = d.n_elem;
-    g.N = N;
-    g.N3 = N3;
-    std::vector<xreal> xq, wq, Dq;
-    gll_rule_x(P, xq, wq, Dq);
-    g.xi.assign(xq.begin(), xq.end());
-    g.w.assign(wq.begin(), wq.end());
-    g.D.assign(Dq.begin(), Dq.end());
+    // rules of every order in use, in extended precision
+    std::vector<xreal> xqs[kMaxN + 1], wqs[kMaxN + 1], Dqs[kMaxN + 1], Is[kMaxN + 1];
     std::vector<xreal> gnodes(G1);
     for (int k = 0; k < G1; ++k) gnodes[k] = -1.0L + 2.0L * k / Pg;
-    const std::vector<xreal> I = interp_matrix(gnodes, xq);
-    g.x.assign(ne * 3 * N3, 0.0);
-    g.J.assign(ne * N3, 0.0);
-    g.Ja.assign(ne * 9 * N3, 0.0);
+    g.Ne.resize(ne);
+    g.off.resize(ne);
+    int64_t tot = 0;
+    for (int64_t e = 0; e < ne; ++e) {
+        const int N = d.P[e] + 1;
+        g.Ne[e] = N;
+        g.off[e] = tot;
+        tot += (int64_t)N * N * N;
+        if (xqs[N].empty()) {
+            gll_rule_x(N - 1, xqs[N], wqs[N], Dqs[N]);
+            Is[N] = interp_matrix(gnodes, xqs[N]);
+        }
+    }
+    g.nodes = tot;
+    g.N = g.Ne[0];
+    g.N3 = g.N * g.N * g.N;
+    for (int N = 2; N <= kMaxN; ++N) {
+        if (xqs[N].empty()) continue;
+        g.xis[N].assign(xqs[N].begin(), xqs[N].end());
+        g.ws[N].assign(wqs[N].begin(), wqs[N].end());
+        g.Ds[N].assign(Dqs[N].begin(), Dqs[N].end());
+    }
+    g.xi = g.xis[g.N];
+    g.w = g.ws[g.N];
+    g.D = g.Ds[g.N];
+    g.x.assign(tot * 3, 0.0);
+    g.J.assign(tot, 0.0);
+    g.Ja.assign(tot * 9, 0.0);
     g.delta.assign(ne, 0.0);
     std::atomic<int64_t> bad{-1};
 
     auto body = [&](int64_t e) {
+        const int N = g.Ne[e], N3 = N * N * N;
+        const std::vector<xreal> &wq = wqs[N], &Dq = Dqs[N], &I = Is[N];
+        const int64_t o = g.off[e];
         std::vector<xreal> t1(N * G1 * G1), t2(N * N * G1), loc(3 * N3), dX(9 * N3), V(3 * N3), dV(9 * N3);
         std::vector<xreal> rel(G3);
         const double *Xe = d.xyz_geom + e * 3 * G3;
@@ -173,7 +204,7 @@ bool build_geometry(const hdg_mesh_desc &d, int P, HostGeometry &g, std::string 
             apply_dir(I, N, G1, 0, rel.data(), G1, G1, G1, t1.data());
             apply_dir(I, N, G1, 1, t1.data(), N, G1, G1, t2.data());
             apply_dir(I, N, G1, 2, t2.data(), N, N, G1, &loc[c * N3]);
-            for (int n = 0; n < N3; ++n) g.x[(e * 3 + c) * N3 + n] = (double)((xreal)Xe[c * G3] + loc[c * N3 + n]);
+            for (int n = 0; n < N3; ++n) g.x[3 * o + c * N3 + n] = (double)((xreal)Xe[c * G3] + loc[c * N3 + n]);
         }
         for (int c = 0; c < 3; ++c)
             for (int k = 0; k < 3; ++k) apply_dir(Dq, N, N, k, &loc[c * N3], N, N, N, &dX[(c * 3 + k) * N3]);
@@ -183,7 +214,7 @@ bool build_geometry(const hdg_mesh_desc &d, int P, HostGeometry &g, std::string 
             const xreal J = m(0, 0) * (m(1, 1) * m(2, 2) - m(1, 2) * m(2, 1))
                           - m(0, 1) * (m(1, 0) * m(2, 2) - m(1, 2) * m(2, 0))
                           + m(0, 2) * (m(1, 0) * m(2, 1) - m(1, 1) * m(2, 0));
-            g.J[e * N3 + n] = (double)J;
+            g.J[o + n] = (double)J;
             const int a = n % N, b = (n / N) % N, c = n / (N * N);
             vol += wq[a] * wq[b] * wq[c] * J;
             if (!(J > 0.0L)) bad.store(e);
@@ -199,9 +230,9 @@ bool build_geometry(const hdg_mesh_desc &d, int P, HostGeometry &g, std::string 
                     if (j != k) apply_dir(Dq, N, N, j, &V[k * N3], N, N, N, &dV[(k * 3 + j) * N3]);
             for (int p = 0; p < N3; ++p) {
                 auto dv = [&](int k, int j) { return dV[(k * 3 + j) * N3 + p]; };
-                g.Ja[((e * 3 + 0) * 3 + n) * N3 + p] = (double)(-(dv(2, 1) - dv(1, 2)));
-                g.Ja[((e * 3 + 1) * 3 + n) * N3 + p] = (double)(-(dv(0, 2) - dv(2, 0)));
-                g.Ja[((e * 3 + 2) * 3 + n) * N3 + p] = (double)(-(dv(1, 0) - dv(0, 1)));
+                g.Ja[9 * o + (0 * 3 + n) * N3 + p] = (double)(-(dv(2, 1) - dv(1, 2)));
+                g.Ja[9 * o + (1 * 3 + n) * N3 + p] = (double)(-(dv(0, 2) - dv(2, 0)));
+                g.Ja[9 * o + (2 * 3 + n) * N3 + p] = (double)(-(dv(1, 0) - dv(0, 1)));
             }
         }
     };

@@ -19,8 +19,8 @@ HDG_OK, HDG_EINVAL, HDG_ENOMEM, HDG_EHIP, HDG_EUNSUPPORTED, HDG_EMESH, HDG_ENONF
 HDG_F64, HDG_F32 = 0, 1
 HDG_WALL, HDG_FARFIELD = -1, -2
 HDG_LES_NONE, HDG_LES_SMAGORINSKY, HDG_LES_VREMAN = 0, 1, 2
-HDG_KERNEL_VISCOUS, HDG_KERNEL_RESIDUAL = 0, 1
-KERNEL_NAMES = {0: "viscous", 1: "residual"}
+HDG_KERNEL_VISCOUS, HDG_KERNEL_RESIDUAL, HDG_KERNEL_MORTAR = 0, 1, 2
+KERNEL_NAMES = {0: "viscous", 1: "residual", 2: "mortar"}
 
 EXPORTED = [
     "hdg_init", "hdg_finalize", "hdg_mesh_create", "hdg_mesh_destroy", "hdg_mesh_set_flags",
@@ -152,15 +152,24 @@ class Context:
 
 
 class Mesh:
-    """Owner of an ``hdg_mesh`` handle plus its sizes."""
+    """Owner of an ``hdg_mesh`` handle plus its sizes.  With one order the
+    state has shape (n_elem, 4, N^3); with several it is flat, element after
+    element ([4][N_e^3] each), and ``offsets`` gives each element's first node."""
 
-    def __init__(self, ctx: Context, handle: int, n_elem: int, P: int):
-        self.ctx, self.handle, self.n_elem, self.P = ctx, handle, n_elem, P
-        self.N3 = (P + 1) ** 3
+    def __init__(self, ctx: Context, handle: int, n_elem: int, P):
+        Ps = np.broadcast_to(np.asarray(P, dtype=np.int32), (n_elem,)).copy()
+        self.ctx, self.handle, self.n_elem = ctx, handle, n_elem
+        self.Ps = Ps
+        self.uniform = bool(np.all(Ps == Ps[0]))
+        self.P = int(Ps[0]) if self.uniform else None
+        self.N3 = (self.P + 1) ** 3 if self.uniform else None
+        n3 = (Ps.astype(np.int64) + 1) ** 3
+        self.nodes = int(n3.sum())
+        self.offsets = np.concatenate([[0], np.cumsum(n3)[:-1]])
 
     @property
     def state_shape(self):
-        return (self.n_elem, 4, self.N3)
+        return (self.n_elem, 4, self.N3) if self.uniform else (4 * self.nodes,)
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -174,11 +183,12 @@ def hdg_init(device: int = 0) -> Context:
     return Context(h.value, device)
 
 
-def hdg_mesh_create(ctx: Context, mesh, P: int, flag, params: Params) -> Mesh:
-    """Create a device mesh from a ``workloads.HexMesh``-like object."""
+def hdg_mesh_create(ctx: Context, mesh, P, flag, params: Params) -> Mesh:
+    """Create a device mesh from a ``workloads.HexMesh``-like object; P is one
+    order or one per element."""
     ne = int(mesh.xyz_geom.shape[0])
     keep = dict(
-        P=np.full(ne, P, dtype=np.int32),
+        P=np.ascontiguousarray(np.broadcast_to(np.asarray(P, dtype=np.int32), (ne,))),
         xyz=np.ascontiguousarray(mesh.xyz_geom, dtype=np.float64),
         flag=np.ascontiguousarray(flag, dtype=np.uint8),
         nbr=np.ascontiguousarray(mesh.nbr, dtype=np.int32),
@@ -198,7 +208,7 @@ def hdg_mesh_create(ctx: Context, mesh, P: int, flag, params: Params) -> Mesh:
     d.orient = keep["o"].ctypes.data_as(C.POINTER(C.c_int8))
     h = C.c_void_p()
     _check(lib().hdg_mesh_create(ctx.handle, C.byref(d), C.byref(params), C.byref(h)), "hdg_mesh_create")
-    return Mesh(ctx, h.value, ne, P)
+    return Mesh(ctx, h.value, ne, keep["P"])
 
 
 def hdg_mesh_set_flags(mesh: Mesh, flag):
@@ -220,7 +230,7 @@ def hdg_mesh_info(mesh: Mesh) -> dict:
 
 
 def hdg_mesh_node_coords(mesh: Mesh) -> np.ndarray:
-    x = np.zeros((mesh.n_elem, 3, mesh.N3))
+    x = np.zeros((mesh.n_elem, 3, mesh.N3) if mesh.uniform else (3 * mesh.nodes,))
     _check(lib().hdg_mesh_node_coords(mesh.handle, x.ctypes.data_as(C.POINTER(C.c_double))), "node_coords")
     return x
 
@@ -258,8 +268,8 @@ def _check_state(mesh: Mesh, t, name: str, f32: bool = False):
         return
     import torch
     dt = torch.float32 if f32 else torch.float64
-    if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or t.numel() != 4 * mesh.n_elem * mesh.N3:
-        raise ValueError(f"{name}: need a contiguous {dt} CUDA tensor of {4 * mesh.n_elem * mesh.N3} entries")
+    if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or t.numel() != 4 * mesh.nodes:
+        raise ValueError(f"{name}: need a contiguous {dt} CUDA tensor of {4 * mesh.nodes} entries")
 
 
 def hdg_residual(mesh: Mesh, q, r, prec: int = HDG_F64, stream=None):

@@ -1,0 +1,168 @@
+"""Meshes of mixed polynomial order on the GPU (mortar faces between orders)
+against the FP64 oracle, element after element."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2403_05463_amd import hdg, workloads as W
+from parity import TOL_F64
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_cuda):
+    return hdg.hdg_init(0)
+
+
+def _fields(om, arr):
+    """Per-field flat vectors of an element-after-element array."""
+    return [np.concatenate([om.element(arr, e, 4)[f] for e in range(om.n_elem)]) for f in range(4)]
+
+
+def _mass(orc, om):
+    J, _ = om.metrics()
+    out = np.empty(om.nodes)
+    for e in range(om.n_elem):
+        P = int(om.Ps[e])
+        _, w, _ = orc.lgl(P)
+        n3 = (P + 1) ** 3
+        o = int(om.offsets[e])
+        out[o:o + n3] = J[o:o + n3] * np.einsum("k,j,i->kji", w, w, w).ravel()
+    return out
+
+
+def _errors(om, mass, got, ref):
+    """Per-field relative errors, floored as in the one-order parity tests."""
+    g, r = _fields(om, got), _fields(om, ref)
+    l2 = np.array([np.sqrt((mass * (a - b) ** 2).sum()) for a, b in zip(g, r)])
+    l2r = np.array([np.sqrt((mass * b ** 2).sum()) for b in r])
+    mx = np.array([np.abs(a - b).max() for a, b in zip(g, r)])
+    mxr = np.array([np.abs(b).max() for b in r])
+    return l2 / np.maximum(l2r, 1e-3 * l2r.max()), mx / np.maximum(mxr, 1e-3 * mxr.max())
+
+
+def _state(om, seed, amp=0.05):
+    X = om.node_coords()
+    out = np.empty(4 * om.nodes)
+    for e in range(om.n_elem):
+        blk = W.taylor_green_state(om.element(X, e, 3)[None], amp, seed + e)[0]
+        om.element(out, e, 4)[:] = blk
+    return out
+
+
+def _cases():
+    m = W.periodic_box(3, Pg=1, curve_amp=0.25)
+    f = W.bernoulli_mask(m.n_elem, 0.5, 2)
+    yield "warped box 3^3, P 2..6", m, f, W.mixed_orders(f, 2), dict(les_model=1, C_les=0.1, mixed_face=0)
+    m2, _ = W.reorient(W.periodic_box(4, Pg=1, curve_amp=0.2), seed=6)
+    f2 = W.bernoulli_mask(m2.n_elem, 0.4, 6)
+    yield "reoriented warped box 4^3, P 2..6, Vreman, reading B", m2, f2, W.mixed_orders(f2, 6), \
+        dict(les_model=2, C_les=0.07, mixed_face=1)
+    g = W.naca_ogrid(48, 16, 4, Pg=1)
+    fg = W.naca_mask(g)
+    yield "O-grid 48x16x4 trilinear, P 2..6", g, fg, W.mixed_orders(fg, 9), \
+        dict(les_model=1, C_les=0.1, mixed_face=0, nu=1e-3, q_inf=W.free_stream(20.0))
+
+
+def _prm(kw):
+    base = dict(c0sq=25.0, nu=5e-3, les_model=1, C_les=0.1, mixed_face=0, q_inf=(0, 0, 0, 0))
+    base.update(kw)
+    return base
+
+
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_mixed_order_residual_parity(orc, torch_cuda, ctx, case):
+    torch = torch_cuda
+    name, mesh, flag, P, kw = list(_cases())[case]
+    prm = _prm(kw)
+    _say(f"mixed-order residual: {name}, orders {np.bincount(P)[2:]}")
+    om = orc.OracleMesh(mesh, P, flag)
+    q = _state(om, 10 + case)
+    ref = om.residual(orc.make_params(**prm), q)
+    m = hdg.hdg_mesh_create(ctx, mesh, P, flag, hdg.make_params(**prm))
+    qd = torch.from_numpy(q).cuda()
+    r = torch.empty_like(qd)
+    hdg.hdg_residual(m, qd, r)
+    torch.cuda.synchronize()
+    l2, mx = _errors(om, _mass(orc, om), r.cpu().numpy(), ref)
+    _say(f"{name}: per-field L2 {l2}, max {mx}")
+    assert max(l2.max(), mx.max()) <= TOL_F64
+    # FP32 residual on the same mesh
+    r32 = torch.empty(qd.shape, dtype=torch.float32, device="cuda")
+    hdg.hdg_residual(m, qd, r32, prec=hdg.HDG_F32)
+    torch.cuda.synchronize()
+    l2f, mxf = _errors(om, _mass(orc, om), r32.cpu().numpy().astype(np.float64), ref)
+    _say(f"{name} FP32: per-field L2 {l2f}, max {mxf}")
+    assert l2f[1:].max() <= 1e-5 and mxf[1:].max() <= 1e-4
+    assert l2f.max() > 1e-10
+
+
+def test_mixed_order_rk_parity(orc, torch_cuda, ctx):
+    torch = torch_cuda
+    name, mesh, flag, P, kw = list(_cases())[0]
+    prm = _prm(kw)
+    om = orc.OracleMesh(mesh, P, flag)
+    q = _state(om, 3)
+    _say(f"mixed-order RK, 3 steps: {name}")
+    ref = om.rk3(orc.make_params(**prm), q, 2e-3, 3)
+    m = hdg.hdg_mesh_create(ctx, mesh, P, flag, hdg.make_params(**prm))
+    qd = torch.from_numpy(q).cuda()
+    dq = torch.empty_like(qd)
+    hdg.hdg_rk3_steps(m, qd, dq, 2e-3, 3)
+    torch.cuda.synchronize()
+    err = np.abs(qd.cpu().numpy() - ref).max() / np.abs(ref).max()
+    _say(f"state error {err:.3e}")
+    assert err < 1e-13
+
+
+def test_mixed_order_conservation_freestream_and_shapes(orc, torch_cuda, ctx):
+    torch = torch_cuda
+    name, mesh, flag, P, kw = list(_cases())[1]
+    prm = hdg.make_params(**_prm(kw))
+    _say(f"conservation, free stream and launch shapes: {name}")
+    om = orc.OracleMesh(mesh, P, flag)
+    mass = _mass(orc, om)
+    m = hdg.hdg_mesh_create(ctx, mesh, P, flag, prm)
+    rng = np.random.default_rng(5)
+    qd = torch.from_numpy(rng.uniform(-1, 1, 4 * om.nodes)).cuda()
+    r = torch.empty_like(qd)
+    hdg.hdg_residual(m, qd, r)
+    red = hdg.hdg_reduce(m, r)
+    R = r.cpu().numpy()
+    for f, Rf in enumerate(_fields(om, R)):
+        mag = np.abs(mass * Rf).sum()
+        assert abs((mass * Rf).sum()) < 1e-13 * mag, f
+        assert abs(red["sum"][f] - (mass * Rf).sum()) < 1e-12 * mag
+    qc = np.empty(4 * om.nodes)
+    for e in range(om.n_elem):
+        om.element(qc, e, 4)[:] = np.array([0.3, 1.0, -0.5, 0.2])[:, None]
+    qcd = torch.from_numpy(qc).cuda()
+    hdg.hdg_residual(m, qcd, r)
+    torch.cuda.synchronize()
+    assert np.abs(r.cpu().numpy()).max() < 1e-10
+    # every launch shape of every order present gives the same bits
+    hdg.hdg_residual(m, qd, r)
+    torch.cuda.synchronize()
+    base = r.cpu().numpy()
+    for B, pers in [(256, True), (512, False), (512, True)]:
+        for N in sorted(set(int(p) + 1 for p in P)):
+            for k in (hdg.HDG_KERNEL_VISCOUS, hdg.HDG_KERNEL_RESIDUAL):
+                hdg.hdg_mesh_set_launch(m, k, hdg.HDG_F64, N, 512 if N >= 7 else B, pers)
+        hdg.hdg_residual(m, qd, r)
+        torch.cuda.synchronize()
+        assert np.array_equal(r.cpu().numpy(), base)

@@ -254,9 +254,10 @@ def test_timing_and_copy_probe(torch_cuda, ctx):
     dq = torch.empty_like(q)
     hdg.hdg_timing_enable(m, True)
     hdg.hdg_rk3_steps(m, q, dq, 1e-7, 2)
-    for k in hdg.KERNEL_NAMES:
+    for k in (hdg.HDG_KERNEL_VISCOUS, hdg.HDG_KERNEL_RESIDUAL):
         ms, n = hdg.hdg_timing_read(m, k)
         assert n == 6 and ms > 0
+    assert hdg.hdg_timing_read(m, hdg.HDG_KERNEL_MORTAR)[1] == 0     # one order: no mortar faces
     hdg.hdg_timing_enable(m, False)
     a = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
