@@ -77,6 +77,55 @@ def cpu_baseline(w, q0, budget_s: float = 12.0) -> dict:
             "sample": f"{evals} full residual evaluations of the same workload ({nodes} nodes), {el:.1f} s"}
 
 
+def mixed_leg(ctx, args, torch, hdg) -> dict:
+    """Mixed-order form: the airfoil O-grid refined twice (192 x 96 x 16,
+    trilinear) with per-element orders 2..6 (higher where viscous), faces
+    between orders coupled through mortars; every order's tiles and the
+    mortar kernels of an RK stage replayed from one captured graph."""
+    from paper_2403_05463_amd import workloads as W
+    t0 = time.perf_counter()
+    w = W.naca_mixed()
+    q0 = W.initial_state(w, None)
+    t1 = time.perf_counter()
+    mesh = hdg.hdg_mesh_create(ctx, w.mesh, w.P, w.flag, hdg.make_params(**w.params))
+    t2 = time.perf_counter()
+    nodes = mesh.nodes
+    P = np.asarray(w.P)
+    nonconf = int(((w.mesh.nbr >= 0) & (P[np.maximum(w.mesh.nbr, 0)] != P[:, None])).sum() // 2)
+    print(f"[bench] {w.name}: {nodes} nodes, {nonconf} mortar faces, set-up {t2 - t1:.1f} s",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    q = torch.from_numpy(q0).cuda()
+    dq = torch.empty_like(q)
+    hdg.hdg_mesh_autotune(mesh, q, reps=2, stream=stream)
+    res = {"config": {"workload": w.name, "elements": w.mesh.n_elem, "nodes": nodes, "dof": 4 * nodes,
+                      "orders": {int(k): int(v) for k, v in zip(*np.unique(P, return_counts=True))},
+                      "viscous_fraction": float(np.mean(w.flag)), "mortar_faces": nonconf, "geometry": "trilinear",
+                      "dt": w.dt, "host_generation_s": t1 - t0, "mesh_create_s": t2 - t1}}
+    steps = args.mixed_steps
+    for prec, tag in ((hdg.HDG_F64, "f64"), (hdg.HDG_F32, "f32")):
+        q.copy_(torch.from_numpy(q0))
+        hdg.hdg_rk3_steps(mesh, q, dq, w.dt, 2, prec=prec, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        hdg.hdg_rk3_steps(mesh, q, dq, w.dt, steps, prec=prec, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        hdg.hdg_timing_enable(mesh, True)
+        hdg.hdg_rk3_steps(mesh, q, dq, w.dt, steps, prec=prec, stream=stream)
+        kern = {name: hdg.hdg_timing_read(mesh, k) for k, name in hdg.KERNEL_NAMES.items()}
+        hdg.hdg_timing_enable(mesh, False)
+        red = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
+        res[tag] = {"value": nodes * 4 * 3 * steps / (ms / 1e3), "unit": "DOF-residual evals/s",
+                    "ms_per_step": ms / steps, "state_finite": bool(red["finite"]),
+                    "kernel_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
+                    "launches_per_step": {k: v[1] / steps for k, v in kern.items()}}
+    del q, dq, mesh
+    return res
+
+
 def serving_leg(ctx, args, torch, hdg) -> dict:
     """Request stream: Poisson arrivals of independent periodic-box solves (n^3
     elements, n uniform in 4..24, P uniform in 2..6, 20-80 % viscous, nu in
@@ -142,6 +191,8 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-mb", type=int, default=1024, help="size of the stream-copy probe")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-order airfoil leg")
+    ap.add_argument("--mixed-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
@@ -268,6 +319,8 @@ def main(argv=None) -> int:
                          "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern32.items()},
                          "roofline": roofline(kern32, True), "dtype": "f32 residual, f64 state"}
     del q, dq
+    if not args.no_mixed:
+        out["mixed_order"] = mixed_leg(ctx, args, torch, hdg)
     if not args.no_serving:
         out["serving"] = serving_leg(ctx, args, torch, hdg)
     if not args.no_cpu_baseline:

@@ -887,7 +887,7 @@ hdg_status hdg_mesh_autotune(hdg_mesh *m, const double *q, int32_t reps, void *s
     if (!m || !q || reps < 1) return fail(HDG_EINVAL, "autotune: need a mesh, a state and reps >= 1");
     HDG_HIP(hipSetDevice(m->ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    const size_t nq = (size_t)m->ne * 4 * m->N3;
+    const size_t nq = (size_t)m->nodes * 4;     // every order: the RK register of the whole mesh
     double *dq = nullptr;
     HDG_HIP(hipMalloc((void **)&dq, nq * sizeof(double)));
     hipEvent_t e0, e1;

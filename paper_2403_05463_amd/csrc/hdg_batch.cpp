@@ -259,7 +259,7 @@ hdg_status hdg_batch_info(const hdg_batch *b, int32_t *n_members, int64_t *n_ele
         if (s.mesh) {
             ++nm;
             ne += s.mesh->ne;
-            nn += s.mesh->ne * s.mesh->N3;
+            nn += s.mesh->nodes;
         }
     if (n_members) *n_members = nm;
     if (n_elements) *n_elements = ne;
@@ -321,7 +321,7 @@ hdg_status hdg_batch_rk3_steps(hdg_batch *b, int32_t nsteps, hdg_prec prec, void
         // odd number of stages in total: the states sit in the ping-pong buffers
         for (const auto &sl : b->slots)
             if (sl.mesh)
-                HDG_HIP(hipMemcpyAsync(sl.q, sl.mesh->qpp, (size_t)sl.mesh->ne * 4 * sl.mesh->N3 * sizeof(double),
+                HDG_HIP(hipMemcpyAsync(sl.q, sl.mesh->qpp, (size_t)sl.mesh->nodes * 4 * sizeof(double),
                                        hipMemcpyDeviceToDevice, s));
     }
     return HDG_OK;

@@ -323,14 +323,16 @@ def naca_thickness(x, t=0.12):
 
 
 def naca_ogrid(ni: int = 96, nj: int = 48, nk: int = 8, Pg: int = 2, radius: float = 20.0,
-               growth: float = 1.128, span: float = 1.0, t: float = 0.12) -> HexMesh:
+               growth: float = 1.128, span: float = 1.0, t: float = 0.12, growth_layers: int = 48) -> HexMesh:
     """Extruded O-grid around a NACA 00xx section (chord 1, leading edge at the origin).
 
     Around-index i runs trailing edge -> lower surface -> leading edge -> upper
     surface (periodic); j runs from the wall (faces eta-, WALL) to a circle of
     ``radius`` about mid-chord (faces eta+, FARFIELD) with geometric growth;
-    k is the periodic span of length ``span``.  Each element is the degree-Pg
-    Lagrange interpolant of the analytic map.
+    k is the periodic span of length ``span``.  The radial map is fixed (growth
+    per layer of a ``growth_layers``-layer grid), so more radial elements
+    refine the same grid.  Each element is the degree-Pg Lagrange interpolant
+    of the analytic map.
     """
     S = ni * Pg           # control points around (periodic)
     R = nj * Pg + 1       # radial
@@ -348,7 +350,7 @@ def naca_ogrid(ni: int = 96, nj: int = 48, nk: int = 8, Pg: int = 2, radius: flo
     xo = 0.5 + radius * np.cos(th)
     yo = radius * np.sin(th)
     r = np.arange(R) / (nj * Pg)
-    fr = (growth ** (nj * r) - 1.0) / (growth ** nj - 1.0)
+    fr = (growth ** (growth_layers * r) - 1.0) / (growth ** growth_layers - 1.0)
     Xg = (1 - fr[None, :]) * xw[:, None] + fr[None, :] * xo[:, None]   # (S, R)
     Yg = (1 - fr[None, :]) * yw[:, None] + fr[None, :] * yo[:, None]
     zg = span * np.arange(Kz) / (nk * Pg)
@@ -473,6 +475,24 @@ def uniform_inflow_state(n_elem: int, N3: int, alpha_deg: float, u_inf: float,
     return q
 
 
+def uniform_inflow_state_flat(P: np.ndarray, alpha_deg: float, u_inf: float, noise: float,
+                              seed: int) -> np.ndarray:
+    """The same stream for per-element orders: element after element, [4][N_e^3]
+    each, noise drawn for all velocity entries in that order."""
+    a = math.radians(alpha_deg)
+    n3 = (np.asarray(P, dtype=np.int64) + 1) ** 3
+    q = np.zeros(4 * int(n3.sum()))
+    off = 4 * np.concatenate([[0], np.cumsum(n3)[:-1]])
+    rng = np.random.default_rng(seed)
+    for e, (o, n) in enumerate(zip(off, n3)):
+        q[o + n:o + 2 * n] = u_inf * math.cos(a)
+        q[o + 2 * n:o + 3 * n] = u_inf * math.sin(a)
+    if noise > 0:
+        vel = np.concatenate([np.arange(o + n, o + 4 * n) for o, n in zip(off, n3)])
+        q[vel] += rng.uniform(-noise * u_inf, noise * u_inf, size=vel.size)
+    return q
+
+
 def free_stream(alpha_deg: float, u_inf: float = 1.0) -> np.ndarray:
     a = math.radians(alpha_deg)
     return np.array([0.0, u_inf * math.cos(a), u_inf * math.sin(a), 0.0])
@@ -508,7 +528,7 @@ def cfl_dt(mesh: HexMesh, P: int, q0: np.ndarray, c0sq: float, cfl: float = 0.5)
 class Workload:
     name: str
     mesh: HexMesh
-    P: int
+    P: int | np.ndarray        # one order, or one per element
     flag: np.ndarray
     params: dict
     dt: float | None
@@ -558,7 +578,25 @@ def tgv_box_precision(n=32, P=5) -> Workload:
                     dict(amp=0.0, seed=0))
 
 
+def naca_mixed(ni: int = 192, nj: int = 96, nk: int = 16, seed: int = 0) -> Workload:
+    """The airfoil O-grid refined twice (192 x 96 x 16 elements) with a per-element
+    order drawn from P = 2..6, higher orders in the viscous region (wall band
+    and wake wedge); trilinear elements, so every face between orders has
+    exact geometry at its lower order.  Re = 1e4, alpha = 20 deg, inflow +
+    1 % noise."""
+    mesh = naca_ogrid(ni, nj, nk, Pg=1)
+    flag = naca_mask(mesh)
+    P = mixed_orders(flag, seed)
+    params = dict(c0sq=25.0, nu=1e-4, les_model=1, C_les=0.1, mixed_face=0, q_inf=free_stream(20.0))
+    return Workload(f"naca0012_ogrid_{ni}x{nj}x{nk}_mixedP2-6", mesh, P, flag, params, 5e-9, 100, "inflow",
+                    dict(alpha_deg=20.0, u_inf=1.0, noise=0.01, seed=0))
+
+
 def initial_state(w: Workload, node_xyz: np.ndarray | None) -> np.ndarray:
+    if np.ndim(w.P) > 0:
+        if w.state != "inflow":
+            raise ValueError("per-element orders: inflow states only")
+        return uniform_inflow_state_flat(w.P, **w.state_args)
     N3 = (w.P + 1) ** 3
     if w.state == "tgv":
         if node_xyz is None:

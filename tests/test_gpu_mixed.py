@@ -166,3 +166,22 @@ def test_mixed_order_conservation_freestream_and_shapes(orc, torch_cuda, ctx):
         hdg.hdg_residual(m, qd, r)
         torch.cuda.synchronize()
         assert np.array_equal(r.cpu().numpy(), base)
+
+
+def test_mixed_order_autotune_keeps_state_and_results(orc, torch_cuda, ctx):
+    """The autotuner's scratch register covers every node of a mesh of mixed
+    order; the state is untouched and the residual unchanged."""
+    torch = torch_cuda
+    name, mesh, flag, P, kw = list(_cases())[0]
+    m = hdg.hdg_mesh_create(ctx, mesh, P, flag, hdg.make_params(**_prm(kw)))
+    om = orc.OracleMesh(mesh, P, flag)
+    q0 = _state(om, 21)
+    qd = torch.from_numpy(q0).cuda()
+    r0, r1 = torch.empty_like(qd), torch.empty_like(qd)
+    hdg.hdg_residual(m, qd, r0)
+    _say(f"autotune on a mixed-order mesh: {name}")
+    hdg.hdg_mesh_autotune(m, qd, reps=1)
+    hdg.hdg_residual(m, qd, r1)
+    torch.cuda.synchronize()
+    assert np.array_equal(qd.cpu().numpy(), q0)
+    assert torch.equal(r0, r1)
