@@ -177,16 +177,16 @@ hdg_status upload_plans(hdg_mesh *m)
             }
         }
     }
-    // mortar lists by higher order: lift (a flagged side), flux (all)
+    // mortar lists by (Nl, Nh): lift (a flagged side), flux (all)
     if (!m->mort_h.empty()) {
         std::vector<int32_t> lists;
         for (int kind = 0; kind < 2; ++kind)
-            for (int Nh = 0; Nh <= hdg::kMaxN + 1; ++Nh) {
-                m->mlist_off[kind][Nh] = (int64_t)lists.size();
-                if (Nh > hdg::kMaxN) continue;
+            for (int key = 0; key <= hdg::kPairKeys; ++key) {
+                m->mlist_off[kind][key] = (int64_t)lists.size();
+                if (key == hdg::kPairKeys) continue;
                 for (size_t k = 0; k < m->mort_h.size(); ++k) {
                     const hdg::MortarRef &r = m->mort_h[k];
-                    if (r.Nh != Nh) continue;
+                    if (hdg::pair_key(r.Nl, r.Nh) != key) continue;
                     if (kind == 0 && !m->flag[r.eh] && !m->flag[r.el]) continue;
                     lists.push_back((int32_t)k);
                 }
@@ -289,22 +289,23 @@ hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi ep
         // mortars: BR1 lift terms (kind 0) before the viscous kernels, numerical
         // fluxes (kind 1) after them and before the residual kernels
         if (!m->mort_h.empty())
-            for (int Nh = 2; Nh <= hdg::kMaxN; ++Nh) {
-                StageArgs a{};
-                a.mem = m->member;
-                a.I64 = m->ctx->I64;
-                a.I32 = m->ctx->I32;
-                a.W64 = m->ctx->W64;
-                a.W32 = m->ctx->W32;
-                a.q_in = q;
-                a.mlist = m->mlist + m->mlist_off[kind][Nh];
-                a.mcount = (int32_t)(m->mlist_off[kind][Nh + 1] - m->mlist_off[kind][Nh]);
-                if (a.mcount == 0) continue;
-                hdg_status st = timed(m, HDG_KERNEL_MORTAR, s, [&] {
-                    return kind == 0 ? hdg::launch_mortar_lift(Nh, f32, a, s) : hdg::launch_mortar_flux(Nh, f32, a, s);
-                });
-                if (st != HDG_OK) return st;
-            }
+            for (int Nh = 3; Nh <= hdg::kMaxN; ++Nh)
+                for (int Nl = 2; Nl < Nh; ++Nl) {
+                    const int key = hdg::pair_key(Nl, Nh);
+                    StageArgs a{};
+                    a.mem = m->member;
+                    a.I64 = m->ctx->I64;
+                    a.I32 = m->ctx->I32;
+                    a.W64 = m->ctx->W64;
+                    a.W32 = m->ctx->W32;
+                    a.q_in = q;
+                    a.mlist = m->mlist + m->mlist_off[kind][key];
+                    a.mcount = (int32_t)(m->mlist_off[kind][key + 1] - m->mlist_off[kind][key]);
+                    if (a.mcount == 0) continue;
+                    hdg_status st = timed(m, HDG_KERNEL_MORTAR, s,
+                                          [&] { return hdg::launch_mortar(kind == 0, Nl, Nh, f32, a, s); });
+                    if (st != HDG_OK) return st;
+                }
         for (int N = 2; N <= hdg::kMaxN; ++N) {
             hdg_status st = launch_one(m, kind, N, m->cfg[kind][pi][N], q, out, dq, epi, f32, A, B, dt, first, s, true);
             if (st != HDG_OK) return st;
@@ -339,6 +340,10 @@ hdg_status validate_desc(const hdg_mesh_desc *d, int &P)
             if (d->P[e2] != d->P[e] && 2 * d->geom_order > std::min(d->P[e], d->P[e2]))
                 return fail(HDG_EUNSUPPORTED, "element " + std::to_string(e) + " face " + std::to_string(f) +
                                                   ": a face between orders needs 2 geom_order <= the lower order");
+            if (d->P[e2] != d->P[e] &&
+                !hdg::mortar_pair_supported(std::min(d->P[e], d->P[e2]) + 1, std::max(d->P[e], d->P[e2]) + 1))
+                return fail(HDG_EUNSUPPORTED, "element " + std::to_string(e) + " face " + std::to_string(f) +
+                                                  ": no mortar kernel for this pair of orders");
             const int o = d->orient[e * 6 + f], o2 = d->orient[(int64_t)e2 * 6 + f2];
             if (o < 0 || o > 7 || o2 < 0 || o2 > 7)
                 return fail(HDG_EMESH, "element " + std::to_string(e) + ": orientation code out of range");

@@ -27,9 +27,10 @@ constexpr int kMortarBit = 1 << 7;  // face between elements of different order:
 
 // A face between elements of different order, coupled through a mortar of
 // the higher order in the higher side's face frame.  Its slab (values of the
-// compute type) holds, for the higher (h) and lower (l) side at the side's
-// own face nodes: viscous traces [3][N^2] (h, l), surface terms [4][N^2]
-// (h, l) and BR1 lift terms [9][N^2] (h, l).
+// compute type) holds, at each side's own face nodes: viscous traces [3][N^2]
+// (h, l), surface terms [4][N^2] (h, l), the higher side's mortar velocity
+// u* - u_r [3][Nh^2] (its s n is the element's own) and the lower side's
+// projected BR1 lift terms [9][Nl^2].
 struct MortarRef {
     int32_t eh, fh, el, fl;  // higher / lower order element and local face
     int32_t Nh, Nl;          // nodes per direction on each side
@@ -46,9 +47,13 @@ __host__ __device__ constexpr int64_t mslab_surf(int Nh, int Nl, bool hi)
 }
 __host__ __device__ constexpr int64_t mslab_lift(int Nh, int Nl, bool hi)
 {
-    return 7 * (Nh * Nh + Nl * Nl) + (hi ? 0 : 9 * Nh * Nh);
+    return 7 * (Nh * Nh + Nl * Nl) + (hi ? 0 : 3 * Nh * Nh);
 }
-__host__ __device__ constexpr int64_t mslab_size(int Nh, int Nl) { return 16 * (Nh * Nh + Nl * Nl); }
+__host__ __device__ constexpr int64_t mslab_size(int Nh, int Nl) { return 10 * Nh * Nh + 16 * Nl * Nl; }
+
+// Mortar lists are kept per (Nl, Nh) pair, at key Nh (kMaxN + 1) + Nl.
+constexpr int kPairKeys = (kMaxN + 1) * (kMaxN + 1);
+__host__ __device__ constexpr int pair_key(int Nl, int Nh) { return Nh * (kMaxN + 1) + Nl; }
 
 // Work is cut into tiles: up to tile_ept() elements of one polynomial order
 // and one equation class, all from one member mesh, processed together by one
@@ -157,11 +162,11 @@ enum class Epi : int { Residual = 0, RkStage = 1 };
 hipError_t launch_viscous(int N, int B, bool f32, bool persistent, const StageArgs &a, int grid, hipStream_t s);
 hipError_t launch_residual(int N, int B, Epi epi, bool f32, bool persistent, const StageArgs &a, int grid,
                            hipStream_t s);
-// Mortar kernels: one 64-lane workgroup per mortar of higher order Nh, over
-// a.mlist[0 .. a.mcount).  The lift kernel (before the viscous kernels) forms
-// the BR1 lift terms, the flux kernel (after them) the surface terms.
-hipError_t launch_mortar_lift(int Nh, bool f32, const StageArgs &a, hipStream_t s);
-hipError_t launch_mortar_flux(int Nh, bool f32, const StageArgs &a, hipStream_t s);
+// Mortar kernels of the pair (Nl, Nh) over a.mlist[0 .. a.mcount): the lift
+// kernel (before the viscous kernels) forms the BR1 lift terms, the flux
+// kernel (after them) the surface terms.  Only supported pairs launch.
+bool mortar_pair_supported(int Nl, int Nh);
+hipError_t launch_mortar(bool lift, int Nl, int Nh, bool f32, const StageArgs &a, hipStream_t s);
 // Reductions of a mesh of mixed order: element after element, eoff / Ne per element.
 hipError_t launch_reduce_mixed(const double *r, const double *mass, const int64_t *eoff, const int8_t *Ne,
                                int64_t n_elem, double *partials, int nblocks, double *final13, hipStream_t s);

@@ -343,15 +343,25 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
                 const T sf = (f & 1) ? T(1) : T(-1);
                 const FaceRef fr = load_face(M.conn, (size_t)c.e * 6 + f);
                 if (fr.code & kMortarBit) {
-                    // mortar: (u* - u_r) (s n) integrated on the mortar, minus (u - u_r) (s n)_own
                     const MortarRef mr = load_mortar(M.mort, fr.face);
-                    const gmem<const T> *lf = gp((const T *)M.mslab) + mr.slab +
-                                              mslab_lift(mr.Nh, mr.Nl, fr.code & kOwnerBit) + fidx;
+                    const bool hi = fr.code & kOwnerBit;
+                    const gmem<const T> *lf = gp((const T *)M.mslab) + mr.slab + mslab_lift(mr.Nh, mr.Nl, hi) + fidx;
+                    if (hi) {
+                        // higher side: the mortar is its own face, (u* - u) (s n)_own
 #pragma unroll
-                    for (int r = 0; r < 3; ++r)
+                        for (int r = 0; r < 3; ++r) {
+                            const T jump = (lf[r * N2] - c.qt[1 + r]) * sf * c.inv_wend;
 #pragma unroll
-                        for (int d = 0; d < 3; ++d)
-                            JG[r][d] += (lf[(r * 3 + d) * N2] - c.qt[1 + r] * sf * c.Ja[dir][d]) * c.inv_wend;
+                            for (int d = 0; d < 3; ++d) JG[r][d] += jump * c.Ja[dir][d];
+                        }
+                    } else {
+                        // lower side: (u* - u_r) (s n) integrated on the mortar, minus (u - u_r) (s n)_own
+#pragma unroll
+                        for (int r = 0; r < 3; ++r)
+#pragma unroll
+                            for (int d = 0; d < 3; ++d)
+                                JG[r][d] += (lf[(r * 3 + d) * N2] - c.qt[1 + r] * sf * c.Ja[dir][d]) * c.inv_wend;
+                    }
                 } else {
 #pragma unroll
                     for (int r = 0; r < 3; ++r) {
@@ -744,136 +754,201 @@ __global__ __launch_bounds__(B) void k_residual(StageArgs A)
 // coefficients as test functions), divided by its own face weights.  Values
 // are formed relative to each side's reference state q_r (its centre node),
 // as in the element kernels, so that only deviations enter the compute type.
+//
+// Launch shape: one kernel per (NL, NH) pair, 256 lanes per workgroup; a
+// mortar takes NH^2 lanes of one wave (64 / NH^2 mortars share a wave).  The
+// lower side's face trace is staged once per mortar in LDS; extension and
+// projection are separable contractions with the interpolation rows held in
+// registers.  The lower side's quantities on the mortar are stored in LDS in
+// its own face frame, where the projection factorises; the mortar weights
+// are symmetric under every face orientation, so w_i w_j of a node is the
+// same in either frame.
 // ---------------------------------------------------------------------------
 
-// Lower side's face-local node (a, b) value extended to mortar node (il, jl)
-// (indices in the lower side's frame on the NH grid), FP64.
-template <int NH>
-__device__ __forceinline__ double extend64(const StageArgs &A, const gmem<const double> *base, int Nl, int fl,
-                                           int il, int jl)
+template <int NL, int NH>
+struct MortarShape {
+    static constexpr int M2 = NH * NH, L2 = NL * NL;
+    static constexpr int N3H = NH * NH * NH, N3L = NL * NL * NL;
+    static constexpr int MPW = 64 / M2;          // mortars per wave
+    static constexpr int SLOTS = 4 * MPW;        // mortars per workgroup
+};
+
+// One lane's mortar and node; `valid` is false for lanes past the last mortar
+// or past the mortars a wave holds.
+template <int NL, int NH>
+struct MortarLane {
+    int slot, node, i, j, il, jl;
+    bool valid;
+    MortarRef mr;
+    const gmem<const double> *qh, *ql;
+};
+
+template <int NL, int NH>
+__device__ __forceinline__ MortarLane<NL, NH> mortar_lane(const StageArgs &A, const Member &M)
 {
-    const double *I = A.I64 + i_offset(Nl, NH);
+    using S = MortarShape<NL, NH>;
+    MortarLane<NL, NH> L;
+    const int lane = threadIdx.x & 63, sub = lane / S::M2;
+    L.node = lane - sub * S::M2;
+    L.slot = (threadIdx.x >> 6) * S::MPW + sub;
+    const int mi = blockIdx.x * S::SLOTS + L.slot;
+    L.valid = sub < S::MPW && mi < A.mcount;
+    L.i = L.node % NH;
+    L.j = L.node / NH;
+    L.il = L.jl = 0;
+    L.qh = L.ql = nullptr;
+    if (L.valid) {
+        L.mr = load_mortar(M.mort, A.mlist[mi]);
+        orient_map<NH>(L.mr.code_h & 7, L.i, L.j, L.il, L.jl);
+        const gmem<const double> *q = gp((const double *)(A.q_in ? A.q_in : M.qA));
+        L.qh = q + 4 * gp(M.eoff)[L.mr.eh];
+        L.ql = q + 4 * gp(M.eoff)[L.mr.el];
+    }
+    return L;
+}
+
+// Extension of a lower-side face field f[a + NL b] (LDS) to mortar node
+// (il, jl): sum_b I[jl][b] sum_a I[il][a] f[a, b], in FP64.
+template <int NL>
+__device__ __forceinline__ double extend_face(const double (&Ia)[NL], const double (&Ib)[NL], const double *f)
+{
     double s = 0.0;
-    for (int b = 0; b < Nl; ++b) {
+#pragma unroll 1
+    for (int b = 0; b < NL; ++b) {
         double sb = 0.0;
-        for (int a = 0; a < Nl; ++a) {
-            const int fs = (fl & 1) ? Nl - 1 : 0, d = fl >> 1;
-            const int node = d == 0 ? fs + Nl * (a + Nl * b) : d == 1 ? a + Nl * (fs + Nl * b) : a + Nl * (b + Nl * fs);
-            sb += I[il * Nl + a] * base[node];
-        }
-        s += I[jl * Nl + b] * sb;
+#pragma unroll
+        for (int a = 0; a < NL; ++a) sb += Ia[a] * f[a + NL * b];
+        s += Ib[b] * sb;
     }
     return s;
 }
 
-template <int NH, class T>
-__device__ __forceinline__ T extendT(const StageArgs &A, const gmem<const T> *tr, int Nl, int il, int jl)
+// Projection onto the lower side's face basis function (a, b): G holds the
+// integrand times the mortar weights at mortar node (il, jl) of the lower
+// frame, Wa / Wb the interpolation columns I[.][a], I[.][b].
+template <int NL, int NH, class T>
+__device__ __forceinline__ T project_face(const T (&Wa)[NH], const T (&Wb)[NH], const T *G)
 {
-    const T *I = itable<T>(A) + i_offset(Nl, NH);
     T s = T(0);
-    for (int b = 0; b < Nl; ++b) {
-        T sb = T(0);
-        for (int a = 0; a < Nl; ++a) sb += I[il * Nl + a] * tr[a + Nl * b];
-        s += I[jl * Nl + b] * sb;
+#pragma unroll 1
+    for (int jl = 0; jl < NH; ++jl) {
+        T sj = T(0);
+#pragma unroll
+        for (int il = 0; il < NH; ++il) sj += Wa[il] * G[il + NH * jl];
+        s += Wb[jl] * sj;
     }
     return s;
 }
 
-// Exact integral on the mortar of G (LDS, [k][NH^2]) against the lower side's
-// face basis function of node (a, b), over that node's face weight.
-template <int NH, class T>
-__device__ __forceinline__ T project(const StageArgs &A, const T *G, int Nl, int code_h, int a, int b)
+template <int NL, int NH, class T>
+__global__ __launch_bounds__(256) void k_mortar_lift(StageArgs A)
 {
-    const T *I = itable<T>(A) + i_offset(Nl, NH);
-    const T *wh = wtable<T>(A) + w_offset(NH);
-    const T *wl = wtable<T>(A) + w_offset(Nl);
-    T s = T(0);
-    for (int j = 0; j < NH; ++j)
-        for (int i = 0; i < NH; ++i) {
-            int il, jl;
-            orient_map<NH>(code_h & 7, i, j, il, jl);
-            s += wh[i] * wh[j] * I[il * Nl + a] * I[jl * Nl + b] * G[i + NH * j];
-        }
-    return s / (wl[a] * wl[b]);
-}
-
-template <int NH, class T>
-__global__ __launch_bounds__(64) void k_mortar_lift(StageArgs A)
-{
-    constexpr int M2 = NH * NH, N3H = NH * NH * NH;
-    __shared__ T G[9 * M2];
-    const int mi = blockIdx.x;
-    if (mi >= A.mcount) return;                  // uniform: the grid is mcount workgroups
+    using S = MortarShape<NL, NH>;
+    constexpr int M2 = S::M2, L2 = S::L2;
+    __shared__ double sq[S::SLOTS][3 * L2];     // lower side's velocity face trace
+    __shared__ T G[S::SLOTS][9 * M2];           // lower side's lift integrand, lower frame
     const Member &M = A.mem[0];
-    const MortarRef mr = load_mortar(M.mort, A.mlist[mi]);
-    const int Nl = mr.Nl, N3L = Nl * Nl * Nl;
-    const gmem<const double> *q = gp((const double *)(A.q_in ? A.q_in : M.qA));
-    const gmem<const double> *qh = q + 4 * elem_off<NH>(M, mr.eh);
-    const gmem<const double> *ql = q + 4 * gp(M.eoff)[mr.el];
-    const int lane = threadIdx.x;
-    const int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (Nl / 2) * (1 + Nl + Nl * Nl);
-    gmem<T> *slab = gp((T *)M.mslab) + mr.slab;
-    if (lane < M2) {
-        const int i = lane % NH, j = lane / NH;
-        int il, jl;
-        orient_map<NH>(mr.code_h & 7, i, j, il, jl);
-        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (mr.geo + lane);
-        const T sn[3] = {g[0] * g[3], g[1] * g[3], g[2] * g[3]};
-        const int nodeh = face_node<NH>(mr.fh, i, j);
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const double uh = qh[(1 + r) * N3H + nodeh];
-            const double ul = extend64<NH>(A, ql + (1 + r) * N3L, Nl, mr.fl, il, jl);
-            const double us = 0.5 * (uh + ul);
-            const T dh = (T)(us - qh[(1 + r) * N3H + crefh]);
-            const T dl = (T)(us - ql[(1 + r) * N3L + crefl]);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                slab[mslab_lift(NH, Nl, true) + (r * 3 + d) * M2 + lane] = dh * sn[d];
-                G[(r * 3 + d) * M2 + lane] = -dl * sn[d];
-            }
+    const MortarLane<NL, NH> L = mortar_lane<NL, NH>(A, M);
+    if (L.valid) {
+        for (int v = L.node; v < 3 * L2; v += M2) {
+            const int r = v / L2, ab = v - r * L2;
+            sq[L.slot][v] = L.ql[(1 + r) * S::N3L + face_node<NL>(L.mr.fl, ab % NL, ab / NL)];
         }
     }
     __syncthreads();
-    if (lane < Nl * Nl) {
-        const int a = lane % Nl, b = lane / Nl;
-        for (int k = 0; k < 9; ++k)
-            slab[mslab_lift(NH, Nl, false) + k * Nl * Nl + lane] = project<NH, T>(A, G + k * M2, Nl, mr.code_h, a, b);
+    if (L.valid) {
+        const double *I = A.I64 + i_offset(NL, NH);
+        const T *wh = wtable<T>(A) + w_offset(NH);
+        double Ia[NL], Ib[NL];
+#pragma unroll
+        for (int a = 0; a < NL; ++a) {
+            Ia[a] = I[L.il * NL + a];
+            Ib[a] = I[L.jl * NL + a];
+        }
+        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (L.mr.geo + L.node);
+        const T w2 = wh[L.i] * wh[L.j];
+        const T sn[3] = {g[0] * g[3] * w2, g[1] * g[3] * w2, g[2] * g[3] * w2};
+        const int nodeh = face_node<NH>(L.mr.fh, L.i, L.j);
+        constexpr int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (NL / 2) * (1 + NL + NL * NL);
+        gmem<T> *lh = gp((T *)M.mslab) + L.mr.slab + mslab_lift(NH, NL, true) + L.node;
+        const int gl = L.il + NH * L.jl;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const double uh = L.qh[(1 + r) * S::N3H + nodeh];
+            const double ul = extend_face<NL>(Ia, Ib, &sq[L.slot][r * L2]);
+            const double us = 0.5 * (uh + ul);
+            // higher side: u* - u_r; its own s n is applied by the element kernel
+            lh[r * M2] = (T)(us - L.qh[(1 + r) * S::N3H + crefh]);
+            const T dl = (T)(us - L.ql[(1 + r) * S::N3L + crefl]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) G[L.slot][(r * 3 + d) * M2 + gl] = -dl * sn[d];
+        }
+    }
+    __syncthreads();
+    if (L.valid && L.node < L2) {
+        const int a = L.node % NL, b = L.node / NL;
+        const T *I = itable<T>(A) + i_offset(NL, NH);
+        const T *wl = wtable<T>(A) + w_offset(NL);
+        T Wa[NH], Wb[NH];
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            Wa[k] = I[k * NL + a];
+            Wb[k] = I[k * NL + b];
+        }
+        const T iw = T(1) / (wl[a] * wl[b]);
+        gmem<T> *ll = gp((T *)M.mslab) + L.mr.slab + mslab_lift(NH, NL, false) + L.node;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ll[k * L2] = project_face<NL, NH, T>(Wa, Wb, &G[L.slot][k * M2]) * iw;
     }
 }
 
-template <int NH, class T>
-__global__ __launch_bounds__(64) void k_mortar_flux(StageArgs A)
+template <int NL, int NH, class T>
+__global__ __launch_bounds__(256) void k_mortar_flux(StageArgs A)
 {
-    constexpr int M2 = NH * NH, N3H = NH * NH * NH;
-    __shared__ T G[4 * M2];
-    const int mi = blockIdx.x;
-    if (mi >= A.mcount) return;
+    using S = MortarShape<NL, NH>;
+    constexpr int M2 = S::M2, L2 = S::L2;
+    __shared__ double sq[S::SLOTS][4 * L2];     // lower side's state face trace
+    __shared__ T st[S::SLOTS][3 * L2];          // lower side's viscous traces
+    __shared__ T G[S::SLOTS][4 * M2];           // lower side's surface integrand, lower frame
     const Member &M = A.mem[0];
-    const MortarRef mr = load_mortar(M.mort, A.mlist[mi]);
-    const int Nl = mr.Nl, N3L = Nl * Nl * Nl;
-    const gmem<const double> *q = gp((const double *)(A.q_in ? A.q_in : M.qA));
-    const gmem<const double> *qh = q + 4 * elem_off<NH>(M, mr.eh);
-    const gmem<const double> *ql = q + 4 * gp(M.eoff)[mr.el];
-    const int lane = threadIdx.x;
-    const int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (Nl / 2) * (1 + Nl + Nl * Nl);
-    gmem<T> *slab = gp((T *)M.mslab) + mr.slab;
-    const T c0sq = (T)M.c0sq, h = T(0.5);
-    if (lane < M2) {
-        const int i = lane % NH, j = lane / NH;
-        int il, jl;
-        orient_map<NH>(mr.code_h & 7, i, j, il, jl);
-        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (mr.geo + lane);
+    const MortarLane<NL, NH> L = mortar_lane<NL, NH>(A, M);
+    bool vh = false, vl = false, visc = false;
+    if (L.valid) {
+        vh = gp(M.flag)[L.mr.eh] != 0;
+        vl = gp(M.flag)[L.mr.el] != 0;
+        visc = (vh || vl) && (M.mixed_face == 0 || (vh && vl));
+        for (int v = L.node; v < 4 * L2; v += M2) {
+            const int x = v / L2, ab = v - x * L2;
+            sq[L.slot][v] = L.ql[x * S::N3L + face_node<NL>(L.mr.fl, ab % NL, ab / NL)];
+        }
+        if (visc && vl) {
+            const gmem<const T> *tl = gp((const T *)M.mslab) + L.mr.slab + mslab_tr(NH, NL, false);
+            for (int v = L.node; v < 3 * L2; v += M2) st[L.slot][v] = tl[v];
+        }
+    }
+    __syncthreads();
+    if (L.valid) {
+        const double *I = A.I64 + i_offset(NL, NH);
+        const T *wh = wtable<T>(A) + w_offset(NH);
+        double Ia[NL], Ib[NL];
+#pragma unroll
+        for (int a = 0; a < NL; ++a) {
+            Ia[a] = I[L.il * NL + a];
+            Ib[a] = I[L.jl * NL + a];
+        }
+        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (L.mr.geo + L.node);
         const T n[3] = {g[0], g[1], g[2]};
         const T sc = g[3];
-        const int nodeh = face_node<NH>(mr.fh, i, j);
+        const int nodeh = face_node<NH>(L.mr.fh, L.i, L.j);
+        constexpr int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (NL / 2) * (1 + NL + NL * NL);
+        const T c0sq = (T)M.c0sq, h = T(0.5);
         double qa[4], qb[4], rh[4], rl[4];       // higher trace, extended lower trace, reference states
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-            qa[x] = qh[x * N3H + nodeh];
-            qb[x] = extend64<NH>(A, ql + x * N3L, Nl, mr.fl, il, jl);
-            rh[x] = qh[x * N3H + crefh];
-            rl[x] = ql[x * N3L + crefl];
+            qa[x] = L.qh[x * S::N3H + nodeh];
+            qb[x] = extend_face<NL>(Ia, Ib, &sq[L.slot][x * L2]);
+            rh[x] = L.qh[x * S::N3H + crefh];
+            rl[x] = L.ql[x * S::N3L + crefl];
         }
         // Roe dissipation |A(q_mean)| dq with L = higher side, R = lower side
         T uL[3], du[3];
@@ -902,21 +977,36 @@ __global__ __launch_bounds__(64) void k_mortar_flux(StageArgs A)
             Ad[1 + d] = lp * vp + lm * vm + l0 * (du[d] - alp * vp - alm * vm);
         }
         // BR1: mean of the two sides' viscous traces along the higher side's s n
-        const bool vh = gp(M.flag)[mr.eh] != 0, vl = gp(M.flag)[mr.el] != 0;
         T fvn[3] = {T(0), T(0), T(0)};
-        if ((vh || vl) && (M.mixed_face == 0 || (vh && vl))) {
-            const gmem<const T> *th = gp((const T *)M.mslab) + mr.slab + mslab_tr(NH, Nl, true);
-            const gmem<const T> *tl = gp((const T *)M.mslab) + mr.slab + mslab_tr(NH, Nl, false);
+        if (visc) {
+            const gmem<const T> *th = gp((const T *)M.mslab) + L.mr.slab + mslab_tr(NH, NL, true) + L.node;
+            T Ta[NL], Tb[NL];
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                Ta[k] = (T)Ia[k];
+                Tb[k] = (T)Ib[k];
+            }
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                const T a_ = vh ? th[r * M2 + lane] : T(0);
-                const T b_ = vl ? extendT<NH, T>(A, tl + r * Nl * Nl, Nl, il, jl) : T(0);
-                fvn[r] = h * (a_ + b_);
+                T b_ = T(0);
+                if (vl) {
+#pragma unroll 1
+                    for (int bb = 0; bb < NL; ++bb) {
+                        T sb = T(0);
+#pragma unroll
+                        for (int aa = 0; aa < NL; ++aa) sb += Ta[aa] * st[L.slot][r * L2 + aa + NL * bb];
+                        b_ += Tb[bb] * sb;
+                    }
+                }
+                fvn[r] = h * ((vh ? th[r * M2] : T(0)) + b_);
             }
         }
         // flux relative to each side's reference flux F_n(q_r):
         //   F* - F_n(q_r) = ((F_n(qa) - F_n(q_r)) + (F_n(qb) - F_n(q_r)))/2 - |A| dq / 2,
         //   F_n(q) - F_n(q_r) = [c0^2 du_n ; u du_n + du u_r,n + dp n], du = u - u_r
+        const T w2 = wh[L.i] * wh[L.j];
+        gmem<T> *sh = gp((T *)M.mslab) + L.mr.slab + mslab_surf(NH, NL, true) + L.node;
+        const int gl = L.il + NH * L.jl;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const double *qr = side == 0 ? rh : rl;
@@ -938,18 +1028,28 @@ __global__ __launch_bounds__(64) void k_mortar_flux(StageArgs A)
             for (int d = 0; d < 3; ++d) out[1 + d] = sc * h * (F[1 + d] - Ad[1 + d]) - fvn[d];
             if (side == 0) {
 #pragma unroll
-                for (int row = 0; row < 4; ++row) slab[mslab_surf(NH, Nl, true) + row * M2 + lane] = out[row];
+                for (int row = 0; row < 4; ++row) sh[row * M2] = out[row];
             } else {
 #pragma unroll
-                for (int row = 0; row < 4; ++row) G[row * M2 + lane] = -out[row];   // outward for the lower side
+                for (int row = 0; row < 4; ++row) G[L.slot][row * M2 + gl] = -out[row] * w2;   // outward for the lower side
             }
         }
     }
     __syncthreads();
-    if (lane < Nl * Nl) {
-        const int a = lane % Nl, b = lane / Nl;
-        for (int row = 0; row < 4; ++row)
-            slab[mslab_surf(NH, Nl, false) + row * Nl * Nl + lane] = project<NH, T>(A, G + row * M2, Nl, mr.code_h, a, b);
+    if (L.valid && L.node < L2) {
+        const int a = L.node % NL, b = L.node / NL;
+        const T *I = itable<T>(A) + i_offset(NL, NH);
+        const T *wl = wtable<T>(A) + w_offset(NL);
+        T Wa[NH], Wb[NH];
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            Wa[k] = I[k * NL + a];
+            Wb[k] = I[k * NL + b];
+        }
+        const T iw = T(1) / (wl[a] * wl[b]);
+        gmem<T> *sl = gp((T *)M.mslab) + L.mr.slab + mslab_surf(NH, NL, false) + L.node;
+#pragma unroll
+        for (int row = 0; row < 4; ++row) sl[row * L2] = project_face<NL, NH, T>(Wa, Wb, &G[L.slot][row * M2]) * iw;
     }
 }
 
@@ -1201,36 +1301,37 @@ int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32)
     return slot;
 }
 
-hipError_t launch_mortar_lift(int Nh, bool f32, const StageArgs &a, hipStream_t s)
+// Every (lower, higher) pair of orders a mortar can join: the lower side has
+// P >= 2 (its geometry must be resolved, 2 Pg <= P, Pg >= 1).
+#define HDG_MORTAR_PAIRS(X) \
+    X(3, 4) X(3, 5) X(4, 5) X(3, 6) X(4, 6) X(5, 6) X(3, 7) X(4, 7) X(5, 7) X(6, 7) X(3, 8) X(4, 8) X(5, 8) X(6, 8) X(7, 8)
+
+bool mortar_pair_supported(int Nl, int Nh)
 {
-    if (a.mcount == 0) return hipSuccess;
-#define C_(n)                                                                                              \
-    do {                                                                                                   \
-        if (f32) hipLaunchKernelGGL((k_mortar_lift<n, float>), dim3(a.mcount), dim3(64), 0, s, a);        \
-        else hipLaunchKernelGGL((k_mortar_lift<n, double>), dim3(a.mcount), dim3(64), 0, s, a);           \
-        return hipGetLastError();                                                                          \
-    } while (0)
-    switch (Nh) {
-    case 3: C_(3); case 4: C_(4); case 5: C_(5); case 6: C_(6); case 7: C_(7); case 8: C_(8);
-    default: return hipErrorInvalidValue;
-    }
-#undef C_
+#define P_(l, h) if (Nl == l && Nh == h) return true;
+    HDG_MORTAR_PAIRS(P_)
+#undef P_
+    return false;
 }
 
-hipError_t launch_mortar_flux(int Nh, bool f32, const StageArgs &a, hipStream_t s)
+template <int NL, int NH, class T>
+static hipError_t launch_mortar_kernel(bool lift, const StageArgs &a, hipStream_t s)
+{
+    const int grid = (a.mcount + MortarShape<NL, NH>::SLOTS - 1) / MortarShape<NL, NH>::SLOTS;
+    if (lift) hipLaunchKernelGGL((k_mortar_lift<NL, NH, T>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_mortar_flux<NL, NH, T>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mortar(bool lift, int Nl, int Nh, bool f32, const StageArgs &a, hipStream_t s)
 {
     if (a.mcount == 0) return hipSuccess;
-#define C_(n)                                                                                              \
-    do {                                                                                                   \
-        if (f32) hipLaunchKernelGGL((k_mortar_flux<n, float>), dim3(a.mcount), dim3(64), 0, s, a);        \
-        else hipLaunchKernelGGL((k_mortar_flux<n, double>), dim3(a.mcount), dim3(64), 0, s, a);           \
-        return hipGetLastError();                                                                          \
-    } while (0)
-    switch (Nh) {
-    case 3: C_(3); case 4: C_(4); case 5: C_(5); case 6: C_(6); case 7: C_(7); case 8: C_(8);
-    default: return hipErrorInvalidValue;
-    }
-#undef C_
+#define P_(l, h)                                                                          \
+    if (Nl == l && Nh == h)                                                               \
+        return f32 ? launch_mortar_kernel<l, h, float>(lift, a, s) : launch_mortar_kernel<l, h, double>(lift, a, s);
+    HDG_MORTAR_PAIRS(P_)
+#undef P_
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce_mixed(const double *r, const double *mass, const int64_t *eoff, const int8_t *Ne,
