@@ -85,7 +85,8 @@ constexpr int tile_lanes(int N)
 constexpr int tile_ept(int N, int B, int kind)
 {
     const int n3 = N * N * N, n2 = N * N;
-    const int per = (12 * n3 + (kind == kTileViscous ? 18 : 24) * n2) * 8;
+    // FP64 LDS arrays plus the element id and six face records staged per tile
+    const int per = (12 * n3 + (kind == kTileViscous ? 18 : 24) * n2) * 8 + 4 + 6 * 16;
     const int by_lanes = B / tile_lanes(N);
     const int by_lds = (tile_lds_budget(B) - n2 * 8) / per;
     return by_lanes < by_lds ? by_lanes : by_lds;

@@ -185,9 +185,18 @@ struct TileCtx {
 // changes nothing in exact arithmetic, while the rounding error of the
 // contraction scales with the deviation instead of the state.  The deviation
 // is formed in FP64 before conversion to the compute type.
+// Element ids and face records of a tile's elements, staged in LDS once per
+// tile so that face tasks and face-node lanes read them without a dependent
+// global load.
+template <int EPT>
+struct TileFaces {
+    int32_t e[EPT];
+    FaceRef f[6 * EPT];
+};
+
 template <int N, int EPT, class T>
 __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, const Tile &tl, T *sD,
-                                          TileCtx<N, T> &c)
+                                          TileFaces<EPT> &tf, TileCtx<N, T> &c)
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3, NL = tile_lanes(N);
     c.tid = threadIdx.x;
@@ -226,6 +235,16 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     c.nu = (T)M.nu;
     c.C_les = (T)M.C_les;
     c.inv_wend = T(N * (N - 1) / 2);   // 1 / w_0 = P (P + 1) / 2
+    for (int x = c.tid; x < 7 * EPT; x += blockDim.x) {
+        if (x < EPT) {
+            tf.e[x] = x < tl.count ? A.elems[tl.first + x] : 0;
+        } else {
+            const int y = x - EPT, s = y / 6;
+            tf.f[y] = s < tl.count ? load_face(M.conn, (size_t)A.elems[tl.first + s] * 6 + (y - 6 * s))
+                                   : FaceRef{0, HDG_WALL, 0, 0};
+        }
+    }
+    __syncthreads();
 }
 
 // Face-node task of a tile: element slot, element id, face, face coordinates.
@@ -235,7 +254,7 @@ struct FaceTask {
 };
 
 template <int N, int EPT>
-__device__ __forceinline__ FaceTask<N> face_task(const StageArgs &A, const Tile &tl, int task)
+__device__ __forceinline__ FaceTask<N> face_task(const TileFaces<EPT> &tf, const Tile &tl, int task)
 {
     constexpr int N2 = Shape<N>::N2, NFT = 6 * N2;
     FaceTask<N> ft;
@@ -245,7 +264,7 @@ __device__ __forceinline__ FaceTask<N> face_task(const StageArgs &A, const Tile 
     const int fn = r - ft.f * N2;
     ft.fa = fn % N;
     ft.fb = fn / N;
-    ft.e = ft.s < tl.count ? A.elems[tl.first + ft.s] : 0;
+    ft.e = tf.e[ft.s];
     return ft;
 }
 
@@ -271,7 +290,8 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
     T *sD = sfu + 3 * NTASK;          // [N2]
     const Member &M = A.mem[tl.member];
     TileCtx<N, T> c;
-    load_tile<N, EPT, T>(A, M, tl, sD, c);
+    __shared__ TileFaces<EPT> tf;
+    load_tile<N, EPT, T>(A, M, tl, sD, tf, c);
     if (c.act) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) lds[r * NN + c.g] = c.qt[1 + r];
@@ -282,8 +302,8 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
     }
 #pragma unroll 1
     for (int task = c.tid; task < NTASK; task += blockDim.x) {
-        const FaceTask<N> ft = face_task<N, EPT>(A, tl, task);
-        const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
+        const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
+        const FaceRef fr = tf.f[ft.s * 6 + ft.f];
         if (ft.s < tl.count && !(fr.code & kMortarBit)) {
             // u* - u = (u_other - u) / 2, formed in FP64
             const gmem<const double> *qm = c.qin + 4 * elem_off<N>(M, ft.e) + face_node<N>(ft.f, ft.fa, ft.fb);
@@ -341,7 +361,7 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
                 const int fidx = (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
                 const int task = tbase + f * N2 + fidx;
                 const T sf = (f & 1) ? T(1) : T(-1);
-                const FaceRef fr = load_face(M.conn, (size_t)c.e * 6 + f);
+                const FaceRef fr = tf.f[c.s * 6 + f];
                 if (fr.code & kMortarBit) {
                     const MortarRef mr = load_mortar(M.mort, fr.face);
                     const bool hi = fr.code & kOwnerBit;
@@ -416,7 +436,7 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
             // side's outward normal): +-(this element's outward)
             const int fidx = (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
             const int task = tbase + f * N2 + fidx;
-            const FaceRef fr = load_face(M.conn, (size_t)c.e * 6 + f);
+            const FaceRef fr = tf.f[c.s * 6 + f];
             const T so = (fr.code & kOwnerBit) ? sf : -sf;
             const T sn[3] = {so * c.Ja[dir][0], so * c.Ja[dir][1], so * c.Ja[dir][2]};
             if (fr.code & kMortarBit) {
@@ -440,8 +460,8 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
     gmem<T> *fvt = gp((T *)M.fvt);
 #pragma unroll 1
     for (int task = c.tid; task < NTASK; task += blockDim.x) {
-        const FaceTask<N> ft = face_task<N, EPT>(A, tl, task);
-        const FaceRef fr = load_face(M.conn, (size_t)ft.e * 6 + ft.f);
+        const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
+        const FaceRef fr = tf.f[ft.s * 6 + ft.f];
         if (ft.s < tl.count && !(fr.code & kMortarBit)) {
             const bool own = fr.code & kOwnerBit;
             int oa = ft.fa, ob = ft.fb;
@@ -466,10 +486,9 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
 // sides' implied fluxes are exact negatives in exact arithmetic.
 template <int N, class T>
 __device__ __forceinline__ void face_jump(const Member &M, const gmem<const double> *qin, T c0sq, int e, bool visc,
-                                          int f, int fa, int fb, T (&F)[4])
+                                          int f, int fa, int fb, const FaceRef &fr, T (&F)[4])
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
-    const FaceRef fr = load_face(M.conn, (size_t)e * 6 + f);
     const bool own = fr.code & kOwnerBit;
     const gmem<const double> *qe = qin + 4 * elem_off<N>(M, e) + face_node<N>(f, fa, fb);
     double qm[4], qo[4];
@@ -553,7 +572,8 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     T *sD = sface + 4 * NTASK;        // [N2]
     const Member &M = A.mem[tl.member];
     TileCtx<N, T> c;
-    load_tile<N, EPT, T>(A, M, tl, sD, c);
+    __shared__ TileFaces<EPT> tf;
+    load_tile<N, EPT, T>(A, M, tl, sD, tf, c);
     const bool visc = gp(M.flag)[c.e] != 0;
 
     // contravariant convective fluxes F^i_row = sum_d Ja^i_d f_{row,d} of the
@@ -582,10 +602,11 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     // share one equation class
 #pragma unroll 1
     for (int task = c.tid; task < NTASK; task += blockDim.x) {
-        const FaceTask<N> ft = face_task<N, EPT>(A, tl, task);
-        if (ft.s < tl.count && !(load_face(M.conn, (size_t)ft.e * 6 + ft.f).code & kMortarBit)) {
+        const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
+        const FaceRef fr = tf.f[ft.s * 6 + ft.f];
+        if (ft.s < tl.count && !(fr.code & kMortarBit)) {
             T F[4];
-            face_jump<N, T>(M, c.qin, c.c0sq, ft.e, visc, ft.f, ft.fa, ft.fb, F);
+            face_jump<N, T>(M, c.qin, c.c0sq, ft.e, visc, ft.f, ft.fa, ft.fb, fr, F);
 #pragma unroll
             for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
         }
@@ -644,7 +665,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
             const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
             const int fa = dir == 0 ? c.j : c.i;
             const int fb = dir == 2 ? c.j : c.k;
-            const FaceRef fr = load_face(M.conn, (size_t)c.e * 6 + f);
+            const FaceRef fr = tf.f[c.s * 6 + f];
             if (fr.code & kMortarBit) {
                 // mortar: the surface term relative to the reference flux,
                 // minus this element's outward deviation flux
