@@ -161,6 +161,7 @@ class OracleMesh:
         if not h:
             raise ValueError("oracle mesh rejected: " + lib().orc_last_error().decode())
         self._h = h
+        self.flag = fl
         assert lib().orc_mesh_nodes(h) == self.nodes
 
     def __del__(self):
@@ -170,8 +171,9 @@ class OracleMesh:
             self._h = None
 
     def set_flags(self, flag):
-        fl = np.ascontiguousarray(flag, dtype=np.uint8)
+        fl = np.ascontiguousarray(flag, dtype=np.uint8).copy()
         lib().orc_set_flags(self._h, fl.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        self.flag = fl
 
     def _shape(self, fields):
         return (self.n_elem, fields, self.N3) if self.uniform else (fields * self.nodes,)

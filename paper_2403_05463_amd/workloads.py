@@ -493,6 +493,58 @@ def uniform_inflow_state_flat(P: np.ndarray, alpha_deg: float, u_inf: float, noi
     return q
 
 
+def developed_airfoil_state(X: np.ndarray, alpha_deg: float = 20.0, u_inf: float = 1.0, t: float = 0.12,
+                            delta: float = 0.02, wake: float = 0.5, w0: float = 0.05, spread: float = 0.1,
+                            span: float = 1.0) -> np.ndarray:
+    """Analytic stand-in for a developed flow around the NACA section (chord
+    1, leading edge at the origin), to be clustered: free stream at angle
+    alpha, damped to zero at the wall over a boundary-layer thickness
+    ``delta`` (tanh of a wall-distance proxy: distance to the chord segment
+    less the local half thickness), times a Gaussian wake deficit behind the
+    trailing edge of depth ``wake`` and width w0 + spread sqrt(s) at a
+    distance s downstream, modulated along the span (period ``span``) by 20 %
+    with a spanwise velocity of 5 % of the deficit, so the wake is
+    three-dimensional.  Zero pressure.  X: node coordinates, (ne, 3, N3)
+    or flat [3 N_e^3] per element; returns the state in the same layout."""
+    flat = X.ndim == 1
+    if flat:
+        raise ValueError("use developed_airfoil_state_flat for meshes of mixed order")
+    x, y, z = X[:, 0], X[:, 1], X[:, 2]
+    u = _developed_velocity(x, y, z, alpha_deg, u_inf, t, delta, wake, w0, spread, span)
+    q = np.zeros((X.shape[0], 4, X.shape[2]))
+    q[:, 1], q[:, 2], q[:, 3] = u
+    return q
+
+
+def _developed_velocity(x, y, z, alpha_deg, u_inf, t, delta, wake, w0, spread, span):
+    xc = np.clip(x, 0.0, 1.0)
+    dy = np.maximum(np.abs(y) - naca_thickness(xc, t), 0.0)
+    d = np.sqrt((x - xc) ** 2 + dy ** 2)
+    a = math.radians(alpha_deg)
+    s = (x - 1.0) * math.cos(a) + y * math.sin(a)
+    n = -(x - 1.0) * math.sin(a) + y * math.cos(a)
+    sp = np.maximum(s, 0.0)
+    sig = w0 + spread * np.sqrt(sp)
+    deficit = np.where(s > 0.0, wake * (w0 / sig) * np.exp(-(n / sig) ** 2), 0.0)
+    ph = 2.0 * math.pi * z / span
+    deficit = deficit * (1.0 + 0.2 * np.sin(ph))
+    bl = np.tanh(d / delta)
+    mag = u_inf * bl * (1.0 - deficit)
+    return mag * math.cos(a), mag * math.sin(a), 0.05 * u_inf * bl * deficit * np.cos(ph)
+
+
+def developed_airfoil_state_flat(X: np.ndarray, Ps: np.ndarray, **kw) -> np.ndarray:
+    """developed_airfoil_state for a flat coordinate array of a mesh of mixed order."""
+    n3 = (np.asarray(Ps, dtype=np.int64) + 1) ** 3
+    off = np.concatenate([[0], np.cumsum(n3)[:-1]])
+    q = np.zeros(4 * int(n3.sum()))
+    for e in range(len(Ps)):
+        blk = X[3 * off[e]:3 * (off[e] + n3[e])].reshape(3, n3[e])
+        v = developed_airfoil_state(blk[None], **kw)[0]
+        q[4 * off[e]:4 * (off[e] + n3[e])] = v.ravel()
+    return q
+
+
 def free_stream(alpha_deg: float, u_inf: float = 1.0) -> np.ndarray:
     a = math.radians(alpha_deg)
     return np.array([0.0, u_inf * math.cos(a), u_inf * math.sin(a), 0.0])
