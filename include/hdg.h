@@ -260,6 +260,54 @@ hdg_status hdg_batch_autotune(hdg_batch *batch, int32_t reps, void *stream);
 hdg_status hdg_batch_get_launch(const hdg_batch *batch, int32_t kernel_class, hdg_prec prec, int32_t N,
                                 hdg_launch_cfg *out);
 
+/* ---- Clustering that produces the equation flags (Sec. 2.1) ----
+ *
+ * Node features: at every node of every element (the flags do not enter),
+ * the invariants of the strain rate S = (J + J^T)/2 and rotation rate
+ * W = (J - J^T)/2 of the velocity gradient J,
+ *   Q_S = (tr(S)^2 - tr(S^2))/2,  R_S = -det(S)/3,  Q_Omega = -tr(W^2)/2,
+ * with J the BR1 lifted gradient the viscous operator uses.
+ * q: device FP64 state of the mesh (state layout).  features: device,
+ * 3 * nodes doubles, [3][nodes] (Q_S, R_S, Q_Omega), node t of element e at
+ * position eoff(e) + t, eoff(e) the element's first node (its state starts at
+ * 4 eoff(e)).  Caller-owned buffers.  Asynchronous on `stream`. */
+hdg_status hdg_cluster_features(hdg_mesh *mesh, const double *q, double *features, void *stream);
+
+typedef struct {
+    int32_t iterations;   /* EM iterations after the initial split, 0..100000 */
+    int32_t pad;
+    double reg_covar;     /* ridge added to each covariance diagonal (standardised units), >= 0 */
+} hdg_gmm_opts;
+
+typedef struct {
+    double feat_mean[3], feat_std[3];  /* centring and scales of (Q_S, R_S, Q_Omega): s_Q, s_Q^(3/2), s_Q */
+    double weight[2];                  /* mixture weights, [0] inviscid, [1] viscous/rotational */
+    double mean[2][3];                 /* component means, standardised units */
+    double cov[2][3][3];               /* component covariances, standardised units */
+    double log_likelihood;             /* mean per node of the last E-step; NaN without iterations */
+    int32_t iterations;                /* E-steps taken */
+    int32_t degenerate;                /* 1: Q_Omega constant, no second region, every p_v = 0 */
+    int64_t n_viscous;                 /* elements assigned to the viscous/rotational region */
+} hdg_gmm_result;
+
+/* Two-component Gaussian mixture over the node features and the element
+ * regions (Sec. 2.1: memberships p_v, p_i = 1 - p_v per node; element means;
+ * an element takes the region of the larger mean, a tie going viscous).
+ * The features are centred and scaled by the flow's gradient scale: s_Q, the
+ * pooled population standard deviation of Q_S and Q_Omega, for those two and
+ * s_Q^(3/2) for R_S (1 if s_Q = 0); nodes with Q_Omega above its mean start in
+ * the second component; EM runs opts->iterations times with full covariances
+ * and a ridge on their diagonals; the component with the larger mean Q_Omega
+ * is the viscous one.
+ * features: device [3][nodes] as written by hdg_cluster_features.
+ * p_visc (device [nodes]) and elem_pv (device [n_elem]) receive the node
+ * memberships and element means when not NULL; flags (host [n_elem]) the
+ * regions, 1 viscous.  Results are deterministic (fixed-order reductions).
+ * Synchronises `stream`.  Apply the flags with hdg_mesh_set_flags. */
+hdg_status hdg_cluster_fit(hdg_mesh *mesh, const double *features, const hdg_gmm_opts *opts,
+                           hdg_gmm_result *result, double *p_visc, double *elem_pv, uint8_t *flags,
+                           void *stream);
+
 /* Plain device-to-device copy kernel (nbytes a multiple of 16, 16-byte aligned
  * pointers): the HBM bandwidth probe that calibrates traffic counters. */
 hdg_status hdg_stream_copy(hdg_ctx *ctx, void *dst_dev, const void *src_dev, int64_t nbytes,

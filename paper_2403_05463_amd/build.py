@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhdg.so")
-SOURCES = ["hdg_api.cpp", "hdg_batch.cpp", "hdg_setup.cpp", "hdg_kernels.hip"]
+SOURCES = ["hdg_api.cpp", "hdg_batch.cpp", "hdg_cluster.cpp", "hdg_setup.cpp", "hdg_kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

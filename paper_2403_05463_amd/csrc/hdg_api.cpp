@@ -87,9 +87,15 @@ void free_device(hdg_mesh *m)
 {
     void *ptrs[] = {m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->partials,
                     m->final13, m->conn, m->flag_d, m->metric32, m->fgeo32, m->eoff, m->foff, m->member,
-                    m->Ne_d, m->mort, m->mslab, m->mgeo, m->mgeo32, m->mlist};
+                    m->Ne_d, m->mort, m->mslab, m->mgeo, m->mgeo32, m->mlist, m->gmm, m->gmm_partials,
+                    m->gmm_flags};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto &pl : m->feat_plans) {
+        if (pl.tiles) (void)hipFree(pl.tiles);
+        if (pl.elems) (void)hipFree(pl.elems);
+    }
+    m->feat_plans.clear();
     for (auto &v : m->plans) {
         for (auto &pl : v) {
             if (pl.tiles) (void)hipFree(pl.tiles);

@@ -145,6 +145,13 @@ struct hdg_mesh {
     hdg::Member host_member{};
     // tile plans per kernel kind, for every (order, workgroup size) pair
     std::vector<hdg::TilePlan> plans[2];
+    // clustering, made on first use: feature tile plans over every element
+    // (one per order) and the mixture's device state and scratch
+    std::vector<hdg::TilePlan> feat_plans;
+    hdg::GmmState *gmm = nullptr;
+    double *gmm_partials = nullptr;
+    uint8_t *gmm_flags = nullptr;
+    int gmm_nblocks = 0;
     hdg::LaunchCfg cfg[2][2][hdg::kMaxN + 1];   // [kind][precision][N]
     int nblocks_reduce = 0;
     int64_t bytes = 0;

@@ -143,7 +143,26 @@ struct StageArgs {
     double rkA, rkB;        // fused RK stage: dq = A dq + dt R; q_next = q + B dq
     int32_t first_stage;    // A = 0: dq is not read
     int32_t parity;         // member mode: stage input is qB if set, else qA
+    int64_t nodes;          // node features: stride of the [3][nodes] output at r
 };
+
+// Two-component Gaussian mixture over standardised node features (device
+// resident, rewritten by each update so that EM iterations need no host).
+// Component k: weight w, mean mu, covariance cov (packed xx, xy, xz, yy, yz,
+// zz), the inverse Li of its lower Cholesky factor (packed 00, 10, 11, 20,
+// 21, 22) and cst = 3/2 log(2 pi) + log det L.
+struct GmmState {
+    double fm[3], fs[3], fsi[3];   // feature means, scales (s_Q, s_Q^3/2, s_Q) and their inverses
+    double w[2], logw[2];
+    double mu[2][3];
+    double cov[2][6];
+    double Li[2][6];
+    double cst[2];
+    double ll;                     // mean log-likelihood of the last E-step
+    int32_t degenerate;            // no node above the mean Q_Omega: no second region
+    int32_t iter;                  // E-steps taken
+};
+constexpr int kGmmStats = 21;      // per component: sum r, sum r d (3), sum r d d^T (6); + sum log-likelihood
 
 // Offset of the N x N derivative matrix in the packed table (N = 2..8).
 __host__ __device__ constexpr int d_offset(int N) { return (N - 1) * N * (2 * N - 1) / 6 - 1; }
@@ -171,6 +190,20 @@ hipError_t launch_mortar(bool lift, int Nl, int Nh, bool f32, const StageArgs &a
 // Reductions of a mesh of mixed order: element after element, eoff / Ne per element.
 hipError_t launch_reduce_mixed(const double *r, const double *mass, const int64_t *eoff, const int8_t *Ne,
                                int64_t n_elem, double *partials, int nblocks, double *final13, hipStream_t s);
+// Node features of every element (BR1 gradient invariants) over the order-N
+// tiles of plan `a` (viscous-kind tiles, workgroup size feature_block(N)).
+int feature_block(int N);
+hipError_t launch_features(int N, const StageArgs &a, int grid, hipStream_t s);
+// Gaussian mixture passes over n nodes of features X[3][n]: mode 0 feature
+// sums, 1 squared deviations, 2 initial split, 3 E-step with statistics;
+// each pass is followed by its update of *st (reg: covariance ridge).
+hipError_t launch_gmm_pass(int mode, const double *X, int64_t n, GmmState *st, double *partials, int nblocks,
+                           double reg, hipStream_t s);
+// Memberships p_v per node (optional), element means (optional) and element
+// regions from the fitted mixture; element e has N3 nodes from e N3, or
+// Ne[e]^3 from eoff[e] when eoff is set.
+hipError_t launch_gmm_assign(const double *X, int64_t n, const GmmState *st, const int64_t *eoff, const int8_t *Ne,
+                             int N3, int64_t ne, double *p_visc, double *elem_pv, uint8_t *flags, hipStream_t s);
 // Resident workgroups per CU of a kernel configuration (occupancy query).
 int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32);
 // Whether kernels are instantiated for order N with workgroup size B.

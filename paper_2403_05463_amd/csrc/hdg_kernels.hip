@@ -280,7 +280,7 @@ __device__ __forceinline__ FaceTask<N> face_task(const TileFaces<EPT> &tf, const
 //     face nodes, and the face traces tau . (s n) oriented by the face
 //     owner's outward normal, staged in LDS and stored by face-node lanes so
 //     that consecutive lanes write consecutive words.
-template <int N, int EPT, class T>
+template <int N, int EPT, class T, bool FEAT = false>
 __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl, char *smem)
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
@@ -396,6 +396,35 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int d = 0; d < 3; ++d) G[r][d] = JG[r][d] * c.invJ;
+    }
+    if constexpr (FEAT) {
+        // node features of the clustering (Sec. 2.1): invariants of the
+        // strain rate S = (G + G^T)/2 and rotation rate W = (G - G^T)/2
+        if (c.act) {
+            T S[3][3], w2 = T(0);
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    S[r][d] = T(0.5) * (G[r][d] + G[d][r]);
+                    const T wr = T(0.5) * (G[r][d] - G[d][r]);
+                    w2 += wr * wr;
+                }
+            const T trS = S[0][0] + S[1][1] + S[2][2];
+            T trS2 = T(0);
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) trS2 += S[r][d] * S[d][r];
+            const T det = S[0][0] * (S[1][1] * S[2][2] - S[1][2] * S[2][1]) -
+                          S[0][1] * (S[1][0] * S[2][2] - S[1][2] * S[2][0]) +
+                          S[0][2] * (S[1][0] * S[2][1] - S[1][1] * S[2][0]);
+            gmem<T> *out = gp((T *)A.r) + c.eo + c.t;
+            out[0] = T(0.5) * (trS * trS - trS2);        // Q_S
+            out[A.nodes] = -det / T(3);                   // R_S
+            out[2 * A.nodes] = T(0.5) * w2;               // Q_Omega = -tr(W^2)/2 = |W|^2/2
+        }
+        return;
     }
     T fv[3][3];
     {
@@ -748,6 +777,18 @@ __global__ __launch_bounds__(B) void k_viscous(StageArgs A)
     }
 }
 
+// Node features of the clustering: the viscous operator's BR1 gradient on
+// every element of the tile list, then its invariants (FP64).
+template <int N, int B>
+__global__ __launch_bounds__(B) void k_features(StageArgs A)
+{
+    constexpr int EPT = tile_ept(N, B, kTileViscous);
+    static_assert(EPT > 0, "tile does not fit the workgroup");
+    constexpr int N2 = N * N, NN = EPT * N * N2, NTASK = EPT * 6 * N2;
+    __shared__ __attribute__((aligned(16))) char smem[(12 * NN + 3 * NTASK + N2) * sizeof(double)];
+    HDG_ONE_TILE(A, tl) viscous_tile<N, EPT, double, true>(A, tl, smem);
+}
+
 template <class T, int EPI, int N, int B, bool PERS>
 __global__ __launch_bounds__(B) void k_residual(StageArgs A)
 {
@@ -1074,6 +1115,231 @@ __global__ __launch_bounds__(256) void k_mortar_flux(StageArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Clustering (Sec. 2.1): a two-component Gaussian mixture over the node
+// features (Q_S, R_S, Q_Omega), fitted by expectation-maximisation.  Every
+// pass streams the three feature arrays once, standardising on the fly, and
+// leaves per-workgroup partial sums (fixed order, no atomics); a one-lane
+// update turns them into the next state in device memory, so a whole fit
+// runs on the stream without the host.
+// ---------------------------------------------------------------------------
+
+constexpr int kGmmBlock = 256;
+
+// E-step of one node: log(w_k N(x | mu_k, cov_k)) for both components,
+// their log-sum-exp and the responsibilities.
+__device__ __forceinline__ void gmm_estep(const gmem<const GmmState> *S, const double (&x)[3], double (&r)[2],
+                                          double &lse)
+{
+    double a[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const gmem<const double> *Li = S->Li[k];
+        const double d0 = x[0] - S->mu[k][0], d1 = x[1] - S->mu[k][1], d2 = x[2] - S->mu[k][2];
+        const double z0 = Li[0] * d0;
+        const double z1 = Li[1] * d0 + Li[2] * d1;
+        const double z2 = Li[3] * d0 + Li[4] * d1 + Li[5] * d2;
+        a[k] = S->logw[k] - S->cst[k] - 0.5 * (z0 * z0 + z1 * z1 + z2 * z2);
+    }
+    const double top = a[0] > a[1] ? a[0] : a[1];
+    lse = top + log(exp(a[0] - top) + exp(a[1] - top));
+    r[0] = exp(a[0] - lse);
+    r[1] = exp(a[1] - lse);
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&acc)[NV], double *partials)
+{
+    __shared__ double red[kGmmBlock / 64][NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double t = acc[v];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        acc[v] = t;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) red[wv][v] = acc[v];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kGmmBlock / 64; ++w) t += red[w][threadIdx.x];
+        gp(partials)[(size_t)blockIdx.x * NV + threadIdx.x] = t;
+    }
+}
+
+// MODE 0: sums of x; 1: sums of (x - mean)^2; 2: statistics of the initial
+// split (Q_Omega above its mean: second component); 3: E-step statistics
+// about the current means, plus the log-likelihood.
+template <int MODE>
+__global__ __launch_bounds__(kGmmBlock) void k_gmm_accum(const double *X, int64_t n, const GmmState *st,
+                                                         double *partials)
+{
+    constexpr int NV = MODE < 2 ? 3 : kGmmStats;
+    const gmem<const GmmState> *S = gp(st);
+    const gmem<const double> *Xg = gp(X);
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    const bool skip = MODE == 3 && S->degenerate;
+    for (int64_t i = (int64_t)blockIdx.x * kGmmBlock + threadIdx.x; !skip && i < n;
+         i += (int64_t)gridDim.x * kGmmBlock) {
+        double x[3] = {Xg[i], Xg[n + i], Xg[2 * n + i]};
+        if constexpr (MODE == 0) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) acc[f] += x[f];
+        } else if constexpr (MODE == 1) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const double d = x[f] - S->fm[f];
+                acc[f] += d * d;
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) x[f] = (x[f] - S->fm[f]) * S->fsi[f];
+            double r[2], c[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+            if constexpr (MODE == 2) {
+                r[1] = x[2] > 0.0 ? 1.0 : 0.0;
+                r[0] = 1.0 - r[1];
+            } else {
+                double lse;
+                gmm_estep(S, x, r, lse);
+                acc[20] += lse;
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) c[k][f] = S->mu[k][f];
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const double d0 = x[0] - c[k][0], d1 = x[1] - c[k][1], d2 = x[2] - c[k][2];
+                double *a = acc + 10 * k;
+                a[0] += r[k];
+                a[1] += r[k] * d0;
+                a[2] += r[k] * d1;
+                a[3] += r[k] * d2;
+                a[4] += r[k] * d0 * d0;
+                a[5] += r[k] * d0 * d1;
+                a[6] += r[k] * d0 * d2;
+                a[7] += r[k] * d1 * d1;
+                a[8] += r[k] * d1 * d2;
+                a[9] += r[k] * d2 * d2;
+            }
+        }
+    }
+    block_sums<NV>(acc, partials);
+}
+
+// Sum the partials in a fixed order and write the next state (one lane).
+template <int MODE>
+__global__ __launch_bounds__(64) void k_gmm_update(const double *partials, int nblocks, int64_t n, double reg,
+                                                   GmmState *st)
+{
+    constexpr int NV = MODE < 2 ? 3 : kGmmStats;
+    __shared__ double tot[NV];
+    if (threadIdx.x < NV) {
+        double t = 0.0;
+        for (int b = 0; b < nblocks; ++b) t += gp(partials)[(size_t)b * NV + threadIdx.x];
+        tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    gmem<GmmState> *S = gp(st);
+    const double dn = (double)n;
+    if constexpr (MODE == 0) {
+        for (int f = 0; f < 3; ++f) S->fm[f] = tot[f] / dn;
+        S->degenerate = 0;
+        S->iter = 0;
+        S->ll = __builtin_nan("");
+    } else if constexpr (MODE == 1) {
+        // gradient scale: pooled deviation s_Q of the two Q invariants; R_S,
+        // a cubed gradient, scales with s_Q^(3/2)
+        const double sq = sqrt(0.5 * (tot[0] / dn + tot[2] / dn));
+        const bool ok = sq > 0.0;
+        S->fs[0] = ok ? sq : 1.0;
+        S->fs[1] = ok ? sq * sqrt(sq) : 1.0;
+        S->fs[2] = ok ? sq : 1.0;
+        for (int f = 0; f < 3; ++f) S->fsi[f] = 1.0 / S->fs[f];
+    } else {
+        if (MODE == 2 && (tot[0] == 0.0 || tot[10] == 0.0)) {
+            S->degenerate = 1;
+            return;
+        }
+        if (MODE == 3) {
+            if (S->degenerate) return;
+            S->ll = tot[20] / dn;
+            S->iter = S->iter + 1;
+        }
+        for (int k = 0; k < 2; ++k) {
+            const double *a = tot + 10 * k;
+            const double nk = a[0] + 10.0 * __DBL_EPSILON__;
+            const double c0 = MODE == 3 ? S->mu[k][0] : 0.0, c1 = MODE == 3 ? S->mu[k][1] : 0.0,
+                         c2 = MODE == 3 ? S->mu[k][2] : 0.0;
+            const double e0 = a[1] / nk, e1 = a[2] / nk, e2 = a[3] / nk;
+            const double C00 = a[4] / nk - e0 * e0 + reg, C01 = a[5] / nk - e0 * e1, C02 = a[6] / nk - e0 * e2,
+                         C11 = a[7] / nk - e1 * e1 + reg, C12 = a[8] / nk - e1 * e2, C22 = a[9] / nk - e2 * e2 + reg;
+            S->mu[k][0] = c0 + e0;
+            S->mu[k][1] = c1 + e1;
+            S->mu[k][2] = c2 + e2;
+            S->w[k] = nk / dn;
+            S->logw[k] = log(nk / dn);
+            S->cov[k][0] = C00; S->cov[k][1] = C01; S->cov[k][2] = C02;
+            S->cov[k][3] = C11; S->cov[k][4] = C12; S->cov[k][5] = C22;
+            // lower Cholesky factor L of the covariance and its inverse
+            const double L00 = sqrt(C00), L10 = C01 / L00, L20 = C02 / L00;
+            const double L11 = sqrt(C11 - L10 * L10), L21 = (C12 - L20 * L10) / L11;
+            const double L22 = sqrt(C22 - L20 * L20 - L21 * L21);
+            const double i00 = 1.0 / L00, i11 = 1.0 / L11, i22 = 1.0 / L22;
+            const double i10 = -L10 * i00 * i11, i21 = -L21 * i11 * i22, i20 = -(L20 * i00 + L21 * i10) * i22;
+            S->Li[k][0] = i00; S->Li[k][1] = i10; S->Li[k][2] = i11;
+            S->Li[k][3] = i20; S->Li[k][4] = i21; S->Li[k][5] = i22;
+            S->cst[k] = 1.5 * log(2.0 * M_PI) + log(L00) + log(L11) + log(L22);
+        }
+    }
+}
+
+// One wave per element: p_v of each node from the fitted mixture (the
+// component with the larger mean Q_Omega is the viscous one), the element
+// mean and the region (mean p_v >= mean p_i = 1 - mean p_v: viscous).
+__global__ __launch_bounds__(kGmmBlock) void k_gmm_assign(const double *X, int64_t n, const GmmState *st,
+                                                          const int64_t *eoff, const int8_t *Ne, int N3, int64_t ne,
+                                                          double *p_visc, double *elem_pv, uint8_t *flags)
+{
+    const int64_t e = (int64_t)blockIdx.x * (kGmmBlock / 64) + (threadIdx.x >> 6);
+    if (e >= ne) return;                       // wave-uniform; no workgroup barrier follows
+    const int lane = threadIdx.x & 63;
+    const gmem<const GmmState> *S = gp(st);
+    const int64_t o = eoff ? gp(eoff)[e] : e * N3;
+    const int n3 = eoff ? (int)gp(Ne)[e] * gp(Ne)[e] * gp(Ne)[e] : N3;
+    const bool deg = S->degenerate != 0;
+    const int vis = S->mu[0][2] > S->mu[1][2] ? 0 : 1;
+    const gmem<const double> *Xg = gp(X);
+    double sum = 0.0;
+    for (int t = lane; t < n3; t += 64) {
+        double p = 0.0;
+        if (!deg) {
+            double x[3], r[2], lse;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) x[f] = (Xg[f * n + o + t] - S->fm[f]) * S->fsi[f];
+            gmm_estep(S, x, r, lse);
+            p = r[vis];
+        }
+        if (p_visc) gp(p_visc)[o + t] = p;
+        sum += p;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if (lane == 0) {
+        const double pm = sum / n3;
+        if (elem_pv) gp(elem_pv)[e] = pm;
+        gp(flags)[e] = pm >= 1.0 - pm ? 1 : 0;
+    }
+}
+
 // Partial reductions over the elements of a mesh of mixed order: workgroup
 // b takes a contiguous range of elements, its lanes stride over each
 // element's nodes.  Fixed order, no atomics.
@@ -1353,6 +1619,48 @@ hipError_t launch_mortar(bool lift, int Nl, int Nh, bool f32, const StageArgs &a
     HDG_MORTAR_PAIRS(P_)
 #undef P_
     return hipErrorInvalidValue;
+}
+
+int feature_block(int N) { return N <= 5 ? 128 : N == 6 ? 256 : 512; }
+
+hipError_t launch_features(int N, const StageArgs &a, int grid, hipStream_t s)
+{
+#define F_(n, b)                                                                             \
+    case n:                                                                                  \
+        static_assert(tile_ept(n, b, kTileViscous) > 0, "feature tile does not fit");       \
+        hipLaunchKernelGGL((k_features<n, b>), dim3(grid), dim3(b), 0, s, a);                \
+        break;
+    switch (N) {
+        F_(2, 128) F_(3, 128) F_(4, 128) F_(5, 128) F_(6, 256) F_(7, 512) F_(8, 512)
+    default: return hipErrorInvalidValue;
+    }
+#undef F_
+    return hipGetLastError();
+}
+
+hipError_t launch_gmm_pass(int mode, const double *X, int64_t n, GmmState *st, double *partials, int nblocks,
+                           double reg, hipStream_t s)
+{
+#define G_(m)                                                                                          \
+    case m:                                                                                            \
+        hipLaunchKernelGGL(k_gmm_accum<m>, dim3(nblocks), dim3(kGmmBlock), 0, s, X, n, st, partials);  \
+        hipLaunchKernelGGL(k_gmm_update<m>, dim3(1), dim3(64), 0, s, partials, nblocks, n, reg, st);   \
+        break;
+    switch (mode) {
+        G_(0) G_(1) G_(2) G_(3)
+    default: return hipErrorInvalidValue;
+    }
+#undef G_
+    return hipGetLastError();
+}
+
+hipError_t launch_gmm_assign(const double *X, int64_t n, const GmmState *st, const int64_t *eoff, const int8_t *Ne,
+                             int N3, int64_t ne, double *p_visc, double *elem_pv, uint8_t *flags, hipStream_t s)
+{
+    const int64_t grid = (ne + kGmmBlock / 64 - 1) / (kGmmBlock / 64);
+    hipLaunchKernelGGL(k_gmm_assign, dim3((unsigned)grid), dim3(kGmmBlock), 0, s, X, n, st, eoff, Ne, N3, ne, p_visc,
+                       elem_pv, flags);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_mixed(const double *r, const double *mass, const int64_t *eoff, const int8_t *Ne,

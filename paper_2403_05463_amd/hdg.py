@@ -30,6 +30,7 @@ EXPORTED = [
     "hdg_mesh_autotune", "hdg_mesh_get_launch", "hdg_mesh_set_launch", "hdg_mesh_set_graphs",
     "hdg_batch_create", "hdg_batch_destroy", "hdg_batch_add", "hdg_batch_remove", "hdg_batch_info",
     "hdg_batch_rk3_steps", "hdg_batch_set_graphs", "hdg_batch_autotune", "hdg_batch_get_launch",
+    "hdg_cluster_features", "hdg_cluster_fit",
 ]
 
 
@@ -37,6 +38,17 @@ class HdgError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"hdg status {status}: {msg}")
         self.status = status
+
+
+class GmmOpts(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("pad", C.c_int32), ("reg_covar", C.c_double)]
+
+
+class GmmResult(C.Structure):
+    _fields_ = [("feat_mean", C.c_double * 3), ("feat_std", C.c_double * 3), ("weight", C.c_double * 2),
+                ("mean", (C.c_double * 3) * 2), ("cov", ((C.c_double * 3) * 3) * 2),
+                ("log_likelihood", C.c_double), ("iterations", C.c_int32), ("degenerate", C.c_int32),
+                ("n_viscous", C.c_int64)]
 
 
 class MeshDesc(C.Structure):
@@ -83,6 +95,9 @@ def lib() -> C.CDLL:
         L.hdg_timing_enable.argtypes = [vp, i32]
         L.hdg_timing_read.argtypes = [vp, i32, dp, C.POINTER(i64)]
         L.hdg_stream_copy.argtypes = [vp, vp, vp, i64, vp]
+        L.hdg_cluster_features.argtypes = [vp, vp, vp, vp]
+        L.hdg_cluster_fit.argtypes = [vp, vp, C.POINTER(GmmOpts), C.POINTER(GmmResult), vp, vp,
+                                      C.POINTER(C.c_uint8), vp]
         L.hdg_mesh_autotune.argtypes = [vp, vp, i32, vp]
         L.hdg_mesh_get_launch.argtypes = [vp, i32, i32, i32, C.POINTER(LaunchCfg)]
         L.hdg_mesh_set_launch.argtypes = [vp, i32, i32, i32, C.POINTER(LaunchCfg)]
@@ -384,6 +399,43 @@ def hdg_batch_get_launch(batch: Batch, kernel_class: int, prec: int, N: int) -> 
     c = LaunchCfg()
     _check(lib().hdg_batch_get_launch(batch.handle, kernel_class, prec, N, C.byref(c)), "hdg_batch_get_launch")
     return dict(block=c.block, persistent=bool(c.persistent), us_per_launch=c.us_per_launch)
+
+
+def _check_f64(t, n: int, name: str):
+    import torch
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need a contiguous float64 CUDA tensor of {n} entries")
+
+
+def hdg_cluster_features(mesh: Mesh, q, features, stream=None):
+    """Node features (Q_S, R_S, Q_Omega) of state q into the device array
+    ``features`` of 3 * nodes doubles ([3][nodes])."""
+    _check_state(mesh, q, "q")
+    _check_f64(features, 3 * mesh.nodes, "features")
+    _check(lib().hdg_cluster_features(mesh.handle, _ptr(q), _ptr(features), _stream(stream)), "hdg_cluster_features")
+
+
+def hdg_cluster_fit(mesh: Mesh, features, iterations: int = 100, reg_covar: float = 1e-6, p_visc=None,
+                    elem_pv=None, stream=None):
+    """Gaussian mixture over the features and element regions; returns
+    (result dict, flags as a uint8 array with one entry per element)."""
+    _check_f64(features, 3 * mesh.nodes, "features")
+    if p_visc is not None:
+        _check_f64(p_visc, mesh.nodes, "p_visc")
+    if elem_pv is not None:
+        _check_f64(elem_pv, mesh.n_elem, "elem_pv")
+    opts = GmmOpts(int(iterations), 0, float(reg_covar))
+    res = GmmResult()
+    flags = np.zeros(mesh.n_elem, dtype=np.uint8)
+    _check(lib().hdg_cluster_fit(mesh.handle, _ptr(features), C.byref(opts), C.byref(res),
+                                 _ptr(p_visc) if p_visc is not None else None,
+                                 _ptr(elem_pv) if elem_pv is not None else None,
+                                 flags.ctypes.data_as(C.POINTER(C.c_uint8)), _stream(stream)), "hdg_cluster_fit")
+    out = dict(feat_mean=np.array(res.feat_mean[:]), feat_std=np.array(res.feat_std[:]),
+               weight=np.array(res.weight[:]), mean=np.array([list(r) for r in res.mean]),
+               cov=np.array([[list(r) for r in c] for c in res.cov]), log_likelihood=res.log_likelihood,
+               iterations=res.iterations, degenerate=bool(res.degenerate), n_viscous=res.n_viscous)
+    return out, flags
 
 
 def hdg_stream_copy(ctx: Context, dst, src, nbytes: int, stream=None):
