@@ -54,9 +54,11 @@ def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: boo
     return float(b)
 
 
-def kernel_symbol(kind: int, N: int, f32: bool, block: int, fused_rk: bool = True) -> str:
+def kernel_symbol(kind: int, N: int, f32: bool, block: int, persistent: bool, fused_rk: bool = True) -> str:
     t = "float" if f32 else "double"
-    return f"k_viscous<{t}, {N}, {block}>" if kind == 0 else f"k_residual<{t}, {1 if fused_rk else 0}, {N}, {block}>"
+    p = "true" if persistent else "false"
+    return f"k_viscous<{t}, {N}, {block}, {p}>" if kind == 0 else \
+        f"k_residual<{t}, {1 if fused_rk else 0}, {N}, {block}, {p}>"
 
 
 def cpu_baseline(w, q0, budget_s: float = 12.0) -> dict:
@@ -126,6 +128,57 @@ def mixed_leg(ctx, args, torch, hdg) -> dict:
     return res
 
 
+def clustering_leg(w, mesh, args, torch, hdg, ms_step: float) -> dict:
+    """Clustering on the benchmark mesh (Sec. 2.1): node features of the
+    developed-flow stand-in, a two-component mixture fitted by EM, element
+    regions.  The EM cost per iteration is the difference of two fits."""
+    from paper_2403_05463_amd import workloads as W
+    X = hdg.hdg_mesh_node_coords(mesh)
+    q = torch.from_numpy(W.developed_airfoil_state(X)).cuda()
+    nodes = mesh.nodes
+    F = torch.empty(3 * nodes, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    hdg.hdg_cluster_features(mesh, q, F, stream=stream)
+    hdg.hdg_cluster_fit(mesh, F, 5, 1e-6, stream=stream)
+    torch.cuda.synchronize()
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        hdg.hdg_cluster_features(mesh, q, F, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    feat_ms = e0.elapsed_time(e1) / reps
+
+    def fit_ms(k):
+        t0 = time.perf_counter()
+        res, flags = hdg.hdg_cluster_fit(mesh, F, k, 1e-6, stream=stream)
+        return 1e3 * (time.perf_counter() - t0), res, flags
+
+    lo, hi = 20, 100
+    t_lo = min(fit_ms(lo)[0] for _ in range(3))
+    runs = [fit_ms(hi) for _ in range(3)]
+    t_hi = min(r[0] for r in runs)
+    _, res, flags = runs[0]
+    it_us = 1e3 * (t_hi - t_lo) / (hi - lo)
+    em_bytes = 24.0 * nodes
+    # a fit ended by the convergence test on the device (change of the mean
+    # log-likelihood below 1e-4), as a dynamic clustering step would run it
+    t0 = time.perf_counter()
+    rt, ft = hdg.hdg_cluster_fit(mesh, F, 500, 1e-6, stream=stream, tol=1e-4)
+    tol_ms = 1e3 * (time.perf_counter() - t0)
+    return {"workload": f"{w.name} developed-flow stand-in", "nodes": nodes,
+            "features_ms": feat_ms, "fit_ms": t_hi, "em_iterations": hi, "em_iteration_us": it_us,
+            "em_pass_GBps": em_bytes / (it_us * 1e-6) / 1e9, "em_pass_bytes": em_bytes,
+            "clustering_ms": feat_ms + t_hi, "clustering_over_rk_step": (feat_ms + t_hi) / ms_step,
+            "tol_1e-4": {"iterations": rt["iterations"], "converged": rt["converged"], "fit_ms": tol_ms,
+                         "clustering_over_rk_step": (feat_ms + tol_ms) / ms_step,
+                         "viscous_fraction": float(ft.mean())},
+            "viscous_fraction": float(flags.mean()), "geometric_mask_fraction": float(np.mean(w.flag)),
+            "agreement_with_geometric_mask": float(np.mean(flags == w.flag)),
+            "log_likelihood": res["log_likelihood"], "weights": [float(x) for x in res["weight"]]}
+
+
 def serving_leg(ctx, args, torch, hdg) -> dict:
     """Request stream: Poisson arrivals of independent periodic-box solves (n^3
     elements, n uniform in 4..24, P uniform in 2..6, 20-80 % viscous, nu in
@@ -192,6 +245,9 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-mb", type=int, default=1024, help="size of the stream-copy probe")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-order airfoil leg")
+    ap.add_argument("--no-cluster", action="store_true", help="skip the clustering leg")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="profiling aid: run only the mixed-order leg and print its JSON")
     ap.add_argument("--mixed-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -210,6 +266,9 @@ def main(argv=None) -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.mixed_only:
+        print(json.dumps({"mixed_order": mixed_leg(hdg.hdg_init(0), args, torch, hdg)}), flush=True)
+        return 0
     w = W.naca_working()
     q0 = W.initial_state(w, None)
     dt = w.dt
@@ -277,7 +336,8 @@ def main(argv=None) -> int:
         bytes_launch = algorithmic_bytes(kinds[dom], w.mesh.n_elem, n_visc, N, fused_rk=True, f32=f32) \
             * evals / max(n, 1)
         achieved = bytes_launch / avg_s / 1e9
-        sym = kernel_symbol(kinds[dom], N, f32, tuned[f"{dom}_{'f32' if f32 else 'f64'}"]["block"])
+        cfg = tuned[f"{dom}_{'f32' if f32 else 'f64'}"]
+        sym = kernel_symbol(kinds[dom], N, f32, cfg["block"], cfg["persistent"])
         return {"kernel": sym, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(TRAFFIC_SUMMARY, sym),
                 "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch}
@@ -319,6 +379,9 @@ def main(argv=None) -> int:
                          "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern32.items()},
                          "roofline": roofline(kern32, True), "dtype": "f32 residual, f64 state"}
     del q, dq
+    if not args.no_cluster:
+        print("[bench] clustering", file=sys.stderr, flush=True)
+        out["clustering"] = clustering_leg(w, mesh, args, torch, hdg, ms / args.steps)
     if not args.no_mixed:
         out["mixed_order"] = mixed_leg(ctx, args, torch, hdg)
     if not args.no_serving:

@@ -93,8 +93,9 @@ enum {
  * pointers are host pointers read during hdg_mesh_create only. */
 typedef struct {
     int32_t n_elem;
-    const int32_t *P;          /* [n_elem] polynomial order, 1..7, per element (Sec. 2.1 runs
-                                  regions of different order side by side).  A face between
+    const int32_t *P;          /* [n_elem] polynomial order, 1..7, per element (Sec. 2.2: the
+                                  order set per element from the regions, p-nonconforming
+                                  faces between them).  A face between
                                   orders is coupled through a mortar of the higher order: the
                                   lower side's traces are extended by their own interpolants,
                                   the Roe + BR1 flux is evaluated on the mortar with the higher
@@ -274,9 +275,11 @@ hdg_status hdg_batch_get_launch(const hdg_batch *batch, int32_t kernel_class, hd
 hdg_status hdg_cluster_features(hdg_mesh *mesh, const double *q, double *features, void *stream);
 
 typedef struct {
-    int32_t iterations;   /* EM iterations after the initial split, 0..100000 */
+    int32_t iterations;   /* most EM iterations after the initial split, 0..100000 */
     int32_t pad;
-    double reg_covar;     /* ridge added to each covariance diagonal (standardised units), >= 0 */
+    double reg_covar;     /* ridge added to each covariance diagonal (scaled units), >= 0 */
+    double tol;           /* stop after the M-step of an iteration whose mean log-likelihood
+                             changed by less than tol from the previous one; 0: run them all */
 } hdg_gmm_opts;
 
 typedef struct {
@@ -287,6 +290,8 @@ typedef struct {
     double log_likelihood;             /* mean per node of the last E-step; NaN without iterations */
     int32_t iterations;                /* E-steps taken */
     int32_t degenerate;                /* 1: Q_Omega constant, no second region, every p_v = 0 */
+    int32_t converged;                 /* 1: stopped by tol before the iteration limit */
+    int32_t pad;
     int64_t n_viscous;                 /* elements assigned to the viscous/rotational region */
 } hdg_gmm_result;
 
@@ -296,9 +301,9 @@ typedef struct {
  * The features are centred and scaled by the flow's gradient scale: s_Q, the
  * pooled population standard deviation of Q_S and Q_Omega, for those two and
  * s_Q^(3/2) for R_S (1 if s_Q = 0); nodes with Q_Omega above its mean start in
- * the second component; EM runs opts->iterations times with full covariances
- * and a ridge on their diagonals; the component with the larger mean Q_Omega
- * is the viscous one.
+ * the second component; EM runs up to opts->iterations times (fewer with
+ * opts->tol > 0) with full covariances and a ridge on their diagonals; the
+ * component with the larger mean Q_Omega is the viscous one.
  * features: device [3][nodes] as written by hdg_cluster_features.
  * p_visc (device [nodes]) and elem_pv (device [n_elem]) receive the node
  * memberships and element means when not NULL; flags (host [n_elem]) the

@@ -20,10 +20,12 @@ Steps, in the order the method takes them:
 
 Readings where the paper is silent (its text names the model and the
 features but not how the mixture is fitted):
-  * full covariance matrices, fitted by expectation-maximisation with a fixed
-    number of iterations (no tolerance test), a ridge ``reg_covar`` added to
-    each covariance diagonal, and the component counts guarded by 10 machine
-    epsilons, as in the common library implementation of the same model;
+  * full covariance matrices, fitted by expectation-maximisation with at
+    most a given number of iterations, optionally ending early once the mean
+    log-likelihood moves by less than ``tol`` between two E-steps (after
+    that iteration's M-step), a ridge ``reg_covar`` added to each covariance
+    diagonal, and the component counts guarded by 10 machine epsilons, as in
+    the common library implementation of the same model;
   * the features are centred (global means) and scaled by the gradient
     scale of the flow: Q_S and Q_W (units of a squared velocity gradient)
     by s_Q, the pooled population standard deviation of Q_S and Q_W, and R_S
@@ -144,8 +146,10 @@ class Fit:
     degenerate: bool          # no second region
 
 
-def fit_gmm(X, iterations: int, reg_covar: float = 1e-6) -> Fit:
-    """Two-component mixture over X[3][nodes] (steps 2 of the module notes)."""
+def fit_gmm(X, iterations: int, reg_covar: float = 1e-6, tol: float = 0.0) -> Fit:
+    """Two-component mixture over X[3][nodes] (step 2 of the module notes):
+    at most ``iterations`` EM iterations, ending after the M-step of one whose
+    mean log-likelihood moved by less than ``tol`` from the previous one."""
     X = np.asarray(X, dtype=np.float64)
     m, s = standardize(X)
     Xs = ((X - m[:, None]) / s[:, None]).T
@@ -161,6 +165,8 @@ def fit_gmm(X, iterations: int, reg_covar: float = 1e-6) -> Fit:
         R, ll = e_step(Xs, mix)
         hist.append(ll)
         mix = m_step(Xs, R, reg_covar)
+        if len(hist) > 1 and abs(hist[-1] - hist[-2]) < tol:
+            break
     R, _ = e_step(Xs, mix)
     v = 0 if mix.mean[0, 2] > mix.mean[1, 2] else 1
     order = [1 - v, v]

@@ -218,7 +218,7 @@ static partner_t partner(const orc_mesh *m, int e, int f, int a, int b)
 }
 
 /* A face between elements of different order (p-nonconforming) is coupled
- * through a mortar (the paper's solver supports such faces, Sec. 2.1):
+ * through a mortar (the paper's solver supports such faces, Sec. 2.2):
  *  - the mortar carries the higher order M and the higher-order side's face
  *    nodes, frame and outward normal;
  *  - the lower-order side's trace is extended to the mortar nodes by its own

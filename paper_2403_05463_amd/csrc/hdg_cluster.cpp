@@ -16,7 +16,7 @@ namespace {
 
 hdg_status fail(hdg_status s, const std::string &msg) { return hdg::set_error(s, msg); }
 
-constexpr int kMaxGmmBlocks = 2048;
+constexpr int kTolChunk = 8;   // EM iterations between convergence checks when a tolerance is set
 
 // Tile plans over every element, one per order present, for the feature
 // kernels; they do not depend on the flags, so they are made once.
@@ -68,7 +68,7 @@ hdg_status gmm_scratch(hdg_mesh *m)
     if (m->gmm) return HDG_OK;
     std::lock_guard<std::mutex> device_lock(hdg::device_mutex());
     const int64_t want = (m->nodes + 255) / 256;
-    m->gmm_nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxGmmBlocks, want));
+    m->gmm_nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(hdg::kMaxGmmBlocks, want));
     HDG_HIP(hipMalloc((void **)&m->gmm_partials, (size_t)m->gmm_nblocks * hdg::kGmmStats * sizeof(double)));
     HDG_HIP(hipMalloc((void **)&m->gmm_flags, (size_t)m->ne));
     HDG_HIP(hipMalloc((void **)&m->gmm, sizeof(GmmState)));
@@ -118,8 +118,9 @@ hdg_status hdg_cluster_fit(hdg_mesh *m, const double *features, const hdg_gmm_op
                            double *p_visc, double *elem_pv, uint8_t *flags, void *stream)
 {
     if (!m || !features || !opts || !res || !flags) return fail(HDG_EINVAL, "cluster_fit: NULL argument");
-    if (opts->iterations < 0 || opts->iterations > 100000 || !(opts->reg_covar >= 0.0) || !std::isfinite(opts->reg_covar))
-        return fail(HDG_EINVAL, "cluster_fit: need 0 <= iterations <= 100000 and a finite reg_covar >= 0");
+    if (opts->iterations < 0 || opts->iterations > 100000 || !(opts->reg_covar >= 0.0) ||
+        !std::isfinite(opts->reg_covar) || !(opts->tol >= 0.0) || !std::isfinite(opts->tol))
+        return fail(HDG_EINVAL, "cluster_fit: need 0 <= iterations <= 100000, finite reg_covar >= 0 and tol >= 0");
     HDG_HIP(hipSetDevice(m->ctx->device));
     hipStream_t s = (hipStream_t)stream;
     hdg_status st = gmm_scratch(m);
@@ -127,9 +128,23 @@ hdg_status hdg_cluster_fit(hdg_mesh *m, const double *features, const hdg_gmm_op
     const int64_t n = m->nodes;
     (void)hipGetLastError();
     for (int mode = 0; mode < 3; ++mode)
-        HDG_HIP(hdg::launch_gmm_pass(mode, features, n, m->gmm, m->gmm_partials, m->gmm_nblocks, opts->reg_covar, s));
-    for (int it = 0; it < opts->iterations; ++it)
-        HDG_HIP(hdg::launch_gmm_pass(3, features, n, m->gmm, m->gmm_partials, m->gmm_nblocks, opts->reg_covar, s));
+        HDG_HIP(hdg::launch_gmm_pass(mode, features, n, m->gmm, m->gmm_partials, m->gmm_nblocks, opts->reg_covar,
+                                     opts->tol, s));
+    // with a tolerance, iterations go in chunks and the device's convergence
+    // flag is read between them, so a converged fit launches no more passes
+    const int chunk = opts->tol > 0.0 ? kTolChunk : std::max(opts->iterations, 1);
+    for (int it = 0; it < opts->iterations;) {
+        const int end = std::min(opts->iterations, it + chunk);
+        for (; it < end; ++it)
+            HDG_HIP(hdg::launch_gmm_pass(3, features, n, m->gmm, m->gmm_partials, m->gmm_nblocks, opts->reg_covar,
+                                         opts->tol, s));
+        if (opts->tol > 0.0 && it < opts->iterations) {
+            GmmState g;
+            HDG_HIP(hipMemcpyAsync(&g, m->gmm, sizeof(GmmState), hipMemcpyDeviceToHost, s));
+            HDG_HIP(hipStreamSynchronize(s));
+            if (g.converged || g.degenerate) break;
+        }
+    }
     HDG_HIP(hdg::launch_gmm_assign(features, n, m->gmm, m->mixed ? m->eoff : nullptr, m->mixed ? m->Ne_d : nullptr,
                                    m->mixed ? 0 : m->N3, m->ne, p_visc, elem_pv, m->gmm_flags, s));
     GmmState g;
@@ -163,6 +178,7 @@ hdg_status hdg_cluster_fit(hdg_mesh *m, const double *features, const hdg_gmm_op
         res->log_likelihood = g.ll;
     }
     res->iterations = g.degenerate ? 0 : g.iter;
+    res->converged = g.converged;
     int64_t nv = 0;
     for (int64_t e = 0; e < m->ne; ++e) nv += flags[e] != 0;
     res->n_viscous = nv;

@@ -161,8 +161,11 @@ struct GmmState {
     double ll;                     // mean log-likelihood of the last E-step
     int32_t degenerate;            // no node above the mean Q_Omega: no second region
     int32_t iter;                  // E-steps taken
+    int32_t converged;             // the last change of ll was below the tolerance: later passes skip
+    int32_t pad;
 };
 constexpr int kGmmStats = 21;      // per component: sum r, sum r d (3), sum r d d^T (6); + sum log-likelihood
+constexpr int kMaxGmmBlocks = 2048; // workgroups of a mixture pass (partial sums per value)
 
 // Offset of the N x N derivative matrix in the packed table (N = 2..8).
 __host__ __device__ constexpr int d_offset(int N) { return (N - 1) * N * (2 * N - 1) / 6 - 1; }
@@ -196,9 +199,10 @@ int feature_block(int N);
 hipError_t launch_features(int N, const StageArgs &a, int grid, hipStream_t s);
 // Gaussian mixture passes over n nodes of features X[3][n]: mode 0 feature
 // sums, 1 squared deviations, 2 initial split, 3 E-step with statistics;
-// each pass is followed by its update of *st (reg: covariance ridge).
+// each pass is followed by its update of *st (reg: covariance ridge; tol:
+// an E-step pass whose log-likelihood changed by less ends the fit).
 hipError_t launch_gmm_pass(int mode, const double *X, int64_t n, GmmState *st, double *partials, int nblocks,
-                           double reg, hipStream_t s);
+                           double reg, double tol, hipStream_t s);
 // Memberships p_v per node (optional), element means (optional) and element
 // regions from the fitted mixture; element e has N3 nodes from e N3, or
 // Ne[e]^3 from eoff[e] when eoff is set.

@@ -1168,7 +1168,7 @@ __device__ __forceinline__ void block_sums(double (&acc)[NV], double *partials)
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < kGmmBlock / 64; ++w) t += red[w][threadIdx.x];
-        gp(partials)[(size_t)blockIdx.x * NV + threadIdx.x] = t;
+        gp(partials)[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;    // [value][workgroup]
     }
 }
 
@@ -1185,7 +1185,7 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_accum(const double *X, int64_
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    const bool skip = MODE == 3 && S->degenerate;
+    const bool skip = MODE == 3 && (S->degenerate || S->converged);
     for (int64_t i = (int64_t)blockIdx.x * kGmmBlock + threadIdx.x; !skip && i < n;
          i += (int64_t)gridDim.x * kGmmBlock) {
         double x[3] = {Xg[i], Xg[n + i], Xg[2 * n + i]};
@@ -1235,15 +1235,40 @@ __global__ __launch_bounds__(kGmmBlock) void k_gmm_accum(const double *X, int64_
 }
 
 // Sum the partials in a fixed order and write the next state (one lane).
+// Lane t of the kGmmUpdate-lane workgroup adds workgroups t, t + kGmmUpdate,
+// ... of every value with all its loads independent, then shuffle trees and
+// one pass over the waves reduce them.
+constexpr int kGmmUpdate = kMaxGmmBlocks / 2;
+
 template <int MODE>
-__global__ __launch_bounds__(64) void k_gmm_update(const double *partials, int nblocks, int64_t n, double reg,
-                                                   GmmState *st)
+__global__ __launch_bounds__(kGmmUpdate) void k_gmm_update(const double *partials, int nblocks, int64_t n,
+                                                           double reg, double tol, GmmState *st)
 {
     constexpr int NV = MODE < 2 ? 3 : kGmmStats;
+    constexpr int NW = kGmmUpdate / 64;
+    __shared__ double red[NW][NV];
     __shared__ double tot[NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const gmem<const double> *p = gp(partials) + (size_t)v * nblocks;
+        const int b0 = threadIdx.x, b1 = threadIdx.x + kGmmUpdate;
+        acc[v] = (b0 < nblocks ? p[b0] : 0.0) + (b1 < nblocks ? p[b1] : 0.0);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[v] += __shfl_xor(acc[v], o);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) red[wv][v] = acc[v];
+    }
+    __syncthreads();
     if (threadIdx.x < NV) {
         double t = 0.0;
-        for (int b = 0; b < nblocks; ++b) t += gp(partials)[(size_t)b * NV + threadIdx.x];
+        for (int w = 0; w < NW; ++w) t += red[w][threadIdx.x];
         tot[threadIdx.x] = t;
     }
     __syncthreads();
@@ -1253,6 +1278,7 @@ __global__ __launch_bounds__(64) void k_gmm_update(const double *partials, int n
     if constexpr (MODE == 0) {
         for (int f = 0; f < 3; ++f) S->fm[f] = tot[f] / dn;
         S->degenerate = 0;
+        S->converged = 0;
         S->iter = 0;
         S->ll = __builtin_nan("");
     } else if constexpr (MODE == 1) {
@@ -1270,8 +1296,11 @@ __global__ __launch_bounds__(64) void k_gmm_update(const double *partials, int n
             return;
         }
         if (MODE == 3) {
-            if (S->degenerate) return;
-            S->ll = tot[20] / dn;
+            if (S->degenerate || S->converged) return;
+            const double ll = tot[20] / dn;
+            // the M-step below still applies; later passes skip
+            if (S->iter > 0 && fabs(ll - S->ll) < tol) S->converged = 1;
+            S->ll = ll;
             S->iter = S->iter + 1;
         }
         for (int k = 0; k < 2; ++k) {
@@ -1639,12 +1668,14 @@ hipError_t launch_features(int N, const StageArgs &a, int grid, hipStream_t s)
 }
 
 hipError_t launch_gmm_pass(int mode, const double *X, int64_t n, GmmState *st, double *partials, int nblocks,
-                           double reg, hipStream_t s)
+                           double reg, double tol, hipStream_t s)
 {
+    if (nblocks < 1 || nblocks > kMaxGmmBlocks) return hipErrorInvalidValue;
 #define G_(m)                                                                                          \
     case m:                                                                                            \
         hipLaunchKernelGGL(k_gmm_accum<m>, dim3(nblocks), dim3(kGmmBlock), 0, s, X, n, st, partials);  \
-        hipLaunchKernelGGL(k_gmm_update<m>, dim3(1), dim3(64), 0, s, partials, nblocks, n, reg, st);   \
+        hipLaunchKernelGGL(k_gmm_update<m>, dim3(1), dim3(kGmmUpdate), 0, s, partials, nblocks, n, reg, tol,  \
+                           st);                                                                         \
         break;
     switch (mode) {
         G_(0) G_(1) G_(2) G_(3)

@@ -41,14 +41,14 @@ class HdgError(RuntimeError):
 
 
 class GmmOpts(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("pad", C.c_int32), ("reg_covar", C.c_double)]
+    _fields_ = [("iterations", C.c_int32), ("pad", C.c_int32), ("reg_covar", C.c_double), ("tol", C.c_double)]
 
 
 class GmmResult(C.Structure):
     _fields_ = [("feat_mean", C.c_double * 3), ("feat_std", C.c_double * 3), ("weight", C.c_double * 2),
                 ("mean", (C.c_double * 3) * 2), ("cov", ((C.c_double * 3) * 3) * 2),
                 ("log_likelihood", C.c_double), ("iterations", C.c_int32), ("degenerate", C.c_int32),
-                ("n_viscous", C.c_int64)]
+                ("converged", C.c_int32), ("pad", C.c_int32), ("n_viscous", C.c_int64)]
 
 
 class MeshDesc(C.Structure):
@@ -416,7 +416,7 @@ def hdg_cluster_features(mesh: Mesh, q, features, stream=None):
 
 
 def hdg_cluster_fit(mesh: Mesh, features, iterations: int = 100, reg_covar: float = 1e-6, p_visc=None,
-                    elem_pv=None, stream=None):
+                    elem_pv=None, stream=None, tol: float = 0.0):
     """Gaussian mixture over the features and element regions; returns
     (result dict, flags as a uint8 array with one entry per element)."""
     _check_f64(features, 3 * mesh.nodes, "features")
@@ -424,7 +424,7 @@ def hdg_cluster_fit(mesh: Mesh, features, iterations: int = 100, reg_covar: floa
         _check_f64(p_visc, mesh.nodes, "p_visc")
     if elem_pv is not None:
         _check_f64(elem_pv, mesh.n_elem, "elem_pv")
-    opts = GmmOpts(int(iterations), 0, float(reg_covar))
+    opts = GmmOpts(int(iterations), 0, float(reg_covar), float(tol))
     res = GmmResult()
     flags = np.zeros(mesh.n_elem, dtype=np.uint8)
     _check(lib().hdg_cluster_fit(mesh.handle, _ptr(features), C.byref(opts), C.byref(res),
@@ -434,7 +434,8 @@ def hdg_cluster_fit(mesh: Mesh, features, iterations: int = 100, reg_covar: floa
     out = dict(feat_mean=np.array(res.feat_mean[:]), feat_std=np.array(res.feat_std[:]),
                weight=np.array(res.weight[:]), mean=np.array([list(r) for r in res.mean]),
                cov=np.array([[list(r) for r in c] for c in res.cov]), log_likelihood=res.log_likelihood,
-               iterations=res.iterations, degenerate=bool(res.degenerate), n_viscous=res.n_viscous)
+               iterations=res.iterations, degenerate=bool(res.degenerate), converged=bool(res.converged),
+               n_viscous=res.n_viscous)
     return out, flags
 
 

@@ -70,7 +70,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: int, cmd_fetch: 
         if k not in write:
             continue
         t = fetch[k] * 1024.0 * f_fetch + write[k] * 1024.0 * f_write
-        lines.append(f"{k:40s} {fetch[k]:12.1f} {write[k]:12.1f} {t:16.0f}")
+        lines.append(f"{k.replace(' ', ''):40s} {fetch[k]:12.1f} {write[k]:12.1f} {t:16.0f}")
     return "\n".join(lines) + "\n"
 
 
@@ -83,9 +83,10 @@ def traffic_for(summary_path: str, kernel_prefix: str):
     m = re.search(r"kernel source hash: (\w+)", text)
     if not m or m.group(1) != kernel_source_hash():
         return None
+    want = kernel_prefix.replace(" ", "")
     for line in text.splitlines():
         parts = line.split()
-        if len(parts) == 4 and parts[0].startswith(kernel_prefix):
+        if len(parts) == 4 and parts[0].startswith(want):
             try:
                 return float(parts[3])
             except ValueError:

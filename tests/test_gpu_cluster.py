@@ -147,6 +147,17 @@ def test_fit_of_oracle_features_and_determinism(orc, torch_cuda, ctx):
     np.testing.assert_allclose(r0["mean"], fo.mixture.mean, rtol=1e-9, atol=1e-10)
     np.testing.assert_allclose(r0["cov"], fo.mixture.cov, rtol=1e-9, atol=1e-10)
     np.testing.assert_allclose(p0, fo.p_visc, atol=1e-9)
+    assert not r0["converged"]
+    # a tolerance ends the fit on the device at the oracle's iteration, unless
+    # the deciding change sits within rounding of the tolerance
+    for tol in (1e-4, 1e-8):
+        ft = CL.fit_gmm(Xo, 500, REG, tol)
+        steps = np.abs(np.diff(ft.history))
+        if np.any(np.abs(steps - tol) < 1e-12):
+            continue
+        rt, _ = hdg.hdg_cluster_fit(m, X, 500, REG, tol=tol)
+        assert rt["converged"] and rt["iterations"] == len(ft.history) < 500
+        np.testing.assert_allclose(rt["mean"], ft.mixture.mean, rtol=1e-9, atol=1e-10)
 
 
 def test_fluid_at_rest_is_degenerate(orc, torch_cuda, ctx):

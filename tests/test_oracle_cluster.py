@@ -125,6 +125,30 @@ def test_scaling_is_unit_free_and_keeps_vanishing_features_small():
     assert np.abs((X[1] - f.feat_mean[1]) / f.feat_std[1]).max() < 1e-20
 
 
+def test_em_tolerance_stop_matches_library():
+    """With a tolerance, the fit stops at the same iteration as the library's
+    EM with the same convergence test."""
+    from sklearn.mixture import GaussianMixture
+    X, _, _ = _two_blobs(2500, 9)
+    X[2] += 0.3 * X[0] ** 2
+    f0 = CL.fit_gmm(X, 0, 1e-6)
+    Xs = ((X - f0.feat_mean[:, None]) / f0.feat_std[:, None]).T
+    R0 = np.zeros((Xs.shape[0], 2))
+    R0[:, 1] = Xs[:, 2] > 0.0
+    R0[:, 0] = 1.0 - R0[:, 1]
+    nk = R0.sum(axis=0)
+    mu0 = R0.T @ Xs / nk[:, None]
+    cov0 = np.stack([(R0[:, k, None] * (Xs - mu0[k])).T @ (Xs - mu0[k]) / nk[k] + 1e-6 * np.eye(3) for k in range(2)])
+    for tol in (1e-2, 1e-5):
+        f = CL.fit_gmm(X, 500, 1e-6, tol)
+        gm = GaussianMixture(2, covariance_type="full", reg_covar=1e-6, max_iter=500, tol=tol,
+                             weights_init=nk / nk.sum(), means_init=mu0, precisions_init=np.linalg.inv(cov0))
+        gm.fit(Xs)
+        assert gm.converged_ and gm.n_iter_ == len(f.history) < 500
+        v = 0 if gm.means_[0, 2] > gm.means_[1, 2] else 1
+        np.testing.assert_allclose(f.mixture.mean, gm.means_[[1 - v, v]], rtol=1e-9, atol=1e-10)
+
+
 def test_em_likelihood_never_decreases():
     X, _, _ = _two_blobs(2000, 11)
     X[2] += 0.5 * X[0] ** 2           # not Gaussian: EM still climbs
