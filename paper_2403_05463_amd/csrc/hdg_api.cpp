@@ -146,6 +146,13 @@ hdg_status upload_plans(hdg_mesh *m)
     m->n_visc = 0;
     for (int64_t e = 0; e < m->ne; ++e) m->n_visc += m->flag[e];
     HDG_HIP(hipMemcpy(m->flag_d, m->flag.data(), m->ne, hipMemcpyHostToDevice));
+    if (!m->conn_h.empty()) {
+        for (FaceRef &r : m->conn_h) {
+            r.code &= ~hdg::kNbrViscBit;
+            if (r.nbr >= 0 && m->flag[r.nbr]) r.code |= hdg::kNbrViscBit;
+        }
+        HDG_HIP(hipMemcpy(m->conn, m->conn_h.data(), m->conn_h.size() * sizeof(FaceRef), hipMemcpyHostToDevice));
+    }
     const std::vector<int> &Ne = m->Ne;
     std::vector<int> cls(m->ne);
     for (auto &v : m->plans) {
@@ -634,6 +641,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         chk(up(m->fgeo32, f32.data(), f32.size() * 4));
     }
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
+    m->conn_h = conn;
     if (m->mixed) {
         std::vector<int8_t> n8(Ne.begin(), Ne.end());
         chk(up(m->eoff, off.data(), off.size() * 8));

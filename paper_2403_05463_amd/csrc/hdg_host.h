@@ -128,6 +128,7 @@ struct hdg_mesh {
     // FP32 copies (one rounding of the FP64 set-up) read by the HDG_F32 kernels
     float *metric32 = nullptr, *fgeo32 = nullptr;
     hdg::FaceRef *conn = nullptr;
+    std::vector<hdg::FaceRef> conn_h;              // host copy (neighbour-flag bits refreshed with the flags)
     uint8_t *flag_d = nullptr;
     int64_t *eoff = nullptr, *foff = nullptr;     // element / face offsets (meshes of mixed order)
     int8_t *Ne_d = nullptr;                        // per-element N (meshes of mixed order)

@@ -24,6 +24,8 @@ struct FaceRef {
 
 constexpr int kOwnerBit = 1 << 6;   // conforming face: this side owns it; mortar: this is the higher side
 constexpr int kMortarBit = 1 << 7;  // face between elements of different order: `face` is the mortar id
+constexpr int kNbrViscBit = 1 << 8; // the neighbour is flagged (kept current with the flags), so a face
+                                    // task issues its viscous-trace loads without first loading the flag
 
 // A face between elements of different order, coupled through a mortar of
 // the higher order in the higher side's face frame.  Its slab (values of the

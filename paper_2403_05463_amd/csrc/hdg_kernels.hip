@@ -194,9 +194,11 @@ struct TileFaces {
     FaceRef f[6 * EPT];
 };
 
-template <int N, int EPT, class T>
+// With STAGE_Q the own state is also staged in LDS, FP64 [4][EPT N^3] at
+// the start of smem, for face tasks to read instead of gathering it again.
+template <int N, int EPT, class T, bool STAGE_Q = false>
 __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, const Tile &tl, T *sD,
-                                          TileFaces<EPT> &tf, TileCtx<N, T> &c)
+                                          TileFaces<EPT> &tf, TileCtx<N, T> &c, double *sq = nullptr)
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3, NL = tile_lanes(N);
     c.tid = threadIdx.x;
@@ -235,6 +237,12 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     c.nu = (T)M.nu;
     c.C_les = (T)M.C_les;
     c.inv_wend = T(N * (N - 1) / 2);   // 1 / w_0 = P (P + 1) / 2
+    if constexpr (STAGE_Q) {
+        if (c.act) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) sq[f * (EPT * N3) + c.g] = c.qd[f];
+        }
+    }
     for (int x = c.tid; x < 7 * EPT; x += blockDim.x) {
         if (x < EPT) {
             tf.e[x] = x < tl.count ? A.elems[tl.first + x] : 0;
@@ -514,15 +522,12 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
 // viscous traces when a side is flagged.  The non-owner sees -F*, and the two
 // sides' implied fluxes are exact negatives in exact arithmetic.
 template <int N, class T>
-__device__ __forceinline__ void face_jump(const Member &M, const gmem<const double> *qin, T c0sq, int e, bool visc,
-                                          int f, int fa, int fb, const FaceRef &fr, T (&F)[4])
+__device__ __forceinline__ void face_jump(const Member &M, const gmem<const double> *qin, T c0sq, bool visc,
+                                          int fa, int fb, const FaceRef &fr, const double (&qm)[4], T (&F)[4])
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
     const bool own = fr.code & kOwnerBit;
-    const gmem<const double> *qe = qin + 4 * elem_off<N>(M, e) + face_node<N>(f, fa, fb);
-    double qm[4], qo[4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) qm[x] = qe[x * N3];
+    double qo[4];
     int oa = fa, ob = fb;
     if (fr.nbr >= 0) {
         int a2, b2;
@@ -573,7 +578,7 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
         const T dF = uL[d] * dun + du[d] * uRn + dp * n[d];
         F[1 + d] = h * sc * (dF + sg * (lp * vp + lm * vm + l0 * tang));
     }
-    const bool nb_visc = fr.nbr >= 0 && gp(M.flag)[fr.nbr];
+    const bool nb_visc = (fr.code & kNbrViscBit) != 0;
     const bool visL = own ? visc : nb_visc;
     const bool visR = own ? nb_visc : visc;
     if (visL || visR) {
@@ -591,7 +596,7 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
     }
 }
 
-template <int N, int EPT, int EPI, class T, bool UNROLL>
+template <int N, int EPT, int EPI, class T>
 __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl, char *smem)
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
@@ -602,8 +607,26 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     const Member &M = A.mem[tl.member];
     TileCtx<N, T> c;
     __shared__ TileFaces<EPT> tf;
-    load_tile<N, EPT, T>(A, M, tl, sD, tf, c);
+    double *sq = (double *)smem;      // [4][NN] own state, FP64, until the fluxes replace it
+    load_tile<N, EPT, T, true>(A, M, tl, sD, tf, c, sq);
     const bool visc = gp(M.flag)[c.e] != 0;
+
+    // face-node tasks, spread evenly over the workgroup; a tile's elements
+    // share one equation class.  The own trace comes from the staged state.
+#pragma unroll 1
+    for (int task = c.tid; task < NTASK; task += blockDim.x) {
+        const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
+        const FaceRef fr = tf.f[ft.s * 6 + ft.f];
+        if (ft.s < tl.count && !(fr.code & kMortarBit)) {
+            const int node = ft.s * N3 + face_node<N>(ft.f, ft.fa, ft.fb);
+            const double qm[4] = {sq[node], sq[NN + node], sq[2 * NN + node], sq[3 * NN + node]};
+            T F[4];
+            face_jump<N, T>(M, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
+#pragma unroll
+            for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
+        }
+    }
+    __syncthreads();     // the staged state is read; the fluxes take its place
 
     // contravariant convective fluxes F^i_row = sum_d Ja^i_d f_{row,d} of the
     // deviation f(q) - f(q_r): c0^2 (u - u_r) and
@@ -627,19 +650,6 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
         }
     }
 
-    // face-node tasks, spread evenly over the workgroup; a tile's elements
-    // share one equation class
-#pragma unroll 1
-    for (int task = c.tid; task < NTASK; task += blockDim.x) {
-        const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
-        const FaceRef fr = tf.f[ft.s * 6 + ft.f];
-        if (ft.s < tl.count && !(fr.code & kMortarBit)) {
-            T F[4];
-            face_jump<N, T>(M, c.qin, c.c0sq, ft.e, visc, ft.f, ft.fa, ft.fb, fr, F);
-#pragma unroll
-            for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
-        }
-    }
     gmem<double> *dqp = gp(A.q_in ? A.dq : M.dq);
     double dq_old[4] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (EPI == (int)Epi::RkStage) {
@@ -651,39 +661,19 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     }
     __syncthreads();
 
-    // reference divergence.  Inside the persistent tile loop the contraction
-    // stays rolled: unrolled there, the scheduler hoists all 12 N LDS reads
-    // and doubles the register count.  A workgroup that takes one tile
-    // unrolls it with the D rows in registers.
+    // reference divergence, with the contraction loop rolled: unrolled, the
+    // scheduler hoists all 12 N LDS reads and needs about twice the
+    // registers (measured: occupancy falls and both launch forms slow down)
     const int base = c.s * N3;
     T V[4] = {T(0), T(0), T(0), T(0)};
-    if constexpr (UNROLL) {
-        T Dx[N], Dy[N], Dz[N];
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            Dx[m] = sD[c.i * N + m];
-            Dy[m] = sD[c.j * N + m];
-            Dz[m] = sD[c.k * N + m];
-        }
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
-                      n2 = base + c.i + N * c.j + N2 * m;
-#pragma unroll
-            for (int row = 0; row < 4; ++row)
-                V[row] += Dx[m] * lds[row * NN + n0] + Dy[m] * lds[(4 + row) * NN + n1] +
-                          Dz[m] * lds[(8 + row) * NN + n2];
-        }
-    } else {
 #pragma unroll 1
-        for (int m = 0; m < N; ++m) {
-            const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
-                      n2 = base + c.i + N * c.j + N2 * m;
-            const T dx = sD[c.i * N + m], dy = sD[c.j * N + m], dz = sD[c.k * N + m];
+    for (int m = 0; m < N; ++m) {
+        const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
+                  n2 = base + c.i + N * c.j + N2 * m;
+        const T dx = sD[c.i * N + m], dy = sD[c.j * N + m], dz = sD[c.k * N + m];
 #pragma unroll
-            for (int row = 0; row < 4; ++row)
-                V[row] += dx * lds[row * NN + n0] + dy * lds[(4 + row) * NN + n1] + dz * lds[(8 + row) * NN + n2];
-        }
+        for (int row = 0; row < 4; ++row)
+            V[row] += dx * lds[row * NN + n0] + dy * lds[(4 + row) * NN + n1] + dz * lds[(8 + row) * NN + n2];
     }
 
     // face nodes: numerical flux minus own flux, over w_end
@@ -757,9 +747,8 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
 
 // One kernel per (kind, order, workgroup size, persistence): a single kernel
 // over every order would carry the register demand of all of them at once
-// (measured: about 1.7x the largest single order), halving occupancy; and a
-// loop around the tile body alone costs the unrolled contraction twice its
-// registers, so only persistent launches loop.
+// (measured: about 1.7x the largest single order), halving occupancy.  Only
+// persistent launches loop over tiles; the others take one tile each.
 template <class T, int N, int B, bool PERS>
 __global__ __launch_bounds__(B) void k_viscous(StageArgs A)
 {
@@ -798,11 +787,11 @@ __global__ __launch_bounds__(B) void k_residual(StageArgs A)
     __shared__ __attribute__((aligned(16))) char smem[(12 * NN + 4 * NTASK + N2) * sizeof(T)];
     if constexpr (PERS) {
         HDG_TILE_LOOP(A, tl) {
-            residual_tile<N, EPT, EPI, T, false>(A, tl, smem);
+            residual_tile<N, EPT, EPI, T>(A, tl, smem);
             __syncthreads();
         }
     } else {
-        HDG_ONE_TILE(A, tl) residual_tile<N, EPT, EPI, T, true>(A, tl, smem);
+        HDG_ONE_TILE(A, tl) residual_tile<N, EPT, EPI, T>(A, tl, smem);
     }
 }
 
