@@ -607,26 +607,33 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     const Member &M = A.mem[tl.member];
     TileCtx<N, T> c;
     __shared__ TileFaces<EPT> tf;
+    // Face tasks read the element's own trace from its state staged in LDS
+    // up to N = 5; above that, keeping the element's context live across the
+    // face tasks costs more registers (and occupancy) than the gathers it
+    // saves, and the trace is gathered from global memory after the fluxes.
+    constexpr bool STAGE = N <= 5;
     double *sq = (double *)smem;      // [4][NN] own state, FP64, until the fluxes replace it
-    load_tile<N, EPT, T, true>(A, M, tl, sD, tf, c, sq);
+    load_tile<N, EPT, T, STAGE>(A, M, tl, sD, tf, c, sq);
     const bool visc = gp(M.flag)[c.e] != 0;
 
-    // face-node tasks, spread evenly over the workgroup; a tile's elements
-    // share one equation class.  The own trace comes from the staged state.
+    if constexpr (STAGE) {
+        // face-node tasks, spread evenly over the workgroup; a tile's elements
+        // share one equation class
 #pragma unroll 1
-    for (int task = c.tid; task < NTASK; task += blockDim.x) {
-        const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
-        const FaceRef fr = tf.f[ft.s * 6 + ft.f];
-        if (ft.s < tl.count && !(fr.code & kMortarBit)) {
-            const int node = ft.s * N3 + face_node<N>(ft.f, ft.fa, ft.fb);
-            const double qm[4] = {sq[node], sq[NN + node], sq[2 * NN + node], sq[3 * NN + node]};
-            T F[4];
-            face_jump<N, T>(M, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
+        for (int task = c.tid; task < NTASK; task += blockDim.x) {
+            const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
+            const FaceRef fr = tf.f[ft.s * 6 + ft.f];
+            if (ft.s < tl.count && !(fr.code & kMortarBit)) {
+                const int node = ft.s * N3 + face_node<N>(ft.f, ft.fa, ft.fb);
+                const double qm[4] = {sq[node], sq[NN + node], sq[2 * NN + node], sq[3 * NN + node]};
+                T F[4];
+                face_jump<N, T>(M, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
 #pragma unroll
-            for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
+                for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
+            }
         }
+        __syncthreads();     // the staged state is read; the fluxes take its place
     }
-    __syncthreads();     // the staged state is read; the fluxes take its place
 
     // contravariant convective fluxes F^i_row = sum_d Ja^i_d f_{row,d} of the
     // deviation f(q) - f(q_r): c0^2 (u - u_r) and
@@ -650,6 +657,21 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
         }
     }
 
+    if constexpr (!STAGE) {
+#pragma unroll 1
+        for (int task = c.tid; task < NTASK; task += blockDim.x) {
+            const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
+            const FaceRef fr = tf.f[ft.s * 6 + ft.f];
+            if (ft.s < tl.count && !(fr.code & kMortarBit)) {
+                const gmem<const double> *qe = c.qin + 4 * elem_off<N>(M, ft.e) + face_node<N>(ft.f, ft.fa, ft.fb);
+                const double qm[4] = {qe[0], qe[N3], qe[2 * N3], qe[3 * N3]};
+                T F[4];
+                face_jump<N, T>(M, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
+#pragma unroll
+                for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
+            }
+        }
+    }
     gmem<double> *dqp = gp(A.q_in ? A.dq : M.dq);
     double dq_old[4] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (EPI == (int)Epi::RkStage) {
