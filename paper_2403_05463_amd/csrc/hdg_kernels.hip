@@ -596,14 +596,68 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
     }
 }
 
+// Surface terms of a face-node lane: the numerical flux minus its own flux,
+// over w_end.  Conforming faces take F* - F_own from the face tasks (sface);
+// a mortar face takes the mortar's surface term relative to the reference
+// flux minus this element's outward deviation flux (own flux from the flux
+// area, so only once the fluxes are there).  CONF and MORT select which.
+template <int N, int EPT, class T, bool CONF, bool MORT>
+__device__ __forceinline__ void surface_terms(const Member &M, const TileFaces<EPT> &tf, const TileCtx<N, T> &c,
+                                              const T *sface, const T *lds, T (&V)[4])
+{
+    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
+    constexpr int NFT = 6 * N2, NN = EPT * N3, NTASK = EPT * NFT;
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+        const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
+        if (c.act && (idx == 0 || idx == N - 1)) {
+            const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
+            const int fa = dir == 0 ? c.j : c.i;
+            const int fb = dir == 2 ? c.j : c.k;
+            const FaceRef fr = tf.f[c.s * 6 + f];
+            if (fr.code & kMortarBit) {
+                if (MORT) {
+                    const MortarRef mr = load_mortar(M.mort, fr.face);
+                    const T sf = (f & 1) ? T(1) : T(-1);
+                    const gmem<const T> *sm = gp((const T *)M.mslab) + mr.slab +
+                                              mslab_surf(mr.Nh, mr.Nl, fr.code & kOwnerBit) + fa + N * fb;
+#pragma unroll
+                    for (int row = 0; row < 4; ++row)
+                        V[row] += (sm[row * N2] - sf * lds[(dir * 4 + row) * NN + c.g]) * c.inv_wend;
+                }
+            } else if (CONF) {
+                const T *Fs = sface + c.s * NFT + f * N2 + fa + N * fb;
+#pragma unroll
+                for (int row = 0; row < 4; ++row) V[row] += Fs[row * NTASK] * c.inv_wend;
+            }
+        }
+    }
+}
+
+// FP64 tiles that stage the state (orders 3 to 5) keep the surface terms in
+// the flux area too, behind the staged state (4 EPT N^3 + 4 EPT 6 N^2 doubles
+// fit in 12 EPT N^3 from N = 3 on): the workgroup's LDS then drops by a
+// quarter, which is what limits occupancy at those orders.
+template <int N, class T>
+constexpr bool residual_sface_in_flux() { return N <= 5 && N >= 3 && sizeof(T) == 8; }
+
+template <int N, int EPT, class T>
+constexpr int residual_lds_words()
+{
+    return 12 * EPT * N * N * N + (residual_sface_in_flux<N, T>() ? 0 : 4 * EPT * 6 * N * N) + N * N;
+}
+
 template <int N, int EPT, int EPI, class T>
 __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl, char *smem)
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
     constexpr int NFT = 6 * N2, NN = EPT * N3, NTASK = EPT * NFT;
+    constexpr bool SF_IN_FLUX = residual_sface_in_flux<N, T>();
     T *lds = (T *)smem;               // [12][NN] contravariant fluxes
-    T *sface = lds + 12 * NN;         // [4][NTASK] surface terms F* - F_own
-    T *sD = sface + 4 * NTASK;        // [N2]
+    // [4][NTASK] surface terms F* - F_own: after the staged state in the flux
+    // area, or after the flux area
+    T *sface = SF_IN_FLUX ? (T *)((double *)smem + 4 * NN) : lds + 12 * NN;
+    T *sD = SF_IN_FLUX ? lds + 12 * NN : sface + 4 * NTASK;   // [N2]
     const Member &M = A.mem[tl.member];
     TileCtx<N, T> c;
     __shared__ TileFaces<EPT> tf;
@@ -633,6 +687,12 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
             }
         }
         __syncthreads();     // the staged state is read; the fluxes take its place
+    }
+    T V[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (SF_IN_FLUX) {
+        // conforming faces' surface terms now, before the fluxes overwrite them
+        surface_terms<N, EPT, T, true, false>(M, tf, c, sface, lds, V);
+        __syncthreads();
     }
 
     // contravariant convective fluxes F^i_row = sum_d Ja^i_d f_{row,d} of the
@@ -687,7 +747,6 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     // scheduler hoists all 12 N LDS reads and needs about twice the
     // registers (measured: occupancy falls and both launch forms slow down)
     const int base = c.s * N3;
-    T V[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll 1
     for (int m = 0; m < N; ++m) {
         const int n0 = base + m + N * c.j + N2 * c.k, n1 = base + c.i + N * m + N2 * c.k,
@@ -698,32 +757,9 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
             V[row] += dx * lds[row * NN + n0] + dy * lds[(4 + row) * NN + n1] + dz * lds[(8 + row) * NN + n2];
     }
 
-    // face nodes: numerical flux minus own flux, over w_end
-#pragma unroll
-    for (int dir = 0; dir < 3; ++dir) {
-        const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
-        if (c.act && (idx == 0 || idx == N - 1)) {
-            const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
-            const int fa = dir == 0 ? c.j : c.i;
-            const int fb = dir == 2 ? c.j : c.k;
-            const FaceRef fr = tf.f[c.s * 6 + f];
-            if (fr.code & kMortarBit) {
-                // mortar: the surface term relative to the reference flux,
-                // minus this element's outward deviation flux
-                const MortarRef mr = load_mortar(M.mort, fr.face);
-                const T sf = (f & 1) ? T(1) : T(-1);
-                const gmem<const T> *sm = gp((const T *)M.mslab) + mr.slab +
-                                          mslab_surf(mr.Nh, mr.Nl, fr.code & kOwnerBit) + fa + N * fb;
-#pragma unroll
-                for (int row = 0; row < 4; ++row)
-                    V[row] += (sm[row * N2] - sf * lds[(dir * 4 + row) * NN + c.g]) * c.inv_wend;
-            } else {
-                const T *Fs = sface + c.s * NFT + f * N2 + fa + N * fb;
-#pragma unroll
-                for (int row = 0; row < 4; ++row) V[row] += Fs[row * NTASK] * c.inv_wend;
-            }
-        }
-    }
+    // face nodes: numerical flux minus own flux, over w_end (mortar faces
+    // only if the conforming ones were added before the fluxes)
+    surface_terms<N, EPT, T, !SF_IN_FLUX, true>(M, tf, c, sface, lds, V);
 
     if (c.act) {
         if (visc) {
@@ -806,7 +842,7 @@ __global__ __launch_bounds__(B) void k_residual(StageArgs A)
     constexpr int EPT = tile_ept(N, B, kTileResidual);
     static_assert(EPT > 0, "tile does not fit the workgroup");
     constexpr int N2 = N * N, NN = EPT * N * N2, NTASK = EPT * 6 * N2;
-    __shared__ __attribute__((aligned(16))) char smem[(12 * NN + 4 * NTASK + N2) * sizeof(T)];
+    __shared__ __attribute__((aligned(16))) char smem[residual_lds_words<N, EPT, T>() * sizeof(T)];
     if constexpr (PERS) {
         HDG_TILE_LOOP(A, tl) {
             residual_tile<N, EPT, EPI, T>(A, tl, smem);
