@@ -520,6 +520,8 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
                 r.code_h = d->orient[e * 6 + f] & 7;
                 r.slab = slab;
                 r.geo = geo;
+                r.oh = off[e];
+                r.ol = off[e2];
                 slab += hdg::mslab_size(r.Nh, r.Nl);
                 geo += (int64_t)r.Nh * r.Nh;
                 fid[e * 6 + f] = (int32_t)nm;

@@ -40,6 +40,7 @@ struct MortarRef {
     int32_t pad;
     int64_t slab;            // first value of the slab
     int64_t geo;             // first mortar node in the mortar geometry [node][4]: n (higher side outward), s
+    int64_t oh, ol;          // first node of each side's element (its state starts at 4 o)
 };
 
 __host__ __device__ constexpr int64_t mslab_tr(int Nh, int Nl, bool hi) { return hi ? 0 : 3 * Nh * Nh; }

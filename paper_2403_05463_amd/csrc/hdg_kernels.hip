@@ -154,6 +154,8 @@ __device__ __forceinline__ MortarRef load_mortar(const MortarRef *mr, int m)
     const gmem<const int64_t> *p64 = gp((const int64_t *)(mr + m)) + 4;
     r.slab = p64[0];
     r.geo = p64[1];
+    r.oh = p64[2];
+    r.ol = p64[3];
     return r;
 }
 
@@ -865,7 +867,8 @@ __global__ __launch_bounds__(B) void k_residual(StageArgs A)
 // as in the element kernels, so that only deviations enter the compute type.
 //
 // Launch shape: one kernel per (NL, NH) pair, 256 lanes per workgroup; a
-// mortar takes NH^2 lanes of one wave (64 / NH^2 mortars share a wave).  The
+// mortar takes NH^2 consecutive lanes (256 / NH^2 mortars per workgroup, a
+// mortar may straddle two waves: every phase ends at a workgroup barrier).  The
 // lower side's face trace is staged once per mortar in LDS; extension and
 // projection are separable contractions with the interpolation rows held in
 // registers.  The lower side's quantities on the mortar are stored in LDS in
@@ -878,12 +881,11 @@ template <int NL, int NH>
 struct MortarShape {
     static constexpr int M2 = NH * NH, L2 = NL * NL;
     static constexpr int N3H = NH * NH * NH, N3L = NL * NL * NL;
-    static constexpr int MPW = 64 / M2;          // mortars per wave
-    static constexpr int SLOTS = 4 * MPW;        // mortars per workgroup
+    static constexpr int SLOTS = 256 / M2;       // mortars per workgroup
 };
 
 // One lane's mortar and node; `valid` is false for lanes past the last mortar
-// or past the mortars a wave holds.
+// or past the workgroup's last whole mortar.
 template <int NL, int NH>
 struct MortarLane {
     int slot, node, i, j, il, jl;
@@ -897,11 +899,10 @@ __device__ __forceinline__ MortarLane<NL, NH> mortar_lane(const StageArgs &A, co
 {
     using S = MortarShape<NL, NH>;
     MortarLane<NL, NH> L;
-    const int lane = threadIdx.x & 63, sub = lane / S::M2;
-    L.node = lane - sub * S::M2;
-    L.slot = (threadIdx.x >> 6) * S::MPW + sub;
+    L.slot = threadIdx.x / S::M2;
+    L.node = threadIdx.x - L.slot * S::M2;
     const int mi = blockIdx.x * S::SLOTS + L.slot;
-    L.valid = sub < S::MPW && mi < A.mcount;
+    L.valid = L.slot < S::SLOTS && mi < A.mcount;
     L.i = L.node % NH;
     L.j = L.node / NH;
     L.il = L.jl = 0;
@@ -910,8 +911,8 @@ __device__ __forceinline__ MortarLane<NL, NH> mortar_lane(const StageArgs &A, co
         L.mr = load_mortar(M.mort, A.mlist[mi]);
         orient_map<NH>(L.mr.code_h & 7, L.i, L.j, L.il, L.jl);
         const gmem<const double> *q = gp((const double *)(A.q_in ? A.q_in : M.qA));
-        L.qh = q + 4 * gp(M.eoff)[L.mr.eh];
-        L.ql = q + 4 * gp(M.eoff)[L.mr.el];
+        L.qh = q + 4 * L.mr.oh;
+        L.ql = q + 4 * L.mr.ol;
     }
     return L;
 }
