@@ -29,20 +29,32 @@ def ctx(torch_cuda):
     return hdg.hdg_init(0)
 
 
+def _node_tables(om):
+    """Per node: its element's first node and node count (flat layout)."""
+    n3 = (om.Ps.astype(np.int64) + 1) ** 3
+    return np.repeat(om.offsets.astype(np.int64), n3), np.repeat(n3, n3)
+
+
 def _fields(om, arr):
-    """Per-field flat vectors of an element-after-element array."""
-    return [np.concatenate([om.element(arr, e, 4)[f] for e in range(om.n_elem)]) for f in range(4)]
+    """Per-field flat vectors of an element-after-element array: node n of
+    element e, field f sits at 4 off_e + f n3_e + (n - off_e)."""
+    off, n3 = _node_tables(om)
+    n = np.arange(om.nodes, dtype=np.int64)
+    flat = np.asarray(arr).ravel()
+    return [flat[n + 3 * off + f * n3] for f in range(4)]
 
 
 def _mass(orc, om):
     J, _ = om.metrics()
+    J = np.asarray(J).ravel()
     out = np.empty(om.nodes)
-    for e in range(om.n_elem):
-        P = int(om.Ps[e])
-        _, w, _ = orc.lgl(P)
-        n3 = (P + 1) ** 3
-        o = int(om.offsets[e])
-        out[o:o + n3] = J[o:o + n3] * np.einsum("k,j,i->kji", w, w, w).ravel()
+    off = om.offsets.astype(np.int64)
+    for P in np.unique(om.Ps):
+        _, w, _ = orc.lgl(int(P))
+        cube = np.einsum("k,j,i->kji", w, w, w).ravel()
+        sel = off[om.Ps == P]
+        idx = (sel[:, None] + np.arange(cube.size)[None]).ravel()
+        out[idx] = J[idx] * np.tile(cube, sel.size)
     return out
 
 
@@ -77,6 +89,11 @@ def _cases():
     fg = W.naca_mask(g)
     yield "O-grid 48x16x4 trilinear, P 2..6", g, fg, W.mixed_orders(fg, 9), \
         dict(les_model=1, C_les=0.1, mixed_face=0, nu=1e-3, q_inf=W.free_stream(20.0))
+    m3, _ = W.reorient(W.periodic_box(4, Pg=1, curve_amp=0.2), seed=11)
+    f3 = W.bernoulli_mask(m3.n_elem, 0.5, 12)
+    yield "reoriented warped box 4^3, P 2..7 (all 15 mortar pairs)", m3, f3, \
+        W.mixed_orders(f3, 3, orders=(2, 3, 4, 5, 6, 7), w_viscous=(1,) * 6, w_euler=(1,) * 6), \
+        dict(les_model=2, C_les=0.07, mixed_face=0)
 
 
 def _prm(kw):
@@ -85,7 +102,7 @@ def _prm(kw):
     return base
 
 
-@pytest.mark.parametrize("case", [0, 1, 2])
+@pytest.mark.parametrize("case", [0, 1, 2, 3])
 def test_mixed_order_residual_parity(orc, torch_cuda, ctx, case):
     torch = torch_cuda
     name, mesh, flag, P, kw = list(_cases())[case]
@@ -185,3 +202,35 @@ def test_mixed_order_autotune_keeps_state_and_results(orc, torch_cuda, ctx):
     torch.cuda.synchronize()
     assert np.array_equal(qd.cpu().numpy(), q0)
     assert torch.equal(r0, r1)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_mixed_airfoil(orc, torch_cuda, ctx):
+    """The mixed-order benchmark mesh itself (192 x 96 x 16 trilinear,
+    P = 2..6, 36.2M nodes, 619k mortar faces): one FP64 residual of the
+    benchmark's initial state, every node against the oracle, and the FP32
+    residual's velocity rows."""
+    torch = torch_cuda
+    w = W.naca_mixed()
+    _say(f"full-size mixed-order residual: {w.name}")
+    om = orc.OracleMesh(w.mesh, w.P, w.flag)
+    q = W.initial_state(w, None)
+    prm = _prm(w.params)
+    ref = om.residual(orc.make_params(**prm), q)
+    m = hdg.hdg_mesh_create(ctx, w.mesh, w.P, w.flag, hdg.make_params(**prm))
+    qd = torch.from_numpy(q).cuda()
+    r = torch.empty_like(qd)
+    hdg.hdg_residual(m, qd, r)
+    torch.cuda.synchronize()
+    got = r.cpu().numpy()
+    del r
+    mass = _mass(orc, om)
+    l2, mx = _errors(om, mass, got, ref)
+    _say(f"per-field L2 {l2}, max {mx}")
+    assert max(l2.max(), mx.max()) <= TOL_F64
+    r32 = torch.empty(qd.shape, dtype=torch.float32, device="cuda")
+    hdg.hdg_residual(m, qd, r32, prec=hdg.HDG_F32)
+    torch.cuda.synchronize()
+    l2f, mxf = _errors(om, mass, r32.cpu().numpy().astype(np.float64), ref)
+    _say(f"FP32 per-field L2 {l2f}, max {mxf}")
+    assert l2f[1:].max() <= 1e-5
