@@ -207,10 +207,33 @@ def serve(requests: list[Request], backend: Backend, mem_budget: int, max_member
     return ServeStats(done, wall, calls, max_seen, peak, dof, counts)
 
 
+def taylor_green_device(torch, X, amp: float, seed: int):
+    """Taylor-Green vortex (the benchmark workloads' formula) evaluated on the
+    device from node coordinates X (n_elem, 3, N^3), plus seeded i.i.d.
+    U[-amp, amp] velocity noise from a device generator: a request's initial
+    state costs no host arithmetic."""
+    x, y, z = X[:, 0], X[:, 1], X[:, 2]
+    q = torch.empty((X.shape[0], 4, X.shape[2]), dtype=torch.float64, device=X.device)
+    q[:, 0] = (torch.cos(2 * x) + torch.cos(2 * y)) * (torch.cos(2 * z) + 2.0) / 16.0
+    q[:, 1] = torch.sin(x) * torch.cos(y) * torch.cos(z)
+    q[:, 2] = -torch.cos(x) * torch.sin(y) * torch.cos(z)
+    q[:, 3] = 0.0
+    if amp > 0:
+        g = torch.Generator(device=X.device)
+        g.manual_seed(int(seed))
+        noise = torch.rand(q[:, 1:4].shape, generator=g, dtype=torch.float64, device=X.device)
+        q[:, 1:4] += (2.0 * noise - 1.0) * amp
+    return q
+
+
 class HdgBackend(Backend):
-    """Device backend: one hdg batch on a non-blocking stream; set-up creates
-    the mesh (host geometry and uploads) and the initial state on a worker
-    thread."""
+    """Device backend: one hdg batch on a non-blocking stream.  Set-up on a
+    worker thread builds the mesh (host geometry and uploads, under the
+    library's device lock); joining, on the stepping thread between batch
+    calls, uploads the node coordinates, evaluates the initial state and the
+    time step on the device and adds the member."""
+
+    C0SQ = 25.0
 
     def __init__(self, ctx, max_members: int, prec: int, torch, stream=None, keep_results: bool = False):
         from . import hdg, workloads as W
@@ -226,44 +249,51 @@ class HdgBackend(Backend):
     def _box(self, n):
         with self._lock:
             if n not in self._boxes:
-                self._boxes[n] = self.W.periodic_box(n, Pg=1)
+                mesh = self.W.periodic_box(n, Pg=1)
+                self._boxes[n] = (mesh, self.W.min_edge_length(mesh))
             return self._boxes[n]
 
     def setup(self, r: Request):
-        hdg, W, torch = self.hdg, self.W, self.torch
-        mesh = self._box(r.n)
+        hdg, W = self.hdg, self.W
+        mesh, hmin = self._box(r.n)
         flag = W.bernoulli_mask(mesh.n_elem, r.frac, r.seed)
         m = hdg.hdg_mesh_create(self.ctx, mesh, r.P, flag,
-                                hdg.make_params(c0sq=25.0, nu=r.nu, les_model=1, C_les=0.1))
-        q0 = W.taylor_green_state(hdg.hdg_mesh_node_coords(m), 0.01, seed=r.seed)
-        dt = 0.5 * W.cfl_dt(mesh, r.P, q0, 25.0)
+                                hdg.make_params(c0sq=self.C0SQ, nu=r.nu, les_model=1, C_les=0.1))
         r.nodes = m.n_elem * m.N3
-        return [m, q0, None, None, dt]
+        return {"mesh": m, "X": hdg.hdg_mesh_node_coords(m), "hmin": hmin, "req": r}
+
+    def _initial(self, h):
+        """Initial state and dt on the device: half the convective limit
+        0.5 h_min / ((P + 1)^2 max(|u| + sqrt(|u|^2 + c0^2)))."""
+        torch = self.torch
+        r = h["req"]
+        q = taylor_green_device(torch, torch.from_numpy(h["X"]).cuda(), 0.01, r.seed)
+        u2 = (q[:, 1:4] ** 2).sum(dim=1)
+        lam = float((u2.sqrt() + (u2 + self.C0SQ).sqrt()).max().item())
+        return q, 0.5 * 0.5 * h["hmin"] / ((r.P + 1) ** 2 * lam)
 
     def join(self, h) -> int:
-        # device arrays are made on the stepping thread, between batch calls
-        torch = self.torch
-        m, q0, _, _, dt = h
-        with torch.cuda.stream(self.stream):
-            q = torch.from_numpy(q0).to("cuda")
-            dq = torch.empty_like(q)
+        with self.torch.cuda.stream(self.stream):
+            q, dt = self._initial(h)
+            dq = self.torch.empty_like(q)
         self.stream.synchronize()
-        h[2], h[3] = q, dq
-        return self.hdg.hdg_batch_add(self.batch, m, q, dq, dt)
+        h.update(q=q, dq=dq, dt=dt)
+        h.pop("X")
+        return self.hdg.hdg_batch_add(self.batch, h["mesh"], q, dq, dt)
 
     def step(self, nsteps: int):
         self.hdg.hdg_batch_rk3_steps(self.batch, nsteps, prec=self.prec, stream=self.stream)
         self.stream.synchronize()
 
     def leave(self, slot: int, h):
-        m, q0, q, dq, dt = h
+        q = h["q"]
         self.hdg.hdg_batch_remove(self.batch, slot)
         out = q.cpu().numpy() if self.keep else bool(self.torch.isfinite(q).all().item())
-        return (out, q0, dt) if self.keep else out
+        return (out, h["dt"]) if self.keep else out
 
     def make_alone(self, r: Request):
         """The same solve, set up on its own: (mesh, q, dq, dt)."""
         h = self.setup(r)
-        m, q0, _, _, dt = h
-        q = self.torch.from_numpy(q0).cuda()
-        return m, q, self.torch.empty_like(q), dt
+        q, dt = self._initial(h)
+        self.torch.cuda.synchronize()
+        return h["mesh"], q, self.torch.empty_like(q), dt

@@ -40,7 +40,7 @@ def test_served_results_equal_alone(torch_cuda, prec):
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
     alone = S.HdgBackend(ctx, max_members=1, prec=prec, torch=torch)
     for r in st.requests:
-        out, q0, dt = r.result
+        out, dt = r.result
         m, q, dq, dt2 = alone.make_alone(r)
         assert dt2 == dt
         hdg.hdg_rk3_steps(m, q, dq, dt, r.nsteps, prec=prec)
