@@ -35,12 +35,14 @@ def build(verbose: bool = False) -> str:
 
 class Params(C.Structure):
     _fields_ = [("c0sq", C.c_double), ("nu", C.c_double), ("les_model", C.c_int),
-                ("C_les", C.c_double), ("mixed_face", C.c_int), ("q_inf", C.c_double * 4)]
+                ("C_les", C.c_double), ("mixed_face", C.c_int), ("q_inf", C.c_double * 4),
+                ("riemann", C.c_int)]
 
 
-def make_params(c0sq=25.0, nu=1e-3, les_model=1, C_les=0.1, mixed_face=0, q_inf=(0, 0, 0, 0)):
+def make_params(c0sq=25.0, nu=1e-3, les_model=1, C_les=0.1, mixed_face=0, q_inf=(0, 0, 0, 0), riemann=0):
     p = Params()
     p.c0sq, p.nu, p.les_model, p.C_les, p.mixed_face = c0sq, nu, les_model, C_les, mixed_face
+    p.riemann = riemann
     for k in range(4):
         p.q_inf[k] = float(q_inf[k])
     return p
@@ -70,6 +72,7 @@ def lib():
         L.orc_filter_width.restype = C.c_double
         L.orc_filter_width.argtypes = [C.c_void_p, C.c_int]
         L.orc_roe_flux.argtypes = [C.c_double, dp, dp, dp, dp]
+        L.orc_rusanov_flux.argtypes = [C.c_double, dp, dp, dp, dp]
         L.orc_les_nut.restype = C.c_double
         L.orc_les_nut.argtypes = [C.c_int, C.c_double, C.c_double, dp]
         L.orc_gradient.argtypes = [C.c_void_p, C.POINTER(Params), dp, dp]
@@ -101,6 +104,15 @@ def roe_flux(c0sq, qL, qR, n):
     n = np.ascontiguousarray(n, dtype=np.float64)
     F = np.zeros(4)
     lib().orc_roe_flux(c0sq, _dp(qL), _dp(qR), _dp(n), _dp(F))
+    return F
+
+
+def rusanov_flux(c0sq, qL, qR, n):
+    qL = np.ascontiguousarray(qL, dtype=np.float64)
+    qR = np.ascontiguousarray(qR, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    F = np.zeros(4)
+    lib().orc_rusanov_flux(c0sq, _dp(qL), _dp(qR), _dp(n), _dp(F))
     return F
 
 

@@ -560,6 +560,30 @@ void orc_roe_flux(double c0sq, const double *qL, const double *qR, const double 
     }
 }
 
+/* Rusanov (local Lax-Friedrichs) flux, the alternative to Roe offered by the
+ * scheme parameters: F = (F(qL) + F(qR))/2 - lambda (qR - qL)/2 with lambda
+ * the larger spectral radius |u_n| + sqrt(u_n^2 + c0^2) of the two states'
+ * normal flux Jacobians. */
+void orc_rusanov_flux(double c0sq, const double *qL, const double *qR, const double *n, double *F)
+{
+    double FL[4], FR[4];
+    normal_flux(c0sq, qL, n, FL);
+    normal_flux(c0sq, qR, n, FR);
+    double uL = qL[1] * n[0] + qL[2] * n[1] + qL[3] * n[2];
+    double uR = qR[1] * n[0] + qR[2] * n[1] + qR[3] * n[2];
+    double lL = fabs(uL) + sqrt(uL * uL + c0sq), lR = fabs(uR) + sqrt(uR * uR + c0sq);
+    double lam = lL > lR ? lL : lR;
+    for (int r = 0; r < 4; ++r) F[r] = 0.5 * (FL[r] + FR[r]) - 0.5 * lam * (qR[r] - qL[r]);
+}
+
+static void numerical_flux(const orc_params *p, const double *qL, const double *qR, const double *n, double *F)
+{
+    if (p->riemann == 1)
+        orc_rusanov_flux(p->c0sq, qL, qR, n, F);
+    else
+        orc_roe_flux(p->c0sq, qL, qR, n, F);
+}
+
 /* LES eddy viscosity from the velocity gradient G[r*3+d] = du_r/dx_d. */
 double orc_les_nut(int model, double C, double delta, const double *G)
 {
@@ -823,7 +847,7 @@ static void face_flux(const orc_mesh *m, const orc_params *p, const double *q, c
     const double *qL = own ? qm : qp;
     const double *qR = own ? qp : qm;
     double F[4];
-    orc_roe_flux(p->c0sq, qL, qR, nh, F);
+    numerical_flux(p, qL, qR, nh, F);
     for (int k = 0; k < 4; ++k) F[k] *= s;
 
     /* BR1 viscous flux: mean of the two sides' viscous fluxes along s n */
@@ -881,7 +905,7 @@ static void mortar_flux(const orc_mesh *m, const orc_params *p, const double *q,
             double s = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
             double nh[3] = {nv[0] / s, nv[1] / s, nv[2] / s};
             double Fr[4];
-            orc_roe_flux(p->c0sq, qh, ql, nh, Fr);
+            numerical_flux(p, qh, ql, nh, Fr);
             fv_dot(m, fv, mt->eh, node, nv, th);
             for (int r = 0; r < 3; ++r) tl[r] = vl ? mortar_extend(m, mt, gl + (4 + r) * Nl * Nl, i, j) : 0.0;
             for (int k = 0; k < 4; ++k) F[k * MM + i + M * j] = s * Fr[k];

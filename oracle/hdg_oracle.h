@@ -32,6 +32,7 @@ typedef struct {
     double C_les;      /* Cs (Smagorinsky) or Cv (Vreman) */
     int mixed_face;    /* 0: viscous flux averaged with a zero Euler side; 1: zero on mixed faces */
     double q_inf[4];   /* far-field state */
+    int riemann;       /* numerical flux: 0 Roe (Sec. 2.3), 1 Rusanov */
 } orc_params;
 
 typedef struct orc_mesh orc_mesh;
@@ -60,6 +61,7 @@ double orc_filter_width(const orc_mesh *m, int e);
 
 /* Building blocks exposed for the pins. */
 void orc_roe_flux(double c0sq, const double *qL, const double *qR, const double *n, double *F);
+void orc_rusanov_flux(double c0sq, const double *qL, const double *qR, const double *n, double *F);
 double orc_les_nut(int model, double C, double delta, const double *G); /* G[r*3+d] = du_r/dx_d */
 
 /* BR1 gradient on every viscous element (others left untouched): G[e][3][3][N_e^3]. */

@@ -74,13 +74,14 @@ def test_mortar_freestream(orc, les, seed):
     assert np.abs(R).max() < 1e-10 * scale
 
 
+@pytest.mark.parametrize("riemann", [0, 1])
 @pytest.mark.parametrize("mixed_face", [0, 1])
-def test_mortar_discrete_conservation(orc, mixed_face):
+def test_mortar_discrete_conservation(orc, mixed_face, riemann):
     m, flag, P = _warped_box(3)
     om = orc.OracleMesh(m, P, flag)
     rng = np.random.default_rng(4)
     q = rng.uniform(-1, 1, size=4 * om.nodes)
-    R = om.residual(_params(orc, mixed_face=mixed_face), q)
+    R = om.residual(_params(orc, mixed_face=mixed_face, riemann=riemann), q)
     WJ = _mass(orc, om)
     for f in range(4):
         Rf = np.concatenate([om.element(R, e, 4)[f] for e in range(om.n_elem)])

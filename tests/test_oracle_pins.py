@@ -208,6 +208,73 @@ def test_roe_dissipation_matches_numpy_eigendecomposition(orc):
         np.testing.assert_allclose(orc.roe_flux(C0SQ, qL, qR, n), expect, rtol=1e-11, atol=1e-11)
 
 
+def test_rusanov_consistency_and_antisymmetry(orc):
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        qL, qR, n = _rand_state_pair(rng)
+        np.testing.assert_allclose(orc.rusanov_flux(C0SQ, qL, qL, n), _Fn(qL, n), rtol=1e-13, atol=1e-13)
+        a = orc.rusanov_flux(C0SQ, qL, qR, n)
+        b = orc.rusanov_flux(C0SQ, qR, qL, -n)
+        np.testing.assert_allclose(a, -b, rtol=1e-12, atol=1e-12)
+
+
+def test_rusanov_speed_is_the_largest_jacobian_eigenvalue(orc):
+    """F_Rus = mean flux - lambda dq / 2 with lambda the largest |eigenvalue|
+    of the normal-flux Jacobian at either state (numpy eig of a
+    finite-difference Jacobian), and it dissipates at least as much as Roe
+    along each Roe eigenvector."""
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        qL, qR, n = _rand_state_pair(rng)
+        lam = 0.0
+        for q in (qL, qR):
+            A = np.zeros((4, 4))
+            for k in range(4):
+                e = np.zeros(4)
+                e[k] = 1.0
+                A[:, k] = (_Fn(q + e, n) - _Fn(q - e, n)) / 2
+            lam = max(lam, np.abs(np.linalg.eigvals(A)).max())
+        expect = 0.5 * (_Fn(qL, n) + _Fn(qR, n)) - 0.5 * lam * (qR - qL)
+        np.testing.assert_allclose(orc.rusanov_flux(C0SQ, qL, qR, n), expect, rtol=1e-11, atol=1e-11)
+        qb = 0.5 * (qL + qR)
+        A = np.zeros((4, 4))
+        for k in range(4):
+            e = np.zeros(4)
+            e[k] = 1.0
+            A[:, k] = (_Fn(qb + e, n) - _Fn(qb - e, n)) / 2
+        assert lam >= np.abs(np.linalg.eigvals(A)).max() - 1e-12
+
+
+def test_rusanov_changes_only_face_nodes_and_only_through_jumps(orc):
+    """The two numerical fluxes differ only in their dissipation of the trace
+    jumps: a discontinuous state gives different residuals at face nodes and
+    identical ones at interior nodes; a continuous (linear) state gives the
+    same residual with either."""
+    P = 3
+    N = P + 1
+    m = W.periodic_box(3, Pg=2, curve_amp=0.3)
+    flag = W.bernoulli_mask(m.n_elem, 0.5, 2)
+    om = orc.OracleMesh(m, P, flag)
+    rng = np.random.default_rng(7)
+    q = rng.uniform(-1, 1, size=(m.n_elem, 4, N ** 3))
+    Ra = om.residual(_params(orc, riemann=0), q)
+    Rb = om.residual(_params(orc, riemann=1), q)
+    i, j, k = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    face = ((i == 0) | (i == N - 1) | (j == 0) | (j == N - 1) | (k == 0) | (k == N - 1)).transpose(2, 1, 0).ravel()
+    assert np.array_equal(Ra[:, :, ~face], Rb[:, :, ~face])
+    assert np.abs(Ra[:, :, face] - Rb[:, :, face]).max() > 1e-3 * np.abs(Ra).max()
+    m2, _ = _interior_box(P)
+    om2 = orc.OracleMesh(m2, P, np.zeros(m2.n_elem, np.uint8))
+    x = om2.node_coords().transpose(0, 2, 1)
+    G = rng.standard_normal((3, 3))
+    q2 = np.empty((m2.n_elem, 4, N ** 3))
+    q2[:, 0] = x @ rng.standard_normal(3)
+    q2[:, 1:] = (x @ G.T).transpose(0, 2, 1)
+    prm = dict(q_inf=(0.0, 0.0, 0.0, 0.0))
+    np.testing.assert_allclose(om2.residual(_params(orc, riemann=1, **prm), q2)[13],
+                               om2.residual(_params(orc, riemann=0, **prm), q2)[13], atol=1e-11 * C0SQ)
+
+
 # --------------------------------------------------------------------------
 # LES closures (App. A: Vreman model; Smagorinsky as the configured model)
 # --------------------------------------------------------------------------
@@ -292,7 +359,8 @@ def test_freestream_preservation_curved_box(orc, les, Pg, P):
     flag = W.bernoulli_mask(m.n_elem, 0.5, 7)
     om = orc.OracleMesh(m, P, flag)
     qc = [0.3, 1.0, -0.5, 0.2]
-    R = om.residual(_params(orc, les_model=les, C_les=0.1 if les == 1 else 0.07), _const_state(m.n_elem, (P + 1) ** 3, qc))
+    R = om.residual(_params(orc, les_model=les, C_les=0.1 if les == 1 else 0.07, riemann=les % 2),
+                    _const_state(m.n_elem, (P + 1) ** 3, qc))
     scale = C0SQ * 1.2 / (2 * math.pi / 3)
     assert np.abs(R).max() < 1e-10 * scale
 
@@ -319,9 +387,10 @@ def _mass(orc, om, P):
     return J * np.einsum("k,j,i->kji", w, w, w).ravel()[None]
 
 
+@pytest.mark.parametrize("riemann", [0, 1])
 @pytest.mark.parametrize("mixed_face", [0, 1])
 @pytest.mark.parametrize("les", [1, 2])
-def test_discrete_conservation_periodic(orc, mixed_face, les):
+def test_discrete_conservation_periodic(orc, mixed_face, les, riemann):
     P = 3
     m, _ = W.reorient(W.periodic_box(3, Pg=2, curve_amp=0.3), seed=5)
     flag = W.bernoulli_mask(m.n_elem, 0.5, 3)
@@ -329,7 +398,7 @@ def test_discrete_conservation_periodic(orc, mixed_face, les):
     rng = np.random.default_rng(9)
     q = rng.uniform(-1, 1, size=(m.n_elem, 4, (P + 1) ** 3))
     R = om.residual(_params(orc, les_model=les, C_les=0.1 if les == 1 else 0.07,
-                            mixed_face=mixed_face), q)
+                            mixed_face=mixed_face, riemann=riemann), q)
     WJ = _mass(orc, om, P)
     for f in range(4):
         tot = (WJ * R[:, f]).sum()
