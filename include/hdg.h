@@ -79,6 +79,7 @@ typedef enum { HDG_F64 = 0, HDG_F32 = 1 } hdg_prec;
 
 enum { HDG_WALL = -1, HDG_FARFIELD = -2 };
 enum { HDG_LES_NONE = 0, HDG_LES_SMAGORINSKY = 1, HDG_LES_VREMAN = 2 };
+enum { HDG_ROE = 0, HDG_RUSANOV = 1 };
 
 /* Kernel classes reported by hdg_timing_read. */
 enum {
@@ -120,6 +121,9 @@ typedef struct {
     int32_t mixed_face;  /* viscous flux on a face with one Euler side: 0 = BR1 mean with
                             a zero Euler-side flux, 1 = no viscous flux */
     double q_inf[4];     /* far-field state (p, u, v, w) */
+    int32_t riemann;     /* numerical flux of the convective terms: HDG_ROE (Sec. 2.3) or
+                            HDG_RUSANOV (mean flux minus the larger spectral radius
+                            |u_n| + sqrt(u_n^2 + c0^2) of the two traces times the jump) */
 } hdg_params;
 
 /* Bind a context to HIP device `device`. */

@@ -118,6 +118,8 @@ hdg_status check_params(const hdg_params *p)
         return fail(HDG_EINVAL, "params: need c0sq > 0, nu >= 0, C_les >= 0");
     if (p->les_model < 0 || p->les_model > 2) return fail(HDG_EINVAL, "params: les_model must be 0, 1 or 2");
     if (p->mixed_face != 0 && p->mixed_face != 1) return fail(HDG_EINVAL, "params: mixed_face must be 0 or 1");
+    if (p->riemann != HDG_ROE && p->riemann != HDG_RUSANOV)
+        return fail(HDG_EINVAL, "params: riemann must be HDG_ROE or HDG_RUSANOV");
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(p->q_inf[k])) return fail(HDG_EINVAL, "params: q_inf not finite");
     return HDG_OK;
@@ -216,6 +218,7 @@ void fill_member_params(Member &mb, const hdg_params &p)
     mb.C_les = p.C_les;
     mb.les_model = p.les_model;
     mb.mixed_face = p.mixed_face;
+    mb.riemann = p.riemann;
     for (int k = 0; k < 4; ++k) mb.qinf[k] = p.q_inf[k];
 }
 

@@ -119,6 +119,8 @@ struct Member {
     double c0sq, nu, C_les, dt;
     double qinf[4];
     int32_t les_model, mixed_face;
+    int32_t riemann;        // HDG_ROE or HDG_RUSANOV
+    int32_t pad;
 };
 
 // Arguments of one persistent launch over a tile list.  With q_in set, the

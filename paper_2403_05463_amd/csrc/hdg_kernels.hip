@@ -561,24 +561,37 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
     const T uLn = uL[0] * n[0] + uL[1] * n[1] + uL[2] * n[2];
     const T dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
     const T uRn = uLn + dun;
-    // mean-state eigen-decomposition of |A| dq (eigenvalues u_n, u_n, u_n +- a)
+    const T sg = own ? T(-1) : T(1);           // -dissipation for the owner, + for the other side
+    // dissipation from the eigen-decomposition of dq at the mean state
+    // (eigenvalues u_n +- a, u_n, u_n): Roe weights each wave by its |speed|;
+    // Rusanov weights every wave by the larger spectral radius lambda of the
+    // two traces, which sums back to lambda dq
     const T un = uLn + h * dun;
     const T a = sqrt(un * un + c0sq);
     const T ia = T(1) / a;
     const T pip = a - un, pim = -a - un;
     const T alp = h * ia * (dp - pim * dun);   // acoustic wave u_n + a
     const T alm = h * ia * (pip * dun - dp);   // acoustic wave u_n - a
-    const T lp = (un + a) * alp, lm = (a - un) * alm, l0 = fabs(un);
-    const T sg = own ? T(-1) : T(1);           // -|A| dq for the owner, + for the other side
-    F[0] = h * sc * (c0sq * dun + sg * (lp * pip + lm * pim));
+    T sp = un + a, sm = a - un, s0 = fabs(un);
+    if (M.riemann == HDG_RUSANOV) {
+        const T lL = fabs(uLn) + sqrt(uLn * uLn + c0sq), lR = fabs(uRn) + sqrt(uRn * uRn + c0sq);
+        sp = sm = s0 = lL > lR ? lL : lR;
+    }
+    const T lp = sp * alp, lm = sm * alm, l0 = s0;
+    T dis[4];
+    dis[0] = lp * pip + lm * pim;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const T ub = uL[d] + h * du[d];
         const T vp = (pip * n[d] + ub) * ia;
         const T vm = -(pim * n[d] + ub) * ia;
-        const T tang = du[d] - alp * vp - alm * vm;
+        dis[1 + d] = lp * vp + lm * vm + l0 * (du[d] - alp * vp - alm * vm);
+    }
+    F[0] = h * sc * (c0sq * dun + sg * dis[0]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
         const T dF = uL[d] * dun + du[d] * uRn + dp * n[d];
-        F[1 + d] = h * sc * (dF + sg * (lp * vp + lm * vm + l0 * tang));
+        F[1 + d] = h * sc * (dF + sg * dis[1 + d]);
     }
     const bool nb_visc = (fr.code & kNbrViscBit) != 0;
     const bool visL = own ? visc : nb_visc;
@@ -1060,7 +1073,7 @@ __global__ __launch_bounds__(256) void k_mortar_flux(StageArgs A)
             rh[x] = L.qh[x * S::N3H + crefh];
             rl[x] = L.ql[x * S::N3L + crefl];
         }
-        // Roe dissipation |A(q_mean)| dq with L = higher side, R = lower side
+        // dissipation with L = higher side, R = lower side
         T uL[3], du[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -1070,13 +1083,20 @@ __global__ __launch_bounds__(256) void k_mortar_flux(StageArgs A)
         const T dp = (T)(qb[0] - qa[0]);
         const T uLn = uL[0] * n[0] + uL[1] * n[1] + uL[2] * n[2];
         const T dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+        // Roe: |A(q_mean)| dq; Rusanov: every wave weighted by lambda (= lambda dq)
         const T un = uLn + h * dun;
         const T a = sqrt(un * un + c0sq);
         const T ia = T(1) / a;
         const T pip = a - un, pim = -a - un;
         const T alp = h * ia * (dp - pim * dun);
         const T alm = h * ia * (pip * dun - dp);
-        const T lp = (un + a) * alp, lm = (a - un) * alm, l0 = fabs(un);
+        T sp = un + a, sm = a - un, s0 = fabs(un);
+        if (M.riemann == HDG_RUSANOV) {
+            const T uRn = uLn + dun;
+            const T lL = fabs(uLn) + sqrt(uLn * uLn + c0sq), lR = fabs(uRn) + sqrt(uRn * uRn + c0sq);
+            sp = sm = s0 = lL > lR ? lL : lR;
+        }
+        const T lp = sp * alp, lm = sm * alm, l0 = s0;
         T Ad[4];
         Ad[0] = lp * pip + lm * pim;
 #pragma unroll

@@ -19,6 +19,7 @@ HDG_OK, HDG_EINVAL, HDG_ENOMEM, HDG_EHIP, HDG_EUNSUPPORTED, HDG_EMESH, HDG_ENONF
 HDG_F64, HDG_F32 = 0, 1
 HDG_WALL, HDG_FARFIELD = -1, -2
 HDG_LES_NONE, HDG_LES_SMAGORINSKY, HDG_LES_VREMAN = 0, 1, 2
+HDG_ROE, HDG_RUSANOV = 0, 1
 HDG_KERNEL_VISCOUS, HDG_KERNEL_RESIDUAL, HDG_KERNEL_MORTAR = 0, 1, 2
 KERNEL_NAMES = {0: "viscous", 1: "residual", 2: "mortar"}
 
@@ -60,7 +61,8 @@ class MeshDesc(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("c0sq", C.c_double), ("nu", C.c_double), ("les_model", C.c_int32),
-                ("C_les", C.c_double), ("mixed_face", C.c_int32), ("q_inf", C.c_double * 4)]
+                ("C_les", C.c_double), ("mixed_face", C.c_int32), ("q_inf", C.c_double * 4),
+                ("riemann", C.c_int32)]
 
 
 class LaunchCfg(C.Structure):
@@ -132,9 +134,10 @@ def hdg_last_error() -> str:
 
 
 def make_params(c0sq=25.0, nu=1e-3, les_model=HDG_LES_SMAGORINSKY, C_les=0.1, mixed_face=0,
-                q_inf=(0.0, 0.0, 0.0, 0.0)) -> Params:
+                q_inf=(0.0, 0.0, 0.0, 0.0), riemann=0) -> Params:
     p = Params()
     p.c0sq, p.nu, p.les_model, p.C_les, p.mixed_face = c0sq, nu, les_model, C_les, mixed_face
+    p.riemann = int(riemann)
     for k in range(4):
         p.q_inf[k] = float(q_inf[k])
     return p

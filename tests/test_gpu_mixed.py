@@ -94,6 +94,8 @@ def _cases():
     yield "reoriented warped box 4^3, P 2..7 (all 15 mortar pairs)", m3, f3, \
         W.mixed_orders(f3, 3, orders=(2, 3, 4, 5, 6, 7), w_viscous=(1,) * 6, w_euler=(1,) * 6), \
         dict(les_model=2, C_les=0.07, mixed_face=0)
+    yield "warped box 3^3, P 2..6, Rusanov flux", m, f, W.mixed_orders(f, 2), \
+        dict(les_model=1, C_les=0.1, mixed_face=0, riemann=1)
 
 
 def _prm(kw):
@@ -102,7 +104,7 @@ def _prm(kw):
     return base
 
 
-@pytest.mark.parametrize("case", [0, 1, 2, 3])
+@pytest.mark.parametrize("case", [0, 1, 2, 3, 4])
 def test_mixed_order_residual_parity(orc, torch_cuda, ctx, case):
     torch = torch_cuda
     name, mesh, flag, P, kw = list(_cases())[case]

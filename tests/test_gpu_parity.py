@@ -95,6 +95,32 @@ def test_residual_parity_orders_and_masks(orc, torch_cuda, ctx, P, mask):
     assert_parity(out, ref, mass, what=f"P={P} {mask}")
 
 
+@pytest.mark.parametrize("P", [2, 4, 6])
+def test_residual_parity_rusanov(orc, torch_cuda, ctx, P):
+    """The Rusanov flux switch: residual (FP64 and FP32) and two RK steps on a
+    curved re-oriented box with a mixed mask."""
+    torch = torch_cuda
+    mesh, _ = W.reorient(W.periodic_box(3, Pg=2, curve_amp=0.3), seed=20 + P)
+    flag = W.bernoulli_mask(mesh.n_elem, 0.5, 20 + P)
+    _say(f"Rusanov flux, reoriented curved box 3^3 P={P}")
+    om = orc.OracleMesh(mesh, P, flag)
+    q = W.taylor_green_state(om.node_coords(), 0.05, seed=P)
+    prm = _params(nu=5e-3, riemann=hdg.HDG_RUSANOV)
+    out, ref, mass, m = _run_pair(orc, torch, ctx, mesh, P, flag, prm, q)
+    assert_parity(out, ref, mass, what=f"Rusanov P={P}")
+    roe = om.residual(orc.make_params(**_params(nu=5e-3)), q)
+    assert np.abs(roe - ref).max() > 1e-6 * np.abs(ref).max()       # the switch changes the result
+    qd = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    r32 = torch.empty(qd.shape, dtype=torch.float32, device="cuda")
+    hdg.hdg_residual(m, qd, r32, prec=hdg.HDG_F32)
+    torch.cuda.synchronize()
+    e = field_errors(r32.cpu().numpy().astype(np.float64), ref, mass)
+    _say(f"Rusanov FP32 P={P}: per-field L2 {e['l2']}")
+    assert e["l2"][1:].max() <= 1e-5                 # velocity rows (pressure row: see the FP32 tests)
+    out, ref, mass, _ = _run_pair(orc, torch, ctx, mesh, P, flag, prm, q, rk=(1e-3, 2))
+    assert_parity(out, ref, mass, what=f"Rusanov RK P={P}")
+
+
 @pytest.mark.parametrize("mixed_face", [0, 1])
 def test_residual_parity_ogrid_small(orc, torch_cuda, ctx, mixed_face):
     mesh = W.naca_ogrid(48, 16, 4, Pg=2)
