@@ -166,6 +166,7 @@ struct TileCtx {
     int g;            // s N^3 + t: node index in the tile's LDS arrays
     bool act;         // the lane holds a node of a real element
     int e;            // member-local element id
+    bool visc;        // the element's equation flag (1 = NS + LES)
     int64_t eo;       // first node of the element
     double qd[4];     // own state, FP64 (the RK stage accumulates in FP64)
     T q[4];           // own state in the compute type
@@ -216,8 +217,23 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     c.k = c.t / N2;
     c.e = A.elems[tl.first + c.s];
     c.eo = elem_off<N>(M, c.e);
+    // Loads are issued before any LDS write that needs one of them: the load
+    // counter is in order, so the metric terms, issued last and needed last,
+    // stay in flight across the barrier while face tasks start.  The first
+    // pass of the derivative-matrix and face-record copies goes through
+    // registers for that reason (N^2 <= 64 and 7 EPT < EPT N^3 never exceed a
+    // workgroup).
     const T *Dm = dtable<T>(A) + d_offset(N);
-    for (int x = c.tid; x < N2; x += blockDim.x) sD[x] = Dm[x];
+    const T dval = c.tid < N2 ? Dm[c.tid] : T(0);
+    int32_t rec_e = 0;
+    FaceRef rec{0, HDG_WALL, 0, 0};
+    if (c.tid < EPT) {
+        if (c.tid < tl.count) rec_e = A.elems[tl.first + c.tid];
+    } else if (c.tid < 7 * EPT) {
+        const int y = c.tid - EPT, s = y / 6;
+        if (s < tl.count) rec = load_face(M.conn, (size_t)A.elems[tl.first + s] * 6 + (y - 6 * s));
+    }
+    c.visc = gp(M.flag)[c.e] != 0;
     c.qin = gp((const double *)(A.q_in ? A.q_in : (A.parity ? M.qB : M.qA)));
     const gmem<double> *qe = c.qin + 4 * c.eo;
     constexpr int cref = (N / 2) * (1 + N + N2);
@@ -239,19 +255,14 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     c.nu = (T)M.nu;
     c.C_les = (T)M.C_les;
     c.inv_wend = T(N * (N - 1) / 2);   // 1 / w_0 = P (P + 1) / 2
+    if (c.tid < N2) sD[c.tid] = dval;
+    if (c.tid < EPT) tf.e[c.tid] = rec_e;
+    else if (c.tid < 7 * EPT) tf.f[c.tid - EPT] = rec;
+    for (int x = c.tid + blockDim.x; x < N2; x += blockDim.x) sD[x] = Dm[x];
     if constexpr (STAGE_Q) {
         if (c.act) {
 #pragma unroll
             for (int f = 0; f < 4; ++f) sq[f * (EPT * N3) + c.g] = c.qd[f];
-        }
-    }
-    for (int x = c.tid; x < 7 * EPT; x += blockDim.x) {
-        if (x < EPT) {
-            tf.e[x] = x < tl.count ? A.elems[tl.first + x] : 0;
-        } else {
-            const int y = x - EPT, s = y / 6;
-            tf.f[y] = s < tl.count ? load_face(M.conn, (size_t)A.elems[tl.first + s] * 6 + (y - 6 * s))
-                                   : FaceRef{0, HDG_WALL, 0, 0};
         }
     }
     __syncthreads();
@@ -512,6 +523,67 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
     }
 }
 
+// 1/sqrt(x) for a normal x > 0: the hardware estimate refined by Newton's
+// method for x^(-1/2), y <- y + y (1 - x y^2) / 2, which squares the relative
+// error (times 3/2) per step; two steps in FP64, one in FP32.
+__device__ __forceinline__ double rsqrt_refined(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return y;
+}
+__device__ __forceinline__ float rsqrt_refined(float x)
+{
+    const float y = __builtin_amdgcn_rsqf(x);
+    return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
+}
+
+// Upwind dissipation D dq of a jump dq = (dp, du) between two traces along a
+// unit normal n, for the artificial-compressibility flux (Sec. 2.3).  The
+// normal Jacobian at the mean state (normal velocity u_n = uLn + dun/2) has
+// the eigenvalues u_n +- a, a = sqrt(u_n^2 + c0^2), and u_n twice; dq splits
+// into the two acoustic waves, amplitudes
+//   alpha_+ = (dp - pi_- du_n) / (2a),  alpha_- = (pi_+ du_n - dp) / (2a),
+//   pi_+- = +-a - u_n, eigenvectors (pi_+-, v_+-) with v_+ = (pi_+ n + u)/a,
+//   v_- = -(pi_- n + u)/a, and the rest, du - alpha_+ v_+ - alpha_- v_-.
+// Roe weights each part by its |eigenvalue|; Rusanov weights all by lambda,
+// the larger spectral radius |u_n| + sqrt(u_n^2 + c0^2) of the two traces
+// (the sum is then lambda dq).  Collecting terms, with s_+-, s_0 the weights:
+//   (D dq)_p = s_+ alpha_+ pi_+ + s_- alpha_- pi_-,
+//   (D dq)_u = X n + Y u + s_0 du,  u = uL + du/2 the mean velocity,
+//   X = P pi_+ - Q pi_-,  Y = P - Q,  P = alpha_+ (s_+ - s_0)/a,  Q = alpha_- (s_- - s_0)/a.
+template <class T>
+struct Dissipation {
+    T p, X, Y, s0;
+};
+
+template <class T>
+__device__ __forceinline__ Dissipation<T> dissipation(int riemann, T c0sq, T uLn, T dun, T dp)
+{
+    const T h = T(0.5);
+    const T un = uLn + h * dun;
+    const T a2 = un * un + c0sq;
+    const T ia = rsqrt_refined(a2);
+    const T a = a2 * ia;
+    const T pip = a - un, pim = -a - un;
+    const T alp = h * ia * (dp - pim * dun);
+    const T alm = h * ia * (pip * dun - dp);
+    T sp = un + a, sm = a - un, s0 = fabs(un);
+    if (riemann == HDG_RUSANOV) {
+        const T uRn = uLn + dun;
+        const T lL = fabs(uLn) + sqrt(uLn * uLn + c0sq), lR = fabs(uRn) + sqrt(uRn * uRn + c0sq);
+        sp = sm = s0 = lL > lR ? lL : lR;
+    }
+    const T P = alp * (sp - s0) * ia, Q = alm * (sm - s0) * ia;
+    Dissipation<T> D;
+    D.p = sp * alp * pip + sm * alm * pim;
+    D.X = P * pip - Q * pim;
+    D.Y = P - Q;
+    D.s0 = s0;
+    return D;
+}
+
 // Surface term of one face node of element e: the single-valued numerical flux
 // minus e's own flux, both outward for e and multiplied by the surface scale.
 // Both elements of a face work with the owner's trace on the left (q_L), the
@@ -523,8 +595,33 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
 // proportional to the jump.  The BR1 viscous flux is the mean of the stored
 // viscous traces when a side is flagged.  The non-owner sees -F*, and the two
 // sides' implied fluxes are exact negatives in exact arithmetic.
+// Member fields that face tasks read, taken once per tile: read through the
+// member record inside the task loop, they are reloaded on every iteration.
+template <class T>
+struct FaceData {
+    const T *geo;             // face geometry in the compute type
+    const T *fvt;             // viscous face traces
+    const int64_t *eoff, *foff;
+    const double *qinf;
+    int32_t riemann, mixed_face;
+};
+
+template <class T>
+__device__ __forceinline__ FaceData<T> face_data(const Member &M)
+{
+    FaceData<T> d;
+    d.geo = (const T *)M.fgeo[prec_index<T>()];
+    d.fvt = (const T *)M.fvt;
+    d.eoff = M.eoff;
+    d.foff = M.foff;
+    d.qinf = M.qinf;
+    d.riemann = M.riemann;
+    d.mixed_face = M.mixed_face;
+    return d;
+}
+
 template <int N, class T>
-__device__ __forceinline__ void face_jump(const Member &M, const gmem<const double> *qin, T c0sq, bool visc,
+__device__ __forceinline__ void face_jump(const FaceData<T> &M, const gmem<const double> *qin, T c0sq, bool visc,
                                           int fa, int fb, const FaceRef &fr, const double (&qm)[4], T (&F)[4])
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
@@ -535,7 +632,7 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
         int a2, b2;
         orient_map<N>(fr.code & 7, fa, fb, a2, b2);
         if (!own) { oa = a2; ob = b2; }
-        const gmem<const double> *qn = qin + 4 * elem_off<N>(M, fr.nbr) + face_node<N>((fr.code >> 3) & 7, a2, b2);
+        const gmem<const double> *qn = qin + 4 * (M.eoff ? gp(M.eoff)[fr.nbr] : (int64_t)fr.nbr * N3) + face_node<N>((fr.code >> 3) & 7, a2, b2);
 #pragma unroll
         for (int x = 0; x < 4; ++x) qo[x] = qn[x * N3];
     } else if (fr.nbr == HDG_WALL) {
@@ -544,55 +641,35 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
         for (int x = 1; x < 4; ++x) qo[x] = -qm[x];
     } else {
 #pragma unroll
-        for (int x = 0; x < 4; ++x) qo[x] = M.qinf[x];
+        for (int x = 0; x < 4; ++x) qo[x] = gp(M.qinf)[x];
     }
     const int fnode = oa + N * ob;
-    const gmem<const T> *g = gp((const T *)M.fgeo[prec_index<T>()]) + 4 * (face_off<N>(M, fr.face) + fnode);
+    const int64_t fo = M.foff ? gp(M.foff)[fr.face] : (int64_t)fr.face * N2;
+    const gmem<const T> *g = gp(M.geo) + 4 * (fo + fnode);
     const T n[3] = {g[0], g[1], g[2]};
     const T sc = g[3];
     T uL[3], du[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+        const double dd = qo[1 + d] - qm[1 + d];
         uL[d] = (T)(own ? qm[1 + d] : qo[1 + d]);
-        du[d] = (T)(own ? qo[1 + d] - qm[1 + d] : qm[1 + d] - qo[1 + d]);
+        du[d] = (T)(own ? dd : -dd);
     }
-    const T dp = (T)(own ? qo[0] - qm[0] : qm[0] - qo[0]);
+    const double dpd = qo[0] - qm[0];
+    const T dp = (T)(own ? dpd : -dpd);
     const T h = T(0.5);
     const T uLn = uL[0] * n[0] + uL[1] * n[1] + uL[2] * n[2];
     const T dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
     const T uRn = uLn + dun;
     const T sg = own ? T(-1) : T(1);           // -dissipation for the owner, + for the other side
-    // dissipation from the eigen-decomposition of dq at the mean state
-    // (eigenvalues u_n +- a, u_n, u_n): Roe weights each wave by its |speed|;
-    // Rusanov weights every wave by the larger spectral radius lambda of the
-    // two traces, which sums back to lambda dq
-    const T un = uLn + h * dun;
-    const T a = sqrt(un * un + c0sq);
-    const T ia = T(1) / a;
-    const T pip = a - un, pim = -a - un;
-    const T alp = h * ia * (dp - pim * dun);   // acoustic wave u_n + a
-    const T alm = h * ia * (pip * dun - dp);   // acoustic wave u_n - a
-    T sp = un + a, sm = a - un, s0 = fabs(un);
-    if (M.riemann == HDG_RUSANOV) {
-        const T lL = fabs(uLn) + sqrt(uLn * uLn + c0sq), lR = fabs(uRn) + sqrt(uRn * uRn + c0sq);
-        sp = sm = s0 = lL > lR ? lL : lR;
-    }
-    const T lp = sp * alp, lm = sm * alm, l0 = s0;
-    T dis[4];
-    dis[0] = lp * pip + lm * pim;
+    const Dissipation<T> D = dissipation<T>(M.riemann, c0sq, uLn, dun, dp);
+    // F_{1+d} = (dF_d + sg (D dq)_d) sc/2 with dF_d = uL_d du_n + du_d uR_n + dp n_d,
+    // the terms collected per vector
+    const T hs = h * sc;
+    const T cU = dun + sg * D.Y, cD = uRn + sg * (h * D.Y + D.s0), cN = dp + sg * D.X;
+    F[0] = hs * (c0sq * dun + sg * D.p);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T ub = uL[d] + h * du[d];
-        const T vp = (pip * n[d] + ub) * ia;
-        const T vm = -(pim * n[d] + ub) * ia;
-        dis[1 + d] = lp * vp + lm * vm + l0 * (du[d] - alp * vp - alm * vm);
-    }
-    F[0] = h * sc * (c0sq * dun + sg * dis[0]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T dF = uL[d] * dun + du[d] * uRn + dp * n[d];
-        F[1 + d] = h * sc * (dF + sg * dis[1 + d]);
-    }
+    for (int d = 0; d < 3; ++d) F[1 + d] = hs * (uL[d] * cU + du[d] * cD + n[d] * cN);
     const bool nb_visc = (fr.code & kNbrViscBit) != 0;
     const bool visL = own ? visc : nb_visc;
     const bool visR = own ? nb_visc : visc;
@@ -600,7 +677,7 @@ __device__ __forceinline__ void face_jump(const Member &M, const gmem<const doub
         // BR1: mean of the two sides' viscous traces (an Euler side contributes
         // zero); a boundary face takes the interior trace.  F* carries -F_v*.
         const bool keep = fr.nbr < 0 || M.mixed_face == 0 || (visL && visR);
-        const gmem<const T> *tv = gp((const T *)M.fvt) + 6 * face_off<N>(M, fr.face) + fnode;
+        const gmem<const T> *tv = gp(M.fvt) + 6 * fo + fnode;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const T tL = visL ? tv[r * N2] : T(0);
@@ -683,7 +760,8 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     constexpr bool STAGE = N <= 5;
     double *sq = (double *)smem;      // [4][NN] own state, FP64, until the fluxes replace it
     load_tile<N, EPT, T, STAGE>(A, M, tl, sD, tf, c, sq);
-    const bool visc = gp(M.flag)[c.e] != 0;
+    const bool visc = c.visc;
+    const FaceData<T> fd = face_data<T>(M);
 
     if constexpr (STAGE) {
         // face-node tasks, spread evenly over the workgroup; a tile's elements
@@ -696,7 +774,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
                 const int node = ft.s * N3 + face_node<N>(ft.f, ft.fa, ft.fb);
                 const double qm[4] = {sq[node], sq[NN + node], sq[2 * NN + node], sq[3 * NN + node]};
                 T F[4];
-                face_jump<N, T>(M, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
+                face_jump<N, T>(fd, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
 #pragma unroll
                 for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
             }
@@ -741,7 +819,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
                 const gmem<const double> *qe = c.qin + 4 * elem_off<N>(M, ft.e) + face_node<N>(ft.f, ft.fa, ft.fb);
                 const double qm[4] = {qe[0], qe[N3], qe[2 * N3], qe[3 * N3]};
                 T F[4];
-                face_jump<N, T>(M, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
+                face_jump<N, T>(fd, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
 #pragma unroll
                 for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
             }
@@ -755,6 +833,14 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
 #pragma unroll
             for (int row = 0; row < 4; ++row) dq_old[row] = dqe[row * N3];
         }
+    }
+    // the viscous operator's volume part, loaded before the contraction so
+    // that its latency is hidden behind it
+    T wvol[3] = {T(0), T(0), T(0)};
+    if (c.act && visc) {
+        const gmem<const T> *wv = gp((const T *)M.wvis) + 3 * c.eo + c.t;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) wvol[r] = wv[r * N3];
     }
     __syncthreads();
 
@@ -777,12 +863,13 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     surface_terms<N, EPT, T, !SF_IN_FLUX, true>(M, tf, c, sface, lds, V);
 
     if (c.act) {
-        if (visc) {
-            const gmem<const T> *wv = gp((const T *)M.wvis) + 3 * c.eo + c.t;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) V[1 + r] += wv[r * N3];
-        }
+        for (int r = 0; r < 3; ++r) V[1 + r] += wvol[r];
         const size_t base_o = 4 * c.eo + c.t;
+        // read from the member record before the first store: a store could
+        // alias it, and a reload after each one would wait for that store
+        const double dt = EPI == (int)Epi::RkStage ? (A.q_in ? A.dt : M.dt) : 0.0;
+        gmem<double> *qout = EPI == (int)Epi::RkStage ? gp(A.q_in ? A.q_out : (A.parity ? M.qA : M.qB)) : nullptr;
 #pragma unroll
         for (int row = 0; row < 4; ++row) {
             const T R = -V[row] * c.invJ;
@@ -792,10 +879,8 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
             } else {
                 // FP64 stage accumulation into the state
                 const double Rd = (double)R;
-                const double dt = A.q_in ? A.dt : M.dt;
                 const double d = A.first_stage ? dt * Rd : A.rkA * dq_old[row] + dt * Rd;
                 dqp[idx] = d;
-                gmem<double> *qout = gp(A.q_in ? A.q_out : (A.parity ? M.qA : M.qB));
                 qout[idx] = c.qd[row] + A.rkB * d;
             }
         }
@@ -1083,29 +1168,11 @@ __global__ __launch_bounds__(256) void k_mortar_flux(StageArgs A)
         const T dp = (T)(qb[0] - qa[0]);
         const T uLn = uL[0] * n[0] + uL[1] * n[1] + uL[2] * n[2];
         const T dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
-        // Roe: |A(q_mean)| dq; Rusanov: every wave weighted by lambda (= lambda dq)
-        const T un = uLn + h * dun;
-        const T a = sqrt(un * un + c0sq);
-        const T ia = T(1) / a;
-        const T pip = a - un, pim = -a - un;
-        const T alp = h * ia * (dp - pim * dun);
-        const T alm = h * ia * (pip * dun - dp);
-        T sp = un + a, sm = a - un, s0 = fabs(un);
-        if (M.riemann == HDG_RUSANOV) {
-            const T uRn = uLn + dun;
-            const T lL = fabs(uLn) + sqrt(uLn * uLn + c0sq), lR = fabs(uRn) + sqrt(uRn * uRn + c0sq);
-            sp = sm = s0 = lL > lR ? lL : lR;
-        }
-        const T lp = sp * alp, lm = sm * alm, l0 = s0;
+        const Dissipation<T> D = dissipation<T>(M.riemann, c0sq, uLn, dun, dp);
         T Ad[4];
-        Ad[0] = lp * pip + lm * pim;
+        Ad[0] = D.p;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T ub = uL[d] + h * du[d];
-            const T vp = (pip * n[d] + ub) * ia;
-            const T vm = -(pim * n[d] + ub) * ia;
-            Ad[1 + d] = lp * vp + lm * vm + l0 * (du[d] - alp * vp - alm * vm);
-        }
+        for (int d = 0; d < 3; ++d) Ad[1 + d] = D.X * n[d] + D.Y * (uL[d] + h * du[d]) + D.s0 * du[d];
         // BR1: mean of the two sides' viscous traces along the higher side's s n
         T fvn[3] = {T(0), T(0), T(0)};
         if (visc) {
