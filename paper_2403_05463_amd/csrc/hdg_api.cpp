@@ -165,7 +165,7 @@ hdg_status upload_plans(hdg_mesh *m)
         v.clear();
     }
     for (int kind = 0; kind < 2; ++kind) {
-        for (int64_t e = 0; e < m->ne; ++e) cls[e] = kind == hdg::kTileViscous ? (m->flag[e] ? 0 : -1) : m->flag[e];
+        for (int64_t e = 0; e < m->ne; ++e) cls[e] = kind == hdg::kTileViscous ? (m->flag[e] ? 1 : -1) : m->flag[e];
         for (int N = 2; N <= hdg::kMaxN; ++N) {
             std::vector<int> cn(m->ne);
             bool any = false;

@@ -85,7 +85,7 @@ hdg_status rebuild_plans(hdg_batch *b)
                     const std::vector<int> &Ne = m->Ne;
                     std::vector<int> cls(m->ne);
                     for (int64_t e = 0; e < m->ne; ++e)
-                        cls[e] = kind == hdg::kTileViscous ? (m->flag[e] ? 0 : -1) : m->flag[e];
+                        cls[e] = kind == hdg::kTileViscous ? (m->flag[e] ? 1 : -1) : m->flag[e];
                     hdg::cut_tiles(m->order, Ne, cls, (int)s, B, kind, tiles, elems);
                 }
                 if (tiles.empty()) continue;

@@ -40,11 +40,12 @@ struct LaunchCfg {
 
 // Split the elements (visited in `order`) into tiles of equal (N, class), each
 // of at most tile_ept(N, B, kind) elements; tiles are ordered by the position
-// of their first element, so the tile list keeps the spatial order.
+// of their first element, so the tile list keeps the spatial order.  Classes
+// are 0 and 1 (-1: left out); a tile's class is stored as its flag.
 inline void cut_tiles(const std::vector<int32_t> &order, const std::vector<int> &Ne, const std::vector<int> &cls,
                int member, int B, int kind, std::vector<Tile> &tiles, std::vector<int32_t> &elems)
 {
-    struct Chunk { size_t pos; int N; std::vector<int32_t> e; };
+    struct Chunk { size_t pos; int cls; std::vector<int32_t> e; };
     std::vector<Chunk> done;
     std::vector<Chunk> open(2 * (hdg::kMaxN + 1));
     std::vector<bool> has(open.size(), false);
@@ -54,7 +55,7 @@ inline void cut_tiles(const std::vector<int32_t> &order, const std::vector<int> 
         const int key = cls[e] * (hdg::kMaxN + 1) + Ne[e];
         const int ept = hdg::tile_ept(Ne[e], B, kind);
         if (!has[key]) {
-            open[key] = Chunk{r, Ne[e], {}};
+            open[key] = Chunk{r, cls[e], {}};
             has[key] = true;
         }
         open[key].e.push_back(e);
@@ -67,7 +68,7 @@ inline void cut_tiles(const std::vector<int32_t> &order, const std::vector<int> 
         if (has[k]) done.push_back(std::move(open[k]));
     std::sort(done.begin(), done.end(), [](const Chunk &a, const Chunk &b) { return a.pos < b.pos; });
     for (auto &c : done) {
-        tiles.push_back(Tile{member, c.N, (int32_t)c.e.size(), (int32_t)elems.size()});
+        tiles.push_back(Tile{member, c.cls, (int32_t)c.e.size(), (int32_t)elems.size()});
         elems.insert(elems.end(), c.e.begin(), c.e.end());
     }
 }

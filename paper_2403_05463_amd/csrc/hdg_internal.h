@@ -63,7 +63,8 @@ __host__ __device__ constexpr int pair_key(int Nl, int Nh) { return Nh * (kMaxN 
 // workgroup of B lanes (element s of the tile owns lanes [s N^3, (s+1) N^3)).
 struct Tile {
     int32_t member;         // index into the member table
-    int32_t N;              // nodes per direction
+    int32_t flag;           // equation flag shared by the tile's elements (residual and viscous tiles);
+                            // the order is the kernel's, one plan per order
     int32_t count;          // elements in this tile (1 .. tile_ept)
     int32_t first;          // first entry in the element array
 };

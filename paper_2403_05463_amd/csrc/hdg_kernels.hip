@@ -166,7 +166,6 @@ struct TileCtx {
     int g;            // s N^3 + t: node index in the tile's LDS arrays
     bool act;         // the lane holds a node of a real element
     int e;            // member-local element id
-    bool visc;        // the element's equation flag (1 = NS + LES)
     int64_t eo;       // first node of the element
     double qd[4];     // own state, FP64 (the RK stage accumulates in FP64)
     T q[4];           // own state in the compute type
@@ -222,18 +221,15 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     // stay in flight across the barrier while face tasks start.  The first
     // pass of the derivative-matrix and face-record copies goes through
     // registers for that reason (N^2 <= 64 and 7 EPT < EPT N^3 never exceed a
-    // workgroup).
+    // workgroup, whose size is at least 128), with unconditional loads at clamped indices: a branch that
+    // wrote the destination registers instead would have to wait for them.
     const T *Dm = dtable<T>(A) + d_offset(N);
-    const T dval = c.tid < N2 ? Dm[c.tid] : T(0);
-    int32_t rec_e = 0;
-    FaceRef rec{0, HDG_WALL, 0, 0};
-    if (c.tid < EPT) {
-        if (c.tid < tl.count) rec_e = A.elems[tl.first + c.tid];
-    } else if (c.tid < 7 * EPT) {
-        const int y = c.tid - EPT, s = y / 6;
-        if (s < tl.count) rec = load_face(M.conn, (size_t)A.elems[tl.first + s] * 6 + (y - 6 * s));
-    }
-    c.visc = gp(M.flag)[c.e] != 0;
+    const T dval = Dm[c.tid < N2 ? c.tid : N2 - 1];
+    const int rs = c.tid < EPT ? c.tid : (c.tid - EPT) / 6;            // element slot of the record
+    // one element per tile: its id is the lane's own (a scalar load), so the
+    // record load does not wait on a vector load
+    const int32_t rel = EPT == 1 ? c.e : A.elems[tl.first + (rs < tl.count ? rs : tl.count - 1)];
+    const FaceRef rrec = load_face(M.conn, (size_t)rel * 6 + (c.tid < EPT ? 0 : (c.tid - EPT) - 6 * rs));
     c.qin = gp((const double *)(A.q_in ? A.q_in : (A.parity ? M.qB : M.qA)));
     const gmem<double> *qe = c.qin + 4 * c.eo;
     constexpr int cref = (N / 2) * (1 + N + N2);
@@ -256,9 +252,8 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     c.C_les = (T)M.C_les;
     c.inv_wend = T(N * (N - 1) / 2);   // 1 / w_0 = P (P + 1) / 2
     if (c.tid < N2) sD[c.tid] = dval;
-    if (c.tid < EPT) tf.e[c.tid] = rec_e;
-    else if (c.tid < 7 * EPT) tf.f[c.tid - EPT] = rec;
-    for (int x = c.tid + blockDim.x; x < N2; x += blockDim.x) sD[x] = Dm[x];
+    if (c.tid < EPT) tf.e[c.tid] = c.tid < tl.count ? rel : 0;
+    else if (c.tid < 7 * EPT) tf.f[c.tid - EPT] = rs < tl.count ? rrec : FaceRef{0, HDG_WALL, 0, 0};
     if constexpr (STAGE_Q) {
         if (c.act) {
 #pragma unroll
@@ -313,6 +308,7 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
     TileCtx<N, T> c;
     __shared__ TileFaces<EPT> tf;
     load_tile<N, EPT, T>(A, M, tl, sD, tf, c);
+    const T delta = (T)gp(M.delta)[c.e];   // LES filter width, loaded here to be ready after the gradient
     if (c.act) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) lds[r * NN + c.g] = c.qt[1 + r];
@@ -449,7 +445,7 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
     }
     T fv[3][3];
     {
-        const T mu = c.nu + les_nut<T>(M.les_model, c.C_les, (T)gp(M.delta)[c.e], G);
+        const T mu = c.nu + les_nut<T>(M.les_model, c.C_les, delta, G);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -760,7 +756,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     constexpr bool STAGE = N <= 5;
     double *sq = (double *)smem;      // [4][NN] own state, FP64, until the fluxes replace it
     load_tile<N, EPT, T, STAGE>(A, M, tl, sD, tf, c, sq);
-    const bool visc = c.visc;
+    const bool visc = tl.flag != 0;   // a tile's elements share one equation flag
     const FaceData<T> fd = face_data<T>(M);
 
     if constexpr (STAGE) {
