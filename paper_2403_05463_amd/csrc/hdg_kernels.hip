@@ -370,6 +370,12 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
                 for (int r = 0; r < 3; ++r) JG[r][d] += g0 * u0[r] + g1 * u1[r] + g2 * u2[r];
             }
         }
+        // the lane's metric terms, read back from LDS rather than kept in
+        // registers through the contraction
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) c.Ja[ii][d] = lds[(3 + 3 * ii + d) * NN + c.g];
 #pragma unroll
         for (int dir = 0; dir < 3; ++dir) {
             const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
@@ -392,12 +398,16 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
                             for (int d = 0; d < 3; ++d) JG[r][d] += jump * c.Ja[dir][d];
                         }
                     } else {
-                        // lower side: (u* - u_r) (s n) integrated on the mortar, minus (u - u_r) (s n)_own
+                        // lower side: (u* - u_r) (s n) integrated on the mortar, minus (u - u_r) (s n)_own;
+                        // one row at a time (scheduling barriers), so that the nine loads do not
+                        // all hold registers at once at the kernel's register peak
 #pragma unroll
-                        for (int r = 0; r < 3; ++r)
+                        for (int r = 0; r < 3; ++r) {
 #pragma unroll
                             for (int d = 0; d < 3; ++d)
                                 JG[r][d] += (lf[(r * 3 + d) * N2] - c.qt[1 + r] * sf * c.Ja[dir][d]) * c.inv_wend;
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
                     }
                 } else {
 #pragma unroll
@@ -568,7 +578,8 @@ __device__ __forceinline__ Dissipation<T> dissipation(int riemann, T c0sq, T uLn
     T sp = un + a, sm = a - un, s0 = fabs(un);
     if (riemann == HDG_RUSANOV) {
         const T uRn = uLn + dun;
-        const T lL = fabs(uLn) + sqrt(uLn * uLn + c0sq), lR = fabs(uRn) + sqrt(uRn * uRn + c0sq);
+        const T xL = uLn * uLn + c0sq, xR = uRn * uRn + c0sq;
+        const T lL = fabs(uLn) + xL * rsqrt_refined(xL), lR = fabs(uRn) + xR * rsqrt_refined(xR);
         sp = sm = s0 = lL > lR ? lL : lR;
     }
     const T P = alp * (sp - s0) * ia, Q = alm * (sm - s0) * ia;
