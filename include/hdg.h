@@ -201,9 +201,9 @@ hdg_status hdg_timing_read(hdg_mesh *mesh, int32_t kernel_class, double *total_m
 
 /* Launch configuration of one kernel class for one precision and one order N
  * = P + 1.  Work is cut into tiles of same-order, same-class elements, one
- * tile per workgroup of `block` lanes (128, 256 or 512; an element takes N^3
- * lanes from P = 3 on rounded to whole 64-lane waves, fewer elements share a
- * wave below); `persistent` launches only as many workgroups as stay
+ * tile per workgroup of `block` lanes (128, 256 or 512, and 384 for N = 7; an
+ * element takes N^3 lanes from P = 3 on rounded to whole 64-lane waves, fewer
+ * elements share a wave below); `persistent` launches only as many workgroups as stay
  * resident, each walking its XCD's share of the tiles, else one workgroup per
  * tile.  The configuration changes launch shape only: results are bitwise
  * identical for every choice. */

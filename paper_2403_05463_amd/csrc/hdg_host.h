@@ -74,7 +74,9 @@ inline void cut_tiles(const std::vector<int32_t> &order, const std::vector<int> 
 }
 
 
-constexpr int kBlocks[3] = {128, 256, 512};
+// Workgroup sizes with kernels; 384 lanes (six waves) serve order 7, whose
+// 343 nodes would leave a third of a 512-lane workgroup idle.
+constexpr int kBlocks[4] = {128, 256, 384, 512};
 
 // Untuned launch configuration of order N: the smallest workgroup that fits
 // an element, one workgroup per tile.

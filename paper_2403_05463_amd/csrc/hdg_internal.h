@@ -71,9 +71,12 @@ struct Tile {
 
 enum TileKind : int { kTileViscous = 0, kTileResidual = 1 };
 
-// LDS budget of one workgroup of B lanes (eight 128-lane, four 256-lane or
-// two 512-lane workgroups share a 160 KB CU).
-constexpr int tile_lds_budget(int B) { return B <= 128 ? 20 * 1024 : B <= 256 ? 40 * 1024 : 78 * 1024; }
+// LDS budget of one workgroup of B lanes (eight 128-lane, four 256-lane,
+// three 384-lane or two 512-lane workgroups share a 160 KB CU).
+constexpr int tile_lds_budget(int B)
+{
+    return B <= 128 ? 20 * 1024 : B <= 256 ? 40 * 1024 : B <= 384 ? 52 * 1024 : 78 * 1024;
+}
 
 // Lanes per element: N^3 packed for N <= 3 (several elements share a wave),
 // whole 64-lane waves from N = 4 on, so that the element is uniform per wave.

@@ -1681,6 +1681,7 @@ hipError_t by_shape(int N, int B, F f)
     if (N == n && B == b) return f(std::integral_constant<int, n>{}, std::integral_constant<int, b>{});
     SH_(2, 128) SH_(3, 128) SH_(4, 128) SH_(5, 128)
     SH_(2, 256) SH_(3, 256) SH_(4, 256) SH_(5, 256) SH_(6, 256)
+    SH_(7, 384)
     SH_(2, 512) SH_(3, 512) SH_(4, 512) SH_(5, 512) SH_(6, 512) SH_(7, 512) SH_(8, 512)
 #undef SH_
     return hipErrorInvalidValue;
@@ -1792,7 +1793,7 @@ hipError_t launch_mortar(bool lift, int Nl, int Nh, bool f32, const StageArgs &a
     return hipErrorInvalidValue;
 }
 
-int feature_block(int N) { return N <= 5 ? 128 : N == 6 ? 256 : 512; }
+int feature_block(int N) { return N <= 5 ? 128 : N == 6 ? 256 : N == 7 ? 384 : 512; }
 
 hipError_t launch_features(int N, const StageArgs &a, int grid, hipStream_t s)
 {
@@ -1802,7 +1803,7 @@ hipError_t launch_features(int N, const StageArgs &a, int grid, hipStream_t s)
         hipLaunchKernelGGL((k_features<n, b>), dim3(grid), dim3(b), 0, s, a);                \
         break;
     switch (N) {
-        F_(2, 128) F_(3, 128) F_(4, 128) F_(5, 128) F_(6, 256) F_(7, 512) F_(8, 512)
+        F_(2, 128) F_(3, 128) F_(4, 128) F_(5, 128) F_(6, 256) F_(7, 384) F_(8, 512)
     default: return hipErrorInvalidValue;
     }
 #undef F_

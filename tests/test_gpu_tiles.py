@@ -31,9 +31,9 @@ def ctx(torch_cuda):
 
 def _shapes(N):
     out = []
-    for B in (128, 256, 512):
+    for B in (128, 256, 384, 512):
         lanes = N ** 3 if N ** 3 < 64 else (N ** 3 + 63) // 64 * 64
-        if lanes <= B and not (N >= 7 and B < 512):
+        if lanes <= B and (B != 384 or N == 7):       # 384-lane kernels exist for order 7 only
             out += [(B, True), (B, False)]
     return out
 
