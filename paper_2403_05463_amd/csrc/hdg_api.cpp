@@ -192,9 +192,11 @@ hdg_status upload_plans(hdg_mesh *m)
             }
         }
     }
-    // mortar lists by (Nl, Nh): lift (a flagged side), flux (all)
+    // mortar lists by (Nl, Nh): lift (a flagged side), flux (all); copies of
+    // the records in list order, so that a mortar kernel loads its record
+    // without first loading an id, with the sides' flags in `flags`
     if (!m->mort_h.empty()) {
-        std::vector<int32_t> lists;
+        std::vector<hdg::MortarRef> lists;
         for (int kind = 0; kind < 2; ++kind)
             for (int key = 0; key <= hdg::kPairKeys; ++key) {
                 m->mlist_off[kind][key] = (int64_t)lists.size();
@@ -203,10 +205,12 @@ hdg_status upload_plans(hdg_mesh *m)
                     const hdg::MortarRef &r = m->mort_h[k];
                     if (hdg::pair_key(r.Nl, r.Nh) != key) continue;
                     if (kind == 0 && !m->flag[r.eh] && !m->flag[r.el]) continue;
-                    lists.push_back((int32_t)k);
+                    hdg::MortarRef c = r;
+                    c.flags = (m->flag[r.eh] ? 1 : 0) | (m->flag[r.el] ? 2 : 0);
+                    lists.push_back(c);
                 }
             }
-        HDG_HIP(hipMemcpy(m->mlist, lists.data(), lists.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HDG_HIP(hipMemcpy(m->mlist, lists.data(), lists.size() * sizeof(hdg::MortarRef), hipMemcpyHostToDevice));
     }
     return HDG_OK;
 }

@@ -143,7 +143,8 @@ struct hdg_mesh {
     hdg::MortarRef *mort = nullptr;
     double *mslab = nullptr, *mgeo = nullptr;
     float *mgeo32 = nullptr;
-    int32_t *mlist = nullptr;                      // mortar ids: lift lists, then flux lists, by (Nl, Nh)
+    hdg::MortarRef *mlist = nullptr;               // mortar records, with the sides' current flags: lift
+                                                   // lists, then flux lists, by (Nl, Nh)
     int64_t mlist_off[2][hdg::kPairKeys + 1] = {}; // [kind][pair_key] start in mlist (kind 0 lift, 1 flux)
     hdg::Member *member = nullptr;              // the mesh's member record (device)
     hdg::Member host_member{};

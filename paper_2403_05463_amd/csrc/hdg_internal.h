@@ -37,7 +37,7 @@ struct MortarRef {
     int32_t eh, fh, el, fl;  // higher / lower order element and local face
     int32_t Nh, Nl;          // nodes per direction on each side
     int32_t code_h;          // orientation code of the higher side (its face coords -> the lower side's)
-    int32_t pad;
+    int32_t flags;           // list copies (mortar kernels): bit 0 higher side flagged, bit 1 lower side
     int64_t slab;            // first value of the slab
     int64_t geo;             // first mortar node in the mortar geometry [node][4]: n (higher side outward), s
     int64_t oh, ol;          // first node of each side's element (its state starts at 4 o)
@@ -142,7 +142,7 @@ struct StageArgs {
     const float *I32;
     const double *W64;      // GLL weights of N nodes at w_offset(N)
     const float *W32;
-    const int32_t *mlist;   // mortar kernels: mortar ids of this launch
+    const MortarRef *mlist; // mortar kernels: records of this launch's mortars, in list order
     int32_t mcount;
     const double *q_in;     // single-member mode
     double *q_out;
@@ -194,7 +194,7 @@ enum class Epi : int { Residual = 0, RkStage = 1 };
 hipError_t launch_viscous(int N, int B, bool f32, bool persistent, const StageArgs &a, int grid, hipStream_t s);
 hipError_t launch_residual(int N, int B, Epi epi, bool f32, bool persistent, const StageArgs &a, int grid,
                            hipStream_t s);
-// Mortar kernels of the pair (Nl, Nh) over a.mlist[0 .. a.mcount): the lift
+// Mortar kernels of the pair (Nl, Nh) over the records a.mlist[0 .. a.mcount): the lift
 // kernel (before the viscous kernels) forms the BR1 lift terms, the flux
 // kernel (after them) the surface terms.  Only supported pairs launch.
 bool mortar_pair_supported(int Nl, int Nh);

@@ -150,7 +150,7 @@ __device__ __forceinline__ MortarRef load_mortar(const MortarRef *mr, int m)
     const gmem<const int32_t> *p = gp((const int32_t *)(mr + m));
     MortarRef r;
     r.eh = p[0]; r.fh = p[1]; r.el = p[2]; r.fl = p[3];
-    r.Nh = p[4]; r.Nl = p[5]; r.code_h = p[6]; r.pad = 0;
+    r.Nh = p[4]; r.Nl = p[5]; r.code_h = p[6]; r.flags = p[7];
     const gmem<const int64_t> *p64 = gp((const int64_t *)(mr + m)) + 4;
     r.slab = p64[0];
     r.geo = p64[1];
@@ -1013,7 +1013,7 @@ __device__ __forceinline__ MortarLane<NL, NH> mortar_lane(const StageArgs &A, co
     L.il = L.jl = 0;
     L.qh = L.ql = nullptr;
     if (L.valid) {
-        L.mr = load_mortar(M.mort, A.mlist[mi]);
+        L.mr = load_mortar(A.mlist, mi);
         orient_map<NH>(L.mr.code_h & 7, L.i, L.j, L.il, L.jl);
         const gmem<const double> *q = gp((const double *)(A.q_in ? A.q_in : M.qA));
         L.qh = q + 4 * L.mr.oh;
@@ -1064,10 +1064,30 @@ __global__ __launch_bounds__(256) void k_mortar_lift(StageArgs A)
     __shared__ T G[S::SLOTS][9 * M2];           // lower side's lift integrand, lower frame
     const Member &M = A.mem[0];
     const MortarLane<NL, NH> L = mortar_lane<NL, NH>(A, M);
+    constexpr int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (NL / 2) * (1 + NL + NL * NL);
+    // the lane's own loads are issued together with the staging loads (one
+    // memory latency before the barrier, not one per dependent step)
+    double uh[3] = {0.0, 0.0, 0.0}, rfh[3] = {0.0, 0.0, 0.0}, rfl[3] = {0.0, 0.0, 0.0};
+    T gv[4] = {T(0), T(0), T(0), T(0)};
     if (L.valid) {
-        for (int v = L.node; v < 3 * L2; v += M2) {
-            const int r = v / L2, ab = v - r * L2;
-            sq[L.slot][v] = L.ql[(1 + r) * S::N3L + face_node<NL>(L.mr.fl, ab % NL, ab / NL)];
+        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (L.mr.geo + L.node);
+        const int nodeh = face_node<NH>(L.mr.fh, L.i, L.j);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) gv[x] = g[x];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            uh[r] = L.qh[(1 + r) * S::N3H + nodeh];
+            rfh[r] = L.qh[(1 + r) * S::N3H + crefh];
+            rfl[r] = L.ql[(1 + r) * S::N3L + crefl];
+        }
+        constexpr int K = (3 * L2 + M2 - 1) / M2;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int v = L.node + k * M2;
+            if (v < 3 * L2) {
+                const int r = v / L2, ab = v - r * L2;
+                sq[L.slot][v] = L.ql[(1 + r) * S::N3L + face_node<NL>(L.mr.fl, ab % NL, ab / NL)];
+            }
         }
     }
     __syncthreads();
@@ -1080,21 +1100,17 @@ __global__ __launch_bounds__(256) void k_mortar_lift(StageArgs A)
             Ia[a] = I[L.il * NL + a];
             Ib[a] = I[L.jl * NL + a];
         }
-        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (L.mr.geo + L.node);
         const T w2 = wh[L.i] * wh[L.j];
-        const T sn[3] = {g[0] * g[3] * w2, g[1] * g[3] * w2, g[2] * g[3] * w2};
-        const int nodeh = face_node<NH>(L.mr.fh, L.i, L.j);
-        constexpr int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (NL / 2) * (1 + NL + NL * NL);
+        const T sn[3] = {gv[0] * gv[3] * w2, gv[1] * gv[3] * w2, gv[2] * gv[3] * w2};
         gmem<T> *lh = gp((T *)M.mslab) + L.mr.slab + mslab_lift(NH, NL, true) + L.node;
         const int gl = L.il + NH * L.jl;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            const double uh = L.qh[(1 + r) * S::N3H + nodeh];
             const double ul = extend_face<NL>(Ia, Ib, &sq[L.slot][r * L2]);
-            const double us = 0.5 * (uh + ul);
+            const double us = 0.5 * (uh[r] + ul);
             // higher side: u* - u_r; its own s n is applied by the element kernel
-            lh[r * M2] = (T)(us - L.qh[(1 + r) * S::N3H + crefh]);
-            const T dl = (T)(us - L.ql[(1 + r) * S::N3L + crefl]);
+            lh[r * M2] = (T)(us - rfh[r]);
+            const T dl = (T)(us - rfl[r]);
 #pragma unroll
             for (int d = 0; d < 3; ++d) G[L.slot][(r * 3 + d) * M2 + gl] = -dl * sn[d];
         }
@@ -1127,18 +1143,45 @@ __global__ __launch_bounds__(256) void k_mortar_flux(StageArgs A)
     __shared__ T G[S::SLOTS][4 * M2];           // lower side's surface integrand, lower frame
     const Member &M = A.mem[0];
     const MortarLane<NL, NH> L = mortar_lane<NL, NH>(A, M);
-    bool vh = false, vl = false, visc = false;
+    // the sides' flags travel in the record; the lane's own loads are issued
+    // together with the staging loads (one memory latency before the barrier)
+    const bool vh = L.valid && (L.mr.flags & 1), vl = L.valid && (L.mr.flags & 2);
+    const bool visc = (vh || vl) && (M.mixed_face == 0 || (vh && vl));
+    constexpr int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (NL / 2) * (1 + NL + NL * NL);
+    double qa[4] = {0.0, 0.0, 0.0, 0.0}, rh[4] = {0.0, 0.0, 0.0, 0.0}, rl[4] = {0.0, 0.0, 0.0, 0.0};
+    T gv[4] = {T(0), T(0), T(0), T(0)}, thv[3] = {T(0), T(0), T(0)};
     if (L.valid) {
-        vh = gp(M.flag)[L.mr.eh] != 0;
-        vl = gp(M.flag)[L.mr.el] != 0;
-        visc = (vh || vl) && (M.mixed_face == 0 || (vh && vl));
-        for (int v = L.node; v < 4 * L2; v += M2) {
-            const int x = v / L2, ab = v - x * L2;
-            sq[L.slot][v] = L.ql[x * S::N3L + face_node<NL>(L.mr.fl, ab % NL, ab / NL)];
+        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (L.mr.geo + L.node);
+        const int nodeh = face_node<NH>(L.mr.fh, L.i, L.j);
+        if (visc && vh) {
+            const gmem<const T> *th = gp((const T *)M.mslab) + L.mr.slab + mslab_tr(NH, NL, true) + L.node;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) thv[r] = th[r * M2];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            gv[x] = g[x];
+            qa[x] = L.qh[x * S::N3H + nodeh];
+            rh[x] = L.qh[x * S::N3H + crefh];
+            rl[x] = L.ql[x * S::N3L + crefl];
+        }
+        constexpr int KQ = (4 * L2 + M2 - 1) / M2;
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) {
+            const int v = L.node + k * M2;
+            if (v < 4 * L2) {
+                const int x = v / L2, ab = v - x * L2;
+                sq[L.slot][v] = L.ql[x * S::N3L + face_node<NL>(L.mr.fl, ab % NL, ab / NL)];
+            }
         }
         if (visc && vl) {
             const gmem<const T> *tl = gp((const T *)M.mslab) + L.mr.slab + mslab_tr(NH, NL, false);
-            for (int v = L.node; v < 3 * L2; v += M2) st[L.slot][v] = tl[v];
+            constexpr int KT = (3 * L2 + M2 - 1) / M2;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                const int v = L.node + k * M2;
+                if (v < 3 * L2) st[L.slot][v] = tl[v];
+            }
         }
     }
     __syncthreads();
@@ -1151,20 +1194,12 @@ __global__ __launch_bounds__(256) void k_mortar_flux(StageArgs A)
             Ia[a] = I[L.il * NL + a];
             Ib[a] = I[L.jl * NL + a];
         }
-        const gmem<const T> *g = gp((const T *)M.mgeo[prec_index<T>()]) + 4 * (L.mr.geo + L.node);
-        const T n[3] = {g[0], g[1], g[2]};
-        const T sc = g[3];
-        const int nodeh = face_node<NH>(L.mr.fh, L.i, L.j);
-        constexpr int crefh = (NH / 2) * (1 + NH + NH * NH), crefl = (NL / 2) * (1 + NL + NL * NL);
+        const T n[3] = {gv[0], gv[1], gv[2]};
+        const T sc = gv[3];
         const T c0sq = (T)M.c0sq, h = T(0.5);
-        double qa[4], qb[4], rh[4], rl[4];       // higher trace, extended lower trace, reference states
+        double qb[4];                            // extended lower trace
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            qa[x] = L.qh[x * S::N3H + nodeh];
-            qb[x] = extend_face<NL>(Ia, Ib, &sq[L.slot][x * L2]);
-            rh[x] = L.qh[x * S::N3H + crefh];
-            rl[x] = L.ql[x * S::N3L + crefl];
-        }
+        for (int x = 0; x < 4; ++x) qb[x] = extend_face<NL>(Ia, Ib, &sq[L.slot][x * L2]);
         // dissipation with L = higher side, R = lower side
         T uL[3], du[3];
 #pragma unroll
@@ -1183,7 +1218,6 @@ __global__ __launch_bounds__(256) void k_mortar_flux(StageArgs A)
         // BR1: mean of the two sides' viscous traces along the higher side's s n
         T fvn[3] = {T(0), T(0), T(0)};
         if (visc) {
-            const gmem<const T> *th = gp((const T *)M.mslab) + L.mr.slab + mslab_tr(NH, NL, true) + L.node;
             T Ta[NL], Tb[NL];
 #pragma unroll
             for (int k = 0; k < NL; ++k) {
@@ -1202,7 +1236,7 @@ __global__ __launch_bounds__(256) void k_mortar_flux(StageArgs A)
                         b_ += Tb[bb] * sb;
                     }
                 }
-                fvn[r] = h * ((vh ? th[r * M2] : T(0)) + b_);
+                fvn[r] = h * (thv[r] + b_);
             }
         }
         // flux relative to each side's reference flux F_n(q_r):
