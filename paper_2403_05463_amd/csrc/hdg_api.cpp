@@ -109,6 +109,14 @@ void free_device(hdg_mesh *m)
     if (m->cap) (void)hipStreamDestroy(m->cap);
     m->gexec = nullptr;
     m->cap = nullptr;
+    for (int i = 0; i < hdg_mesh::kSide; ++i) {
+        if (m->side[i]) (void)hipStreamDestroy(m->side[i]);
+        if (m->ev_join[i]) (void)hipEventDestroy(m->ev_join[i]);
+        m->side[i] = nullptr;
+        m->ev_join[i] = nullptr;
+    }
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+    m->ev_fork = nullptr;
 }
 
 hdg_status check_params(const hdg_params *p)
@@ -299,16 +307,82 @@ hdg_status launch_one(hdg_mesh *m, int kind, int N, const LaunchCfg &cf, const d
     return HDG_OK;
 }
 
+// Side streams and their events, made before any capture (default priority).
+hdg_status side_streams(hdg_mesh *m)
+{
+    if (m->ev_fork) return HDG_OK;
+    for (int i = 0; i < hdg_mesh::kSide; ++i) {
+        HDG_HIP(hipStreamCreateWithFlags(&m->side[i], hipStreamNonBlocking));
+        HDG_HIP(hipEventCreateWithFlags(&m->ev_join[i], hipEventDisableTiming));
+    }
+    HDG_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+    return HDG_OK;
+}
+
+// Launches of one phase of a stage that do not depend on each other (the
+// mortar pairs, the orders): the first runs on the launch stream, later ones
+// round-robin on side streams that first wait for the launch stream's work
+// before the phase; end() joins them back.  Under capture the fork and join
+// become graph edges, so the graph's branches may run concurrently.  Off
+// (everything on the launch stream) while kernel timing is on.
+class Phase {
+public:
+    Phase(hdg_mesh *m, hipStream_t s, bool par) : m_(m), s_(s), par_(par && m->ev_fork) {}
+    hdg_status begin()
+    {
+        if (par_) HDG_HIP(hipEventRecord(m_->ev_fork, s_));
+        return HDG_OK;
+    }
+    // stream for the next launch
+    hdg_status next(hipStream_t &st)
+    {
+        const int k = n_++;
+        if (!par_ || k == 0) {
+            st = s_;
+            return HDG_OK;
+        }
+        const int i = (k - 1) % hdg_mesh::kSide;
+        if (!used_[i]) {
+            HDG_HIP(hipStreamWaitEvent(m_->side[i], m_->ev_fork, 0));
+            used_[i] = true;
+        }
+        st = m_->side[i];
+        return HDG_OK;
+    }
+    hdg_status end()
+    {
+        for (int i = 0; i < hdg_mesh::kSide; ++i)
+            if (used_[i]) {
+                HDG_HIP(hipEventRecord(m_->ev_join[i], m_->side[i]));
+                HDG_HIP(hipStreamWaitEvent(s_, m_->ev_join[i], 0));
+                used_[i] = false;
+            }
+        n_ = 0;
+        return HDG_OK;
+    }
+
+private:
+    hdg_mesh *m_;
+    hipStream_t s_;
+    bool par_;
+    int n_ = 0;
+    bool used_[hdg_mesh::kSide] = {};
+};
+
 // One residual evaluation (EPI Residual) or one fused RK stage (EPI RkStage):
-// the viscous kernels of every order present, then the residual kernels.
+// per kind (viscous, then residual) the mortar kernels of every pair of
+// orders, then the element kernels of every order; launches within each of
+// these four phases are independent.
 hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi epi, bool f32, double A,
                      double B, double dt, bool first, hipStream_t s)
 {
     const int pi = f32 ? 1 : 0;
+    Phase ph(m, s, !m->timing);
     for (int kind = 0; kind < 2; ++kind) {
         // mortars: BR1 lift terms (kind 0) before the viscous kernels, numerical
         // fluxes (kind 1) after them and before the residual kernels
-        if (!m->mort_h.empty())
+        if (!m->mort_h.empty()) {
+            HDG_TRY(ph.begin());
             for (int Nh = 3; Nh <= hdg::kMaxN; ++Nh)
                 for (int Nl = 2; Nl < Nh; ++Nl) {
                     const int key = hdg::pair_key(Nl, Nh);
@@ -322,14 +396,21 @@ hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi ep
                     a.mlist = m->mlist + m->mlist_off[kind][key];
                     a.mcount = (int32_t)(m->mlist_off[kind][key + 1] - m->mlist_off[kind][key]);
                     if (a.mcount == 0) continue;
-                    hdg_status st = timed(m, HDG_KERNEL_MORTAR, s,
-                                          [&] { return hdg::launch_mortar(kind == 0, Nl, Nh, f32, a, s); });
-                    if (st != HDG_OK) return st;
+                    hipStream_t ls;
+                    HDG_TRY(ph.next(ls));
+                    HDG_TRY(timed(m, HDG_KERNEL_MORTAR, ls,
+                                  [&] { return hdg::launch_mortar(kind == 0, Nl, Nh, f32, a, ls); }));
                 }
-        for (int N = 2; N <= hdg::kMaxN; ++N) {
-            hdg_status st = launch_one(m, kind, N, m->cfg[kind][pi][N], q, out, dq, epi, f32, A, B, dt, first, s, true);
-            if (st != HDG_OK) return st;
+            HDG_TRY(ph.end());
         }
+        HDG_TRY(ph.begin());
+        for (int N = 2; N <= hdg::kMaxN; ++N) {
+            if (!find_plan(m, kind, N, m->cfg[kind][pi][N].B)) continue;
+            hipStream_t ls;
+            HDG_TRY(ph.next(ls));
+            HDG_TRY(launch_one(m, kind, N, m->cfg[kind][pi][N], q, out, dq, epi, f32, A, B, dt, first, ls, true));
+        }
+        HDG_TRY(ph.end());
     }
     return HDG_OK;
 }
@@ -687,6 +768,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     }
     if (s2 == HDG_OK) s2 = upload_member(m);
     if (s2 == HDG_OK) s2 = upload_plans(m);
+    if (s2 == HDG_OK) s2 = side_streams(m);   // here, never under a caller's capture
     if (s2 != HDG_OK) {
         free_device(m);
         delete m;

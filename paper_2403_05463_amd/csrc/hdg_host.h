@@ -114,6 +114,12 @@ int launch_grid(const TilePlan &pl, int kind, Epi epi, bool f32, bool persistent
             return hdg::set_error(HDG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+#define HDG_TRY(call)                                                                      \
+    do {                                                                                   \
+        const hdg_status st_ = (call);                                                     \
+        if (st_ != HDG_OK) return st_;                                                     \
+    } while (0)
+
 struct hdg_mesh {
     hdg_ctx *ctx = nullptr;
     int64_t ne = 0;
@@ -169,6 +175,11 @@ struct hdg_mesh {
     // ends where it started), replayed on the caller's stream
     bool graphs = true;
     hipStream_t cap = nullptr;             // private stream used only for capture
+    // independent launches of one phase of a stage (mortar pairs, orders)
+    // spread over side streams forked from the launch stream and joined back
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kSide] = {};
     hipGraphExec_t gexec = nullptr;
     const double *g_q = nullptr;
     const double *g_dq = nullptr;
