@@ -256,7 +256,7 @@ def main(argv=None) -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the multi-GPU element partition is a design only in this build", file=sys.stderr)
+              "the multi-GPU element partition is designed but not implemented", file=sys.stderr)
         return 2
 
     import torch

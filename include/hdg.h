@@ -70,7 +70,7 @@ typedef enum {
     HDG_EINVAL = -1,        /* bad argument (null pointer, size, code) */
     HDG_ENOMEM = -2,        /* device or host allocation failed */
     HDG_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
-    HDG_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+    HDG_EUNSUPPORTED = -4,  /* valid request the library does not implement */
     HDG_EMESH = -5,         /* inconsistent mesh description */
     HDG_ENONFINITE = -6     /* hdg_reduce found a NaN or Inf */
 } hdg_status;

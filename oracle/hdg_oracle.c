@@ -9,7 +9,7 @@
  * splits independent elements across threads; every element's arithmetic is
  * the same sequential loop whatever the thread count.
  *
- * Method (paper: Sec. 2.3 and App. A-B), as read for this build:
+ * Method (paper: Sec. 2.3 and App. A-B), as read here:
  *  - unknowns (p, u, v, w) of the incompressible equations in artificial
  *    compressibility form, dp/dt + c0^2 div u = 0 (unit density);
  *  - every element gets the convective flux (Sec. 2.3); elements flagged
