@@ -948,7 +948,6 @@ __global__ __launch_bounds__(B) void k_residual(StageArgs A)
 {
     constexpr int EPT = tile_ept(N, B, kTileResidual);
     static_assert(EPT > 0, "tile does not fit the workgroup");
-    constexpr int N2 = N * N, NN = EPT * N * N2, NTASK = EPT * 6 * N2;
     __shared__ __attribute__((aligned(16))) char smem[residual_lds_words<N, EPT, T>() * sizeof(T)];
     if constexpr (PERS) {
         HDG_TILE_LOOP(A, tl) {
