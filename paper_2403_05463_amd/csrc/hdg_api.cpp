@@ -109,14 +109,7 @@ void free_device(hdg_mesh *m)
     if (m->cap) (void)hipStreamDestroy(m->cap);
     m->gexec = nullptr;
     m->cap = nullptr;
-    for (int i = 0; i < hdg_mesh::kSide; ++i) {
-        if (m->side[i]) (void)hipStreamDestroy(m->side[i]);
-        if (m->ev_join[i]) (void)hipEventDestroy(m->ev_join[i]);
-        m->side[i] = nullptr;
-        m->ev_join[i] = nullptr;
-    }
-    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
-    m->ev_fork = nullptr;
+    m->ss.destroy();
 }
 
 hdg_status check_params(const hdg_params *p)
@@ -307,68 +300,6 @@ hdg_status launch_one(hdg_mesh *m, int kind, int N, const LaunchCfg &cf, const d
     return HDG_OK;
 }
 
-// Side streams and their events, made before any capture (default priority).
-hdg_status side_streams(hdg_mesh *m)
-{
-    if (m->ev_fork) return HDG_OK;
-    for (int i = 0; i < hdg_mesh::kSide; ++i) {
-        HDG_HIP(hipStreamCreateWithFlags(&m->side[i], hipStreamNonBlocking));
-        HDG_HIP(hipEventCreateWithFlags(&m->ev_join[i], hipEventDisableTiming));
-    }
-    HDG_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
-    return HDG_OK;
-}
-
-// Launches of one phase of a stage that do not depend on each other (the
-// mortar pairs, the orders): the first runs on the launch stream, later ones
-// round-robin on side streams that first wait for the launch stream's work
-// before the phase; end() joins them back.  Under capture the fork and join
-// become graph edges, so the graph's branches may run concurrently.  Off
-// (everything on the launch stream) while kernel timing is on.
-class Phase {
-public:
-    Phase(hdg_mesh *m, hipStream_t s, bool par) : m_(m), s_(s), par_(par && m->ev_fork) {}
-    hdg_status begin()
-    {
-        if (par_) HDG_HIP(hipEventRecord(m_->ev_fork, s_));
-        return HDG_OK;
-    }
-    // stream for the next launch
-    hdg_status next(hipStream_t &st)
-    {
-        const int k = n_++;
-        if (!par_ || k == 0) {
-            st = s_;
-            return HDG_OK;
-        }
-        const int i = (k - 1) % hdg_mesh::kSide;
-        if (!used_[i]) {
-            HDG_HIP(hipStreamWaitEvent(m_->side[i], m_->ev_fork, 0));
-            used_[i] = true;
-        }
-        st = m_->side[i];
-        return HDG_OK;
-    }
-    hdg_status end()
-    {
-        for (int i = 0; i < hdg_mesh::kSide; ++i)
-            if (used_[i]) {
-                HDG_HIP(hipEventRecord(m_->ev_join[i], m_->side[i]));
-                HDG_HIP(hipStreamWaitEvent(s_, m_->ev_join[i], 0));
-                used_[i] = false;
-            }
-        n_ = 0;
-        return HDG_OK;
-    }
-
-private:
-    hdg_mesh *m_;
-    hipStream_t s_;
-    bool par_;
-    int n_ = 0;
-    bool used_[hdg_mesh::kSide] = {};
-};
-
 // One residual evaluation (EPI Residual) or one fused RK stage (EPI RkStage):
 // per kind (viscous, then residual) the mortar kernels of every pair of
 // orders, then the element kernels of every order; launches within each of
@@ -377,7 +308,7 @@ hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi ep
                      double B, double dt, bool first, hipStream_t s)
 {
     const int pi = f32 ? 1 : 0;
-    Phase ph(m, s, !m->timing);
+    hdg::Phase ph(m->ss, s, !m->timing);
     for (int kind = 0; kind < 2; ++kind) {
         // mortars: BR1 lift terms (kind 0) before the viscous kernels, numerical
         // fluxes (kind 1) after them and before the residual kernels
@@ -768,7 +699,10 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     }
     if (s2 == HDG_OK) s2 = upload_member(m);
     if (s2 == HDG_OK) s2 = upload_plans(m);
-    if (s2 == HDG_OK) s2 = side_streams(m);   // here, never under a caller's capture
+    // side streams for the concurrent phases, which only a mesh of several
+    // orders has launches for; made here, never under a caller's capture, and
+    // under the library mutex taken above for the uploads
+    if (s2 == HDG_OK && m->mixed) s2 = m->ss.create();
     if (s2 != HDG_OK) {
         free_device(m);
         delete m;

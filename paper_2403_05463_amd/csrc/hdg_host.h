@@ -120,6 +120,90 @@ int launch_grid(const TilePlan &pl, int kind, Epi epi, bool f32, bool persistent
         if (st_ != HDG_OK) return st_;                                                     \
     } while (0)
 
+namespace hdg {
+
+// Side streams (default priority) and events for the independent launches of
+// one phase of a stage; made once, outside any capture.
+struct SideStreams {
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
+
+    hdg_status create()
+    {
+        if (fork) return HDG_OK;
+        for (int i = 0; i < kSide; ++i) {
+            HDG_HIP(hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking));
+            HDG_HIP(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+        }
+        HDG_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        return HDG_OK;
+    }
+    void destroy()
+    {
+        for (int i = 0; i < kSide; ++i) {
+            if (side[i]) (void)hipStreamDestroy(side[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+            side[i] = nullptr;
+            join[i] = nullptr;
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        fork = nullptr;
+    }
+};
+
+// Launches of one phase of a stage that do not depend on each other (the
+// mortar pairs, the orders): the first runs on the launch stream, later ones
+// round-robin on side streams that first wait for the launch stream's work
+// before the phase; end() joins them back.  Under capture the fork and join
+// become graph edges, so the graph's branches may run concurrently.  With
+// `par` false everything runs on the launch stream.
+class Phase {
+public:
+    Phase(SideStreams &ss, hipStream_t s, bool par) : ss_(ss), s_(s), par_(par && ss.fork) {}
+    hdg_status begin()
+    {
+        n_ = 0;
+        if (par_) HDG_HIP(hipEventRecord(ss_.fork, s_));
+        return HDG_OK;
+    }
+    // stream for the next launch
+    hdg_status next(hipStream_t &st)
+    {
+        const int k = n_++;
+        if (!par_ || k == 0) {
+            st = s_;
+            return HDG_OK;
+        }
+        const int i = (k - 1) % SideStreams::kSide;
+        if (!used_[i]) {
+            HDG_HIP(hipStreamWaitEvent(ss_.side[i], ss_.fork, 0));
+            used_[i] = true;
+        }
+        st = ss_.side[i];
+        return HDG_OK;
+    }
+    hdg_status end()
+    {
+        for (int i = 0; i < SideStreams::kSide; ++i)
+            if (used_[i]) {
+                HDG_HIP(hipEventRecord(ss_.join[i], ss_.side[i]));
+                HDG_HIP(hipStreamWaitEvent(s_, ss_.join[i], 0));
+                used_[i] = false;
+            }
+        return HDG_OK;
+    }
+
+private:
+    SideStreams &ss_;
+    hipStream_t s_;
+    bool par_;
+    int n_ = 0;
+    bool used_[SideStreams::kSide] = {};
+};
+
+}  // namespace hdg
+
 struct hdg_mesh {
     hdg_ctx *ctx = nullptr;
     int64_t ne = 0;
@@ -175,11 +259,7 @@ struct hdg_mesh {
     // ends where it started), replayed on the caller's stream
     bool graphs = true;
     hipStream_t cap = nullptr;             // private stream used only for capture
-    // independent launches of one phase of a stage (mortar pairs, orders)
-    // spread over side streams forked from the launch stream and joined back
-    static constexpr int kSide = 3;
-    hipStream_t side[kSide] = {};
-    hipEvent_t ev_fork = nullptr, ev_join[kSide] = {};
+    hdg::SideStreams ss;                   // for the independent launches of a stage's phases
     hipGraphExec_t gexec = nullptr;
     const double *g_q = nullptr;
     const double *g_dq = nullptr;
