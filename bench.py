@@ -74,9 +74,31 @@ def cpu_baseline(w, q0, budget_s: float = 12.0) -> dict:
         el = time.perf_counter() - t0
         if el >= budget_s or evals >= 1000:
             break
-    return {"value": nodes * 4 * evals / el, "unit": "DOF-residual evals/s", "cores": oracle.get_threads(),
+    threads = oracle.get_threads()
+    # the same on one core, a few evaluations
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        evals1 = 0
+        while True:
+            om.residual(prm, q0)
+            evals1 += 1
+            el1 = time.perf_counter() - t0
+            if el1 >= budget_s / 3 or evals1 >= 100:
+                break
+    finally:
+        oracle.set_threads(threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": nodes * 4 * evals / el, "unit": "DOF-residual evals/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{evals} full residual evaluations of the same workload ({nodes} nodes), {el:.1f} s"}
+            "sample": f"{evals} full residual evaluations of the same workload ({nodes} nodes), {el:.1f} s",
+            "value_1core": nodes * 4 * evals1 / el1, "sample_1core": f"{evals1} evaluations, {el1:.1f} s",
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def mixed_leg(ctx, args, torch, hdg) -> dict:
@@ -302,10 +324,11 @@ def main(argv=None) -> int:
         hdg.hdg_timing_enable(mesh, True)
         hdg.hdg_rk3_steps(mesh, q, dq, dt, args.steps, prec=prec, stream=stream)
         kern = {name: hdg.hdg_timing_read(mesh, k) for k, name in hdg.KERNEL_NAMES.items()}
+        samples = {name: hdg.hdg_timing_samples(mesh, k) for k, name in hdg.KERNEL_NAMES.items()}
         hdg.hdg_timing_enable(mesh, False)
-        return t_start.elapsed_time(t_end), kern
+        return t_start.elapsed_time(t_end), kern, samples
 
-    ms, kern = timed_run(hdg.HDG_F64)
+    ms, kern, samples = timed_run(hdg.HDG_F64)
     red = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
 
     # plain copy kernel of known size: attainable HBM bandwidth, and the
@@ -327,7 +350,7 @@ def main(argv=None) -> int:
     kinds = {name: k for k, name in hdg.KERNEL_NAMES.items()}
     evals = 3 * args.steps
 
-    def roofline(kern, f32):
+    def roofline(kern, f32, samples):
         """Dominant kernel class: algorithmic bytes per launch over its mean event-timed duration."""
         dom = max(kern, key=lambda k: kern[k][0])
         tot, n = kern[dom]
@@ -338,11 +361,14 @@ def main(argv=None) -> int:
         achieved = bytes_launch / avg_s / 1e9
         cfg = tuned[f"{dom}_{'f32' if f32 else 'f64'}"]
         sym = kernel_symbol(kinds[dom], N, f32, cfg["block"], cfg["persistent"])
+        sm = samples.get(dom) or [avg_s * 1e6]
         return {"kernel": sym, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(TRAFFIC_SUMMARY, sym),
-                "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch}
+                "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch,
+                "launches_timed": len(sm),
+                "launch_us_p10_p50_p90": [float(np.percentile(sm, p)) for p in (10, 50, 90)]}
 
-    roof = roofline(kern, False)
+    roof = roofline(kern, False, samples)
     achieved = roof["achieved"]
     out = {
         "metric": METRIC,
@@ -372,12 +398,12 @@ def main(argv=None) -> int:
     # precision form on the same workload and state: FP32 contractions and
     # fluxes, FP64 state and RK accumulation
     q.copy_(torch.from_numpy(q0))
-    ms32, kern32 = timed_run(hdg.HDG_F32)
+    ms32, kern32, samples32 = timed_run(hdg.HDG_F32)
     red32 = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
     out["fp32_plain"] = {"value": nodes * 4 * evals / (ms32 / 1e3), "ms_per_step": ms32 / args.steps,
                          "speedup_vs_fp64": ms / ms32, "state_finite": bool(red32["finite"]),
                          "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern32.items()},
-                         "roofline": roofline(kern32, True), "dtype": "f32 residual, f64 state"}
+                         "roofline": roofline(kern32, True, samples32), "dtype": "f32 residual, f64 state"}
     del q, dq
     if not args.no_cluster:
         print("[bench] clustering", file=sys.stderr, flush=True)

@@ -199,6 +199,13 @@ hdg_status hdg_reduce(hdg_mesh *mesh, const double *r_dev, double out_sum[4], do
 hdg_status hdg_timing_enable(hdg_mesh *mesh, int32_t enable);
 hdg_status hdg_timing_read(hdg_mesh *mesh, int32_t kernel_class, double *total_ms, int64_t *launches);
 
+/* Per-launch durations (microseconds, launch order) of one kernel class
+ * since timing was enabled: us[0 .. min(*count, capacity)) is filled and
+ * *count receives the number of launches recorded.  us may be NULL when
+ * capacity is 0 (a size query).  Synchronises with the recorded events.
+ * HDG_EINVAL on a NULL mesh or count or a bad class. */
+hdg_status hdg_timing_samples(hdg_mesh *mesh, int32_t kernel_class, float *us, int64_t capacity, int64_t *count);
+
 /* Launch configuration of one kernel class for one precision and one order N
  * = P + 1.  Work is cut into tiles of same-order, same-class elements, one
  * tile per workgroup of `block` lanes (128, 256 or 512, and 384 for N = 7; an

@@ -926,6 +926,26 @@ hdg_status hdg_timing_read(hdg_mesh *m, int32_t kind, double *total_ms, int64_t 
     return HDG_OK;
 }
 
+hdg_status hdg_timing_samples(hdg_mesh *m, int32_t kind, float *us, int64_t capacity, int64_t *count)
+{
+    if (!m || !count || kind < 0 || kind >= HDG_KERNEL_COUNT || capacity < 0 || (capacity > 0 && !us))
+        return fail(HDG_EINVAL, "timing_samples: bad argument");
+    HDG_HIP(hipSetDevice(m->ctx->device));
+    if (m->ev_used > 0) HDG_HIP(hipEventSynchronize(m->ev[m->ev_used - 1]));
+    int64_t cnt = 0;
+    for (size_t p = 0; p < m->ev_used / 2; ++p) {
+        if (m->ev_kind[p] != kind) continue;
+        if (cnt < capacity) {
+            float ms = 0.0f;
+            HDG_HIP(hipEventElapsedTime(&ms, m->ev[2 * p], m->ev[2 * p + 1]));
+            us[cnt] = ms * 1000.0f;
+        }
+        ++cnt;
+    }
+    *count = cnt;
+    return HDG_OK;
+}
+
 hdg_status hdg_mesh_autotune(hdg_mesh *m, const double *q, int32_t reps, void *stream)
 {
     if (!m || !q || reps < 1) return fail(HDG_EINVAL, "autotune: need a mesh, a state and reps >= 1");

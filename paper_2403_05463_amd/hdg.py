@@ -27,7 +27,8 @@ EXPORTED = [
     "hdg_init", "hdg_finalize", "hdg_mesh_create", "hdg_mesh_destroy", "hdg_mesh_set_flags",
     "hdg_mesh_set_params", "hdg_mesh_info", "hdg_mesh_node_coords", "hdg_mesh_geometry", "hdg_residual",
     "hdg_rk3_steps",
-    "hdg_reduce", "hdg_timing_enable", "hdg_timing_read", "hdg_stream_copy", "hdg_last_error",
+    "hdg_reduce", "hdg_timing_enable", "hdg_timing_read", "hdg_timing_samples", "hdg_stream_copy",
+    "hdg_last_error",
     "hdg_mesh_autotune", "hdg_mesh_get_launch", "hdg_mesh_set_launch", "hdg_mesh_set_graphs",
     "hdg_batch_create", "hdg_batch_destroy", "hdg_batch_add", "hdg_batch_remove", "hdg_batch_info",
     "hdg_batch_rk3_steps", "hdg_batch_set_graphs", "hdg_batch_autotune", "hdg_batch_get_launch",
@@ -96,6 +97,7 @@ def lib() -> C.CDLL:
         L.hdg_reduce.argtypes = [vp, vp, dp, dp, dp, vp]
         L.hdg_timing_enable.argtypes = [vp, i32]
         L.hdg_timing_read.argtypes = [vp, i32, dp, C.POINTER(i64)]
+        L.hdg_timing_samples.argtypes = [vp, i32, C.POINTER(C.c_float), i64, C.POINTER(i64)]
         L.hdg_stream_copy.argtypes = [vp, vp, vp, i64, vp]
         L.hdg_cluster_features.argtypes = [vp, vp, vp, vp]
         L.hdg_cluster_fit.argtypes = [vp, vp, C.POINTER(GmmOpts), C.POINTER(GmmResult), vp, vp,
@@ -322,6 +324,15 @@ def hdg_timing_read(mesh: Mesh, kernel_class: int) -> tuple[float, int]:
     ms, n = C.c_double(), C.c_int64()
     _check(lib().hdg_timing_read(mesh.handle, kernel_class, C.byref(ms), C.byref(n)), "hdg_timing_read")
     return ms.value, n.value
+
+
+def hdg_timing_samples(mesh: Mesh, kernel_class: int) -> list[float]:
+    """Per-launch durations in microseconds, in launch order."""
+    n = C.c_int64()
+    _check(lib().hdg_timing_samples(mesh.handle, kernel_class, None, 0, C.byref(n)), "hdg_timing_samples")
+    buf = (C.c_float * max(n.value, 1))()
+    _check(lib().hdg_timing_samples(mesh.handle, kernel_class, buf, n.value, C.byref(n)), "hdg_timing_samples")
+    return [float(buf[i]) for i in range(n.value)]
 
 
 def hdg_mesh_autotune(mesh: Mesh, q, reps: int = 5, stream=None):

@@ -283,7 +283,11 @@ def test_timing_and_copy_probe(torch_cuda, ctx):
     for k in (hdg.HDG_KERNEL_VISCOUS, hdg.HDG_KERNEL_RESIDUAL):
         ms, n = hdg.hdg_timing_read(m, k)
         assert n == 6 and ms > 0
+        us = hdg.hdg_timing_samples(m, k)                           # the same launches, one by one
+        assert len(us) == n and min(us) > 0
+        assert abs(sum(us) / 1e3 - ms) <= 1e-3 * ms
     assert hdg.hdg_timing_read(m, hdg.HDG_KERNEL_MORTAR)[1] == 0     # one order: no mortar faces
+    assert hdg.hdg_timing_samples(m, hdg.HDG_KERNEL_MORTAR) == []
     hdg.hdg_timing_enable(m, False)
     a = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
