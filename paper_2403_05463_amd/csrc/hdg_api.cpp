@@ -107,8 +107,10 @@ void free_device(hdg_mesh *m)
     m->ev.clear();
     if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
     if (m->cap) (void)hipStreamDestroy(m->cap);
+    if (m->g_done) (void)hipEventDestroy(m->g_done);
     m->gexec = nullptr;
     m->cap = nullptr;
+    m->g_done = nullptr;
     m->ss.destroy();
 }
 
@@ -137,6 +139,9 @@ const TilePlan *find_plan(const hdg_mesh *m, int kind, int N, int B)
 // Drop the captured RK graph (its launches bake in plans, shapes and buffers).
 void drop_graph(hdg_mesh *m)
 {
+    // the executable may still run (its branches on several streams): wait
+    // for its last replay before destroying it
+    if (m->gexec && m->g_done) (void)hipEventSynchronize(m->g_done);
     if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
     m->gexec = nullptr;
     m->g_prec = -1;
@@ -819,6 +824,7 @@ hdg_status hdg_rk3_steps(hdg_mesh *m, double *q, double *dq, double dt, int32_t 
         if (!m->gexec || m->g_q != q || m->g_dq != dq || m->g_dt != dt || m->g_prec != (int)prec) {
             drop_graph(m);
             if (!m->cap) HDG_HIP(hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking));
+            if (!m->g_done) HDG_HIP(hipEventCreateWithFlags(&m->g_done, hipEventDisableTiming));
             // occupancy queries happen before capture, not inside it
             for (int kind = 0; kind < 2; ++kind)
                 for (int N = 2; N <= hdg::kMaxN; ++N) {
@@ -851,6 +857,7 @@ hdg_status hdg_rk3_steps(hdg_mesh *m, double *q, double *dq, double dt, int32_t 
             m->g_prec = (int)prec;
         }
         for (int32_t k = 0; k < nsteps / 2; ++k) HDG_HIP(hipGraphLaunch(m->gexec, s));
+        HDG_HIP(hipEventRecord(m->g_done, s));
         eager = nsteps % 2;
     }
     double *cur = q, *nxt = m->qpp;

@@ -259,6 +259,7 @@ struct hdg_mesh {
     // ends where it started), replayed on the caller's stream
     bool graphs = true;
     hipStream_t cap = nullptr;             // private stream used only for capture
+    hipEvent_t g_done = nullptr;           // recorded behind the last replay of gexec
     hdg::SideStreams ss;                   // for the independent launches of a stage's phases
     hipGraphExec_t gexec = nullptr;
     const double *g_q = nullptr;
