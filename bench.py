@@ -31,16 +31,18 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_naca0012_ogrid_96x48x8_P4.txt")
 
 
-def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: bool, f32: bool = False) -> float:
+def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: bool, f32: bool = False,
+                      first_stage: bool = False) -> float:
     """Bytes a launch must move at least once (perfect caching).
 
     Residual kernel, every element: state 32 B/node (FP64 in both precision
     forms), metric terms (1/J + 9 Ja) 80 B/node in FP64, 40 in FP32; fused
-    RK stage: + dq read/write 64 + next state 32 (residual only: + R 32 in
-    FP64, 16 in FP32); face geometry (n, s) 32 B (16) per face node, three
-    faces owned per element.  Flagged elements add the viscous divergence
-    part (24 B/node, 12 in FP32) and both sides' viscous face traces (24 B,
-    12 in FP32, per face node and side).
+    RK stage: + dq write 32 and read 32 (not read in the first stage, whose
+    coefficient A is zero) + next state 32 (residual only: + R 32 in FP64,
+    16 in FP32); face geometry (n, s) 32 B (16) per face node, three faces
+    owned per element.  Flagged elements add the viscous divergence part
+    (24 B/node, 12 in FP32) and both sides' viscous face traces (24 B, 12 in
+    FP32, per face node and side).
     Viscous kernel, flagged elements: velocity 24 + metric terms per node,
     out the viscous part per node and six faces of traces.
     """
@@ -48,7 +50,7 @@ def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: boo
     met, tv, fg = (40, 12, 16) if f32 else (80, 24, 32)
     if kind == 0:
         return float(n_visc * ((24 + met + tv) * N3 + 6 * N2 * tv))
-    per_node = 32 + met + (96 if fused_rk else (16 if f32 else 32))
+    per_node = 32 + met + ((64 if first_stage else 96) if fused_rk else (16 if f32 else 32))
     b = n_elem * (per_node * N3 + 3 * N2 * fg)
     b += n_visc * (tv * N3 + 6 * N2 * tv)
     return float(b)
@@ -355,9 +357,11 @@ def main(argv=None) -> int:
         dom = max(kern, key=lambda k: kern[k][0])
         tot, n = kern[dom]
         avg_s = tot / max(n, 1) / 1e3
-        # every stage runs each kernel class once over its element set
-        bytes_launch = algorithmic_bytes(kinds[dom], w.mesh.n_elem, n_visc, N, fused_rk=True, f32=f32) \
-            * evals / max(n, 1)
+        # every stage runs each kernel class once over its element set; the
+        # first of the three stages does not read the RK register
+        per_step = sum(algorithmic_bytes(kinds[dom], w.mesh.n_elem, n_visc, N, fused_rk=True, f32=f32,
+                                         first_stage=(st == 0)) for st in range(3))
+        bytes_launch = per_step * args.steps / max(n, 1)
         achieved = bytes_launch / avg_s / 1e9
         cfg = tuned[f"{dom}_{'f32' if f32 else 'f64'}"]
         sym = kernel_symbol(kinds[dom], N, f32, cfg["block"], cfg["persistent"])
