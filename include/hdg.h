@@ -254,8 +254,10 @@ typedef struct hdg_batch hdg_batch;
 hdg_status hdg_batch_create(hdg_ctx *ctx, int32_t max_members, hdg_batch **out);
 void hdg_batch_destroy(hdg_batch *batch);
 /* Adds `mesh` with its state q_dev, register dq_dev (distinct device arrays of
- * the mesh's state length) and dt > 0; returns the slot.  HDG_ENOMEM when
- * every slot is taken, HDG_EINVAL if the mesh is already a member. */
+ * the mesh's state length) and dt > 0; returns the slot.  A mesh of several
+ * orders joins the order-N launches with its order-N elements and adds its
+ * own mortar launches to each stage.  HDG_ENOMEM when every slot is taken,
+ * HDG_EINVAL if the mesh is already a member. */
 hdg_status hdg_batch_add(hdg_batch *batch, hdg_mesh *mesh, double *q_dev, double *dq_dev, double dt,
                          int32_t *slot);
 hdg_status hdg_batch_remove(hdg_batch *batch, int32_t slot);

@@ -81,11 +81,13 @@ hdg_status rebuild_plans(hdg_batch *b)
                 std::vector<int32_t> elems;
                 for (size_t s = 0; s < b->slots.size(); ++s) {
                     const hdg_mesh *m = b->slots[s].mesh;
-                    if (!m || m->N != N) continue;
+                    if (!m || (!m->mixed && m->N != N)) continue;
+                    // a member of several orders gives this plan its order-N elements
                     const std::vector<int> &Ne = m->Ne;
                     std::vector<int> cls(m->ne);
                     for (int64_t e = 0; e < m->ne; ++e)
-                        cls[e] = kind == hdg::kTileViscous ? (m->flag[e] ? 1 : -1) : m->flag[e];
+                        cls[e] = Ne[e] != N ? -1
+                                 : kind == hdg::kTileViscous ? (m->flag[e] ? 1 : -1) : m->flag[e];
                     hdg::cut_tiles(m->order, Ne, cls, (int)s, B, kind, tiles, elems);
                 }
                 if (tiles.empty()) continue;
@@ -109,7 +111,32 @@ hdg_status rebuild_plans(hdg_batch *b)
 // residual kernels.  Stage input is each member's qB if parity, else qA.
 hdg_status batch_stage(hdg_batch *b, bool f32, double A, double B, bool first, int parity, hipStream_t s)
 {
-    for (int kind = 0; kind < 2; ++kind)
+    for (int kind = 0; kind < 2; ++kind) {
+        // members of several orders: their mortar kernels (BR1 lift before the
+        // viscous kernels, numerical fluxes before the residual kernels), one
+        // launch per member and pair of orders, reading the stage's input state
+        for (size_t slot = 0; slot < b->slots.size(); ++slot) {
+            const hdg_mesh *m = b->slots[slot].mesh;
+            if (!m || m->mort_h.empty()) continue;
+            for (int Nh = 3; Nh <= hdg::kMaxN; ++Nh)
+                for (int Nl = 2; Nl < Nh; ++Nl) {
+                    const int key = hdg::pair_key(Nl, Nh);
+                    StageArgs a{};
+                    a.mem = b->members + slot;
+                    a.I64 = b->ctx->I64;
+                    a.I32 = b->ctx->I32;
+                    a.W64 = b->ctx->W64;
+                    a.W32 = b->ctx->W32;
+                    a.parity = parity;
+                    a.mlist = m->mlist + m->mlist_off[kind][key];
+                    a.mcount = (int32_t)(m->mlist_off[kind][key + 1] - m->mlist_off[kind][key]);
+                    if (a.mcount == 0) continue;
+                    (void)hipGetLastError();
+                    const hipError_t e = hdg::launch_mortar(kind == 0, Nl, Nh, f32, a, s);
+                    if (e != hipSuccess)
+                        return fail(HDG_EHIP, std::string("batch mortar launch: ") + hipGetErrorString(e));
+                }
+        }
         for (int N = 2; N <= hdg::kMaxN; ++N) {
             const LaunchCfg &cf = b->cfg[kind][f32][N];
             const TilePlan *pl = find_plan(b, kind, N, cf.B);
@@ -132,6 +159,7 @@ hdg_status batch_stage(hdg_batch *b, bool f32, double A, double B, bool first, i
                                                      : hdg::launch_residual(N, pl->B, Epi::RkStage, f32, cf.persistent, a, grid, s);
             if (e != hipSuccess) return fail(HDG_EHIP, std::string("batch kernel launch: ") + hipGetErrorString(e));
         }
+    }
     return HDG_OK;
 }
 
@@ -206,7 +234,6 @@ hdg_status hdg_batch_add(hdg_batch *b, hdg_mesh *m, double *q, double *dq, doubl
     if (st != HDG_OK) return st;
     if (!m || !q || !dq || q == dq) return fail(HDG_EINVAL, "batch_add: need a mesh and distinct q, dq");
     if (m->ctx->device != b->ctx->device) return fail(HDG_EINVAL, "batch_add: mesh is on another device");
-    if (m->mixed) return fail(HDG_EUNSUPPORTED, "batch_add: members must have one polynomial order each");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HDG_EINVAL, "batch_add: need dt > 0");
     // a free slot no launch refers to any more; a slot freed since the last
     // plan rebuild may still be read by launches in flight

@@ -1014,7 +1014,8 @@ __device__ __forceinline__ MortarLane<NL, NH> mortar_lane(const StageArgs &A, co
     if (L.valid) {
         L.mr = load_mortar(A.mlist, mi);
         orient_map<NH>(L.mr.code_h & 7, L.i, L.j, L.il, L.jl);
-        const gmem<const double> *q = gp((const double *)(A.q_in ? A.q_in : M.qA));
+        // the stage's input state: given, or the member's ping-pong buffer
+        const gmem<const double> *q = gp((const double *)(A.q_in ? A.q_in : (A.parity ? M.qB : M.qA)));
         L.qh = q + 4 * L.mr.oh;
         L.ql = q + 4 * L.mr.ol;
     }

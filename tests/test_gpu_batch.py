@@ -84,6 +84,52 @@ def test_batch_members_equal_alone(torch_cuda, ctx, prec, graphs):
         assert np.array_equal(q.cpu().numpy(), alone[i]), f"member {i} differs from its solve alone"
 
 
+def _mixed_member(ctx, seed):
+    """A warped periodic box whose elements carry orders 2..6 (faces between
+    orders through mortars), with a TGV state per element."""
+    mesh = W.periodic_box(3, Pg=1, curve_amp=0.25)
+    flag = W.bernoulli_mask(mesh.n_elem, 0.5, seed)
+    Pe = W.mixed_orders(flag, seed)
+    m = hdg.hdg_mesh_create(ctx, mesh, Pe, flag, hdg.make_params(c0sq=25.0, nu=5e-3, les_model=1, C_les=0.1))
+    x = hdg.hdg_mesh_node_coords(m)
+    n3 = (Pe.astype(np.int64) + 1) ** 3
+    off = np.concatenate([[0], np.cumsum(n3)])
+    q0 = np.empty(4 * off[-1])
+    for e in range(len(Pe)):
+        X = x[3 * off[e]:3 * off[e + 1]].reshape(3, n3[e])
+        q0[4 * off[e]:4 * off[e + 1]] = W.taylor_green_state(X[None], 0.05, seed + e)[0].ravel()
+    return m, q0, 2e-3, np.bincount(Pe)[2:]
+
+
+@pytest.mark.parametrize("prec", [hdg.HDG_F64, hdg.HDG_F32])
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batch_with_mixed_order_member(torch_cuda, ctx, prec, graphs):
+    """A member of several orders (its own mortar launches in every stage)
+    among one-order members: every member equals its solve alone, bitwise."""
+    torch = torch_cuda
+    reqs = _requests(3, seed=51 + prec)
+    made = [_make(ctx, r) for r in reqs]
+    mm, mq0, mdt, counts = _mixed_member(ctx, 4)
+    made.insert(1, (mm, mq0, mdt))
+    _say(f"batch with a mixed-order member (orders 2..6: {counts}) and boxes "
+         f"{[(r['n'], r['P']) for r in reqs]}, prec {prec}, graphs {graphs}")
+    alone = [_alone(torch, m, q0, dt, 5, prec) for (m, q0, dt) in made]
+    b = hdg.hdg_batch_create(ctx, 6)
+    hdg.hdg_batch_set_graphs(b, graphs)
+    qs = []
+    for (m, q0, dt) in made:
+        q = torch.from_numpy(q0).cuda()
+        hdg.hdg_batch_add(b, m, q, torch.empty_like(q), dt)
+        qs.append(q)
+    hdg.hdg_batch_rk3_steps(b, 5, prec=prec)
+    torch.cuda.synchronize()
+    for i, q in enumerate(qs):
+        out = q.cpu().numpy()
+        assert np.isfinite(out).all()
+        assert np.array_equal(out, alone[i]), f"member {i} differs from its solve alone"
+    assert np.abs(alone[1] - mq0).max() > 1e-6                 # the mixed member did move
+
+
 def test_batch_join_and_leave(torch_cuda, ctx):
     """Members join and leave between calls (continuous batching); each one's
     state equals its own solve advanced by the steps it was in the batch."""
