@@ -20,7 +20,7 @@ HDG_F64, HDG_F32 = 0, 1
 HDG_WALL, HDG_FARFIELD = -1, -2
 HDG_LES_NONE, HDG_LES_SMAGORINSKY, HDG_LES_VREMAN = 0, 1, 2
 HDG_ROE, HDG_RUSANOV = 0, 1
-HDG_KERNEL_VISCOUS, HDG_KERNEL_RESIDUAL, HDG_KERNEL_MORTAR = 0, 1, 2
+HDG_KERNEL_VISCOUS, HDG_KERNEL_RESIDUAL, HDG_KERNEL_MORTAR, HDG_KERNEL_COUNT = 0, 1, 2, 3
 KERNEL_NAMES = {0: "viscous", 1: "residual", 2: "mortar"}
 
 EXPORTED = [

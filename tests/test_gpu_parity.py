@@ -269,6 +269,10 @@ def test_error_paths(torch_cuda, ctx):
     r = torch.full_like(q, float("nan"))
     out = hdg.hdg_reduce(m, r, allow_nonfinite=True)
     assert not out["finite"]
+    with pytest.raises(hdg.HdgError) as ex:                        # no such kernel class
+        hdg.hdg_timing_samples(m, hdg.HDG_KERNEL_COUNT)
+    assert ex.value.status == hdg.HDG_EINVAL
+    assert hdg.hdg_timing_samples(m, hdg.HDG_KERNEL_RESIDUAL) == []  # timing never enabled
 
 
 def test_timing_and_copy_probe(torch_cuda, ctx):
