@@ -121,14 +121,15 @@ def test_residual_parity_rusanov(orc, torch_cuda, ctx, P):
     assert_parity(out, ref, mass, what=f"Rusanov RK P={P}")
 
 
-@pytest.mark.parametrize("mixed_face", [0, 1])
-def test_residual_parity_ogrid_small(orc, torch_cuda, ctx, mixed_face):
+@pytest.mark.parametrize("mixed_face,riemann", [(0, 0), (1, 0), (0, 1)])
+def test_residual_parity_ogrid_small(orc, torch_cuda, ctx, mixed_face, riemann):
+    """Walls and far field (ghost states), both mixed-face readings, both fluxes."""
     mesh = W.naca_ogrid(48, 16, 4, Pg=2)
     flag = W.naca_mask(mesh)
     P = 4
-    _say(f"O-grid 48x16x4 P=4 mixed_face={mixed_face}")
+    _say(f"O-grid 48x16x4 P=4 mixed_face={mixed_face} riemann={riemann}")
     q = W.uniform_inflow_state(mesh.n_elem, 125, 20.0, 1.0, 0.01, seed=3)
-    prm = _params(nu=1e-4, q_inf=W.free_stream(20.0), mixed_face=mixed_face)
+    prm = _params(nu=1e-4, q_inf=W.free_stream(20.0), mixed_face=mixed_face, riemann=riemann)
     out, ref, mass, _ = _run_pair(orc, torch_cuda, ctx, mesh, P, flag, prm, q)
     assert_parity(out, ref, mass, what="ogrid small")
 
