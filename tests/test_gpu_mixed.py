@@ -149,6 +149,34 @@ def test_mixed_order_rk_parity(orc, torch_cuda, ctx):
     assert err < 1e-13
 
 
+def test_mixed_order_concurrent_phases_on_a_stream(orc, torch_cuda, ctx):
+    """The independent launches of each stage phase run on side streams forked
+    from the caller's stream: on a non-default stream, eagerly and from the
+    captured graph, results equal the default stream's bitwise."""
+    torch = torch_cuda
+    name, mesh, flag, P, kw = list(_cases())[0]
+    om = orc.OracleMesh(mesh, P, flag)
+    q = _state(om, 7)
+    _say(f"concurrent phases on a side stream: {name}")
+    m = hdg.hdg_mesh_create(ctx, mesh, P, flag, hdg.make_params(**_prm(kw)))
+    qd = torch.from_numpy(q).cuda()
+    r0 = torch.empty_like(qd)
+    hdg.hdg_residual(m, qd, r0)
+    q0 = qd.clone()
+    hdg.hdg_rk3_steps(m, q0, torch.empty_like(qd), 2e-3, 3)
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        r1 = torch.empty_like(qd)
+        q1 = qd.clone()
+        d1 = torch.empty_like(qd)
+    hdg.hdg_residual(m, qd, r1, stream=st)
+    hdg.hdg_rk3_steps(m, q1, d1, 2e-3, 3, stream=st)       # one graph replay and one eager step
+    st.synchronize()
+    assert torch.equal(r0, r1)
+    assert torch.equal(q0, q1)
+
+
 def test_mixed_order_conservation_freestream_and_shapes(orc, torch_cuda, ctx):
     torch = torch_cuda
     name, mesh, flag, P, kw = list(_cases())[1]
