@@ -88,6 +88,11 @@ def test_host_geometry_rejects_bad_meshes():
     with pytest.raises(hdg.HdgError) as ex:
         hdg.hdg_mesh_geometry(m, 8)
     assert ex.value.status == hdg.HDG_EUNSUPPORTED
+    empty = W.HexMesh(Pg=1, xyz_geom=m.xyz_geom[:0], corners=m.corners[:0], nbr=m.nbr[:0],
+                      nbr_face=m.nbr_face[:0], orient=m.orient[:0], centroid=m.centroid[:0])
+    with pytest.raises(hdg.HdgError) as ex:                      # no elements
+        hdg.hdg_mesh_geometry(empty, 3)
+    assert ex.value.status == hdg.HDG_EINVAL
 
 
 @pytest.mark.parametrize("make", [

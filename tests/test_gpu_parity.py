@@ -134,6 +134,29 @@ def test_residual_parity_ogrid_small(orc, torch_cuda, ctx, mixed_face, riemann):
     assert_parity(out, ref, mass, what="ogrid small")
 
 
+@pytest.mark.parametrize("flagged", [0, 1])
+def test_single_element_all_boundary(orc, torch_cuda, ctx, flagged):
+    """One element whose six faces are far-field boundaries (no interior face,
+    one tile of one element): residual and RK against the oracle; zero RK
+    steps leave the state as it was."""
+    torch = torch_cuda
+    mesh = W.box((1, 1, 1), periodic=(False, False, False))
+    flag = np.array([flagged], np.uint8)
+    P = 3
+    _say(f"single element, far field on all faces, flagged={flagged}")
+    om = orc.OracleMesh(mesh, P, flag)
+    q = W.taylor_green_state(om.node_coords(), 0.05, seed=2)
+    prm = _params(nu=5e-3, q_inf=(0.0, 0.5, 0.0, 0.0))
+    out, ref, mass, m = _run_pair(orc, torch_cuda, ctx, mesh, P, flag, prm, q)
+    assert_parity(out, ref, mass, what="single element")
+    out, ref, mass, _ = _run_pair(orc, torch_cuda, ctx, mesh, P, flag, prm, q, rk=(1e-3, 3))
+    assert_parity(out, ref, mass, what="single element rk3")
+    qd = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    hdg.hdg_rk3_steps(m, qd, torch.empty_like(qd), 1e-3, 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(qd.cpu().numpy(), q)
+
+
 def test_residual_parity_naca_working_size(orc, torch_cuda, ctx):
     """The benchmark workload at full size (96x48x8, P=4, 4.6M nodes), all outputs."""
     w = W.naca_working()
