@@ -43,7 +43,12 @@
  *   e.g. from torch tensors).  The library owns geometry, metric terms,
  *   connectivity, element lists and its scratch (face viscous-flux traces, the
  *   RK ping-pong state, reduction partials) from hdg_mesh_create to
- *   hdg_mesh_destroy.  No call after hdg_mesh_create allocates device memory.
+ *   hdg_mesh_destroy.  hdg_residual, hdg_rk3_steps and hdg_reduce allocate no
+ *   device memory.  These calls do: hdg_mesh_set_flags (new tile lists),
+ *   hdg_mesh_autotune (a trial buffer, freed before it returns), the first
+ *   hdg_cluster_features / hdg_cluster_fit on a mesh (feature tile lists, EM
+ *   partials; kept until hdg_mesh_destroy) and the first RK call after graphs
+ *   are enabled (graph instantiation).
  *
  * Errors
  *   Every call returns an hdg_status and never throws across the ABI;
