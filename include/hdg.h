@@ -56,7 +56,10 @@
  *   hdg_mesh_create validates the mesh (symmetric connectivity, mutually
  *   inverse orientation codes, positive Jacobian).  Kernel launch failures
  *   map to HDG_EHIP.  Calls taking a stream are asynchronous on it, except
- *   hdg_reduce and hdg_timing_read, which synchronise it.
+ *   hdg_reduce, hdg_mesh_autotune, hdg_batch_autotune and hdg_cluster_fit,
+ *   which synchronise it.  hdg_mesh_set_flags and hdg_mesh_set_params wait
+ *   for the device; hdg_timing_read and hdg_timing_samples wait for the
+ *   launches they report.
  */
 #ifndef HDG_H
 #define HDG_H
