@@ -38,3 +38,13 @@ def test_residual_only_and_viscous_bytes():
     # viscous kernel, flagged elements: velocity 24 + metric 80 in, viscous part
     # 24 and six faces of traces out
     assert bench.algorithmic_bytes(0, NE, NV, N, fused_rk=True) == NV * ((24 + 80 + 24) * N3 + 6 * N2 * 24)
+
+
+def test_more_than_one_gpu_is_refused(capsys, monkeypatch):
+    # one GPU only: asking for more, or running under a launcher with
+    # WORLD_SIZE > 1, exits with status 2 and a message, before any GPU work
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "exactly one GPU" in capsys.readouterr().err
+    monkeypatch.setenv("WORLD_SIZE", "4")
+    assert bench.main([]) == 2
+    assert "WORLD_SIZE 4" in capsys.readouterr().err
