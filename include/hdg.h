@@ -134,7 +134,10 @@ typedef struct {
                             |u_n| + sqrt(u_n^2 + c0^2) of the two traces times the jump) */
 } hdg_params;
 
-/* Bind a context to HIP device `device`. */
+/* Bind a context to HIP device `device`.  hdg_finalize releases the
+ * caller's hold on it; the context (its operator tables on the device) lives
+ * on until the last mesh and batch made from it are destroyed as well, so the
+ * handles may be released in any order.  Each handle is released once. */
 hdg_status hdg_init(hdg_ctx **ctx, int32_t device);
 void hdg_finalize(hdg_ctx *ctx);
 

@@ -463,13 +463,7 @@ hdg_status hdg_init(hdg_ctx **ctx, int32_t device)
 
 void hdg_finalize(hdg_ctx *ctx)
 {
-    if (!ctx) return;
-    (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    void *ps[] = {ctx->D64, ctx->D32, ctx->I64, ctx->I32, ctx->W64, ctx->W32};
-    for (void *p : ps)
-        if (p) (void)hipFree(p);
-    delete ctx;
+    if (ctx) hdg::ctx_release(ctx);
 }
 
 hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_params *params, hdg_mesh **out)
@@ -713,6 +707,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         delete m;
         return s2;
     }
+    hdg::ctx_retain(ctx);
     *out = m;
     return HDG_OK;
 }
@@ -724,7 +719,9 @@ void hdg_mesh_destroy(hdg_mesh *m)
     (void)hipSetDevice(m->ctx->device);
     (void)hipDeviceSynchronize();
     free_device(m);
+    hdg_ctx *ctx = m->ctx;
     delete m;
+    hdg::ctx_release(ctx);
 }
 
 hdg_status hdg_mesh_set_flags(hdg_mesh *m, const uint8_t *flag_host)

@@ -212,6 +212,7 @@ hdg_status hdg_batch_create(hdg_ctx *ctx, int32_t max_members, hdg_batch **out)
         delete b;
         return fail(HDG_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
     }
+    hdg::ctx_retain(ctx);
     *out = b;
     return HDG_OK;
 }
@@ -225,7 +226,9 @@ void hdg_batch_destroy(hdg_batch *b)
     free_plans(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     (void)hipFree(b->members);
+    hdg_ctx *ctx = b->ctx;
     delete b;
+    hdg::ctx_release(ctx);
 }
 
 hdg_status hdg_batch_add(hdg_batch *b, hdg_mesh *m, double *q, double *dq, double dt, int32_t *slot)

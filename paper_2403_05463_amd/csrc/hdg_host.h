@@ -3,13 +3,19 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "hdg_internal.h"
 
+// The context's tables are shared by every mesh and batch made from it: it
+// is reference counted (hdg_init and each successful create take a count,
+// hdg_finalize and each destroy return one), so that the handles may be
+// released in any order.
 struct hdg_ctx {
+    std::atomic<int> refs{1};
     int device = 0;
     int n_cu = 0;
     double *D64 = nullptr;     // derivative matrices for N = 2..8, packed at d_offset(N)
@@ -21,6 +27,20 @@ struct hdg_ctx {
 };
 
 namespace hdg {
+
+inline void ctx_retain(hdg_ctx *c) { c->refs.fetch_add(1, std::memory_order_relaxed); }
+
+// Returns one count; the last one frees the tables and the context.
+inline void ctx_release(hdg_ctx *c)
+{
+    if (c->refs.fetch_sub(1, std::memory_order_acq_rel) != 1) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    void *ps[] = {c->D64, c->D32, c->I64, c->I32, c->W64, c->W32};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    delete c;
+}
 
 // Tile list of one kernel kind, one order N and one workgroup size, on the device.
 struct TilePlan {

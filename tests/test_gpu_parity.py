@@ -2,6 +2,7 @@
 
 Every case prints its name, shape and seed before touching the GPU.
 """
+import math
 import sys
 
 import numpy as np
@@ -322,3 +323,32 @@ def test_timing_and_copy_probe(torch_cuda, ctx):
     hdg.hdg_stream_copy(ctx, b, a, a.numel() * 8)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_handles_released_in_any_order(orc, torch_cuda):
+    """The context is released first (as a garbage collector may do with a
+    cycle): the mesh made from it still computes the same residual, and its
+    and a batch's destruction afterwards leave no HIP error behind for the
+    next torch launch."""
+    torch = torch_cuda
+    mesh, _ = W.reorient(W.periodic_box(3, Pg=2, curve_amp=0.2), seed=3)
+    flag = W.bernoulli_mask(mesh.n_elem, 0.5, 3)
+    _say("handles released in any order: box 3^3 P=3")
+    c2 = hdg.hdg_init(0)
+    m = hdg.hdg_mesh_create(c2, mesh, 3, flag, hdg.make_params(**_params()))
+    b = hdg.hdg_batch_create(c2, 2)
+    q = W.taylor_green_state(orc.OracleMesh(mesh, 3, flag).node_coords(), 0.05, seed=3)
+    qd = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    r0 = torch.empty_like(qd)
+    hdg.hdg_residual(m, qd, r0)
+    torch.cuda.synchronize()
+    hdg.lib().hdg_finalize(c2.handle)
+    c2.handle = None
+    r1 = torch.empty_like(qd)
+    hdg.hdg_residual(m, qd, r1)
+    torch.cuda.synchronize()
+    assert torch.equal(r0, r1)
+    del b, m
+    x = torch.cos(torch.ones(1000, dtype=torch.float64, device="cuda")).sum()
+    torch.cuda.synchronize()
+    assert abs(x.item() - 1000 * math.cos(1.0)) < 1e-9
