@@ -610,3 +610,118 @@ def test_channel_profile_exact_with_boundaries(orc, bc, P):
     expect = np.zeros_like(R)
     expect[:, 3] = -2 * nu
     np.testing.assert_allclose(R, expect, atol=1e-11)
+
+
+@pytest.mark.parametrize("mixed_face", [0, 1])
+def test_reading_a_viscous_terms_superpose_over_elements(orc, mixed_face):
+    """Reading A (Sec. 2.3 mixed faces, Sec. 4 single-valued flux) makes the
+    hybrid residual the Navier-Stokes residual with a per-element viscosity
+    mu_e = flag_e nu (LES off): the viscous part is linear in the vector of
+    mu_e, so for any mask M
+        R(M, nu) - R(M, 0) = sum_{e in M} [R({e}, nu) - R({e}, 0)]
+    to round-off.  Reading B (no viscous flux on a face with one Euler side)
+    breaks it on every face between two flagged elements, and so would a
+    one-sided face taking the whole viscous trace instead of half the mean."""
+    P = 3
+    m = W.periodic_box(4, Pg=2, curve_amp=0.3)
+    M = W.bernoulli_mask(m.n_elem, 0.5, 9)
+    rng = np.random.default_rng(14)
+    q = rng.uniform(-1, 1, size=(m.n_elem, 4, (P + 1) ** 3))
+
+    def visc_part(flag):
+        om = orc.OracleMesh(m, P, flag)
+        kw = dict(les_model=0, C_les=0.0, mixed_face=mixed_face)
+        return om.residual(_params(orc, nu=0.02, **kw), q) - om.residual(_params(orc, nu=0.0, **kw), q)
+
+    whole = visc_part(M)
+    summed = np.zeros_like(whole)
+    for e in np.flatnonzero(M):
+        one = np.zeros(m.n_elem, np.uint8)
+        one[e] = 1
+        summed += visc_part(one)
+    scale = np.abs(whole).max()
+    assert scale > 1e-3
+    dev = np.abs(whole - summed).max() / scale
+    if mixed_face == 0:
+        assert dev < 1e-12, dev
+    else:
+        assert dev > 1e-3, dev
+
+
+@pytest.mark.parametrize("P", [3, 4])
+@pytest.mark.parametrize("les", [1, 2])
+def test_eddy_viscosity_exact_on_quadratic_shear(orc, P, les):
+    """u = (f(y), 0, 0), f = a (y - y0)^2 with f' > 0 on the box, p constant,
+    every element viscous.  Then div u = 0, the convective terms vanish, and
+    grad u has the single entry du/dy = f'.
+      Smagorinsky (App. A closure with C_s): 2 S:S = f'^2, nu_t = (C_s Delta)^2 f',
+        tau_xy = (nu + nu_t) f', so R_u = d tau_xy/dy = nu f'' + 2 (C_s Delta)^2 f' f''.
+      Vreman (App. A): beta has the single entry Delta^2 f'^2, B_beta = 0, nu_t = 0,
+        so R_u = nu f''.
+    tau_xy is a polynomial of degree 2 in y, so interior elements reproduce it
+    exactly.  Delta = V_e^(1/3) / (P + 1) with V_e the (equal) parallelepiped
+    volume.  Pins the stress 2 (nu + nu_t) S with nu_t from the element's own
+    filter width (a stress (2 nu + nu_t) S, or nu_t missing, fails)."""
+    lo, hi = (-1.2, -0.9, -1.0), (1.3, 1.0, 0.8)
+    m, ec = _interior_box(P)
+    om = orc.OracleMesh(m, P, np.ones(m.n_elem, np.uint8))
+    X = om.node_coords()
+    a, y0 = 0.7, -3.0
+    q = np.zeros((m.n_elem, 4, (P + 1) ** 3))
+    q[:, 0] = 0.3
+    q[:, 1] = a * (X[:, 1] - y0) ** 2
+    nu, C = 0.01, (0.4 if les == 1 else 0.07)
+    R = om.residual(_params(orc, nu=nu, les_model=les, C_les=C, q_inf=(0.3, 0.0, 0.0, 0.0)), q)
+    V = np.prod([(hi[d] - lo[d]) / 3 for d in range(3)])
+    delta = V ** (1.0 / 3.0) / (P + 1)
+    assert abs(om.filter_width(ec) - delta) < 1e-14
+    fp, fpp = 2 * a * (X[ec, 1] - y0), 2 * a
+    expect_u = nu * fpp + (2 * (C * delta) ** 2 * fp * fpp if les == 1 else 0.0)
+    np.testing.assert_allclose(R[ec, 1], expect_u, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(R[ec, [0, 2, 3]], 0.0, rtol=0, atol=1e-11 * C0SQ)
+    if les == 1:
+        # the eddy viscosity is a visible part of the result
+        assert np.abs(expect_u - nu * fpp).max() > 1e-3
+
+
+def test_eddy_viscosity_uses_the_elements_own_filter_width(orc):
+    """On a graded box (affine elements of different volumes) and a linear
+    velocity field u = G x, the Smagorinsky viscosity of a lone flagged element
+    e is the constant nu_e = (C_s Delta_e)^2 sqrt(2 S:S), Delta_e =
+    V_e^(1/3) / (P + 1) (App. A closure; filter width from the element's
+    volume).  Its viscous terms must then equal those of a plain viscosity
+    nu_e with LES off, element by element: both give the stress 2 nu_e S.
+    The flagged elements have only interior faces, so their lifted gradient
+    is G exactly (the far-field ghost state would bend it on boundary faces)."""
+    P = 3
+    m = W.box((5, 4, 4), lo=(0.0, 0.0, 0.0), hi=(2.0, 1.5, 1.0), Pg=1)
+    # grade x and y: x -> x + 0.4 x^2, y -> y + 0.3 y^2 (the elements stay boxes)
+    xyz = m.xyz_geom.copy()
+    xyz[:, 0] = xyz[:, 0] + 0.4 * xyz[:, 0] ** 2
+    xyz[:, 1] = xyz[:, 1] + 0.3 * xyz[:, 1] ** 2
+    m = W.HexMesh(Pg=1, xyz_geom=xyz, corners=m.corners, nbr=m.nbr, nbr_face=m.nbr_face,
+                  orient=m.orient, centroid=xyz.mean(axis=2))
+    vols = np.array([np.prod(np.ptp(xyz[e], axis=1)) for e in range(m.n_elem)])
+    assert vols.max() / vols.min() > 3
+    G = np.array([[0.3, -0.8, 0.2], [0.5, -0.1, 0.4], [-0.6, 0.7, -0.2]])
+    S = 0.5 * (G + G.T)
+    rate = math.sqrt(2 * (S * S).sum())
+    C = 0.3
+    interior = [i + 5 * (j + 4 * k) for (i, j, k) in ((1, 1, 1), (3, 2, 2), (2, 1, 2))]
+    assert np.ptp(vols[interior]) > 0.2 * vols[interior].max()
+    for e in interior:
+        assert np.all(m.nbr[e] >= 0)
+        flag = np.zeros(m.n_elem, np.uint8)
+        flag[e] = 1
+        om = orc.OracleMesh(m, P, flag)
+        X = om.node_coords()
+        q = np.zeros((m.n_elem, 4, (P + 1) ** 3))
+        q[:, 0] = 0.1
+        q[:, 1:] = np.einsum("rd,edn->ern", G, X)
+        base = om.residual(_params(orc, nu=0.0, les_model=0, C_les=0.0), q)
+        les = om.residual(_params(orc, nu=0.0, les_model=1, C_les=C), q) - base
+        delta = vols[e] ** (1.0 / 3.0) / (P + 1)
+        nu_e = (C * delta) ** 2 * rate
+        plain = om.residual(_params(orc, nu=nu_e, les_model=0, C_les=0.0), q) - base
+        assert np.abs(plain).max() > 1e-6
+        np.testing.assert_allclose(les, plain, rtol=0, atol=1e-12 * np.abs(plain).max() + 1e-15)
