@@ -29,31 +29,43 @@ METRIC = "DOF-residual evals/s (mixed NS-LES/Euler DG), plain vs batched FP32; p
 HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE summary of the benchmark's kernels (rocprofv3 --pmc)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_naca0012_ogrid_96x48x8_P4.txt")
+# VALU instruction counts of the same kernels (rocprofv3 --pmc SQ_INSTS_VALU_*)
+FLOPS_SUMMARY = os.path.join(ROOT, "profiles", "flops_naca0012_ogrid_96x48x8_P4.txt")
 
 
-def algorithmic_bytes(kind: int, n_elem: int, n_visc: int, N: int, fused_rk: bool, f32: bool = False,
-                      first_stage: bool = False) -> float:
-    """Bytes a launch must move at least once (perfect caching).
-
-    Residual kernel, every element: state 32 B/node (FP64 in both precision
-    forms), metric terms (1/J + 9 Ja) 80 B/node in FP64, 40 in FP32; fused
-    RK stage: + dq write 32 and read 32 (not read in the first stage, whose
-    coefficient A is zero) + next state 32 (residual only: + R 32 in FP64,
-    16 in FP32); face geometry (n, s) 32 B (16) per face node, three faces
-    owned per element.  Flagged elements add the viscous divergence part
-    (24 B/node, 12 in FP32) and both sides' viscous face traces (24 B, 12 in
-    FP32, per face node and side).
-    Viscous kernel, flagged elements: velocity 24 + metric terms per node,
-    out the viscous part per node and six faces of traces.
-    """
+def algorithmic_bytes(n_elem: int, N: int, fused_rk: bool, f32: bool = False, first_stage: bool = False) -> float:
+    """Algorithmic bytes of one hybrid residual evaluation over the whole mesh
+    (the operator's inputs and outputs, each moved once): state q 32 B/node
+    (FP64 in both precision forms), metric terms 1/J + 9 Ja 80 B/node (40 in
+    FP32), the owned face geometry (unit normal and surface scale, 32 B per
+    face node, 16 in FP32, three faces per element), and the output: R 32
+    B/node (16 in FP32), or for a fused RK stage the register dq read 32 (not
+    in the first stage, whose coefficient A is zero) and written 32 plus the
+    next state 32.  The viscous kernel's intermediates (viscous part and face
+    traces, written and read back) are a property of this implementation and
+    are not counted; ``intermediate_bytes`` gives them."""
     N3, N2 = N ** 3, N ** 2
-    met, tv, fg = (40, 12, 16) if f32 else (80, 24, 32)
-    if kind == 0:
-        return float(n_visc * ((24 + met + tv) * N3 + 6 * N2 * tv))
-    per_node = 32 + met + ((64 if first_stage else 96) if fused_rk else (16 if f32 else 32))
-    b = n_elem * (per_node * N3 + 3 * N2 * fg)
-    b += n_visc * (tv * N3 + 6 * N2 * tv)
-    return float(b)
+    met, fg = (40, 16) if f32 else (80, 32)
+    out = ((64 if first_stage else 96) if fused_rk else (16 if f32 else 32))
+    return float(n_elem * ((32 + met + out) * N3 + 3 * N2 * fg))
+
+
+def intermediate_bytes(n_visc: int, N: int, f32: bool = False) -> float:
+    """Bytes of the viscous kernel's outputs that the residual kernel reads back,
+    per stage (flagged elements): the viscous part of the divergence 24 B/node
+    (12 in FP32) and both sides' viscous face traces, 24 B (12) per face node
+    and side on six faces.  Written once and read once."""
+    N3, N2 = N ** 3, N ** 2
+    tv = 12 if f32 else 24
+    return float(n_visc * (tv * N3 + 6 * N2 * tv))
+
+
+def viscous_kernel_bytes(n_visc: int, N: int, f32: bool = False) -> float:
+    """Bytes the viscous kernel moves at least: velocity 24 B/node and metric
+    terms in, the viscous part per node and six faces of traces out."""
+    N3, N2 = N ** 3, N ** 2
+    met, tv = (40, 12) if f32 else (80, 24)
+    return float(n_visc * ((24 + met + tv) * N3 + 6 * N2 * tv))
 
 
 def kernel_symbol(kind: int, N: int, f32: bool, block: int, persistent: bool, fused_rk: bool = True) -> str:
@@ -61,6 +73,31 @@ def kernel_symbol(kind: int, N: int, f32: bool, block: int, persistent: bool, fu
     p = "true" if persistent else "false"
     return f"k_viscous<{t}, {N}, {block}, {p}>" if kind == 0 else \
         f"k_residual<{t}, {1 if fused_rk else 0}, {N}, {block}, {p}>"
+
+
+def fp32_residual_error(mesh, q, torch, hdg) -> dict:
+    """Per-field relative error of the FP32 residual at state q against this
+    library's FP64 residual (itself within 1e-12 of the FP64 oracle in the
+    parity tests), in the mass-weighted L2 norm and the max norm, each
+    floored at 1e-3 of the largest field's norm (the parity norm).  The
+    pressure row of a nearly divergence-free field is a small difference of
+    terms of size c0^2 |grad u|, which an FP32 evaluation cannot beat; its
+    error against its own (floored) norm is reported as is."""
+    r64 = torch.empty_like(q)
+    r32 = torch.empty(q.shape, dtype=torch.float32, device=q.device)
+    hdg.hdg_residual(mesh, q, r64)
+    hdg.hdg_residual(mesh, q, r32, prec=hdg.HDG_F32)
+    ref = hdg.hdg_reduce(mesh, r64)
+    d = r32.double() - r64
+    err = hdg.hdg_reduce(mesh, d)
+    out = {"reference": "FP64 path of this library", "norm": "per field, floored at 1e-3 of the largest"}
+    for key in ("l2", "max"):
+        den = np.maximum(ref[key], 1e-3 * ref[key].max())
+        out[key] = [float(x) for x in err[key] / den]
+        out[key + "_unfloored"] = [float(x) for x in err[key] / np.maximum(ref[key], 1e-300)]
+    out["fields"] = ["p", "u", "v", "w"]
+    del r64, r32, d
+    return out
 
 
 def cpu_baseline(w, q0, budget_s: float = 12.0) -> dict:
@@ -182,8 +219,7 @@ def secondary_leg(ctx, args, torch, hdg) -> dict:
     us = hdg.hdg_timing_samples(mesh, hdg.HDG_KERNEL_RESIDUAL)
     hdg.hdg_timing_enable(mesh, False)
     red = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
-    per_step = sum(algorithmic_bytes(1, w.mesh.n_elem, n_visc, N, fused_rk=True, first_stage=(st == 0))
-                   for st in range(3))
+    per_step = sum(algorithmic_bytes(w.mesh.n_elem, N, fused_rk=True, first_stage=(st == 0)) for st in range(3))
     avg_us = float(np.mean(us))
     achieved = per_step / 3 / (avg_us * 1e-6) / 1e9
     cfg = hdg.hdg_mesh_get_launch(mesh, hdg.HDG_KERNEL_RESIDUAL, hdg.HDG_F64, N)
@@ -191,6 +227,8 @@ def secondary_leg(ctx, args, torch, hdg) -> dict:
     return {"workload": w.name, "nodes": nodes, "viscous_elements": n_visc, "steps": steps,
             "value": nodes * 4 * 3 * steps / (ms / 1e3), "unit": "DOF-residual evals/s",
             "ms_per_step": ms / steps, "state_finite": bool(red["finite"]),
+            "stage_roofline": {"achieved": per_step / (ms / steps * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": per_step / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "roofline": {"kernel": kernel_symbol(1, N, False, cfg["block"], cfg["persistent"]), "bound": "hbm",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": avg_us,
@@ -332,7 +370,7 @@ def main(argv=None) -> int:
 
     import torch
     from paper_2403_05463_amd import hdg, workloads as W
-    from paper_2403_05463_amd.profiling import traffic_for
+    from paper_2403_05463_amd.profiling import flops_for, traffic_for
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -400,24 +438,41 @@ def main(argv=None) -> int:
     evals = 3 * args.steps
 
     def roofline(kern, f32, samples):
-        """Dominant kernel class: algorithmic bytes per launch over its mean event-timed duration."""
-        dom = max(kern, key=lambda k: kern[k][0])
+        """The residual kernel (the dominant class): the operator's algorithmic
+        bytes per launch over its mean event-timed duration."""
+        dom = "residual"
+        assert max(kern, key=lambda k: kern[k][0]) == dom, kern
         tot, n = kern[dom]
         avg_s = tot / max(n, 1) / 1e3
-        # every stage runs each kernel class once over its element set; the
+        # every stage runs the residual kernel once over every element; the
         # first of the three stages does not read the RK register
-        per_step = sum(algorithmic_bytes(kinds[dom], w.mesh.n_elem, n_visc, N, fused_rk=True, f32=f32,
-                                         first_stage=(st == 0)) for st in range(3))
+        per_step = sum(algorithmic_bytes(w.mesh.n_elem, N, fused_rk=True, f32=f32, first_stage=(st == 0))
+                       for st in range(3))
         bytes_launch = per_step * args.steps / max(n, 1)
         achieved = bytes_launch / avg_s / 1e9
+        inter = intermediate_bytes(n_visc, N, f32)
         cfg = tuned[f"{dom}_{'f32' if f32 else 'f64'}"]
         sym = kernel_symbol(kinds[dom], N, f32, cfg["block"], cfg["persistent"])
         sm = samples.get(dom) or [avg_s * 1e6]
         return {"kernel": sym, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(TRAFFIC_SUMMARY, sym),
                 "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_launch,
+                "with_viscous_intermediates": {"bytes_per_launch": bytes_launch + inter,
+                                               "achieved": (bytes_launch + inter) / avg_s / 1e9},
+                "flops": flops_for(FLOPS_SUMMARY, sym, avg_s),
                 "launches_timed": len(sm),
                 "launch_us_p10_p50_p90": [float(np.percentile(sm, p)) for p in (10, 50, 90)]}
+
+    def stage_roofline(ms_step, f32):
+        """The whole stage (viscous and residual kernels, and mortars if any):
+        the operator's algorithmic bytes of the three stages of a step over
+        the graph-replayed time per step."""
+        per_step = sum(algorithmic_bytes(w.mesh.n_elem, N, fused_rk=True, f32=f32, first_stage=(st == 0))
+                       for st in range(3))
+        achieved = per_step / (ms_step * 1e-3) / 1e9
+        return {"bound": "hbm", "bytes_per_step": per_step, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "target_ms_per_step_at_half_peak": per_step / (0.5 * HBM_PEAK_GBS * 1e9) * 1e3}
 
     roof = roofline(kern, False, samples)
     achieved = roof["achieved"]
@@ -438,6 +493,7 @@ def main(argv=None) -> int:
                    "nodes": nodes, "dof": nodes * 4, "viscous_elements": n_visc,
                    "residuals_per_step": 3, "dt": dt, "rk": "3-stage low-storage (2N)"},
         "roofline": roof,
+        "stage_roofline": stage_roofline(ms / args.steps, False),
         "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern.items()},
         "node_evals_per_s": nodes * evals / (ms / 1e3),
         "state_finite": bool(red["finite"]),
@@ -449,12 +505,16 @@ def main(argv=None) -> int:
     # precision form on the same workload and state: FP32 contractions and
     # fluxes, FP64 state and RK accumulation
     q.copy_(torch.from_numpy(q0))
+    fp32_err = fp32_residual_error(mesh, q, torch, hdg)
     ms32, kern32, samples32 = timed_run(hdg.HDG_F32)
     red32 = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
     out["fp32_plain"] = {"value": nodes * 4 * evals / (ms32 / 1e3), "ms_per_step": ms32 / args.steps,
                          "speedup_vs_fp64": ms / ms32, "state_finite": bool(red32["finite"]),
                          "kernels_us_per_launch": {k: (v[0] / max(v[1], 1) * 1e3) for k, v in kern32.items()},
-                         "roofline": roofline(kern32, True, samples32), "dtype": "f32 residual, f64 state"}
+                         "roofline": roofline(kern32, True, samples32),
+                         "stage_roofline": stage_roofline(ms32 / args.steps, True),
+                         "residual_error": fp32_err,
+                         "dtype": "f32 residual, f64 state"}
     del q, dq
     if not args.no_cluster:
         print("[bench] clustering", file=sys.stderr, flush=True)

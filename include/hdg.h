@@ -182,8 +182,9 @@ hdg_status hdg_residual(hdg_mesh *mesh, const void *q_dev, void *r_dev, hdg_prec
 /* nsteps steps of the three-stage low-storage RK (Sec. 2.3; Williamson 2N
  * coefficients A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15)) on the device
  * state q_dev in place.  dq_dev is the caller's second register (same length);
- * its content on entry is ignored, on return it holds the last stage's
- * register.  dt > 0 fixed.  prec selects the residual arithmetic (as in
+ * its content on entry is ignored and on return unspecified: a step's first
+ * stage does not read the register (A = 0), so its last stage does not store
+ * it.  dt > 0 fixed.  prec selects the residual arithmetic (as in
  * hdg_residual); the stage accumulation dq = A dq + dt R, q += B dq and both
  * registers are double in either case. */
 hdg_status hdg_rk3_steps(hdg_mesh *mesh, double *q_dev, double *dq_dev, double dt, int32_t nsteps,

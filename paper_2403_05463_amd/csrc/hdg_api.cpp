@@ -280,7 +280,7 @@ StageArgs stage_args(const hdg_mesh *m, const TilePlan &pl)
 
 // One launch of kernel `kind` over the order-N tiles with configuration cf.
 hdg_status launch_one(hdg_mesh *m, int kind, int N, const LaunchCfg &cf, const double *q, void *out, double *dq,
-                      Epi epi, bool f32, double A, double B, double dt, bool first, hipStream_t s, bool time_it)
+                      Epi epi, bool f32, double A, double B, double dt, int stage, hipStream_t s, bool time_it)
 {
     const TilePlan *pl = find_plan(m, kind, N, cf.B);
     if (!pl) return HDG_OK;
@@ -292,7 +292,8 @@ hdg_status launch_one(hdg_mesh *m, int kind, int N, const LaunchCfg &cf, const d
     a.dt = dt;
     a.rkA = A;
     a.rkB = B;
-    a.first_stage = first ? 1 : 0;
+    a.first_stage = stage == 0 ? 1 : 0;
+    a.store_dq = stage == 2 ? 0 : 1;
     const int grid = grid_for(m, *pl, kind, epi, f32, cf.persistent);
     auto go = [&] {
         return kind == hdg::kTileViscous ? hdg::launch_viscous(N, pl->B, f32, cf.persistent, a, grid, s)
@@ -310,7 +311,7 @@ hdg_status launch_one(hdg_mesh *m, int kind, int N, const LaunchCfg &cf, const d
 // orders, then the element kernels of every order; launches within each of
 // these four phases are independent.
 hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi epi, bool f32, double A,
-                     double B, double dt, bool first, hipStream_t s)
+                     double B, double dt, int stage, hipStream_t s)
 {
     const int pi = f32 ? 1 : 0;
     hdg::Phase ph(m->ss, s, !m->timing);
@@ -344,7 +345,7 @@ hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi ep
             if (!find_plan(m, kind, N, m->cfg[kind][pi][N].B)) continue;
             hipStream_t ls;
             HDG_TRY(ph.next(ls));
-            HDG_TRY(launch_one(m, kind, N, m->cfg[kind][pi][N], q, out, dq, epi, f32, A, B, dt, first, ls, true));
+            HDG_TRY(launch_one(m, kind, N, m->cfg[kind][pi][N], q, out, dq, epi, f32, A, B, dt, stage, ls, true));
         }
         HDG_TRY(ph.end());
     }
@@ -791,7 +792,7 @@ hdg_status hdg_residual(hdg_mesh *m, const void *q, void *r, hdg_prec prec, void
     if (q == r) return fail(HDG_EINVAL, "residual must not alias the state");
     if (prec != HDG_F64 && prec != HDG_F32) return fail(HDG_EINVAL, "prec must be HDG_F64 or HDG_F32");
     HDG_HIP(hipSetDevice(m->ctx->device));
-    return run_stage(m, (const double *)q, r, nullptr, Epi::Residual, prec == HDG_F32, 0.0, 0.0, 0.0, false,
+    return run_stage(m, (const double *)q, r, nullptr, Epi::Residual, prec == HDG_F32, 0.0, 0.0, 0.0, 1,
                      (hipStream_t)stream);
 }
 
@@ -809,7 +810,7 @@ hdg_status hdg_rk3_steps(hdg_mesh *m, double *q, double *dq, double dt, int32_t 
     const bool f32 = prec == HDG_F32;
     auto one_step = [&](double *&cur, double *&nxt, hipStream_t st_) -> hdg_status {
         for (int st = 0; st < 3; ++st) {
-            hdg_status r = run_stage(m, cur, nxt, dq, Epi::RkStage, f32, A[st], B[st], dt, st == 0, st_);
+            hdg_status r = run_stage(m, cur, nxt, dq, Epi::RkStage, f32, A[st], B[st], dt, st, st_);
             if (r != HDG_OK) return r;
             std::swap(cur, nxt);
         }
@@ -980,7 +981,7 @@ hdg_status hdg_mesh_autotune(hdg_mesh *m, const double *q, int32_t reps, void *s
                         cf.persistent = pers != 0;
                         auto once = [&] {
                             return launch_one(m, kind, N, cf, q, m->qpp, dq, Epi::RkStage, pi == 1, -0.5, 0.5, 1e-9,
-                                              false, s, false);
+                                              1, s, false);
                         };
                         st = once();
                         if (st != HDG_OK) break;

@@ -30,6 +30,17 @@ struct hdg_batch {
     LaunchCfg cfg[2][2][hdg::kMaxN + 1];
     bool dirty = true;                         // plans out of date with the slots
     int64_t version = 0;                       // bumped on every membership change
+    int64_t last_call_version = -1;            // membership of the previous stepping call
+    // Completion of this batch's launches.  Every call that launches waits
+    // for the previous call's event first when it runs on another stream, so
+    // the calls form one chain and `done`, recorded behind the last call,
+    // completes only after every launch the batch has made.  Tile lists, the
+    // member table and the captured graph are rewritten or freed only once
+    // the work that reads them is ordered before (same stream) or has
+    // completed (host wait on `done`).
+    hipEvent_t done = nullptr;
+    bool done_recorded = false;
+    hipStream_t last_stream = nullptr;
     // captured RK steps
     bool graphs = true;
     hipStream_t cap = nullptr;
@@ -42,8 +53,31 @@ namespace {
 
 hdg_status fail(hdg_status s, const std::string &msg) { return hdg::set_error(s, msg); }
 
+// Wait until every launch this batch has made has completed.
+void wait_idle(hdg_batch *b)
+{
+    if (b->done_recorded) (void)hipEventSynchronize(b->done);
+}
+
+// Order stream s after the batch's previous call (on whatever stream it ran).
+hdg_status join_chain(hdg_batch *b, hipStream_t s)
+{
+    if (!b->done) HDG_HIP(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+    if (b->done_recorded && b->last_stream != s) HDG_HIP(hipStreamWaitEvent(s, b->done, 0));
+    return HDG_OK;
+}
+
+hdg_status mark_done(hdg_batch *b, hipStream_t s)
+{
+    HDG_HIP(hipEventRecord(b->done, s));
+    b->done_recorded = true;
+    b->last_stream = s;
+    return HDG_OK;
+}
+
 void free_plans(hdg_batch *b)
 {
+    wait_idle(b);
     for (auto &v : b->plans) {
         for (auto &pl : v) {
             if (pl.tiles) (void)hipFree(pl.tiles);
@@ -55,7 +89,11 @@ void free_plans(hdg_batch *b)
 
 void drop_graph(hdg_batch *b)
 {
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    // the executable may still be running its last replay
+    if (b->gexec) {
+        wait_idle(b);
+        (void)hipGraphExecDestroy(b->gexec);
+    }
     b->gexec = nullptr;
     b->g_version = -1;
     b->g_prec = -1;
@@ -64,15 +102,37 @@ void drop_graph(hdg_batch *b)
 const TilePlan *find_plan(const hdg_batch *b, int kind, int N, int B)
 {
     for (const auto &pl : b->plans[kind])
-        if (pl.N == N && pl.B == B) return &pl;
+        if (pl.N == N && pl.B == B && pl.ntiles > 0) return &pl;
     return nullptr;
 }
 
-// Tile lists over every member, for every (kind, order, workgroup size).
-// Called with no batch launch in flight.
-hdg_status rebuild_plans(hdg_batch *b)
+// Device buffer of at least `need` items for a tile list, grown by doubling:
+// the old buffer is freed only after the batch's launches have completed.
+template <class T>
+hdg_status ensure_capacity(hdg_batch *b, T *&buf, int64_t &cap, int64_t need)
 {
-    free_plans(b);
+    if (need <= cap) return HDG_OK;
+    int64_t n = cap > 0 ? cap : 64;
+    while (n < need) n *= 2;
+    if (buf) {
+        wait_idle(b);
+        (void)hipFree(buf);
+        buf = nullptr;
+        cap = 0;
+    }
+    HDG_HIP(hipMalloc((void **)&buf, (size_t)n * sizeof(T)));
+    cap = n;
+    return HDG_OK;
+}
+
+// Tile lists over every member, for every (kind, order, workgroup size).
+// A plan keeps its device buffers across membership changes (they only grow);
+// the new lists are copied in on stream s, behind the batch's earlier
+// launches (the chain on s), so no host wait is needed unless a buffer grows.
+hdg_status rebuild_plans(hdg_batch *b, hipStream_t s)
+{
+    for (auto &v : b->plans)
+        for (auto &pl : v) pl.ntiles = 0;
     for (int kind = 0; kind < 2; ++kind)
         for (int N = 2; N <= hdg::kMaxN; ++N)
             for (int B : hdg::kBlocks) {
@@ -91,16 +151,27 @@ hdg_status rebuild_plans(hdg_batch *b)
                     hdg::cut_tiles(m->order, Ne, cls, (int)s, B, kind, tiles, elems);
                 }
                 if (tiles.empty()) continue;
-                TilePlan pl;
-                pl.N = N;
-                pl.B = B;
-                pl.ntiles = (int32_t)tiles.size();
-                pl.chunk = (pl.ntiles + hdg::kXcd - 1) / hdg::kXcd;
-                HDG_HIP(hipMalloc((void **)&pl.tiles, tiles.size() * sizeof(Tile)));
-                HDG_HIP(hipMalloc((void **)&pl.elems, elems.size() * sizeof(int32_t)));
-                HDG_HIP(hipMemcpy(pl.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
-                HDG_HIP(hipMemcpy(pl.elems, elems.data(), elems.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-                b->plans[kind].push_back(pl);
+                TilePlan *pl = nullptr;
+                for (auto &q : b->plans[kind])
+                    if (q.N == N && q.B == B) pl = &q;
+                if (!pl) {
+                    b->plans[kind].emplace_back();
+                    pl = &b->plans[kind].back();
+                    pl->N = N;
+                    pl->B = B;
+                }
+                hdg_status st = ensure_capacity(b, pl->tiles, pl->tiles_cap, (int64_t)tiles.size());
+                if (st == HDG_OK) st = ensure_capacity(b, pl->elems, pl->elems_cap, (int64_t)elems.size());
+                if (st != HDG_OK) return st;
+                pl->ntiles = (int32_t)tiles.size();
+                pl->chunk = (pl->ntiles + hdg::kXcd - 1) / hdg::kXcd;
+                // host copies kept with the plan: the source of an asynchronous copy stays valid
+                pl->h_tiles.swap(tiles);
+                pl->h_elems.swap(elems);
+                HDG_HIP(hipMemcpyAsync(pl->tiles, pl->h_tiles.data(), pl->h_tiles.size() * sizeof(Tile),
+                                       hipMemcpyHostToDevice, s));
+                HDG_HIP(hipMemcpyAsync(pl->elems, pl->h_elems.data(), pl->h_elems.size() * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, s));
             }
     b->dirty = false;
     for (auto &sl : b->slots) sl.stale = false;
@@ -109,7 +180,7 @@ hdg_status rebuild_plans(hdg_batch *b)
 
 // One fused RK stage of every member: viscous kernels of each order, then
 // residual kernels.  Stage input is each member's qB if parity, else qA.
-hdg_status batch_stage(hdg_batch *b, bool f32, double A, double B, bool first, int parity, hipStream_t s)
+hdg_status batch_stage(hdg_batch *b, bool f32, double A, double B, int stage, int parity, hipStream_t s)
 {
     for (int kind = 0; kind < 2; ++kind) {
         // members of several orders: their mortar kernels (BR1 lift before the
@@ -151,7 +222,8 @@ hdg_status batch_stage(hdg_batch *b, bool f32, double A, double B, bool first, i
             a.D32 = b->ctx->D32;
             a.rkA = A;
             a.rkB = B;
-            a.first_stage = first ? 1 : 0;
+            a.first_stage = stage == 0 ? 1 : 0;
+            a.store_dq = stage == 2 ? 0 : 1;
             a.parity = parity;
             const int grid = hdg::launch_grid(*pl, kind, Epi::RkStage, f32, cf.persistent, b->ctx->n_cu);
             (void)hipGetLastError();
@@ -172,7 +244,7 @@ hdg_status batch_steps(hdg_batch *b, int32_t nsteps, bool f32, hipStream_t s)
     int parity = 0;
     for (int32_t step = 0; step < nsteps; ++step)
         for (int st = 0; st < 3; ++st) {
-            hdg_status r = batch_stage(b, f32, kA[st], kB[st], st == 0, parity, s);
+            hdg_status r = batch_stage(b, f32, kA[st], kB[st], st, parity, s);
             if (r != HDG_OK) return r;
             parity ^= 1;
         }
@@ -221,10 +293,11 @@ void hdg_batch_destroy(hdg_batch *b)
 {
     if (!b) return;
     (void)hipSetDevice(b->ctx->device);
-    (void)hipDeviceSynchronize();
+    wait_idle(b);
     drop_graph(b);
     free_plans(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->done) (void)hipEventDestroy(b->done);
     (void)hipFree(b->members);
     hdg_ctx *ctx = b->ctx;
     delete b;
@@ -238,27 +311,24 @@ hdg_status hdg_batch_add(hdg_batch *b, hdg_mesh *m, double *q, double *dq, doubl
     if (!m || !q || !dq || q == dq) return fail(HDG_EINVAL, "batch_add: need a mesh and distinct q, dq");
     if (m->ctx->device != b->ctx->device) return fail(HDG_EINVAL, "batch_add: mesh is on another device");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HDG_EINVAL, "batch_add: need dt > 0");
-    // a free slot no launch refers to any more; a slot freed since the last
-    // plan rebuild may still be read by launches in flight
+    // a free slot, preferably one no plan has referred to since the last
+    // rebuild; launches in flight may read any slot of the member table, so
+    // the record is written once the batch's launches have completed
     int32_t free_slot = -1;
-    bool need_sync = false;
     for (size_t s = 0; s < b->slots.size(); ++s) {
         if (b->slots[s].mesh == m) return fail(HDG_EINVAL, "batch_add: mesh is already a member");
         if (!b->slots[s].mesh && !b->slots[s].stale && free_slot < 0) free_slot = (int32_t)s;
     }
     if (free_slot < 0)
         for (size_t s = 0; s < b->slots.size() && free_slot < 0; ++s)
-            if (!b->slots[s].mesh) {
-                free_slot = (int32_t)s;
-                need_sync = true;
-            }
+            if (!b->slots[s].mesh) free_slot = (int32_t)s;
     if (free_slot < 0) return fail(HDG_ENOMEM, "batch_add: no free slot");
     Member mb = m->host_member;
     mb.qA = q;
     mb.qB = m->qpp;
     mb.dq = dq;
     mb.dt = dt;
-    if (need_sync) HDG_HIP(hipDeviceSynchronize());
+    wait_idle(b);
     HDG_HIP(hipMemcpy(b->members + free_slot, &mb, sizeof(Member), hipMemcpyHostToDevice));
     b->slots[free_slot] = hdg_batch::Slot{m, q, dq, dt, false};
     b->dirty = true;
@@ -305,14 +375,20 @@ hdg_status hdg_batch_rk3_steps(hdg_batch *b, int32_t nsteps, hdg_prec prec, void
     if (prec != HDG_F64 && prec != HDG_F32) return fail(HDG_EINVAL, "prec must be HDG_F64 or HDG_F32");
     hipStream_t s = (hipStream_t)stream;
     const bool f32 = prec == HDG_F32;
+    st = join_chain(b, s);
+    if (st != HDG_OK) return st;
+    // membership as in the previous call: a captured graph pays off; right
+    // after a change (a member joined or left) the steps run eagerly, so that
+    // a stream of joins and leaves costs no capture and no host wait
+    const bool stable = b->version == b->last_call_version;
+    b->last_call_version = b->version;
     if (b->dirty) {
-        HDG_HIP(hipStreamSynchronize(s));     // old plans may still be read by launches in flight
         drop_graph(b);
-        st = rebuild_plans(b);
+        st = rebuild_plans(b, s);
         if (st != HDG_OK) return st;
     }
     int32_t eager = nsteps;
-    if (b->graphs && nsteps >= 2) {
+    if (b->graphs && stable && nsteps >= 2) {
         if (!b->gexec || b->g_version != b->version || b->g_prec != (int)prec) {
             drop_graph(b);
             if (!b->cap) HDG_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
@@ -342,19 +418,28 @@ hdg_status hdg_batch_rk3_steps(hdg_batch *b, int32_t nsteps, hdg_prec prec, void
             b->g_version = b->version;
             b->g_prec = (int)prec;
         }
-        for (int32_t k = 0; k < nsteps / 2; ++k) HDG_HIP(hipGraphLaunch(b->gexec, s));
+        for (int32_t k = 0; k < nsteps / 2; ++k) {
+            const hipError_t e = hipGraphLaunch(b->gexec, s);
+            if (e != hipSuccess) {
+                (void)mark_done(b, s);
+                return fail(HDG_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+            }
+        }
         eager = nsteps % 2;
     }
     st = batch_steps(b, eager, f32, s);
-    if (st != HDG_OK) return st;
-    if (eager % 2) {
+    if (st == HDG_OK && eager % 2) {
         // odd number of stages in total: the states sit in the ping-pong buffers
         for (const auto &sl : b->slots)
-            if (sl.mesh)
-                HDG_HIP(hipMemcpyAsync(sl.q, sl.mesh->qpp, (size_t)sl.mesh->nodes * 4 * sizeof(double),
-                                       hipMemcpyDeviceToDevice, s));
+            if (sl.mesh && st == HDG_OK) {
+                const hipError_t e = hipMemcpyAsync(sl.q, sl.mesh->qpp, (size_t)sl.mesh->nodes * 4 * sizeof(double),
+                                                    hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) st = fail(HDG_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+            }
     }
-    return HDG_OK;
+    // recorded whatever happened above, so that later waits cover every launch made
+    const hdg_status md = mark_done(b, s);
+    return st != HDG_OK ? st : md;
 }
 
 hdg_status hdg_batch_set_graphs(hdg_batch *b, int32_t enable)
@@ -372,12 +457,13 @@ hdg_status hdg_batch_autotune(hdg_batch *b, int32_t reps, void *stream)
     if (st != HDG_OK) return st;
     if (reps < 1) return fail(HDG_EINVAL, "batch_autotune: reps >= 1");
     hipStream_t s = (hipStream_t)stream;
+    st = join_chain(b, s);
+    if (st != HDG_OK) return st;
+    drop_graph(b);
     if (b->dirty) {
-        HDG_HIP(hipDeviceSynchronize());
-        st = rebuild_plans(b);
+        st = rebuild_plans(b, s);
         if (st != HDG_OK) return st;
     }
-    drop_graph(b);
     hipEvent_t e0, e1;
     HDG_HIP(hipEventCreate(&e0));
     HDG_HIP(hipEventCreate(&e1));
@@ -403,6 +489,7 @@ hdg_status hdg_batch_autotune(hdg_batch *b, int32_t reps, void *stream)
                         a.rkA = 0.0;
                         a.rkB = 0.5;
                         a.first_stage = 1;
+                        a.store_dq = 1;
                         a.parity = 0;
                         const int grid = hdg::launch_grid(*pl, kind, Epi::RkStage, pi == 1, pers != 0, b->ctx->n_cu);
                         auto once = [&]() -> hdg_status {
@@ -433,10 +520,12 @@ hdg_status hdg_batch_autotune(hdg_batch *b, int32_t reps, void *stream)
                 }
                 if (st == HDG_OK && best.us >= 0.0) b->cfg[kind][pi][N] = best;
             }
+    const hdg_status md = mark_done(b, s);
+    b->last_call_version = b->version;         // the next call at this membership may capture
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return st;
+    return st != HDG_OK ? st : md;
 }
 
 hdg_status hdg_batch_get_launch(const hdg_batch *b, int32_t kernel_class, hdg_prec prec, int32_t N,

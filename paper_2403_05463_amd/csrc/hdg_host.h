@@ -48,6 +48,10 @@ struct TilePlan {
     int32_t ntiles = 0, chunk = 0;
     Tile *tiles = nullptr;
     int32_t *elems = nullptr;
+    // batches: device capacity (items) and the host copy of the last upload
+    int64_t tiles_cap = 0, elems_cap = 0;
+    std::vector<Tile> h_tiles;
+    std::vector<int32_t> h_elems;
 };
 
 // Launch configuration of one (kernel kind, precision, order): workgroup size

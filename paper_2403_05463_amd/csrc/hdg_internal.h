@@ -151,6 +151,8 @@ struct StageArgs {
     double dt;
     double rkA, rkB;        // fused RK stage: dq = A dq + dt R; q_next = q + B dq
     int32_t first_stage;    // A = 0: dq is not read
+    int32_t store_dq;       // 0: dq is not written (the step's last stage: the next stage, the first of
+                            // a step, does not read it)
     int32_t parity;         // member mode: stage input is qB if set, else qA
     int64_t nodes;          // node features: stride of the [3][nodes] output at r
 };

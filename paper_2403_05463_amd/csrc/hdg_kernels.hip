@@ -627,9 +627,16 @@ __device__ __forceinline__ FaceData<T> face_data(const Member &M)
     return d;
 }
 
-template <int N, class T>
+// jf, when given, points at this element's Ja^dir at the face node (three
+// values NTASK apart) and sf is the face's side (-1 for a minus face, +1 for
+// a plus face): sf Ja^dir is this element's outward s n, the owner's is its
+// negative on the other side (the two elements' metric terms agree at a
+// shared face node to round-off).  Without jf the owner's stored unit normal
+// and scale are read.
+template <int N, class T, int NTASK = 0>
 __device__ __forceinline__ void face_jump(const FaceData<T> &M, const gmem<const double> *qin, T c0sq, bool visc,
-                                          int fa, int fb, const FaceRef &fr, const double (&qm)[4], T (&F)[4])
+                                          int fa, int fb, const FaceRef &fr, const double (&qm)[4], T (&F)[4],
+                                          const T *jf = nullptr, T sf = T(1))
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
     const bool own = fr.code & kOwnerBit;
@@ -652,9 +659,23 @@ __device__ __forceinline__ void face_jump(const FaceData<T> &M, const gmem<const
     }
     const int fnode = oa + N * ob;
     const int64_t fo = M.foff ? gp(M.foff)[fr.face] : (int64_t)fr.face * N2;
-    const gmem<const T> *g = gp(M.geo) + 4 * (fo + fnode);
-    const T n[3] = {g[0], g[1], g[2]};
-    const T sc = g[3];
+    T n[3], sc;
+    if constexpr (NTASK > 0) {
+        // the owner's outward s n from this element's own metric terms
+        const T so = own ? sf : -sf;
+        const T v[3] = {so * jf[0], so * jf[NTASK], so * jf[2 * NTASK]};
+        const T v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const T iv = rsqrt_refined(v2);
+        sc = v2 * iv;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) n[d] = v[d] * iv;
+    } else {
+        const gmem<const T> *g = gp(M.geo) + 4 * (fo + fnode);
+        n[0] = g[0];
+        n[1] = g[1];
+        n[2] = g[2];
+        sc = g[3];
+    }
     T uL[3], du[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -740,10 +761,17 @@ __device__ __forceinline__ void surface_terms(const Member &M, const TileFaces<E
 template <int N, class T>
 constexpr bool residual_sface_in_flux() { return N <= 5 && N >= 3 && sizeof(T) == 8; }
 
+// Order-5 tiles take the face normals from the element's own metric terms,
+// staged per face node in LDS ([3][EPT 6 N^2] after the derivative matrix),
+// instead of loading the stored face geometry.
+template <int N>
+constexpr bool residual_face_ja() { return N == 5; }
+
 template <int N, int EPT, class T>
 constexpr int residual_lds_words()
 {
-    return 12 * EPT * N * N * N + (residual_sface_in_flux<N, T>() ? 0 : 4 * EPT * 6 * N * N) + N * N;
+    return 12 * EPT * N * N * N + (residual_sface_in_flux<N, T>() ? 0 : 4 * EPT * 6 * N * N) + N * N +
+           (residual_face_ja<N>() ? 3 * EPT * 6 * N * N : 0);
 }
 
 template <int N, int EPT, int EPI, class T>
@@ -757,6 +785,8 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     // area, or after the flux area
     T *sface = SF_IN_FLUX ? (T *)((double *)smem + 4 * NN) : lds + 12 * NN;
     T *sD = SF_IN_FLUX ? lds + 12 * NN : sface + 4 * NTASK;   // [N2]
+    constexpr bool FACE_JA = residual_face_ja<N>();
+    T *sjf = sD + N2;                 // [3][NTASK] Ja^dir at the face nodes (FACE_JA)
     const Member &M = A.mem[tl.member];
     TileCtx<N, T> c;
     __shared__ TileFaces<EPT> tf;
@@ -770,6 +800,22 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     const bool visc = tl.flag != 0;   // a tile's elements share one equation flag
     const FaceData<T> fd = face_data<T>(M);
 
+    if constexpr (FACE_JA) {
+        // each face node's Ja^dir, for the face tasks' normals
+        if (c.act) {
+#pragma unroll
+            for (int dir = 0; dir < 3; ++dir) {
+                const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
+                if (idx == 0 || idx == N - 1) {
+                    const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
+                    const int task = c.s * NFT + f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) sjf[d * NTASK + task] = c.Ja[dir][d];
+                }
+            }
+        }
+        __syncthreads();
+    }
     if constexpr (STAGE) {
         // face-node tasks, spread evenly over the workgroup; a tile's elements
         // share one equation class
@@ -781,7 +827,11 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
                 const int node = ft.s * N3 + face_node<N>(ft.f, ft.fa, ft.fb);
                 const double qm[4] = {sq[node], sq[NN + node], sq[2 * NN + node], sq[3 * NN + node]};
                 T F[4];
-                face_jump<N, T>(fd, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
+                if constexpr (FACE_JA)
+                    face_jump<N, T, NTASK>(fd, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F, sjf + task,
+                                           (ft.f & 1) ? T(1) : T(-1));
+                else
+                    face_jump<N, T>(fd, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
 #pragma unroll
                 for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
             }
@@ -887,7 +937,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
                 // FP64 stage accumulation into the state
                 const double Rd = (double)R;
                 const double d = A.first_stage ? dt * Rd : A.rkA * dq_old[row] + dt * Rd;
-                dqp[idx] = d;
+                if (A.store_dq) dqp[idx] = d;
                 qout[idx] = c.qd[row] + A.rkB * d;
             }
         }
@@ -943,8 +993,14 @@ __global__ __launch_bounds__(B) void k_features(StageArgs A)
     HDG_ONE_TILE(A, tl) viscous_tile<N, EPT, double, true>(A, tl, smem);
 }
 
+// Waves per SIMD the compiler must keep resident (a register cap): the FP64
+// one-tile residual kernel of order 5 in 128-lane workgroups holds five
+// waves (at most 96 VGPRs, no spills); the rest are left to the compiler.
+template <class T, int N, int B, bool PERS>
+constexpr int residual_min_waves() { return (sizeof(T) == 8 && !PERS && N == 5 && B == 128) ? 5 : 1; }
+
 template <class T, int EPI, int N, int B, bool PERS>
-__global__ __launch_bounds__(B) void k_residual(StageArgs A)
+__global__ __launch_bounds__(B, (residual_min_waves<T, N, B, PERS>())) void k_residual(StageArgs A)
 {
     constexpr int EPT = tile_ept(N, B, kTileResidual);
     static_assert(EPT > 0, "tile does not fit the workgroup");

@@ -5,7 +5,13 @@
 ``python -m paper_2403_05463_amd.profiling traffic <fetch.csv> <write.csv> --copy-bytes B --cmd "<command>"``
     HBM bytes per dispatch from two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
     runs, each scaled by what the same counter reads for the plain copy kernel
-    of known size (copy bytes / counter reading).
+    of known size (copy bytes / counter reading);
+``python -m paper_2403_05463_amd.profiling flops <f64.csv> <f32.csv> --cmd64 "<command>" --cmd32 "<command>"``
+    floating-point operations per dispatch from ``--pmc SQ_INSTS_VALU_ADD_F64
+    SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64`` (and
+    the F32 counters): the counters count wave instructions, so FLOPs =
+    64 (ADD + MUL + TRANS + 2 FMA), an upper bound that counts every lane of
+    a wave, active or not.
 
 The traffic summary records a hash of the kernel sources; ``traffic_for``
 returns its figure only while the sources are unchanged.
@@ -94,6 +100,55 @@ def traffic_for(summary_path: str, kernel_prefix: str):
     return None
 
 
+FLOP_COUNTERS = {64: ["SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                      "SQ_INSTS_VALU_TRANS_F64"],
+                 32: ["SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_FMA_F32",
+                      "SQ_INSTS_VALU_TRANS_F32"]}
+# MI355X peak vector rates (TFLOP/s)
+PEAK_TFLOPS = {64: 78.6, 32: 157.3}
+
+
+def flops_summary(csv64: str, csv32: str, cmd64: str, cmd32: str) -> str:
+    lines = ["# floating-point operations per dispatch from VALU instruction counters",
+             f"command (FP64 counters): {cmd64}", f"command (FP32 counters): {cmd32}",
+             f"kernel source hash: {kernel_source_hash()}",
+             "FLOPs = 64 (ADD + MUL + TRANS + 2 FMA) per precision (wave instructions x 64 lanes)", "",
+             f"{'kernel':40s} {'flops_f64':>14s} {'flops_f32':>14s}"]
+    per = {}
+    for bits, path in ((64, csv64), (32, csv32)):
+        add, mul, fma, trans = (_per_kernel(path, c) for c in FLOP_COUNTERS[bits])
+        for k in fma:
+            per.setdefault(k, {})[bits] = 64.0 * (add.get(k, 0) + mul.get(k, 0) + trans.get(k, 0) + 2 * fma[k])
+    for k in sorted(per):
+        lines.append(f"{k.replace(' ', ''):40s} {per[k].get(64, 0.0):14.4e} {per[k].get(32, 0.0):14.4e}")
+    return "\n".join(lines) + "\n"
+
+
+def flops_for(summary_path: str, kernel_prefix: str, avg_launch_s: float):
+    """FLOP count per dispatch of the first kernel starting with ``kernel_prefix``
+    and its rate over ``avg_launch_s`` against the peak of the kernel's
+    arithmetic type, or None if the summary is missing or the kernel sources
+    changed since it was taken."""
+    if not os.path.exists(summary_path):
+        return None
+    text = open(summary_path).read()
+    m = re.search(r"kernel source hash: (\w+)", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    want = kernel_prefix.replace(" ", "")
+    bits = 32 if want.startswith("k_residual<float") or want.startswith("k_viscous<float") else 64
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) == 3 and parts[0].startswith(want):
+            f64, f32 = float(parts[1]), float(parts[2])
+            main = f64 if bits == 64 else f32
+            tf = main / avg_launch_s / 1e12
+            return {"flops_per_launch": main, "other_precision_flops": f32 if bits == 64 else f64,
+                    "achieved_tflops": tf, "peak_tflops": PEAK_TFLOPS[bits], "frac": tf / PEAK_TFLOPS[bits],
+                    "unit": "TFLOP/s", "arith": f"f{bits}"}
+    return None
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -108,9 +163,17 @@ def main(argv=None):
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--out")
+    f = sub.add_parser("flops")
+    f.add_argument("csv64")
+    f.add_argument("csv32")
+    f.add_argument("--cmd64", required=True)
+    f.add_argument("--cmd32", required=True)
+    f.add_argument("--out")
     a = ap.parse_args(argv)
     if a.what == "stats":
         text = stats_summary(a.csv, a.cmd)
+    elif a.what == "flops":
+        text = flops_summary(a.csv64, a.csv32, a.cmd64, a.cmd32)
     else:
         text = traffic_summary(a.fetch_csv, a.write_csv, a.copy_bytes, a.cmd_fetch, a.cmd_write)
     if a.out:

@@ -47,6 +47,7 @@ class Request:
     nodes: int = 0
     est_bytes: int = 0
     result: object = None
+    refused: str = ""           # why the request was not served ("" if it was)
 
     @property
     def latency(self) -> float:
@@ -100,15 +101,18 @@ class Backend:
 
 @dataclass
 class ServeStats:
-    requests: list
+    requests: list              # served to completion
     wall_s: float
     steps_launched: int
     max_members: int
     peak_bytes: int
     dof_evals: float
     member_counts: list = field(default_factory=list)
+    refused: list = field(default_factory=list)   # refused on their own (``Request.refused`` says why)
 
     def summary(self) -> dict:
+        if not self.requests:
+            return {"requests": 0, "refused": len(self.refused), "wall_s": self.wall_s}
         lat = np.array([r.latency for r in self.requests])
         queue = np.array([r.t_admit - r.arrival for r in self.requests])
         setup = np.array([r.t_join - r.t_admit for r in self.requests])
@@ -117,7 +121,7 @@ class ServeStats:
         def pct(a, p):
             return float(np.percentile(a, p))
         return {
-            "requests": len(self.requests),
+            "requests": len(self.requests), "refused": len(self.refused),
             "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99), "mean_latency_s": float(lat.mean()),
             "p50_queue_s": pct(queue, 50), "p99_queue_s": pct(queue, 99),
             "p50_setup_s": pct(setup, 50), "p99_setup_s": pct(setup, 99),
@@ -134,12 +138,17 @@ def serve(requests: list[Request], backend: Backend, mem_budget: int, max_member
           sleep=time.sleep, realtime: bool = True) -> ServeStats:
     """Run the request stream to completion.  With `realtime`, a request is
     only visible once the clock has passed its arrival time; otherwise all
-    arrive at once (a backlog)."""
+    arrive at once (a backlog).
+
+    A request that can never be served is refused on its own and the stream
+    goes on: one whose footprint exceeds the whole memory budget (refused on
+    arrival, before it could hold up the queue behind it) and one whose
+    set-up raises (its memory is released).  Refused requests are listed in
+    ``ServeStats.refused`` with the reason in ``Request.refused``."""
     reqs = sorted(requests, key=lambda r: r.arrival)
     for r in reqs:
         r.est_bytes = footprint_bytes(r.n, r.P)
-        if r.est_bytes > mem_budget:
-            raise ValueError(f"request {r.rid} needs {r.est_bytes} bytes, more than the budget {mem_budget}")
+    refused = []
     pending = collections.deque()
     setups = {}                       # future -> request
     ready = collections.deque()       # (request, handle) set up, waiting to join
@@ -154,11 +163,17 @@ def serve(requests: list[Request], backend: Backend, mem_budget: int, max_member
     t0 = clock()
     nxt = 0
     with cf.ThreadPoolExecutor(max_workers=setup_workers) as pool:
-        while len(done) < len(reqs):
+        while len(done) + len(refused) < len(reqs):
             now = clock() - t0
             while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= now):
-                pending.append(reqs[nxt])
+                r = reqs[nxt]
                 nxt += 1
+                if r.est_bytes > mem_budget:
+                    r.refused = f"needs {r.est_bytes} bytes, more than the budget {mem_budget}"
+                    r.t_done = clock() - t0
+                    refused.append(r)
+                else:
+                    pending.append(r)
             # admission: arrival order, memory budget, slots (set-up ones count)
             while pending and used + pending[0].est_bytes <= mem_budget and \
                     len(active) + len(setups) + len(ready) < max_members:
@@ -169,7 +184,13 @@ def serve(requests: list[Request], backend: Backend, mem_budget: int, max_member
                 setups[pool.submit(backend.setup, r)] = r
             for fut in [f for f in setups if f.done()]:
                 r = setups.pop(fut)
-                ready.append((r, fut.result()))
+                try:
+                    ready.append((r, fut.result()))
+                except Exception as ex:            # this request only: release it and go on
+                    r.refused = f"set-up failed: {ex}"
+                    r.t_done = clock() - t0
+                    used -= r.est_bytes
+                    refused.append(r)
             # join at the step boundary
             while ready:
                 r, h = ready.popleft()
@@ -204,7 +225,7 @@ def serve(requests: list[Request], backend: Backend, mem_budget: int, max_member
                 elif timeout > 0:
                     sleep(min(timeout, 0.05))
     wall = clock() - t0
-    return ServeStats(done, wall, calls, max_seen, peak, dof, counts)
+    return ServeStats(done, wall, calls, max_seen, peak, dof, counts, refused)
 
 
 def taylor_green_device(torch, X, amp: float, seed: int):
@@ -236,6 +257,9 @@ class HdgBackend(Backend):
     C0SQ = 25.0
 
     def __init__(self, ctx, max_members: int, prec: int, torch, stream=None, keep_results: bool = False):
+        """keep_results: a finished request's result is a dict of its final and
+        initial states (host arrays), time step and mesh, else whether its
+        final state is finite."""
         from . import hdg, workloads as W
         self.hdg, self.W, self.torch = hdg, W, torch
         self.ctx = ctx
@@ -278,6 +302,8 @@ class HdgBackend(Backend):
             dq = self.torch.empty_like(q)
         self.stream.synchronize()
         h.update(q=q, dq=dq, dt=dt)
+        if self.keep:
+            h["q0"] = q.cpu().numpy()
         h.pop("X")
         return self.hdg.hdg_batch_add(self.batch, h["mesh"], q, dq, dt)
 
@@ -288,8 +314,10 @@ class HdgBackend(Backend):
     def leave(self, slot: int, h):
         q = h["q"]
         self.hdg.hdg_batch_remove(self.batch, slot)
-        out = q.cpu().numpy() if self.keep else bool(self.torch.isfinite(q).all().item())
-        return (out, h["dt"]) if self.keep else out
+        if self.keep:
+            # final state, time step, initial state and the mesh (for checks)
+            return {"q": q.cpu().numpy(), "dt": h["dt"], "q0": h["q0"], "mesh": h["mesh"]}
+        return bool(self.torch.isfinite(q).all().item())
 
     def make_alone(self, r: Request):
         """The same solve, set up on its own: (mesh, q, dq, dt)."""

@@ -12,32 +12,58 @@ N3, N2 = N ** 3, N ** 2
 
 
 def test_fused_stage_bytes_fp64():
-    # per node: q 32, 1/J and Ja 80, dq written 32 and read 32, next state 32;
-    # three owned faces of N^2 nodes with n and s (4 doubles) per element;
-    # flagged: viscous volume part 3 doubles per node, both sides' traces
-    # 3 doubles per face node on six faces
-    later = NE * (N3 * (32 + 80 + 32 + 32 + 32) + 3 * N2 * 4 * 8) + NV * (N3 * 3 * 8 + 6 * N2 * 3 * 8)
+    # the operator's bytes per node: q 32, 1/J and Ja 80, dq written 32 and
+    # read 32, next state 32; three owned faces of N^2 nodes with n and s (4
+    # doubles) per element.  The viscous intermediates are not counted.
+    later = NE * (N3 * (32 + 80 + 32 + 32 + 32) + 3 * N2 * 4 * 8)
     first = later - NE * N3 * 32                      # A = 0: dq is not read
-    assert bench.algorithmic_bytes(1, NE, NV, N, fused_rk=True) == later
-    assert bench.algorithmic_bytes(1, NE, NV, N, fused_rk=True, first_stage=True) == first
-    assert later == 1118587200
+    assert bench.algorithmic_bytes(NE, N, fused_rk=True) == later
+    assert bench.algorithmic_bytes(NE, N, fused_rk=True, first_stage=True) == first
+    assert later == 1046937600
+    # averaged over the three stages: (208 + 208 + 176 + 3 * 96 / N) / 3 B/node
+    avg = sum(bench.algorithmic_bytes(NE, N, fused_rk=True, first_stage=(s == 0)) for s in range(3)) / 3
+    assert abs(avg / (NE * N3) - (592 / 3 + 96 / N)) < 1e-9
 
 
 def test_fused_stage_bytes_fp32():
-    # metric, face geometry and viscous parts in FP32; state and RK in FP64
-    later = NE * (N3 * (32 + 40 + 96) + 3 * N2 * 4 * 4) + NV * (N3 * 3 * 4 + 6 * N2 * 3 * 4)
-    assert bench.algorithmic_bytes(1, NE, NV, N, fused_rk=True, f32=True) == later
-    assert bench.algorithmic_bytes(1, NE, NV, N, fused_rk=True, f32=True, first_stage=True) == \
-        later - NE * N3 * 32
+    # metric and face geometry in FP32; state and RK in FP64
+    later = NE * (N3 * (32 + 40 + 96) + 3 * N2 * 4 * 4)
+    assert bench.algorithmic_bytes(NE, N, fused_rk=True, f32=True) == later
+    assert bench.algorithmic_bytes(NE, N, fused_rk=True, f32=True, first_stage=True) == later - NE * N3 * 32
 
 
-def test_residual_only_and_viscous_bytes():
-    # residual form: R written instead of the RK traffic
-    assert bench.algorithmic_bytes(1, NE, NV, N, fused_rk=False) == \
-        NE * (N3 * (32 + 80 + 32) + 3 * N2 * 32) + NV * (N3 * 24 + 6 * N2 * 24)
+def test_residual_only_intermediate_and_viscous_bytes():
+    # the survey's residual figure: 144 + 96 / N B/node
+    assert bench.algorithmic_bytes(NE, N, fused_rk=False) == NE * N3 * (144 + 96 / N)
+    # viscous part (3 doubles per node) and both sides' traces (3 doubles per face node, six faces)
+    assert bench.intermediate_bytes(NV, N) == NV * (N3 * 24 + 6 * N2 * 24)
+    assert bench.intermediate_bytes(NV, N, f32=True) == NV * (N3 * 12 + 6 * N2 * 12)
     # viscous kernel, flagged elements: velocity 24 + metric 80 in, viscous part
     # 24 and six faces of traces out
-    assert bench.algorithmic_bytes(0, NE, NV, N, fused_rk=True) == NV * ((24 + 80 + 24) * N3 + 6 * N2 * 24)
+    assert bench.viscous_kernel_bytes(NV, N) == NV * ((24 + 80 + 24) * N3 + 6 * N2 * 24)
+
+
+def test_flops_summary_parsing(tmp_path, monkeypatch):
+    from paper_2403_05463_amd import profiling as prof
+    rows = ["Kernel_Name,Counter_Name,Counter_Value"]
+    for c, v in zip(prof.FLOP_COUNTERS[64], (10, 20, 30, 5)):
+        rows.append(f"\"k_residual<double, 1, 5, 128, false>(StageArgs)\",{c},{v}")
+    rows32 = ["Kernel_Name,Counter_Name,Counter_Value"]
+    for c, v in zip(prof.FLOP_COUNTERS[32], (1, 2, 3, 4)):
+        rows32.append(f"\"k_residual<double, 1, 5, 128, false>(StageArgs)\",{c},{v}")
+    a, b = tmp_path / "a.csv", tmp_path / "b.csv"
+    a.write_text("\n".join(rows) + "\n")
+    b.write_text("\n".join(rows32) + "\n")
+    out = tmp_path / "flops.txt"
+    out.write_text(prof.flops_summary(str(a), str(b), "cmd64", "cmd32"))
+    r = prof.flops_for(str(out), "k_residual<double, 1, 5, 128, false>", 1e-6)
+    assert r["flops_per_launch"] == 64.0 * (10 + 20 + 5 + 2 * 30)
+    assert r["other_precision_flops"] == 64.0 * (1 + 2 + 4 + 2 * 3)
+    assert abs(r["achieved_tflops"] - r["flops_per_launch"] / 1e-6 / 1e12) < 1e-9
+    assert r["peak_tflops"] == 78.6
+    # a summary taken from other kernel sources is not used
+    monkeypatch.setattr(prof, "kernel_source_hash", lambda: "0" * 16)
+    assert prof.flops_for(str(out), "k_residual<double, 1, 5, 128, false>", 1e-6) is None
 
 
 def test_more_than_one_gpu_is_refused(capsys, monkeypatch):

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2403_05463_amd import hdg, workloads as W
+from parity import TOL_F32, TOL_F64, flat_errors, flat_mass, increment_errors, oracle_mass
 
 pytestmark = pytest.mark.gpu
 
@@ -78,7 +79,10 @@ def test_batch_members_equal_alone(torch_cuda, ctx, prec, graphs):
         qs.append(q)
     info = hdg.hdg_batch_info(b)
     assert info["n_members"] == len(reqs)
-    hdg.hdg_batch_rk3_steps(b, 5, prec=prec)
+    # the first call after members joined runs eagerly, the next at the same
+    # membership replays a captured graph (when graphs are on)
+    hdg.hdg_batch_rk3_steps(b, 1, prec=prec)
+    hdg.hdg_batch_rk3_steps(b, 4, prec=prec)
     torch.cuda.synchronize()
     for i, q in enumerate(qs):
         assert np.array_equal(q.cpu().numpy(), alone[i]), f"member {i} differs from its solve alone"
@@ -121,7 +125,8 @@ def test_batch_with_mixed_order_member(torch_cuda, ctx, prec, graphs):
         q = torch.from_numpy(q0).cuda()
         hdg.hdg_batch_add(b, m, q, torch.empty_like(q), dt)
         qs.append(q)
-    hdg.hdg_batch_rk3_steps(b, 5, prec=prec)
+    hdg.hdg_batch_rk3_steps(b, 1, prec=prec)
+    hdg.hdg_batch_rk3_steps(b, 4, prec=prec)
     torch.cuda.synchronize()
     for i, q in enumerate(qs):
         out = q.cpu().numpy()
@@ -200,3 +205,95 @@ def test_batch_autotune_keeps_results(torch_cuda, ctx):
         assert np.array_equal(qs[i].cpu().numpy(), _alone(torch, m, q0, dt, 2, hdg.HDG_F64))
     c = hdg.hdg_batch_get_launch(b, hdg.HDG_KERNEL_RESIDUAL, hdg.HDG_F64, reqs[0]["P"] + 1)
     assert c["us_per_launch"] > 0
+
+
+def test_batch_precision_switch_and_two_streams(torch_cuda, ctx):
+    """One batch stepped in FP64, then FP32 (the captured graph is dropped and
+    recaptured), then on a second stream and back: each member equals its
+    solve alone stepped through the same sequence, bitwise.  The batch's calls
+    are chained, so a call on another stream starts after the previous one."""
+    torch = torch_cuda
+    reqs = _requests(3, seed=61)
+    made = [_make(ctx, r) for r in reqs]
+    _say(f"precision switch and two streams, boxes {[(r['n'], r['P']) for r in reqs]}")
+    seq = [(hdg.HDG_F64, 1, 0), (hdg.HDG_F64, 2, 0), (hdg.HDG_F32, 2, 0), (hdg.HDG_F32, 4, 1),
+           (hdg.HDG_F64, 2, 1), (hdg.HDG_F64, 3, 0)]
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    alone = []
+    for (m, q0, dt) in made:
+        q = torch.from_numpy(q0).cuda()
+        dq = torch.empty_like(q)
+        for prec, k, _ in seq:
+            hdg.hdg_rk3_steps(m, q, dq, dt, k, prec=prec)
+        torch.cuda.synchronize()
+        alone.append(q.cpu().numpy())
+    b = hdg.hdg_batch_create(ctx, 4)
+    qs = []
+    for (m, q0, dt) in made:
+        q = torch.from_numpy(q0).cuda()
+        hdg.hdg_batch_add(b, m, q, torch.empty_like(q), dt)
+        qs.append(q)
+    torch.cuda.synchronize()
+    for prec, k, on_side in seq:
+        hdg.hdg_batch_rk3_steps(b, k, prec=prec, stream=side if on_side else main)
+    torch.cuda.synchronize()
+    for i, q in enumerate(qs):
+        assert np.array_equal(q.cpu().numpy(), alone[i]), f"member {i} differs from its solve alone"
+
+
+def _oracle_case(orc, r):
+    mesh = W.periodic_box(r["n"], Pg=1)
+    flag = W.bernoulli_mask(mesh.n_elem, r["frac"], r["seed"])
+    prm = dict(c0sq=25.0, nu=r["nu"], les_model=1, C_les=0.1, mixed_face=0, q_inf=(0, 0, 0, 0))
+    return orc.OracleMesh(mesh, r["P"], flag), orc.make_params(**prm)
+
+
+@pytest.mark.parametrize("prec", [hdg.HDG_F64, hdg.HDG_F32])
+def test_batch_members_match_oracle(orc, torch_cuda, ctx, prec):
+    """Members of one batch (three one-order boxes of different orders and a
+    member of orders 2..6 with mortars) against the FP64 oracle's RK3, per
+    field on the increments q - q0: FP64 within 1e-12 (or the states'
+    rounding floor), FP32 residual arithmetic within 1e-5 on the velocity rows
+    (the pressure row's floored error is reported)."""
+    torch = torch_cuda
+    reqs = [dict(n=3, P=2, frac=0.5, nu=3e-3, seed=71), dict(n=3, P=4, frac=0.3, nu=1e-3, seed=72),
+            dict(n=3, P=5, frac=0.7, nu=5e-3, seed=73)]
+    made = [_make(ctx, r) for r in reqs]
+    mm, mq0, mdt, counts = _mixed_member(ctx, 8)
+    steps = 4
+    _say(f"batch vs oracle, prec {prec}: boxes {[(r['n'], r['P']) for r in reqs]} and orders 2..6 {counts}")
+    b = hdg.hdg_batch_create(ctx, 4)
+    qs = []
+    for (m, q0, dt) in made + [(mm, mq0, mdt)]:
+        q = torch.from_numpy(np.ascontiguousarray(q0)).cuda()
+        hdg.hdg_batch_add(b, m, q, torch.empty_like(q), dt)
+        qs.append(q)
+    hdg.hdg_batch_rk3_steps(b, 1, prec=prec)
+    hdg.hdg_batch_rk3_steps(b, steps - 1, prec=prec)
+    torch.cuda.synchronize()
+    for i, (r, (m, q0, dt)) in enumerate(zip(reqs, made)):
+        om, po = _oracle_case(orc, r)
+        ref = om.rk3(po, q0, dt, steps)
+        out = qs[i].cpu().numpy().reshape(ref.shape)
+        e = increment_errors(out, ref, q0, oracle_mass(orc, om, r["P"]))
+        _say(f"member {i} (P={r['P']}): increment errors L2 {e['l2']}, max {e['max']}")
+        if prec == hdg.HDG_F64:
+            assert np.all(e["l2"] <= np.maximum(TOL_F64, e["floor_l2"]))
+            assert np.all(e["max"] <= np.maximum(TOL_F64, e["floor_max"]))
+        else:
+            assert e["l2"][1:].max() <= TOL_F32 and e["max"][1:].max() <= 10 * TOL_F32
+            assert e["l2"][1:].max() > 1e-12          # the FP32 path ran
+    # the member of several orders
+    mesh = W.periodic_box(3, Pg=1, curve_amp=0.25)
+    flag = W.bernoulli_mask(mesh.n_elem, 0.5, 8)
+    om = orc.OracleMesh(mesh, W.mixed_orders(flag, 8), flag)
+    po = orc.make_params(c0sq=25.0, nu=5e-3, les_model=1, C_les=0.1)
+    ref = om.rk3(po, mq0, mdt, steps)
+    out = qs[3].cpu().numpy()
+    l2, mx = flat_errors(om, flat_mass(orc, om), out - mq0, ref - mq0)
+    _say(f"mixed-order member: increment errors L2 {l2}, max {mx}")
+    if prec == hdg.HDG_F64:
+        assert max(l2.max(), mx.max()) <= TOL_F64
+    else:
+        assert l2[1:].max() <= TOL_F32 and mx[1:].max() <= 10 * TOL_F32

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2403_05463_amd import hdg, workloads as W
-from parity import TOL_F32, fp32_errors, oracle_mass, pressure_term_scale
+from parity import TOL_F32, fp32_errors, increment_errors, oracle_mass, pressure_term_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -84,9 +84,15 @@ def test_fp32_rk_steps_track_fp64_oracle(orc, torch_cuda, ctx):
     dq = torch.empty_like(q)
     hdg.hdg_rk3_steps(m, q, dq, w.dt, w.nsteps, prec=hdg.HDG_F32)
     ref = om.rk3(orc.make_params(**w.params), q0, w.dt, w.nsteps)
-    err = np.abs(q.cpu().numpy() - ref).max() / np.abs(ref).max()
+    out = q.cpu().numpy()
+    err = np.abs(out - ref).max() / np.abs(ref).max()
     _say(f"state error after {w.nsteps} steps: {err:.3e}")
     assert err < 1e-6
+    # the increments q - q0, per field in the floored norms: they are sums of
+    # dt R over the stages, so they carry the FP32 residual's relative error
+    e = increment_errors(out, ref, q0, oracle_mass(orc, om, w.P))
+    _say(f"increment errors after {w.nsteps} steps: per-field L2 {e['l2']}, max {e['max']}")
+    assert e["l2"].max() <= TOL_F32 and e["max"].max() <= 10 * TOL_F32
 
 
 def test_precision_form_tgv32_P5(orc, torch_cuda, ctx):
@@ -115,6 +121,9 @@ def test_precision_form_tgv32_P5(orc, torch_cuda, ctx):
     e1 = np.abs(d1).max(axis=(0, 2)) / np.abs(ref1).max()
     _say(f"1 step vs oracle: per-field max error / max|q| {e1}")
     assert e1.max() < 1e-7
+    ei = increment_errors(q.cpu().numpy(), ref1, q0, mass)
+    _say(f"1 step vs oracle: increment errors per field, L2 {ei['l2']}, max {ei['max']}")
+    assert ei["l2"][1:].max() <= TOL_F32 and ei["max"][1:].max() <= 10 * TOL_F32
     for steps in (100, 1000):
         q32 = torch.from_numpy(q0).cuda()
         q64 = torch.from_numpy(q0).cuda()

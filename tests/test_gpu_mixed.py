@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2403_05463_amd import hdg, workloads as W
-from parity import TOL_F64
+from parity import TOL_F64, flat_errors, flat_fields, flat_mass
 
 pytestmark = pytest.mark.gpu
 
@@ -29,43 +29,12 @@ def ctx(torch_cuda):
     return hdg.hdg_init(0)
 
 
-def _node_tables(om):
-    """Per node: its element's first node and node count (flat layout)."""
-    n3 = (om.Ps.astype(np.int64) + 1) ** 3
-    return np.repeat(om.offsets.astype(np.int64), n3), np.repeat(n3, n3)
-
-
-def _fields(om, arr):
-    """Per-field flat vectors of an element-after-element array: node n of
-    element e, field f sits at 4 off_e + f n3_e + (n - off_e)."""
-    off, n3 = _node_tables(om)
-    n = np.arange(om.nodes, dtype=np.int64)
-    flat = np.asarray(arr).ravel()
-    return [flat[n + 3 * off + f * n3] for f in range(4)]
-
-
 def _mass(orc, om):
-    J, _ = om.metrics()
-    J = np.asarray(J).ravel()
-    out = np.empty(om.nodes)
-    off = om.offsets.astype(np.int64)
-    for P in np.unique(om.Ps):
-        _, w, _ = orc.lgl(int(P))
-        cube = np.einsum("k,j,i->kji", w, w, w).ravel()
-        sel = off[om.Ps == P]
-        idx = (sel[:, None] + np.arange(cube.size)[None]).ravel()
-        out[idx] = J[idx] * np.tile(cube, sel.size)
-    return out
+    return flat_mass(orc, om)
 
 
 def _errors(om, mass, got, ref):
-    """Per-field relative errors, floored as in the one-order parity tests."""
-    g, r = _fields(om, got), _fields(om, ref)
-    l2 = np.array([np.sqrt((mass * (a - b) ** 2).sum()) for a, b in zip(g, r)])
-    l2r = np.array([np.sqrt((mass * b ** 2).sum()) for b in r])
-    mx = np.array([np.abs(a - b).max() for a, b in zip(g, r)])
-    mxr = np.array([np.abs(b).max() for b in r])
-    return l2 / np.maximum(l2r, 1e-3 * l2r.max()), mx / np.maximum(mxr, 1e-3 * mxr.max())
+    return flat_errors(om, mass, got, ref)
 
 
 def _state(om, seed, amp=0.05):
@@ -144,9 +113,14 @@ def test_mixed_order_rk_parity(orc, torch_cuda, ctx):
     dq = torch.empty_like(qd)
     hdg.hdg_rk3_steps(m, qd, dq, 2e-3, 3)
     torch.cuda.synchronize()
-    err = np.abs(qd.cpu().numpy() - ref).max() / np.abs(ref).max()
+    out = qd.cpu().numpy()
+    err = np.abs(out - ref).max() / np.abs(ref).max()
     _say(f"state error {err:.3e}")
     assert err < 1e-13
+    # the increments q - q0 per field, at the one-order tests' bound
+    l2, mx = _errors(om, _mass(orc, om), out - q, ref - q)
+    _say(f"increment errors: per-field L2 {l2}, max {mx}")
+    assert max(l2.max(), mx.max()) <= TOL_F64
 
 
 def test_mixed_order_concurrent_phases_on_a_stream(orc, torch_cuda, ctx):
@@ -191,7 +165,7 @@ def test_mixed_order_conservation_freestream_and_shapes(orc, torch_cuda, ctx):
     hdg.hdg_residual(m, qd, r)
     red = hdg.hdg_reduce(m, r)
     R = r.cpu().numpy()
-    for f, Rf in enumerate(_fields(om, R)):
+    for f, Rf in enumerate(flat_fields(om, R)):
         mag = np.abs(mass * Rf).sum()
         assert abs((mass * Rf).sum()) < 1e-13 * mag, f
         assert abs(red["sum"][f] - (mass * Rf).sum()) < 1e-12 * mag

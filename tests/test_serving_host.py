@@ -103,7 +103,44 @@ def test_continuous_batching_refills_slots():
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
 
 
-def test_oversized_request_is_rejected():
+@pytest.mark.parametrize("realtime", [False, True])
+def test_oversized_request_is_refused_alone(realtime):
+    """A request larger than the whole budget is refused on its own; the
+    requests before and after it are served."""
+    reqs = S.make_requests(12, rate=500.0, seed=4, n_range=(3, 5), p_range=(1, 3), nsteps=5)
+    big = reqs[5]
+    big.n, big.P = 40, 7
+    budget = 4 * max(S.footprint_bytes(r.n, r.P) for r in reqs if r is not big)
+    assert S.footprint_bytes(big.n, big.P) > budget
+    be = FakeBackend(max_members=3)
+    st = S.serve(reqs, be, mem_budget=budget, max_members=3, max_steps_per_call=2, realtime=realtime)
+    assert [r.rid for r in st.refused] == [big.rid] and "budget" in big.refused
+    assert sorted(r.rid for r in st.requests) == sorted(r.rid for r in reqs if r is not big)
+    assert all(r.steps_done == r.nsteps and not r.refused for r in st.requests)
+    assert big.steps_done == 0 and big.rid not in {rid for _, m in be.calls for rid in m}
+    s = st.summary()
+    assert s["requests"] == 11 and s["refused"] == 1
+
+
+class FailingSetup(FakeBackend):
+    def setup(self, r):
+        if r.rid == 2:
+            raise RuntimeError("mesh rejected")
+        return super().setup(r)
+
+
+def test_failed_setup_is_refused_alone():
+    reqs = S.make_requests(8, rate=1e4, seed=6, n_range=(3, 4), p_range=(1, 2), nsteps=4)
+    budget = 2 * max(S.footprint_bytes(r.n, r.P) for r in reqs)
+    be = FailingSetup(max_members=2)
+    st = S.serve(reqs, be, mem_budget=budget, max_members=2, max_steps_per_call=2, realtime=False)
+    assert [r.rid for r in st.refused] == [2] and "mesh rejected" in st.refused[0].refused
+    assert len(st.requests) == 7 and all(r.steps_done == r.nsteps for r in st.requests)
+    assert st.peak_bytes <= budget
+
+
+def test_only_oversized_requests():
     r = S.make_requests(1, seed=0)[0]
-    with pytest.raises(ValueError):
-        S.serve([r], FakeBackend(1), mem_budget=1000, max_members=1)
+    st = S.serve([r], FakeBackend(1), mem_budget=1000, max_members=1)
+    assert st.requests == [] and st.refused == [r]
+    assert st.summary() == {"requests": 0, "refused": 1, "wall_s": st.wall_s}
