@@ -204,6 +204,25 @@ hdg_status hdg_mesh_set_graphs(hdg_mesh *mesh, int32_t enable);
 hdg_status hdg_reduce(hdg_mesh *mesh, const double *r_dev, double out_sum[4], double out_l2[4],
                       double out_max[4], void *stream);
 
+/* Allocation-free variant of hdg_reduce, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The same reductions of the device array r_dev
+ * (state layout) with the same kernels and workgroup count, so the results
+ * are bitwise those of hdg_reduce; the partial sums live in a fixed device
+ * array of the library (1024 workgroups x 13 doubles, 104 KiB per GPU, held
+ * until the process ends) and the results go to the caller's device buffer
+ * out_dev[13]: out_dev[f] = sum w_a w_b w_c J r_f, out_dev[4 + f] = the same
+ * of r_f^2 (the square of hdg_reduce's L2 norm), out_dev[8 + f] = max |r_f|,
+ * out_dev[12] = 1.0 if any entry is NaN or Inf, else 0.0 (f = p, u, v, w).
+ * Asynchronous on `stream`: no host wait, no allocation, no library routine
+ * that allocates.  The scratch array is shared by every call on one GPU, so
+ * calls that overlap on a GPU (concurrent streams, other threads) race; it
+ * needs no clearing (every partial a call reads, it has written).
+ * HDG_EINVAL on a NULL argument; HDG_EUNSUPPORTED if the mesh needed more
+ * partial sums than the array holds (not the case for any mesh hdg_mesh_create
+ * builds: it uses at most 1024 workgroups). */
+hdg_status hdg_reduce_noalloc(hdg_mesh *mesh, const double *r_dev, double *out_dev, void *stream);
+
 /* Kernel timing: while enabled, every launch the mesh makes is bracketed by
  * HIP events on its stream (up to 65536 launches are kept).  hdg_timing_read
  * synchronises on the last event, then returns the summed duration and count

@@ -413,9 +413,13 @@ hdg_status hdg_init(hdg_ctx **ctx, int32_t device)
     HDG_HIP(hipSetDevice(device));
     hipDeviceProp_t prop;
     HDG_HIP(hipGetDeviceProperties(&prop, device));
+    double *scr = nullptr;
+    const hipError_t es = hdg::scratch_address(device, &scr);
+    if (es != hipSuccess) return fail(HDG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(es));
     auto *c = new hdg_ctx();
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
+    c->scratch = scr;
     // derivative matrices of every supported order, FP64 and one FP32 rounding
     std::vector<double> d64(hdg::kDTableSize);
     for (int N = 2; N <= hdg::kMaxN; ++N) {
@@ -895,6 +899,25 @@ hdg_status hdg_reduce(hdg_mesh *m, const double *r, double out_sum[4], double ou
         if (out_max) out_max[f] = h[8 + f];
     }
     if (h[12] != 0.0) return fail(HDG_ENONFINITE, "non-finite value in reduced array");
+    return HDG_OK;
+}
+
+hdg_status hdg_reduce_noalloc(hdg_mesh *m, const double *r, double *out, void *stream)
+{
+    if (!m || !r || !out) return fail(HDG_EINVAL, "reduce_noalloc: NULL argument");
+    if (!m->ctx->scratch) return fail(HDG_EHIP, "reduce_noalloc: no scratch address on this device");
+    if (m->nblocks_reduce > hdg::kReduceScratchBlocks)
+        return fail(HDG_EUNSUPPORTED, "reduce_noalloc: the mesh needs " + std::to_string(m->nblocks_reduce) +
+                                          " partial sums per value, the scratch holds " +
+                                          std::to_string(hdg::kReduceScratchBlocks));
+    HDG_HIP(hipSetDevice(m->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    // the same kernels and workgroup count as hdg_reduce, with the partials in
+    // the device's scratch array and the 13 results in the caller's buffer
+    hipError_t e = m->mixed ? hdg::launch_reduce_mixed(r, m->mass, m->eoff, m->Ne_d, m->ne, m->ctx->scratch,
+                                                       m->nblocks_reduce, out, s)
+                            : hdg::launch_reduce(m->N, r, m->mass, m->ne, m->ctx->scratch, m->nblocks_reduce, out, s);
+    if (e != hipSuccess) return fail(HDG_EHIP, std::string("reduce launch: ") + hipGetErrorString(e));
     return HDG_OK;
 }
 

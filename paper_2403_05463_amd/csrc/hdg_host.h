@@ -24,6 +24,7 @@ struct hdg_ctx {
     float *I32 = nullptr;
     double *W64 = nullptr;     // GLL weights, at w_offset(N)
     float *W32 = nullptr;
+    double *scratch = nullptr; // this device's reduction scratch (kReduceScratchBlocks x 13 doubles)
 };
 
 namespace hdg {

@@ -227,6 +227,14 @@ hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_e
                          double *partials, int nblocks, double *final13, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s);
 
+// The allocation-free reduction keeps its partial sums in a device array of
+// fixed size (kReduceScratchBlocks workgroups x 13 values) in hdg_kernels.hip.
+// scratch_address gives its address on `device`, which must be current; the
+// first call per device looks it up, later calls return the kept address.
+constexpr int kReduceScratchBlocks = 1024;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_address(int device, double **ptr);
+
 // Host-side mesh geometry (hdg_setup.cpp), element after element: element e
 // has Ne[e] nodes per direction and starts at node off[e].
 struct HostGeometry {

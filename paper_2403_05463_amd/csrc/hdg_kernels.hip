@@ -32,7 +32,16 @@
 // run no gradient, LES or viscous-flux arithmetic at all.
 #include "hdg_internal.h"
 
+#include <mutex>
 #include <type_traits>
+
+// Scratch of the allocation-free reduction (hdg_reduce_noalloc): the
+// per-workgroup partial sums, kReduceScratchBlocks x 13 doubles (104 KiB).
+// Each GPU the library runs on holds one copy until the process ends.  Host
+// code never passes this name to a kernel (on the host it is a stand-in, not a
+// device address): it uses the address scratch_address() obtained with
+// hipGetSymbolAddress on that device.
+static __device__ __align__(256) double scratch[hdg::kReduceScratchBlocks * 13];
 
 namespace hdg {
 namespace {
@@ -1948,6 +1957,24 @@ hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_e
 #define C_(n) launch_reduce_n<n>(r, mass, n_elem, partials, nblocks, final13, s)
     HDG_DISPATCH_N(N, C_)
 #undef C_
+}
+
+hipError_t scratch_address(int device, double **ptr)
+{
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices || !ptr) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        // called with `device` current: each GPU holds its own copy of the
+        // array at its own address
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (double *)p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s)
