@@ -159,6 +159,15 @@ hdg_status hdg_mesh_set_params(hdg_mesh *mesh, const hdg_params *params);
 hdg_status hdg_mesh_info(const hdg_mesh *mesh, int64_t *n_nodes, int64_t *state_len,
                          int64_t *device_bytes, int32_t *n_viscous);
 
+/* Distinct metric blocks the kernels read.  Elements whose control points,
+ * relative to their first one, agree to 1e-12 of the element's size (and
+ * whose orders agree) are translates of one another with the same metric
+ * terms (App. B: J and Ja depend only on derivatives of the map); each reads
+ * the block of the first of them, and the processing order keeps such
+ * elements together.  An extruded mesh of k identical layers has n_elem / k
+ * blocks; a mesh without repeated elements has n_elem. */
+hdg_status hdg_mesh_metric_blocks(const hdg_mesh *mesh, int64_t *blocks);
+
 /* Physical coordinates of the collocation nodes, host array [n_elem][3][N^3]. */
 hdg_status hdg_mesh_node_coords(const hdg_mesh *mesh, double *xyz_host);
 

@@ -85,7 +85,7 @@ hdg_status dev_alloc(hdg_mesh *m, T **p, size_t count)
 
 void free_device(hdg_mesh *m)
 {
-    void *ptrs[] = {m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->partials,
+    void *ptrs[] = {m->mrep, m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->partials,
                     m->final13, m->conn, m->flag_d, m->metric32, m->fgeo32, m->eoff, m->foff, m->member,
                     m->Ne_d, m->mort, m->mslab, m->mgeo, m->mgeo32, m->mlist, m->gmm, m->gmm_partials,
                     m->gmm_flags};
@@ -614,7 +614,12 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         }
     }
     m->x = std::move(g.x);
-    m->order = hdg::locality_order(*d);
+    // translates share one metric block; the processing order keeps each
+    // group together
+    std::vector<int32_t> rep;
+    m->metric_blocks = hdg::metric_groups(*d, rep);
+    const bool share = m->metric_blocks < ne;
+    m->order = hdg::locality_order(*d, share ? &rep : nullptr);
     m->nblocks_reduce = (int)std::min<int64_t>(1024, (g.nodes + 255) / 256);
     m->nblocks_reduce = (int)std::min<int64_t>(m->nblocks_reduce, ne);
 
@@ -633,6 +638,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(dev_alloc(m, &m->partials, (size_t)m->nblocks_reduce * 13));
     chk(dev_alloc(m, &m->final13, 13));
     chk(dev_alloc(m, &m->conn, conn.size()));
+    if (share) chk(dev_alloc(m, &m->mrep, (size_t)ne));
     chk(dev_alloc(m, &m->flag_d, (size_t)ne));
     chk(dev_alloc(m, &m->member, 1));
     if (m->mixed) {
@@ -666,6 +672,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         chk(up(m->fgeo32, f32.data(), f32.size() * 4));
     }
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
+    if (share) chk(up(m->mrep, rep.data(), rep.size() * sizeof(int32_t)));
     m->conn_h = conn;
     if (m->mixed) {
         std::vector<int8_t> n8(Ne.begin(), Ne.end());
@@ -693,6 +700,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         mb.conn = m->conn;
         mb.flag = m->flag_d;
         mb.delta = m->delta;
+        mb.mrep = m->mrep;
         // one order: offsets are e N^3 and face N^2, no tables
         mb.eoff = m->mixed ? m->eoff : nullptr;
         mb.foff = m->mixed ? m->foff : nullptr;
@@ -758,6 +766,13 @@ hdg_status hdg_mesh_info(const hdg_mesh *m, int64_t *n_nodes, int64_t *state_len
     if (state_len) *state_len = 4 * m->nodes;
     if (device_bytes) *device_bytes = m->bytes;
     if (n_viscous) *n_viscous = m->n_visc;
+    return HDG_OK;
+}
+
+hdg_status hdg_mesh_metric_blocks(const hdg_mesh *m, int64_t *blocks)
+{
+    if (!m || !blocks) return fail(HDG_EINVAL, "NULL argument");
+    *blocks = m->metric_blocks;
     return HDG_OK;
 }
 

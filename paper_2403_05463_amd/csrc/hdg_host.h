@@ -248,6 +248,8 @@ struct hdg_mesh {
     hdg::FaceRef *conn = nullptr;
     std::vector<hdg::FaceRef> conn_h;              // host copy (neighbour-flag bits refreshed with the flags)
     uint8_t *flag_d = nullptr;
+    int32_t *mrep = nullptr;                       // metric block of each element (translates share), or NULL
+    int64_t metric_blocks = 0;                     // distinct metric blocks
     int64_t *eoff = nullptr, *foff = nullptr;     // element / face offsets (meshes of mixed order)
     int8_t *Ne_d = nullptr;                        // per-element N (meshes of mixed order)
     bool mixed = false;                            // elements of more than one order

@@ -115,6 +115,7 @@ struct Member {
     const FaceRef *conn;    // [e][6]
     const uint8_t *flag;    // [e]
     const double *delta;    // [e] LES filter width
+    const int32_t *mrep;    // [e] element whose metric block e reads (its translate), or NULL: its own
     const int64_t *eoff;    // [e] first node of the element; NULL: e N^3 (one order)
     const int64_t *foff;    // [face] first face node of the face; NULL: face N^2
     const MortarRef *mort;  // [mortar] faces between orders (NULL if none)
@@ -257,7 +258,16 @@ void gll_interp(int Plo, int Phi, std::vector<double> &I);
 // Interpolate geometry to the GLL nodes of each element's order and build
 // curl-form metric terms.  Returns false (with msg) on a non-positive Jacobian.
 bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg);
-// Spatially local processing order of the elements (recursive bisection of centroids).
-std::vector<int32_t> locality_order(const hdg_mesh_desc &d);
+// Spatially local processing order of the elements (recursive bisection of
+// centroids).  With rep (metric-sharing groups: rep[e] is the element whose
+// metric block e reads), the groups are ordered by the bisection of their
+// mean centroids and each group's elements follow one another, so that the
+// block is read from HBM once and then from the cache.
+std::vector<int32_t> locality_order(const hdg_mesh_desc &d, const std::vector<int32_t> *rep = nullptr);
+// Elements that are translates of one another (same order, control points
+// relative to the first one equal to 1e-12 of the element's size) share one
+// metric block: rep[e] is the first such element.  Returns the number of
+// distinct blocks.
+int64_t metric_groups(const hdg_mesh_desc &d, std::vector<int32_t> &rep);
 
 }  // namespace hdg

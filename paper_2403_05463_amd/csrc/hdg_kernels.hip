@@ -250,7 +250,9 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
         c.qr[f] = (T)ref;
         c.qt[f] = (T)(c.qd[f] - ref);
     }
-    const gmem<const T> *me = gp((const T *)M.metric[prec_index<T>()]) + 10 * c.eo;
+    // an element that is a translate of another reads that one's metric block
+    const int64_t mo = M.mrep ? elem_off<N>(M, gp(M.mrep)[c.e]) : c.eo;
+    const gmem<const T> *me = gp((const T *)M.metric[prec_index<T>()]) + 10 * mo;
     c.invJ = me[c.t];
 #pragma unroll
     for (int ii = 0; ii < 3; ++ii)
@@ -1002,14 +1004,8 @@ __global__ __launch_bounds__(B) void k_features(StageArgs A)
     HDG_ONE_TILE(A, tl) viscous_tile<N, EPT, double, true>(A, tl, smem);
 }
 
-// Waves per SIMD the compiler must keep resident (a register cap): the FP64
-// one-tile residual kernel of order 5 in 128-lane workgroups holds five
-// waves (at most 96 VGPRs, no spills); the rest are left to the compiler.
-template <class T, int N, int B, bool PERS>
-constexpr int residual_min_waves() { return (sizeof(T) == 8 && !PERS && N == 5 && B == 128) ? 5 : 1; }
-
 template <class T, int EPI, int N, int B, bool PERS>
-__global__ __launch_bounds__(B, (residual_min_waves<T, N, B, PERS>())) void k_residual(StageArgs A)
+__global__ __launch_bounds__(B) void k_residual(StageArgs A)
 {
     constexpr int EPT = tile_ept(N, B, kTileResidual);
     static_assert(EPT > 0, "tile does not fit the workgroup");

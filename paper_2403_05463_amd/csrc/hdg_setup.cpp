@@ -10,7 +10,9 @@
 #include <atomic>
 #include <cmath>
 #include <numeric>
+#include <string>
 #include <thread>
+#include <unordered_map>
 
 #include "hdg_internal.h"
 
@@ -275,7 +277,7 @@ void bisect(std::vector<int32_t> &ids, size_t lo, size_t hi, const std::vector<d
 
 }  // namespace
 
-std::vector<int32_t> locality_order(const hdg_mesh_desc &d)
+std::vector<int32_t> locality_order(const hdg_mesh_desc &d, const std::vector<int32_t> *rep)
 {
     const int G1 = d.geom_order + 1, G3 = G1 * G1 * G1;
     std::vector<double> cen(3 * (size_t)d.n_elem);
@@ -285,10 +287,85 @@ std::vector<int32_t> locality_order(const hdg_mesh_desc &d)
             for (int k = 0; k < G3; ++k) s += d.xyz_geom[(e * 3 + c) * G3 + k];
             cen[3 * e + c] = s / G3;
         }
-    std::vector<int32_t> ids(d.n_elem);
-    std::iota(ids.begin(), ids.end(), 0);
-    bisect(ids, 0, ids.size(), cen, 0);
+    if (!rep) {
+        std::vector<int32_t> ids(d.n_elem);
+        std::iota(ids.begin(), ids.end(), 0);
+        bisect(ids, 0, ids.size(), cen, 0);
+        return ids;
+    }
+    // groups in bisection order of their mean centroids, members in id order
+    std::vector<int32_t> gid(d.n_elem, -1), heads;
+    std::vector<std::vector<int32_t>> members;
+    for (int32_t e = 0; e < d.n_elem; ++e) {
+        const int32_t r = (*rep)[e];
+        if (gid[r] < 0) {
+            gid[r] = (int32_t)heads.size();
+            heads.push_back(r);
+            members.emplace_back();
+        }
+        members[gid[r]].push_back(e);
+    }
+    std::vector<double> gc(3 * heads.size(), 0.0);
+    for (size_t g = 0; g < heads.size(); ++g) {
+        for (int32_t e : members[g])
+            for (int c = 0; c < 3; ++c) gc[3 * g + c] += cen[3 * e + c];
+        for (int c = 0; c < 3; ++c) gc[3 * g + c] /= (double)members[g].size();
+    }
+    std::vector<int32_t> gids(heads.size());
+    std::iota(gids.begin(), gids.end(), 0);
+    bisect(gids, 0, gids.size(), gc, 0);
+    std::vector<int32_t> ids;
+    ids.reserve(d.n_elem);
+    for (int32_t g : gids)
+        for (int32_t e : members[g]) ids.push_back(e);
     return ids;
+}
+
+int64_t metric_groups(const hdg_mesh_desc &d, std::vector<int32_t> &rep)
+{
+    const int G1 = d.geom_order + 1, G3 = G1 * G1 * G1;
+    rep.resize(d.n_elem);
+    // key: the order and the relative control points rounded to 1e-10 of the
+    // element's size; a hit is confirmed to 1e-12 of that size
+    std::unordered_map<std::string, std::vector<int32_t>> buckets;
+    std::vector<double> rel(3 * G3);
+    std::string key;
+    int64_t groups = 0;
+    for (int32_t e = 0; e < d.n_elem; ++e) {
+        double size = 0.0;
+        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < G3; ++k) {
+                const double v = d.xyz_geom[((int64_t)e * 3 + c) * G3 + k] - d.xyz_geom[((int64_t)e * 3 + c) * G3];
+                rel[c * G3 + k] = v;
+                size = std::max(size, std::fabs(v));
+            }
+        key.assign((const char *)&d.P[e], sizeof(int32_t));
+        for (double v : rel) {
+            const int64_t q = (int64_t)std::llround(v / (1e-10 * size));
+            key.append((const char *)&q, sizeof q);
+        }
+        auto &cand = buckets[key];
+        int32_t found = -1;
+        for (int32_t r : cand) {
+            double dev = 0.0;
+            for (int c = 0; c < 3; ++c)
+                for (int k = 0; k < G3; ++k) {
+                    const double vr = d.xyz_geom[((int64_t)r * 3 + c) * G3 + k] - d.xyz_geom[((int64_t)r * 3 + c) * G3];
+                    dev = std::max(dev, std::fabs(vr - rel[c * G3 + k]));
+                }
+            if (dev <= 1e-12 * size) {
+                found = r;
+                break;
+            }
+        }
+        if (found < 0) {
+            cand.push_back(e);
+            found = e;
+            ++groups;
+        }
+        rep[e] = found;
+    }
+    return groups;
 }
 
 }  // namespace hdg

@@ -25,7 +25,7 @@ KERNEL_NAMES = {0: "viscous", 1: "residual", 2: "mortar"}
 
 EXPORTED = [
     "hdg_init", "hdg_finalize", "hdg_mesh_create", "hdg_mesh_destroy", "hdg_mesh_set_flags",
-    "hdg_mesh_set_params", "hdg_mesh_info", "hdg_mesh_node_coords", "hdg_mesh_geometry", "hdg_residual",
+    "hdg_mesh_set_params", "hdg_mesh_info", "hdg_mesh_metric_blocks", "hdg_mesh_node_coords", "hdg_mesh_geometry", "hdg_residual",
     "hdg_rk3_steps",
     "hdg_reduce", "hdg_reduce_noalloc", "hdg_timing_enable", "hdg_timing_read", "hdg_timing_samples", "hdg_stream_copy",
     "hdg_last_error",
@@ -90,6 +90,7 @@ def lib() -> C.CDLL:
         L.hdg_mesh_set_flags.argtypes = [vp, C.POINTER(C.c_uint8)]
         L.hdg_mesh_set_params.argtypes = [vp, C.POINTER(Params)]
         L.hdg_mesh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
+        L.hdg_mesh_metric_blocks.argtypes = [vp, C.POINTER(i64)]
         L.hdg_mesh_node_coords.argtypes = [vp, dp]
         L.hdg_mesh_geometry.argtypes = [C.POINTER(MeshDesc), dp, dp, dp, dp, dp, dp]
         L.hdg_residual.argtypes = [vp, vp, vp, i32, vp]
@@ -241,6 +242,12 @@ def hdg_mesh_set_flags(mesh: Mesh, flag):
 
 def hdg_mesh_set_params(mesh: Mesh, params: Params):
     _check(lib().hdg_mesh_set_params(mesh.handle, C.byref(params)), "hdg_mesh_set_params")
+
+
+def hdg_mesh_metric_blocks(mesh: Mesh) -> int:
+    n = C.c_int64()
+    _check(lib().hdg_mesh_metric_blocks(mesh.handle, C.byref(n)), "hdg_mesh_metric_blocks")
+    return n.value
 
 
 def hdg_mesh_info(mesh: Mesh) -> dict:
