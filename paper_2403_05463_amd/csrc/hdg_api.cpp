@@ -85,7 +85,7 @@ hdg_status dev_alloc(hdg_mesh *m, T **p, size_t count)
 
 void free_device(hdg_mesh *m)
 {
-    void *ptrs[] = {m->mrep, m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->partials,
+    void *ptrs[] = {m->moff, m->metric, m->fgeo, m->fvt, m->wvis, m->qpp, m->mass, m->delta, m->partials,
                     m->final13, m->conn, m->flag_d, m->metric32, m->fgeo32, m->eoff, m->foff, m->member,
                     m->Ne_d, m->mort, m->mslab, m->mgeo, m->mgeo32, m->mlist, m->gmm, m->gmm_partials,
                     m->gmm_flags};
@@ -103,6 +103,16 @@ void free_device(hdg_mesh *m)
         }
         v.clear();
     }
+    for (auto &pl : m->plans_indep) {
+        if (pl.tiles) (void)hipFree(pl.tiles);
+        if (pl.elems) (void)hipFree(pl.elems);
+    }
+    m->plans_indep.clear();
+    if (m->indep_stream) (void)hipStreamDestroy(m->indep_stream);
+    if (m->indep_fork) (void)hipEventDestroy(m->indep_fork);
+    if (m->indep_join) (void)hipEventDestroy(m->indep_join);
+    m->indep_stream = nullptr;
+    m->indep_fork = m->indep_join = nullptr;
     for (hipEvent_t e : m->ev) (void)hipEventDestroy(e);
     m->ev.clear();
     if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
@@ -163,15 +173,32 @@ hdg_status upload_plans(hdg_mesh *m)
     }
     const std::vector<int> &Ne = m->Ne;
     std::vector<int> cls(m->ne);
-    for (auto &v : m->plans) {
-        for (auto &pl : v) {
+    for (auto *v : {&m->plans[0], &m->plans[1], &m->plans_indep}) {
+        for (auto &pl : *v) {
             if (pl.tiles) (void)hipFree(pl.tiles);
             if (pl.elems) (void)hipFree(pl.elems);
         }
-        v.clear();
+        v->clear();
     }
-    for (int kind = 0; kind < 2; ++kind) {
-        for (int64_t e = 0; e < m->ne; ++e) cls[e] = kind == hdg::kTileViscous ? (m->flag[e] ? 1 : -1) : m->flag[e];
+    // Euler elements whose face neighbours are all Euler (one-order meshes
+    // with flagged elements): their residual reads no viscous trace
+    std::vector<uint8_t> indep(m->ne, 0);
+    if (!m->mixed && m->n_visc > 0 && m->n_visc < m->ne)
+        for (int64_t e = 0; e < m->ne; ++e) {
+            bool ok = !m->flag[e];
+            for (int f = 0; f < 6 && ok; ++f) {
+                const int32_t nb = m->conn_h[e * 6 + f].nbr;
+                ok = nb < 0 || !m->flag[nb];
+            }
+            indep[e] = ok ? 1 : 0;
+        }
+    for (int kind = 0; kind < 3; ++kind) {
+        std::vector<hdg::TilePlan> &dst = kind == 2 ? m->plans_indep : m->plans[kind];
+        for (int64_t e = 0; e < m->ne; ++e)
+            cls[e] = kind == hdg::kTileViscous ? (m->flag[e] ? 1 : -1)
+                     : kind == 1           ? (indep[e] ? -1 : m->flag[e])
+                                           : (indep[e] ? 0 : -1);
+        const int tkind = kind == hdg::kTileViscous ? hdg::kTileViscous : hdg::kTileResidual;
         for (int N = 2; N <= hdg::kMaxN; ++N) {
             std::vector<int> cn(m->ne);
             bool any = false;
@@ -184,7 +211,7 @@ hdg_status upload_plans(hdg_mesh *m)
                 if (!hdg::shape_supported(N, B)) continue;
                 std::vector<Tile> tiles;
                 std::vector<int32_t> elems;
-                hdg::cut_tiles(m->order, Ne, cn, 0, B, kind, tiles, elems);
+                hdg::cut_tiles(m->order, Ne, cn, 0, B, tkind, tiles, elems);
                 TilePlan pl;
                 pl.N = N;
                 pl.B = B;
@@ -194,7 +221,7 @@ hdg_status upload_plans(hdg_mesh *m)
                 HDG_HIP(hipMalloc((void **)&pl.elems, elems.size() * sizeof(int32_t)));
                 HDG_HIP(hipMemcpy(pl.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
                 HDG_HIP(hipMemcpy(pl.elems, elems.data(), elems.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-                m->plans[kind].push_back(pl);
+                dst.push_back(pl);
             }
         }
     }
@@ -280,9 +307,16 @@ StageArgs stage_args(const hdg_mesh *m, const TilePlan &pl)
 
 // One launch of kernel `kind` over the order-N tiles with configuration cf.
 hdg_status launch_one(hdg_mesh *m, int kind, int N, const LaunchCfg &cf, const double *q, void *out, double *dq,
-                      Epi epi, bool f32, double A, double B, double dt, int stage, hipStream_t s, bool time_it)
+                      Epi epi, bool f32, double A, double B, double dt, int stage, hipStream_t s, bool time_it,
+                      bool indep = false)
 {
-    const TilePlan *pl = find_plan(m, kind, N, cf.B);
+    const TilePlan *pl = nullptr;
+    if (indep) {
+        for (const auto &p : m->plans_indep)
+            if (p.N == N && p.B == cf.B) pl = &p;
+    } else {
+        pl = find_plan(m, kind, N, cf.B);
+    }
     if (!pl) return HDG_OK;
     StageArgs a = stage_args(m, *pl);
     a.q_in = q;
@@ -315,6 +349,20 @@ hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi ep
 {
     const int pi = f32 ? 1 : 0;
     hdg::Phase ph(m->ss, s, !m->timing);
+    // residual tiles that read nothing the viscous kernel writes run on their
+    // own stream alongside the viscous kernel and the other residual tiles
+    // (a parallel branch of a captured graph); serial while kernel timing is on
+    const bool split = !m->plans_indep.empty();
+    hipStream_t is = split && !m->timing ? m->indep_stream : s;
+    if (split) {
+        if (is != s) {
+            HDG_HIP(hipEventRecord(m->indep_fork, s));
+            HDG_HIP(hipStreamWaitEvent(is, m->indep_fork, 0));
+        }
+        for (int N = 2; N <= hdg::kMaxN; ++N)
+            HDG_TRY(launch_one(m, 1, N, m->cfg[1][pi][N], q, out, dq, epi, f32, A, B, dt, stage, is, true, true));
+        if (is != s) HDG_HIP(hipEventRecord(m->indep_join, is));
+    }
     for (int kind = 0; kind < 2; ++kind) {
         // mortars: BR1 lift terms (kind 0) before the viscous kernels, numerical
         // fluxes (kind 1) after them and before the residual kernels
@@ -349,6 +397,7 @@ hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi ep
         }
         HDG_TRY(ph.end());
     }
+    if (is != s) HDG_HIP(hipStreamWaitEvent(s, m->indep_join, 0));
     return HDG_OK;
 }
 
@@ -483,11 +532,17 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     const int64_t ne = d->n_elem;
     HDG_HIP(hipSetDevice(ctx->device));
 
+    // translates share one metric block: group them first, so that set-up
+    // computes each block once
+    std::vector<int32_t> rep;
+    const int64_t nblocks = hdg::metric_groups(*d, rep);
+    const bool share = nblocks < ne;
     hdg::HostGeometry g;
     std::string msg;
-    if (!hdg::build_geometry(*d, g, msg)) return fail(HDG_EMESH, msg);
+    if (!hdg::build_geometry(*d, g, msg, share ? &rep : nullptr)) return fail(HDG_EMESH, msg);
 
     auto *m = new hdg_mesh();
+    m->metric_blocks = nblocks;
     m->ctx = ctx;
     m->ne = ne;
     m->Ne = g.Ne;
@@ -601,24 +656,38 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
                 for (int a = 0; a < N; ++a)
                     put_normal(&fgeo[(foff[r.face] + a + N * b) * 4], e, f, face_node(N, f, a, b));
         }
-    std::vector<double> metric(g.nodes * 10), mass(g.nodes);
+    // metric blocks: one per group of translates, [block][10][N^3]; moff[e] is
+    // the first node of the block element e reads
+    std::vector<int64_t> moff;
+    int64_t mnodes = g.nodes;
+    if (share) {
+        moff.assign(ne, -1);
+        mnodes = 0;
+        for (int64_t e = 0; e < ne; ++e)
+            if (rep[e] == e) {
+                moff[e] = mnodes;
+                mnodes += (int64_t)Ne[e] * Ne[e] * Ne[e];
+            }
+        for (int64_t e = 0; e < ne; ++e) moff[e] = moff[rep[e]];
+    }
+    std::vector<double> metric(mnodes * 10), mass(g.nodes);
     for (int64_t e = 0; e < ne; ++e) {
         const int N = Ne[e], N3 = N * N * N;
         const std::vector<double> &w = g.ws[N];
+        const bool first = !share || rep[e] == e;
+        const int64_t mo = share ? moff[e] : off[e];
         for (int n = 0; n < N3; ++n) {
             const double J = g.J[off[e] + n];
-            metric[10 * off[e] + n] = 1.0 / J;
-            for (int k = 0; k < 9; ++k) metric[10 * off[e] + (int64_t)(1 + k) * N3 + n] = g.Ja[9 * off[e] + (int64_t)k * N3 + n];
+            if (first) {
+                metric[10 * mo + n] = 1.0 / J;
+                for (int k = 0; k < 9; ++k) metric[10 * mo + (int64_t)(1 + k) * N3 + n] = g.Ja[9 * off[e] + (int64_t)k * N3 + n];
+            }
             const int a = n % N, b = (n / N) % N, c = n / (N * N);
             mass[off[e] + n] = w[a] * w[b] * w[c] * J;
         }
     }
     m->x = std::move(g.x);
-    // translates share one metric block; the processing order keeps each
-    // group together
-    std::vector<int32_t> rep;
-    m->metric_blocks = hdg::metric_groups(*d, rep);
-    const bool share = m->metric_blocks < ne;
+    // the processing order keeps each group of translates together
     m->order = hdg::locality_order(*d, share ? &rep : nullptr);
     m->nblocks_reduce = (int)std::min<int64_t>(1024, (g.nodes + 255) / 256);
     m->nblocks_reduce = (int)std::min<int64_t>(m->nblocks_reduce, ne);
@@ -638,7 +707,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(dev_alloc(m, &m->partials, (size_t)m->nblocks_reduce * 13));
     chk(dev_alloc(m, &m->final13, 13));
     chk(dev_alloc(m, &m->conn, conn.size()));
-    if (share) chk(dev_alloc(m, &m->mrep, (size_t)ne));
+    if (share) chk(dev_alloc(m, &m->moff, (size_t)ne));
     chk(dev_alloc(m, &m->flag_d, (size_t)ne));
     chk(dev_alloc(m, &m->member, 1));
     if (m->mixed) {
@@ -672,7 +741,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         chk(up(m->fgeo32, f32.data(), f32.size() * 4));
     }
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
-    if (share) chk(up(m->mrep, rep.data(), rep.size() * sizeof(int32_t)));
+    if (share) chk(up(m->moff, moff.data(), moff.size() * sizeof(int64_t)));
     m->conn_h = conn;
     if (m->mixed) {
         std::vector<int8_t> n8(Ne.begin(), Ne.end());
@@ -700,7 +769,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         mb.conn = m->conn;
         mb.flag = m->flag_d;
         mb.delta = m->delta;
-        mb.mrep = m->mrep;
+        mb.moff = m->moff;
         // one order: offsets are e N^3 and face N^2, no tables
         mb.eoff = m->mixed ? m->eoff : nullptr;
         mb.foff = m->mixed ? m->foff : nullptr;
@@ -715,6 +784,14 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     // orders has launches for; made here, never under a caller's capture, and
     // under the library mutex taken above for the uploads
     if (s2 == HDG_OK && m->mixed) s2 = m->ss.create();
+    // the stream of the residual tiles that run alongside the viscous kernel
+    if (s2 == HDG_OK && !m->mixed) {
+        hipError_t e1 = hipStreamCreateWithFlags(&m->indep_stream, hipStreamNonBlocking);
+        hipError_t e2 = hipEventCreateWithFlags(&m->indep_fork, hipEventDisableTiming);
+        hipError_t e3 = hipEventCreateWithFlags(&m->indep_join, hipEventDisableTiming);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+            s2 = fail(HDG_EHIP, "stream or event creation for the independent residual tiles failed");
+    }
     if (s2 != HDG_OK) {
         free_device(m);
         delete m;

@@ -248,7 +248,8 @@ struct hdg_mesh {
     hdg::FaceRef *conn = nullptr;
     std::vector<hdg::FaceRef> conn_h;              // host copy (neighbour-flag bits refreshed with the flags)
     uint8_t *flag_d = nullptr;
-    int32_t *mrep = nullptr;                       // metric block of each element (translates share), or NULL
+    int64_t *moff = nullptr;                       // first node of each element's metric block (translates
+                                                   // share one), or NULL: blocks in element order
     int64_t metric_blocks = 0;                     // distinct metric blocks
     int64_t *eoff = nullptr, *foff = nullptr;     // element / face offsets (meshes of mixed order)
     int8_t *Ne_d = nullptr;                        // per-element N (meshes of mixed order)
@@ -265,8 +266,14 @@ struct hdg_mesh {
     int64_t mlist_off[2][hdg::kPairKeys + 1] = {}; // [kind][pair_key] start in mlist (kind 0 lift, 1 flux)
     hdg::Member *member = nullptr;              // the mesh's member record (device)
     hdg::Member host_member{};
-    // tile plans per kernel kind, for every (order, workgroup size) pair
+    // tile plans per kernel kind, for every (order, workgroup size) pair;
+    // on a one-order mesh with flagged elements, the residual tiles of Euler
+    // elements none of whose neighbours is flagged sit apart: they read nothing
+    // the viscous kernel writes, so they run alongside it
     std::vector<hdg::TilePlan> plans[2];
+    std::vector<hdg::TilePlan> plans_indep;
+    hipStream_t indep_stream = nullptr;            // their stream (made at creation)
+    hipEvent_t indep_fork = nullptr, indep_join = nullptr;
     // clustering, made on first use: feature tile plans over every element
     // (one per order) and the mixture's device state and scratch
     std::vector<hdg::TilePlan> feat_plans;

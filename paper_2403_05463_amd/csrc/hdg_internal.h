@@ -115,7 +115,8 @@ struct Member {
     const FaceRef *conn;    // [e][6]
     const uint8_t *flag;    // [e]
     const double *delta;    // [e] LES filter width
-    const int32_t *mrep;    // [e] element whose metric block e reads (its translate), or NULL: its own
+    const int64_t *moff;    // [e] first node of the metric block e reads (translates share one), or
+                            // NULL: e's own, at its first node
     const int64_t *eoff;    // [e] first node of the element; NULL: e N^3 (one order)
     const int64_t *foff;    // [face] first face node of the face; NULL: face N^2
     const MortarRef *mort;  // [mortar] faces between orders (NULL if none)
@@ -257,7 +258,11 @@ void gll_rule(int P, std::vector<double> &xi, std::vector<double> &w, std::vecto
 void gll_interp(int Plo, int Phi, std::vector<double> &I);
 // Interpolate geometry to the GLL nodes of each element's order and build
 // curl-form metric terms.  Returns false (with msg) on a non-positive Jacobian.
-bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg);
+// With rep (metric_groups), an element other than its group's first copies
+// that one's J, Ja and filter width instead of computing them; its node
+// coordinates are its own.
+bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg,
+                    const std::vector<int32_t> *rep = nullptr);
 // Spatially local processing order of the elements (recursive bisection of
 // centroids).  With rep (metric-sharing groups: rep[e] is the element whose
 // metric block e reads), the groups are ordered by the bisection of their

@@ -250,8 +250,8 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
         c.qr[f] = (T)ref;
         c.qt[f] = (T)(c.qd[f] - ref);
     }
-    // an element that is a translate of another reads that one's metric block
-    const int64_t mo = M.mrep ? elem_off<N>(M, gp(M.mrep)[c.e]) : c.eo;
+    // translates of one element share its metric block
+    const int64_t mo = M.moff ? gp(M.moff)[c.e] : c.eo;
     const gmem<const T> *me = gp((const T *)M.metric[prec_index<T>()]) + 10 * mo;
     c.invJ = me[c.t];
 #pragma unroll

@@ -152,7 +152,7 @@ void gll_interp(int Plo, int Phi, std::vector<double> &I)
     I.assign(Ix.begin(), Ix.end());
 }
 
-bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg)
+bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, const std::vector<int32_t> *rep)
 {
     const int Pg = d.geom_order, G1 = Pg + 1, G3 = G1 * G1 * G1;
     const int64_t ne = d.n_elem;
@@ -208,6 +208,8 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg)
             apply_dir(I, N, G1, 2, t2.data(), N, N, G1, &loc[c * N3]);
             for (int n = 0; n < N3; ++n) g.x[3 * o + c * N3 + n] = (double)((xreal)Xe[c * G3] + loc[c * N3 + n]);
         }
+        // a translate of an earlier element takes its metric terms (second pass)
+        if (rep && (*rep)[e] != e) return;
         for (int c = 0; c < 3; ++c)
             for (int k = 0; k < 3; ++k) apply_dir(Dq, N, N, k, &loc[c * N3], N, N, N, &dX[(c * 3 + k) * N3]);
         xreal vol = 0.0L;
@@ -245,6 +247,22 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg)
             for (int64_t e = t; e < ne; e += nt) body(e);
         });
     for (auto &th : pool) th.join();
+    if (rep) {
+        std::vector<std::thread> pool2;
+        for (int t = 0; t < nt; ++t)
+            pool2.emplace_back([&, t] {
+                for (int64_t e = t; e < ne; e += nt) {
+                    const int64_t r = (*rep)[e];
+                    if (r == e) continue;
+                    const int64_t N3 = (int64_t)g.Ne[e] * g.Ne[e] * g.Ne[e];
+                    std::copy(g.J.begin() + g.off[r], g.J.begin() + g.off[r] + N3, g.J.begin() + g.off[e]);
+                    std::copy(g.Ja.begin() + 9 * g.off[r], g.Ja.begin() + 9 * (g.off[r] + N3),
+                              g.Ja.begin() + 9 * g.off[e]);
+                    g.delta[e] = g.delta[r];
+                }
+            });
+        for (auto &th : pool2) th.join();
+    }
     if (bad.load() >= 0) {
         msg = "non-positive Jacobian in element " + std::to_string(bad.load());
         return false;

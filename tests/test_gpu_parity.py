@@ -324,7 +324,9 @@ def test_timing_and_copy_probe(torch_cuda, ctx):
     hdg.hdg_rk3_steps(m, q, dq, 1e-7, 2)
     for k in (hdg.HDG_KERNEL_VISCOUS, hdg.HDG_KERNEL_RESIDUAL):
         ms, n = hdg.hdg_timing_read(m, k)
-        assert n == 6 and ms > 0
+        # one viscous launch per stage; the residual tiles of Euler elements
+        # with no flagged neighbour are a launch of their own
+        assert (n == 6 if k == hdg.HDG_KERNEL_VISCOUS else n == 12) and ms > 0
         us = hdg.hdg_timing_samples(m, k)                           # the same launches, one by one
         assert len(us) == n and min(us) > 0
         assert abs(sum(us) / 1e3 - ms) <= 1e-3 * ms
