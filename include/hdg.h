@@ -257,14 +257,19 @@ hdg_status hdg_timing_samples(hdg_mesh *mesh, int32_t kernel_class, float *us, i
 typedef struct {
     int32_t block;
     int32_t persistent;
-    double us_per_launch;   /* measured by hdg_mesh_autotune, else 0 */
+    double us_per_launch;   /* the autotuner's timing with this choice: a whole fused RK stage
+                               (hdg_mesh_autotune) or this kernel's launch (hdg_batch_autotune);
+                               0 when not tuned */
 } hdg_launch_cfg;
 
-/* Autotuner: for each precision, kernel class and order present, times every
- * supported (block, persistent) pair on this mesh with reps launches of a
- * fused RK stage reading q_dev (device state, not modified) and keeps the
- * fastest.  Allocates a scratch register for the duration of the call and
- * writes the mesh's internal ping-pong state; synchronises the stream.
+/* Autotuner: for each precision, kernel class and order present (residual
+ * kernels first, then viscous ones), times every supported (block,
+ * persistent) pair on this mesh with reps whole fused RK stages reading q_dev
+ * (device state, not modified), launched as the RK driver launches them
+ * (every launch of the stage, with its concurrent branches), and keeps the
+ * fastest.  Allocates a scratch register for the duration of the call,
+ * writes the mesh's internal ping-pong state, drops any captured graph and
+ * synchronises the stream.
  * Default without tuning: the smallest block that fits an element, one
  * workgroup per tile. */
 hdg_status hdg_mesh_autotune(hdg_mesh *mesh, const double *q_dev, int32_t reps, void *stream);

@@ -1081,10 +1081,13 @@ hdg_status hdg_mesh_autotune(hdg_mesh *m, const double *q, int32_t reps, void *s
     const bool was_timing = m->timing;
     m->timing = false;
     drop_graph(m);
-    // an RK stage as the RK driver runs it; the next state goes to the
-    // internal ping-pong buffer, which a later step overwrites
+    // a whole RK stage as the RK driver runs it (every launch, with the
+    // concurrent branches), so that each choice is timed in the company it
+    // keeps; the next state goes to the internal ping-pong buffer, which a
+    // later step overwrites.  Residual kernels first, then viscous ones.
     for (int pi = 0; pi < 2 && st == HDG_OK; ++pi)
-        for (int kind = 0; kind < 2 && st == HDG_OK; ++kind)
+        for (int kind : {1, 0}) {
+            if (st != HDG_OK) break;
             for (int N = 2; N <= hdg::kMaxN && st == HDG_OK; ++N) {
                 LaunchCfg best;
                 best.us = -1.0;
@@ -1094,9 +1097,9 @@ hdg_status hdg_mesh_autotune(hdg_mesh *m, const double *q, int32_t reps, void *s
                         LaunchCfg cf;
                         cf.B = B;
                         cf.persistent = pers != 0;
+                        m->cfg[kind][pi][N] = cf;
                         auto once = [&] {
-                            return launch_one(m, kind, N, cf, q, m->qpp, dq, Epi::RkStage, pi == 1, -0.5, 0.5, 1e-9,
-                                              1, s, false);
+                            return run_stage(m, q, m->qpp, dq, Epi::RkStage, pi == 1, -0.5, 0.5, 1e-9, 1, s);
                         };
                         st = once();
                         if (st != HDG_OK) break;
@@ -1113,8 +1116,9 @@ hdg_status hdg_mesh_autotune(hdg_mesh *m, const double *q, int32_t reps, void *s
                         if (best.us < 0.0 || cf.us < best.us) best = cf;
                     }
                 }
-                if (st == HDG_OK && best.us >= 0.0) m->cfg[kind][pi][N] = best;
+                if (best.us >= 0.0) m->cfg[kind][pi][N] = best;
             }
+        }
     m->timing = was_timing;
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(e0);

@@ -207,9 +207,12 @@ struct TileFaces {
 
 // With STAGE_Q the own state is also staged in LDS, FP64 [4][EPT N^3] at
 // the start of smem, for face tasks to read instead of gathering it again.
+// With sjf, each face node's Ja^dir is staged there too, [3][EPT 6 N^2] in
+// face-task order, for the face tasks' normals.
 template <int N, int EPT, class T, bool STAGE_Q = false>
 __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, const Tile &tl, T *sD,
-                                          TileFaces<EPT> &tf, TileCtx<N, T> &c, double *sq = nullptr)
+                                          TileFaces<EPT> &tf, TileCtx<N, T> &c, double *sq = nullptr,
+                                          T *sjf = nullptr)
 {
     constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3, NL = tile_lanes(N);
     c.tid = threadIdx.x;
@@ -269,6 +272,19 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
         if (c.act) {
 #pragma unroll
             for (int f = 0; f < 4; ++f) sq[f * (EPT * N3) + c.g] = c.qd[f];
+        }
+    }
+    if (sjf && c.act) {
+        constexpr int NTASK = EPT * 6 * N2;
+#pragma unroll
+        for (int dir = 0; dir < 3; ++dir) {
+            const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
+            if (idx == 0 || idx == N - 1) {
+                const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
+                const int task = c.s * 6 * N2 + f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) sjf[d * NTASK + task] = c.Ja[dir][d];
+            }
         }
     }
     __syncthreads();
@@ -807,26 +823,10 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     // saves, and the trace is gathered from global memory after the fluxes.
     constexpr bool STAGE = N <= 5;
     double *sq = (double *)smem;      // [4][NN] own state, FP64, until the fluxes replace it
-    load_tile<N, EPT, T, STAGE>(A, M, tl, sD, tf, c, sq);
+    // the face nodes' Ja^dir are staged with the rest, behind the same barrier
+    load_tile<N, EPT, T, STAGE>(A, M, tl, sD, tf, c, sq, FACE_JA ? sjf : nullptr);
     const bool visc = tl.flag != 0;   // a tile's elements share one equation flag
     const FaceData<T> fd = face_data<T>(M);
-
-    if constexpr (FACE_JA) {
-        // each face node's Ja^dir, for the face tasks' normals
-        if (c.act) {
-#pragma unroll
-            for (int dir = 0; dir < 3; ++dir) {
-                const int idx = dir == 0 ? c.i : dir == 1 ? c.j : c.k;
-                if (idx == 0 || idx == N - 1) {
-                    const int f = 2 * dir + (idx == N - 1 ? 1 : 0);
-                    const int task = c.s * NFT + f * N2 + (dir == 0 ? c.j : c.i) + N * (dir == 2 ? c.j : c.k);
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) sjf[d * NTASK + task] = c.Ja[dir][d];
-                }
-            }
-        }
-        __syncthreads();
-    }
     if constexpr (STAGE) {
         // face-node tasks, spread evenly over the workgroup; a tile's elements
         // share one equation class
