@@ -94,18 +94,21 @@ void free_device(hdg_mesh *m)
     for (auto &pl : m->feat_plans) {
         if (pl.tiles) (void)hipFree(pl.tiles);
         if (pl.elems) (void)hipFree(pl.elems);
+        if (pl.emo) (void)hipFree(pl.emo);
     }
     m->feat_plans.clear();
     for (auto &v : m->plans) {
         for (auto &pl : v) {
             if (pl.tiles) (void)hipFree(pl.tiles);
             if (pl.elems) (void)hipFree(pl.elems);
+            if (pl.emo) (void)hipFree(pl.emo);
         }
         v.clear();
     }
     for (auto &pl : m->plans_indep) {
         if (pl.tiles) (void)hipFree(pl.tiles);
         if (pl.elems) (void)hipFree(pl.elems);
+        if (pl.emo) (void)hipFree(pl.emo);
     }
     m->plans_indep.clear();
     if (m->indep_stream) (void)hipStreamDestroy(m->indep_stream);
@@ -177,6 +180,7 @@ hdg_status upload_plans(hdg_mesh *m)
         for (auto &pl : *v) {
             if (pl.tiles) (void)hipFree(pl.tiles);
             if (pl.elems) (void)hipFree(pl.elems);
+            if (pl.emo) (void)hipFree(pl.emo);
         }
         v->clear();
     }
@@ -221,6 +225,14 @@ hdg_status upload_plans(hdg_mesh *m)
                 HDG_HIP(hipMalloc((void **)&pl.elems, elems.size() * sizeof(int32_t)));
                 HDG_HIP(hipMemcpy(pl.tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
                 HDG_HIP(hipMemcpy(pl.elems, elems.data(), elems.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+                if (!m->moff_h.empty()) {
+                    // the metric block of each entry next to its element id: the
+                    // kernels' metric loads then wait for one load fewer
+                    std::vector<int64_t> emo(elems.size());
+                    for (size_t k = 0; k < elems.size(); ++k) emo[k] = m->moff_h[elems[k]];
+                    HDG_HIP(hipMalloc((void **)&pl.emo, emo.size() * sizeof(int64_t)));
+                    HDG_HIP(hipMemcpy(pl.emo, emo.data(), emo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+                }
                 dst.push_back(pl);
             }
         }
@@ -294,6 +306,7 @@ StageArgs stage_args(const hdg_mesh *m, const TilePlan &pl)
     a.mem = m->member;
     a.tiles = pl.tiles;
     a.elems = pl.elems;
+    a.emo = pl.emo;
     a.ntiles = pl.ntiles;
     a.chunk = pl.chunk;
     a.D64 = m->ctx->D64;
@@ -742,6 +755,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     }
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
     if (share) chk(up(m->moff, moff.data(), moff.size() * sizeof(int64_t)));
+    if (share) m->moff_h = moff;
     m->conn_h = conn;
     if (m->mixed) {
         std::vector<int8_t> n8(Ne.begin(), Ne.end());

@@ -49,6 +49,7 @@ struct TilePlan {
     int32_t ntiles = 0, chunk = 0;
     Tile *tiles = nullptr;
     int32_t *elems = nullptr;
+    int64_t *emo = nullptr;          // metric block of each entry of elems (meshes whose translates share one)
     // batches: device capacity (items) and the host copy of the last upload
     int64_t tiles_cap = 0, elems_cap = 0;
     std::vector<Tile> h_tiles;
@@ -247,6 +248,7 @@ struct hdg_mesh {
     float *metric32 = nullptr, *fgeo32 = nullptr;
     hdg::FaceRef *conn = nullptr;
     std::vector<hdg::FaceRef> conn_h;              // host copy (neighbour-flag bits refreshed with the flags)
+    std::vector<int64_t> moff_h;                   // host copy of moff (meshes with shared metric blocks)
     uint8_t *flag_d = nullptr;
     int64_t *moff = nullptr;                       // first node of each element's metric block (translates
                                                    // share one), or NULL: blocks in element order

@@ -136,6 +136,8 @@ struct StageArgs {
     const Member *mem;
     const Tile *tiles;
     const int32_t *elems;   // member-local element ids, grouped by tile
+    const int64_t *emo;     // per entry of elems: first node of the element's metric block (shared by its
+                            // translates), or NULL: the member's own offsets
     int32_t ntiles;
     int32_t chunk;          // tiles per XCD chunk; the grid is a multiple of kXcd
     const double *D64;      // derivative matrices for N = 2..8, packed at d_offset(N)

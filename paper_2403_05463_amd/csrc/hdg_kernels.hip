@@ -253,8 +253,9 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
         c.qr[f] = (T)ref;
         c.qt[f] = (T)(c.qd[f] - ref);
     }
-    // translates of one element share its metric block
-    const int64_t mo = M.moff ? gp(M.moff)[c.e] : c.eo;
+    // translates of one element share its metric block; the tile plan holds
+    // the block of each entry beside its element id (one dependent load fewer)
+    const int64_t mo = A.emo ? A.emo[tl.first + c.s] : M.moff ? gp(M.moff)[c.e] : c.eo;
     const gmem<const T> *me = gp((const T *)M.metric[prec_index<T>()]) + 10 * mo;
     c.invJ = me[c.t];
 #pragma unroll
@@ -654,36 +655,58 @@ __device__ __forceinline__ FaceData<T> face_data(const Member &M)
     return d;
 }
 
+// The other side's trace at a face node of element e, in FP64: the
+// neighbour's node (its face frame mapped by the orientation code), the wall
+// ghost (p, -u) or the far-field state.  The load is issued for every lane,
+// at this element's own node where there is no conforming neighbour (a
+// boundary or a mortar face), so that callers may gather several tasks'
+// traces before using any of them.
+template <int N, class T>
+__device__ __forceinline__ void face_other(const FaceData<T> &M, const gmem<const double> *qin,
+                                           const gmem<const double> *qself, int fa, int fb, const FaceRef &fr,
+                                           double (&qo)[4])
+{
+    constexpr int N3 = Shape<N>::N3;
+    const gmem<const double> *qn = qself;
+    if (fr.nbr >= 0 && !(fr.code & kMortarBit)) {
+        int a2, b2;
+        orient_map<N>(fr.code & 7, fa, fb, a2, b2);
+        qn = qin + 4 * (M.eoff ? gp(M.eoff)[fr.nbr] : (int64_t)fr.nbr * N3) + face_node<N>((fr.code >> 3) & 7, a2, b2);
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) qo[x] = qn[x * N3];
+}
+
+// Boundary ghosts replace the gathered value where there is no neighbour.
+template <class T>
+__device__ __forceinline__ void face_ghost(const FaceData<T> &M, const FaceRef &fr, const double (&qm)[4],
+                                           double (&qo)[4])
+{
+    if (fr.nbr == HDG_WALL) {
+        qo[0] = qm[0];
+#pragma unroll
+        for (int x = 1; x < 4; ++x) qo[x] = -qm[x];
+    } else if (fr.nbr < 0) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) qo[x] = gp(M.qinf)[x];
+    }
+}
+
 // jf, when given, points at this element's Ja^dir at the face node (three
 // values NTASK apart) and sf is the face's side (-1 for a minus face, +1 for
 // a plus face): sf Ja^dir is this element's outward s n, the owner's is its
 // negative on the other side (the two elements' metric terms agree at a
 // shared face node to round-off).  Without jf the owner's stored unit normal
-// and scale are read.
+// and scale are read.  qo is the other side's trace (face_other, face_ghost).
 template <int N, class T, int NTASK = 0>
-__device__ __forceinline__ void face_jump(const FaceData<T> &M, const gmem<const double> *qin, T c0sq, bool visc,
-                                          int fa, int fb, const FaceRef &fr, const double (&qm)[4], T (&F)[4],
-                                          const T *jf = nullptr, T sf = T(1))
+__device__ __forceinline__ void face_flux(const FaceData<T> &M, T c0sq, bool visc, int fa, int fb,
+                                          const FaceRef &fr, const double (&qm)[4], const double (&qo)[4],
+                                          T (&F)[4], const T *jf = nullptr, T sf = T(1))
 {
-    constexpr int N2 = Shape<N>::N2, N3 = Shape<N>::N3;
+    constexpr int N2 = Shape<N>::N2;
     const bool own = fr.code & kOwnerBit;
-    double qo[4];
     int oa = fa, ob = fb;
-    if (fr.nbr >= 0) {
-        int a2, b2;
-        orient_map<N>(fr.code & 7, fa, fb, a2, b2);
-        if (!own) { oa = a2; ob = b2; }
-        const gmem<const double> *qn = qin + 4 * (M.eoff ? gp(M.eoff)[fr.nbr] : (int64_t)fr.nbr * N3) + face_node<N>((fr.code >> 3) & 7, a2, b2);
-#pragma unroll
-        for (int x = 0; x < 4; ++x) qo[x] = qn[x * N3];
-    } else if (fr.nbr == HDG_WALL) {
-        qo[0] = qm[0];
-#pragma unroll
-        for (int x = 1; x < 4; ++x) qo[x] = -qm[x];
-    } else {
-#pragma unroll
-        for (int x = 0; x < 4; ++x) qo[x] = gp(M.qinf)[x];
-    }
+    if (fr.nbr >= 0 && !own) orient_map<N>(fr.code & 7, fa, fb, oa, ob);
     const int fnode = oa + N * ob;
     const int64_t fo = M.foff ? gp(M.foff)[fr.face] : (int64_t)fr.face * N2;
     T n[3], sc;
@@ -829,25 +852,41 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
     const FaceData<T> fd = face_data<T>(M);
     if constexpr (STAGE) {
         // face-node tasks, spread evenly over the workgroup; a tile's elements
-        // share one equation class
+        // share one equation class.  A task's own trace comes from the staged
+        // state, the other side's from global memory.
 #pragma unroll 1
         for (int task = c.tid; task < NTASK; task += blockDim.x) {
             const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
             const FaceRef fr = tf.f[ft.s * 6 + ft.f];
             if (ft.s < tl.count && !(fr.code & kMortarBit)) {
-                const int node = ft.s * N3 + face_node<N>(ft.f, ft.fa, ft.fb);
+                const int fnode = face_node<N>(ft.f, ft.fa, ft.fb), node = ft.s * N3 + fnode;
                 const double qm[4] = {sq[node], sq[NN + node], sq[2 * NN + node], sq[3 * NN + node]};
+                double qo[4];
+                face_other<N, T>(fd, c.qin, c.qin + 4 * elem_off<N>(M, ft.e) + fnode, ft.fa, ft.fb, fr, qo);
+                face_ghost<T>(fd, fr, qm, qo);
                 T F[4];
                 if constexpr (FACE_JA)
-                    face_jump<N, T, NTASK>(fd, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F, sjf + task,
+                    face_flux<N, T, NTASK>(fd, c.c0sq, visc, ft.fa, ft.fb, fr, qm, qo, F, sjf + task,
                                            (ft.f & 1) ? T(1) : T(-1));
                 else
-                    face_jump<N, T>(fd, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
+                    face_flux<N, T>(fd, c.c0sq, visc, ft.fa, ft.fb, fr, qm, qo, F);
 #pragma unroll
                 for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
             }
         }
         __syncthreads();     // the staged state is read; the fluxes take its place
+        if constexpr (sizeof(T) == 8) {
+            // the own state and its deviation from the reference, taken again
+            // from the lane's own staged slots (which only this lane's fluxes
+            // overwrite) rather than held in registers through the face tasks
+            // (FP64: 16 registers fewer at the kernel's register peak)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                c.qd[f] = sq[f * NN + c.g];
+                c.q[f] = (T)c.qd[f];
+                c.qt[f] = (T)(c.qd[f] - (double)c.qr[f]);
+            }
+        }
     }
     T V[4] = {T(0), T(0), T(0), T(0)};
     if constexpr (SF_IN_FLUX) {
@@ -886,8 +925,11 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
             if (ft.s < tl.count && !(fr.code & kMortarBit)) {
                 const gmem<const double> *qe = c.qin + 4 * elem_off<N>(M, ft.e) + face_node<N>(ft.f, ft.fa, ft.fb);
                 const double qm[4] = {qe[0], qe[N3], qe[2 * N3], qe[3 * N3]};
+                double qo[4];
+                face_other<N, T>(fd, c.qin, qe, ft.fa, ft.fb, fr, qo);
+                face_ghost<T>(fd, fr, qm, qo);
                 T F[4];
-                face_jump<N, T>(fd, c.qin, c.c0sq, visc, ft.fa, ft.fb, fr, qm, F);
+                face_flux<N, T>(fd, c.c0sq, visc, ft.fa, ft.fb, fr, qm, qo, F);
 #pragma unroll
                 for (int row = 0; row < 4; ++row) sface[row * NTASK + task] = F[row];
             }
@@ -899,7 +941,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
         if (!A.first_stage) {
             const gmem<double> *dqe = dqp + 4 * c.eo + c.t;
 #pragma unroll
-            for (int row = 0; row < 4; ++row) dq_old[row] = dqe[row * N3];
+            for (int row = 0; row < 4; ++row) dq_old[row] = __builtin_nontemporal_load(dqe + row * N3);
         }
     }
     // the viscous operator's volume part, loaded before the contraction so
@@ -948,8 +990,11 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
                 // FP64 stage accumulation into the state
                 const double Rd = (double)R;
                 const double d = A.first_stage ? dt * Rd : A.rkA * dq_old[row] + dt * Rd;
-                if (A.store_dq) dqp[idx] = d;
-                qout[idx] = c.qd[row] + A.rkB * d;
+                // streaming stores: the next state and the register are not
+                // read again in this stage, and left out of the L2 they leave
+                // room for the states that neighbouring tiles gather
+                if (A.store_dq) __builtin_nontemporal_store(d, dqp + idx);
+                __builtin_nontemporal_store(c.qd[row] + A.rkB * d, qout + idx);
             }
         }
     }
@@ -1004,8 +1049,14 @@ __global__ __launch_bounds__(B) void k_features(StageArgs A)
     HDG_ONE_TILE(A, tl) viscous_tile<N, EPT, double, true>(A, tl, smem);
 }
 
+// FP64 order-5 tiles launched one per workgroup fit five waves per SIMD
+// (at most 96 registers) without spilling; the persistent form's tile loop
+// would spill there and keeps the compiler's choice.
+template <class T, int N, bool PERS>
+constexpr int residual_min_waves() { return sizeof(T) == 8 && N == 5 && !PERS ? 5 : 1; }
+
 template <class T, int EPI, int N, int B, bool PERS>
-__global__ __launch_bounds__(B) void k_residual(StageArgs A)
+__global__ __launch_bounds__(B, (residual_min_waves<T, N, PERS>())) void k_residual(StageArgs A)
 {
     constexpr int EPT = tile_ept(N, B, kTileResidual);
     static_assert(EPT > 0, "tile does not fit the workgroup");
