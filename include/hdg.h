@@ -266,8 +266,8 @@ typedef struct {
  * kernels first, then viscous ones), times every supported (block,
  * persistent) pair on this mesh with reps whole fused RK stages reading q_dev
  * (device state, not modified), launched as the RK driver launches them
- * (every launch of the stage, with its concurrent branches), and keeps the
- * fastest.  Allocates a scratch register for the duration of the call,
+ * (every launch of the stage, with its concurrent branches), three times,
+ * and keeps the pair with the least time.  Allocates a scratch register for the duration of the call,
  * writes the mesh's internal ping-pong state, drops any captured graph and
  * synchronises the stream.
  * Default without tuning: the smallest block that fits an element, one

@@ -1116,17 +1116,23 @@ hdg_status hdg_mesh_autotune(hdg_mesh *m, const double *q, int32_t reps, void *s
                             return run_stage(m, q, m->qpp, dq, Epi::RkStage, pi == 1, -0.5, 0.5, 1e-9, 1, s);
                         };
                         st = once();
-                        if (st != HDG_OK) break;
-                        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(HDG_EHIP, "hipEventRecord"); break; }
-                        for (int r = 0; r < reps && st == HDG_OK; ++r) st = once();
-                        if (st != HDG_OK) break;
-                        float ms = 0.0f;
-                        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                            st = fail(HDG_EHIP, "autotune event timing");
-                            break;
+                        // the least of three timings of reps stages back to back:
+                        // other work on the device only ever adds time
+                        cf.us = -1.0;
+                        for (int trial = 0; trial < 3 && st == HDG_OK; ++trial) {
+                            if (hipEventRecord(e0, s) != hipSuccess) { st = fail(HDG_EHIP, "hipEventRecord"); break; }
+                            for (int r = 0; r < reps && st == HDG_OK; ++r) st = once();
+                            if (st != HDG_OK) break;
+                            float ms = 0.0f;
+                            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                                st = fail(HDG_EHIP, "autotune event timing");
+                                break;
+                            }
+                            const double us = 1e3 * ms / reps;
+                            if (cf.us < 0.0 || us < cf.us) cf.us = us;
                         }
-                        cf.us = 1e3 * ms / reps;
+                        if (st != HDG_OK) break;
                         if (best.us < 0.0 || cf.us < best.us) best = cf;
                     }
                 }

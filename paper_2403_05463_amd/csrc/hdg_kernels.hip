@@ -1051,12 +1051,13 @@ __global__ __launch_bounds__(B) void k_features(StageArgs A)
 
 // FP64 order-5 tiles launched one per workgroup fit five waves per SIMD
 // (at most 96 registers) without spilling; the persistent form's tile loop
-// would spill there and keeps the compiler's choice.
-template <class T, int N, bool PERS>
-constexpr int residual_min_waves() { return sizeof(T) == 8 && N == 5 && !PERS ? 5 : 1; }
+// would spill there and keeps the compiler's choice, and 512-lane
+// workgroups are held to four waves by their LDS.
+template <class T, int N, int B, bool PERS>
+constexpr int residual_min_waves() { return sizeof(T) == 8 && N == 5 && B <= 256 && !PERS ? 5 : 1; }
 
 template <class T, int EPI, int N, int B, bool PERS>
-__global__ __launch_bounds__(B, (residual_min_waves<T, N, PERS>())) void k_residual(StageArgs A)
+__global__ __launch_bounds__(B, (residual_min_waves<T, N, B, PERS>())) void k_residual(StageArgs A)
 {
     constexpr int EPT = tile_ept(N, B, kTileResidual);
     static_assert(EPT > 0, "tile does not fit the workgroup");
