@@ -232,8 +232,11 @@ hdg_status hdg_reduce(hdg_mesh *mesh, const double *r_dev, double out_sum[4], do
  * builds: it uses at most 1024 workgroups). */
 hdg_status hdg_reduce_noalloc(hdg_mesh *mesh, const double *r_dev, double *out_dev, void *stream);
 
-/* Kernel timing: while enabled, every launch the mesh makes is bracketed by
- * HIP events on its stream (up to 65536 launches are kept).  hdg_timing_read
+/* Kernel timing: while enabled, every launch the mesh makes is serialised on
+ * its stream and carries a pair of HIP events that the dispatch itself
+ * records at the kernel's start and end (hipExtLaunchKernelGGL), so that a
+ * launch's time is the kernel's own duration (up to 65536 launches are
+ * kept).  hdg_timing_read
  * synchronises on the last event, then returns the summed duration and count
  * of the launches of one kernel class (HDG_KERNEL_*) since enabling. */
 hdg_status hdg_timing_enable(hdg_mesh *mesh, int32_t enable);

@@ -283,17 +283,21 @@ int grid_for(const hdg_mesh *m, const TilePlan &pl, int kind, Epi epi, bool f32,
     return hdg::launch_grid(pl, kind, epi, f32, persistent, m->ctx->n_cu);
 }
 
-// Launch with optional event bracketing for the kernel timer.
+// Launch, with the kernel timer's events recorded by the dispatch itself
+// (start and end of the kernel) while timing is on.
 template <class F>
-hdg_status timed(hdg_mesh *m, int kind, hipStream_t s, F launch)
+hdg_status timed(hdg_mesh *m, int kind, F launch)
 {
     const bool rec = m->timing && m->ev_used + 2 <= m->ev.size();
-    if (rec) HDG_HIP(hipEventRecord(m->ev[m->ev_used], s));
+    hdg::LaunchEvents ev;
+    if (rec) {
+        ev.start = m->ev[m->ev_used];
+        ev.stop = m->ev[m->ev_used + 1];
+    }
     (void)hipGetLastError();   // the launch check below must see this launch's status only
-    hipError_t e = launch();
+    hipError_t e = launch(ev);
     if (e != hipSuccess) return fail(HDG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     if (rec) {
-        HDG_HIP(hipEventRecord(m->ev[m->ev_used + 1], s));
         m->ev_kind[m->ev_used / 2] = kind;
         m->ev_used += 2;
     }
@@ -342,13 +346,13 @@ hdg_status launch_one(hdg_mesh *m, int kind, int N, const LaunchCfg &cf, const d
     a.first_stage = stage == 0 ? 1 : 0;
     a.store_dq = stage == 2 ? 0 : 1;
     const int grid = grid_for(m, *pl, kind, epi, f32, cf.persistent);
-    auto go = [&] {
-        return kind == hdg::kTileViscous ? hdg::launch_viscous(N, pl->B, f32, cf.persistent, a, grid, s)
-                                         : hdg::launch_residual(N, pl->B, epi, f32, cf.persistent, a, grid, s);
+    auto go = [&](const hdg::LaunchEvents &ev) {
+        return kind == hdg::kTileViscous ? hdg::launch_viscous(N, pl->B, f32, cf.persistent, a, grid, s, ev)
+                                         : hdg::launch_residual(N, pl->B, epi, f32, cf.persistent, a, grid, s, ev);
     };
-    if (time_it) return timed(m, kind == hdg::kTileViscous ? HDG_KERNEL_VISCOUS : HDG_KERNEL_RESIDUAL, s, go);
+    if (time_it) return timed(m, kind == hdg::kTileViscous ? HDG_KERNEL_VISCOUS : HDG_KERNEL_RESIDUAL, go);
     (void)hipGetLastError();
-    hipError_t e = go();
+    hipError_t e = go(hdg::LaunchEvents{});
     if (e != hipSuccess) return fail(HDG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     return HDG_OK;
 }
@@ -396,8 +400,9 @@ hdg_status run_stage(hdg_mesh *m, const double *q, void *out, double *dq, Epi ep
                     if (a.mcount == 0) continue;
                     hipStream_t ls;
                     HDG_TRY(ph.next(ls));
-                    HDG_TRY(timed(m, HDG_KERNEL_MORTAR, ls,
-                                  [&] { return hdg::launch_mortar(kind == 0, Nl, Nh, f32, a, ls); }));
+                    HDG_TRY(timed(m, HDG_KERNEL_MORTAR, [&](const hdg::LaunchEvents &ev) {
+                        return hdg::launch_mortar(kind == 0, Nl, Nh, f32, a, ls, ev);
+                    }));
                 }
             HDG_TRY(ph.end());
         }

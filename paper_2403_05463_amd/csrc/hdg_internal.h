@@ -197,14 +197,22 @@ enum class Epi : int { Residual = 0, RkStage = 1 };
 // workgroup size B, persistence) over a tile list of order-N tiles; grid of
 // `grid` workgroups, a multiple of kXcd (non-persistent: kXcd * chunk or
 // more).  Return hipSuccess or the launch error.
-hipError_t launch_viscous(int N, int B, bool f32, bool persistent, const StageArgs &a, int grid, hipStream_t s);
+// With ev.start set, the dispatch itself records ev.start and ev.stop when
+// the kernel starts and ends (the kernel timer: the span is the kernel's own
+// duration, without the queue's gaps around it).
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+hipError_t launch_viscous(int N, int B, bool f32, bool persistent, const StageArgs &a, int grid, hipStream_t s,
+                          const LaunchEvents &ev = {});
 hipError_t launch_residual(int N, int B, Epi epi, bool f32, bool persistent, const StageArgs &a, int grid,
-                           hipStream_t s);
+                           hipStream_t s, const LaunchEvents &ev = {});
 // Mortar kernels of the pair (Nl, Nh) over the records a.mlist[0 .. a.mcount): the lift
 // kernel (before the viscous kernels) forms the BR1 lift terms, the flux
 // kernel (after them) the surface terms.  Only supported pairs launch.
 bool mortar_pair_supported(int Nl, int Nh);
-hipError_t launch_mortar(bool lift, int Nl, int Nh, bool f32, const StageArgs &a, hipStream_t s);
+hipError_t launch_mortar(bool lift, int Nl, int Nh, bool f32, const StageArgs &a, hipStream_t s,
+                         const LaunchEvents &ev = {});
 // Reductions of a mesh of mixed order: element after element, eoff / Ne per element.
 hipError_t launch_reduce_mixed(const double *r, const double *mass, const int64_t *eoff, const int8_t *Ne,
                                int64_t n_elem, double *partials, int nblocks, double *final13, hipStream_t s);

@@ -32,6 +32,8 @@
 // run no gradient, LES or viscous-flux arithmetic at all.
 #include "hdg_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <mutex>
 #include <type_traits>
 
@@ -1841,43 +1843,57 @@ bool grid_ok(const StageArgs &a, int grid, bool pers)
     return pers || grid / kXcd >= a.chunk;
 }
 
-hipError_t launch_viscous(int N, int B, bool f32, bool pers, const StageArgs &a, int grid, hipStream_t s)
+// One launch of a stage kernel (argument: the StageArgs by value), with the
+// dispatch recording the timer's events when they are given.
+template <class K>
+static void launch_stage_kernel(K kernel, int grid, int block, hipStream_t s, const LaunchEvents &ev,
+                                const StageArgs &a)
+{
+    if (ev.start)
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, ev.start, ev.stop, 0, a);
+    else
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, a);
+}
+
+hipError_t launch_viscous(int N, int B, bool f32, bool pers, const StageArgs &a, int grid, hipStream_t s,
+                          const LaunchEvents &ev)
 {
     if (a.ntiles == 0) return hipSuccess;
     if (!grid_ok(a, grid, pers)) return hipErrorInvalidValue;
     return by_shape(N, B, [&](auto nc, auto bc) {
         constexpr int NN = decltype(nc)::value, BB = decltype(bc)::value;
         if (f32) {
-            if (pers) hipLaunchKernelGGL((k_viscous<float, NN, BB, true>), dim3(grid), dim3(BB), 0, s, a);
-            else hipLaunchKernelGGL((k_viscous<float, NN, BB, false>), dim3(grid), dim3(BB), 0, s, a);
+            if (pers) launch_stage_kernel(k_viscous<float, NN, BB, true>, grid, BB, s, ev, a);
+            else launch_stage_kernel(k_viscous<float, NN, BB, false>, grid, BB, s, ev, a);
         } else {
-            if (pers) hipLaunchKernelGGL((k_viscous<double, NN, BB, true>), dim3(grid), dim3(BB), 0, s, a);
-            else hipLaunchKernelGGL((k_viscous<double, NN, BB, false>), dim3(grid), dim3(BB), 0, s, a);
+            if (pers) launch_stage_kernel(k_viscous<double, NN, BB, true>, grid, BB, s, ev, a);
+            else launch_stage_kernel(k_viscous<double, NN, BB, false>, grid, BB, s, ev, a);
         }
         return hipGetLastError();
     });
 }
 
 template <class T, int NN, int BB>
-void launch_residual_t(Epi epi, bool pers, const StageArgs &a, int grid, hipStream_t s)
+void launch_residual_t(Epi epi, bool pers, const StageArgs &a, int grid, hipStream_t s, const LaunchEvents &ev)
 {
     if (epi == Epi::Residual) {
-        if (pers) hipLaunchKernelGGL((k_residual<T, 0, NN, BB, true>), dim3(grid), dim3(BB), 0, s, a);
-        else hipLaunchKernelGGL((k_residual<T, 0, NN, BB, false>), dim3(grid), dim3(BB), 0, s, a);
+        if (pers) launch_stage_kernel(k_residual<T, 0, NN, BB, true>, grid, BB, s, ev, a);
+        else launch_stage_kernel(k_residual<T, 0, NN, BB, false>, grid, BB, s, ev, a);
     } else {
-        if (pers) hipLaunchKernelGGL((k_residual<T, 1, NN, BB, true>), dim3(grid), dim3(BB), 0, s, a);
-        else hipLaunchKernelGGL((k_residual<T, 1, NN, BB, false>), dim3(grid), dim3(BB), 0, s, a);
+        if (pers) launch_stage_kernel(k_residual<T, 1, NN, BB, true>, grid, BB, s, ev, a);
+        else launch_stage_kernel(k_residual<T, 1, NN, BB, false>, grid, BB, s, ev, a);
     }
 }
 
-hipError_t launch_residual(int N, int B, Epi epi, bool f32, bool pers, const StageArgs &a, int grid, hipStream_t s)
+hipError_t launch_residual(int N, int B, Epi epi, bool f32, bool pers, const StageArgs &a, int grid, hipStream_t s,
+                           const LaunchEvents &ev)
 {
     if (a.ntiles == 0) return hipSuccess;
     if (!grid_ok(a, grid, pers)) return hipErrorInvalidValue;
     return by_shape(N, B, [&](auto nc, auto bc) {
         constexpr int NN = decltype(nc)::value, BB = decltype(bc)::value;
-        if (f32) launch_residual_t<float, NN, BB>(epi, pers, a, grid, s);
-        else launch_residual_t<double, NN, BB>(epi, pers, a, grid, s);
+        if (f32) launch_residual_t<float, NN, BB>(epi, pers, a, grid, s, ev);
+        else launch_residual_t<double, NN, BB>(epi, pers, a, grid, s, ev);
         return hipGetLastError();
     });
 }
@@ -1921,20 +1937,21 @@ bool mortar_pair_supported(int Nl, int Nh)
 }
 
 template <int NL, int NH, class T>
-static hipError_t launch_mortar_kernel(bool lift, const StageArgs &a, hipStream_t s)
+static hipError_t launch_mortar_kernel(bool lift, const StageArgs &a, hipStream_t s, const LaunchEvents &ev)
 {
     const int grid = (a.mcount + MortarShape<NL, NH>::SLOTS - 1) / MortarShape<NL, NH>::SLOTS;
-    if (lift) hipLaunchKernelGGL((k_mortar_lift<NL, NH, T>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_mortar_flux<NL, NH, T>), dim3(grid), dim3(256), 0, s, a);
+    if (lift) launch_stage_kernel(k_mortar_lift<NL, NH, T>, grid, 256, s, ev, a);
+    else launch_stage_kernel(k_mortar_flux<NL, NH, T>, grid, 256, s, ev, a);
     return hipGetLastError();
 }
 
-hipError_t launch_mortar(bool lift, int Nl, int Nh, bool f32, const StageArgs &a, hipStream_t s)
+hipError_t launch_mortar(bool lift, int Nl, int Nh, bool f32, const StageArgs &a, hipStream_t s,
+                         const LaunchEvents &ev)
 {
     if (a.mcount == 0) return hipSuccess;
 #define P_(l, h)                                                                          \
     if (Nl == l && Nh == h)                                                               \
-        return f32 ? launch_mortar_kernel<l, h, float>(lift, a, s) : launch_mortar_kernel<l, h, double>(lift, a, s);
+        return f32 ? launch_mortar_kernel<l, h, float>(lift, a, s, ev) : launch_mortar_kernel<l, h, double>(lift, a, s, ev);
     HDG_MORTAR_PAIRS(P_)
 #undef P_
     return hipErrorInvalidValue;

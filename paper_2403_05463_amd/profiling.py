@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 output for the kernels of this library.
 
-``python -m paper_2403_05463_amd.profiling stats <kernel_stats.csv> --cmd "<command>"``
-    per-kernel call count and mean duration from ``--kernel-trace --stats``;
+``python -m paper_2403_05463_amd.profiling stats <kernel_stats.csv> [--trace <kernel_trace.csv>] --cmd "<command>"``
+    per-kernel call count and mean duration from ``--kernel-trace --stats``,
+    and with the trace the mean over the dispatches that ran alone;
 ``python -m paper_2403_05463_amd.profiling traffic <fetch.csv> <write.csv> --copy-bytes B --cmd "<command>"``
     HBM bytes per dispatch from two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
     runs, each scaled by what the same counter reads for the plain copy kernel
@@ -42,13 +43,39 @@ def short_name(name: str) -> str:
     return (m.group(1) + (m.group(2) or "")) if m else name[:48]
 
 
-def stats_summary(path: str, cmd: str) -> str:
+def isolated_dispatches(trace_csv: str) -> dict:
+    """Per kernel: durations (ns) of the dispatches that overlapped no other
+    dispatch in time, i.e. that had the device to themselves (a kernel timed
+    with the library's per-launch events runs alone; graph replays overlap
+    independent branches)."""
+    rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]))
+            for r in csv.DictReader(open(trace_csv))]
+    rows.sort()
+    out = collections.defaultdict(list)
+    reach = -1          # latest end among earlier dispatches
+    for i, (s0, e0, k) in enumerate(rows):
+        alone = s0 >= reach and (i + 1 == len(rows) or rows[i + 1][0] >= e0)
+        reach = max(reach, e0)
+        if alone:
+            out[k].append(e0 - s0)
+    return out
+
+
+def stats_summary(path: str, cmd: str, trace_csv: str = None) -> str:
     rows = list(csv.DictReader(open(path)))
-    lines = [f"# rocprofv3 kernel statistics", f"command: {cmd}", f"kernel source hash: {kernel_source_hash()}", "",
-             f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'share':>7s}"]
+    iso = isolated_dispatches(trace_csv) if trace_csv else {}
+    lines = [f"# rocprofv3 kernel statistics", f"command: {cmd}", f"kernel source hash: {kernel_source_hash()}",
+             "alone: dispatches that overlapped no other dispatch, and their mean duration" if trace_csv else "", "",
+             f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'share':>7s}"
+             + (f" {'alone':>6s} {'alone_avg_us':>12s}" if trace_csv else "")]
     for r in rows:
-        lines.append(f"{short_name(r['Name']):40s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
-                     f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}%")
+        name = short_name(r["Name"])
+        line = (f"{name.replace(' ', ''):40s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}%")
+        if trace_csv:
+            d = iso.get(name, [])
+            line += f" {len(d):6d} {(sum(d) / len(d) / 1e3 if d else float('nan')):12.2f}"
+        lines.append(line)
     return "\n".join(lines) + "\n"
 
 
@@ -154,6 +181,7 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="what", required=True)
     s = sub.add_parser("stats")
     s.add_argument("csv")
+    s.add_argument("--trace", help="kernel_trace.csv of the same run: adds the dispatches that ran alone")
     s.add_argument("--cmd", required=True)
     s.add_argument("--out")
     t = sub.add_parser("traffic")
@@ -171,7 +199,7 @@ def main(argv=None):
     f.add_argument("--out")
     a = ap.parse_args(argv)
     if a.what == "stats":
-        text = stats_summary(a.csv, a.cmd)
+        text = stats_summary(a.csv, a.cmd, a.trace)
     elif a.what == "flops":
         text = flops_summary(a.csv64, a.csv32, a.cmd64, a.cmd32)
     else:
