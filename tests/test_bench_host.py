@@ -74,3 +74,19 @@ def test_more_than_one_gpu_is_refused(capsys, monkeypatch):
     monkeypatch.setenv("WORLD_SIZE", "4")
     assert bench.main([]) == 2
     assert "WORLD_SIZE 4" in capsys.readouterr().err
+
+
+def test_shared_metric_saving():
+    """Translated elements share one metric block: the bytes not moved are
+    the metric terms of every element but one per block, 80 B/node in FP64
+    and 40 in FP32; the fraction against them uses the remaining bytes."""
+    N, E, Bk = 5, 36864, 4608
+    assert bench.shared_metric_saving(E, E, N) == 0.0
+    assert bench.shared_metric_saving(E, Bk, N) == (E - Bk) * 80 * N ** 3
+    assert bench.shared_metric_saving(E, Bk, N, f32=True) == (E - Bk) * 40 * N ** 3
+    alg = bench.algorithmic_bytes(E, N, fused_rk=True)
+    sv = bench.shared_metric_saving(E, Bk, N)
+    r = bench.with_shared_metrics(alg, sv, 1e-4)
+    assert r["bytes"] == alg - sv
+    assert abs(r["achieved"] - (alg - sv) / 1e-4 / 1e9) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / bench.HBM_PEAK_GBS) < 1e-15
