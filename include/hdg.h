@@ -141,9 +141,14 @@ typedef struct {
 hdg_status hdg_init(hdg_ctx **ctx, int32_t device);
 void hdg_finalize(hdg_ctx *ctx);
 
-/* Validate the mesh, build the Gauss-Lobatto-Legendre rules, node geometry,
- * metric terms (curl form), face normals, mortars, element lists, and upload
- * them.  Synchronous.  HDG_EMESH on inconsistent connectivity or J <= 0.
+/* Set-up of the discretisation of App. B on the mesh: validate it, build
+ * the Gauss-Lobatto-Legendre rules, node geometry, metric terms J and Ja
+ * (curl form; translated elements share one block), face normals, the
+ * mortars between elements of different order (Sec. 2.2), element lists,
+ * and upload them.  The equation flag of each element (Sec. 2.1 regions)
+ * comes with the description.  Synchronous.  HDG_EMESH on inconsistent
+ * connectivity or J <= 0, HDG_EUNSUPPORTED on a face between orders whose
+ * lower order cannot represent the geometry (2 geom_order > P).
  * State layout: element after element, [4][(P_e+1)^3] each. */
 hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *desc, const hdg_params *params,
                            hdg_mesh **out);
@@ -206,8 +211,10 @@ hdg_status hdg_rk3_steps(hdg_mesh *mesh, double *q_dev, double *dq_dev, double d
  * Re-flagging, new parameters or launch shapes drop the captured graph. */
 hdg_status hdg_mesh_set_graphs(hdg_mesh *mesh, int32_t enable);
 
-/* Per-field reductions of a device array in state layout: mass-weighted sum
- * sum w_a w_b w_c J r (discrete conservation), mass-weighted L2 norm and max
+/* Per-field reductions of a device array in state layout, with the
+ * quadrature of App. B (GLL weights times J at each node): mass-weighted sum
+ * sum w_a w_b w_c J r (the discrete conservation statement of the scheme's
+ * single-valued face fluxes, Sec. 2.3), mass-weighted L2 norm and max
  * |r|.  Host outputs, any may be NULL.  Synchronises the stream.
  * HDG_ENONFINITE if any entry is NaN or Inf (outputs still written). */
 hdg_status hdg_reduce(hdg_mesh *mesh, const double *r_dev, double out_sum[4], double out_l2[4],
