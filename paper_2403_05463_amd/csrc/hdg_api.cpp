@@ -196,6 +196,12 @@ hdg_status upload_plans(hdg_mesh *m)
             }
             indep[e] = ok ? 1 : 0;
         }
+    // a handful of independent elements (a scattered mask: almost every Euler
+    // element has a flagged neighbour) is not worth a launch and a fork of
+    // its own
+    int64_t n_indep = 0;
+    for (int64_t e = 0; e < m->ne; ++e) n_indep += indep[e];
+    if (16 * n_indep < m->ne) std::fill(indep.begin(), indep.end(), (uint8_t)0);
     for (int kind = 0; kind < 3; ++kind) {
         std::vector<hdg::TilePlan> &dst = kind == 2 ? m->plans_indep : m->plans[kind];
         for (int64_t e = 0; e < m->ne; ++e)
