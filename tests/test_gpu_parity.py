@@ -333,6 +333,32 @@ def test_timing_and_copy_probe(torch_cuda, ctx):
     assert hdg.hdg_timing_read(m, hdg.HDG_KERNEL_MORTAR)[1] == 0     # one order: no mortar faces
     assert hdg.hdg_timing_samples(m, hdg.HDG_KERNEL_MORTAR) == []
     hdg.hdg_timing_enable(m, False)
+    # the timer's events are recorded by each dispatch: the launches run one
+    # after another, so their durations add up to less than the span of the
+    # steps on the stream
+    hdg.hdg_timing_enable(m, True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hdg.hdg_rk3_steps(m, q, dq, 1e-7, 2)
+    e1.record()
+    torch.cuda.synchronize()
+    span = e0.elapsed_time(e1)
+    total = sum(hdg.hdg_timing_read(m, k)[0] for k in (hdg.HDG_KERNEL_VISCOUS, hdg.HDG_KERNEL_RESIDUAL))
+    _say(f"kernel time {total:.4f} ms of a {span:.4f} ms span")
+    assert 0 < total < span
+    hdg.hdg_timing_enable(m, False)
+    # a scattered mask (periodic 4^3 box, Bernoulli(0.5)): 2 of the 28 Euler
+    # elements have no flagged neighbour, too few for a launch of their own,
+    # so each stage takes one residual launch
+    box = W.periodic_box(4, Pg=1)
+    fb = W.bernoulli_mask(box.n_elem, 0.5, 1)
+    mb = hdg.hdg_mesh_create(ctx, box, 3, fb, hdg.make_params(**w.params))
+    qb = torch.zeros(mb.nodes * 4, dtype=torch.float64, device="cuda")
+    hdg.hdg_timing_enable(mb, True)
+    hdg.hdg_rk3_steps(mb, qb, torch.empty_like(qb), 1e-3, 2)
+    assert hdg.hdg_timing_read(mb, hdg.HDG_KERNEL_VISCOUS)[1] == 6
+    assert hdg.hdg_timing_read(mb, hdg.HDG_KERNEL_RESIDUAL)[1] == 6
+    hdg.hdg_timing_enable(mb, False)
     a = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     hdg.hdg_stream_copy(ctx, b, a, a.numel() * 8)
