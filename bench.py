@@ -245,6 +245,18 @@ def secondary_leg(ctx, args, torch, hdg) -> dict:
     us = hdg.hdg_timing_samples(mesh, hdg.HDG_KERNEL_RESIDUAL)
     hdg.hdg_timing_enable(mesh, False)
     red = hdg.hdg_reduce(mesh, q, allow_nonfinite=True)
+    # the precision form on the same box: FP32 residual, FP64 state (the
+    # graph-replayed step, and the residual's per-field error in the floored
+    # norms against this library's FP64 path at the initial state)
+    q.copy_(torch.from_numpy(q0))
+    f32_err = fp32_residual_error(mesh, q, torch, hdg)
+    hdg.hdg_rk3_steps(mesh, q, dq, w.dt, 2, prec=hdg.HDG_F32, stream=stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    hdg.hdg_rk3_steps(mesh, q, dq, w.dt, steps, prec=hdg.HDG_F32, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1)
     per_step = sum(algorithmic_bytes(w.mesh.n_elem, N, fused_rk=True, first_stage=(st == 0)) for st in range(3))
     avg_us = float(np.mean(us))
     launches_per_step = len(us) / steps
@@ -257,6 +269,8 @@ def secondary_leg(ctx, args, torch, hdg) -> dict:
             "value": nodes * 4 * 3 * steps / (ms / 1e3), "unit": "DOF-residual evals/s",
             "ms_per_step": ms / steps, "state_finite": bool(red["finite"]),
             "metric_blocks": blocks,
+            "fp32": {"ms_per_step": ms32 / steps, "value": nodes * 4 * 3 * steps / (ms32 / 1e3),
+                     "residual_error": f32_err},
             "stage_roofline": {"achieved": per_step / (ms / steps * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": per_step / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                "with_shared_metrics": with_shared_metrics(per_step, saving, ms / steps * 1e-3)},
