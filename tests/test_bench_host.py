@@ -33,7 +33,7 @@ def test_fused_stage_bytes_fp32():
 
 
 def test_residual_only_intermediate_and_viscous_bytes():
-    # the survey's residual figure: 144 + 96 / N B/node
+    # the residual-only operator: state 32 + metric terms 80 + R 32 B/node, three owned faces of geometry
     assert bench.algorithmic_bytes(NE, N, fused_rk=False) == NE * N3 * (144 + 96 / N)
     # viscous part (3 doubles per node) and both sides' traces (3 doubles per face node, six faces)
     assert bench.intermediate_bytes(NV, N) == NV * (N3 * 24 + 6 * N2 * 24)
