@@ -95,6 +95,7 @@ void free_device(hdg_mesh *m)
         if (pl.tiles) (void)hipFree(pl.tiles);
         if (pl.elems) (void)hipFree(pl.elems);
         if (pl.emo) (void)hipFree(pl.emo);
+        if (pl.eoe) (void)hipFree(pl.eoe);
     }
     m->feat_plans.clear();
     for (auto &v : m->plans) {
@@ -102,6 +103,7 @@ void free_device(hdg_mesh *m)
             if (pl.tiles) (void)hipFree(pl.tiles);
             if (pl.elems) (void)hipFree(pl.elems);
             if (pl.emo) (void)hipFree(pl.emo);
+            if (pl.eoe) (void)hipFree(pl.eoe);
         }
         v.clear();
     }
@@ -109,6 +111,7 @@ void free_device(hdg_mesh *m)
         if (pl.tiles) (void)hipFree(pl.tiles);
         if (pl.elems) (void)hipFree(pl.elems);
         if (pl.emo) (void)hipFree(pl.emo);
+        if (pl.eoe) (void)hipFree(pl.eoe);
     }
     m->plans_indep.clear();
     if (m->indep_stream) (void)hipStreamDestroy(m->indep_stream);
@@ -181,6 +184,7 @@ hdg_status upload_plans(hdg_mesh *m)
             if (pl.tiles) (void)hipFree(pl.tiles);
             if (pl.elems) (void)hipFree(pl.elems);
             if (pl.emo) (void)hipFree(pl.emo);
+            if (pl.eoe) (void)hipFree(pl.eoe);
         }
         v->clear();
     }
@@ -238,6 +242,13 @@ hdg_status upload_plans(hdg_mesh *m)
                     for (size_t k = 0; k < elems.size(); ++k) emo[k] = m->moff_h[elems[k]];
                     HDG_HIP(hipMalloc((void **)&pl.emo, emo.size() * sizeof(int64_t)));
                     HDG_HIP(hipMemcpy(pl.emo, emo.data(), emo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+                }
+                if (m->mixed) {
+                    // likewise each entry's first node, instead of a lookup in eoff
+                    std::vector<int64_t> eoe(elems.size());
+                    for (size_t k = 0; k < elems.size(); ++k) eoe[k] = m->eoff_h[elems[k]];
+                    HDG_HIP(hipMalloc((void **)&pl.eoe, eoe.size() * sizeof(int64_t)));
+                    HDG_HIP(hipMemcpy(pl.eoe, eoe.data(), eoe.size() * sizeof(int64_t), hipMemcpyHostToDevice));
                 }
                 dst.push_back(pl);
             }
@@ -317,6 +328,7 @@ StageArgs stage_args(const hdg_mesh *m, const TilePlan &pl)
     a.tiles = pl.tiles;
     a.elems = pl.elems;
     a.emo = pl.emo;
+    a.eoe = pl.eoe;
     a.ntiles = pl.ntiles;
     a.chunk = pl.chunk;
     a.D64 = m->ctx->D64;
@@ -659,7 +671,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
             FaceRef &r = conn[e * 6 + f];
             r.face = fid[e * 6 + f];
             r.nbr = d->nbr[e * 6 + f];
-            r.pad = 0;
+            r.nbr_off = 0;
             const int N = Ne[e];
             if (mortar_face(e, f)) {
                 const bool hi = Ne[e] > Ne[r.nbr];
@@ -680,6 +692,20 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
                 for (int a = 0; a < N; ++a)
                     put_normal(&fgeo[(foff[r.face] + a + N * b) * 4], e, f, face_node(N, f, a, b));
         }
+    // meshes of mixed order: a conforming face's record carries its first
+    // face node and the neighbour's first node, so that the kernels' trace,
+    // geometry and neighbour loads wait for no table lookup
+    if (m->mixed) {
+        if (g.nodes > INT32_MAX || nfn > INT32_MAX) {
+            delete m;    // nothing on the device yet
+            return fail(HDG_EUNSUPPORTED, "a mesh of mixed order needs fewer than 2^31 nodes and face nodes");
+        }
+        for (FaceRef &r : conn)
+            if (!(r.code & hdg::kMortarBit)) {
+                r.face = (int32_t)foff[r.face];
+                if (r.nbr >= 0) r.nbr_off = (int32_t)off[r.nbr];
+            }
+    }
     // metric blocks: one per group of translates, [block][10][N^3]; moff[e] is
     // the first node of the block element e reads
     std::vector<int64_t> moff;
@@ -767,6 +793,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     chk(up(m->conn, conn.data(), conn.size() * sizeof(FaceRef)));
     if (share) chk(up(m->moff, moff.data(), moff.size() * sizeof(int64_t)));
     if (share) m->moff_h = moff;
+    if (m->mixed) m->eoff_h = off;
     m->conn_h = conn;
     if (m->mixed) {
         std::vector<int8_t> n8(Ne.begin(), Ne.end());

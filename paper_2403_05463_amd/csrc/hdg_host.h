@@ -50,6 +50,7 @@ struct TilePlan {
     Tile *tiles = nullptr;
     int32_t *elems = nullptr;
     int64_t *emo = nullptr;          // metric block of each entry of elems (meshes whose translates share one)
+    int64_t *eoe = nullptr;          // first node of each entry's element (meshes of mixed order)
     // batches: device capacity (items) and the host copy of the last upload
     int64_t tiles_cap = 0, elems_cap = 0;
     std::vector<Tile> h_tiles;
@@ -249,6 +250,7 @@ struct hdg_mesh {
     hdg::FaceRef *conn = nullptr;
     std::vector<hdg::FaceRef> conn_h;              // host copy (neighbour-flag bits refreshed with the flags)
     std::vector<int64_t> moff_h;                   // host copy of moff (meshes with shared metric blocks)
+    std::vector<int64_t> eoff_h;                   // host copy of eoff (meshes of mixed order)
     uint8_t *flag_d = nullptr;
     int64_t *moff = nullptr;                       // first node of each element's metric block (translates
                                                    // share one), or NULL: blocks in element order

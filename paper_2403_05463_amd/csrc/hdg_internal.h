@@ -16,10 +16,12 @@ constexpr int kXcd = 8;           // MI355X: 8 accelerator complex dies, each wi
 
 // One record per (element, local face), consumed by the kernels.
 struct FaceRef {
-    int32_t face;   // canonical face id: index into face geometry and viscous traces
-    int32_t nbr;    // neighbour element, or HDG_WALL / HDG_FARFIELD
-    int32_t code;   // bits 0-2 orientation, bits 3-5 neighbour's local face, bit 6 owner
-    int32_t pad;
+    int32_t face;     // conforming face: where its nodes start in the face geometry and viscous
+                      // traces (one-order meshes: the canonical face id f, nodes from f N^2; meshes
+                      // of mixed order: that first face node itself); mortar face: the mortar id
+    int32_t nbr;      // neighbour element, or HDG_WALL / HDG_FARFIELD
+    int32_t code;     // bits 0-2 orientation, bits 3-5 neighbour's local face, bit 6 owner
+    int32_t nbr_off;  // meshes of mixed order, conforming face: the neighbour's first node; else 0
 };
 
 constexpr int kOwnerBit = 1 << 6;   // conforming face: this side owns it; mortar: this is the higher side
@@ -138,6 +140,8 @@ struct StageArgs {
     const int32_t *elems;   // member-local element ids, grouped by tile
     const int64_t *emo;     // per entry of elems: first node of the element's metric block (shared by its
                             // translates), or NULL: the member's own offsets
+    const int64_t *eoe;     // per entry of elems: the element's first node (meshes of mixed order), or
+                            // NULL: the member's offsets
     int32_t ntiles;
     int32_t chunk;          // tiles per XCD chunk; the grid is a multiple of kXcd
     const double *D64;      // derivative matrices for N = 2..8, packed at d_offset(N)

@@ -128,20 +128,31 @@ __device__ __forceinline__ int64_t elem_off(const Member &M, int e)
     return M.eoff ? gp(M.eoff)[e] : (int64_t)e * (N * N * N);
 }
 
+// A conforming face's first face node: on a mesh of mixed order the record
+// holds it (no lookup), on a one-order mesh it is f N^2.
 template <int N>
-__device__ __forceinline__ int64_t face_off(const Member &M, int f)
+__device__ __forceinline__ int64_t face_first(bool mixed, const FaceRef &r)
 {
-    return M.foff ? gp(M.foff)[f] : (int64_t)f * (N * N);
+    return mixed ? (int64_t)r.face : (int64_t)r.face * (N * N);
+}
+
+// The neighbour's first node across a conforming face (record on a mesh of
+// mixed order, nbr N^3 otherwise).
+template <int N>
+__device__ __forceinline__ int64_t nbr_first(bool mixed, const FaceRef &r)
+{
+    return mixed ? (int64_t)r.nbr_off : (int64_t)r.nbr * (N * N * N);
 }
 
 __device__ __forceinline__ FaceRef load_face(const FaceRef *conn, size_t i)
 {
-    const gmem<const int32_t> *p = gp((const int32_t *)conn) + 4 * i;
+    typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+    const i32x4 v = *(gp((const i32x4 *)conn) + i);      // one 16-byte load
     FaceRef r;
-    r.face = p[0];
-    r.nbr = p[1];
-    r.code = p[2];
-    r.pad = 0;
+    r.face = v.x;
+    r.nbr = v.y;
+    r.code = v.z;
+    r.nbr_off = v.w;
     return r;
 }
 
@@ -204,6 +215,7 @@ struct TileCtx {
 template <int EPT>
 struct TileFaces {
     int32_t e[EPT];
+    int64_t eo[EPT];          // the elements' first nodes
     FaceRef f[6 * EPT];
 };
 
@@ -229,7 +241,7 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     c.j = (c.t / N) % N;
     c.k = c.t / N2;
     c.e = A.elems[tl.first + c.s];
-    c.eo = elem_off<N>(M, c.e);
+    c.eo = A.eoe ? A.eoe[tl.first + c.s] : elem_off<N>(M, c.e);
     // Loads are issued before any LDS write that needs one of them: the load
     // counter is in order, so the metric terms, issued last and needed last,
     // stay in flight across the barrier while face tasks start.  The first
@@ -243,6 +255,9 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     // one element per tile: its id is the lane's own (a scalar load), so the
     // record load does not wait on a vector load
     const int32_t rel = EPT == 1 ? c.e : A.elems[tl.first + (rs < tl.count ? rs : tl.count - 1)];
+    // the record lanes' element's first node, for face tasks (EPT > 1)
+    const int64_t reo = EPT == 1 ? c.eo
+                        : A.eoe ? A.eoe[tl.first + (rs < tl.count ? rs : tl.count - 1)] : elem_off<N>(M, rel);
     const FaceRef rrec = load_face(M.conn, (size_t)rel * 6 + (c.tid < EPT ? 0 : (c.tid - EPT) - 6 * rs));
     c.qin = gp((const double *)(A.q_in ? A.q_in : (A.parity ? M.qB : M.qA)));
     const gmem<double> *qe = c.qin + 4 * c.eo;
@@ -269,7 +284,10 @@ __device__ __forceinline__ void load_tile(const StageArgs &A, const Member &M, c
     c.C_les = (T)M.C_les;
     c.inv_wend = T(N * (N - 1) / 2);   // 1 / w_0 = P (P + 1) / 2
     if (c.tid < N2) sD[c.tid] = dval;
-    if (c.tid < EPT) tf.e[c.tid] = c.tid < tl.count ? rel : 0;
+    if (c.tid < EPT) {
+        tf.e[c.tid] = c.tid < tl.count ? rel : 0;
+        tf.eo[c.tid] = c.tid < tl.count ? reo : 0;
+    }
     else if (c.tid < 7 * EPT) tf.f[c.tid - EPT] = rs < tl.count ? rrec : FaceRef{0, HDG_WALL, 0, 0};
     if constexpr (STAGE_Q) {
         if (c.act) {
@@ -353,12 +371,13 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
         const FaceRef fr = tf.f[ft.s * 6 + ft.f];
         if (ft.s < tl.count && !(fr.code & kMortarBit)) {
             // u* - u = (u_other - u) / 2, formed in FP64
-            const gmem<const double> *qm = c.qin + 4 * elem_off<N>(M, ft.e) + face_node<N>(ft.f, ft.fa, ft.fb);
+            const gmem<const double> *qm = c.qin + 4 * tf.eo[ft.s] + face_node<N>(ft.f, ft.fa, ft.fb);
             double uo[3];
             if (fr.nbr >= 0) {
                 int a2, b2;
                 orient_map<N>(fr.code & 7, ft.fa, ft.fb, a2, b2);
-                const gmem<const double> *qn = c.qin + 4 * elem_off<N>(M, fr.nbr) + face_node<N>((fr.code >> 3) & 7, a2, b2);
+                const gmem<const double> *qn = c.qin + 4 * nbr_first<N>(M.eoff != nullptr, fr) +
+                                               face_node<N>((fr.code >> 3) & 7, a2, b2);
 #pragma unroll
                 for (int r = 0; r < 3; ++r) uo[r] = qn[(1 + r) * N3];
             } else {
@@ -552,7 +571,7 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
             const bool own = fr.code & kOwnerBit;
             int oa = ft.fa, ob = ft.fb;
             if (!own) orient_map<N>(fr.code & 7, ft.fa, ft.fb, oa, ob);
-            gmem<T> *out = fvt + 6 * face_off<N>(M, fr.face) + (own ? 0 : 3 * N2) + oa + N * ob;
+            gmem<T> *out = fvt + 6 * face_first<N>(M.foff != nullptr, fr) + (own ? 0 : 3 * N2) + oa + N * ob;
 #pragma unroll
             for (int r = 0; r < 3; ++r) out[r * N2] = sfu[r * NTASK + task];
         }
@@ -673,7 +692,7 @@ __device__ __forceinline__ void face_other(const FaceData<T> &M, const gmem<cons
     if (fr.nbr >= 0 && !(fr.code & kMortarBit)) {
         int a2, b2;
         orient_map<N>(fr.code & 7, fa, fb, a2, b2);
-        qn = qin + 4 * (M.eoff ? gp(M.eoff)[fr.nbr] : (int64_t)fr.nbr * N3) + face_node<N>((fr.code >> 3) & 7, a2, b2);
+        qn = qin + 4 * nbr_first<N>(M.eoff != nullptr, fr) + face_node<N>((fr.code >> 3) & 7, a2, b2);
     }
 #pragma unroll
     for (int x = 0; x < 4; ++x) qo[x] = qn[x * N3];
@@ -710,7 +729,7 @@ __device__ __forceinline__ void face_flux(const FaceData<T> &M, T c0sq, bool vis
     int oa = fa, ob = fb;
     if (fr.nbr >= 0 && !own) orient_map<N>(fr.code & 7, fa, fb, oa, ob);
     const int fnode = oa + N * ob;
-    const int64_t fo = M.foff ? gp(M.foff)[fr.face] : (int64_t)fr.face * N2;
+    const int64_t fo = face_first<N>(M.foff != nullptr, fr);
     T n[3], sc;
     if constexpr (NTASK > 0) {
         // the owner's outward s n from this element's own metric terms
@@ -864,7 +883,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
                 const int fnode = face_node<N>(ft.f, ft.fa, ft.fb), node = ft.s * N3 + fnode;
                 const double qm[4] = {sq[node], sq[NN + node], sq[2 * NN + node], sq[3 * NN + node]};
                 double qo[4];
-                face_other<N, T>(fd, c.qin, c.qin + 4 * elem_off<N>(M, ft.e) + fnode, ft.fa, ft.fb, fr, qo);
+                face_other<N, T>(fd, c.qin, c.qin + 4 * tf.eo[ft.s] + fnode, ft.fa, ft.fb, fr, qo);
                 face_ghost<T>(fd, fr, qm, qo);
                 T F[4];
                 if constexpr (FACE_JA)
@@ -925,7 +944,7 @@ __device__ __forceinline__ void residual_tile(const StageArgs &A, const Tile &tl
             const FaceTask<N> ft = face_task<N, EPT>(tf, tl, task);
             const FaceRef fr = tf.f[ft.s * 6 + ft.f];
             if (ft.s < tl.count && !(fr.code & kMortarBit)) {
-                const gmem<const double> *qe = c.qin + 4 * elem_off<N>(M, ft.e) + face_node<N>(ft.f, ft.fa, ft.fb);
+                const gmem<const double> *qe = c.qin + 4 * tf.eo[ft.s] + face_node<N>(ft.f, ft.fa, ft.fb);
                 const double qm[4] = {qe[0], qe[N3], qe[2 * N3], qe[3 * N3]};
                 double qo[4];
                 face_other<N, T>(fd, c.qin, qe, ft.fa, ft.fb, fr, qo);
