@@ -653,6 +653,10 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
             if (!mortar_face(e, f) && !is_owner(e, f))
                 fid[e * 6 + f] = fid[(int64_t)d->nbr[e * 6 + f] * 6 + d->nbr_face[e * 6 + f]];
     m->nfaces = nf;
+    if (slab > INT32_MAX) {
+        delete m;    // nothing on the device yet
+        return fail(HDG_EUNSUPPORTED, "mortar slabs need fewer than 2^31 values");
+    }
     std::vector<double> fgeo(std::max<int64_t>(nfn, 1) * 4), mgeo(std::max<int64_t>(geo, 1) * 4);
     std::vector<FaceRef> conn(ne * 6);
     auto put_normal = [&](double *o, int64_t e, int f, int n) {
@@ -675,7 +679,10 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
             const int N = Ne[e];
             if (mortar_face(e, f)) {
                 const bool hi = Ne[e] > Ne[r.nbr];
-                r.code = hdg::kMortarBit | (hi ? hdg::kOwnerBit : 0);
+                // the other side's order and the slab travel in the record, so
+                // that the element kernels need not load the mortar's
+                r.code = hdg::kMortarBit | (hi ? hdg::kOwnerBit : 0) | Ne[r.nbr];
+                r.nbr_off = (int32_t)m->mort_h[r.face].slab;
                 if (hi) {
                     const hdg::MortarRef &mr = m->mort_h[r.face];
                     for (int b = 0; b < N; ++b)

@@ -21,11 +21,14 @@ struct FaceRef {
                       // of mixed order: that first face node itself); mortar face: the mortar id
     int32_t nbr;      // neighbour element, or HDG_WALL / HDG_FARFIELD
     int32_t code;     // bits 0-2 orientation, bits 3-5 neighbour's local face, bit 6 owner
-    int32_t nbr_off;  // meshes of mixed order, conforming face: the neighbour's first node; else 0
+    int32_t nbr_off;  // meshes of mixed order, conforming face: the neighbour's first node; mortar
+                      // face: the first value of the mortar's slab; else 0
 };
 
 constexpr int kOwnerBit = 1 << 6;   // conforming face: this side owns it; mortar: this is the higher side
-constexpr int kMortarBit = 1 << 7;  // face between elements of different order: `face` is the mortar id
+constexpr int kMortarBit = 1 << 7;  // face between elements of different order: `face` is the mortar id,
+                                    // `nbr_off` the first value of its slab, bits 0-3 of the code the
+                                    // other side's order N
 constexpr int kNbrViscBit = 1 << 8; // the neighbour is flagged (kept current with the flags), so a face
                                     // task issues its viscous-trace loads without first loading the flag
 

@@ -144,6 +144,26 @@ __device__ __forceinline__ int64_t nbr_first(bool mixed, const FaceRef &r)
     return mixed ? (int64_t)r.nbr_off : (int64_t)r.nbr * (N * N * N);
 }
 
+// A mortar face's slab and the two sides' orders, from the element's own
+// order and its face record (no load of the mortar's record).
+struct MortarSide {
+    int64_t slab;
+    int Nh, Nl;
+    bool hi;
+};
+
+template <int N>
+__device__ __forceinline__ MortarSide mortar_side(const FaceRef &r)
+{
+    MortarSide m;
+    const int other = r.code & 15;
+    m.hi = (r.code & kOwnerBit) != 0;
+    m.slab = (int64_t)(uint32_t)r.nbr_off;
+    m.Nh = m.hi ? N : other;
+    m.Nl = m.hi ? other : N;
+    return m;
+}
+
 __device__ __forceinline__ FaceRef load_face(const FaceRef *conn, size_t i)
 {
     typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
@@ -435,8 +455,8 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
                 const T sf = (f & 1) ? T(1) : T(-1);
                 const FaceRef fr = tf.f[c.s * 6 + f];
                 if (fr.code & kMortarBit) {
-                    const MortarRef mr = load_mortar(M.mort, fr.face);
-                    const bool hi = fr.code & kOwnerBit;
+                    const MortarSide mr = mortar_side<N>(fr);
+                    const bool hi = mr.hi;
                     const gmem<const T> *lf = gp((const T *)M.mslab) + mr.slab + mslab_lift(mr.Nh, mr.Nl, hi) + fidx;
                     if (hi) {
                         // higher side: the mortar is its own face, (u* - u) (s n)_own
@@ -545,8 +565,8 @@ __device__ __forceinline__ void viscous_tile(const StageArgs &A, const Tile &tl,
             const T so = (fr.code & kOwnerBit) ? sf : -sf;
             const T sn[3] = {so * c.Ja[dir][0], so * c.Ja[dir][1], so * c.Ja[dir][2]};
             if (fr.code & kMortarBit) {
-                const MortarRef mr = load_mortar(M.mort, fr.face);
-                gmem<T> *tr = gp((T *)M.mslab) + mr.slab + mslab_tr(mr.Nh, mr.Nl, fr.code & kOwnerBit) + fidx;
+                const MortarSide mr = mortar_side<N>(fr);
+                gmem<T> *tr = gp((T *)M.mslab) + mr.slab + mslab_tr(mr.Nh, mr.Nl, mr.hi) + fidx;
 #pragma unroll
                 for (int r = 0; r < 3; ++r) tr[r * N2] = fv[r][0] * sn[0] + fv[r][1] * sn[1] + fv[r][2] * sn[2];
             } else {
@@ -808,10 +828,10 @@ __device__ __forceinline__ void surface_terms(const Member &M, const TileFaces<E
             const FaceRef fr = tf.f[c.s * 6 + f];
             if (fr.code & kMortarBit) {
                 if (MORT) {
-                    const MortarRef mr = load_mortar(M.mort, fr.face);
+                    const MortarSide mr = mortar_side<N>(fr);
                     const T sf = (f & 1) ? T(1) : T(-1);
-                    const gmem<const T> *sm = gp((const T *)M.mslab) + mr.slab +
-                                              mslab_surf(mr.Nh, mr.Nl, fr.code & kOwnerBit) + fa + N * fb;
+                    const gmem<const T> *sm = gp((const T *)M.mslab) + mr.slab + mslab_surf(mr.Nh, mr.Nl, mr.hi) +
+                                              fa + N * fb;
 #pragma unroll
                     for (int row = 0; row < 4; ++row)
                         V[row] += (sm[row * N2] - sf * lds[(dir * 4 + row) * NN + c.g]) * c.inv_wend;
