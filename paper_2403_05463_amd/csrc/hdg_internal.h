@@ -123,7 +123,8 @@ struct Member {
     const int64_t *moff;    // [e] first node of the metric block e reads (translates share one), or
                             // NULL: e's own, at its first node
     const int64_t *eoff;    // [e] first node of the element; NULL: e N^3 (one order)
-    const int64_t *foff;    // [face] first face node of the face; NULL: face N^2
+    const int64_t *foff;    // [face] first face node of the face; NULL: face N^2.  Set on a mesh of
+                            // mixed order, whose face records then hold these offsets themselves
     const MortarRef *mort;  // [mortar] faces between orders (NULL if none)
     void *mslab;            // mortar slabs (compute type)
     const void *mgeo[2];    // mortar geometry [node][4], FP64 and FP32

@@ -119,9 +119,11 @@ __device__ __forceinline__ gmem<P> *gp(P *p)
     return (gmem<P> *)p;
 }
 
-// First node of element e and first face node of face f: tables for meshes
-// of mixed order, plain products when every element has order N (the
-// tables are then absent and no dependent load sits on the address path).
+// First node of element e: a table on a mesh of mixed order, a plain
+// product when every element has order N (the table is then absent).  On
+// the hot paths the tile-list entry (eoe) and the face records carry these
+// offsets, so no table lookup sits between a record and the loads it
+// addresses; the table serves the batch and clustering paths.
 template <int N>
 __device__ __forceinline__ int64_t elem_off(const Member &M, int e)
 {
