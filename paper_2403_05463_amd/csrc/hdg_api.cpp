@@ -2,6 +2,7 @@
 // include/hdg.h): mesh ingest and validation, device buffers, the launch
 // sequence of one residual / one RK stage, reductions and kernel timing.
 #include <algorithm>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -53,6 +54,25 @@ int launch_grid(const TilePlan &pl, int kind, Epi epi, bool f32, bool persistent
 namespace {
 
 hdg_status fail(hdg_status s, const std::string &msg) { return hdg::set_error(s, msg); }
+
+// fn(e) for every element on up to 16 host threads (elements interleaved);
+// fn writes only what belongs to its element.
+template <class F>
+void parallel_elements(int64_t ne, F fn)
+{
+    const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+    const int nt = (int)std::min<int64_t>(std::min<int64_t>(16, hw), ne / 256 + 1);
+    if (nt <= 1) {
+        for (int64_t e = 0; e < ne; ++e) fn(e);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+            for (int64_t e = t; e < ne; e += nt) fn(e);
+        });
+    for (auto &th : pool) th.join();
+}
 
 int face_node(int N, int f, int a, int b)
 {
@@ -600,7 +620,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
     const std::vector<int64_t> &off = g.off;
     auto Ja_at = [&](int64_t e, int i, int c, int n) {
         const int N = Ne[e];
-        return g.Ja[9 * off[e] + (int64_t)(i * 3 + c) * N * N * N + n];
+        return g.Ja[9 * g.moff[e] + (int64_t)(i * 3 + c) * N * N * N + n];
     };
 
     // Faces.  A conforming face (both sides of one order) is canonical with
@@ -670,7 +690,9 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         o[2] = v[2] / sc;
         o[3] = sc;
     };
-    for (int64_t e = 0; e < ne; ++e)
+    // records and face geometry, element by element (each owned face and each
+    // mortar is written by one element only)
+    parallel_elements(ne, [&](int64_t e) {
         for (int f = 0; f < 6; ++f) {
             FaceRef &r = conn[e * 6 + f];
             r.face = fid[e * 6 + f];
@@ -699,6 +721,7 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
                 for (int a = 0; a < N; ++a)
                     put_normal(&fgeo[(foff[r.face] + a + N * b) * 4], e, f, face_node(N, f, a, b));
         }
+    });
     // meshes of mixed order: a conforming face's record carries its first
     // face node and the neighbour's first node, so that the kernels' trace,
     // geometry and neighbour loads wait for no table lookup
@@ -728,21 +751,22 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
         for (int64_t e = 0; e < ne; ++e) moff[e] = moff[rep[e]];
     }
     std::vector<double> metric(mnodes * 10), mass(g.nodes);
-    for (int64_t e = 0; e < ne; ++e) {
+    parallel_elements(ne, [&](int64_t e) {
         const int N = Ne[e], N3 = N * N * N;
         const std::vector<double> &w = g.ws[N];
         const bool first = !share || rep[e] == e;
         const int64_t mo = share ? moff[e] : off[e];
         for (int n = 0; n < N3; ++n) {
-            const double J = g.J[off[e] + n];
+            const double J = g.J[g.moff[e] + n];
             if (first) {
                 metric[10 * mo + n] = 1.0 / J;
-                for (int k = 0; k < 9; ++k) metric[10 * mo + (int64_t)(1 + k) * N3 + n] = g.Ja[9 * off[e] + (int64_t)k * N3 + n];
+                for (int k = 0; k < 9; ++k)
+                    metric[10 * mo + (int64_t)(1 + k) * N3 + n] = g.Ja[9 * g.moff[e] + (int64_t)k * N3 + n];
             }
             const int a = n % N, b = (n / N) % N, c = n / (N * N);
             mass[off[e] + n] = w[a] * w[b] * w[c] * J;
         }
-    }
+    });
     m->x = std::move(g.x);
     // the processing order keeps each group of translates together
     m->order = hdg::locality_order(*d, share ? &rep : nullptr);

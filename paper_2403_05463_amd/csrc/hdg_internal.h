@@ -265,8 +265,10 @@ struct HostGeometry {
     std::vector<double> xi, w, D;          // GLL rule and derivative matrix of element 0's order
     std::vector<double> xis[kMaxN + 1], ws[kMaxN + 1], Ds[kMaxN + 1];   // every order in use
     std::vector<double> x;                 // [e][3][Ne^3]
-    std::vector<double> J;                 // [e][Ne^3]
-    std::vector<double> Ja;                // [e][3][3][Ne^3]
+    std::vector<int64_t> moff;             // [e] first node of e's values in J and Ja: off[e], or with
+                                           // translates sharing, the group's one slot
+    std::vector<double> J;                 // [slot][Ne^3]
+    std::vector<double> Ja;                // [slot][3][3][Ne^3]
     std::vector<double> delta;             // [e]
 };
 

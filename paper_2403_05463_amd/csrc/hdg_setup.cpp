@@ -185,9 +185,24 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, c
     g.xi = g.xis[g.N];
     g.w = g.ws[g.N];
     g.D = g.Ds[g.N];
+    // metric terms once per group of translates: slots for the groups'
+    // first elements only (every element's own slot without groups)
+    g.moff.assign(ne, 0);
+    int64_t mtot = tot;
+    if (rep) {
+        mtot = 0;
+        for (int64_t e = 0; e < ne; ++e)
+            if ((*rep)[e] == e) {
+                g.moff[e] = mtot;
+                mtot += (int64_t)g.Ne[e] * g.Ne[e] * g.Ne[e];
+            }
+        for (int64_t e = 0; e < ne; ++e) g.moff[e] = g.moff[(*rep)[e]];
+    } else {
+        g.moff = g.off;
+    }
     g.x.assign(tot * 3, 0.0);
-    g.J.assign(tot, 0.0);
-    g.Ja.assign(tot * 9, 0.0);
+    g.J.assign(mtot, 0.0);
+    g.Ja.assign(mtot * 9, 0.0);
     g.delta.assign(ne, 0.0);
     std::atomic<int64_t> bad{-1};
 
@@ -208,8 +223,10 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, c
             apply_dir(I, N, G1, 2, t2.data(), N, N, G1, &loc[c * N3]);
             for (int n = 0; n < N3; ++n) g.x[3 * o + c * N3 + n] = (double)((xreal)Xe[c * G3] + loc[c * N3 + n]);
         }
-        // a translate of an earlier element takes its metric terms (second pass)
+        // a translate of another element shares its slot (and takes its filter
+        // width in a second pass)
         if (rep && (*rep)[e] != e) return;
+        const int64_t mo = g.moff[e];
         for (int c = 0; c < 3; ++c)
             for (int k = 0; k < 3; ++k) apply_dir(Dq, N, N, k, &loc[c * N3], N, N, N, &dX[(c * 3 + k) * N3]);
         xreal vol = 0.0L;
@@ -218,7 +235,7 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, c
             const xreal J = m(0, 0) * (m(1, 1) * m(2, 2) - m(1, 2) * m(2, 1))
                           - m(0, 1) * (m(1, 0) * m(2, 2) - m(1, 2) * m(2, 0))
                           + m(0, 2) * (m(1, 0) * m(2, 1) - m(1, 1) * m(2, 0));
-            g.J[o + n] = (double)J;
+            g.J[mo + n] = (double)J;
             const int a = n % N, b = (n / N) % N, c = n / (N * N);
             vol += wq[a] * wq[b] * wq[c] * J;
             if (!(J > 0.0L)) bad.store(e);
@@ -234,9 +251,9 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, c
                     if (j != k) apply_dir(Dq, N, N, j, &V[k * N3], N, N, N, &dV[(k * 3 + j) * N3]);
             for (int p = 0; p < N3; ++p) {
                 auto dv = [&](int k, int j) { return dV[(k * 3 + j) * N3 + p]; };
-                g.Ja[9 * o + (0 * 3 + n) * N3 + p] = (double)(-(dv(2, 1) - dv(1, 2)));
-                g.Ja[9 * o + (1 * 3 + n) * N3 + p] = (double)(-(dv(0, 2) - dv(2, 0)));
-                g.Ja[9 * o + (2 * 3 + n) * N3 + p] = (double)(-(dv(1, 0) - dv(0, 1)));
+                g.Ja[9 * mo + (0 * 3 + n) * N3 + p] = (double)(-(dv(2, 1) - dv(1, 2)));
+                g.Ja[9 * mo + (1 * 3 + n) * N3 + p] = (double)(-(dv(0, 2) - dv(2, 0)));
+                g.Ja[9 * mo + (2 * 3 + n) * N3 + p] = (double)(-(dv(1, 0) - dv(0, 1)));
             }
         }
     };
@@ -247,22 +264,8 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, c
             for (int64_t e = t; e < ne; e += nt) body(e);
         });
     for (auto &th : pool) th.join();
-    if (rep) {
-        std::vector<std::thread> pool2;
-        for (int t = 0; t < nt; ++t)
-            pool2.emplace_back([&, t] {
-                for (int64_t e = t; e < ne; e += nt) {
-                    const int64_t r = (*rep)[e];
-                    if (r == e) continue;
-                    const int64_t N3 = (int64_t)g.Ne[e] * g.Ne[e] * g.Ne[e];
-                    std::copy(g.J.begin() + g.off[r], g.J.begin() + g.off[r] + N3, g.J.begin() + g.off[e]);
-                    std::copy(g.Ja.begin() + 9 * g.off[r], g.Ja.begin() + 9 * (g.off[r] + N3),
-                              g.Ja.begin() + 9 * g.off[e]);
-                    g.delta[e] = g.delta[r];
-                }
-            });
-        for (auto &th : pool2) th.join();
-    }
+    if (rep)
+        for (int64_t e = 0; e < ne; ++e) g.delta[e] = g.delta[(*rep)[e]];
     if (bad.load() >= 0) {
         msg = "non-positive Jacobian in element " + std::to_string(bad.load());
         return false;
