@@ -92,39 +92,29 @@ def connectivity(corners: np.ndarray, boundary_type) -> tuple[np.ndarray, np.nda
     order = np.lexsort(flat.T[::-1])
     sk = flat[order]
     same = np.all(sk[1:] == sk[:-1], axis=1)
+    if np.any(same[:-1] & same[1:]):
+        raise ValueError("non-manifold face shared by more than two elements")
+    # faces with equal corner sets come in adjacent pairs of the sorted order
+    start = np.nonzero(same)[0]
+    g0, g1 = order[start], order[start + 1]
     paired = np.zeros(flat.shape[0], dtype=bool)
-    i = 0
-    n = flat.shape[0]
-    while i < n:
-        if i + 1 < n and same[i]:
-            if i + 2 < n and same[i + 1]:
-                raise ValueError("non-manifold face shared by more than two elements")
-            g0, g1 = order[i], order[i + 1]
-            e0, f0 = divmod(int(g0), 6)
-            e1, f1 = divmod(int(g1), 6)
-            for (ea, fa, eb, fb) in ((e0, f0, e1, f1), (e1, f1, e0, f0)):
-                ca = face_ids[ea, fa]
-                cb = face_ids[eb, fb]
-                code = -1
-                for o in range(8):
-                    ok = True
-                    for bb in range(2):
-                        for aa in range(2):
-                            s, t = orient_map(o, aa, bb, 1)
-                            if ca[aa + 2 * bb] != cb[s + 2 * t]:
-                                ok = False
-                    if ok:
-                        code = o
-                        break
-                if code < 0:
-                    raise ValueError("matching face corners admit no orientation code")
-                nbr[ea, fa] = eb
-                nbr_face[ea, fa] = fb
-                orient[ea, fa] = code
-            paired[g0] = paired[g1] = True
-            i += 2
-        else:
-            i += 1
+    paired[g0] = paired[g1] = True
+    # corner k = a + 2 b of a face maps to corner s + 2 t of the other side's
+    # face under orientation code o
+    omap = np.array([[orient_map(o, k % 2, k // 2, 1)[0] + 2 * orient_map(o, k % 2, k // 2, 1)[1]
+                      for k in range(4)] for o in range(8)])
+    flat_ids = face_ids.reshape(-1, 4)
+    for ga, gb in ((g0, g1), (g1, g0)):
+        ca, cb = flat_ids[ga], flat_ids[gb]
+        ok = np.stack([np.all(ca == cb[:, omap[o]], axis=1) for o in range(8)], axis=1)
+        if not np.all(ok.any(axis=1)):
+            raise ValueError("matching face corners admit no orientation code")
+        code = np.argmax(ok, axis=1)                    # the first code that matches
+        ea, fa = np.divmod(ga, 6)
+        eb, fb = np.divmod(gb, 6)
+        nbr[ea, fa] = eb
+        nbr_face[ea, fa] = fb
+        orient[ea, fa] = code
     for g in np.nonzero(~paired)[0]:
         e, f = divmod(int(g), 6)
         nbr[e, f] = boundary_type(e, f)
