@@ -121,6 +121,21 @@ static xreal lagrange_value(int M1, const xreal *nodes, int k, xreal x)
     return v;
 }
 
+/* d l_k / dx at x: sum over m != k of 1/(x_k - x_m) times the product of
+ * the remaining factors of l_k */
+static xreal lagrange_deriv(int M1, const xreal *nodes, int k, xreal x)
+{
+    xreal s = 0.0L;
+    for (int m = 0; m < M1; ++m) {
+        if (m == k) continue;
+        xreal t = 1.0L / (nodes[k] - nodes[m]);
+        for (int j = 0; j < M1; ++j)
+            if (j != k && j != m) t *= (x - nodes[j]) / (nodes[k] - nodes[j]);
+        s += t;
+    }
+    return s;
+}
+
 static void lgl_rule_x(int P, xreal *xi, xreal *w, xreal *D)
 {
     int N = P + 1;
@@ -247,7 +262,206 @@ static double interp_coef(const orc_mesh *m, int Nlo, int Nhi, int i, int k)
 /* Mesh construction: geometry at the nodes, curl-form metrics               */
 /* ------------------------------------------------------------------------ */
 
-static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
+/* Metric terms where orders meet.
+ *
+ * Reading (the paper's solver couples elements of different order, Sec. 2.2,
+ * with curl-form metrics, App. B; how the two are made compatible on curved
+ * faces is not stated): on a mesh of mixed order the curl-form product field
+ * V = X_l grad_xi X_m is restricted on the element boundary before its curl is
+ * taken, so that both sides of a face carry one polynomial normal s n:
+ *  - edge rule: on an edge around which the orders differ, the component of V
+ *    along the edge is replaced by its interpolant at the GLL points of degree
+ *    P_E - 1, P_E the lowest order around the edge;
+ *  - face rule: on a face between orders P_lo < P_hi, both sides replace each
+ *    of the two tangential components by its interpolant of degree P_lo - 1
+ *    along its own direction and P_lo across it, whose values on the face's
+ *    edges along that direction come from the edge rule.
+ * The face-normal metric (the tangential curl of these two components) then
+ * has degree <= P_lo - 1 in each face direction on both sides, which the
+ * mortar's exact integration against the lower side's basis reproduces.  The
+ * discrete metric identities hold for any nodal V (difference operators of a
+ * tensor grid commute).  A face or edge whose elements all have one order is
+ * left alone, so a mesh of one order is unchanged.
+ *
+ * Local edge k runs along reference direction k / 4; bit 0 (bit 1) of k gives
+ * the end, 0 or 1, of the lower (higher) of the two other directions. */
+static void other_dirs(int dir, int *p, int *q)
+{
+    *p = dir == 0 ? 1 : 0;
+    *q = dir == 2 ? 1 : 2;
+}
+
+static int edge_between(const int c0[3], const int c1[3])
+{
+    int dir = c0[0] != c1[0] ? 0 : c0[1] != c1[1] ? 1 : 2, p, q;
+    other_dirs(dir, &p, &q);
+    return 4 * dir + c0[p] + 2 * c0[q];
+}
+
+/* element corner of face-local corner (a, b) of local face f */
+static void face_corner(int f, int a, int b, int c[3])
+{
+    int d = f / 2, p, q;
+    other_dirs(d, &p, &q);
+    c[d] = f & 1;
+    c[p] = a;
+    c[q] = b;
+}
+
+/* fdeg[e][6]: P_lo of a face between orders, else 0.  edeg[e][12]: lowest order
+ * around an edge where orders differ, else 0.  The lowest and highest order
+ * around each edge are propagated across faces until nothing changes. */
+static void boundary_orders(int ne, const int *P, const int *nbr, const signed char *nbr_face,
+                            const signed char *orient, int *fdeg, int *edeg)
+{
+    static const int corners[4][4] = {{0, 0, 1, 0}, {0, 1, 1, 1}, {0, 0, 0, 1}, {1, 0, 1, 1}};
+    int *lo = malloc(sizeof(int) * 12 * (size_t)ne), *hi = malloc(sizeof(int) * 12 * (size_t)ne);
+    for (int e = 0; e < ne; ++e)
+        for (int k = 0; k < 12; ++k) lo[e * 12 + k] = hi[e * 12 + k] = P[e];
+    int changed = 1;
+    while (changed) {
+        changed = 0;
+        for (int e = 0; e < ne; ++e)
+            for (int f = 0; f < 6; ++f) {
+                int e2 = nbr[e * 6 + f];
+                if (e2 < 0) continue;
+                int f2 = nbr_face[e * 6 + f];
+                for (int s = 0; s < 4; ++s) {
+                    int c0[3], c1[3], d0[3], d1[3], a2, b2;
+                    face_corner(f, corners[s][0], corners[s][1], c0);
+                    face_corner(f, corners[s][2], corners[s][3], c1);
+                    orient_map(orient[e * 6 + f], 1, corners[s][0], corners[s][1], &a2, &b2);
+                    face_corner(f2, a2, b2, d0);
+                    orient_map(orient[e * 6 + f], 1, corners[s][2], corners[s][3], &a2, &b2);
+                    face_corner(f2, a2, b2, d1);
+                    int k = e * 12 + edge_between(c0, c1), k2 = e2 * 12 + edge_between(d0, d1);
+                    int l = lo[k] < lo[k2] ? lo[k] : lo[k2], h = hi[k] > hi[k2] ? hi[k] : hi[k2];
+                    if (l != lo[k] || l != lo[k2] || h != hi[k] || h != hi[k2]) {
+                        lo[k] = lo[k2] = l;
+                        hi[k] = hi[k2] = h;
+                        changed = 1;
+                    }
+                }
+            }
+    }
+    for (int e = 0; e < ne; ++e) {
+        for (int k = 0; k < 12; ++k) edeg[e * 12 + k] = lo[e * 12 + k] < hi[e * 12 + k] ? lo[e * 12 + k] : 0;
+        for (int f = 0; f < 6; ++f) {
+            int e2 = nbr[e * 6 + f];
+            fdeg[e * 6 + f] = (e2 >= 0 && P[e2] != P[e]) ? (P[e] < P[e2] ? P[e] : P[e2]) : 0;
+        }
+    }
+    free(lo);
+    free(hi);
+}
+
+/* V_k of physical row nn, (X_l - X_l(first control point)) dX_m/dxi_k with
+ * (nn, m, l) cyclic, at reference point xi, from the degree-Pg map. */
+static xreal map_V(int Pg, const xreal *gn, const double *X, int nn, int k, const xreal xi[3])
+{
+    int G1 = Pg + 1, G3 = G1 * G1 * G1, mm = (nn + 1) % 3, ll = (nn + 2) % 3;
+    xreal lv[3][MAXN], ld[3][MAXN];
+    for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < G1; ++j) {
+            lv[d][j] = lagrange_value(G1, gn, j, xi[d]);
+            ld[d][j] = lagrange_deriv(G1, gn, j, xi[d]);
+        }
+    const double *Xl = X + (size_t)ll * G3, *Xm = X + (size_t)mm * G3;
+    xreal xl = 0.0L, dxm = 0.0L;
+    for (int k3 = 0; k3 < G1; ++k3)
+        for (int k2 = 0; k2 < G1; ++k2)
+            for (int k1 = 0; k1 < G1; ++k1) {
+                int i = k1 + G1 * k2 + G1 * G1 * k3;
+                xl += ((xreal)Xl[i] - (xreal)Xl[0]) * lv[0][k1] * lv[1][k2] * lv[2][k3];
+                xreal b = (k == 0 ? ld[0][k1] : lv[0][k1]) * (k == 1 ? ld[1][k2] : lv[1][k2])
+                          * (k == 2 ? ld[2][k3] : lv[2][k3]);
+                dxm += ((xreal)Xm[i] - (xreal)Xm[0]) * b;
+            }
+    return xl * dxm;
+}
+
+/* the edge rule's polynomial on local edge k (degree pe - 1) at coordinate t
+ * along the edge */
+static xreal edge_poly(int Pg, const xreal *gn, const double *X, int nn, int k, int pe, xreal t)
+{
+    xreal xs[MAXN], ws[MAXN], Ds[MAXN * MAXN];
+    lgl_rule_x(pe - 1, xs, ws, Ds);
+    int dir = k / 4, p, q;
+    other_dirs(dir, &p, &q);
+    xreal s = 0.0L;
+    for (int j = 0; j < pe; ++j) {
+        xreal pt[3];
+        pt[dir] = xs[j];
+        pt[p] = (k & 1) ? 1.0L : -1.0L;
+        pt[q] = (k & 2) ? 1.0L : -1.0L;
+        s += lagrange_value(pe, xs, j, t) * map_V(Pg, gn, X, nn, dir, pt);
+    }
+    return s;
+}
+
+/* Applies the edge and face rules to the nodal V[3][N^3] of row nn. */
+static void restrict_boundary(int N, const xreal *xq, int Pg, const xreal *gn, const double *X, int nn,
+                              const int *fdeg, const int *edeg, xreal *V)
+{
+    int N3 = N * N * N;
+    for (int k = 0; k < 12; ++k) {
+        if (!edeg[k]) continue;
+        int dir = k / 4, p, q;
+        other_dirs(dir, &p, &q);
+        for (int a = 0; a < N; ++a) {
+            int idx[3];
+            idx[dir] = a;
+            idx[p] = (k & 1) ? N - 1 : 0;
+            idx[q] = (k & 2) ? N - 1 : 0;
+            V[dir * N3 + idx[0] + N * idx[1] + N * N * idx[2]] = edge_poly(Pg, gn, X, nn, k, edeg[k], xq[a]);
+        }
+    }
+    for (int f = 0; f < 6; ++f) {
+        int pf = fdeg[f];
+        if (!pf) continue;
+        int d = f / 2, t[2];
+        other_dirs(d, &t[0], &t[1]);
+        xreal xa[MAXN], xb[MAXN], wx[MAXN], Dx[MAXN * MAXN];
+        lgl_rule_x(pf - 1, xa, wx, Dx);   /* pf points along the component's own direction */
+        lgl_rule_x(pf, xb, wx, Dx);       /* pf + 1 points across it */
+        for (int ci = 0; ci < 2; ++ci) {
+            int c = t[ci], o = t[1 - ci];
+            xreal S[MAXN][MAXN];
+            for (int i = 0; i < pf; ++i)
+                for (int j = 0; j <= pf; ++j) {
+                    if (j == 0 || j == pf) {
+                        /* on the face's edge along c, at the end j of direction o */
+                        int cc[3], p, q;
+                        cc[d] = f & 1;
+                        cc[o] = j == pf;
+                        cc[c] = 0;
+                        other_dirs(c, &p, &q);
+                        int k = 4 * c + cc[p] + 2 * cc[q];
+                        if (edeg[k]) { S[i][j] = edge_poly(Pg, gn, X, nn, k, edeg[k], xa[i]); continue; }
+                    }
+                    xreal pt[3];
+                    pt[d] = (f & 1) ? 1.0L : -1.0L;
+                    pt[c] = xa[i];
+                    pt[o] = xb[j];
+                    S[i][j] = map_V(Pg, gn, X, nn, c, pt);
+                }
+            for (int a = 0; a < N; ++a)
+                for (int b = 0; b < N; ++b) {
+                    xreal v = 0.0L;
+                    for (int i = 0; i < pf; ++i)
+                        for (int j = 0; j <= pf; ++j)
+                            v += lagrange_value(pf, xa, i, xq[a]) * lagrange_value(pf + 1, xb, j, xq[b]) * S[i][j];
+                    int idx[3];
+                    idx[d] = (f & 1) ? N - 1 : 0;
+                    idx[c] = a;
+                    idx[o] = b;
+                    V[c * N3 + idx[0] + N * idx[1] + N * N * idx[2]] = v;
+                }
+        }
+    }
+}
+
+static void element_metrics(orc_mesh *m, int e, int Pg, const double *X, const int *fdeg, const int *edeg)
 {
     int N = NE(m, e), N3 = N3E(m, e), G1 = Pg + 1;
     xreal xq[MAXN], wq[MAXN], Dq[MAXN * MAXN];
@@ -318,6 +532,7 @@ static void element_metrics(orc_mesh *m, int e, int Pg, const double *X)
         for (int k = 0; k < 3; ++k)
             for (int n = 0; n < N3; ++n)
                 V[k * N3 + n] = xl[ll * N3 + n] * dX[(mm * 3 + k) * N3 + n];
+        restrict_boundary(N, xq, Pg, gn, X, nn, fdeg, edeg, V);
         for (int n = 0; n < N3; ++n) {
             xreal d1V2, d2V1, d2V0, d0V2, d0V1, d1V0;
             DREF(V + 2 * N3, 1, n, d1V2);
@@ -385,17 +600,19 @@ orc_mesh *orc_mesh_new_mixed(int ne, const int *P, int Pg, const double *xyz_geo
                 }
         }
 
-    /* mortar faces need geometry the lower order represents exactly: the
-     * curl-form metric terms of a degree-Pg map have degree 2 Pg per face
-     * direction */
+    /* a face between orders: the face rule needs P_lo >= 2 (degree P_lo - 1
+     * >= 1 along each direction), and P_lo >= Pg so that the restricted
+     * product field of both sides differs only by a translation term whose
+     * curl vanishes exactly */
     for (int e = 0; e < ne; ++e)
         for (int f = 0; f < 6; ++f) {
             int e2 = nbr[e * 6 + f];
             if (e2 >= 0 && P[e2] != P[e]) {
                 int plo = P[e] < P[e2] ? P[e] : P[e2];
-                if (2 * Pg > plo) {
+                if (plo < 2 || plo < Pg) {
                     snprintf(g_err, sizeof g_err,
-                             "element %d face %d: orders %d/%d need geometry order <= %d", e, f, P[e], P[e2], plo / 2);
+                             "element %d face %d: orders %d/%d need a lower order >= 2 and >= the geometry order %d",
+                             e, f, P[e], P[e2], Pg);
                     return NULL;
                 }
             }
@@ -423,8 +640,13 @@ orc_mesh *orc_mesh_new_mixed(int ne, const int *P, int Pg, const double *xyz_geo
     memcpy(m->orient, orient, ne * 6);
     memcpy(m->flag, flag, ne);
     size_t G3 = (size_t)(Pg + 1) * (Pg + 1) * (Pg + 1);
+    int *fdeg = malloc(sizeof(int) * 6 * (size_t)ne), *edeg = malloc(sizeof(int) * 12 * (size_t)ne);
+    boundary_orders(ne, P, nbr, nbr_face, orient, fdeg, edeg);
 #pragma omp parallel for schedule(static) num_threads(orc_get_threads())
-    for (int e = 0; e < ne; ++e) element_metrics(m, e, Pg, xyz_geom + (size_t)e * 3 * G3);
+    for (int e = 0; e < ne; ++e)
+        element_metrics(m, e, Pg, xyz_geom + (size_t)e * 3 * G3, fdeg + 6 * (size_t)e, edeg + 12 * (size_t)e);
+    free(fdeg);
+    free(edeg);
     for (int e = 0; e < ne; ++e)
         for (size_t i = 0; i < (size_t)N3E(m, e); ++i)
             if (!(m->J[m->off[e] + i] > 0.0)) {

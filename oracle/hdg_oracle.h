@@ -46,7 +46,7 @@ orc_mesh *orc_mesh_new(int n_elem, int P, int Pg, const double *xyz_geom,
                        const int *nbr, const signed char *nbr_face,
                        const signed char *orient, const unsigned char *flag);
 /* Per-element orders P[e]; faces between different orders are coupled through
- * a mortar (see hdg_oracle.c) and need 2 Pg <= the lower order. */
+ * a mortar (see hdg_oracle.c) and need a lower order >= 2 and >= Pg. */
 orc_mesh *orc_mesh_new_mixed(int n_elem, const int *P, int Pg, const double *xyz_geom,
                              const int *nbr, const signed char *nbr_face,
                              const signed char *orient, const unsigned char *flag);

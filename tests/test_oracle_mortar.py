@@ -1,6 +1,7 @@
 """Pins of the oracle's coupling of elements of different order (mortar
 faces): free stream, discrete conservation, polynomial exactness across the
-mortar from both sides, and orientation invariance."""
+mortar from both sides, and orientation invariance; on curved (quadratic and
+cubic) geometry, one face normal on both sides of every such face."""
 import math
 
 import numpy as np
@@ -54,12 +55,17 @@ def test_mixed_orders_really_mix(orc):
     assert P[flag == 1].mean() > P[flag == 0].mean()
 
 
-def test_mortar_rejects_curved_geometry_at_low_order(orc):
-    m = W.periodic_box(3, Pg=2, curve_amp=0.2)
-    P = np.full(m.n_elem, 3, dtype=np.int32)
+def test_mortar_rejects_orders_below_the_geometry(orc):
+    m = W.periodic_box(3, Pg=3, curve_amp=0.15)
+    P = np.full(m.n_elem, 2, dtype=np.int32)
     P[0] = 4
     with pytest.raises(ValueError):
         orc.OracleMesh(m, P, np.zeros(m.n_elem, np.uint8))
+    m1 = W.periodic_box(3, Pg=1, curve_amp=0.2)
+    P1 = np.full(m1.n_elem, 1, dtype=np.int32)
+    P1[0] = 3
+    with pytest.raises(ValueError):
+        orc.OracleMesh(m1, P1, np.zeros(m1.n_elem, np.uint8))
 
 
 @pytest.mark.parametrize("les", [1, 2])
@@ -232,3 +238,151 @@ def test_mortar_equals_conforming_face_after_raising_the_order(orc, viscous):
         Rc = om_c.residual(prm, q_c)
         ra, rb = om_m.element(Rm, A, 4), Rc[A]
         assert np.abs(ra - rb).max() < 1e-12 * np.abs(rb).max()
+
+
+# --- curved faces between orders -------------------------------------------
+#
+# Curl-form metric terms of a degree-Pg map have degree 2 Pg - 1 per face
+# direction, more than a low-order side represents.  The oracle restricts the
+# curl-form product field on faces and edges where orders meet so that both
+# sides carry one face normal of degree <= P_lo - 1 per direction (reading in
+# the oracle's header of that code).  These pins check that reading's purpose
+# directly (one normal, of that degree) and its consequences (free stream and
+# conservation through curved mortars).
+
+
+def _curved_mixed_box(Pg, seed):
+    m = W.periodic_box(3, Pg=Pg, curve_amp=0.2 if Pg == 2 else 0.15)
+    flag = W.bernoulli_mask(m.n_elem, 0.5, seed)
+    P = np.maximum(W.mixed_orders(flag, seed), Pg).astype(np.int32)
+    return m, flag, P
+
+
+@pytest.mark.parametrize("Pg", [2, 3])
+@pytest.mark.parametrize("les", [0, 1, 2])
+def test_curved_mortar_freestream(orc, Pg, les):
+    m, flag, P = _curved_mixed_box(Pg, 1 + les)
+    assert len(set(P.tolist())) >= 3
+    om = orc.OracleMesh(m, P, flag)
+    qc = np.array([0.3, 1.0, -0.5, 0.2])
+    q = _flat(om, 4, lambda e, n3: np.repeat(qc[:, None], n3, axis=1))
+    R = om.residual(_params(orc, les_model=les, C_les=0.07 if les == 2 else 0.1), q)
+    scale = C0SQ * 1.2 / (2 * math.pi / 3)
+    assert np.abs(R).max() < 1e-11 * scale
+    G = om.gradient(_params(orc), q)
+    assert np.abs(np.concatenate([om.element(G, e, 9).ravel() for e in range(m.n_elem) if flag[e]])).max() < 1e-11
+
+
+@pytest.mark.parametrize("Pg", [2, 3])
+@pytest.mark.parametrize("mixed_face", [0, 1])
+def test_curved_mortar_discrete_conservation(orc, Pg, mixed_face):
+    m, flag, P = _curved_mixed_box(Pg, 7)
+    om = orc.OracleMesh(m, P, flag)
+    rng = np.random.default_rng(9)
+    q = rng.uniform(-1, 1, size=4 * om.nodes)
+    R = om.residual(_params(orc, mixed_face=mixed_face), q)
+    WJ = _mass(orc, om)
+    for f in range(4):
+        Rf = np.concatenate([om.element(R, e, 4)[f] for e in range(om.n_elem)])
+        tot = (WJ * Rf).sum()
+        mag = np.abs(WJ * Rf).sum()
+        assert abs(tot) < 1e-13 * mag, (f, tot, mag)
+
+
+def _face_normals(om, Ja, e, f):
+    """Element e's outward s n at the nodes of its local face f: [a][b][3],
+    (a, b) the face-local indices (the two other reference directions in
+    increasing order)."""
+    N = int(om.Ps[e]) + 1
+    A = om.element(Ja, e, 9).reshape(3, 3, N, N, N)[f // 2]      # [d][c][b][a]
+    s = (f & 1) * (N - 1)
+    d = f // 2
+    F = A[:, :, :, s] if d == 0 else A[:, :, s, :] if d == 1 else A[:, s]
+    return (1.0 if f & 1 else -1.0) * np.transpose(F, (2, 1, 0))
+
+
+def _orient_map(o, M, a, b):
+    s, t = (b, a) if o & 1 else (a, b)
+    return (M - s if o & 2 else s), (M - t if o & 4 else t)
+
+
+@pytest.mark.parametrize("Pg", [2, 3])
+def test_curved_mortar_one_face_normal(orc, Pg):
+    """On every face between orders the lower side's s n is a polynomial of
+    degree <= P_lo - 1 per face direction, and the higher side's s n at its
+    own face nodes is the same polynomial, with the opposite sign."""
+    m, flag, P = _curved_mixed_box(Pg, 11)
+    om = orc.OracleMesh(m, P, flag)
+    _, Ja = om.metrics()
+    checked = 0
+    worst_deg = worst_match = 0.0
+    for e in range(m.n_elem):
+        for f in range(6):
+            e2 = int(m.nbr[e, f])
+            if e2 < 0 or P[e2] >= P[e]:
+                continue
+            f2 = int(m.nbr_face[e, f])
+            M, Nl = int(P[e]) + 1, int(P[e2]) + 1
+            xh, _, _ = orc.lgl(M - 1)
+            xl, _, _ = orc.lgl(Nl - 1)
+            xd, _, _ = orc.lgl(Nl - 2)
+            nh = _face_normals(om, Ja, e, f)
+            nl = _face_normals(om, Ja, e2, f2)
+            scale = np.abs(nl).max()
+            # degree <= P_lo - 1: the values at P_lo points reproduce all nodes
+            Ld = _lagrange_matrix(xd, xl)
+            Ld_back = _lagrange_matrix(xl, xd)
+            fit = np.einsum("ai,bj,ijc->abc", Ld, Ld, np.einsum("ia,jb,abc->ijc", Ld_back, Ld_back, nl))
+            worst_deg = max(worst_deg, np.abs(fit - nl).max() / scale)
+            # the same polynomial seen from the higher side
+            L = _lagrange_matrix(xl, xh)
+            for j in range(M):
+                for i in range(M):
+                    il, jl = _orient_map(int(m.orient[e, f]), M - 1, i, j)
+                    val = np.einsum("a,b,abc->c", L[il], L[jl], nl)
+                    worst_match = max(worst_match, np.abs(nh[i, j] + val).max() / scale)
+            checked += 1
+    assert checked > m.n_elem
+    assert worst_deg < 1e-13, worst_deg
+    assert worst_match < 1e-13, worst_match
+
+
+@pytest.mark.parametrize("Pg", [2, 3])
+def test_curved_mortar_metric_identities(orc, Pg):
+    """sum_i d(Ja^i)/dxi^i = 0 at every node of every element."""
+    m, flag, P = _curved_mixed_box(Pg, 13)
+    om = orc.OracleMesh(m, P, flag)
+    _, Ja = om.metrics()
+    worst = 0.0
+    for e in range(m.n_elem):
+        N = int(P[e]) + 1
+        _, _, D = orc.lgl(N - 1)
+        A = om.element(Ja, e, 9).reshape(3, 3, N, N, N)             # [i][d][c][b][a]
+        div = (np.einsum("ak,dcbk->dcba", D, A[0]) + np.einsum("bk,dcka->dcba", D, A[1])
+               + np.einsum("ck,dkba->dcba", D, A[2]))
+        worst = max(worst, np.abs(div).max() / np.abs(A).max())
+    assert worst < 1e-13, worst
+
+
+def test_uniform_order_metrics_are_not_restricted(orc):
+    """On a mesh of one order the restriction changes nothing: a single
+    element of another order far away leaves every element that shares no
+    edge or face with it bitwise as on the uniform mesh."""
+    m = W.periodic_box(4, Pg=2, curve_amp=0.2)
+    P0 = np.full(m.n_elem, 3, dtype=np.int32)
+    P1 = P0.copy()
+    P1[0] = 5
+    om0 = orc.OracleMesh(m, P0, np.zeros(m.n_elem, np.uint8))
+    om1 = orc.OracleMesh(m, P1, np.zeros(m.n_elem, np.uint8))
+    _, Ja0 = om0.metrics()
+    _, Ja1 = om1.metrics()
+    near = set(int(v) for v in np.where(np.isin(m.corners, m.corners[0]).any(axis=1))[0])
+    same = changed = 0
+    for e in range(1, m.n_elem):
+        a, b = om0.element(Ja0, e, 9).ravel(), om1.element(Ja1, e, 9).ravel()
+        if e in near:
+            changed += int(not np.array_equal(a, b))
+        else:
+            assert np.array_equal(a, b), e
+            same += 1
+    assert same > 0 and changed > 0
