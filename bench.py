@@ -156,7 +156,7 @@ def cpu_baseline(w, q0, budget_s: float = 12.0) -> dict:
 
 def mixed_leg(ctx, args, torch, hdg) -> dict:
     """Mixed-order form: the airfoil O-grid refined twice (192 x 96 x 16,
-    trilinear) with per-element orders 2..6 (higher where viscous), faces
+    quadratic) with per-element orders 2..6 (higher where viscous), faces
     between orders coupled through mortars; every order's tiles and the
     mortar kernels of an RK stage replayed from one captured graph."""
     from paper_2403_05463_amd import workloads as W
@@ -177,7 +177,7 @@ def mixed_leg(ctx, args, torch, hdg) -> dict:
     hdg.hdg_mesh_autotune(mesh, q, reps=2, stream=stream)
     res = {"config": {"workload": w.name, "elements": w.mesh.n_elem, "nodes": nodes, "dof": 4 * nodes,
                       "orders": {int(k): int(v) for k, v in zip(*np.unique(P, return_counts=True))},
-                      "viscous_fraction": float(np.mean(w.flag)), "mortar_faces": nonconf, "geometry": "trilinear",
+                      "viscous_fraction": float(np.mean(w.flag)), "mortar_faces": nonconf, "geometry": "quadratic",
                       "dt": w.dt, "host_generation_s": t1 - t0, "mesh_create_s": t2 - t1}}
     steps = args.mixed_steps
     orders, counts = np.unique(P, return_counts=True)

@@ -109,9 +109,16 @@ typedef struct {
                                   lower side's traces are extended by their own interpolants,
                                   the Roe + BR1 flux is evaluated on the mortar with the higher
                                   side's normal, and the lower side's surface integral is exact
-                                  on the mortar.  Such faces need 2 geom_order <= the lower
-                                  order (HDG_EUNSUPPORTED otherwise): the face geometry must
-                                  be exact at that order. */
+                                  on the mortar.  Where orders meet, the curl-form metric
+                                  terms are built from a product field x_l grad x_m whose
+                                  boundary values are restricted (on such a face to degree
+                                  P_lo - 1 along each tangential component's own direction
+                                  and P_lo across it; on an edge where orders differ to the
+                                  lowest order around it minus one along the edge), so that
+                                  both sides of the face share one polynomial normal and a
+                                  constant state stays constant on curved meshes.  Such
+                                  faces need a lower order >= 2 and >= geom_order
+                                  (HDG_EUNSUPPORTED otherwise). */
     int32_t geom_order;        /* Pg >= 1: geometry control points per direction minus one */
     const double *xyz_geom;    /* [n_elem][3][(Pg+1)^3] */
     const uint8_t *flag;       /* [n_elem] 1: Navier-Stokes + LES, 0: Euler (Sec. 2.3) */
@@ -148,7 +155,7 @@ void hdg_finalize(hdg_ctx *ctx);
  * and upload them.  The equation flag of each element (Sec. 2.1 regions)
  * comes with the description.  Synchronous.  HDG_EMESH on inconsistent
  * connectivity or J <= 0, HDG_EUNSUPPORTED on a face between orders whose
- * lower order cannot represent the geometry (2 geom_order > P).
+ * lower order is below 2 or below geom_order.
  * State layout: element after element, [4][(P_e+1)^3] each. */
 hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *desc, const hdg_params *params,
                            hdg_mesh **out);

@@ -480,9 +480,9 @@ hdg_status validate_desc(const hdg_mesh_desc *d, int &P)
             if (e2 >= ne || f2 < 0 || f2 > 5 || d->nbr[(int64_t)e2 * 6 + f2] != e || d->nbr_face[(int64_t)e2 * 6 + f2] != f)
                 return fail(HDG_EMESH, "element " + std::to_string(e) + " face " + std::to_string(f) +
                                            ": asymmetric connectivity");
-            if (d->P[e2] != d->P[e] && 2 * d->geom_order > std::min(d->P[e], d->P[e2]))
+            if (d->P[e2] != d->P[e] && std::min(d->P[e], d->P[e2]) < std::max(2, d->geom_order))
                 return fail(HDG_EUNSUPPORTED, "element " + std::to_string(e) + " face " + std::to_string(f) +
-                                                  ": a face between orders needs 2 geom_order <= the lower order");
+                                                  ": a face between orders needs a lower order >= 2 and >= geom_order");
             if (d->P[e2] != d->P[e] &&
                 !hdg::mortar_pair_supported(std::min(d->P[e], d->P[e2]) + 1, std::max(d->P[e], d->P[e2]) + 1))
                 return fail(HDG_EUNSUPPORTED, "element " + std::to_string(e) + " face " + std::to_string(f) +
@@ -590,12 +590,14 @@ hdg_status hdg_mesh_create(hdg_ctx *ctx, const hdg_mesh_desc *d, const hdg_param
 
     // translates share one metric block: group them first, so that set-up
     // computes each block once
+    hdg::BoundaryOrders bo;
+    hdg::boundary_orders(*d, bo);
     std::vector<int32_t> rep;
-    const int64_t nblocks = hdg::metric_groups(*d, rep);
+    const int64_t nblocks = hdg::metric_groups(*d, rep, &bo);
     const bool share = nblocks < ne;
     hdg::HostGeometry g;
     std::string msg;
-    if (!hdg::build_geometry(*d, g, msg, share ? &rep : nullptr)) return fail(HDG_EMESH, msg);
+    if (!hdg::build_geometry(*d, g, msg, share ? &rep : nullptr, &bo)) return fail(HDG_EMESH, msg);
 
     auto *m = new hdg_mesh();
     m->metric_blocks = nblocks;

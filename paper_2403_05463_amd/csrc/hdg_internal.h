@@ -281,18 +281,38 @@ void gll_interp(int Plo, int Phi, std::vector<double> &I);
 // With rep (metric_groups), an element other than its group's first copies
 // that one's J, Ja and filter width instead of computing them; its node
 // coordinates are its own.
+// Metric terms where orders meet.  The curl-form product field
+// V_k = x_l dx_m/dxi_k is restricted on the element boundary before its curl
+// is taken, so that both sides of every face carry one polynomial s n:
+//  - edge rule: on an edge around which the orders differ, the component
+//    along the edge becomes its interpolant at the GLL points of degree
+//    P_E - 1, P_E the lowest order around the edge;
+//  - face rule: on a face between orders P_lo < P_hi, both sides give each
+//    tangential component its interpolant of degree P_lo - 1 along its own
+//    direction and P_lo across it (edge values along it from the edge rule).
+// The face normal then has degree <= P_lo - 1 per face direction on both
+// sides, which the mortar's exact integration against the lower side's basis
+// reproduces (free stream); the discrete metric identities hold for any nodal
+// V.  face[e][6] is P_lo on a face between orders, edge[e][12] is P_E on an
+// edge where orders differ (edge k runs along xi^(k/4); bit 0 / bit 1 of k
+// is the end of the lower / higher other direction), 0 elsewhere.
+struct BoundaryOrders {
+    std::vector<int8_t> face, edge;
+    bool any = false;       // some face or edge is restricted
+};
+void boundary_orders(const hdg_mesh_desc &d, BoundaryOrders &b);
 bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg,
-                    const std::vector<int32_t> *rep = nullptr);
+                    const std::vector<int32_t> *rep = nullptr, const BoundaryOrders *bo = nullptr);
 // Spatially local processing order of the elements (recursive bisection of
 // centroids).  With rep (metric-sharing groups: rep[e] is the element whose
 // metric block e reads), the groups are ordered by the bisection of their
 // mean centroids and each group's elements follow one another, so that the
 // block is read from HBM once and then from the cache.
 std::vector<int32_t> locality_order(const hdg_mesh_desc &d, const std::vector<int32_t> *rep = nullptr);
-// Elements that are translates of one another (same order, control points
-// relative to the first one equal to 1e-12 of the element's size) share one
-// metric block: rep[e] is the first such element.  Returns the number of
-// distinct blocks.
-int64_t metric_groups(const hdg_mesh_desc &d, std::vector<int32_t> &rep);
+// Elements that are translates of one another (same order, same restricted
+// faces and edges, control points relative to the first one equal to 1e-12
+// of the element's size) share one metric block: rep[e] is the first such
+// element.  Returns the number of distinct blocks.
+int64_t metric_groups(const hdg_mesh_desc &d, std::vector<int32_t> &rep, const BoundaryOrders *bo = nullptr);
 
 }  // namespace hdg

@@ -152,7 +152,260 @@ void gll_interp(int Plo, int Phi, std::vector<double> &I)
     I.assign(Ix.begin(), Ix.end());
 }
 
-bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, const std::vector<int32_t> *rep)
+namespace {
+
+// Reference-cube corner (bits along xi1, xi2, xi3) of corner (a, b) of local
+// face f; the face's own coordinates are the two other directions in
+// increasing order, as for its nodes.
+void face_corner_bits(int f, int a, int b, int c[3])
+{
+    const int d = f / 2;
+    c[d] = f & 1;
+    c[d == 0 ? 1 : 0] = a;
+    c[d == 2 ? 1 : 2] = b;
+}
+
+// Local edge through two corners: 4 * direction + end of the lower other
+// direction + 2 * end of the higher one.
+int edge_through(const int u[3], const int v[3])
+{
+    int dir = 0;
+    while (u[dir] == v[dir]) ++dir;
+    return 4 * dir + u[dir == 0 ? 1 : 0] + 2 * u[dir == 2 ? 1 : 2];
+}
+
+int64_t root_of(std::vector<int64_t> &par, int64_t x)
+{
+    while (par[x] != x) {
+        par[x] = par[par[x]];
+        x = par[x];
+    }
+    return x;
+}
+
+}  // namespace
+
+// The element edges meeting at one mesh edge are joined through the faces
+// that share it (union-find over element-edge slots); each mesh edge then
+// knows the lowest and highest order around it.  A rule whose interpolation
+// is exact is skipped: the product field has degree 2 Pg - 1 along an edge
+// and (2 Pg - 1, 2 Pg) on a face, so an edge with 2 Pg <= P_E and a face with
+// 2 Pg <= P_lo none of whose edges is restricted keep their values.
+void boundary_orders(const hdg_mesh_desc &d, BoundaryOrders &b)
+{
+    const int64_t ne = d.n_elem;
+    b.face.assign(ne * 6, 0);
+    b.edge.assign(ne * 12, 0);
+    b.any = false;
+    for (int64_t e = 1; e < ne && !b.any; ++e) b.any = d.P[e] != d.P[0];
+    if (!b.any) return;
+    static const int sides[4][4] = {{0, 0, 1, 0}, {0, 1, 1, 1}, {0, 0, 0, 1}, {1, 0, 1, 1}};
+    std::vector<int64_t> par(ne * 12);
+    std::iota(par.begin(), par.end(), 0);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int32_t e2 = d.nbr[e * 6 + f];
+            if (e2 < 0) continue;
+            if (d.P[e2] != d.P[e]) b.face[e * 6 + f] = (int8_t)std::min(d.P[e], d.P[e2]);
+            const int f2 = d.nbr_face[e * 6 + f], o = d.orient[e * 6 + f];
+            for (const auto &sd : sides) {
+                int u[3], v[3], u2[3], v2[3];
+                face_corner_bits(f, sd[0], sd[1], u);
+                face_corner_bits(f, sd[2], sd[3], v);
+                // the same two corners in the neighbour's face coordinates
+                auto across = [&](int a, int bb, int out[3]) {
+                    const int s = (o & 1) ? bb : a, t = (o & 1) ? a : bb;
+                    face_corner_bits(f2, (o & 2) ? 1 - s : s, (o & 4) ? 1 - t : t, out);
+                };
+                across(sd[0], sd[1], u2);
+                across(sd[2], sd[3], v2);
+                const int64_t x = root_of(par, e * 12 + edge_through(u, v));
+                const int64_t y = root_of(par, (int64_t)e2 * 12 + edge_through(u2, v2));
+                if (x != y) par[std::max(x, y)] = std::min(x, y);
+            }
+        }
+    std::vector<int8_t> lo(ne * 12, 127), hi(ne * 12, 0);
+    for (int64_t slot = 0; slot < ne * 12; ++slot) {
+        const int64_t r = root_of(par, slot);
+        const int8_t P = (int8_t)d.P[slot / 12];
+        lo[r] = std::min(lo[r], P);
+        hi[r] = std::max(hi[r], P);
+    }
+    const int twice_pg = 2 * d.geom_order;
+    for (int64_t slot = 0; slot < ne * 12; ++slot) {
+        const int64_t r = root_of(par, slot);
+        if (lo[r] < hi[r] && lo[r] < twice_pg) b.edge[slot] = lo[r];
+    }
+    // edges of each local face: along a (bit of b) and along b (bit of a)
+    for (int64_t e = 0; e < ne; ++e)
+        for (int f = 0; f < 6; ++f) {
+            if (!b.face[e * 6 + f] || b.face[e * 6 + f] < twice_pg) continue;
+            bool edges = false;
+            for (const auto &sd : sides) {
+                int u[3], v[3];
+                face_corner_bits(f, sd[0], sd[1], u);
+                face_corner_bits(f, sd[2], sd[3], v);
+                edges = edges || b.edge[e * 12 + edge_through(u, v)] != 0;
+            }
+            if (!edges) b.face[e * 6 + f] = 0;
+        }
+    b.any = false;
+    for (int8_t c : b.face) b.any = b.any || c;
+    for (int8_t c : b.edge) b.any = b.any || c;
+}
+
+namespace {
+
+// One overwritten entry of the curl-form product field: component k at node
+// p, its value for each physical row n.
+struct BoundaryValue {
+    int k;
+    int p;
+    xreal v[3];
+};
+
+// The edge and face rules on element e (see BoundaryOrders): the values
+// they give to the element's boundary entries of V_k = (x_l - x_l0) dx_m/dxi_k,
+// (n, m, l) cyclic, x_l0 the first control point.  Edges come first, faces
+// after (a face rule's edge values are the edge rule's).
+void boundary_values(const double *Xe, int Pg, const std::vector<xreal> &gnodes, const std::vector<xreal> &Dg,
+                     int N, const std::vector<xreal> &xq, const int8_t *fo, const int8_t *eo,
+                     std::vector<BoundaryValue> &out)
+{
+    const int G1 = Pg + 1, G3 = G1 * G1 * G1;
+    out.clear();
+    auto ctrl = [&](int c, const int i[3]) {
+        return (xreal)Xe[c * G3 + i[0] + G1 * (i[1] + G1 * i[2])] - (xreal)Xe[c * G3];
+    };
+    // the edge rule's samples: V along edge k at its pe GLL points (degree pe - 1)
+    auto edge_samples = [&](int k, int pe, std::vector<xreal> &xs, std::vector<xreal> &vals) {
+        std::vector<xreal> ww, DD;
+        gll_rule_x(pe - 1, xs, ww, DD);
+        const int dir = k / 4, p = dir == 0 ? 1 : 0, q = dir == 2 ? 1 : 2;
+        xreal line[3][13], dline[3][13];
+        for (int c = 0; c < 3; ++c)
+            for (int g = 0; g < G1; ++g) {
+                int i[3];
+                i[dir] = g;
+                i[p] = (k & 1) * Pg;
+                i[q] = ((k >> 1) & 1) * Pg;
+                line[c][g] = ctrl(c, i);
+            }
+        for (int c = 0; c < 3; ++c)
+            for (int g = 0; g < G1; ++g) {
+                xreal s = 0.0L;
+                for (int h = 0; h < G1; ++h) s += Dg[g * G1 + h] * line[c][h];
+                dline[c][g] = s;
+            }
+        const std::vector<xreal> L = interp_matrix(gnodes, xs);
+        vals.assign(3 * pe, 0.0L);
+        for (int j = 0; j < pe; ++j) {
+            xreal X[3] = {0, 0, 0}, dX[3] = {0, 0, 0};
+            for (int c = 0; c < 3; ++c)
+                for (int g = 0; g < G1; ++g) {
+                    X[c] += L[j * G1 + g] * line[c][g];
+                    dX[c] += L[j * G1 + g] * dline[c][g];
+                }
+            for (int n = 0; n < 3; ++n) vals[n * pe + j] = X[(n + 2) % 3] * dX[(n + 1) % 3];
+        }
+    };
+    for (int k = 0; k < 12; ++k) {
+        const int pe = eo[k];
+        if (!pe) continue;
+        std::vector<xreal> xs, vals;
+        edge_samples(k, pe, xs, vals);
+        const std::vector<xreal> Ie = interp_matrix(xs, xq);
+        const int dir = k / 4, p = dir == 0 ? 1 : 0, q = dir == 2 ? 1 : 2;
+        for (int a = 0; a < N; ++a) {
+            int i[3];
+            i[dir] = a;
+            i[p] = (k & 1) * (N - 1);
+            i[q] = ((k >> 1) & 1) * (N - 1);
+            BoundaryValue bv{dir, i[0] + N * (i[1] + N * i[2]), {0, 0, 0}};
+            for (int n = 0; n < 3; ++n)
+                for (int j = 0; j < pe; ++j) bv.v[n] += Ie[a * pe + j] * vals[n * pe + j];
+            out.push_back(bv);
+        }
+    }
+    for (int f = 0; f < 6; ++f) {
+        const int pf = fo[f];
+        if (!pf) continue;
+        const int d = f / 2, side = f & 1, t[2] = {d == 0 ? 1 : 0, d == 2 ? 1 : 2};
+        std::vector<xreal> xa, xb, ww, DD;
+        gll_rule_x(pf - 1, xa, ww, DD);      // pf points along the component's own direction
+        gll_rule_x(pf, xb, ww, DD);          // pf + 1 points across it
+        const std::vector<xreal> La = interp_matrix(gnodes, xa), Lb = interp_matrix(gnodes, xb);
+        const std::vector<xreal> Ia = interp_matrix(xa, xq), Ib = interp_matrix(xb, xq);
+        for (int ci = 0; ci < 2; ++ci) {
+            const int c = t[ci], o = t[1 - ci];
+            // control net of the face as [g along c][g along o], and its derivative along c
+            std::vector<xreal> net(3 * G1 * G1), dnet(3 * G1 * G1, 0.0L);
+            for (int cc = 0; cc < 3; ++cc)
+                for (int gc = 0; gc < G1; ++gc)
+                    for (int go = 0; go < G1; ++go) {
+                        int i[3];
+                        i[d] = side * Pg;
+                        i[c] = gc;
+                        i[o] = go;
+                        net[(cc * G1 + gc) * G1 + go] = ctrl(cc, i);
+                    }
+            for (int cc = 0; cc < 3; ++cc)
+                for (int gc = 0; gc < G1; ++gc)
+                    for (int go = 0; go < G1; ++go)
+                        for (int h = 0; h < G1; ++h)
+                            dnet[(cc * G1 + gc) * G1 + go] += Dg[gc * G1 + h] * net[(cc * G1 + h) * G1 + go];
+            std::vector<xreal> S(3 * pf * (pf + 1));
+            for (int i = 0; i < pf; ++i)
+                for (int j = 0; j <= pf; ++j) {
+                    xreal X[3] = {0, 0, 0}, dX[3] = {0, 0, 0};
+                    for (int cc = 0; cc < 3; ++cc)
+                        for (int gc = 0; gc < G1; ++gc)
+                            for (int go = 0; go < G1; ++go) {
+                                const xreal wgt = La[i * G1 + gc] * Lb[j * G1 + go];
+                                X[cc] += wgt * net[(cc * G1 + gc) * G1 + go];
+                                dX[cc] += wgt * dnet[(cc * G1 + gc) * G1 + go];
+                            }
+                    for (int n = 0; n < 3; ++n) S[(n * pf + i) * (pf + 1) + j] = X[(n + 2) % 3] * dX[(n + 1) % 3];
+                }
+            // the two edges of the face along c take the edge rule's polynomial
+            for (int end = 0; end < 2; ++end) {
+                int bits[3] = {0, 0, 0};
+                bits[d] = side;
+                bits[o] = end;
+                const int k = 4 * c + bits[c == 0 ? 1 : 0] + 2 * bits[c == 2 ? 1 : 2];
+                if (!eo[k]) continue;
+                std::vector<xreal> xs, vals;
+                edge_samples(k, eo[k], xs, vals);
+                const std::vector<xreal> Ie = interp_matrix(xs, xa);
+                const int j = end ? pf : 0, pe = eo[k];
+                for (int i = 0; i < pf; ++i)
+                    for (int n = 0; n < 3; ++n) {
+                        xreal v = 0.0L;
+                        for (int m = 0; m < pe; ++m) v += Ie[i * pe + m] * vals[n * pe + m];
+                        S[(n * pf + i) * (pf + 1) + j] = v;
+                    }
+            }
+            for (int a = 0; a < N; ++a)
+                for (int b = 0; b < N; ++b) {
+                    int i3[3];
+                    i3[d] = side * (N - 1);
+                    i3[c] = a;
+                    i3[o] = b;
+                    BoundaryValue bv{c, i3[0] + N * (i3[1] + N * i3[2]), {0, 0, 0}};
+                    for (int n = 0; n < 3; ++n)
+                        for (int i = 0; i < pf; ++i)
+                            for (int j = 0; j <= pf; ++j)
+                                bv.v[n] += Ia[a * pf + i] * Ib[b * (pf + 1) + j] * S[(n * pf + i) * (pf + 1) + j];
+                    out.push_back(bv);
+                }
+        }
+    }
+}
+
+}  // namespace
+
+bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, const std::vector<int32_t> *rep,
+                    const BoundaryOrders *bo)
 {
     const int Pg = d.geom_order, G1 = Pg + 1, G3 = G1 * G1 * G1;
     const int64_t ne = d.n_elem;
@@ -160,6 +413,22 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, c
     std::vector<xreal> xqs[kMaxN + 1], wqs[kMaxN + 1], Dqs[kMaxN + 1], Is[kMaxN + 1];
     std::vector<xreal> gnodes(G1);
     for (int k = 0; k < G1; ++k) gnodes[k] = -1.0L + 2.0L * k / Pg;
+    // derivative matrix on the geometry's equispaced nodes (barycentric weights)
+    std::vector<xreal> Dg(G1 * G1, 0.0L), bwg(G1, 1.0L);
+    for (int j = 0; j < G1; ++j)
+        for (int k = 0; k < G1; ++k)
+            if (k != j) bwg[j] /= (gnodes[j] - gnodes[k]);
+    for (int i = 0; i < G1; ++i)
+        for (int j = 0; j < G1; ++j)
+            if (j != i) {
+                Dg[i * G1 + j] = (bwg[j] / bwg[i]) / (gnodes[i] - gnodes[j]);
+                Dg[i * G1 + i] -= Dg[i * G1 + j];
+            }
+    BoundaryOrders own_bo;
+    if (!bo) {
+        boundary_orders(d, own_bo);
+        bo = &own_bo;
+    }
     g.Ne.resize(ne);
     g.off.resize(ne);
     int64_t tot = 0;
@@ -212,6 +481,7 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, c
         const int64_t o = g.off[e];
         std::vector<xreal> t1(N * G1 * G1), t2(N * N * G1), loc(3 * N3), dX(9 * N3), V(3 * N3), dV(9 * N3);
         std::vector<xreal> rel(G3);
+        std::vector<BoundaryValue> bvals;
         const double *Xe = d.xyz_geom + e * 3 * G3;
         // geometry at the nodes, relative to the element's first control point
         // (the metric terms do not depend on a translation; this keeps their
@@ -241,11 +511,15 @@ bool build_geometry(const hdg_mesh_desc &d, HostGeometry &g, std::string &msg, c
             if (!(J > 0.0L)) bad.store(e);
         }
         g.delta[e] = (double)(std::cbrt(vol) / N);
-        // curl form: Ja^i_n = -(curl_xi (x_l grad_xi x_m))_i, (n, m, l) cyclic
+        // curl form: Ja^i_n = -(curl_xi (x_l grad_xi x_m))_i, (n, m, l) cyclic,
+        // with the product field restricted where orders meet
+        if (bo->any)
+            boundary_values(Xe, Pg, gnodes, Dg, N, xqs[N], &bo->face[e * 6], &bo->edge[e * 12], bvals);
         for (int n = 0; n < 3; ++n) {
             const int mm = (n + 1) % 3, ll = (n + 2) % 3;
             for (int k = 0; k < 3; ++k)
                 for (int p = 0; p < N3; ++p) V[k * N3 + p] = loc[ll * N3 + p] * dX[(mm * 3 + k) * N3 + p];
+            for (const BoundaryValue &bv : bvals) V[bv.k * N3 + bv.p] = bv.v[n];
             for (int k = 0; k < 3; ++k)
                 for (int j = 0; j < 3; ++j)
                     if (j != k) apply_dir(Dq, N, N, j, &V[k * N3], N, N, N, &dV[(k * 3 + j) * N3]);
@@ -342,7 +616,7 @@ std::vector<int32_t> locality_order(const hdg_mesh_desc &d, const std::vector<in
     return ids;
 }
 
-int64_t metric_groups(const hdg_mesh_desc &d, std::vector<int32_t> &rep)
+int64_t metric_groups(const hdg_mesh_desc &d, std::vector<int32_t> &rep, const BoundaryOrders *bo)
 {
     const int G1 = d.geom_order + 1, G3 = G1 * G1 * G1;
     rep.resize(d.n_elem);
@@ -361,6 +635,10 @@ int64_t metric_groups(const hdg_mesh_desc &d, std::vector<int32_t> &rep)
                 size = std::max(size, std::fabs(v));
             }
         key.assign((const char *)&d.P[e], sizeof(int32_t));
+        if (bo && bo->any) {     // restricted boundaries are part of the metric terms
+            key.append((const char *)&bo->face[e * 6], 6);
+            key.append((const char *)&bo->edge[e * 12], 12);
+        }
         for (double v : rel) {
             const int64_t q = (int64_t)std::llround(v / (1e-10 * size));
             key.append((const char *)&q, sizeof q);

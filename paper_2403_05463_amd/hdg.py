@@ -263,26 +263,46 @@ def hdg_mesh_node_coords(mesh: Mesh) -> np.ndarray:
     return x
 
 
-def hdg_mesh_geometry(mesh, P: int) -> dict:
-    """Host-only geometry of a mesh description: node coordinates, J, Ja and the GLL rule."""
+def _geometry_desc(mesh, Pa):
+    """A mesh description for the host-only geometry call; the arrays it
+    points to are kept on the returned structure."""
     ne = int(mesh.xyz_geom.shape[0])
-    N = P + 1
-    N3 = N ** 3
-    Pa = np.full(ne, P, dtype=np.int32)
-    xyz = np.ascontiguousarray(mesh.xyz_geom, dtype=np.float64)
-    flag = np.zeros(ne, dtype=np.uint8)
-    nbr = np.ascontiguousarray(mesh.nbr, dtype=np.int32)
-    nf = np.ascontiguousarray(mesh.nbr_face, dtype=np.int8)
-    o = np.ascontiguousarray(mesh.orient, dtype=np.int8)
+    keep = dict(P=Pa, xyz=np.ascontiguousarray(mesh.xyz_geom, dtype=np.float64),
+                flag=np.zeros(ne, dtype=np.uint8), nbr=np.ascontiguousarray(mesh.nbr, dtype=np.int32),
+                nf=np.ascontiguousarray(mesh.nbr_face, dtype=np.int8),
+                o=np.ascontiguousarray(mesh.orient, dtype=np.int8))
     d = MeshDesc()
+    d._keep = keep
     d.n_elem = ne
-    d.P = Pa.ctypes.data_as(C.POINTER(C.c_int32))
+    d.P = keep["P"].ctypes.data_as(C.POINTER(C.c_int32))
     d.geom_order = int(mesh.Pg)
-    d.xyz_geom = xyz.ctypes.data_as(C.POINTER(C.c_double))
-    d.flag = flag.ctypes.data_as(C.POINTER(C.c_uint8))
-    d.nbr = nbr.ctypes.data_as(C.POINTER(C.c_int32))
-    d.nbr_face = nf.ctypes.data_as(C.POINTER(C.c_int8))
-    d.orient = o.ctypes.data_as(C.POINTER(C.c_int8))
+    d.xyz_geom = keep["xyz"].ctypes.data_as(C.POINTER(C.c_double))
+    d.flag = keep["flag"].ctypes.data_as(C.POINTER(C.c_uint8))
+    d.nbr = keep["nbr"].ctypes.data_as(C.POINTER(C.c_int32))
+    d.nbr_face = keep["nf"].ctypes.data_as(C.POINTER(C.c_int8))
+    d.orient = keep["o"].ctypes.data_as(C.POINTER(C.c_int8))
+    return d
+
+
+def hdg_mesh_geometry(mesh, P) -> dict:
+    """Host-only geometry of a mesh description: node coordinates, J, Ja and the GLL rule.
+
+    P is one order or one per element.  With several orders the arrays are
+    flat, element after element (x: [3][N_e^3], J: [N_e^3], Ja: [3][3][N_e^3]
+    each), and the GLL rule is not returned."""
+    ne = int(mesh.xyz_geom.shape[0])
+    Pa = np.ascontiguousarray(np.broadcast_to(np.asarray(P, dtype=np.int32), (ne,)))
+    if ne and (Pa != Pa[0]).any():
+        nodes = int(((Pa.astype(np.int64) + 1) ** 3).sum())
+        out = dict(x=np.zeros(3 * nodes), J=np.zeros(nodes), Ja=np.zeros(9 * nodes))
+        d = _geometry_desc(mesh, Pa)
+        dp = C.POINTER(C.c_double)
+        _check(lib().hdg_mesh_geometry(C.byref(d), *(out[k].ctypes.data_as(dp) for k in ("x", "J", "Ja")),
+                                       None, None, None), "hdg_mesh_geometry")
+        return out
+    N = int(Pa[0]) + 1 if ne else int(np.max(P)) + 1
+    N3 = N ** 3
+    d = _geometry_desc(mesh, Pa)
     out = dict(x=np.zeros((ne, 3, N3)), J=np.zeros((ne, N3)), Ja=np.zeros((ne, 3, 3, N3)),
                xi=np.zeros(N), w=np.zeros(N), D=np.zeros((N, N)))
     dp = C.POINTER(C.c_double)

@@ -621,12 +621,11 @@ def tgv_box_precision(n=32, P=5) -> Workload:
 
 
 def naca_mixed(ni: int = 192, nj: int = 96, nk: int = 16, seed: int = 0) -> Workload:
-    """The airfoil O-grid refined twice (192 x 96 x 16 elements) with a per-element
-    order drawn from P = 2..6, higher orders in the viscous region (wall band
-    and wake wedge); trilinear elements, so every face between orders has
-    exact geometry at its lower order.  Re = 1e4, alpha = 20 deg, inflow +
-    1 % noise."""
-    mesh = naca_ogrid(ni, nj, nk, Pg=1)
+    """The airfoil O-grid refined twice (192 x 96 x 16 elements), quadratic
+    elements as on the one-order airfoil, with a per-element order drawn from
+    P = 2..6, higher orders in the viscous region (wall band and wake wedge).
+    Re = 1e4, alpha = 20 deg, inflow + 1 % noise."""
+    mesh = naca_ogrid(ni, nj, nk, Pg=2)
     flag = naca_mask(mesh)
     P = mixed_orders(flag, seed)
     params = dict(c0sq=25.0, nu=1e-4, les_model=1, C_les=0.1, mixed_face=0, q_inf=free_stream(20.0))

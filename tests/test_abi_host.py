@@ -63,6 +63,23 @@ def test_host_geometry_matches_oracle(orc, mesh, P):
     assert np.abs(g["Ja"] - Ja).max() < 1e-12 * np.abs(Ja).max()
 
 
+@pytest.mark.parametrize("Pg,seed", [(2, 1), (3, 2), (1, 3)])
+def test_host_geometry_of_mixed_orders_matches_oracle(orc, Pg, seed):
+    """Curved meshes of mixed order: the library's restriction of the
+    curl-form product field where orders meet gives the oracle's metric terms."""
+    m = W.periodic_box(3, Pg=Pg, curve_amp=0.2 if Pg > 1 else 0.25)
+    if seed == 2:
+        m = W.reorient(m, 5)[0]
+    flag = W.bernoulli_mask(m.n_elem, 0.5, seed)
+    P = np.maximum(W.mixed_orders(flag, seed), max(Pg, 2)).astype(np.int32)
+    g = hdg.hdg_mesh_geometry(m, P)
+    om = orc.OracleMesh(m, P, flag)
+    J, Ja = om.metrics()
+    np.testing.assert_allclose(g["x"], om.node_coords(), atol=1e-13)
+    np.testing.assert_allclose(g["J"], J, rtol=1e-12)
+    assert np.abs(g["Ja"] - Ja).max() < 1e-12 * np.abs(Ja).max()
+
+
 def test_host_geometry_rejects_bad_meshes():
     m = W.periodic_box(3, Pg=1)
     bad = W.HexMesh(Pg=1, xyz_geom=m.xyz_geom, corners=m.corners, nbr=m.nbr.copy(), nbr_face=m.nbr_face,

@@ -88,12 +88,17 @@ def test_batch_members_equal_alone(torch_cuda, ctx, prec, graphs):
         assert np.array_equal(q.cpu().numpy(), alone[i]), f"member {i} differs from its solve alone"
 
 
-def _mixed_member(ctx, seed):
-    """A warped periodic box whose elements carry orders 2..6 (faces between
-    orders through mortars), with a TGV state per element."""
-    mesh = W.periodic_box(3, Pg=1, curve_amp=0.25)
+def _mixed_mesh(seed):
+    """A curved (quadratic) periodic box whose elements carry orders 2..6
+    (faces between orders through mortars)."""
+    mesh = W.periodic_box(3, Pg=2, curve_amp=0.2)
     flag = W.bernoulli_mask(mesh.n_elem, 0.5, seed)
-    Pe = W.mixed_orders(flag, seed)
+    return mesh, flag, W.mixed_orders(flag, seed)
+
+
+def _mixed_member(ctx, seed):
+    """The mixed-order box with a TGV state per element."""
+    mesh, flag, Pe = _mixed_mesh(seed)
     m = hdg.hdg_mesh_create(ctx, mesh, Pe, flag, hdg.make_params(c0sq=25.0, nu=5e-3, les_model=1, C_les=0.1))
     x = hdg.hdg_mesh_node_coords(m)
     n3 = (Pe.astype(np.int64) + 1) ** 3
@@ -285,9 +290,8 @@ def test_batch_members_match_oracle(orc, torch_cuda, ctx, prec):
             assert e["l2"][1:].max() <= TOL_F32 and e["max"][1:].max() <= 10 * TOL_F32
             assert e["l2"][1:].max() > 1e-12          # the FP32 path ran
     # the member of several orders
-    mesh = W.periodic_box(3, Pg=1, curve_amp=0.25)
-    flag = W.bernoulli_mask(mesh.n_elem, 0.5, 8)
-    om = orc.OracleMesh(mesh, W.mixed_orders(flag, 8), flag)
+    mesh, flag, Pe = _mixed_mesh(8)
+    om = orc.OracleMesh(mesh, Pe, flag)
     po = orc.make_params(c0sq=25.0, nu=5e-3, les_model=1, C_les=0.1)
     ref = om.rk3(po, mq0, mdt, steps)
     out = qs[3].cpu().numpy()

@@ -54,9 +54,9 @@ def _cases():
     f2 = W.bernoulli_mask(m2.n_elem, 0.4, 6)
     yield "reoriented warped box 4^3, P 2..6, Vreman, reading B", m2, f2, W.mixed_orders(f2, 6), \
         dict(les_model=2, C_les=0.07, mixed_face=1)
-    g = W.naca_ogrid(48, 16, 4, Pg=1)
+    g = W.naca_ogrid(48, 16, 4, Pg=2)
     fg = W.naca_mask(g)
-    yield "O-grid 48x16x4 trilinear, P 2..6", g, fg, W.mixed_orders(fg, 9), \
+    yield "O-grid 48x16x4 quadratic, P 2..6", g, fg, W.mixed_orders(fg, 9), \
         dict(les_model=1, C_les=0.1, mixed_face=0, nu=1e-3, q_inf=W.free_stream(20.0))
     m3, _ = W.reorient(W.periodic_box(4, Pg=1, curve_amp=0.2), seed=11)
     f3 = W.bernoulli_mask(m3.n_elem, 0.5, 12)
@@ -65,6 +65,15 @@ def _cases():
         dict(les_model=2, C_les=0.07, mixed_face=0)
     yield "warped box 3^3, P 2..6, Rusanov flux", m, f, W.mixed_orders(f, 2), \
         dict(les_model=1, C_les=0.1, mixed_face=0, riemann=1)
+    # curved faces between orders: the metric terms restricted where orders meet
+    mq = W.periodic_box(3, Pg=2, curve_amp=0.2)
+    fq = W.bernoulli_mask(mq.n_elem, 0.5, 14)
+    yield "quadratic curved box 3^3, P 2..6", mq, fq, W.mixed_orders(fq, 14), \
+        dict(les_model=1, C_les=0.1, mixed_face=0)
+    mc, _ = W.reorient(W.periodic_box(3, Pg=3, curve_amp=0.15), seed=15)
+    fc = W.bernoulli_mask(mc.n_elem, 0.5, 15)
+    yield "reoriented cubic curved box 3^3, P 3..6, Vreman, reading B", mc, fc, \
+        np.maximum(W.mixed_orders(fc, 15), 3), dict(les_model=2, C_les=0.07, mixed_face=1)
 
 
 def _prm(kw):
@@ -73,7 +82,7 @@ def _prm(kw):
     return base
 
 
-@pytest.mark.parametrize("case", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("case", [0, 1, 2, 3, 4, 5, 6])
 def test_mixed_order_residual_parity(orc, torch_cuda, ctx, case):
     torch = torch_cuda
     name, mesh, flag, P, kw = list(_cases())[case]
@@ -100,9 +109,10 @@ def test_mixed_order_residual_parity(orc, torch_cuda, ctx, case):
     assert l2f.max() > 1e-10
 
 
-def test_mixed_order_rk_parity(orc, torch_cuda, ctx):
+@pytest.mark.parametrize("case", [0, 5])
+def test_mixed_order_rk_parity(orc, torch_cuda, ctx, case):
     torch = torch_cuda
-    name, mesh, flag, P, kw = list(_cases())[0]
+    name, mesh, flag, P, kw = list(_cases())[case]
     prm = _prm(kw)
     om = orc.OracleMesh(mesh, P, flag)
     q = _state(om, 3)
@@ -151,9 +161,10 @@ def test_mixed_order_concurrent_phases_on_a_stream(orc, torch_cuda, ctx):
     assert torch.equal(q0, q1)
 
 
-def test_mixed_order_conservation_freestream_and_shapes(orc, torch_cuda, ctx):
+@pytest.mark.parametrize("case", [1, 5])
+def test_mixed_order_conservation_freestream_and_shapes(orc, torch_cuda, ctx, case):
     torch = torch_cuda
-    name, mesh, flag, P, kw = list(_cases())[1]
+    name, mesh, flag, P, kw = list(_cases())[case]
     prm = hdg.make_params(**_prm(kw))
     _say(f"conservation, free stream and launch shapes: {name}")
     om = orc.OracleMesh(mesh, P, flag)
@@ -210,7 +221,7 @@ def test_mixed_order_autotune_keeps_state_and_results(orc, torch_cuda, ctx):
 
 @pytest.mark.timeout(600)
 def test_full_size_mixed_airfoil(orc, torch_cuda, ctx):
-    """The mixed-order benchmark mesh itself (192 x 96 x 16 trilinear,
+    """The mixed-order benchmark mesh itself (192 x 96 x 16 quadratic,
     P = 2..6, 36.2M nodes, 619k mortar faces): one FP64 residual of the
     benchmark's initial state, every node against the oracle, and the FP32
     residual's velocity rows."""
