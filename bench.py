@@ -423,7 +423,14 @@ def main(argv=None) -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     if args.mixed_only:
-        print(json.dumps({"mixed_order": mixed_leg(hdg.hdg_init(0), args, torch, hdg)}), flush=True)
+        ctx = hdg.hdg_init(0)
+        # one plain copy of known size first, the calibration of a traffic profile
+        src = torch.empty((args.copy_mb << 20) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        hdg.hdg_stream_copy(ctx, dst, src, args.copy_mb << 20, stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        del src, dst
+        print(json.dumps({"mixed_order": mixed_leg(ctx, args, torch, hdg)}), flush=True)
         return 0
     w = W.naca_working()
     q0 = W.initial_state(w, None)

@@ -79,16 +79,24 @@ def stats_summary(path: str, cmd: str, trace_csv: str = None) -> str:
     return "\n".join(lines) + "\n"
 
 
-def _per_kernel(path: str, counter: str) -> dict:
-    acc = collections.defaultdict(list)
+def _per_kernel(path: str, counter: str, counts: dict = None) -> dict:
+    """Mean counter value per dispatch of each kernel (a dispatch's rows,
+    one per XCD or instance, summed); ``counts`` receives the dispatch count."""
+    acc = collections.defaultdict(float)
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
-            acc[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in acc.items()}
+            acc[(short_name(r["Kernel_Name"]), r.get("Dispatch_Id", ""))] += float(r["Counter_Value"])
+    per = collections.defaultdict(list)
+    for (k, _), v in acc.items():
+        per[k].append(v)
+    if counts is not None:
+        counts.update({k: len(v) for k, v in per.items()})
+    return {k: sum(v) / len(v) for k, v in per.items()}
 
 
 def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: int, cmd_fetch: str, cmd_write: str) -> str:
-    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
+    counts = {}
+    fetch = _per_kernel(fetch_csv, "FETCH_SIZE", counts)
     write = _per_kernel(write_csv, "WRITE_SIZE")
     copy = next(k for k in fetch if k.startswith("k_copy"))
     f_fetch = copy_bytes / (fetch[copy] * 1024.0)
@@ -98,12 +106,12 @@ def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: int, cmd_fetch: 
              f"kernel source hash: {kernel_source_hash()}",
              f"calibration: plain copy of {copy_bytes} bytes reads FETCH_SIZE {fetch[copy]:.1f} KiB "
              f"and WRITE_SIZE {write[copy]:.1f} KiB; factors fetch {f_fetch:.4f}, write {f_write:.4f}", "",
-             f"{'kernel':40s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'traffic_bytes':>16s}"]
+             f"{'kernel':40s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'traffic_bytes':>16s} {'dispatches':>10s}"]
     for k in sorted(fetch):
         if k not in write:
             continue
         t = fetch[k] * 1024.0 * f_fetch + write[k] * 1024.0 * f_write
-        lines.append(f"{k.replace(' ', ''):40s} {fetch[k]:12.1f} {write[k]:12.1f} {t:16.0f}")
+        lines.append(f"{k.replace(' ', ''):40s} {fetch[k]:12.1f} {write[k]:12.1f} {t:16.0f} {counts[k]:10d}")
     return "\n".join(lines) + "\n"
 
 
@@ -119,7 +127,7 @@ def traffic_for(summary_path: str, kernel_prefix: str):
     want = kernel_prefix.replace(" ", "")
     for line in text.splitlines():
         parts = line.split()
-        if len(parts) == 4 and parts[0].startswith(want):
+        if len(parts) in (4, 5) and parts[0].startswith(want):
             try:
                 return float(parts[3])
             except ValueError:
