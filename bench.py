@@ -31,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_naca0012_ogrid_96x48x8_P4.txt")
 # VALU instruction counts of the same kernels (rocprofv3 --pmc SQ_INSTS_VALU_*)
 FLOPS_SUMMARY = os.path.join(ROOT, "profiles", "flops_naca0012_ogrid_96x48x8_P4.txt")
+# FETCH_SIZE / WRITE_SIZE summary of the mixed-order airfoil's kernels
+MIXED_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_naca0012_ogrid_192x96x16_mixedP2-6.txt")
 
 
 def algorithmic_bytes(n_elem: int, N: int, fused_rk: bool, f32: bool = False, first_stage: bool = False) -> float:
@@ -211,8 +213,48 @@ def mixed_leg(ctx, args, torch, hdg) -> dict:
                                        "frac": bps / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS},
                     "kernel_ms_per_step": {k: v[0] / steps for k, v in kern.items()},
                     "launches_per_step": {k: v[1] / steps for k, v in kern.items()}}
+        tps = mixed_traffic_per_step(mesh, hdg, w.mesh, P, np.asarray(w.flag), prec == hdg.HDG_F32)
+        res[tag]["traffic_roofline"] = None if tps is None else {
+            "bytes_per_step": tps, "achieved": tps / (ms / steps * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": tps / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "source": os.path.relpath(MIXED_TRAFFIC_SUMMARY, ROOT)}
     del q, dq, mesh
     return res
+
+
+def mixed_traffic_per_step(mesh, hdg, mesh_desc, P, flag, f32: bool):
+    """Measured HBM traffic of one RK step on a mesh of mixed order: the
+    per-dispatch FETCH_SIZE + WRITE_SIZE bytes of the profile summary, summed
+    over the kernels a stage launches (each order's viscous and residual
+    kernel in the launch shape the mesh uses, each pair's mortar lift kernel
+    where a side is flagged and flux kernel), times three stages; None when
+    the summary is missing or the kernel sources changed since it was taken."""
+    from paper_2403_05463_amd.profiling import traffic_for
+    prec = hdg.HDG_F32 if f32 else hdg.HDG_F64
+    t = "float" if f32 else "double"
+    nb = mesh_desc.nbr
+    e_idx = np.repeat(np.arange(len(P)), 6).reshape(-1, 6)
+    hi = (nb >= 0) & (P[np.maximum(nb, 0)] < P[:, None])
+    nl, nh = P[np.maximum(nb, 0)][hi] + 1, P[e_idx][hi] + 1
+    vis = (flag[np.maximum(nb, 0)][hi] != 0) | (flag[e_idx][hi] != 0)
+    syms = []
+    for N in np.unique(P + 1):
+        for kind in (hdg.HDG_KERNEL_VISCOUS, hdg.HDG_KERNEL_RESIDUAL):
+            if kind == hdg.HDG_KERNEL_VISCOUS and not np.any(flag[P + 1 == N]):
+                continue
+            lc = hdg.hdg_mesh_get_launch(mesh, kind, prec, int(N))
+            syms.append(kernel_symbol(kind, int(N), f32, lc["block"], lc["persistent"]))
+    for a, b in sorted(set(zip(nl.tolist(), nh.tolist()))):
+        syms.append(f"k_mortar_flux<{a}, {b}, {t}>")
+        if np.any(vis[(nl == a) & (nh == b)]):
+            syms.append(f"k_mortar_lift<{a}, {b}, {t}>")
+    total = 0.0
+    for sym in syms:
+        v = traffic_for(MIXED_TRAFFIC_SUMMARY, sym)
+        if v is None:
+            return None
+        total += v
+    return 3.0 * total
 
 
 def secondary_leg(ctx, args, torch, hdg) -> dict:

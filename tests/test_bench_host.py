@@ -90,3 +90,43 @@ def test_shared_metric_saving():
     assert r["bytes"] == alg - sv
     assert abs(r["achieved"] - (alg - sv) / 1e-4 / 1e9) < 1e-9
     assert abs(r["frac"] - r["achieved"] / bench.HBM_PEAK_GBS) < 1e-15
+
+
+def test_mixed_traffic_sums_the_kernels_a_stage_launches(tmp_path, monkeypatch):
+    """The mixed-order step's measured traffic: per stage, each order's
+    viscous kernel (flagged elements present) and residual kernel in the
+    mesh's launch shape, each pair's flux kernel and, where a side is
+    flagged, its lift kernel; three stages per step."""
+    import numpy as np
+
+    from paper_2403_05463_amd import profiling
+
+    class Mesh:   # two elements per order pair along x: orders 2 | 3, flags 0 | 1
+        nbr = np.array([[1, 1, -1, -1, -1, -1], [0, 0, -1, -1, -1, -1]])
+
+    P = np.array([2, 3])
+    flag = np.array([0, 1], dtype=np.uint8)
+    text = "\n".join([f"kernel source hash: {profiling.kernel_source_hash()}", "",
+                      "k_residual<double,1,3,256,false> 0 0 1000 1",
+                      "k_residual<double,1,4,128,true> 0 0 2000 1",
+                      "k_viscous<double,4,256,false> 0 0 300 1",
+                      "k_mortar_flux<3,4,double> 0 0 40 1",
+                      "k_mortar_lift<3,4,double> 0 0 5 1"]) + "\n"
+    path = tmp_path / "traffic.txt"
+    path.write_text(text)
+    monkeypatch.setattr(bench, "MIXED_TRAFFIC_SUMMARY", str(path))
+
+    class Hdg:
+        HDG_F64, HDG_F32, HDG_KERNEL_VISCOUS, HDG_KERNEL_RESIDUAL = 0, 1, 0, 1
+
+        @staticmethod
+        def hdg_mesh_get_launch(mesh, kind, prec, N):
+            return {(1, 3): dict(block=256, persistent=False), (1, 4): dict(block=128, persistent=True),
+                    (0, 4): dict(block=256, persistent=False)}[(kind, N)]
+
+    assert bench.mixed_traffic_per_step(None, Hdg, Mesh, P, flag, False) == 3 * (1000 + 2000 + 300 + 40 + 5)
+    # an order without flagged elements launches no viscous kernel; a pair
+    # without a flagged side no lift kernel
+    assert bench.mixed_traffic_per_step(None, Hdg, Mesh, P, np.zeros(2, np.uint8), False) == 3 * (1000 + 2000 + 40)
+    # a kernel missing from the summary: no figure
+    assert bench.mixed_traffic_per_step(None, Hdg, Mesh, P, flag, True) is None
