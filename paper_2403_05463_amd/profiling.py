@@ -7,6 +7,8 @@
     HBM bytes per dispatch from two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
     runs, each scaled by what the same counter reads for the plain copy kernel
     of known size (copy bytes / counter reading);
+``python -m paper_2403_05463_amd.profiling timeline <kernel_trace.csv> --kernel <name> [--kernel <name>] --cmd "<command>"``
+    start, end, duration and idle gap of the named kernels' dispatches;
 ``python -m paper_2403_05463_amd.profiling flops <f64.csv> <f32.csv> --cmd64 "<command>" --cmd32 "<command>"``
     floating-point operations per dispatch from ``--pmc SQ_INSTS_VALU_ADD_F64
     SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64`` (and
@@ -76,6 +78,29 @@ def stats_summary(path: str, cmd: str, trace_csv: str = None) -> str:
             d = iso.get(name, [])
             line += f" {len(d):6d} {(sum(d) / len(d) / 1e3 if d else float('nan')):12.2f}"
         lines.append(line)
+    return "\n".join(lines) + "\n"
+
+
+def timeline_summary(trace_csv: str, kernels: list, cmd: str, first: int = 0, count: int = 30) -> str:
+    """Start, end and duration (µs, relative to the first listed dispatch) of
+    the dispatches of the named kernels, in start order, from a
+    ``--kernel-trace`` run: which launches overlap, and the idle gap between
+    dependent ones.  ``first`` skips that many of the matching dispatches."""
+    rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]),
+                   r.get("Queue_Id", "")) for r in csv.DictReader(open(trace_csv)))
+    want = [k.replace(" ", "") for k in kernels]
+    rows = [r for r in rows if r[2].replace(" ", "") in want][first:first + count]
+    lines = ["# kernel dispatch timeline (rocprofv3 --kernel-trace)", f"command: {cmd}",
+             f"kernel source hash: {kernel_source_hash()}", "",
+             f"{'start_us':>10s} {'end_us':>10s} {'dur_us':>8s} {'gap_us':>8s} {'queue':>5s}  kernel"]
+    if not rows:
+        return "\n".join(lines) + "\n"
+    t0, reach = rows[0][0], None
+    for s0, e0, k, q in rows:
+        # gap: idle time since every earlier dispatch ended (negative: overlap)
+        gap = "" if reach is None else f"{(s0 - reach) / 1e3:8.1f}"
+        lines.append(f"{(s0 - t0) / 1e3:10.1f} {(e0 - t0) / 1e3:10.1f} {(e0 - s0) / 1e3:8.1f} {gap:>8s} {q:>5s}  {k}")
+        reach = e0 if reach is None else max(reach, e0)
     return "\n".join(lines) + "\n"
 
 
@@ -199,6 +224,13 @@ def main(argv=None):
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--out")
+    tl = sub.add_parser("timeline")
+    tl.add_argument("trace_csv")
+    tl.add_argument("--kernel", action="append", required=True, help="kernel name as in the stats (repeatable)")
+    tl.add_argument("--first", type=int, default=0)
+    tl.add_argument("--count", type=int, default=30)
+    tl.add_argument("--cmd", required=True)
+    tl.add_argument("--out")
     f = sub.add_parser("flops")
     f.add_argument("csv64")
     f.add_argument("csv32")
@@ -208,6 +240,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.what == "stats":
         text = stats_summary(a.csv, a.cmd, a.trace)
+    elif a.what == "timeline":
+        text = timeline_summary(a.trace_csv, a.kernel, a.cmd, a.first, a.count)
     elif a.what == "flops":
         text = flops_summary(a.csv64, a.csv32, a.cmd64, a.cmd32)
     else:

@@ -130,3 +130,23 @@ def test_mixed_traffic_sums_the_kernels_a_stage_launches(tmp_path, monkeypatch):
     assert bench.mixed_traffic_per_step(None, Hdg, Mesh, P, np.zeros(2, np.uint8), False) == 3 * (1000 + 2000 + 40)
     # a kernel missing from the summary: no figure
     assert bench.mixed_traffic_per_step(None, Hdg, Mesh, P, flag, True) is None
+
+
+def test_timeline_summary_gaps(tmp_path):
+    """The dispatch timeline: times relative to the first listed dispatch, and
+    the gap to the latest end among earlier dispatches (negative: overlap)."""
+    from paper_2403_05463_amd import profiling
+
+    path = tmp_path / "trace.csv"
+    path.write_text('"Kernel_Name","Start_Timestamp","End_Timestamp","Queue_Id"\n'
+                    '"k_residual<double, 1, 5, 256, false>(x)",1000000,1255000,1\n'
+                    '"k_viscous<double, 5, 256, false>(x)",1010000,1150000,4\n'
+                    '"k_other(x)",1100000,1200000,2\n'
+                    '"k_residual<double, 1, 5, 256, false>(x)",1150000,1274000,4\n'
+                    '"k_residual<double, 1, 5, 256, false>(x)",1284000,1500000,1\n')
+    text = profiling.timeline_summary(str(path), ["k_residual<double, 1, 5, 256, false>",
+                                                  "k_viscous<double, 5, 256, false>"], "cmd")
+    rows = [ln.split() for ln in text.splitlines()[5:]]
+    assert [r[0] for r in rows] == ["0.0", "10.0", "150.0", "284.0"]
+    assert rows[1][3] == "-245.0" and rows[2][3] == "-105.0" and rows[3][3] == "10.0"
+    assert all("k_other" not in ln for ln in text.splitlines())
