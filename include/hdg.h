@@ -246,6 +246,17 @@ hdg_status hdg_reduce(hdg_mesh *mesh, const double *r_dev, double out_sum[4], do
  * builds: it uses at most 1024 workgroups). */
 hdg_status hdg_reduce_noalloc(hdg_mesh *mesh, const double *r_dev, double *out_dev, void *stream);
 
+/* Largest wave speed of the state q_dev (device, state layout), for the time
+ * step of the explicit RK (Sec. 2.3): the flux Jacobian of the
+ * artificial-compressibility system along a unit normal n has eigenvalues
+ * u.n and u.n +- sqrt((u.n)^2 + c0^2), so the largest magnitude over all n
+ * at a node is |u| + sqrt(|u|^2 + c0^2); *out_host receives its maximum over
+ * every node.  Uses the mesh's reduction buffers (one such call or
+ * hdg_reduce at a time per mesh), allocates nothing, synchronises the
+ * stream.  HDG_EINVAL on a NULL argument; HDG_ENONFINITE if a velocity is
+ * NaN or Inf (*out_host is then the maximum over the finite nodes). */
+hdg_status hdg_max_wave_speed(hdg_mesh *mesh, const double *q_dev, double *out_host, void *stream);
+
 /* Kernel timing: while enabled, every launch the mesh makes is serialised on
  * its stream and carries a pair of HIP events that the dispatch itself
  * records at the kernel's start and end (hipExtLaunchKernelGGL), so that a

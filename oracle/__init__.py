@@ -131,6 +131,18 @@ def rk3_riccati(y0, dt, nsteps):
     return lib().orc_rk3_riccati(y0, dt, nsteps)
 
 
+def max_wave_speed(q: np.ndarray, c0sq: float) -> float:
+    """Largest wave speed over the nodes of a state q given as (nodes, 4)
+    rows p, u, v, w.  The artificial-compressibility flux along a unit normal
+    n, F_n(q) = [c0^2 u.n ; u (u.n) + p n], has the Jacobian eigenvalues u.n
+    and u.n +- sqrt((u.n)^2 + c0^2) (Sec. 2.3 time step; the system of App. B
+    in the artificial-compressibility reading), whose largest magnitude over
+    all n is |u| + sqrt(|u|^2 + c0^2), reached at n parallel to u."""
+    u = np.asarray(q, dtype=np.float64)[:, 1:4]
+    a = np.sqrt((u * u).sum(axis=1))
+    return float(np.max(a + np.sqrt(a * a + c0sq)))
+
+
 def set_threads(n: int):
     lib().orc_set_threads(int(n))
 

@@ -1079,6 +1079,24 @@ hdg_status hdg_reduce(hdg_mesh *m, const double *r, double out_sum[4], double ou
     return HDG_OK;
 }
 
+hdg_status hdg_max_wave_speed(hdg_mesh *m, const double *q, double *out, void *stream)
+{
+    if (!m || !q || !out) return fail(HDG_EINVAL, "max_wave_speed: NULL argument");
+    HDG_HIP(hipSetDevice(m->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    // the reduction's partial and result buffers (one call at a time per mesh,
+    // as for hdg_reduce)
+    hipError_t e = hdg::launch_wave_speed(q, m->mixed ? m->eoff : nullptr, m->mixed ? m->Ne_d : nullptr, m->N, m->ne,
+                                          m->prm.c0sq, m->partials, m->nblocks_reduce, m->final13, s);
+    if (e != hipSuccess) return fail(HDG_EHIP, std::string("wave speed launch: ") + hipGetErrorString(e));
+    double h[2];
+    HDG_HIP(hipMemcpyAsync(h, m->final13, sizeof h, hipMemcpyDeviceToHost, s));
+    HDG_HIP(hipStreamSynchronize(s));
+    *out = h[0];
+    if (h[1] != 0.0) return fail(HDG_ENONFINITE, "non-finite velocity in the state");
+    return HDG_OK;
+}
+
 hdg_status hdg_reduce_noalloc(hdg_mesh *m, const double *r, double *out, void *stream)
 {
     if (!m || !r || !out) return fail(HDG_EINVAL, "reduce_noalloc: NULL argument");

@@ -243,6 +243,11 @@ hipError_t launch_gmm_assign(const double *X, int64_t n, const GmmState *st, con
 int resident_blocks_per_cu(int kind, int N, int B, Epi epi, bool f32);
 // Whether kernels are instantiated for order N with workgroup size B.
 bool shape_supported(int N, int B);
+// Largest wave speed |u| + sqrt(|u|^2 + c0^2) over a state and a non-finite
+// flag into final2[2] (nblocks partial pairs; element ranges as the reduction).
+// eoff / Ne per element on a mesh of mixed order, else NULL and order N.
+hipError_t launch_wave_speed(const double *q, const int64_t *eoff, const int8_t *Ne, int N, int64_t n_elem,
+                             double c0sq, double *partials, int nblocks, double *final2, hipStream_t s);
 hipError_t launch_reduce(int N, const double *r, const double *mass, int64_t n_elem,
                          double *partials, int nblocks, double *final13, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s);

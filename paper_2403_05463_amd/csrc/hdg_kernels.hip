@@ -1815,6 +1815,67 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double *partials, in
     if (threadIdx.x < 13) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Largest wave speed of the artificial-compressibility flux over the state:
+// the flux Jacobian along a unit normal n has eigenvalues u.n and
+// u.n +- sqrt((u.n)^2 + c0^2), whose largest magnitude over all n is
+// |u| + sqrt(|u|^2 + c0^2).  Per-block maxima over whole elements (the
+// reduction's element ranges), with a non-finite flag; element e has N^3
+// nodes from e N^3, or Ne[e]^3 from eoff[e] when eoff is set.
+__global__ __launch_bounds__(256) void k_wave_speed_partial(const double *q, const int64_t *eoff, const int8_t *Ne,
+                                                            int Nu, int64_t ne, double c0sq, double *partials)
+{
+    __shared__ double red[2][256];
+    double lam = 0.0, bad = 0.0;
+    const int64_t per = (ne + gridDim.x - 1) / gridDim.x;
+    const int64_t e0 = (int64_t)blockIdx.x * per, e1 = e0 + per < ne ? e0 + per : ne;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int N = eoff ? Ne[e] : Nu;
+        const int N3 = N * N * N;
+        const int64_t o = eoff ? eoff[e] : e * (int64_t)N3;
+        for (int n = threadIdx.x; n < N3; n += blockDim.x) {
+            const double *qe = q + 4 * o + n;
+            const double u = qe[N3], v = qe[2 * N3], w = qe[3 * N3];
+            const double a = sqrt(u * u + v * v + w * w);
+            const double l = a + sqrt(a * a + c0sq);
+            if (!isfinite(l)) bad = 1.0;
+            else lam = l > lam ? l : lam;
+        }
+    }
+    red[0][threadIdx.x] = lam;
+    red[1][threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) partials[(size_t)blockIdx.x * 2 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Maxima of the per-block pairs into out[2].
+__global__ __launch_bounds__(256) void k_max2_final(const double *partials, int nblocks, double *out)
+{
+    __shared__ double red[2][256];
+    double acc[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        acc[0] = fmax(acc[0], partials[(size_t)b * 2]);
+        acc[1] = fmax(acc[1], partials[(size_t)b * 2 + 1]);
+    }
+    red[0][threadIdx.x] = acc[0];
+    red[1][threadIdx.x] = acc[1];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kCopyUnroll = 2;
 constexpr int kCopyBlock = 512;
@@ -2049,6 +2110,17 @@ hipError_t launch_reduce_mixed(const double *r, const double *mass, const int64_
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partials, nblocks, final13);
+    return hipGetLastError();
+}
+
+hipError_t launch_wave_speed(const double *q, const int64_t *eoff, const int8_t *Ne, int N, int64_t n_elem,
+                             double c0sq, double *partials, int nblocks, double *final2, hipStream_t s)
+{
+    if (nblocks < 1 || n_elem < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_wave_speed_partial, dim3(nblocks), dim3(256), 0, s, q, eoff, Ne, N, n_elem, c0sq, partials);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_max2_final, dim3(1), dim3(256), 0, s, partials, nblocks, final2);
     return hipGetLastError();
 }
 

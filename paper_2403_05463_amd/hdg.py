@@ -27,7 +27,7 @@ EXPORTED = [
     "hdg_init", "hdg_finalize", "hdg_mesh_create", "hdg_mesh_destroy", "hdg_mesh_set_flags",
     "hdg_mesh_set_params", "hdg_mesh_info", "hdg_mesh_metric_blocks", "hdg_mesh_node_coords", "hdg_mesh_geometry", "hdg_residual",
     "hdg_rk3_steps",
-    "hdg_reduce", "hdg_reduce_noalloc", "hdg_timing_enable", "hdg_timing_read", "hdg_timing_samples", "hdg_stream_copy",
+    "hdg_reduce", "hdg_reduce_noalloc", "hdg_max_wave_speed", "hdg_timing_enable", "hdg_timing_read", "hdg_timing_samples", "hdg_stream_copy",
     "hdg_last_error",
     "hdg_mesh_autotune", "hdg_mesh_get_launch", "hdg_mesh_set_launch", "hdg_mesh_set_graphs",
     "hdg_batch_create", "hdg_batch_destroy", "hdg_batch_add", "hdg_batch_remove", "hdg_batch_info",
@@ -97,6 +97,7 @@ def lib() -> C.CDLL:
         L.hdg_rk3_steps.argtypes = [vp, vp, vp, C.c_double, i32, i32, vp]
         L.hdg_reduce.argtypes = [vp, vp, dp, dp, dp, vp]
         L.hdg_reduce_noalloc.argtypes = [vp, vp, vp, vp]
+        L.hdg_max_wave_speed.argtypes = [vp, vp, dp, vp]
         L.hdg_timing_enable.argtypes = [vp, i32]
         L.hdg_timing_read.argtypes = [vp, i32, dp, C.POINTER(i64)]
         L.hdg_timing_samples.argtypes = [vp, i32, C.POINTER(C.c_float), i64, C.POINTER(i64)]
@@ -352,6 +353,14 @@ def hdg_reduce_noalloc(mesh: Mesh, r, out, stream=None):
     if out is None or out.dtype != torch.float64 or out.numel() < 13 or not out.is_cuda or not out.is_contiguous():
         raise HdgError(HDG_EINVAL, "hdg_reduce_noalloc: out must be a contiguous float64 device tensor of 13 values")
     _check(lib().hdg_reduce_noalloc(mesh.handle, _ptr(r), _ptr(out), _stream(stream)), "hdg_reduce_noalloc")
+
+
+def hdg_max_wave_speed(mesh: Mesh, q, stream=None) -> float:
+    """Largest |u| + sqrt(|u|^2 + c0^2) over the nodes of state q."""
+    _check_state(mesh, q, "q")
+    out = C.c_double()
+    _check(lib().hdg_max_wave_speed(mesh.handle, _ptr(q), C.byref(out), _stream(stream)), "hdg_max_wave_speed")
+    return out.value
 
 
 def hdg_timing_enable(mesh: Mesh, enable: bool = True):

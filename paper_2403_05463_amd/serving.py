@@ -292,8 +292,7 @@ class HdgBackend(Backend):
         torch = self.torch
         r = h["req"]
         q = taylor_green_device(torch, torch.from_numpy(h["X"]).cuda(), 0.01, r.seed)
-        u2 = (q[:, 1:4] ** 2).sum(dim=1)
-        lam = float((u2.sqrt() + (u2 + self.C0SQ).sqrt()).max().item())
+        lam = self.hdg.hdg_max_wave_speed(h["mesh"], q, stream=torch.cuda.current_stream())
         return q, 0.5 * 0.5 * h["hmin"] / ((r.P + 1) ** 2 * lam)
 
     def join(self, h) -> int:

@@ -417,3 +417,36 @@ def test_translated_elements_share_metric_blocks(orc, torch_cuda, ctx):
     out, ref, mass, _ = _run_pair(orc, torch, ctx, og, 4, flag, prm, q)
     e = assert_parity(out, ref, mass, what="extruded O-grid with shared metric blocks")
     _say(f"errors l2={e['l2']} max={e['max']}")
+
+
+def _rows(q, P):
+    """(nodes, 4) rows p, u, v, w of a flat state, element after element."""
+    out, o = [], 0
+    for p in P:
+        n3 = (int(p) + 1) ** 3
+        out.append(q[4 * o:4 * (o + n3)].reshape(4, n3).T)
+        o += n3
+    return np.concatenate(out)
+
+
+def test_max_wave_speed_matches_oracle(orc, torch_cuda, ctx):
+    torch = torch_cuda
+    rng = np.random.default_rng(21)
+    mesh = W.periodic_box(3, Pg=1, curve_amp=0.2)
+    flag = W.bernoulli_mask(mesh.n_elem, 0.5, 3)
+    for label, P in (("one order P = 4", np.full(mesh.n_elem, 4, np.int32)),
+                     ("orders 2..6", W.mixed_orders(flag, 5).astype(np.int32))):
+        _say(f"max wave speed, warped box 3^3, {label}")
+        m = hdg.hdg_mesh_create(ctx, mesh, P, flag, hdg.make_params(**_params(c0sq=16.0)))
+        q = rng.normal(size=4 * int(((P + 1) ** 3).sum()))
+        got = hdg.hdg_max_wave_speed(m, torch.from_numpy(q).cuda())
+        ref = orc.max_wave_speed(_rows(q, P), 16.0)
+        assert abs(got - ref) <= 1e-14 * ref, (label, got, ref)
+    qn = torch.from_numpy(q).cuda()
+    qn[2] = float("nan")                       # a pressure: not part of the wave speed
+    assert hdg.hdg_max_wave_speed(m, qn) == got
+    n3 = (int(P[0]) + 1) ** 3
+    qn[2 * n3 + 2] = float("inf")              # a velocity (v) of the first element
+    with pytest.raises(hdg.HdgError) as ex:
+        hdg.hdg_max_wave_speed(m, qn)
+    assert ex.value.status == hdg.HDG_ENONFINITE

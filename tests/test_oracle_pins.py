@@ -208,6 +208,32 @@ def test_roe_dissipation_matches_numpy_eigendecomposition(orc):
         np.testing.assert_allclose(orc.roe_flux(C0SQ, qL, qR, n), expect, rtol=1e-11, atol=1e-11)
 
 
+def test_max_wave_speed_closed_forms_and_eigenvalues(orc):
+    """Fluid at rest: c0.  |u| = 3, c0 = 4: 3 + 5.  Random states: no
+    eigenvalue of the flux Jacobian along any sampled unit normal exceeds
+    it, and the normal along u attains it (numpy eigenvalues)."""
+    assert orc.max_wave_speed(np.zeros((5, 4)), C0SQ) == pytest.approx(math.sqrt(C0SQ), rel=1e-15)
+    assert orc.max_wave_speed(np.array([[0.3, 0.0, 3.0, 0.0]]), 16.0) == pytest.approx(8.0, rel=1e-15)
+    rng = np.random.default_rng(11)
+    q = rng.normal(size=(6, 4))
+    lam = orc.max_wave_speed(q, C0SQ)
+
+    def jac(qn, n):
+        A = np.zeros((4, 4))
+        for k in range(4):
+            e = np.zeros(4)
+            e[k] = 1.0
+            A[:, k] = (_Fn(qn + e, n) - _Fn(qn - e, n)) / 2
+        return A
+
+    best = 0.0
+    for qn in q:
+        for n in list(rng.normal(size=(40, 3))) + [qn[1:4]]:
+            n = n / np.linalg.norm(n)
+            best = max(best, np.abs(np.linalg.eigvals(jac(qn, n))).max())
+    assert best == pytest.approx(lam, rel=1e-12)
+
+
 def test_rusanov_consistency_and_antisymmetry(orc):
     rng = np.random.default_rng(3)
     for _ in range(50):
