@@ -43,8 +43,8 @@
  *   e.g. from torch tensors).  The library owns geometry, metric terms,
  *   connectivity, element lists and its scratch (face viscous-flux traces, the
  *   RK ping-pong state, reduction partials) from hdg_mesh_create to
- *   hdg_mesh_destroy.  hdg_residual, hdg_rk3_steps and hdg_reduce allocate no
- *   device memory.  These calls do: hdg_mesh_set_flags (new tile lists),
+ *   hdg_mesh_destroy.  hdg_residual, hdg_rk3_steps, hdg_reduce and
+ *   hdg_max_wave_speed allocate no device memory.  These calls do: hdg_mesh_set_flags (new tile lists),
  *   hdg_mesh_autotune (a trial buffer, freed before it returns), the first
  *   hdg_cluster_features / hdg_cluster_fit on a mesh (feature tile lists, EM
  *   partials; kept until hdg_mesh_destroy) and the first RK call after graphs
@@ -56,8 +56,8 @@
  *   hdg_mesh_create validates the mesh (symmetric connectivity, mutually
  *   inverse orientation codes, positive Jacobian).  Kernel launch failures
  *   map to HDG_EHIP.  Calls taking a stream are asynchronous on it, except
- *   hdg_reduce, hdg_mesh_autotune, hdg_batch_autotune and hdg_cluster_fit,
- *   which synchronise it.  hdg_mesh_set_flags and hdg_mesh_set_params wait
+ *   hdg_reduce, hdg_max_wave_speed, hdg_mesh_autotune, hdg_batch_autotune
+ *   and hdg_cluster_fit, which synchronise it.  hdg_mesh_set_flags and hdg_mesh_set_params wait
  *   for the device; hdg_timing_read and hdg_timing_samples wait for the
  *   launches they report.
  */
