@@ -63,7 +63,34 @@ def isolated_dispatches(trace_csv: str) -> dict:
     return out
 
 
-def stats_summary(path: str, cmd: str, trace_csv: str = None) -> str:
+def timer_windows(trace_csv: str, kernel: str, count: int, max_gap_ns: int = 50000) -> list:
+    """Mean durations (ns) of `kernel` in each serial window of the trace that
+    holds exactly `count` of its dispatches: a window is a run of dispatches
+    that each overlapped no other and follow one another within max_gap_ns,
+    as the library's kernel timer launches them (one stream, one at a time)."""
+    rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]))
+                  for r in csv.DictReader(open(trace_csv)))
+    want = kernel.replace(" ", "")
+    out, cur, reach, prev_end = [], [], -1, None
+    for i, (s0, e0, k) in enumerate(rows):
+        alone = s0 >= reach and (i + 1 == len(rows) or rows[i + 1][0] >= e0)
+        reach = max(reach, e0)
+        if not alone or (prev_end is not None and s0 - prev_end > max_gap_ns):
+            if len(cur) == count:
+                out.append(sum(cur) / len(cur))
+            cur = []
+        if alone:
+            if k.replace(" ", "") == want:
+                cur.append(e0 - s0)
+            prev_end = e0
+        else:
+            prev_end = None
+    if len(cur) == count:
+        out.append(sum(cur) / len(cur))
+    return out
+
+
+def stats_summary(path: str, cmd: str, trace_csv: str = None, timer: str = None) -> str:
     rows = list(csv.DictReader(open(path)))
     iso = isolated_dispatches(trace_csv) if trace_csv else {}
     lines = [f"# rocprofv3 kernel statistics", f"command: {cmd}", f"kernel source hash: {kernel_source_hash()}",
@@ -78,6 +105,11 @@ def stats_summary(path: str, cmd: str, trace_csv: str = None) -> str:
             d = iso.get(name, [])
             line += f" {len(d):6d} {(sum(d) / len(d) / 1e3 if d else float('nan')):12.2f}"
         lines.append(line)
+    if trace_csv and timer:
+        name, count = timer.rsplit(":", 1)
+        means = timer_windows(trace_csv, name, int(count))
+        lines += ["", f"kernel timer windows of {name.replace(' ', '')} ({count} dispatches each, one stream, "
+                      f"one at a time): mean " + ", ".join(f"{m / 1e3:.2f}" for m in means) + " us"]
     return "\n".join(lines) + "\n"
 
 
@@ -216,6 +248,7 @@ def main(argv=None):
     s.add_argument("csv")
     s.add_argument("--trace", help="kernel_trace.csv of the same run: adds the dispatches that ran alone")
     s.add_argument("--cmd", required=True)
+    s.add_argument("--timer", help="KERNEL:COUNT: mean duration in each serial window of COUNT dispatches")
     s.add_argument("--out")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
@@ -239,7 +272,7 @@ def main(argv=None):
     f.add_argument("--out")
     a = ap.parse_args(argv)
     if a.what == "stats":
-        text = stats_summary(a.csv, a.cmd, a.trace)
+        text = stats_summary(a.csv, a.cmd, a.trace, a.timer)
     elif a.what == "timeline":
         text = timeline_summary(a.trace_csv, a.kernel, a.cmd, a.first, a.count)
     elif a.what == "flops":

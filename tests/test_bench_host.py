@@ -150,3 +150,23 @@ def test_timeline_summary_gaps(tmp_path):
     assert [r[0] for r in rows] == ["0.0", "10.0", "150.0", "284.0"]
     assert rows[1][3] == "-245.0" and rows[2][3] == "-105.0" and rows[3][3] == "10.0"
     assert all("k_other" not in ln for ln in text.splitlines())
+
+
+def test_timer_windows_mean_of_serial_runs(tmp_path):
+    """Timer windows: runs of dispatches that overlap nothing and follow one
+    another closely; the named kernel's mean in each run with exactly the
+    requested count.  Overlapped dispatches (graph replays) break a run."""
+    from paper_2403_05463_amd import profiling
+
+    R, V = "k_residual<double, 1, 5, 256, false>", "k_viscous<double, 5, 256, false>"
+    rows = [(R, 0, 100), (V, 50, 120)]                            # overlapped: not a window
+    t = 1_000_000
+    for k, d in ((V, 60), (R, 120), (R, 70), (V, 62), (R, 118), (R, 72)):   # serial, 10 us gaps
+        rows.append((k, t, t + d * 1000))
+        t += d * 1000 + 10_000
+    path = tmp_path / "trace.csv"
+    path.write_text('"Kernel_Name","Start_Timestamp","End_Timestamp"\n' +
+                    "".join(f'"{k}(x)",{a},{b}\n' for k, a, b in rows))
+    means = profiling.timer_windows(str(path), R, 4)
+    assert means == [(120 + 70 + 118 + 72) * 1000 / 4]
+    assert profiling.timer_windows(str(path), R, 3) == []
